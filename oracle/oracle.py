@@ -1,0 +1,335 @@
+"""ctypes binding of the C oracle plus numpy reference pieces.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
+
+* ``Space`` (strings, levels, row starts, addresses): pinned by the
+  closed-form space dimension, which reproduces the paper's table of
+  determinant counts (application section, table of orbitals and
+  coefficients), and by brute-force enumeration in the tests.
+* ``sigma`` / ``dense_h`` / ``diag``: pinned by the closed-form reference
+  energy, Hermiticity, the non-interacting limit, the one-electron-per-spin
+  Kronecker construction, orbital-rotation invariance of FCI, alpha/beta
+  swap covariance and exact diagonalisation (tests/test_oracle_*.py).
+* ``apply_word``: pinned by the paper's two worked sign examples
+  (Eqs. contract and add).
+* ``terms``: pinned by an independent closed-form count in the tests.
+* ``dropped_bound``: pinned by the Weyl inequality against exact spectra.
+* ``davidson``: pinned by dense diagonalisation on small spaces.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from math import comb
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.environ.get("ISCI_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
+
+NBUCKET = 42
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+_LIB = None
+
+
+def lib():
+    """Load liboracle.so, building it first if it is absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            from .build import build
+            build()
+        L = ctypes.CDLL(LIBPATH)
+        L.orc_space_create.restype = ctypes.c_void_p
+        L.orc_space_create.argtypes = [ctypes.c_int] * 4
+        L.orc_space_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_space_dim.restype = _i64
+        L.orc_space_dim.argtypes = [ctypes.c_void_p]
+        L.orc_space_nstr.restype = _i64
+        L.orc_space_nstr.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_space_strings.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p]
+        L.orc_space_rowstart.argtypes = [ctypes.c_void_p, _i64p]
+        L.orc_space_address.restype = _i64
+        L.orc_space_address.argtypes = [ctypes.c_void_p, _i32p, _i32p]
+        L.orc_sigma.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                _dp, _i64, _i64, _i64p, _dp]
+        L.orc_diag.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _i64, _i64p, _dp]
+        L.orc_terms.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _i64p, _i64p]
+        L.orc_dense_h.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_dropped_bound.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_apply_word.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int, _ip, _ip]
+        L.orc_num_threads.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _ints(h, eri):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    n = h.shape[0]
+    if h.shape != (n, n) or eri.shape != (n, n, n, n):
+        raise ValueError("h must be [norb,norb] and eri [norb]^4")
+    return h, eri
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+class Space:
+    """Truncated CI space of the oracle (strings and determinant addresses).
+
+    Strings per spin: ascending orbital sets sorted by (excitation level,
+    colex); row Ia holds the beta strings of level <= L - level(Ia).
+    """
+
+    def __init__(self, norb: int, nalpha: int, nbeta: int, level: int):
+        self.norb, self.nalpha, self.nbeta, self.level = norb, nalpha, nbeta, level
+        self._h = lib().orc_space_create(norb, nalpha, nbeta, level)
+        if not self._h:
+            raise ValueError("invalid space")
+        self.dim = int(lib().orc_space_dim(self._h))
+
+    def close(self):
+        if self._h:
+            lib().orc_space_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nstr(self, spin: int) -> int:
+        return int(lib().orc_space_nstr(self._h, spin))
+
+    def strings(self, spin: int):
+        n = self.nbeta if spin else self.nalpha
+        ns = self.nstr(spin)
+        orbs = np.zeros((ns, max(n, 1)), dtype=np.int32)
+        lev = np.zeros(ns, dtype=np.int32)
+        lib().orc_space_strings(self._h, spin, _p(orbs, _i32p), _p(lev, _i32p))
+        return orbs[:, :n].copy(), lev
+
+    def rowstart(self):
+        rs = np.zeros(self.nstr(0) + 1, dtype=np.int64)
+        lib().orc_space_rowstart(self._h, _p(rs, _i64p))
+        return rs
+
+    def address(self, alpha, beta) -> int:
+        a = np.ascontiguousarray(sorted(alpha), dtype=np.int32)
+        b = np.ascontiguousarray(sorted(beta), dtype=np.int32)
+        if a.size == 0:
+            a = np.zeros(1, dtype=np.int32)
+        if b.size == 0:
+            b = np.zeros(1, dtype=np.int32)
+        return int(lib().orc_space_address(self._h, _p(a, _i32p), _p(b, _i32p)))
+
+    def determinants(self):
+        """List of (alpha tuple, beta tuple) in address order."""
+        ao, _ = self.strings(0)
+        bo, _ = self.strings(1)
+        rs = self.rowstart()
+        out = []
+        for ia in range(len(ao)):
+            for ib in range(int(rs[ia + 1] - rs[ia])):
+                out.append((tuple(int(x) for x in ao[ia]), tuple(int(x) for x in bo[ib])))
+        return out
+
+
+def sigma(space: Space, h, eri, tau: float, c, targets=None) -> np.ndarray:
+    """sigma_v(I) = sum_J (H_tau)_IJ c_v(J) for I in targets (default all).
+
+    c is [nvec][dim]; returns [nvec][len(targets)]."""
+    h, eri = _ints(h, eri)
+    c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.float64)
+    nvec = c.shape[0]
+    if c.shape[1] != space.dim:
+        raise ValueError("c has wrong length")
+    if targets is None:
+        nt = space.dim
+        tp = None
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tg.size
+        tp = _p(tg, _i64p)
+    out = np.zeros((nvec, nt))
+    for v0 in range(0, nvec, 64):
+        v1 = min(nvec, v0 + 64)
+        cc = np.ascontiguousarray(c[v0:v1])
+        oo = np.zeros((v1 - v0, nt))
+        rc = lib().orc_sigma(space._h, _p(h), _p(eri), float(tau), v1 - v0, _p(cc),
+                             space.dim, nt, tp, _p(oo))
+        if rc:
+            raise RuntimeError("orc_sigma failed")
+        out[v0:v1] = oo
+    return out
+
+
+def diag(space: Space, h, eri, tau: float, targets=None) -> np.ndarray:
+    h, eri = _ints(h, eri)
+    if targets is None:
+        nt, tp = space.dim, None
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        nt, tp = tg.size, _p(tg, _i64p)
+    out = np.zeros(nt)
+    lib().orc_diag(space._h, _p(h), _p(eri), float(tau), nt, tp, _p(out))
+    return out
+
+
+def terms(space: Space, h, eri, tau: float):
+    """(kept, all) unit counts per bucket (42 buckets, see bucket_names())."""
+    h, eri = _ints(h, eri)
+    kept = np.zeros(NBUCKET, dtype=np.int64)
+    allc = np.zeros(NBUCKET, dtype=np.int64)
+    lib().orc_terms(space._h, _p(h), _p(eri), float(tau), _p(kept, _i64p), _p(allc, _i64p))
+    return kept, allc
+
+
+def dense_h(space: Space, h, eri, tau: float) -> np.ndarray:
+    if space.dim > 20000:
+        raise ValueError("dense H only for tiny spaces")
+    h, eri = _ints(h, eri)
+    H = np.zeros((space.dim, space.dim))
+    lib().orc_dense_h(space._h, _p(h), _p(eri), float(tau), _p(H))
+    return H
+
+
+def dropped_bound(space: Space, h, eri, tau: float) -> float:
+    h, eri = _ints(h, eri)
+    b = np.zeros(1)
+    lib().orc_dropped_bound(space._h, _p(h), _p(eri), float(tau), _p(b))
+    return float(b[0])
+
+
+def apply_word(word, order: int = 0):
+    """word: list of ('+', k) creators / ('-', k) annihilators, left to right,
+    acting on the vacuum.  Returns (sign, creators) or (0, None)."""
+    n = len(word)
+    ty = np.array([1 if t == "+" else -1 for t, _ in word], dtype=np.intc)
+    op = np.array([k for _, k in word], dtype=np.intc)
+    out = np.zeros(max(n, 1), dtype=np.intc)
+    sg = np.zeros(1, dtype=np.intc)
+    ln = lib().orc_apply_word(n, _p(ty, _ip), _p(op, _ip), int(order), _p(out, _ip), _p(sg, _ip))
+    if ln < 0:
+        return 0, None
+    return int(sg[0]), [int(x) for x in out[:ln]]
+
+
+def bucket_names():
+    names = []
+    ov = "ov"
+    for spin in "ab":
+        for ep in range(2):
+            for eq in range(2):
+                names.append(f"1b_{spin}_{ov[ep]}{ov[eq]}")
+    for spin in ("aa", "bb"):
+        for nc in range(3):
+            for na in range(3):
+                names.append(f"ss_{spin}_c{nc}a{na}")
+    for ep in range(2):
+        for eq in range(2):
+            for er in range(2):
+                for es in range(2):
+                    names.append(f"ab_{ov[ep]}{ov[eq]}|{ov[er]}{ov[es]}")
+    return names
+
+
+def dim_closed_form(norb: int, nalpha: int, nbeta: int, level: int) -> int:
+    """sum over ka + kb <= level of C(na,ka) C(norb-na,ka) C(nb,kb) C(norb-nb,kb)."""
+    tot = 0
+    for ka in range(0, nalpha + 1):
+        for kb in range(0, nbeta + 1):
+            if ka + kb <= level:
+                tot += (comb(nalpha, ka) * comb(norb - nalpha, ka)
+                        * comb(nbeta, kb) * comb(norb - nbeta, kb))
+    return tot
+
+
+def e_ref_closed_form(h, eri, nalpha: int, nbeta: int) -> float:
+    """E_ref = sum_i h_ii + 1/2 sum_ij [(ii|jj) - delta_{spin} (ij|ji)] over
+    the occupied spin orbitals of the reference (orbitals 0..n-1 per spin)."""
+    occ = [(i, 0) for i in range(nalpha)] + [(i, 1) for i in range(nbeta)]
+    e = sum(h[i, i] for i, _ in occ)
+    for i, si in occ:
+        for j, sj in occ:
+            e += 0.5 * eri[i, i, j, j]
+            if si == sj:
+                e -= 0.5 * eri[i, j, j, i]
+    return float(e)
+
+
+def dense_eigh(space: Space, h, eri, tau: float):
+    H = dense_h(space, h, eri, tau)
+    return np.linalg.eigh(H)
+
+
+def davidson(space: Space, h, eri, tau: float, nroots: int = 1, tol: float = 1e-8,
+             maxiter: int = 200, max_subspace: int | None = None, diagonal=None):
+    """Textbook Davidson (Davidson 1975) on the oracle sigma.
+
+    Returns (energies, vectors [nroots][dim], residual norms)."""
+    dim = space.dim
+    D = diag(space, h, eri, tau) if diagonal is None else diagonal
+    k = min(nroots, dim)
+    mmax = max_subspace or max(24, 8 * k)
+    mmax = min(mmax, dim)
+    order = np.argsort(D, kind="stable")
+    V = np.zeros((dim, min(dim, max(k, 2 * k))))
+    for i in range(V.shape[1]):
+        V[order[i], i] = 1.0
+    W = sigma(space, h, eri, tau, V.T).T
+    theta = None
+    rn = None
+    for _ in range(maxiter):
+        G = V.T @ W
+        G = 0.5 * (G + G.T)
+        th, y = np.linalg.eigh(G)
+        th, y = th[:k], y[:, :k]
+        X = V @ y
+        R = W @ y - X * th
+        rn = np.linalg.norm(R, axis=0)
+        theta = th
+        if np.all(rn <= tol):
+            return th, X.T, rn
+        new = []
+        for i in range(k):
+            if rn[i] <= tol:
+                continue
+            den = th[i] - D
+            den = np.where(np.abs(den) < 1e-8, np.copysign(1e-8, den), den)
+            new.append(R[:, i] / den)
+        if V.shape[1] + len(new) > mmax:
+            V = X.copy()
+            W = W @ y
+            Q, _ = np.linalg.qr(V)
+            # re-express W in the orthonormalised basis
+            W = sigma(space, h, eri, tau, Q.T).T
+            V = Q
+        add = []
+        for t in new:
+            for _rep in range(2):
+                t = t - V @ (V.T @ t)
+                for a in add:
+                    t = t - a * (a @ t)
+            nrm = np.linalg.norm(t)
+            if nrm > 1e-10:
+                add.append(t / nrm)
+        if not add:
+            break
+        A = np.stack(add, axis=1)
+        WA = sigma(space, h, eri, tau, A.T).T
+        V = np.hstack([V, A])
+        W = np.hstack([W, WA])
+    return theta, (V @ np.linalg.eigh(0.5 * (V.T @ W + W.T @ V))[1][:, :k]).T, rn

@@ -1,0 +1,36 @@
+"""Mutation check of the oracle pins: plant a mistake in the oracle (a
+compile-time switch in the C source), rebuild it into a temporary library
+and require that the pin suite rejects it.  Everything runs on the CPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = [
+    "ORC_PLANT_AB_SIGN",          # wrong sign of alpha-beta doubles
+    "ORC_PLANT_AB_INDEX",         # (pr|qs) instead of (pq|rs): transposed operand
+    "ORC_PLANT_SS_EXCHANGE",      # (pq|rs) + (ps|rq): wrong exchange sign
+    "ORC_PLANT_DROP_SS_SINGLE",   # dropped same-spin term of single excitations
+    "ORC_PLANT_SINGLE_NOSIGN",    # phase of single excitations ignored
+    "ORC_PLANT_DROP_AB_DIAG",     # dropped alpha-beta Coulomb term of the diagonal
+    "ORC_PLANT_KEEP_GE",          # keep rule |I| >= tau instead of |I| > tau
+]
+
+PINS = ("reference_energy or hermiticity or noninteracting or kronecker or rotation "
+        "or swap or strict or term_counts_integral")
+
+
+@pytest.mark.parametrize("macro", MUTANTS)
+def test_pins_reject_planted_mistake(macro, tmp_path):
+    sys.path.insert(0, ROOT)
+    from oracle.build import build
+    lib = build(out=str(tmp_path / f"liboracle_{macro}.so"), defines=[macro])
+    env = dict(os.environ, ISCI_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"pins did not catch {macro}:\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout

@@ -1,0 +1,366 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each check is an
+independent construction (closed forms, textbook linear algebra, the
+paper's printed numbers and worked examples, an integral-driven count).
+"""
+import os
+from itertools import combinations
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle as O
+from isci_inputs import recipe_a, recipe_b, recipe_random, random_vectors
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- P1
+def _table_norb():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table_norb.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        f = line.split()
+        rows.append((int(f[0]), int(f[1]), [None if x == "-" else int(x) for x in f[2:5]]))
+    return rows
+
+
+def test_table_norb_closed_form():
+    """Closed-form dimension reproduces every entry of the paper's table."""
+    rows = _table_norb()
+    assert len(rows) == 15
+    n = 0
+    for _R, norb, counts in rows:
+        for L, want in zip((2, 3, 4), counts):
+            if want is None:
+                continue
+            assert O.dim_closed_form(norb, 2, 2, L) == want
+            n += 1
+    assert n == 15 + 7 + 5
+
+
+@pytest.mark.parametrize("norb,L", [(106, 2), (142, 2), (106, 3), (250, 2)])
+def test_table_norb_enumeration(norb, L):
+    """The oracle's explicit string enumeration and row layout give the
+    paper's printed counts."""
+    want = {r[1]: r[2] for r in _table_norb()}[norb][L - 2]
+    S = O.Space(norb, 2, 2, L)
+    assert S.dim == want
+
+
+def _brute_dets(norb, na, nb, L):
+    out = []
+    for a in combinations(range(norb), na):
+        la = sum(x >= na for x in a)
+        for b in combinations(range(norb), nb):
+            lb = sum(x >= nb for x in b)
+            if la + lb <= L:
+                out.append((a, b))
+    return out
+
+
+@pytest.mark.parametrize("norb,na,nb,L", [(7, 2, 2, 2), (8, 2, 2, 3), (6, 3, 2, 2),
+                                          (6, 2, 2, 4), (5, 1, 2, 1), (6, 0, 2, 2),
+                                          (7, 3, 3, 6)])
+def test_layout_brute_force(norb, na, nb, L):
+    """Every determinant appears exactly once; rows are alpha strings in
+    (level, colex) order; each row holds a prefix of the beta order."""
+    S = O.Space(norb, na, nb, L)
+    dets = S.determinants()
+    brute = _brute_dets(norb, na, nb, L)
+    assert S.dim == len(brute) == len(set(dets))
+    assert set(dets) == set(brute)
+
+    def key(s, n):
+        return (sum(x >= n for x in s), tuple(sorted(s, reverse=True)))
+
+    ao, _ = S.strings(0)
+    bo, _ = S.strings(1)
+    ka = [key(tuple(r), na) for r in ao]
+    kb = [key(tuple(r), nb) for r in bo]
+    assert ka == sorted(ka) and kb == sorted(kb)
+    for i, (a, b) in enumerate(dets):
+        assert S.address(a, b) == i
+
+
+# ---------------------------------------------------------------- P2
+def _sign_examples():
+    m = {"a": 1, "b": 2, "c": 3, "d": 4}
+    for line in open(os.path.join(GOLDEN, "sign_examples.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        name, word, order, sign, res = [x.strip() for x in line.split("|")]
+        ops = [(tok[0], m[tok[1]]) for tok in word.split()]
+        yield name, ops, {"none": 0, "desc": -1, "asc": 1}[order], int(sign), [m[x] for x in res.split()]
+
+
+@pytest.mark.parametrize("ex", list(_sign_examples()), ids=lambda e: e[0])
+def test_paper_sign_examples(ex):
+    _name, ops, order, sign, res = ex
+    s, out = O.apply_word(ops, order)
+    assert (s, out) == (sign, res)
+
+
+def test_word_vanishing_cases():
+    # a contraction that does not match returns no string
+    assert O.apply_word([("-", 2), ("-", 1), ("+", 4), ("+", 3), ("+", 1)]) == (0, None)
+    assert O.apply_word([("+", 1), ("+", 1)]) == (0, None)
+
+
+# ---------------------------------------------------------------- P4
+@pytest.mark.parametrize("recipe", ["A", "B", "R"])
+@pytest.mark.parametrize("na,nb", [(2, 2), (3, 1), (1, 0)])
+def test_reference_energy_closed_form(recipe, na, nb):
+    norb = 7
+    h, eri = _ints(recipe, norb, 3)
+    S = O.Space(norb, na, nb, 2)
+    e0 = np.zeros((1, S.dim))
+    e0[0, 0] = 1.0
+    sig = O.sigma(S, h, eri, 0.0, e0, targets=[0])[0, 0]
+    assert abs(sig - O.e_ref_closed_form(h, eri, na, nb)) <= 1e-12 * max(1.0, abs(sig))
+
+
+def _ints(recipe, norb, seed):
+    if recipe == "A":
+        return recipe_a(norb, seed=seed)
+    if recipe == "B":
+        return recipe_b(norb, seed=seed)
+    return recipe_random(norb, seed=seed)
+
+
+# ---------------------------------------------------------------- P5
+@pytest.mark.parametrize("recipe", ["A", "B", "R"])
+@pytest.mark.parametrize("norb,na,nb,L,tau", [(7, 2, 2, 2, 0.0), (7, 2, 2, 3, 1e-6),
+                                              (6, 3, 2, 3, 0.0), (8, 2, 2, 4, 1e-3)])
+def test_hermiticity(recipe, norb, na, nb, L, tau):
+    h, eri = _ints(recipe, norb, 5)
+    S = O.Space(norb, na, nb, L)
+    H = O.dense_h(S, h, eri, tau)
+    assert np.abs(H - H.T).max() <= 1e-13 * np.abs(H).max()
+    u, v = random_vectors(S.dim, 2, 9)
+    su, sv = O.sigma(S, h, eri, tau, np.stack([u, v]))
+    assert abs(u @ sv - v @ su) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * np.abs(H).max()
+
+
+# ---------------------------------------------------------------- P7
+def test_noninteracting_limit():
+    """eri = 0: FCI ground energy is the sum of the lowest na + nb orbital
+    energies, and the alpha one-body action on the antisymmetric pair
+    tensor is T' = h T + T h^T."""
+    norb = 7
+    h, _ = recipe_random(norb, seed=2)
+    eri = np.zeros((norb,) * 4)
+    S = O.Space(norb, 2, 2, 4)
+    w = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))
+    eps = np.linalg.eigvalsh(h)
+    assert abs(w[0] - (2 * eps[:2].sum())) <= 1e-11
+
+    # pair-tensor check on one vector
+    dets = S.determinants()
+    c = random_vectors(S.dim, 1, 4)[0]
+    T = np.zeros((norb, norb, norb, norb))
+    for val, ((a1, a2), (b1, b2)) in zip(c, dets):
+        for (x, y, sa) in ((a1, a2, 1), (a2, a1, -1)):
+            for (u, v, sb) in ((b1, b2, 1), (b2, b1, -1)):
+                T[x, y, u, v] = sa * sb * val
+    Tp = (np.einsum("pq,qbcd->pbcd", h, T) + np.einsum("pq,aqcd->apcd", h, T)
+          + np.einsum("pq,abqd->abpd", h, T) + np.einsum("pq,abcq->abcp", h, T))
+    sig = O.sigma(S, h, eri, 0.0, c[None])[0]
+    want = np.array([Tp[a1, a2, b1, b2] for ((a1, a2), (b1, b2)) in dets])
+    assert np.abs(sig - want).max() <= 1e-12 * np.abs(want).max()
+
+
+# ---------------------------------------------------------------- P8
+@pytest.mark.parametrize("seed", [0, 1])
+def test_one_electron_per_spin_kronecker(seed):
+    """na = nb = 1 FCI: H = h (x) 1 + 1 (x) h + G, G[(p,r),(q,s)] = (pq|rs).
+    With an unstructured eri this fixes the integral index order."""
+    norb = 6
+    h, eri = recipe_random(norb, seed=seed)
+    S = O.Space(norb, 1, 1, 2)
+    H = O.dense_h(S, h, eri, 0.0)
+    dets = S.determinants()
+    idx = [a[0] * norb + b[0] for a, b in dets]
+    I = np.eye(norb)
+    K = np.kron(h, I) + np.kron(I, h) + eri.transpose(0, 2, 1, 3).reshape(norb * norb, norb * norb)
+    K = K[np.ix_(idx, idx)]
+    assert np.abs(H - K).max() <= 1e-13
+
+
+# ---------------------------------------------------------------- P9
+def test_fci_orbital_rotation_invariance():
+    norb = 6
+    h, eri = recipe_random(norb, seed=7)
+    rng = np.random.default_rng(3)
+    U, _ = np.linalg.qr(rng.normal(size=(norb, norb)))
+    h2 = U.T @ h @ U
+    eri2 = np.einsum("pqrs,pi,qj,rk,sl->ijkl", eri, U, U, U, U, optimize=True)
+    S = O.Space(norb, 2, 2, 4)
+    w1 = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))
+    w2 = np.linalg.eigvalsh(O.dense_h(S, h2, eri2, 0.0))
+    assert np.abs(w1 - w2).max() <= 1e-10
+
+
+def test_fci_orbital_rotation_invariance_unequal_spins():
+    norb = 6
+    h, eri = recipe_random(norb, seed=8)
+    rng = np.random.default_rng(4)
+    U, _ = np.linalg.qr(rng.normal(size=(norb, norb)))
+    h2 = U.T @ h @ U
+    eri2 = np.einsum("pqrs,pi,qj,rk,sl->ijkl", eri, U, U, U, U, optimize=True)
+    S = O.Space(norb, 3, 1, 4)
+    w1 = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))
+    w2 = np.linalg.eigvalsh(O.dense_h(S, h2, eri2, 0.0))
+    assert np.abs(w1 - w2).max() <= 1e-10
+
+
+# ---------------------------------------------------------------- P10
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_alpha_beta_swap_covariance(L):
+    norb = 7
+    h, eri = recipe_random(norb, seed=11)
+    S = O.Space(norb, 2, 2, L)
+    dets = S.determinants()
+    pos = {d: i for i, d in enumerate(dets)}
+    perm = np.array([pos[(b, a)] for a, b in dets])
+    c = random_vectors(S.dim, 1, 2)[0]
+    s1 = O.sigma(S, h, eri, 1e-3, c[perm][None])[0]
+    s2 = O.sigma(S, h, eri, 1e-3, c[None])[0][perm]
+    assert np.abs(s1 - s2).max() <= 1e-12 * np.abs(s2).max()
+
+
+# ---------------------------------------------------------------- P6
+@pytest.mark.parametrize("recipe,norb,L", [("A", 10, 4), ("B", 12, 2), ("A", 14, 2), ("B", 9, 3)])
+def test_davidson_matches_dense(recipe, norb, L):
+    h, eri = _ints(recipe, norb, 1)
+    S = O.Space(norb, 2, 2, L)
+    w = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))
+    e, X, rn = O.davidson(S, h, eri, 0.0, nroots=2, tol=1e-9)
+    assert np.all(rn <= 1e-9)
+    assert np.abs(e - w[:2]).max() <= 1e-12 * max(1.0, abs(w[0])) + 1e-13
+
+
+# ---------------------------------------------------------------- P11
+@pytest.mark.parametrize("tau", [1e-6, 1e-4, 1e-2])
+def test_screening_bound(tau):
+    """Weyl: |lambda_k(H_0) - lambda_k(H_tau)| <= ||H_0 - H_tau||_2 <= B(tau)."""
+    h, eri = recipe_a(10, seed=2)
+    S = O.Space(10, 2, 2, 3)
+    w0 = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))
+    wt = np.linalg.eigvalsh(O.dense_h(S, h, eri, tau))
+    B = O.dropped_bound(S, h, eri, tau)
+    D = O.dense_h(S, h, eri, 0.0) - O.dense_h(S, h, eri, tau)
+    # D carries the rounding of two dense sums; allow for it
+    assert B >= np.abs(D).sum(axis=1).max() - 1e-13
+    assert np.abs(w0 - wt).max() <= B + 1e-13
+    if tau >= 1e-4:
+        assert B > 0.0
+
+
+def test_screening_tau_zero_is_exact():
+    """tau = 0 drops only exact zeros, which contribute nothing."""
+    h, eri = recipe_a(9, seed=3)
+    eri = eri.copy()
+    eri[np.abs(eri) < 1e-9] = 0.0
+    S = O.Space(9, 2, 2, 3)
+    assert O.dropped_bound(S, h, eri, 0.0) == 0.0
+
+
+def test_strict_threshold():
+    """A unit exactly equal to tau is dropped (keep rule |I| > tau)."""
+    norb = 5
+    h, eri = recipe_random(norb, seed=5)
+    tau = abs(h[3, 1])
+    S = O.Space(norb, 1, 0, 1)
+    H = O.dense_h(S, h, eri, tau)
+    # one alpha electron, no beta: H is h restricted to the (level<=1) space
+    ao, _ = S.strings(0)
+    idx = [int(r[0]) for r in ao]
+    want = h[np.ix_(idx, idx)].copy()
+    want[np.abs(want) <= tau] = 0.0
+    assert np.array_equal(H, want)
+
+
+# ---------------------------------------------------------------- P12
+def _integral_driven_counts(h, eri, norb, L, tau):
+    """Independent count for na = nb = 2, written in the paper's loop
+    order: integral indices outside, spectator strings inside."""
+    n = 2
+    e = (np.arange(norb) >= n).astype(int)
+    # number of beta strings with level <= l
+    nb_le = [sum(comb(n, n - k) * comb(norb - n, k) for k in range(0, min(l, 2) + 1)) if l >= 0 else 0
+             for l in range(0, 5)]
+
+    def nble(l):
+        return nb_le[l] if l >= 0 else 0
+
+    one = 0
+    for p in range(norb):
+        for q in range(norb):
+            if abs(h[max(p, q), min(p, q)]) <= tau:
+                continue
+            for x in range(norb):
+                if x in (p, q):
+                    continue
+                la = max(e[x] + e[p], e[x] + e[q])
+                one += nble(L - la)
+    one *= 2  # alpha and beta
+    ss = 0
+    for p in range(norb):
+        for r in range(p):
+            for q in range(norb):
+                for s in range(q):
+                    val = eri[p, q, r, s] - eri[p, s, r, q]
+                    if abs(val) <= tau:
+                        continue
+                    la = max(e[p] + e[r], e[q] + e[s])
+                    ss += nble(L - la)
+    ss *= 2
+    ab = 0
+    ex = e
+    for p in range(norb):
+        for q in range(norb):
+            for r in range(norb):
+                for s in range(norb):
+                    if abs(eri[p, q, r, s]) <= tau:
+                        continue
+                    for x in range(norb):
+                        if x in (p, q):
+                            continue
+                        for y in range(norb):
+                            if y in (r, s):
+                                continue
+                            src = ex[x] + ex[q] + ex[y] + ex[s]
+                            dst = ex[x] + ex[p] + ex[y] + ex[r]
+                            if src <= L and dst <= L:
+                                ab += 1
+    return one, ss, ab
+
+
+@pytest.mark.parametrize("recipe,norb,L,tau", [("R", 6, 2, 0.0), ("B", 7, 3, 1e-3), ("A", 8, 2, 1e-6)])
+def test_term_counts_integral_driven(recipe, norb, L, tau):
+    h, eri = _ints(recipe, norb, 3)
+    S = O.Space(norb, 2, 2, L)
+    kept, allc = O.terms(S, h, eri, tau)
+    one, ss, ab = _integral_driven_counts(h, eri, norb, L, tau)
+    assert kept[0:8].sum() == one
+    assert kept[8:26].sum() == ss
+    assert kept[26:42].sum() == ab
+    if tau == 0.0:
+        assert np.array_equal(kept, allc)
+    assert len(O.bucket_names()) == 42
+
+
+def test_term_count_alpha_beta_swap_symmetry():
+    h, eri = recipe_b(8, seed=4)
+    S = O.Space(8, 2, 2, 3)
+    kept, _ = O.terms(S, h, eri, 1e-8)
+    assert np.array_equal(kept[0:4], kept[4:8])
+    assert np.array_equal(kept[8:17], kept[17:26])
+    ab = kept[26:42].reshape(2, 2, 2, 2)
+    assert np.array_equal(ab, ab.transpose(2, 3, 0, 1))
