@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the ISCI sigma step on one MI355X.
+
+A step is one sigma product sigma = H_tau c over a block of nvec vectors
+of the named workload (default: CISDT, 4 electrons, 60 orbitals in a 60
+bohr box, 120 auxiliary points, tau = 1e-14, nvec = 8), with inputs
+resident in HBM.  Prints one JSON line with sigma-vectors/s, screened
+terms/s, the roofline position of the dominant kernel (timed with HIP
+events on the launch stream), a CPU-oracle baseline timed on a bounded
+sample of target determinants, and p50/p99 of Davidson solve latency on
+the small CISD workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+METRIC = "σ-vectors/s + screened terms/s (% roofline); p50/p99 Davidson solve latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cisdt_n60")
+    ap.add_argument("--nvec", type=int, default=None)
+    ap.add_argument("--tau", type=float, default=None)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--skip-davidson", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sigma_traffic.json"),
+                    help="HBM bytes per launch from rocprofv3 counters (optional)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the sigma step on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1609_07757_amd as isci
+    from isci_inputs import random_vectors, workload
+
+    W = workload(a.workload)
+    nvec = a.nvec or W.nvec
+    tau = W.tau if a.tau is None else a.tau
+    dev = torch.device("cuda:0")
+    h, eri = W.integrals()
+    hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb,
+                          W.nalpha, W.nbeta, W.level, tau)
+    st = isci.isci_get_stats(hd)
+    dim = hd.dim
+    c = torch.from_numpy(random_vectors(dim, nvec, seed=21)).to(dev)
+    sg = torch.empty_like(c)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        isci.isci_sigma(hd, c, sg, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(a.steps):
+        isci.isci_sigma(hd, c, sg, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    ms_per_step = ev_ms / a.steps
+    nlaunch = (nvec + 7) // 8           # sigma kernel launches per step (8 vectors per launch)
+    terms = int(st["terms_total"])
+    flops_step = 2.0 * terms * nvec
+    sig_per_s = nvec * a.steps / (ev_ms * 1e-3)
+    terms_per_s = terms * nvec * a.steps / (ev_ms * 1e-3)
+    achieved = flops_step / (ms_per_step * 1e-3) / 1e12   # TFLOP/s of the sigma kernel launch(es)
+    traffic = None
+    if os.path.exists(a.traffic_json):
+        try:
+            tj = json.load(open(a.traffic_json))
+            key = f"{a.workload}:nvec{nvec}:tau{tau:g}"
+            if key in tj and tj[key].get("kernel_version") == "k_sigma_generic":
+                traffic = tj[key]["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": sig_per_s,
+        "unit": "σ-vectors/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (recipe A 1D local-orbital integrals, seeded)",
+        "config": {"workload": a.workload, "norb": W.norb, "nalpha": W.nalpha, "nbeta": W.nbeta,
+                   "max_excitation": W.level, "tau": tau, "nvec": nvec, "dim": dim,
+                   "box": W.box_len, "naux": W.n_aux, "seed": W.seed},
+        "screened_terms_per_s": terms_per_s,
+        "terms_per_vector": terms,
+        "kept_integral_units": int(st["kept_total"]),
+        "wall_s_timed": wall,
+        "roofline": {"bound": "alu", "kernel": "k_sigma_generic", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic, "launches_per_step": nlaunch,
+                     "algorithmic_flops_per_step": flops_step},
+    }
+    if not a.skip_davidson:
+        out["davidson"] = davidson_latency(isci, torch, dev)
+    if not a.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, h, eri, tau, nvec, dim, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def davidson_latency(isci, torch, dev, reps=9):
+    """p50 / p99 latency of a full Davidson solve (create excluded) on the
+    plain CISD workload (20 orbitals, lowest root)."""
+    import numpy as np
+    from isci_inputs import workload
+    W = workload("cisd_n20")
+    h, eri = W.integrals()
+    hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb, 2, 2,
+                          W.level, W.tau)
+    lat, en, iters = [], None, 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, _, info = isci.isci_davidson(hd, nroots=1)
+        lat.append(time.perf_counter() - t0)
+        en, iters = float(e[0]), info["iterations"]
+    lat = np.array(lat) * 1e3
+    return {"workload": "cisd_n20", "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "energy": en, "iterations": iters, "solves": reps}
+
+
+def cpu_baseline(W, h, eri, tau, nvec, dim, seconds):
+    """The CPU oracle (plain Slater-Condon, OpenMP over targets) timed on a
+    bounded sample of target determinants of the same workload, scaled to
+    sigma-vectors/s."""
+    import numpy as np
+    import oracle as O
+    from isci_inputs import random_vectors
+    S = O.Space(W.norb, W.nalpha, W.nbeta, W.level)
+    c = random_vectors(dim, nvec, seed=21)
+    rng = np.random.default_rng(0)
+    n = 64
+    t = 0.0
+    while True:
+        tg = np.sort(rng.choice(dim, size=min(n, dim), replace=False))
+        t0 = time.perf_counter()
+        O.sigma(S, h, eri, tau, c, targets=tg)
+        t = time.perf_counter() - t0
+        if t >= seconds or n >= dim:
+            break
+        n = int(min(dim, max(2 * n, n * seconds / max(t, 1e-3) * 1.05)))
+    frac = len(tg) / dim
+    value = nvec * frac / t
+    return {"value": value, "unit": "σ-vectors/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{len(tg)} of {dim} target determinants (random, seed 0), nvec={nvec}, "
+                      f"{t:.1f} s; scaled by dim/sample"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * isci.h -- C ABI of libisci, an FP64 implementation for AMD MI355X
+ * (gfx950) of the sigma-vector step sigma = H c of the Integral Screened
+ * Configuration Interaction method (Sorensen, Bauch & Madsen, "The
+ * Integral Screened Configuration Interaction Method"), plus the
+ * eigensolver around it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Hamiltonian: Eq. ham / index_un of the paper, spin-restricted orbitals:
+ *   H = sum_pq h_pq (E^a_pq + E^b_pq)
+ *     + 1/2 sum_pqrs (pq|rs) sum_{s,s'} a+_{p s} a+_{r s'} a_{s s'} a_{q s},
+ * with g_pqrs = (pq|rs) in chemists' order.  h is read from its lower
+ * triangle (p >= q) and eri from its canonical element (p>=q, r>=s,
+ * (p,q) >= (r,s) lexicographically); the other positions are never read,
+ * so the caller may pass a tensor that is only filled there.
+ *
+ * Screening (section "The ISCI and Integral screening", Eqs. sigma_int
+ * and sigma_split): every elementary integral unit with |unit| <= tau is
+ * removed from H (ties at exactly tau are dropped).  The units are h_pq
+ * (one-body), the antisymmetrised same-spin coefficient (pq|rs) - (ps|rq)
+ * formed by one subtraction (Eq. index_re), and the raw (pq|rs) of the
+ * alpha-beta class.  tau = 0 keeps every non-zero unit.
+ *
+ * CI space (Eqs. ci_ansatz, ci_hierarchy): the reference occupies
+ * orbitals 0..n-1 of each spin; the level of a string is its number of
+ * electrons in orbitals >= n; the space holds every (alpha, beta) string
+ * pair with level_a + level_b <= max_excitation (2 CISD, 3 CISDT, 4
+ * CISDTQ; a value >= na + nb gives full CI).
+ *
+ * Vector layout (all vectors, device memory, FP64): per spin the strings
+ * (ascending orbital sets) are sorted by (level, colex order -- highest
+ * orbital compared first).  Rows are alpha strings in that order; the row
+ * of an alpha string of level k holds the beta strings of level
+ * <= max_excitation - k, which is a prefix of the beta order.  The
+ * determinant |Ia Ib> = (prod_{p in Ia, ascending} a+_{p alpha})
+ * (prod_{q in Ib, ascending} a+_{q beta}) |vac> sits at
+ * rowstart(Ia) + index(Ib).  isci_strings / isci_rowstart export the
+ * tables so a caller can map by occupation.
+ *
+ * Streams and ownership: device pointers belong to the caller.  Every
+ * entry point that takes a stream enqueues its work on that stream in
+ * stream order and returns without synchronising, except isci_create
+ * (one synchronisation to size the screened lists) and isci_davidson
+ * (one small device-to-host copy per iteration, and a final
+ * synchronisation).  A handle owns its device tables and frees them in
+ * isci_destroy.  A handle is not thread safe; distinct handles may be
+ * used concurrently on distinct streams.
+ *
+ * Errors: functions return an isci_status and never throw.  Argument
+ * errors are detected before anything is enqueued.  isci_last_error()
+ * returns a per-thread message for the last failure.
+ *
+ * Limits of this build: norb <= 255, 0 <= na, nb <= 4, dim < 2^62,
+ * nvec >= 1 (vectors are processed in chunks of 8).
+ */
+#ifndef ISCI_H
+#define ISCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isci_ctx *isci_handle;
+
+typedef enum {
+    ISCI_OK = 0,
+    ISCI_E_INVALID = -1,        /* bad argument; nothing was enqueued */
+    ISCI_E_OOM = -2,            /* device allocation failed */
+    ISCI_E_HIP = -3,            /* a HIP runtime call failed */
+    ISCI_E_NOT_CONVERGED = -4,  /* Davidson hit max_iter; best estimates returned */
+    ISCI_E_UNSUPPORTED = -5     /* outside the limits of this build */
+} isci_status;
+
+#define ISCI_NBUCKET 42
+#define ISCI_MAX_ROOTS 32
+
+/* Screening statistics.  Buckets follow the paper's Hamiltonian classes
+ * (Eqs. class_to_ex_dx .. the_end): 0..3 one-body alpha and 4..7 one-body
+ * beta indexed 2 e_p + e_q; 8..16 same-spin alpha and 17..25 same-spin
+ * beta indexed 3 (#virtual creators) + (#virtual annihilators); 26..41
+ * alpha-beta indexed 8 e_p + 4 e_q + 2 e_r + e_s, where e_x = 1 if orbital
+ * x is virtual for its spin (x >= n).  kept[b] counts kept integral units
+ * (one-body (p,q) pairs, same-spin (p>r, q>s) pairs, alpha-beta (p,q,r,s)
+ * quadruples); terms[b] counts the (unit, source determinant, target
+ * determinant) products one sigma vector performs -- the paper's
+ * operation-count unit. */
+typedef struct {
+    int64_t dim;
+    int64_t nstr_alpha, nstr_beta;
+    int64_t kept[ISCI_NBUCKET];
+    int64_t terms[ISCI_NBUCKET];
+    int64_t kept_total;
+    int64_t terms_total;
+    int64_t device_bytes;       /* bytes of device memory owned by the handle */
+} isci_stats;
+
+typedef struct {
+    double tol_residual;        /* converged when every root has ||r||_2 <= this (default 1e-7) */
+    double tol_energy;          /* ... and |dE| <= this between iterations (default 1e-11) */
+    int max_iter;               /* default 200 */
+    int max_subspace;           /* default max(32, 6 (nroots + 2)) */
+    int block;                  /* correction vectors per iteration (default nroots + 2) */
+} isci_davidson_opts;
+
+typedef struct {
+    int iterations;
+    int converged;              /* 1 if every root met both tolerances */
+    int sigma_calls;            /* sigma vectors computed */
+    double residual[ISCI_MAX_ROOTS];
+} isci_davidson_info;
+
+/* Set defaults in *o. */
+void isci_davidson_defaults(isci_davidson_opts *o);
+
+/* Build a handle: validate, enumerate strings and the row layout, build
+ * the screened integral lists on the device (one pass over h and eri),
+ * count kept units and sigma terms per bucket, and tabulate the diagonal
+ * units.  h: device [norb*norb]; eri: device [norb^4] ((pq|rs) at
+ * ((p*norb+q)*norb+r)*norb+s).  Both are only read during this call (in
+ * stream order; the call synchronises the stream before returning). */
+isci_status isci_create(isci_handle *out, const double *h, const double *eri, int norb,
+                        int nalpha, int nbeta, int max_excitation, double tau,
+                        hipStream_t stream);
+
+/* Number of determinants. */
+isci_status isci_dim(isci_handle hd, int64_t *dim);
+
+/* sigma[v*lds + I] = sum_J (H_tau)_IJ c[v*ldc + J] for v < nvec, all I
+ * (Eq. sigma).  c and sigma are device arrays of nvec vectors with leading
+ * dimensions ldc, lds >= dim; sigma is overwritten and must not overlap c.
+ * Asynchronous on `stream`. */
+isci_status isci_sigma(isci_handle hd, int nvec, const double *c, int64_t ldc,
+                       double *sigma, int64_t lds, hipStream_t stream);
+
+/* diag[I] = (H_tau)_II (the diagonal units kept by the same rule).
+ * Device array of length dim.  Asynchronous. */
+isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
+
+/* Lowest nroots eigenpairs by block Davidson (FP64, device resident; the
+ * small projected eigenproblem is solved on the host).  guess: device
+ * [nguess][dim] or NULL (unit vectors on the lowest diagonal entries,
+ * ties to the lowest address).  energies: host [nroots].  vectors: device
+ * [nroots][dim] or NULL.  info may be NULL.  Returns ISCI_E_NOT_CONVERGED
+ * with the best estimates when max_iter is reached. */
+isci_status isci_davidson(isci_handle hd, int nroots, const isci_davidson_opts *opts,
+                          const double *guess, int nguess, double *energies, double *vectors,
+                          isci_davidson_info *info, hipStream_t stream);
+
+/* Host copies of the string tables: orbitals [nstr][n] (ascending) and
+ * level [nstr] in layout order; either pointer may be NULL.  spin 0 is
+ * alpha, 1 beta. */
+isci_status isci_strings(isci_handle hd, int spin, int32_t *orbitals, int32_t *level,
+                         int64_t *nstr);
+
+/* Host copy of the row starts: rowstart[nstr_alpha + 1]. */
+isci_status isci_rowstart(isci_handle hd, int64_t *rowstart);
+
+/* Screening statistics (host struct). */
+isci_status isci_get_stats(isci_handle hd, isci_stats *s);
+
+void isci_destroy(isci_handle hd);
+const char *isci_status_string(isci_status s);
+const char *isci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISCI_H */

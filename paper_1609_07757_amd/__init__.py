@@ -1,0 +1,194 @@
+"""MI355X (gfx950) FP64 library for the sigma step of Integral Screened
+Configuration Interaction (Sorensen, Bauch & Madsen).
+
+The compute lives in ``libisci.so`` (HIP kernels behind the C ABI of
+``include/isci.h``).  This module is a thin binding with the same entry
+point names; PyTorch only supplies device memory (tensors) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import IsciDavidsonInfo, IsciDavidsonOpts, IsciError, IsciStats, check
+
+__all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
+           "isci_strings", "isci_rowstart", "isci_get_stats", "isci_destroy", "IsciError",
+           "lib_path", "BUCKET_NAMES"]
+
+
+def lib_path() -> str:
+    return _lib.LIBPATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev_f64(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns an isci_handle; destroyed with the object or by isci_destroy."""
+
+    def __init__(self, ptr, norb, nalpha, nbeta, level, tau):
+        self._ptr = ptr
+        self.norb, self.nalpha, self.nbeta, self.level, self.tau = norb, nalpha, nbeta, level, tau
+        self.dim = isci_dim(self)
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("handle destroyed")
+        return self._ptr
+
+    def destroy(self):
+        if self._ptr is not None:
+            _lib.load().isci_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
+                stream=None) -> Handle:
+    L = _lib.load()
+    hp = _dev_f64(h, "h")
+    ep = _dev_f64(eri, "eri")
+    if h.numel() != norb * norb or eri.numel() != norb ** 4:
+        raise ValueError("h must hold norb^2 and eri norb^4 elements")
+    out = ctypes.c_void_p()
+    st = L.isci_create(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
+                       int(max_excitation), float(tau), _stream_ptr(stream))
+    check(st, "isci_create")
+    return Handle(out, norb, nalpha, nbeta, max_excitation, tau)
+
+
+def isci_dim(hd: Handle) -> int:
+    d = ctypes.c_int64()
+    check(_lib.load().isci_dim(hd.ptr, ctypes.byref(d)), "isci_dim")
+    return int(d.value)
+
+
+def isci_sigma(hd: Handle, c, sigma=None, stream=None):
+    """sigma = H_tau c for c of shape [nvec, dim] (or [dim]); returns sigma."""
+    torch = _torch()
+    squeeze = c.dim() == 1
+    c2 = c.unsqueeze(0) if squeeze else c
+    if c2.shape[-1] != hd.dim:
+        raise ValueError("c has wrong length")
+    if sigma is None:
+        sigma = torch.empty_like(c2)
+    s2 = sigma.unsqueeze(0) if sigma.dim() == 1 else sigma
+    st = _lib.load().isci_sigma(hd.ptr, int(c2.shape[0]), _dev_f64(c2, "c"), int(c2.stride(0)),
+                                _dev_f64(s2, "sigma"), int(s2.stride(0)), _stream_ptr(stream))
+    check(st, "isci_sigma")
+    return sigma.squeeze(0) if (squeeze and sigma.dim() == 2) else sigma
+
+
+def isci_diag(hd: Handle, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(hd.dim, dtype=torch.float64, device="cuda")
+    check(_lib.load().isci_diag(hd.ptr, _dev_f64(out, "diag"), _stream_ptr(stream)), "isci_diag")
+    return out
+
+
+def isci_davidson(hd: Handle, nroots: int = 1, tol_residual: float = 1e-7, tol_energy: float = 1e-11,
+                  max_iter: int = 200, max_subspace: int = 0, block: int = 0, guess=None,
+                  want_vectors: bool = False, stream=None, raise_on_nonconv: bool = True):
+    """Lowest nroots eigenpairs.  Returns (energies ndarray, vectors or None, info dict)."""
+    torch = _torch()
+    L = _lib.load()
+    o = IsciDavidsonOpts()
+    L.isci_davidson_defaults(ctypes.byref(o))
+    o.tol_residual, o.tol_energy, o.max_iter = tol_residual, tol_energy, max_iter
+    o.max_subspace, o.block = max_subspace, block
+    en = (ctypes.c_double * nroots)()
+    info = IsciDavidsonInfo()
+    vec = torch.empty((nroots, hd.dim), dtype=torch.float64, device="cuda") if want_vectors else None
+    gp, ng = ctypes.c_void_p(0), 0
+    if guess is not None:
+        gp, ng = _dev_f64(guess, "guess"), int(guess.shape[0])
+    st = L.isci_davidson(hd.ptr, int(nroots), ctypes.byref(o), gp, ng, en,
+                         _dev_f64(vec, "vectors") if vec is not None else ctypes.c_void_p(0),
+                         ctypes.byref(info), _stream_ptr(stream))
+    inf = {"iterations": info.iterations, "converged": bool(info.converged),
+           "sigma_calls": info.sigma_calls, "residual": list(info.residual)[:nroots], "status": st}
+    if st != _lib.ISCI_OK and not (st == _lib.ISCI_E_NOT_CONVERGED and not raise_on_nonconv):
+        check(st, "isci_davidson")
+    return np.array(list(en)), vec, inf
+
+
+def isci_strings(hd: Handle, spin: int):
+    """(orbitals [nstr][n] int32, level [nstr] int32) in layout order."""
+    L = _lib.load()
+    ns = ctypes.c_int64()
+    check(L.isci_strings(hd.ptr, int(spin), None, None, ctypes.byref(ns)), "isci_strings")
+    n = hd.nbeta if spin else hd.nalpha
+    orb = np.zeros((ns.value, max(n, 1)), dtype=np.int32)
+    lev = np.zeros(ns.value, dtype=np.int32)
+    check(L.isci_strings(hd.ptr, int(spin), orb.ctypes.data_as(ctypes.c_void_p),
+                         lev.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns)), "isci_strings")
+    return orb[:, :n].copy(), lev
+
+
+def isci_rowstart(hd: Handle):
+    na = isci_get_stats(hd)["nstr_alpha"]
+    rs = np.zeros(na + 1, dtype=np.int64)
+    check(_lib.load().isci_rowstart(hd.ptr, rs.ctypes.data_as(ctypes.c_void_p)), "isci_rowstart")
+    return rs
+
+
+def isci_get_stats(hd: Handle) -> dict:
+    s = IsciStats()
+    check(_lib.load().isci_get_stats(hd.ptr, ctypes.byref(s)), "isci_get_stats")
+    return {"dim": s.dim, "nstr_alpha": s.nstr_alpha, "nstr_beta": s.nstr_beta,
+            "kept": np.array(list(s.kept), dtype=np.int64), "terms": np.array(list(s.terms), dtype=np.int64),
+            "kept_total": s.kept_total, "terms_total": s.terms_total, "device_bytes": s.device_bytes}
+
+
+def isci_destroy(hd: Handle):
+    hd.destroy()
+
+
+def _bucket_names():
+    names = []
+    ov = "ov"
+    for spin in "ab":
+        for ep in range(2):
+            for eq in range(2):
+                names.append(f"1b_{spin}_{ov[ep]}{ov[eq]}")
+    for spin in ("aa", "bb"):
+        for nc in range(3):
+            for na in range(3):
+                names.append(f"ss_{spin}_c{nc}a{na}")
+    for ep in range(2):
+        for eq in range(2):
+            for er in range(2):
+                for es in range(2):
+                    names.append(f"ab_{ov[ep]}{ov[eq]}|{ov[er]}{ov[es]}")
+    return names
+
+
+BUCKET_NAMES = _bucket_names()

@@ -1,0 +1,102 @@
+"""ctypes binding of libisci (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts
+Python / torch arguments to pointers, sizes and streams and maps status
+codes to exceptions.  If libisci.so is missing the import fails loudly --
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libisci.so")
+
+NBUCKET = 42
+MAX_ROOTS = 32
+
+ISCI_OK = 0
+ISCI_E_INVALID = -1
+ISCI_E_OOM = -2
+ISCI_E_HIP = -3
+ISCI_E_NOT_CONVERGED = -4
+ISCI_E_UNSUPPORTED = -5
+
+# Exported symbols declared in include/isci.h.
+ABI_SYMBOLS = (
+    "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
+    "isci_davidson_defaults", "isci_strings", "isci_rowstart", "isci_get_stats",
+    "isci_destroy", "isci_status_string", "isci_last_error",
+)
+
+
+class IsciStats(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int64), ("nstr_alpha", ctypes.c_int64), ("nstr_beta", ctypes.c_int64),
+                ("kept", ctypes.c_int64 * NBUCKET), ("terms", ctypes.c_int64 * NBUCKET),
+                ("kept_total", ctypes.c_int64), ("terms_total", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class IsciDavidsonOpts(ctypes.Structure):
+    _fields_ = [("tol_residual", ctypes.c_double), ("tol_energy", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int), ("block", ctypes.c_int)]
+
+
+class IsciDavidsonInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("sigma_calls", ctypes.c_int),
+                ("residual", ctypes.c_double * MAX_ROOTS)]
+
+
+class IsciError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def load(path: str = LIBPATH):
+    """Load libisci.so and declare its signatures."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"libisci.so not built ({path}); run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.isci_create.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i32, i32, dbl, vp]
+    L.isci_create.restype = i32
+    L.isci_dim.argtypes = [vp, ctypes.POINTER(i64)]
+    L.isci_dim.restype = i32
+    L.isci_sigma.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.isci_sigma.restype = i32
+    L.isci_diag.argtypes = [vp, vp, vp]
+    L.isci_diag.restype = i32
+    L.isci_davidson.argtypes = [vp, i32, ctypes.POINTER(IsciDavidsonOpts), vp, i32,
+                                ctypes.POINTER(dbl), vp, ctypes.POINTER(IsciDavidsonInfo), vp]
+    L.isci_davidson.restype = i32
+    L.isci_davidson_defaults.argtypes = [ctypes.POINTER(IsciDavidsonOpts)]
+    L.isci_davidson_defaults.restype = None
+    L.isci_strings.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
+    L.isci_strings.restype = i32
+    L.isci_rowstart.argtypes = [vp, vp]
+    L.isci_rowstart.restype = i32
+    L.isci_get_stats.argtypes = [vp, ctypes.POINTER(IsciStats)]
+    L.isci_get_stats.restype = i32
+    L.isci_destroy.argtypes = [vp]
+    L.isci_destroy.restype = None
+    L.isci_status_string.argtypes = [i32]
+    L.isci_status_string.restype = ctypes.c_char_p
+    L.isci_last_error.argtypes = []
+    L.isci_last_error.restype = ctypes.c_char_p
+    _LIB = L
+    return L
+
+
+def check(status: int, what: str = "isci"):
+    if status != ISCI_OK:
+        L = load()
+        msg = L.isci_last_error().decode(errors="replace")
+        raise IsciError(status, f"{what}: {L.isci_status_string(status).decode()}: {msg}")

@@ -1,0 +1,104 @@
+// Device helpers shared by the libisci kernels: binomials, packed strings,
+// string ranks in (level, colex) order, phases, canonical integral reads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "isci_internal.h"
+
+namespace isci {
+
+// C(x, k) for 0 <= k <= 4 (exact: each partial product is a binomial).
+__host__ __device__ inline long long binom(int x, int k)
+{
+    if (k < 0 || x < k) return 0;
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (x - k + i) / i;
+    return r;
+}
+
+__host__ __device__ inline void unpack_str(uint32_t s, int n, int *o)
+{
+#pragma unroll
+    for (int i = 0; i < ISCI_MAXN; ++i)
+        if (i < n) o[i] = (s >> (8 * i)) & 0xff;
+}
+
+__host__ __device__ inline uint32_t pack_str(const int *o, int n)
+{
+    uint32_t s = 0;
+    for (int i = 0; i < n; ++i) s |= (uint32_t)o[i] << (8 * i);
+    return s;
+}
+
+// level = number of electrons in orbitals >= n
+__host__ __device__ inline int str_level(const int *o, int n)
+{
+    int l = 0;
+    for (int i = 0; i < n; ++i) l += (o[i] >= n);
+    return l;
+}
+
+// index of an ascending orbital list in (level, colex) order
+__host__ __device__ inline int str_index(const int *o, const SpinTab &T)
+{
+    const int n = T.n;
+    int ip = 0, io = 0;
+    long long rp = 0, ro = 0;
+    for (int i = 0; i < n; ++i) {
+        int x = o[i];
+        if (x >= n) { ++ip; rp += binom(x - n, ip); }
+        else        { ++io; ro += binom(x, io); }
+    }
+    return T.lev_off[ip] + (int)(rp * T.occ_mult[ip] + ro);
+}
+
+// (-1)^{#{x in o, x != o[skip], x < p}}: phase of a+_p acting on the
+// string o without element `skip` (skip = -1: none)
+__host__ __device__ inline int phase_below(const int *o, int n, int skip, int p)
+{
+    int c = 0;
+    for (int i = 0; i < n; ++i) c += (i != skip) & (o[i] < p);
+    return (c & 1) ? -1 : 1;
+}
+
+// o without element `skip`, then insert q (kept ascending) -> out; returns
+// false if q is already present among the kept elements.
+__host__ __device__ inline bool replace_one(const int *o, int n, int skip, int q, int *out)
+{
+    int k = 0;
+    bool placed = false;
+    for (int i = 0; i < n; ++i) {
+        if (i == skip) continue;
+        int x = o[i];
+        if (x == q) return false;
+        if (!placed && q < x) { out[k++] = q; placed = true; }
+        out[k++] = x;
+    }
+    if (!placed) out[k++] = q;
+    return true;
+}
+
+// canonical element of (pq|rs): p>=q, r>=s, (p,q) >= (r,s)
+__host__ __device__ inline size_t eri_canon(int n, int p, int q, int r, int s)
+{
+    int t;
+    if (p < q) { t = p; p = q; q = t; }
+    if (r < s) { t = r; r = s; s = t; }
+    if (p < r || (p == r && q < s)) { t = p; p = r; r = t; t = q; q = s; s = t; }
+    return (((size_t)p * n + q) * n + r) * n + s;
+}
+
+__device__ inline double geri(const double *eri, int n, int p, int q, int r, int s)
+{
+    return eri[eri_canon(n, p, q, r, s)];
+}
+
+__device__ inline double gh(const double *h, int n, int p, int q)
+{
+    return p >= q ? h[(size_t)p * n + q] : h[(size_t)q * n + p];
+}
+
+}  // namespace isci

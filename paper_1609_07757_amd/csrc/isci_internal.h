@@ -1,0 +1,119 @@
+// Internal definitions of libisci (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/isci.h"
+
+#define ISCI_MAXN 4          // electrons per spin handled by the kernels
+#define ISCI_MAXNORB 255     // orbitals fit in one byte
+#define ISCI_MAXLEV 8        // level tables sized for 2 * ISCI_MAXN
+
+namespace isci {
+
+// Binomial table C(x, k) for x < 256, k <= ISCI_MAXN (+1 for counting).
+constexpr int kBinomK = ISCI_MAXN + 1;
+
+// Strings of one spin, sorted by (level, colex).  Within level k the
+// index is lev_off[k] + colexrank(particles - n) * C(n, n - k)
+// + colexrank(kept occupied), colexrank({e_1 < ... < e_m}) = sum C(e_i, i).
+struct SpinTab {
+    int n;                       // electrons of this spin
+    int nocc;                    // reference occupied orbitals (= n)
+    int nvirt;                   // norb - n
+    int maxlev;                  // highest level present (<= L)
+    int nstr;                    // number of strings with level <= maxlev
+    int lev_off[ISCI_MAXLEV + 2];
+    int occ_mult[ISCI_MAXN + 1]; // C(n, n - k)
+    int le[ISCI_MAXLEV + 2];     // number of strings with level <= l (l = 0..L)
+};
+
+// Device tables owned by a handle.
+struct DevTabs {
+    uint32_t *astr = nullptr, *bstr = nullptr;  // packed strings (8 bits per orbital)
+    int8_t *alev = nullptr, *blev = nullptr;
+    int64_t *rowstart = nullptr;                // [nstr_a + 1]
+    // one-body list, CSR over p: (q, h_pq)
+    int *h_off = nullptr;
+    uint8_t *h_q = nullptr;
+    double *h_v = nullptr;
+    // same-spin list, CSR over pair index P(p>r) = p(p-1)/2 + r: (q<<8 | s, value)
+    int *ss_off = nullptr;
+    uint16_t *ss_qs = nullptr;
+    double *ss_v = nullptr;
+    // alpha-beta list, CSR over (p, q, r): (s, (pq|rs))
+    long long *ab_off = nullptr;
+    uint8_t *ab_s = nullptr;
+    double *ab_v = nullptr;
+    // alpha (p -> active q) list: q with at least one kept (pq|rs)
+    int *pq_off = nullptr;
+    uint8_t *pq_q = nullptr;
+    // diagonal units
+    double *hd = nullptr;    // h_pp
+    double *jj = nullptr;    // (pp|qq)
+    double *ssd = nullptr;   // (pp|qq) - (pq|qp)
+    unsigned long long *counters = nullptr;  // [2 * ISCI_NBUCKET] kept, terms
+};
+
+struct SigmaArgs {
+    int norb, L;
+    double tau;
+    SpinTab sa, sb;
+    const uint32_t *astr, *bstr;
+    const int8_t *alev, *blev;
+    const int64_t *rowstart;
+    const int *h_off; const uint8_t *h_q; const double *h_v;
+    const int *ss_off; const uint16_t *ss_qs; const double *ss_v;
+    const long long *ab_off; const uint8_t *ab_s; const double *ab_v;
+    const int *pq_off; const uint8_t *pq_q;
+    const double *hd, *jj, *ssd;
+};
+
+}  // namespace isci
+
+struct isci_ctx {
+    int norb = 0, na = 0, nb = 0, L = 0;
+    double tau = 0.0;
+    int device = 0;
+    int64_t dim = 0;
+    isci::SpinTab sa{}, sb{};
+    isci::DevTabs d;
+    isci_stats stats{};
+    std::vector<void *> allocs;
+    std::vector<int32_t> h_aorb, h_borb, h_alev, h_blev;  // host string tables
+    std::vector<int64_t> h_rowstart;
+    int max_rowlen = 0;
+    // scratch for the eigensolver (grown on demand)
+    std::vector<void *> work;
+};
+
+namespace isci {
+
+// error plumbing
+void set_error(const std::string &msg);
+isci_status hip_fail(hipError_t e, const char *what);
+#define ISCI_HIP(call)                                              \
+    do {                                                            \
+        hipError_t _e = (call);                                     \
+        if (_e != hipSuccess) return isci::hip_fail(_e, #call);     \
+    } while (0)
+
+void *dev_alloc(isci_ctx *c, size_t bytes);
+SigmaArgs sigma_args(const isci_ctx *c);
+
+isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t ldc,
+                         double *sv, int64_t lds, hipStream_t s);
+isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
+
+// device vector helpers used by the eigensolver
+isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int k,
+                 int64_t n, double *out_dev, double *partial, int nblk, hipStream_t s);
+int dots_blocks(int64_t n);
+isci_status lincomb(const double *V, int64_t ldv, int m, const double *Y /*dev [k][m]*/, int k,
+                    double *out, int64_t ldo, int64_t n, double beta, hipStream_t s);
+
+}  // namespace isci

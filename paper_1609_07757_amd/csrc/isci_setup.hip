@@ -1,0 +1,614 @@
+// libisci setup: argument checks, string enumeration and row layout,
+// the on-device screened-integral list builder, screening statistics and
+// the small entry points of the ABI.
+//
+// The list builder is one pass over h and the canonical elements of eri.
+// Every elementary unit of the paper's index-restricted Hamiltonian
+// (Eq. index_re) is formed once and kept iff |unit| > tau (Eqs. sigma_int,
+// sigma_split):
+//   one-body   h_pq                          CSR over p        -> (q, h_pq)
+//   same-spin  (pq|rs) - (ps|rq), p>r, q>s   CSR over pair(p,r) -> (q, s, value)
+//   alpha-beta (pq|rs)                       CSR over (p,q,r)  -> (s, value)
+// These lists are the "integral loops" of the sigma kernels: the kernels
+// iterate over kept units only, so screened integrals cost nothing there.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "isci_device.h"
+#include "isci_internal.h"
+
+namespace isci {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+isci_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ISCI_E_OOM : ISCI_E_HIP;
+}
+
+void *dev_alloc(isci_ctx *c, size_t bytes)
+{
+    void *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    c->stats.device_bytes += (int64_t)bytes;
+    return p;
+}
+
+// ------------------------------------------------------------------ host tables
+
+static void spin_table(SpinTab &T, int norb, int n, int L)
+{
+    memset(&T, 0, sizeof(T));
+    T.n = n;
+    T.nocc = n;
+    T.nvirt = norb - n;
+    T.maxlev = std::min(std::min(n, norb - n), L);
+    int acc = 0;
+    for (int k = 0; k <= T.maxlev; ++k) {
+        T.lev_off[k] = acc;
+        T.occ_mult[k] = (int)binom(n, n - k);
+        acc += (int)(binom(n, n - k) * binom(norb - n, k));
+    }
+    for (int k = T.maxlev + 1; k <= ISCI_MAXLEV + 1; ++k) T.lev_off[k] = acc;
+    T.nstr = acc;
+    for (int l = 0; l <= ISCI_MAXLEV + 1; ++l) T.le[l] = T.lev_off[std::min(l, T.maxlev) + 1];
+}
+
+// enumerate all strings of a spin and place each at its rank; checks that
+// the rank is a bijection onto 0..nstr-1
+static bool enumerate(const SpinTab &T, int norb, std::vector<int32_t> &orb,
+                      std::vector<int32_t> &lev, std::vector<uint32_t> &packed)
+{
+    const int n = T.n;
+    orb.assign((size_t)T.nstr * std::max(n, 1), 0);
+    lev.assign(T.nstr, -1);
+    packed.assign(T.nstr, 0);
+    int idx[ISCI_MAXN];
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    for (;;) {
+        int l = str_level(idx, n);
+        if (l <= T.maxlev) {
+            int r = str_index(idx, T);
+            if (r < 0 || r >= T.nstr || lev[r] >= 0) return false;
+            lev[r] = l;
+            packed[r] = pack_str(idx, n);
+            for (int i = 0; i < n; ++i) orb[(size_t)r * n + i] = idx[i];
+        }
+        int i = n - 1;
+        while (i >= 0 && idx[i] == norb - n + i) --i;
+        if (i < 0) break;
+        idx[i]++;
+        for (int j = i + 1; j < n; ++j) idx[j] = idx[j - 1] + 1;
+    }
+    for (int r = 0; r < T.nstr; ++r)
+        if (lev[r] < 0) return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ scan
+
+template <typename T>
+__global__ void k_scan_block(const T *in, T *out, T *bsum, int64_t N)
+{
+    __shared__ T s[1024];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 1024 + tid;
+    const T v = i < N ? in[i] : 0;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        T t = tid >= off ? s[tid - off] : 0;
+        __syncthreads();
+        s[tid] += t;
+        __syncthreads();
+    }
+    if (i < N) out[i] = s[tid] - v;
+    if (tid == 1023) bsum[blockIdx.x] = s[1023];
+}
+
+template <typename T>
+__global__ void k_scan_add(T *out, const T *boff, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < N) out[i] += boff[blockIdx.x];
+}
+
+// exclusive scan in place of a[0..N-1] on stream s
+template <typename T>
+static isci_status scan_inplace(T *a, int64_t N, hipStream_t s)
+{
+    const int64_t nb = (N + 1023) / 1024;
+    T *bs = nullptr;
+    ISCI_HIP(hipMallocAsync((void **)&bs, sizeof(T) * (size_t)(nb + 1), s));
+    k_scan_block<T><<<(unsigned)nb, 1024, 0, s>>>(a, a, bs, N);
+    ISCI_HIP(hipGetLastError());
+    if (nb > 1) {
+        isci_status st = scan_inplace<T>(bs, nb, s);
+        if (st != ISCI_OK) return st;
+        k_scan_add<T><<<(unsigned)nb, 1024, 0, s>>>(a, bs, N);
+        ISCI_HIP(hipGetLastError());
+    }
+    ISCI_HIP(hipFreeAsync(bs, s));
+    return ISCI_OK;
+}
+
+// ------------------------------------------------------------------ term counting
+
+// number of m-subsets (spectators) of the orbitals outside a set that
+// holds o_ex occupied and v_ex virtual orbitals of this spin, at level l
+__device__ inline long long nsub(const SpinTab &T, int m, int l, int o_ex, int v_ex)
+{
+    if (m < 0 || l < 0 || l > m) return 0;
+    return binom(T.nocc - o_ex, m - l) * binom(T.nvirt - v_ex, l);
+}
+
+__device__ inline int isv(const SpinTab &T, int x) { return x >= T.nocc; }
+
+// strings of the other spin with level <= l (0 if l < 0)
+__device__ inline long long le_of(const SpinTab &T, int l)
+{
+    if (l < 0) return 0;
+    return T.le[l > ISCI_MAXLEV + 1 ? ISCI_MAXLEV + 1 : l];
+}
+
+// sigma terms of one-body unit h_pq acting in spin T (other spin U)
+__device__ long long terms_1b(const SpinTab &T, const SpinTab &U, int L, int p, int q)
+{
+    if (T.n < 1) return 0;
+    int o = (p < T.nocc) + (q != p && q < T.nocc);
+    int v = (p >= T.nocc) + (q != p && q >= T.nocc);
+    int em = max(isv(T, p), isv(T, q));
+    long long t = 0;
+    for (int l = 0; l <= T.n - 1; ++l) t += nsub(T, T.n - 1, l, o, v) * le_of(U, L - l - em);
+    return t;
+}
+
+// sigma terms of same-spin unit (p>r, q>s) acting in spin T
+__device__ long long terms_ss(const SpinTab &T, const SpinTab &U, int L, int p, int r, int q, int s)
+{
+    if (T.n < 2) return 0;
+    int e[4] = {p, r, q, s};
+    int o = 0, v = 0;
+    for (int i = 0; i < 4; ++i) {
+        bool dup = false;
+        for (int j = 0; j < i; ++j) dup |= (e[j] == e[i]);
+        if (dup) continue;
+        if (e[i] < T.nocc) ++o; else ++v;
+    }
+    int em = max(isv(T, p) + isv(T, r), isv(T, q) + isv(T, s));
+    long long t = 0;
+    for (int l = 0; l <= T.n - 2; ++l) t += nsub(T, T.n - 2, l, o, v) * le_of(U, L - l - em);
+    return t;
+}
+
+// sigma terms of alpha-beta unit (pq|rs), alpha q->p, beta s->r
+__device__ long long terms_ab(const SpinTab &A, const SpinTab &B, int L, int p, int q, int r, int s)
+{
+    if (A.n < 1 || B.n < 1) return 0;
+    int oa = (p < A.nocc) + (q != p && q < A.nocc), va = (p >= A.nocc) + (q != p && q >= A.nocc);
+    int ob = (r < B.nocc) + (s != r && s < B.nocc), vb = (r >= B.nocc) + (s != r && s >= B.nocc);
+    int T = L - max(isv(A, q) + isv(B, s), isv(A, p) + isv(B, r));
+    long long t = 0;
+    for (int la = 0; la <= A.n - 1; ++la) {
+        long long na = nsub(A, A.n - 1, la, oa, va);
+        if (!na) continue;
+        for (int lb = 0; lb <= B.n - 1 && la + lb <= T; ++lb) t += na * nsub(B, B.n - 1, lb, ob, vb);
+    }
+    return t;
+}
+
+// ------------------------------------------------------------------ list builder kernels
+
+__global__ void k_h_count(const double *h, int n, double tau, int *cnt)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int c = 0;
+    for (int q = 0; q < n; ++q) c += fabs(gh(h, n, p, q)) > tau;
+    cnt[p] = c;
+}
+
+__global__ void k_h_fill(const double *h, int n, double tau, const int *off, uint8_t *hq, double *hv,
+                         SpinTab sa, SpinTab sb, int L, unsigned long long *ctr)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int k = off[p];
+    for (int q = 0; q < n; ++q) {
+        double v = gh(h, n, p, q);
+        if (!(fabs(v) > tau)) continue;
+        hq[k] = (uint8_t)q;
+        hv[k] = v;
+        ++k;
+        int ba = 2 * isv(sa, p) + isv(sa, q), bb = 4 + 2 * isv(sb, p) + isv(sb, q);
+        if (sa.n > 0) {
+            atomicAdd(&ctr[ba], 1ull);
+            atomicAdd(&ctr[ISCI_NBUCKET + ba], (unsigned long long)terms_1b(sa, sb, L, p, q));
+        }
+        if (sb.n > 0) {
+            atomicAdd(&ctr[bb], 1ull);
+            atomicAdd(&ctr[ISCI_NBUCKET + bb], (unsigned long long)terms_1b(sb, sa, L, p, q));
+        }
+    }
+}
+
+__device__ inline void pair_of(int P, int &p, int &r)
+{
+    // P = p(p-1)/2 + r, p > r >= 0
+    int x = (int)((1.0 + sqrt(1.0 + 8.0 * (double)P)) * 0.5);
+    while (x * (x - 1) / 2 > P) --x;
+    while ((x + 1) * x / 2 <= P) ++x;
+    p = x;
+    r = P - x * (x - 1) / 2;
+}
+
+__global__ void k_ss_count(const double *eri, int n, double tau, int *cnt)
+{
+    const int np = n * (n - 1) / 2;
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= np) return;
+    int p, r;
+    pair_of(P, p, r);
+    int c = 0;
+    for (int q = 1; q < n; ++q)
+        for (int s = 0; s < q; ++s) {
+            double v = geri(eri, n, p, q, r, s) - geri(eri, n, p, s, r, q);
+            c += fabs(v) > tau;
+        }
+    cnt[P] = c;
+}
+
+__global__ void k_ss_fill(const double *eri, int n, double tau, const int *off, uint16_t *qs,
+                          double *val, SpinTab sa, SpinTab sb, int L, unsigned long long *ctr)
+{
+    const int np = n * (n - 1) / 2;
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= np) return;
+    int p, r;
+    pair_of(P, p, r);
+    int k = off[P];
+    for (int q = 1; q < n; ++q)
+        for (int s = 0; s < q; ++s) {
+            double v = geri(eri, n, p, q, r, s) - geri(eri, n, p, s, r, q);
+            if (!(fabs(v) > tau)) continue;
+            qs[k] = (uint16_t)((q << 8) | s);
+            val[k] = v;
+            ++k;
+            for (int spin = 0; spin < 2; ++spin) {
+                const SpinTab &T = spin ? sb : sa;
+                const SpinTab &U = spin ? sa : sb;
+                if (T.n < 2) continue;
+                int b = 8 + 9 * spin + 3 * (isv(T, p) + isv(T, r)) + isv(T, q) + isv(T, s);
+                atomicAdd(&ctr[b], 1ull);
+                atomicAdd(&ctr[ISCI_NBUCKET + b], (unsigned long long)terms_ss(T, U, L, p, r, q, s));
+            }
+        }
+}
+
+__global__ void k_ab_count(const double *eri, int n, double tau, long long *cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (t >= n3) return;
+    const int p = (int)(t / ((int64_t)n * n)), q = (int)((t / n) % n), r = (int)(t % n);
+    int c = 0;
+    for (int s = 0; s < n; ++s) c += fabs(geri(eri, n, p, q, r, s)) > tau;
+    cnt[t] = c;
+}
+
+__global__ void k_ab_fill(const double *eri, int n, double tau, const long long *off, uint8_t *ss, double *val,
+                          SpinTab sa, SpinTab sb, int L, unsigned long long *ctr)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (t >= n3) return;
+    const int p = (int)(t / ((int64_t)n * n)), q = (int)((t / n) % n), r = (int)(t % n);
+    long long k = off[t];
+    unsigned long long kept[16] = {0}, terms[16] = {0};
+    for (int s = 0; s < n; ++s) {
+        double v = geri(eri, n, p, q, r, s);
+        if (!(fabs(v) > tau)) continue;
+        ss[k] = (uint8_t)s;
+        val[k] = v;
+        ++k;
+        int b = 8 * isv(sa, p) + 4 * isv(sa, q) + 2 * isv(sb, r) + isv(sb, s);
+        kept[b] += 1;
+        terms[b] += (unsigned long long)terms_ab(sa, sb, L, p, q, r, s);
+    }
+    if (sa.n > 0 && sb.n > 0)
+        for (int b = 0; b < 16; ++b)
+            if (kept[b]) {
+                atomicAdd(&ctr[26 + b], kept[b]);
+                atomicAdd(&ctr[ISCI_NBUCKET + 26 + b], terms[b]);
+            }
+}
+
+// number of active q (non-empty (p,q,*) alpha-beta lists) per p
+__global__ void k_pq_count(const long long *ab_off, int n, int *cnt)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int c = 0;
+    for (int q = 0; q < n; ++q) {
+        int64_t b = ((int64_t)p * n + q) * n;
+        c += ab_off[b + n] > ab_off[b];
+    }
+    cnt[p] = c;
+}
+
+__global__ void k_pq_fill(const long long *ab_off, int n, const int *off, uint8_t *pq)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int k = off[p];
+    for (int q = 0; q < n; ++q) {
+        int64_t b = ((int64_t)p * n + q) * n;
+        if (ab_off[b + n] > ab_off[b]) pq[k++] = (uint8_t)q;
+    }
+}
+
+// diagonal units: h_pp, (pp|qq), and (pp|qq) - (pq|qp) formed with the
+// smaller index first
+__global__ void k_diag_units(const double *h, const double *eri, int n, double *hd, double *jj, double *ssd)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int p = t / n, q = t % n;
+    if (q == 0) hd[p] = gh(h, n, p, p);
+    jj[t] = geri(eri, n, p, p, q, q);
+    const int a = min(p, q), b = max(p, q);
+    ssd[t] = geri(eri, n, a, a, b, b) - geri(eri, n, a, b, b, a);
+}
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+SigmaArgs sigma_args(const isci_ctx *c)
+{
+    SigmaArgs A;
+    A.norb = c->norb; A.L = c->L; A.tau = c->tau;
+    A.sa = c->sa; A.sb = c->sb;
+    A.astr = c->d.astr; A.bstr = c->d.bstr; A.alev = c->d.alev; A.blev = c->d.blev;
+    A.rowstart = c->d.rowstart;
+    A.h_off = c->d.h_off; A.h_q = c->d.h_q; A.h_v = c->d.h_v;
+    A.ss_off = c->d.ss_off; A.ss_qs = c->d.ss_qs; A.ss_v = c->d.ss_v;
+    A.ab_off = c->d.ab_off; A.ab_s = c->d.ab_s; A.ab_v = c->d.ab_v;
+    A.pq_off = c->d.pq_off; A.pq_q = c->d.pq_q;
+    A.hd = c->d.hd; A.jj = c->d.jj; A.ssd = c->d.ssd;
+    return A;
+}
+
+static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, hipStream_t s)
+{
+    const int n = c->norb;
+    const int64_t n3 = (int64_t)n * n * n;
+    const int np = n * (n - 1) / 2;
+    DevTabs &d = c->d;
+    d.h_off = (int *)dev_alloc(c, sizeof(int) * (n + 1));
+    d.ss_off = (int *)dev_alloc(c, sizeof(int) * (np + 1));
+    d.ab_off = (long long *)dev_alloc(c, sizeof(long long) * (n3 + 1));
+    d.pq_off = (int *)dev_alloc(c, sizeof(int) * (n + 1));
+    d.counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * 2 * ISCI_NBUCKET);
+    d.hd = (double *)dev_alloc(c, sizeof(double) * n);
+    d.jj = (double *)dev_alloc(c, sizeof(double) * n * n);
+    d.ssd = (double *)dev_alloc(c, sizeof(double) * n * n);
+    if (!d.h_off || !d.ss_off || !d.ab_off || !d.pq_off || !d.counters || !d.hd || !d.jj || !d.ssd) {
+        set_error("device allocation failed (list offsets)");
+        return ISCI_E_OOM;
+    }
+    ISCI_HIP(hipMemsetAsync(d.counters, 0, sizeof(unsigned long long) * 2 * ISCI_NBUCKET, s));
+    ISCI_HIP(hipMemsetAsync(d.h_off, 0, sizeof(int) * (n + 1), s));
+    ISCI_HIP(hipMemsetAsync(d.ss_off, 0, sizeof(int) * (np + 1), s));
+    ISCI_HIP(hipMemsetAsync(d.ab_off, 0, sizeof(long long) * (n3 + 1), s));
+    ISCI_HIP(hipMemsetAsync(d.pq_off, 0, sizeof(int) * (n + 1), s));
+
+    k_h_count<<<nblk(n, 64), 64, 0, s>>>(h, n, c->tau, d.h_off);
+    if (np > 0) k_ss_count<<<nblk(np, 64), 64, 0, s>>>(eri, n, c->tau, d.ss_off);
+    k_ab_count<<<nblk(n3, 256), 256, 0, s>>>(eri, n, c->tau, d.ab_off);
+    k_diag_units<<<nblk((int64_t)n * n, 256), 256, 0, s>>>(h, eri, n, d.hd, d.jj, d.ssd);
+    ISCI_HIP(hipGetLastError());
+    isci_status st;
+    if ((st = scan_inplace<int>(d.h_off, n + 1, s)) != ISCI_OK) return st;
+    if ((st = scan_inplace<int>(d.ss_off, np + 1, s)) != ISCI_OK) return st;
+    if ((st = scan_inplace<long long>(d.ab_off, n3 + 1, s)) != ISCI_OK) return st;
+    k_pq_count<<<nblk(n, 64), 64, 0, s>>>(d.ab_off, n, d.pq_off);
+    ISCI_HIP(hipGetLastError());
+    if ((st = scan_inplace<int>(d.pq_off, n + 1, s)) != ISCI_OK) return st;
+
+    int tot[4];
+    long long tot_ab = 0;
+    ISCI_HIP(hipMemcpyAsync(&tot[0], d.h_off + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipMemcpyAsync(&tot[1], d.ss_off + np, sizeof(int), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipMemcpyAsync(&tot_ab, d.ab_off + n3, sizeof(long long), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipMemcpyAsync(&tot[3], d.pq_off + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipStreamSynchronize(s));
+
+    d.h_q = (uint8_t *)dev_alloc(c, tot[0]);
+    d.h_v = (double *)dev_alloc(c, sizeof(double) * tot[0]);
+    d.ss_qs = (uint16_t *)dev_alloc(c, sizeof(uint16_t) * tot[1]);
+    d.ss_v = (double *)dev_alloc(c, sizeof(double) * tot[1]);
+    d.ab_s = (uint8_t *)dev_alloc(c, (size_t)tot_ab);
+    d.ab_v = (double *)dev_alloc(c, sizeof(double) * (size_t)tot_ab);
+    d.pq_q = (uint8_t *)dev_alloc(c, tot[3]);
+    if (!d.h_q || !d.h_v || !d.ss_qs || !d.ss_v || !d.ab_s || !d.ab_v || !d.pq_q) {
+        set_error("device allocation failed (lists)");
+        return ISCI_E_OOM;
+    }
+    k_h_fill<<<nblk(n, 64), 64, 0, s>>>(h, n, c->tau, d.h_off, d.h_q, d.h_v, c->sa, c->sb, c->L, d.counters);
+    if (np > 0)
+        k_ss_fill<<<nblk(np, 64), 64, 0, s>>>(eri, n, c->tau, d.ss_off, d.ss_qs, d.ss_v, c->sa, c->sb, c->L,
+                                               d.counters);
+    k_ab_fill<<<nblk(n3, 256), 256, 0, s>>>(eri, n, c->tau, d.ab_off, d.ab_s, d.ab_v, c->sa, c->sb, c->L,
+                                             d.counters);
+    k_pq_fill<<<nblk(n, 64), 64, 0, s>>>(d.ab_off, n, d.pq_off, d.pq_q);
+    ISCI_HIP(hipGetLastError());
+    unsigned long long ctr[2 * ISCI_NBUCKET];
+    ISCI_HIP(hipMemcpyAsync(ctr, d.counters, sizeof(ctr), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipStreamSynchronize(s));
+    c->stats.kept_total = 0;
+    c->stats.terms_total = 0;
+    for (int b = 0; b < ISCI_NBUCKET; ++b) {
+        c->stats.kept[b] = (int64_t)ctr[b];
+        c->stats.terms[b] = (int64_t)ctr[ISCI_NBUCKET + b];
+        c->stats.terms_total += c->stats.terms[b];
+    }
+    // distinct kept integral units: one-body counted once, same-spin once, alpha-beta once
+    c->stats.kept_total = (int64_t)tot[0] + tot[1] + tot_ab;
+    return ISCI_OK;
+}
+
+static void destroy(isci_ctx *c)
+{
+    if (!c) return;
+    for (void *p : c->allocs) (void)hipFree(p);
+    for (void *p : c->work) (void)hipFree(p);
+    delete c;
+}
+
+}  // namespace isci
+
+using namespace isci;
+
+extern "C" {
+
+const char *isci_last_error(void) { return g_last_error.c_str(); }
+
+const char *isci_status_string(isci_status s)
+{
+    switch (s) {
+    case ISCI_OK: return "ok";
+    case ISCI_E_INVALID: return "invalid argument";
+    case ISCI_E_OOM: return "out of device memory";
+    case ISCI_E_HIP: return "HIP runtime error";
+    case ISCI_E_NOT_CONVERGED: return "not converged";
+    case ISCI_E_UNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}
+
+isci_status isci_create(isci_handle *out, const double *h, const double *eri, int norb, int nalpha,
+                        int nbeta, int max_excitation, double tau, hipStream_t stream)
+{
+    if (!out) { set_error("out is NULL"); return ISCI_E_INVALID; }
+    *out = nullptr;
+    if (!h || !eri) { set_error("h or eri is NULL"); return ISCI_E_INVALID; }
+    if (norb < 1) { set_error("norb < 1"); return ISCI_E_INVALID; }
+    if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb) {
+        set_error("electron counts outside [0, norb]");
+        return ISCI_E_INVALID;
+    }
+    if (max_excitation < 0) { set_error("max_excitation < 0"); return ISCI_E_INVALID; }
+    if (!(tau >= 0.0) || std::isinf(tau)) { set_error("tau must be finite and >= 0"); return ISCI_E_INVALID; }
+    if (norb > ISCI_MAXNORB) { set_error("norb > 255 is not supported"); return ISCI_E_UNSUPPORTED; }
+    if (nalpha > ISCI_MAXN || nbeta > ISCI_MAXN) {
+        set_error("more than 4 electrons per spin is not supported");
+        return ISCI_E_UNSUPPORTED;
+    }
+    isci_ctx *c = new (std::nothrow) isci_ctx();
+    if (!c) { set_error("host allocation failed"); return ISCI_E_OOM; }
+    c->norb = norb; c->na = nalpha; c->nb = nbeta; c->tau = tau;
+    const int lmax = std::min(nalpha, norb - nalpha) + std::min(nbeta, norb - nbeta);
+    c->L = std::min(max_excitation, lmax);
+    spin_table(c->sa, norb, nalpha, c->L);
+    spin_table(c->sb, norb, nbeta, c->L);
+    if (hipGetDevice(&c->device) != hipSuccess) { destroy(c); set_error("hipGetDevice failed"); return ISCI_E_HIP; }
+
+    std::vector<uint32_t> pa, pb;
+    if (!enumerate(c->sa, norb, c->h_aorb, c->h_alev, pa) || !enumerate(c->sb, norb, c->h_borb, c->h_blev, pb)) {
+        destroy(c);
+        set_error("internal: string rank is not a bijection");
+        return ISCI_E_HIP;
+    }
+    // rows: alpha strings; row of level k holds beta strings of level <= L - k
+    c->h_rowstart.assign((size_t)c->sa.nstr + 1, 0);
+    int64_t acc = 0;
+    for (int i = 0; i < c->sa.nstr; ++i) {
+        c->h_rowstart[i] = acc;
+        int64_t len = c->sb.le[c->L - c->h_alev[i]];
+        c->max_rowlen = std::max<int>(c->max_rowlen, (int)len);
+        acc += len;
+    }
+    c->h_rowstart[c->sa.nstr] = acc;
+    c->dim = acc;
+    if (acc >= ((int64_t)1 << 62)) { destroy(c); set_error("dimension too large"); return ISCI_E_UNSUPPORTED; }
+    c->stats.dim = acc;
+    c->stats.nstr_alpha = c->sa.nstr;
+    c->stats.nstr_beta = c->sb.nstr;
+
+    // upload string tables
+    std::vector<int8_t> la(c->sa.nstr), lb(c->sb.nstr);
+    for (int i = 0; i < c->sa.nstr; ++i) la[i] = (int8_t)c->h_alev[i];
+    for (int i = 0; i < c->sb.nstr; ++i) lb[i] = (int8_t)c->h_blev[i];
+    c->d.astr = (uint32_t *)dev_alloc(c, sizeof(uint32_t) * c->sa.nstr);
+    c->d.bstr = (uint32_t *)dev_alloc(c, sizeof(uint32_t) * c->sb.nstr);
+    c->d.alev = (int8_t *)dev_alloc(c, c->sa.nstr);
+    c->d.blev = (int8_t *)dev_alloc(c, c->sb.nstr);
+    c->d.rowstart = (int64_t *)dev_alloc(c, sizeof(int64_t) * (c->sa.nstr + 1));
+    if (!c->d.astr || !c->d.bstr || !c->d.alev || !c->d.blev || !c->d.rowstart) {
+        destroy(c);
+        set_error("device allocation failed (strings)");
+        return ISCI_E_OOM;
+    }
+    hipError_t e = hipSuccess;
+    e = e ? e : hipMemcpyAsync(c->d.astr, pa.data(), sizeof(uint32_t) * pa.size(), hipMemcpyHostToDevice, stream);
+    e = e ? e : hipMemcpyAsync(c->d.bstr, pb.data(), sizeof(uint32_t) * pb.size(), hipMemcpyHostToDevice, stream);
+    e = e ? e : hipMemcpyAsync(c->d.alev, la.data(), la.size(), hipMemcpyHostToDevice, stream);
+    e = e ? e : hipMemcpyAsync(c->d.blev, lb.data(), lb.size(), hipMemcpyHostToDevice, stream);
+    e = e ? e : hipMemcpyAsync(c->d.rowstart, c->h_rowstart.data(), sizeof(int64_t) * c->h_rowstart.size(),
+                               hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) { destroy(c); return hip_fail(e, "upload string tables"); }
+    isci_status st = build_lists(c, h, eri, stream);
+    if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
+    *out = c;
+    return ISCI_OK;
+}
+
+isci_status isci_dim(isci_handle c, int64_t *dim)
+{
+    if (!c || !dim) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    *dim = c->dim;
+    return ISCI_OK;
+}
+
+isci_status isci_get_stats(isci_handle c, isci_stats *s)
+{
+    if (!c || !s) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    *s = c->stats;
+    return ISCI_OK;
+}
+
+isci_status isci_strings(isci_handle c, int spin, int32_t *orbitals, int32_t *level, int64_t *nstr)
+{
+    if (!c || (spin != 0 && spin != 1)) { set_error("bad handle or spin"); return ISCI_E_INVALID; }
+    const SpinTab &T = spin ? c->sb : c->sa;
+    const std::vector<int32_t> &o = spin ? c->h_borb : c->h_aorb;
+    const std::vector<int32_t> &l = spin ? c->h_blev : c->h_alev;
+    if (nstr) *nstr = T.nstr;
+    if (orbitals && T.n > 0)
+        for (int i = 0; i < T.nstr; ++i)
+            for (int j = 0; j < T.n; ++j) orbitals[(size_t)i * T.n + j] = o[(size_t)i * T.n + j];
+    if (level) std::copy(l.begin(), l.end(), level);
+    return ISCI_OK;
+}
+
+isci_status isci_rowstart(isci_handle c, int64_t *rowstart)
+{
+    if (!c || !rowstart) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    std::copy(c->h_rowstart.begin(), c->h_rowstart.end(), rowstart);
+    return ISCI_OK;
+}
+
+void isci_destroy(isci_handle c) { destroy(c); }
+
+}  // extern "C"

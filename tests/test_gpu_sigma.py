@@ -1,0 +1,185 @@
+"""GPU parity: the HIP sigma path (through the C ABI) against the CPU
+oracle on the same seeded inputs.
+
+Bar: integer string / address tables and term counts bit-exact; sigma
+elementwise |delta| <= 1e-12 * ||sigma||_inf (FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from isci_inputs import canonicalize_eri, random_vectors, recipe_a, recipe_b, recipe_random
+
+from gpu_common import create, gpu_sigma, rel_err, sample_targets, torch_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _ints(recipe, norb, seed):
+    if recipe == "A":
+        return recipe_a(norb, seed=seed)
+    if recipe == "B":
+        return recipe_b(norb, seed=seed)
+    return recipe_random(norb, seed=seed)
+
+
+CASES = [
+    # recipe, norb, na, nb, L, tau, nvec
+    ("B", 8, 2, 2, 2, 0.0, 1),
+    ("B", 10, 2, 2, 3, 1e-10, 3),
+    ("R", 7, 2, 2, 4, 0.0, 2),
+    ("A", 12, 2, 2, 2, 1e-14, 8),
+    ("B", 9, 3, 2, 3, 1e-8, 9),
+    ("R", 6, 3, 3, 6, 1e-3, 1),
+    ("R", 8, 4, 3, 3, 1e-6, 2),
+    ("R", 6, 1, 1, 2, 0.0, 4),
+    ("B", 7, 1, 0, 1, 0.0, 1),
+    ("R", 6, 0, 2, 2, 0.0, 1),
+    ("B", 11, 2, 1, 2, 1e-9, 5),
+    ("R", 5, 2, 2, 0, 0.0, 1),     # reference only
+    ("R", 6, 2, 2, 1, 1e-4, 2),    # singles only
+    ("R", 4, 4, 4, 8, 0.0, 1),     # no virtual orbitals
+    ("B", 20, 2, 2, 2, 1e-14, 1),  # CISD 20 orbitals, recipe B
+    ("B", 16, 2, 2, 3, 1e-12, 17),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
+def test_sigma_parity(case):
+    recipe, norb, na, nb, L, tau, nvec = case
+    h, eri = _ints(recipe, norb, 3)
+    hd = create(h, eri, norb, na, nb, L, tau)
+    S = O.Space(norb, na, nb, L)
+    assert hd.dim == S.dim
+    c = random_vectors(S.dim, nvec, seed=11)
+    got = gpu_sigma(hd, c)
+    ref = O.sigma(S, h, eri, tau, c)
+    assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("case", [("B", 10, 2, 2, 3), ("R", 8, 3, 1, 4), ("R", 7, 0, 3, 2),
+                                  ("A", 30, 2, 2, 3), ("R", 9, 4, 4, 2)])
+def test_strings_and_rowstart_bitexact(case):
+    import paper_1609_07757_amd as isci
+    recipe, norb, na, nb, L = case
+    h, eri = _ints(recipe, norb, 1)
+    hd = create(h, eri, norb, na, nb, L, 0.0)
+    S = O.Space(norb, na, nb, L)
+    for spin in (0, 1):
+        go, gl = isci.isci_strings(hd, spin)
+        oo, ol = S.strings(spin)
+        assert np.array_equal(go, oo) and np.array_equal(gl, ol)
+    assert np.array_equal(isci.isci_rowstart(hd), S.rowstart())
+
+
+@pytest.mark.parametrize("case", [("B", 8, 2, 2, 3, 1e-9), ("R", 7, 2, 2, 2, 0.0), ("A", 10, 2, 2, 4, 1e-14),
+                                  ("R", 7, 3, 2, 3, 0.2), ("B", 9, 2, 1, 2, 1e-6), ("R", 6, 1, 1, 2, 0.0)])
+def test_term_counts_bitexact(case):
+    import paper_1609_07757_amd as isci
+    recipe, norb, na, nb, L, tau = case
+    h, eri = _ints(recipe, norb, 2)
+    hd = create(h, eri, norb, na, nb, L, tau)
+    S = O.Space(norb, na, nb, L)
+    kept, _ = O.terms(S, h, eri, tau)
+    st = isci.isci_get_stats(hd)
+    assert np.array_equal(st["terms"], kept)
+    assert st["terms_total"] == int(kept.sum())
+
+
+@pytest.mark.parametrize("case", [("B", 10, 2, 2, 3, 1e-10), ("R", 7, 3, 2, 4, 1e-3), ("A", 20, 2, 2, 2, 1e-14)])
+def test_diag_parity(case):
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    recipe, norb, na, nb, L, tau = case
+    h, eri = _ints(recipe, norb, 4)
+    hd = create(h, eri, norb, na, nb, L, tau)
+    d = isci.isci_diag(hd).cpu().numpy()
+    S = O.Space(norb, na, nb, L)
+    ref = O.diag(S, h, eri, tau)
+    assert rel_err(d, ref) <= TOL
+
+
+def test_noncanonical_positions_are_ignored():
+    """Only canonical elements of eri (and the lower triangle of h) are read."""
+    norb, L, tau = 8, 3, 1e-9
+    h, eri = recipe_b(norb, seed=6)
+    rng = np.random.default_rng(0)
+    noisy = eri + rng.normal(scale=1e-3, size=eri.shape)
+    noisy = noisy.copy()
+    canon = canonicalize_eri(noisy)
+    hn = h + np.triu(rng.normal(scale=1e-3, size=h.shape), 1)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, 2, seed=3)
+    g1 = gpu_sigma(create(hn, noisy, norb, 2, 2, L, tau), c)
+    g2 = gpu_sigma(create(np.tril(hn) + np.tril(hn, -1).T, canon, norb, 2, 2, L, tau), c)
+    assert np.array_equal(g1, g2)
+    ref = O.sigma(S, hn, noisy, tau, c)
+    assert rel_err(g1, ref) <= TOL
+
+
+def test_everything_screened():
+    norb = 8
+    h, eri = recipe_b(norb, seed=1)
+    tau = 1e6
+    hd = create(h, eri, norb, 2, 2, 3, tau)
+    c = random_vectors(hd.dim, 1, seed=1)
+    assert np.all(gpu_sigma(hd, c) == 0.0)
+
+
+def test_leading_dimension_and_no_overrun():
+    norb = 9
+    h, eri = recipe_b(norb, seed=2)
+    S = O.Space(norb, 2, 2, 3)
+    hd = create(h, eri, norb, 2, 2, 3, 1e-10)
+    c = random_vectors(S.dim, 3, seed=2)
+    got = gpu_sigma(hd, c, ld=S.dim + 37)
+    assert rel_err(got, O.sigma(S, h, eri, 1e-10, c)) <= TOL
+
+
+def test_hermiticity_large():
+    """u . H v == v . H u at a size beyond the dense oracle."""
+    norb, L = 40, 3
+    h, eri = recipe_b(norb, seed=9)
+    hd = create(h, eri, norb, 2, 2, L, 1e-12)
+    u, v = random_vectors(hd.dim, 2, seed=4)
+    s = gpu_sigma(hd, np.stack([u, v]))
+    a, b = u @ s[1], v @ s[0]
+    assert abs(a - b) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * max(1.0, np.abs(s).max())
+
+
+@pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 1), ("cisdt_n30", 600, 2),
+                                           ("cisdt_n60", 300, 8), ("fci_n48", 200, 8)])
+def test_sigma_workloads(wl, nsamp, nvec):
+    """Named workloads (recipe A): full comparison for the small one, sampled
+    targets (row ends included) at full size for the others."""
+    from isci_inputs import workload
+    W = workload(wl)
+    h, eri = W.integrals()
+    hd = create(h, eri, W.norb, W.nalpha, W.nbeta, W.level, W.tau)
+    S = O.Space(W.norb, W.nalpha, W.nbeta, W.level)
+    assert hd.dim == S.dim
+    c = random_vectors(S.dim, nvec, seed=21)
+    got = gpu_sigma(hd, c)
+    if nsamp is None:
+        ref = O.sigma(S, h, eri, W.tau, c)
+        assert rel_err(got, ref) <= TOL
+    else:
+        tg = sample_targets(S.rowstart(), S.dim, nsamp, seed=5)
+        ref = O.sigma(S, h, eri, W.tau, c, targets=tg)
+        scale = np.abs(got).max()
+        assert np.abs(got[:, tg] - ref).max() <= TOL * scale
+
+
+@pytest.mark.parametrize("k,tau", [(0, 0.0), (1, 1e-14), (2, 1e-10)])
+def test_sigma_tau_sweep_cisdt_n30(k, tau):
+    from isci_inputs import workload
+    W = workload("cisdt_n30")
+    h, eri = W.integrals()
+    hd = create(h, eri, W.norb, 2, 2, 3, tau)
+    S = O.Space(W.norb, 2, 2, 3)
+    c = random_vectors(S.dim, 1, seed=8)
+    got = gpu_sigma(hd, c)
+    tg = sample_targets(S.rowstart(), S.dim, 400, seed=100 + k)
+    ref = O.sigma(S, h, eri, tau, c, targets=tg)
+    assert np.abs(got[:, tg] - ref).max() <= TOL * np.abs(got).max()
