@@ -163,6 +163,62 @@ isci_status isci_rowstart(isci_handle hd, int64_t *rowstart);
 /* Screening statistics (host struct). */
 isci_status isci_get_stats(isci_handle hd, isci_stats *s);
 
+/* ---------------------------------------------------------------------
+ * Multi-instance eigensolver engine (batched and served Davidson solves).
+ *
+ * An engine owns a stream and any number of Davidson solves ("slots"),
+ * each on its own handle.  isci_engine_step advances every unfinished slot
+ * by one Davidson iteration: one fused sigma launch covers the new basis
+ * vectors of all slots (a persistent grid over a work list of (slot, alpha
+ * row, beta block) items, heaviest first), followed by each slot's block
+ * algebra; three host synchronisations per step serve all slots together.
+ * Slots may be added and released between steps (continuous batching).
+ * A slot's arithmetic does not depend on which other slots share the
+ * engine, so a solve gives the same energies alone or in a mix.
+ * isci_davidson is an engine with a single slot.
+ * ------------------------------------------------------------------- */
+typedef struct isci_engine_s *isci_engine;
+
+isci_status isci_engine_create(isci_engine *out, hipStream_t stream);
+
+/* Launch shape of the fused sigma: grid = persistent workgroups (0: one per
+ * work item); heaviest_first orders work items by estimated cost. */
+isci_status isci_engine_config(isci_engine e, int grid, int heaviest_first);
+
+/* Admit a Davidson solve (allocates its subspace on the device, builds the
+ * initial basis; synchronises the engine stream).  guess as in
+ * isci_davidson.  *slot receives the slot id. */
+isci_status isci_engine_add(isci_engine e, isci_handle hd, int nroots, const isci_davidson_opts *opts,
+                            const double *guess, int nguess, int *slot);
+
+/* One Davidson iteration for every unfinished slot; *nactive (may be
+ * NULL) receives the number of slots that were advanced. */
+isci_status isci_engine_step(isci_engine e, int *nactive);
+
+/* State of a slot: *done = 1 when converged or stopped.  energies (host
+ * [nroots]) hold the current Ritz values; vectors (device [nroots][dim])
+ * are written only when done.  Returns the slot's final status once done
+ * (ISCI_OK or ISCI_E_NOT_CONVERGED), ISCI_OK before. */
+isci_status isci_engine_result(isci_engine e, int slot, int *done, double *energies, double *vectors,
+                               isci_davidson_info *info);
+
+/* Free a slot's device memory (its id may be reused). */
+isci_status isci_engine_release(isci_engine e, int slot);
+
+/* Fused sigma over n handles in one launch on the engine stream:
+ * sigma_i = H_i c_i for nvec[i] vectors with leading dimensions ldc[i],
+ * lds[i] (host arrays of device pointers).  Asynchronous. */
+isci_status isci_engine_sigma(isci_engine e, int n, const isci_handle *hds, const int *nvec,
+                              const double *const *c, const int64_t *ldc, double *const *sigma,
+                              const int64_t *lds);
+
+void isci_engine_destroy(isci_engine e);
+
+/* Device bytes a Davidson solve of nroots roots on this handle allocates
+ * (the admission footprint; the handle's own tables are in
+ * isci_stats.device_bytes).  -1 on bad arguments. */
+int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_opts *opts);
+
 void isci_destroy(isci_handle hd);
 const char *isci_status_string(isci_status s);
 const char *isci_last_error(void);

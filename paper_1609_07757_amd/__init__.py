@@ -16,7 +16,9 @@ from ._lib import IsciDavidsonInfo, IsciDavidsonOpts, IsciError, IsciStats, chec
 
 __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
            "isci_strings", "isci_rowstart", "isci_get_stats", "isci_destroy", "IsciError",
-           "lib_path", "BUCKET_NAMES"]
+           "lib_path", "BUCKET_NAMES", "Engine", "isci_engine_create", "isci_engine_config",
+           "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
+           "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint"]
 
 
 def lib_path() -> str:
@@ -114,6 +116,14 @@ def isci_diag(hd: Handle, out=None, stream=None):
     return out
 
 
+def _opts(tol_residual=1e-7, tol_energy=1e-11, max_iter=200, max_subspace=0, block=0):
+    o = IsciDavidsonOpts()
+    _lib.load().isci_davidson_defaults(ctypes.byref(o))
+    o.tol_residual, o.tol_energy, o.max_iter = tol_residual, tol_energy, max_iter
+    o.max_subspace, o.block = max_subspace, block
+    return o
+
+
 def isci_davidson(hd: Handle, nroots: int = 1, tol_residual: float = 1e-7, tol_energy: float = 1e-11,
                   max_iter: int = 200, max_subspace: int = 0, block: int = 0, guess=None,
                   want_vectors: bool = False, stream=None, raise_on_nonconv: bool = True):
@@ -192,3 +202,105 @@ def _bucket_names():
 
 
 BUCKET_NAMES = _bucket_names()
+
+
+# ---------------------------------------------------------------- engine
+
+class Engine:
+    """Owns an isci_engine (multi-instance Davidson + fused sigma)."""
+
+    def __init__(self, ptr, stream):
+        self._ptr = ptr
+        self.stream = stream
+        self.handles = {}
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("engine destroyed")
+        return self._ptr
+
+    def destroy(self):
+        if self._ptr is not None:
+            _lib.load().isci_engine_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def isci_engine_create(stream=None) -> Engine:
+    out = ctypes.c_void_p()
+    sp = _stream_ptr(stream)
+    check(_lib.load().isci_engine_create(ctypes.byref(out), sp), "isci_engine_create")
+    return Engine(out, sp)
+
+
+def isci_engine_config(e: Engine, grid: int = 0, heaviest_first: bool = True):
+    check(_lib.load().isci_engine_config(e.ptr, int(grid), 1 if heaviest_first else 0), "isci_engine_config")
+
+
+def isci_engine_add(e: Engine, hd: Handle, nroots: int = 1, guess=None, **opts) -> int:
+    slot = ctypes.c_int()
+    o = _opts(**opts)
+    gp, ng = ctypes.c_void_p(0), 0
+    if guess is not None:
+        gp, ng = _dev_f64(guess, "guess"), int(guess.shape[0])
+    check(_lib.load().isci_engine_add(e.ptr, hd.ptr, int(nroots), ctypes.byref(o), gp, ng, ctypes.byref(slot)),
+          "isci_engine_add")
+    e.handles[slot.value] = (hd, nroots)
+    return slot.value
+
+
+def isci_engine_step(e: Engine) -> int:
+    n = ctypes.c_int()
+    check(_lib.load().isci_engine_step(e.ptr, ctypes.byref(n)), "isci_engine_step")
+    return n.value
+
+
+def isci_engine_result(e: Engine, slot: int, want_vectors: bool = False):
+    """(done, energies, vectors or None, info)."""
+    torch = _torch()
+    hd, nroots = e.handles[slot]
+    done = ctypes.c_int()
+    en = (ctypes.c_double * nroots)()
+    info = IsciDavidsonInfo()
+    vec = None
+    st = _lib.load().isci_engine_result(e.ptr, slot, ctypes.byref(done), en, None, ctypes.byref(info))
+    if st not in (_lib.ISCI_OK, _lib.ISCI_E_NOT_CONVERGED):
+        check(st, "isci_engine_result")
+    if done.value and want_vectors:
+        vec = torch.empty((nroots, hd.dim), dtype=torch.float64, device="cuda")
+        _lib.load().isci_engine_result(e.ptr, slot, None, None, _dev_f64(vec, "vectors"), None)
+    inf = {"iterations": info.iterations, "converged": bool(info.converged),
+           "sigma_calls": info.sigma_calls, "residual": list(info.residual)[:nroots], "status": st}
+    return bool(done.value), np.array(list(en)), vec, inf
+
+
+def isci_engine_release(e: Engine, slot: int):
+    check(_lib.load().isci_engine_release(e.ptr, int(slot)), "isci_engine_release")
+    e.handles.pop(slot, None)
+
+
+def isci_engine_sigma(e: Engine, handles, cs, sigmas):
+    """Fused sigma: sigmas[i] = H_i cs[i] for every handle, one launch."""
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+    NV = (ctypes.c_int * n)(*[int(c.shape[0]) if c.dim() == 2 else 1 for c in cs])
+    C = (ctypes.c_void_p * n)(*[_dev_f64(c, "c").value for c in cs])
+    S = (ctypes.c_void_p * n)(*[_dev_f64(s, "sigma").value for s in sigmas])
+    LC = (ctypes.c_int64 * n)(*[int(c.stride(0)) if c.dim() == 2 else h.dim for c, h in zip(cs, handles)])
+    LS = (ctypes.c_int64 * n)(*[int(s.stride(0)) if s.dim() == 2 else h.dim for s, h in zip(sigmas, handles)])
+    check(_lib.load().isci_engine_sigma(e.ptr, n, H, NV, C, LC, S, LS), "isci_engine_sigma")
+
+
+def isci_engine_destroy(e: Engine):
+    e.destroy()
+
+
+def isci_davidson_footprint(hd: Handle, nroots: int = 1, **opts) -> int:
+    o = _opts(**opts)
+    return int(_lib.load().isci_davidson_footprint(hd.ptr, int(nroots), ctypes.byref(o)))

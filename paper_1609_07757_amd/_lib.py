@@ -28,6 +28,9 @@ ABI_SYMBOLS = (
     "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
     "isci_davidson_defaults", "isci_strings", "isci_rowstart", "isci_get_stats",
     "isci_destroy", "isci_status_string", "isci_last_error",
+    "isci_engine_create", "isci_engine_config", "isci_engine_add", "isci_engine_step",
+    "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
+    "isci_davidson_footprint",
 )
 
 
@@ -91,6 +94,28 @@ def load(path: str = LIBPATH):
     L.isci_status_string.restype = ctypes.c_char_p
     L.isci_last_error.argtypes = []
     L.isci_last_error.restype = ctypes.c_char_p
+    L.isci_engine_create.argtypes = [ctypes.POINTER(vp), vp]
+    L.isci_engine_create.restype = i32
+    L.isci_engine_config.argtypes = [vp, i32, i32]
+    L.isci_engine_config.restype = i32
+    L.isci_engine_add.argtypes = [vp, vp, i32, ctypes.POINTER(IsciDavidsonOpts), vp, i32,
+                                  ctypes.POINTER(ctypes.c_int)]
+    L.isci_engine_add.restype = i32
+    L.isci_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.isci_engine_step.restype = i32
+    L.isci_engine_result.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl), vp,
+                                     ctypes.POINTER(IsciDavidsonInfo)]
+    L.isci_engine_result.restype = i32
+    L.isci_engine_release.argtypes = [vp, i32]
+    L.isci_engine_release.restype = i32
+    L.isci_engine_sigma.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                    ctypes.POINTER(i64)]
+    L.isci_engine_sigma.restype = i32
+    L.isci_engine_destroy.argtypes = [vp]
+    L.isci_engine_destroy.restype = None
+    L.isci_davidson_footprint.argtypes = [vp, i32, ctypes.POINTER(IsciDavidsonOpts)]
+    L.isci_davidson_footprint.restype = i64
     _LIB = L
     return L
 

@@ -57,6 +57,7 @@ struct DevTabs {
     double *jj = nullptr;    // (pp|qq)
     double *ssd = nullptr;   // (pp|qq) - (pq|qp)
     unsigned long long *counters = nullptr;  // [2 * ISCI_NBUCKET] kept, terms
+    int2 *plan = nullptr;                     // work items (alpha row, first beta target)
 };
 
 struct SigmaArgs {
@@ -73,6 +74,19 @@ struct SigmaArgs {
     const double *hd, *jj, *ssd;
 };
 
+// One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)
+// vectors at c / s with leading dimensions ldc / lds; its work items are
+// plan[0..nitems) of the instance (one alpha row, 256 beta targets each)
+// and occupy the global item range [item0, item0 + nitems).
+struct BatchVec {
+    int inst, nv;
+    const double *c;
+    double *s;
+    int64_t ldc, lds;
+    const int2 *plan;
+    int nitems, item0;
+};
+
 }  // namespace isci
 
 struct isci_ctx {
@@ -87,6 +101,7 @@ struct isci_ctx {
     std::vector<int32_t> h_aorb, h_borb, h_alev, h_blev;  // host string tables
     std::vector<int64_t> h_rowstart;
     int max_rowlen = 0;
+    int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     // scratch for the eigensolver (grown on demand)
     std::vector<void *> work;
 };
@@ -108,6 +123,8 @@ SigmaArgs sigma_args(const isci_ctx *c);
 isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t ldc,
                          double *sv, int64_t lds, hipStream_t s);
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
+isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
+                                 int nvmax, int grid, hipStream_t s);
 
 // device vector helpers used by the eigensolver
 isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int k,

@@ -541,6 +541,14 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     }
     c->h_rowstart[c->sa.nstr] = acc;
     c->dim = acc;
+    // work plan of one sigma job: (alpha row, first beta target) per block of
+    // 256 targets, rows in layout order
+    std::vector<int2> plan;
+    for (int i = 0; i < c->sa.nstr; ++i) {
+        const int len = (int)(c->h_rowstart[i + 1] - c->h_rowstart[i]);
+        for (int b0 = 0; b0 < len; b0 += 256) plan.push_back(make_int2(i, b0));
+    }
+    c->nplan = (int)plan.size();
     if (acc >= ((int64_t)1 << 62)) { destroy(c); set_error("dimension too large"); return ISCI_E_UNSUPPORTED; }
     c->stats.dim = acc;
     c->stats.nstr_alpha = c->sa.nstr;
@@ -555,7 +563,8 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     c->d.alev = (int8_t *)dev_alloc(c, c->sa.nstr);
     c->d.blev = (int8_t *)dev_alloc(c, c->sb.nstr);
     c->d.rowstart = (int64_t *)dev_alloc(c, sizeof(int64_t) * (c->sa.nstr + 1));
-    if (!c->d.astr || !c->d.bstr || !c->d.alev || !c->d.blev || !c->d.rowstart) {
+    c->d.plan = (int2 *)dev_alloc(c, sizeof(int2) * plan.size());
+    if (!c->d.astr || !c->d.bstr || !c->d.alev || !c->d.blev || !c->d.rowstart || !c->d.plan) {
         destroy(c);
         set_error("device allocation failed (strings)");
         return ISCI_E_OOM;
@@ -567,6 +576,7 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     e = e ? e : hipMemcpyAsync(c->d.blev, lb.data(), lb.size(), hipMemcpyHostToDevice, stream);
     e = e ? e : hipMemcpyAsync(c->d.rowstart, c->h_rowstart.data(), sizeof(int64_t) * c->h_rowstart.size(),
                                hipMemcpyHostToDevice, stream);
+    e = e ? e : hipMemcpyAsync(c->d.plan, plan.data(), sizeof(int2) * plan.size(), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) { destroy(c); return hip_fail(e, "upload string tables"); }
     isci_status st = build_lists(c, h, eri, stream);
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }

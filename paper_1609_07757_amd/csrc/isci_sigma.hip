@@ -17,6 +17,8 @@
 // eta(Y,p,r) eta(Y,q,s) with eta(Y,q,s) = eps(Y,q) eps(Y,s).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "isci_device.h"
 #include "isci_internal.h"
 
@@ -48,15 +50,15 @@ __device__ inline bool replace_two(const int *o, int n, int i, int j, int q, int
     return true;
 }
 
+// sigma for the target determinant (ia, ib) of one instance, vectors v < nv
 template <int NV>
-__global__ __launch_bounds__(256) void k_sigma_generic(SigmaArgs A, int nv, const double *__restrict__ c,
-                                                       int64_t ldc, double *__restrict__ sg, int64_t lds)
+__device__ __forceinline__ void sigma_target(const SigmaArgs &A, int ia, int ib, int nv,
+                                             const double *__restrict__ c, int64_t ldc,
+                                             double *__restrict__ sg, int64_t lds)
 {
-    const int ia = blockIdx.x;
     const int la = A.alev[ia];
     const int L = A.L;
     const int rlen = A.sb.le[L - la];
-    const int ib = blockIdx.y * blockDim.x + threadIdx.x;
     if (ib >= rlen) return;
     const int na = A.sa.n, nb = A.sb.n, norb = A.norb;
     int ao[ISCI_MAXN], bo[ISCI_MAXN], jo[ISCI_MAXN];
@@ -181,6 +183,30 @@ __global__ __launch_bounds__(256) void k_sigma_generic(SigmaArgs A, int nv, cons
         if (v < nv) dst[v * lds] = acc[v];
 }
 
+template <int NV>
+__global__ __launch_bounds__(256) void k_sigma_generic(SigmaArgs A, int nv, const double *__restrict__ c,
+                                                       int64_t ldc, double *__restrict__ sg, int64_t lds)
+{
+    sigma_target<NV>(A, blockIdx.x, blockIdx.y * blockDim.x + threadIdx.x, nv, c, ldc, sg, lds);
+}
+
+// Fused sigma over many instances: a persistent grid walks the global
+// work-item range; item g belongs to the job whose range holds it (jobs
+// are few, so a linear search over their start offsets is cheap and
+// uniform across the workgroup).
+template <int NV>
+__global__ __launch_bounds__(256) void k_sigma_batched(const SigmaArgs *__restrict__ args,
+                                                       const BatchVec *__restrict__ vecs, int njobs, int nitems)
+{
+    int job = 0;
+    for (int g = blockIdx.x; g < nitems; g += gridDim.x) {
+        while (job + 1 < njobs && vecs[job + 1].item0 <= g) ++job;
+        const BatchVec &bv = vecs[job];
+        const int2 w = bv.plan[g - bv.item0];
+        sigma_target<NV>(args[bv.inst], w.x, w.y + threadIdx.x, bv.nv, bv.c, bv.ldc, bv.s, bv.lds);
+    }
+}
+
 // diagonal of H_tau: kept diagonal units
 __global__ __launch_bounds__(256) void k_diag(SigmaArgs A, double *__restrict__ out)
 {
@@ -225,6 +251,23 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             k_sigma_generic<8><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
         ISCI_HIP(hipGetLastError());
     }
+    return ISCI_OK;
+}
+
+isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
+                                 int nvmax, int grid, hipStream_t s)
+{
+    if (nitems <= 0 || njobs <= 0) return ISCI_OK;
+    grid = grid > 0 ? std::min(grid, nitems) : nitems;
+    if (nvmax <= 1)
+        k_sigma_batched<1><<<grid, 256, 0, s>>>(args_dev, vecs_dev, njobs, nitems);
+    else if (nvmax <= 2)
+        k_sigma_batched<2><<<grid, 256, 0, s>>>(args_dev, vecs_dev, njobs, nitems);
+    else if (nvmax <= 4)
+        k_sigma_batched<4><<<grid, 256, 0, s>>>(args_dev, vecs_dev, njobs, nitems);
+    else
+        k_sigma_batched<8><<<grid, 256, 0, s>>>(args_dev, vecs_dev, njobs, nitems);
+    ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }
 

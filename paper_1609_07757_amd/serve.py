@@ -1,0 +1,243 @@
+"""Serving loop for Davidson solves with continuous batching.
+
+Requests arrive over time (each carries its integrals, norb, electron
+counts, excitation level, tau and number of roots).  The loop admits
+requests in arrival order while their device footprint fits the HBM
+budget and a slot is free, adds them to a running multi-instance engine
+(``isci_engine``) at the next iteration boundary, advances every admitted
+solve by one Davidson iteration per step (one fused sigma launch for all
+of them), and retires finished solves, freeing their memory for the
+queue.  Latency is measured from arrival to energies.
+
+The scheduler is written against a small executor interface so that its
+admission and batching logic can be exercised on the CPU with a mock
+executor; ``GpuExecutor`` drives the HIP library through the C ABI.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from math import comb
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float              # seconds on the server clock
+    norb: int
+    nalpha: int
+    nbeta: int
+    level: int
+    tau: float
+    nroots: int
+    payload: object = None      # executor-specific (integrals or a generator)
+    # filled by the server
+    admitted: float | None = None
+    finished: float | None = None
+    energies: np.ndarray | None = None
+    info: dict = field(default_factory=dict)
+    status: str = "queued"      # queued | running | done | rejected | cancelled
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def ci_dim(norb, na, nb, level):
+    tot = 0
+    for ka in range(na + 1):
+        for kb in range(nb + 1):
+            if ka + kb <= level:
+                tot += comb(na, ka) * comb(norb - na, ka) * comb(nb, kb) * comb(norb - nb, kb)
+    return tot
+
+
+def davidson_bytes(dim: int, nroots: int) -> int:
+    """Device bytes of one Davidson solve with default options (the same
+    sizing rule as the library: nroots + 2 followed roots, subspace
+    max(32, 6 (nroots + 2)), thick restart keeping <= 2 kk + 4 vectors)."""
+    kk = min(dim, nroots + 2)
+    mmax = min(max(32, 6 * kk, 2 * kk), dim)
+    keep = max(kk, min(2 * kk + 4, mmax // 2))
+    nscr = max(kk, keep)
+    nblk = min(512, max(1, (dim + 255) // 256))
+    return 8 * dim * (2 * mmax + nscr + 2 * kk + 1) + 8 * (mmax * mmax + 8 * mmax + 64 + nblk * mmax * mmax + 3 * (mmax + 8))
+
+
+def handle_bytes_bound(norb: int, dim: int) -> int:
+    """Upper bound of a handle's resident tables (screened lists assume
+    every alpha-beta unit is kept) plus the transient dense eri."""
+    n3 = norb ** 3
+    lists = 8 * (n3 + 1) + 9 * norb ** 4 // 8 + 4 * norb * norb * 16
+    strings = 8 * (norb * norb) * 4
+    return 8 * norb ** 4 + lists + strings + 8 * dim
+
+
+class Server:
+    """Continuous-batching scheduler.
+
+    executor: object with
+        footprint(req) -> int          device bytes needed while the request runs
+        start(req) -> token            build the handle and admit the solve
+        step() -> int                  one iteration for all running solves
+        poll(token) -> (done, energies, info)
+        finish(token)                  free the solve and its handle
+    hbm_budget: bytes available for running requests.
+    max_slots: concurrently running solves.
+    clock: callable returning seconds (default time.perf_counter relative to run()).
+    """
+
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 64, clock=None):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.clock = clock
+        self.used = 0
+        self.queue: deque[Request] = deque()
+        self.running: dict = {}          # token -> (req, bytes)
+        self.done: list[Request] = []
+        self.steps = 0
+        self.peak_used = 0
+        self.peak_running = 0
+
+    def _now(self):
+        return self.clock() - self._t0
+
+    def cancel(self, rid: int) -> bool:
+        for r in list(self.queue):
+            if r.rid == rid:
+                self.queue.remove(r)
+                r.status = "cancelled"
+                self.done.append(r)
+                return True
+        for tok, (r, b) in list(self.running.items()):
+            if r.rid == rid:
+                self.ex.finish(tok)
+                del self.running[tok]
+                self.used -= b
+                r.status = "cancelled"
+                self.done.append(r)
+                return True
+        return False
+
+    def _admit(self):
+        """Admit queued requests in arrival order while they fit; a request
+        larger than the whole budget is rejected; one that does not fit now
+        waits (head of line) until memory frees up."""
+        while self.queue and len(self.running) < self.max_slots:
+            r = self.queue[0]
+            need = int(self.ex.footprint(r))
+            if need > self.budget:
+                self.queue.popleft()
+                r.status = "rejected"
+                r.finished = self._now()
+                self.done.append(r)
+                continue
+            if self.used + need > self.budget:
+                break
+            self.queue.popleft()
+            tok = self.ex.start(r)
+            r.admitted = self._now()
+            r.status = "running"
+            self.running[tok] = (r, need)
+            self.used += need
+            self.peak_used = max(self.peak_used, self.used)
+        self.peak_running = max(self.peak_running, len(self.running))
+
+    def _retire(self):
+        for tok, (r, b) in list(self.running.items()):
+            done, en, info = self.ex.poll(tok)
+            if done:
+                r.finished = self._now()
+                r.energies = en
+                r.info = info
+                r.status = "done"
+                self.ex.finish(tok)
+                del self.running[tok]
+                self.used -= b
+                self.done.append(r)
+
+    def run(self, requests, max_wall: float | None = None):
+        """Serve `requests` (sorted by arrival).  Returns the finished list."""
+        if self.clock is None:
+            self.clock = time.perf_counter
+        self._t0 = self.clock()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        while pending or self.queue or self.running:
+            now = self._now()
+            if max_wall is not None and now > max_wall:
+                break
+            while pending and pending[0].arrival <= now:
+                self.queue.append(pending.popleft())
+            self._admit()
+            if self.running:
+                self.ex.step()
+                self.steps += 1
+                self._retire()
+            elif pending:
+                wait = pending[0].arrival - self._now()
+                if wait > 0:
+                    self._sleep(wait)
+        return self.done
+
+    def _sleep(self, dt):
+        if self.clock is time.perf_counter:
+            time.sleep(min(dt, 0.05))
+        elif hasattr(self.clock, "advance"):
+            self.clock.advance(dt)
+
+    def report(self):
+        lat = np.array([r.latency for r in self.done if r.status == "done"])
+        out = {"served": int(len(lat)), "rejected": sum(r.status == "rejected" for r in self.done),
+               "steps": self.steps, "peak_running": self.peak_running, "peak_bytes": self.peak_used}
+        if len(lat):
+            out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                        "mean_s": float(lat.mean())})
+        return out
+
+
+class GpuExecutor:
+    """Runs requests on the HIP library: integrals are produced on the
+    device by `payload` (a callable returning (h, eri) CUDA tensors), the
+    handle is built, the dense eri is dropped, and the solve joins the
+    engine.  Footprint = transient eri + handle tables (bound) + subspace."""
+
+    def __init__(self, davidson_opts=None, stream=None):
+        import paper_1609_07757_amd as isci
+        self.isci = isci
+        self.eng = isci.isci_engine_create(stream)
+        self.opts = davidson_opts or {}
+        self.sigma_vectors = 0
+        self.handles = {}
+
+    def footprint(self, r: Request) -> int:
+        dim = ci_dim(r.norb, r.nalpha, r.nbeta, r.level)
+        return handle_bytes_bound(r.norb, dim) + davidson_bytes(dim, r.nroots)
+
+    def start(self, r: Request):
+        h, eri = r.payload()
+        hd = self.isci.isci_create(h, eri, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
+        del h, eri
+        slot = self.isci.isci_engine_add(self.eng, hd, nroots=r.nroots, **self.opts)
+        self.handles[slot] = hd
+        return slot
+
+    def step(self) -> int:
+        return self.isci.isci_engine_step(self.eng)
+
+    def poll(self, slot):
+        done, en, _, info = self.isci.isci_engine_result(self.eng, slot)
+        if done:
+            self.sigma_vectors += info["sigma_calls"]
+        return done, en, info
+
+    def finish(self, slot):
+        self.isci.isci_engine_release(self.eng, slot)
+        hd = self.handles.pop(slot)
+        hd.destroy()
+
+    def close(self):
+        self.eng.destroy()

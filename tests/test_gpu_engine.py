@@ -1,0 +1,120 @@
+"""GPU tests of the multi-instance engine: the fused sigma over several
+handles equals each handle's own sigma, and batched Davidson solves give
+the same energies in a mix as alone (and match the oracle)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from isci_inputs import random_vectors, recipe_a, recipe_b
+
+from gpu_common import create, gpu_sigma, rel_err, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+MIX = [("B", 8, 2, 1e-10, 1), ("A", 12, 3, 1e-12, 2), ("B", 10, 4, 1e-12, 3),
+       ("A", 20, 2, 1e-14, 1), ("B", 6, 2, 0.0, 2), ("A", 16, 3, 1e-12, 4)]
+
+
+def _make(case, seed):
+    recipe, norb, L, tau, nroots = case
+    h, eri = (recipe_a if recipe == "A" else recipe_b)(norb, seed=seed)
+    return h, eri, create(h, eri, norb, 2, 2, L, tau)
+
+
+def test_fused_sigma_equals_single():
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    hs, cs, ss, refs = [], [], [], []
+    for i, case in enumerate(MIX):
+        h, eri, hd = _make(case, 30 + i)
+        nv = 1 + (i % 3) * 4          # 1, 5, 9 vectors (9 spans two launches of 8)
+        c = random_vectors(hd.dim, nv, seed=i)
+        hs.append(hd)
+        cs.append(torch.from_numpy(c).to(dev))
+        ss.append(torch.full((nv, hd.dim), float("nan"), dtype=torch.float64, device=dev))
+        refs.append(gpu_sigma(hd, c))
+        S = O.Space(case[1], 2, 2, case[2])
+        assert rel_err(refs[-1], O.sigma(S, h, eri, case[3], c)) <= 1e-12
+    e = isci.isci_engine_create()
+    for grid, order in ((0, True), (64, True), (7, False)):
+        isci.isci_engine_config(e, grid, order)
+        isci.isci_engine_sigma(e, hs, cs, ss)
+        torch.cuda.synchronize()
+        for s, r in zip(ss, refs):
+            assert np.array_equal(s.cpu().numpy(), r)
+    e.destroy()
+
+
+def test_batched_davidson_alone_equals_mix():
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    made = [_make(case, 50 + i) for i, case in enumerate(MIX)]
+    alone = []
+    for (h, eri, hd), case in zip(made, MIX):
+        e, _, info = isci.isci_davidson(hd, nroots=case[4], tol_residual=1e-8)
+        assert info["converged"]
+        alone.append(e)
+        S = O.Space(case[1], 2, 2, case[2])
+        w = np.linalg.eigvalsh(O.dense_h(S, h, eri, case[3]))
+        assert np.abs(e - w[:case[4]]).max() <= 1e-10
+    eng = isci.isci_engine_create()
+    slots = [isci.isci_engine_add(eng, hd, nroots=case[4], tol_residual=1e-8)
+             for (h, eri, hd), case in zip(made, MIX)]
+    steps = 0
+    while isci.isci_engine_step(eng) > 0:
+        steps += 1
+        assert steps < 1000
+    for sl, ref in zip(slots, alone):
+        done, en, _, info = isci.isci_engine_result(eng, sl)
+        assert done and info["converged"]
+        assert np.array_equal(en, ref)
+    eng.destroy()
+
+
+def test_continuous_admission_same_energies():
+    """Slots admitted while others are mid-solve converge to the same
+    energies as alone; released slots free their ids for reuse."""
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    made = [_make(case, 70 + i) for i, case in enumerate(MIX)]
+    alone = [isci.isci_davidson(hd, nroots=case[4])[0] for (h, eri, hd), case in zip(made, MIX)]
+    eng = isci.isci_engine_create()
+    pending = list(range(len(MIX)))
+    live = {}
+    results = {}
+    it = 0
+    while pending or live:
+        if pending and it % 3 == 0:
+            i = pending.pop(0)
+            live[isci.isci_engine_add(eng, made[i][2], nroots=MIX[i][4])] = i
+        isci.isci_engine_step(eng)
+        for sl in list(live):
+            done, en, _, info = isci.isci_engine_result(eng, sl)
+            if done:
+                results[live.pop(sl)] = en
+                isci.isci_engine_release(eng, sl)
+        it += 1
+        assert it < 2000
+    for i, ref in enumerate(alone):
+        assert np.array_equal(results[i], ref)
+    eng.destroy()
+
+
+def test_footprint_positive_and_monotone():
+    import paper_1609_07757_amd as isci
+    torch_dev()
+    _, _, hd = _make(("A", 20, 2, 1e-14, 1), 1)
+    f1 = isci.isci_davidson_footprint(hd, 1)
+    f3 = isci.isci_davidson_footprint(hd, 3)
+    assert 0 < f1 < f3
+    assert f1 >= 8 * hd.dim * 32
+
+
+def test_python_footprint_model_matches_library():
+    import paper_1609_07757_amd as isci
+    from paper_1609_07757_amd.serve import davidson_bytes
+    torch_dev()
+    for case in MIX[:3]:
+        _, _, hd = _make(case, 2)
+        for k in (1, 2, 4):
+            assert davidson_bytes(hd.dim, k) == isci.isci_davidson_footprint(hd, k)
