@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--workload", default="cisdt_n60")
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
+    ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
@@ -61,6 +62,15 @@ def main():
     h, eri = W.integrals()
     hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb,
                           W.nalpha, W.nbeta, W.level, tau)
+    variant = {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
+               "mfma": isci.SIGMA_MFMA}[a.kernel]
+    isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
+    if variant == isci.SIGMA_GENERAL or W.nalpha != 2 or W.nbeta != 2:
+        kname = "k_sigma_generic"
+    elif variant == isci.SIGMA_MFMA:
+        kname = "k_sigma_ab_mfma+k_sigma_n2"
+    else:
+        kname = "k_sigma_n2"
     st = isci.isci_get_stats(hd)
     dim = hd.dim
     c = torch.from_numpy(random_vectors(dim, nvec, seed=21)).to(dev)
@@ -91,7 +101,7 @@ def main():
         try:
             tj = json.load(open(a.traffic_json))
             key = f"{a.workload}:nvec{nvec}:tau{tau:g}"
-            if key in tj and tj[key].get("kernel_version") == "k_sigma_generic":
+            if key in tj and tj[key].get("kernel_version") == kname:
                 traffic = tj[key]["bytes_per_launch"]
         except Exception:
             traffic = None
@@ -115,7 +125,7 @@ def main():
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
         "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "kernel": "k_sigma_generic", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "launches_per_step": nlaunch,
                      "algorithmic_flops_per_step": flops_step},

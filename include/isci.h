@@ -219,6 +219,20 @@ void isci_engine_destroy(isci_engine e);
  * isci_stats.device_bytes).  -1 on bad arguments. */
 int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_opts *opts);
 
+/* Per-handle options.
+ *   ISCI_OPT_SIGMA_KERNEL: ISCI_SIGMA_AUTO (default: pair kernel when both
+ *   spins hold two electrons, else the general one), ISCI_SIGMA_GENERAL
+ *   (string algebra for any electron count), ISCI_SIGMA_PAIR (two-electron
+ *   pair tables; ISCI_E_UNSUPPORTED otherwise), ISCI_SIGMA_MFMA (pair
+ *   tables, alpha-beta class on FP64 matrix cores; two electrons per spin).
+ *   All give the same sigma up to rounding. */
+#define ISCI_OPT_SIGMA_KERNEL 1
+#define ISCI_SIGMA_AUTO 0
+#define ISCI_SIGMA_GENERAL 1
+#define ISCI_SIGMA_PAIR 2
+#define ISCI_SIGMA_MFMA 3   /* pair kernel for one-body / same-spin + FP64 MFMA tiles for alpha-beta */
+isci_status isci_set_option(isci_handle hd, int option, int value);
+
 void isci_destroy(isci_handle hd);
 const char *isci_status_string(isci_status s);
 const char *isci_last_error(void);

@@ -58,6 +58,18 @@ struct DevTabs {
     double *ssd = nullptr;   // (pp|qq) - (pq|qp)
     unsigned long long *counters = nullptr;  // [2 * ISCI_NBUCKET] kept, terms
     int2 *plan = nullptr;                     // work items (alpha row, first beta target)
+    // two-electron spins: index of string {a, b} (a != b) in layout order,
+    // -1 when a == b or the string is above the level cut
+    int *apidx = nullptr, *bpidx = nullptr;
+    // alpha-beta MFMA tiles (two electrons per spin): orbitals grouped in
+    // blocks of 4 (occupied block padded with -1); per ordered row-block pair
+    // (A,B) a CSR list of column chunks (q, S-block) with their 16x4 values
+    // (pq|rs), p in A, r in B, s in S, laid out in MFMA operand-A lane order
+    int8_t *blk_orb = nullptr;      // [nblk][4]
+    int *chunk_off = nullptr;       // [nblk*nblk + 1]
+    int2 *chunk_desc = nullptr;     // (q, S)
+    double *chunk_val = nullptr;    // [nchunk][64]
+    uchar4 *quads = nullptr;        // target tiles (X, P, Y, R) with X<=P, Y<=R, level <= L
 };
 
 struct SigmaArgs {
@@ -72,6 +84,16 @@ struct SigmaArgs {
     const long long *ab_off; const uint8_t *ab_s; const double *ab_v;
     const int *pq_off; const uint8_t *pq_q;
     const double *hd, *jj, *ssd;
+    const int *apidx, *bpidx;
+    int variant;             // 1: general strings, 2: two-electron pair tables, 3: pair + MFMA alpha-beta
+    int classes;             // bit 0 one-body, bit 1 same-spin, bit 2 alpha-beta (pair kernel)
+    int accumulate;          // pair kernel adds into sigma instead of overwriting
+    int nblk;
+    const int8_t *blk_orb;
+    const int *chunk_off;
+    const int2 *chunk_desc;
+    const double *chunk_val;
+    const uchar4 *quads;
 };
 
 // One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)
@@ -102,6 +124,9 @@ struct isci_ctx {
     std::vector<int64_t> h_rowstart;
     int max_rowlen = 0;
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
+    int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
+    int nblk = 0, nchunk = 0, nquad = 0;
+    bool have_tiles = false;
     // scratch for the eigensolver (grown on demand)
     std::vector<void *> work;
 };

@@ -386,7 +386,135 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.ab_off = c->d.ab_off; A.ab_s = c->d.ab_s; A.ab_v = c->d.ab_v;
     A.pq_off = c->d.pq_off; A.pq_q = c->d.pq_q;
     A.hd = c->d.hd; A.jj = c->d.jj; A.ssd = c->d.ssd;
+    A.apidx = c->d.apidx; A.bpidx = c->d.bpidx;
+    const bool pair_ok = c->sa.n == 2 && c->sb.n == 2;
+    A.variant = (c->sigma_variant == ISCI_SIGMA_GENERAL || !pair_ok) ? 1 : 2;
+    if (pair_ok && c->have_tiles && c->sigma_variant == ISCI_SIGMA_MFMA) A.variant = 3;
+    A.classes = 7;
+    A.accumulate = 0;
+    A.nblk = c->nblk;
+    A.blk_orb = c->d.blk_orb;
+    A.chunk_off = c->d.chunk_off;
+    A.chunk_desc = c->d.chunk_desc;
+    A.chunk_val = c->d.chunk_val;
+    A.quads = c->d.quads;
     return A;
+}
+
+
+// ------------------------------------------------------------------ alpha-beta MFMA tiles
+
+// mark column chunk ((A*nb + B)*norb + q)*nb + S of every kept (pq|rs)
+__global__ void k_chunk_mark(const long long *ab_off, const uint8_t *ab_s, int n, const int *orb_blk, int nb,
+                             unsigned *bits)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;
+    const int p = (int)(t / ((int64_t)n * n)), q = (int)((t / n) % n), r = (int)(t % n);
+    for (long long e = ab_off[t]; e < ab_off[t + 1]; ++e) {
+        const int s = ab_s[e];
+        const long long key = (((long long)orb_blk[p] * nb + orb_blk[r]) * n + q) * nb + orb_blk[s];
+        atomicOr(&bits[key >> 5], 1u << (key & 31));
+    }
+}
+
+__global__ void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * nb) return;
+    const long long k0 = (long long)g * n * nb, k1 = k0 + (long long)n * nb;
+    int c = 0;
+    for (long long k = k0; k < k1; ++k) c += (bits[k >> 5] >> (k & 31)) & 1u;
+    cnt[g] = c;
+}
+
+__global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int nb, double tau,
+                             const int8_t *blk_orb, const int *off, int2 *desc, double *val)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * nb) return;
+    const int Ab = g / nb, Bb = g % nb;
+    const long long k0 = (long long)g * n * nb;
+    int w = off[g];
+    for (int q = 0; q < n; ++q)
+        for (int S = 0; S < nb; ++S) {
+            const long long k = k0 + (long long)q * nb + S;
+            if (!((bits[k >> 5] >> (k & 31)) & 1u)) continue;
+            desc[w] = make_int2(q, S);
+            for (int l = 0; l < 64; ++l) {
+                const int i = l & 15, kk = l >> 4;
+                const int p = blk_orb[Ab * 4 + (i >> 2)], r = blk_orb[Bb * 4 + (i & 3)], s = blk_orb[S * 4 + kk];
+                double v = 0.0;
+                if (p >= 0 && r >= 0 && s >= 0) {
+                    v = geri(eri, n, p, q, r, s);
+                    if (!(fabs(v) > tau)) v = 0.0;
+                }
+                val[(size_t)w * 64 + l] = v;
+            }
+            ++w;
+        }
+}
+
+// blocks of four orbitals, o/v pure (two electrons per spin: the occupied
+// block is {0, 1, -, -}); target tiles with level <= L; column chunks
+static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
+{
+    const int n = c->norb;
+    std::vector<int8_t> bo;
+    bo.insert(bo.end(), {0, (int8_t)(n > 1 ? 1 : -1), -1, -1});
+    for (int v = 2; v < n; v += 4)
+        for (int k = 0; k < 4; ++k) bo.push_back((int8_t)(v + k < n ? v + k : -1));
+    const int nb = (int)bo.size() / 4;
+    std::vector<int> ob(n, 0);
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 4; ++k)
+            if (bo[b * 4 + k] >= 0) ob[bo[b * 4 + k]] = b;
+    std::vector<uchar4> quads;
+    for (int X = 0; X < nb; ++X)
+        for (int P = X; P < nb; ++P)
+            for (int Y = 0; Y < nb; ++Y)
+                for (int R = Y; R < nb; ++R) {
+                    const int lev = (X != 0) + (P != 0) + (Y != 0) + (R != 0);
+                    if (lev > c->L) continue;
+                    quads.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
+                }
+    c->nblk = nb;
+    c->nquad = (int)quads.size();
+    DevTabs &d = c->d;
+    d.blk_orb = (int8_t *)dev_alloc(c, bo.size());
+    d.quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, quads.size()));
+    int *dob = (int *)dev_alloc(c, sizeof(int) * n);
+    const long long nkeys = (long long)nb * nb * n * nb;
+    unsigned *bits = nullptr;
+    ISCI_HIP(hipMallocAsync((void **)&bits, sizeof(unsigned) * (size_t)((nkeys + 31) / 32 + 1), s));
+    d.chunk_off = (int *)dev_alloc(c, sizeof(int) * (nb * nb + 1));
+    if (!d.blk_orb || !d.quads || !dob || !d.chunk_off) { set_error("device allocation failed (tiles)"); return ISCI_E_OOM; }
+    ISCI_HIP(hipMemcpyAsync(d.blk_orb, bo.data(), bo.size(), hipMemcpyHostToDevice, s));
+    if (!quads.empty())
+        ISCI_HIP(hipMemcpyAsync(d.quads, quads.data(), sizeof(uchar4) * quads.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(dob, ob.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemsetAsync(bits, 0, sizeof(unsigned) * (size_t)((nkeys + 31) / 32 + 1), s));
+    ISCI_HIP(hipMemsetAsync(d.chunk_off, 0, sizeof(int) * (nb * nb + 1), s));
+    const int64_t n3 = (int64_t)n * n * n;
+    k_chunk_mark<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(d.ab_off, d.ab_s, n, dob, nb, bits);
+    k_chunk_count<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, n, nb, d.chunk_off);
+    ISCI_HIP(hipGetLastError());
+    isci_status st = scan_inplace<int>(d.chunk_off, nb * nb + 1, s);
+    if (st != ISCI_OK) return st;
+    int tot = 0;
+    ISCI_HIP(hipMemcpyAsync(&tot, d.chunk_off + nb * nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipStreamSynchronize(s));   // also keeps the host tables above alive until copied
+    d.chunk_desc = (int2 *)dev_alloc(c, sizeof(int2) * std::max(1, tot));
+    d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * (size_t)std::max(1, tot));
+    if (!d.chunk_desc || !d.chunk_val) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
+    k_chunk_fill<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, eri, n, nb, c->tau, d.blk_orb, d.chunk_off, d.chunk_desc,
+                                                     d.chunk_val);
+    ISCI_HIP(hipGetLastError());
+    ISCI_HIP(hipFreeAsync(bits, s));
+    ISCI_HIP(hipStreamSynchronize(s));
+    c->nchunk = tot;
+    c->have_tiles = true;
+    return ISCI_OK;
 }
 
 static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, hipStream_t s)
@@ -578,8 +706,33 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
                                hipMemcpyHostToDevice, stream);
     e = e ? e : hipMemcpyAsync(c->d.plan, plan.data(), sizeof(int2) * plan.size(), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) { destroy(c); return hip_fail(e, "upload string tables"); }
+    // pair-index tables for two-electron spins
+    for (int spin = 0; spin < 2; ++spin) {
+        const SpinTab &T = spin ? c->sb : c->sa;
+        if (T.n != 2) continue;
+        std::vector<int> pidx((size_t)norb * norb, -1);
+        for (int a = 0; a < norb; ++a)
+            for (int b = 0; b < norb; ++b) {
+                if (a == b) continue;
+                int o[2] = {std::min(a, b), std::max(a, b)};
+                if (str_level(o, 2) > T.maxlev) continue;
+                pidx[(size_t)a * norb + b] = str_index(o, T);
+            }
+        int *dp = (int *)dev_alloc(c, sizeof(int) * pidx.size());
+        if (!dp) { destroy(c); set_error("device allocation failed (pair index)"); return ISCI_E_OOM; }
+        hipError_t e2 = hipMemcpyAsync(dp, pidx.data(), sizeof(int) * pidx.size(), hipMemcpyHostToDevice, stream);
+        if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload pair index"); }
+        // the host vector dies here: wait for the copy
+        e2 = hipStreamSynchronize(stream);
+        if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload pair index"); }
+        (spin ? c->d.bpidx : c->d.apidx) = dp;
+    }
     isci_status st = build_lists(c, h, eri, stream);
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
+    if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
+        st = build_tiles(c, eri, stream);
+        if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
+    }
     *out = c;
     return ISCI_OK;
 }
@@ -617,6 +770,24 @@ isci_status isci_rowstart(isci_handle c, int64_t *rowstart)
     if (!c || !rowstart) { set_error("NULL argument"); return ISCI_E_INVALID; }
     std::copy(c->h_rowstart.begin(), c->h_rowstart.end(), rowstart);
     return ISCI_OK;
+}
+
+isci_status isci_set_option(isci_handle c, int option, int value)
+{
+    if (!c) { set_error("NULL handle"); return ISCI_E_INVALID; }
+    switch (option) {
+    case ISCI_OPT_SIGMA_KERNEL:
+        if (value < ISCI_SIGMA_AUTO || value > ISCI_SIGMA_MFMA) { set_error("bad sigma kernel"); return ISCI_E_INVALID; }
+        if ((value == ISCI_SIGMA_PAIR || value == ISCI_SIGMA_MFMA) && !(c->sa.n == 2 && c->sb.n == 2 && c->have_tiles)) {
+            set_error("pair kernel needs two electrons of each spin");
+            return ISCI_E_UNSUPPORTED;
+        }
+        c->sigma_variant = value;
+        return ISCI_OK;
+    default:
+        set_error("unknown option");
+        return ISCI_E_INVALID;
+    }
 }
 
 void isci_destroy(isci_handle c) { destroy(c); }

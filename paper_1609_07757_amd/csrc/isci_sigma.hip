@@ -183,6 +183,246 @@ __device__ __forceinline__ void sigma_target(const SigmaArgs &A, int ia, int ib,
         if (v < nv) dst[v * lds] = acc[v];
 }
 
+
+// Two electrons of each spin.  Strings are orbital pairs; E_pq takes
+// {x, q} to {x, p} with phase sgn(p - x) sgn(q - x) (x the spectator), and
+// the same-spin unit maps {s < q} to {r < p} with phase +1.  String
+// indices come from the pair tables, so no string algebra remains in the
+// loops.
+__device__ __forceinline__ int sgn2(int a, int b) { return (a > b) ? 1 : -1; }   // sgn(a - b), a != b
+
+template <int NV>
+__device__ __forceinline__ void sigma_target_n2(const SigmaArgs &A, int ia, int ib, int nv,
+                                                const double *__restrict__ c, int64_t ldc,
+                                                double *__restrict__ sg, int64_t lds)
+{
+    const int la = A.alev[ia];
+    const int L = A.L;
+    const int rlen = A.sb.le[L - la];
+    if (ib >= rlen) return;
+    const int norb = A.norb;
+    const uint32_t as = A.astr[ia], bs = A.bstr[ib];
+    const int a0 = as & 0xff, a1 = (as >> 8) & 0xff;
+    const int b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
+    const int lb = A.blev[ib];
+    const int64_t myrow = A.rowstart[ia];
+    const int *__restrict__ apx = A.apidx;
+    const int *__restrict__ bpx = A.bpidx;
+
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+
+    const bool do1 = A.classes & 1, doss = A.classes & 2, doab = A.classes & 4;
+    // one-body alpha
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int p = i ? a1 : a0, x = i ? a0 : a1;
+        const int sp = sgn2(p, x);
+        for (int e = do1 ? A.h_off[p] : 0; e < (do1 ? A.h_off[p + 1] : 0); ++e) {
+            const int q = A.h_q[e];
+            if (q == x) continue;
+            const int ja = apx[x * norb + q];
+            if (ja < 0 || A.alev[ja] + lb > L) continue;
+            const double f = (double)(sp * sgn2(q, x)) * A.h_v[e];
+            const double *src = c + A.rowstart[ja] + ib;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += f * src[v * ldc];
+        }
+    }
+    // same-spin alpha: {s < q} -> {a0 < a1}
+    if (doss) {
+        const int P = a1 * (a1 - 1) / 2 + a0;
+        for (int e = A.ss_off[P]; e < A.ss_off[P + 1]; ++e) {
+            const int q = A.ss_qs[e] >> 8, s2 = A.ss_qs[e] & 0xff;
+            const int ja = apx[q * norb + s2];
+            if (ja < 0 || A.alev[ja] + lb > L) continue;
+            const double f = A.ss_v[e];
+            const double *src = c + A.rowstart[ja] + ib;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += f * src[v * ldc];
+        }
+    }
+    const int bmax = rlen;
+    // one-body beta
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int r = i ? b1 : b0, y = i ? b0 : b1;
+        const int sr = sgn2(r, y);
+        for (int e = do1 ? A.h_off[r] : 0; e < (do1 ? A.h_off[r + 1] : 0); ++e) {
+            const int s2 = A.h_q[e];
+            if (s2 == y) continue;
+            const int jb = bpx[y * norb + s2];
+            if (jb < 0 || jb >= bmax) continue;
+            const double f = (double)(sr * sgn2(s2, y)) * A.h_v[e];
+            const double *src = c + myrow + jb;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += f * src[v * ldc];
+        }
+    }
+    // same-spin beta
+    if (doss) {
+        const int P = b1 * (b1 - 1) / 2 + b0;
+        for (int e = A.ss_off[P]; e < A.ss_off[P + 1]; ++e) {
+            const int q = A.ss_qs[e] >> 8, s2 = A.ss_qs[e] & 0xff;
+            const int jb = bpx[q * norb + s2];
+            if (jb < 0 || jb >= bmax) continue;
+            const double f = A.ss_v[e];
+            const double *src = c + myrow + jb;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += f * src[v * ldc];
+        }
+    }
+    // alpha-beta
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int p = i ? a1 : a0, x = i ? a0 : a1;
+        const int sp = sgn2(p, x);
+        for (int e1 = doab ? A.pq_off[p] : 0; e1 < (doab ? A.pq_off[p + 1] : 0); ++e1) {
+            const int q = A.pq_q[e1];
+            if (q == x) continue;
+            const int ja = apx[x * norb + q];
+            if (ja < 0) continue;
+            const int lj = A.alev[ja];
+            if (lj > L) continue;
+            const int lenJ = A.sb.le[L - lj];
+            const int sa = sp * sgn2(q, x);
+            const double *rowJ = c + A.rowstart[ja];
+            const long long base = ((long long)p * norb + q) * norb;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int r = k ? b1 : b0, y = k ? b0 : b1;
+                const int sr = sa * sgn2(r, y);
+                const int *__restrict__ yrow = bpx + y * norb;
+                const long long e0 = A.ab_off[base + r], e1e = A.ab_off[base + r + 1];
+                for (long long e = e0; e < e1e; ++e) {
+                    const int s2 = A.ab_s[e];
+                    if (s2 == y) continue;
+                    const int jb = yrow[s2];
+                    if (jb < 0 || jb >= lenJ) continue;
+                    const double f = (double)(sr * sgn2(s2, y)) * A.ab_v[e];
+                    const double *src = rowJ + jb;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        if (v < nv) acc[v] += f * src[v * ldc];
+                }
+            }
+        }
+    }
+    double *dst = sg + myrow + ib;
+    if (A.accumulate) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) dst[v * lds] += acc[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) dst[v * lds] = acc[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alpha-beta class on FP64 matrix cores (two electrons per spin).
+//
+// With T[x][q][y][s] = sgn(q-x) sgn(s-y) c({x,q},{y,s}) (the CI vector as an
+// antisymmetric pair tensor in each spin), the alpha-beta class is
+//   T'[x][p][y][r] = S[x][p][y][r] - S[p][x][y][r] - S[x][p][r][y] + S[p][x][r][y],
+//   S[x][p][y][r]  = sum_{q,s} (pq|rs) T[x][q][y][s],
+// i.e. for fixed spectators (x, y) a product with the screened matrix
+// W[(p,r),(q,s)] = (pq|rs) (the alpha-beta ladder of Eqs. h200ca..h200ab
+// when all four indices are virtual).  Orbitals are grouped in blocks of
+// four (o/v pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
+// block X, p in P, y in Y, r in R and computes the four role products
+// (which of x/p and y/r is the spectator) on four waves, one
+// 16 x 16 x 4 MFMA per (column chunk, vector): rows = the 16 active pairs,
+// columns = the 16 spectator pairs, K = 4 columns (q, s) of a chunk.  The
+// roles are combined through LDS and sigma is written once (no atomics).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, const double *__restrict__ c,
+                                                       int64_t ldc, double *__restrict__ sg, int64_t lds)
+{
+    __shared__ double tile[4][NV][16][17];
+    const uchar4 qd = A.quads[blockIdx.x];
+    const int X = qd.x, P = qd.y, Y = qd.z, R = qd.w;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool sameA = X == P, sameB = Y == R;
+    const int norb = A.norb, L = A.L, nb = A.nblk;
+    int Ab, Bb, Cb, Db;
+    bool active;
+    if (wave == 0) { Ab = P; Bb = R; Cb = X; Db = Y; active = true; }
+    else if (wave == 1) { Ab = X; Bb = R; Cb = P; Db = Y; active = !sameA; }
+    else if (wave == 2) { Ab = P; Bb = Y; Cb = X; Db = R; active = !sameB; }
+    else { Ab = X; Bb = Y; Cb = P; Db = R; active = !sameA && !sameB; }
+    v4d acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const int n = lane & 15, k = lane >> 4;
+        const int x = A.blk_orb[Cb * 4 + (n >> 2)], y = A.blk_orb[Db * 4 + (n & 3)];
+        const int espec = (Cb != 0) + (Db != 0);
+        const int row = Ab * nb + Bb;
+        const int e0 = A.chunk_off[row], e1 = A.chunk_off[row + 1];
+        for (int e = e0; e < e1; ++e) {
+            const int2 d = A.chunk_desc[e];
+            const int q = d.x, S = d.y;
+            if (espec + (q >= 2) + (S != 0) > L) continue;     // source level above the cut
+            const double a = A.chunk_val[(size_t)e * 64 + lane];
+            const int s = A.blk_orb[S * 4 + k];
+            bool ok = x >= 0 && y >= 0 && s >= 0 && x != q && y != s;
+            int64_t addr = 0;
+            double f = 0.0;
+            if (ok) {
+                const int ja = A.apidx[x * norb + q], jb = A.bpidx[y * norb + s];
+                ok = ja >= 0 && jb >= 0 && jb < A.sb.le[L - A.alev[ja]];
+                if (ok) {
+                    addr = A.rowstart[ja] + jb;
+                    f = ((q > x) == (s > y)) ? 1.0 : -1.0;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double b = (ok && v < nv) ? f * c[v * ldc + addr] : 0.0;
+                acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[v], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) tile[wave][v][4 * (lane >> 4) + g][lane & 15] = acc[v][g];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int ix = (t >> 6) & 3, ip = (t >> 4) & 3, iy = (t >> 2) & 3, ir = t & 3;
+    const int x = A.blk_orb[X * 4 + ix], p = A.blk_orb[P * 4 + ip];
+    const int y = A.blk_orb[Y * 4 + iy], r = A.blk_orb[R * 4 + ir];
+    if (x < 0 || p < 0 || y < 0 || r < 0 || x >= p || y >= r) return;
+    const int ja = A.apidx[x * norb + p], jb = A.bpidx[y * norb + r];
+    if (ja < 0 || jb < 0 || jb >= A.sb.le[L - A.alev[ja]]) return;
+    const int t1 = sameA ? 0 : 1, t2 = sameB ? 0 : 2;
+    const int t3 = (sameA && sameB) ? 0 : sameA ? 2 : sameB ? 1 : 3;
+    double *dst = sg + A.rowstart[ja] + jb;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v >= nv) break;
+        const double val = tile[0][v][ip * 4 + ir][ix * 4 + iy] - tile[t1][v][ix * 4 + ir][ip * 4 + iy]
+                         - tile[t2][v][ip * 4 + iy][ix * 4 + ir] + tile[t3][v][ix * 4 + iy][ip * 4 + ir];
+        dst[v * lds] = val;
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_sigma_n2(SigmaArgs A, int nv, const double *__restrict__ c,
+                                                  int64_t ldc, double *__restrict__ sg, int64_t lds)
+{
+    sigma_target_n2<NV>(A, blockIdx.x, blockIdx.y * blockDim.x + threadIdx.x, nv, c, ldc, sg, lds);
+}
+
 template <int NV>
 __global__ __launch_bounds__(256) void k_sigma_generic(SigmaArgs A, int nv, const double *__restrict__ c,
                                                        int64_t ldc, double *__restrict__ sg, int64_t lds)
@@ -203,7 +443,11 @@ __global__ __launch_bounds__(256) void k_sigma_batched(const SigmaArgs *__restri
         while (job + 1 < njobs && vecs[job + 1].item0 <= g) ++job;
         const BatchVec &bv = vecs[job];
         const int2 w = bv.plan[g - bv.item0];
-        sigma_target<NV>(args[bv.inst], w.x, w.y + threadIdx.x, bv.nv, bv.c, bv.ldc, bv.s, bv.lds);
+        const SigmaArgs &A = args[bv.inst];
+        if (A.variant >= 2)
+            sigma_target_n2<NV>(A, w.x, w.y + threadIdx.x, bv.nv, bv.c, bv.ldc, bv.s, bv.lds);
+        else
+            sigma_target<NV>(A, w.x, w.y + threadIdx.x, bv.nv, bv.c, bv.ldc, bv.s, bv.lds);
     }
 }
 
@@ -241,7 +485,40 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
         const int nv = nvec - v0 < 8 ? nvec - v0 : 8;
         const double *cc = cv + (int64_t)v0 * ldc;
         double *ss = sv + (int64_t)v0 * lds;
-        if (nv == 1)
+        if (A.variant == 3) {
+            // alpha-beta on matrix cores (writes sigma), then one-body and
+            // same-spin with the pair kernel (adds)
+            for (int u0 = 0; u0 < nv; u0 += 4) {
+                const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                if (c->nquad > 0)
+                    k_sigma_ab_mfma<4><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                 ss + (int64_t)u0 * lds, lds);
+            }
+            SigmaArgs B = A;
+            B.classes = 3;
+            B.accumulate = 1;
+            if (nv == 1)
+                k_sigma_n2<1><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
+            else if (nv == 2)
+                k_sigma_n2<2><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
+            else if (nv <= 4)
+                k_sigma_n2<4><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
+            else
+                k_sigma_n2<8><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
+            ISCI_HIP(hipGetLastError());
+            continue;
+        }
+        const bool n2 = A.variant == 2;
+        if (n2) {
+            if (nv == 1)
+                k_sigma_n2<1><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
+            else if (nv == 2)
+                k_sigma_n2<2><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
+            else if (nv <= 4)
+                k_sigma_n2<4><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
+            else
+                k_sigma_n2<8><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
+        } else if (nv == 1)
             k_sigma_generic<1><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
         else if (nv == 2)
             k_sigma_generic<2><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);

@@ -13,7 +13,7 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def create(h, eri, norb, na, nb, L, tau):
+def create(h, eri, norb, na, nb, L, tau, variant=0):
     import paper_1609_07757_amd as isci
     torch, dev = torch_dev()
     ht = torch.from_numpy(np.ascontiguousarray(h)).to(dev)
@@ -21,6 +21,8 @@ def create(h, eri, norb, na, nb, L, tau):
     hd = isci.isci_create(ht, et, norb, na, nb, L, tau)
     torch.cuda.synchronize()
     del ht, et
+    if variant:
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
     return hd
 
 

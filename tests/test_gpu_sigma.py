@@ -45,11 +45,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
-def test_sigma_parity(case):
+def test_sigma_parity(case, variant):
+    """variant 1: general string kernel; 2: pair tables; 3: pair tables +
+    MFMA alpha-beta tiles (2 and 3 need two electrons per spin)."""
     recipe, norb, na, nb, L, tau, nvec = case
+    if variant > 1 and not (na == 2 and nb == 2):
+        pytest.skip("pair kernels need two electrons per spin")
     h, eri = _ints(recipe, norb, 3)
-    hd = create(h, eri, norb, na, nb, L, tau)
+    hd = create(h, eri, norb, na, nb, L, tau, variant)
     S = O.Space(norb, na, nb, L)
     assert hd.dim == S.dim
     c = random_vectors(S.dim, nvec, seed=11)
@@ -148,15 +153,16 @@ def test_hermiticity_large():
     assert abs(a - b) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * max(1.0, np.abs(s).max())
 
 
+@pytest.mark.parametrize("variant", [3, 2, 1])
 @pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 1), ("cisdt_n30", 600, 2),
                                            ("cisdt_n60", 300, 8), ("fci_n48", 200, 8)])
-def test_sigma_workloads(wl, nsamp, nvec):
+def test_sigma_workloads(wl, nsamp, nvec, variant):
     """Named workloads (recipe A): full comparison for the small one, sampled
-    targets (row ends included) at full size for the others."""
+    targets (row ends included) at full size for the others; both kernels."""
     from isci_inputs import workload
     W = workload(wl)
     h, eri = W.integrals()
-    hd = create(h, eri, W.norb, W.nalpha, W.nbeta, W.level, W.tau)
+    hd = create(h, eri, W.norb, W.nalpha, W.nbeta, W.level, W.tau, variant)
     S = O.Space(W.norb, W.nalpha, W.nbeta, W.level)
     assert hd.dim == S.dim
     c = random_vectors(S.dim, nvec, seed=21)
@@ -183,3 +189,11 @@ def test_sigma_tau_sweep_cisdt_n30(k, tau):
     tg = sample_targets(S.rowstart(), S.dim, 400, seed=100 + k)
     ref = O.sigma(S, h, eri, tau, c, targets=tg)
     assert np.abs(got[:, tg] - ref).max() <= TOL * np.abs(got).max()
+
+
+def test_pair_kernel_rejected_for_other_electron_counts():
+    import paper_1609_07757_amd as isci
+    h, eri = recipe_b(7, seed=1)
+    hd = create(h, eri, 7, 3, 2, 2, 0.0)
+    with pytest.raises(isci.IsciError):
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, isci.SIGMA_PAIR)
