@@ -65,12 +65,6 @@ def main():
     variant = {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
                "mfma": isci.SIGMA_MFMA}[a.kernel]
     isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
-    if variant == isci.SIGMA_GENERAL or W.nalpha != 2 or W.nbeta != 2:
-        kname = "k_sigma_generic"
-    elif variant == isci.SIGMA_MFMA:
-        kname = "k_sigma_ab_mfma+k_sigma_n2"
-    else:
-        kname = "k_sigma_n2"
     st = isci.isci_get_stats(hd)
     dim = hd.dim
     c = torch.from_numpy(random_vectors(dim, nvec, seed=21)).to(dev)
@@ -90,12 +84,40 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     ms_per_step = ev_ms / a.steps
-    nlaunch = (nvec + 7) // 8           # sigma kernel launches per step (8 vectors per launch)
     terms = int(st["terms_total"])
+    tb = st["terms"]
+    terms_ab = int(tb[26:42].sum())
+    terms_rest = terms - terms_ab
     flops_step = 2.0 * terms * nvec
     sig_per_s = nvec * a.steps / (ev_ms * 1e-3)
     terms_per_s = terms * nvec * a.steps / (ev_ms * 1e-3)
-    achieved = flops_step / (ms_per_step * 1e-3) / 1e12   # TFLOP/s of the sigma kernel launch(es)
+    # per-kernel durations: HIP events recorded by the library around each
+    # launch on this stream, over a second timed pass of the same steps
+    isci.isci_profile(hd, True)
+    for _ in range(a.steps):
+        isci.isci_sigma(hd, c, sg, stream=stream)
+    torch.cuda.synchronize()
+    prof = isci.isci_profile_read(hd)
+    isci.isci_profile(hd, False)
+    # algorithmic flops each kernel performs per step (2 per sigma term per vector)
+    terms_1b = int(tb[0:8].sum())
+    kflops = {"k_sigma_generic": 2.0 * terms * nvec, "k_sigma_n2": 2.0 * terms * nvec,
+              "k_sigma_ab_mfma": 2.0 * terms_ab * nvec,
+              "k_sigma_n2(same-spin)": 2.0 * (terms_rest - terms_1b) * nvec,
+              "k_onebody_a+b": 2.0 * terms_1b * nvec}
+    kernels = {}
+    for name, (tot_ms, nl) in prof.items():
+        per_launch_ms = tot_ms / nl
+        launches_per_step = nl / a.steps
+        fl = kflops[name] / launches_per_step
+        kernels[name] = {"avg_launch_ms": per_launch_ms, "launches_per_step": launches_per_step,
+                         "share_of_step": tot_ms / a.steps / ms_per_step,
+                         "algorithmic_flops_per_launch": fl,
+                         "tflops": fl / (per_launch_ms * 1e-3) / 1e12}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
+    kname = dom
+    achieved = kernels[dom]["tflops"]
+    nlaunch = kernels[dom]["launches_per_step"]
     traffic = None
     if os.path.exists(a.traffic_json):
         try:
@@ -125,10 +147,15 @@ def main():
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
         "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic, "launches_per_step": nlaunch,
-                     "algorithmic_flops_per_step": flops_step},
+        "roofline": {"bound": "mfma" if kname == "k_sigma_ab_mfma" else "alu", "kernel": kname,
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "launches_per_step": nlaunch,
+                     "avg_launch_ms": kernels[kname]["avg_launch_ms"],
+                     "algorithmic_flops_per_launch": kernels[kname]["algorithmic_flops_per_launch"]},
+        "step_tflops": flops_step / (ms_per_step * 1e-3) / 1e12,
+        "step_frac_fp64": flops_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "kernels": kernels,
     }
     if not a.skip_davidson:
         out["davidson"] = davidson_latency(isci, torch, dev)

@@ -233,6 +233,19 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_SIGMA_MFMA 3   /* pair kernel for one-body / same-spin + FP64 MFMA tiles for alpha-beta */
 isci_status isci_set_option(isci_handle hd, int option, int value);
 
+/* Kernel timing hook (for measurement).  When enabled, HIP events are
+ * recorded on the launch stream around every sigma kernel launch of the
+ * handle; isci_profile_read synchronises those events and returns the
+ * summed milliseconds and launch count of one kernel since the last read,
+ * then clears them.  Kernel ids: */
+#define ISCI_KERNEL_GENERAL 0   /* k_sigma_generic: all classes, any electron count */
+#define ISCI_KERNEL_PAIR 1      /* k_sigma_n2: all classes, two electrons per spin */
+#define ISCI_KERNEL_AB_MFMA 2   /* k_sigma_ab_mfma: alpha-beta class on matrix cores */
+#define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
+#define ISCI_KERNEL_ONEBODY 4   /* k_onebody_a + k_onebody_b: one-body classes, two electrons per spin */
+isci_status isci_profile(isci_handle hd, int enable);
+isci_status isci_profile_read(isci_handle hd, int kernel, double *total_ms, int64_t *launches);
+
 void isci_destroy(isci_handle hd);
 const char *isci_status_string(isci_status s);
 const char *isci_last_error(void);

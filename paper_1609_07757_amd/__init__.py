@@ -312,3 +312,24 @@ def isci_engine_destroy(e: Engine):
 def isci_davidson_footprint(hd: Handle, nroots: int = 1, **opts) -> int:
     o = _opts(**opts)
     return int(_lib.load().isci_davidson_footprint(hd.ptr, int(nroots), ctypes.byref(o)))
+
+
+KERNEL_NAMES = {0: "k_sigma_generic", 1: "k_sigma_n2", 2: "k_sigma_ab_mfma", 3: "k_sigma_n2(same-spin)",
+                4: "k_onebody_a+b"}
+
+
+def isci_profile(hd: Handle, enable: bool = True):
+    check(_lib.load().isci_profile(hd.ptr, 1 if enable else 0), "isci_profile")
+
+
+def isci_profile_read(hd: Handle) -> dict:
+    """{kernel name: (total ms, launches)} of the launches recorded since the last read."""
+    out = {}
+    L = _lib.load()
+    for k, name in KERNEL_NAMES.items():
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(L.isci_profile_read(hd.ptr, k, ctypes.byref(ms), ctypes.byref(n)), "isci_profile_read")
+        if n.value:
+            out[name] = (ms.value, n.value)
+    return out

@@ -30,7 +30,7 @@ ABI_SYMBOLS = (
     "isci_destroy", "isci_status_string", "isci_last_error",
     "isci_engine_create", "isci_engine_config", "isci_engine_add", "isci_engine_step",
     "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
-    "isci_davidson_footprint", "isci_set_option",
+    "isci_davidson_footprint", "isci_set_option", "isci_profile", "isci_profile_read",
 )
 
 
@@ -118,6 +118,10 @@ def load(path: str = LIBPATH):
     L.isci_davidson_footprint.restype = i64
     L.isci_set_option.argtypes = [vp, i32, i32]
     L.isci_set_option.restype = i32
+    L.isci_profile.argtypes = [vp, i32]
+    L.isci_profile.restype = i32
+    L.isci_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.isci_profile_read.restype = i32
     _LIB = L
     return L
 

@@ -12,6 +12,7 @@
 #define ISCI_MAXN 4          // electrons per spin handled by the kernels
 #define ISCI_MAXNORB 255     // orbitals fit in one byte
 #define ISCI_MAXLEV 8        // level tables sized for 2 * ISCI_MAXN
+#define ISCI_NKERNEL_IDS 5   // ISCI_KERNEL_* ids of the timing hook
 
 namespace isci {
 
@@ -70,6 +71,7 @@ struct DevTabs {
     int2 *chunk_desc = nullptr;     // (q, S)
     double *chunk_val = nullptr;    // [nchunk][64]
     uchar4 *quads = nullptr;        // target tiles (X, P, Y, R) with X<=P, Y<=R, level <= L
+    double *hscreen = nullptr;      // [norb][norb] h with screened units set to 0 (one-body kernels)
 };
 
 struct SigmaArgs {
@@ -126,7 +128,12 @@ struct isci_ctx {
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int nblk = 0, nchunk = 0, nquad = 0;
+    int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
+    // optional per-kernel timing: HIP events recorded around each launch on
+    // the launch stream, summed when read
+    bool profile = false;
+    std::vector<hipEvent_t> prof_ev[ISCI_NKERNEL_IDS];   // start/stop pairs
     // scratch for the eigensolver (grown on demand)
     std::vector<void *> work;
 };
@@ -136,6 +143,11 @@ namespace isci {
 // error plumbing
 void set_error(const std::string &msg);
 isci_status hip_fail(hipError_t e, const char *what);
+#define ISCI_CHECK(call)                                            \
+    do {                                                            \
+        isci_status _st = (call);                                   \
+        if (_st != ISCI_OK) return _st;                             \
+    } while (0)
 #define ISCI_HIP(call)                                              \
     do {                                                            \
         hipError_t _e = (call);                                     \
@@ -147,6 +159,8 @@ SigmaArgs sigma_args(const isci_ctx *c);
 
 isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t ldc,
                          double *sv, int64_t lds, hipStream_t s);
+// records a start (begin=true) or stop event for kernel id `k` when profiling
+isci_status prof_mark(const isci_ctx *c, int k, bool begin, hipStream_t s);
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);

@@ -359,6 +359,15 @@ __global__ void k_pq_fill(const long long *ab_off, int n, const int *off, uint8_
     }
 }
 
+// h with every screened unit zeroed (dense, for the one-body row kernels)
+__global__ void k_hscreen(const double *h, int n, double tau, double *hs)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const double v = gh(h, n, t / n, t % n);
+    hs[t] = fabs(v) > tau ? v : 0.0;
+}
+
 // diagonal units: h_pp, (pp|qq), and (pp|qq) - (pq|qp) formed with the
 // smaller index first
 __global__ void k_diag_units(const double *h, const double *eri, int n, double *hd, double *jj, double *ssd)
@@ -517,6 +526,16 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     return ISCI_OK;
 }
 
+static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
+{
+    const int n = c->norb;
+    c->d.hscreen = (double *)dev_alloc(c, sizeof(double) * n * n);
+    if (!c->d.hscreen) { set_error("device allocation failed (h)"); return ISCI_E_OOM; }
+    k_hscreen<<<(n * n + 255) / 256, 256, 0, s>>>(h, n, c->tau, c->d.hscreen);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
 static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, hipStream_t s)
 {
     const int n = c->norb;
@@ -593,12 +612,35 @@ static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, 
     }
     // distinct kept integral units: one-body counted once, same-spin once, alpha-beta once
     c->stats.kept_total = (int64_t)tot[0] + tot[1] + tot_ab;
+    c->nkept_h = tot[0];
+    c->nkept_ab = tot_ab;
     return ISCI_OK;
+}
+
+isci_status prof_mark(const isci_ctx *cc, int k, bool begin, hipStream_t s)
+{
+    if (!cc->profile) return ISCI_OK;
+    isci_ctx *c = const_cast<isci_ctx *>(cc);
+    hipEvent_t ev;
+    ISCI_HIP(hipEventCreate(&ev));
+    ISCI_HIP(hipEventRecord(ev, s));
+    (void)begin;
+    c->prof_ev[k].push_back(ev);
+    return ISCI_OK;
+}
+
+static void prof_clear(isci_ctx *c)
+{
+    for (int k = 0; k < ISCI_NKERNEL_IDS; ++k) {
+        for (hipEvent_t e : c->prof_ev[k]) (void)hipEventDestroy(e);
+        c->prof_ev[k].clear();
+    }
 }
 
 static void destroy(isci_ctx *c)
 {
     if (!c) return;
+    prof_clear(c);
     for (void *p : c->allocs) (void)hipFree(p);
     for (void *p : c->work) (void)hipFree(p);
     delete c;
@@ -731,6 +773,8 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
         st = build_tiles(c, eri, stream);
+        if (st == ISCI_OK) st = build_hscreen(c, h, stream);
+        if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     }
     *out = c;
@@ -788,6 +832,37 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         set_error("unknown option");
         return ISCI_E_INVALID;
     }
+}
+
+isci_status isci_profile(isci_handle c, int enable)
+{
+    if (!c) { set_error("NULL handle"); return ISCI_E_INVALID; }
+    c->profile = enable != 0;
+    if (!c->profile) prof_clear(c);
+    return ISCI_OK;
+}
+
+isci_status isci_profile_read(isci_handle c, int kernel, double *total_ms, int64_t *launches)
+{
+    if (!c || kernel < 0 || kernel >= ISCI_NKERNEL_IDS || !total_ms || !launches) {
+        set_error("bad profile query");
+        return ISCI_E_INVALID;
+    }
+    std::vector<hipEvent_t> &ev = c->prof_ev[kernel];
+    double tot = 0.0;
+    int64_t n = 0;
+    for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+        ISCI_HIP(hipEventSynchronize(ev[i + 1]));
+        float ms = 0.0f;
+        ISCI_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        tot += ms;
+        ++n;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    *total_ms = tot;
+    *launches = n;
+    return ISCI_OK;
 }
 
 void isci_destroy(isci_handle c) { destroy(c); }

@@ -416,6 +416,145 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// One-body classes for two electrons per spin (add into sigma).
+//
+// Alpha: for a spectator x the target rows {x, a} receive
+//   sum_q h_aq sgn(a - x) sgn(q - x) c({x, q}, J)
+// for every beta index J both rows hold.  A workgroup takes one x, a block
+// of 8 target orbitals a and 256 consecutive J; each thread keeps 8 x NV
+// accumulators, so every source element loaded feeds 8 targets.  The
+// spectator role is split over two launches (x < a, then x > a) so that
+// each sigma row is updated by one workgroup per launch.
+template <int NV>
+__global__ __launch_bounds__(256) void k_onebody_a(SigmaArgs A, int nv, const double *__restrict__ c,
+                                                   int64_t ldc, double *__restrict__ sg, int64_t lds,
+                                                   const double *__restrict__ hs, int upper)
+{
+    const int norb = A.norb, L = A.L;
+    const int x = blockIdx.x;
+    const int a0 = blockIdx.y * 8;
+    const int J = blockIdx.z * 256 + threadIdx.x;
+    const int *apx = A.apidx;
+    // target rows
+    int ta[8];
+    int tlen[8];
+    int64_t trow[8];
+    int maxlen = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int a = a0 + i;
+        ta[i] = -1;
+        tlen[i] = 0;
+        trow[i] = 0;
+        if (a < norb && a != x && ((a > x) == (upper != 0))) {
+            const int ja = apx[x * norb + a];
+            if (ja >= 0) {
+                ta[i] = a;
+                tlen[i] = A.sb.le[L - A.alev[ja]];
+                trow[i] = A.rowstart[ja];
+                maxlen = max(maxlen, tlen[i]);
+            }
+        }
+    }
+    if ((int)(blockIdx.z * 256) >= maxlen) return;
+    double acc[8][NV];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
+    for (int q = 0; q < norb; ++q) {
+        if (q == x) continue;
+        const int jq = apx[x * norb + q];
+        if (jq < 0) continue;
+        const int slen = A.sb.le[L - A.alev[jq]];
+        if ((int)(blockIdx.z * 256) >= slen) continue;
+        double hq[8];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            hq[i] = ta[i] >= 0 ? hs[ta[i] * norb + q] : 0.0;
+            any |= hq[i] != 0.0;
+        }
+        if (!any || J >= slen) continue;
+        const double sq = (q > x) ? 1.0 : -1.0;
+        const double *src = c + A.rowstart[jq] + J;
+        double cv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cv[v] = (v < nv) ? sq * src[v * ldc] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[i][v] += hq[i] * cv[v];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (ta[i] < 0 || J >= tlen[i]) continue;
+        const double sa = (ta[i] > x) ? 1.0 : -1.0;
+        double *dst = sg + trow[i] + J;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) dst[v * lds] += sa * acc[i][v];
+    }
+}
+
+// Beta: within the alpha row I,
+//   sigma(I, {y<b}) += sum_s h_bs sgn(s - y) c(I, {y, s}) - sum_s h_ys sgn(s - b) c(I, {b, s}).
+// A workgroup stages row I (NV vectors) in LDS; one thread per target.
+// Rows that do not fit in LDS (STAGE = false) are read from global memory.
+template <int NV, bool STAGE>
+__global__ __launch_bounds__(256) void k_onebody_b(SigmaArgs A, int nv, const double *__restrict__ c,
+                                                   int64_t ldc, double *__restrict__ sg, int64_t lds,
+                                                   const double *__restrict__ hs)
+{
+    extern __shared__ double lrow[];   // [len][NV]
+    const int norb = A.norb, L = A.L;
+    const int ia = blockIdx.x;
+    const int len = A.sb.le[L - A.alev[ia]];
+    const int64_t base = A.rowstart[ia];
+    if (STAGE) {
+        for (int t = threadIdx.x; t < len; t += blockDim.x)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) lrow[t * NV + v] = (v < nv) ? c[v * ldc + base + t] : 0.0;
+        __syncthreads();
+    }
+    auto row = [&](int j, int v) -> double {
+        return STAGE ? lrow[j * NV + v] : (v < nv ? c[v * ldc + base + j] : 0.0);
+    };
+    const int *bpx = A.bpidx;
+    for (int ib = threadIdx.x; ib < len; ib += blockDim.x) {
+        const uint32_t bs = A.bstr[ib];
+        const int y = bs & 0xff, b = (bs >> 8) & 0xff;
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        for (int s = 0; s < norb; ++s) {
+            const double hb = hs[b * norb + s], hy = hs[y * norb + s];
+            if (hb != 0.0 && s != y) {
+                const int j = bpx[y * norb + s];
+                if (j >= 0 && j < len) {
+                    const double f = (s > y) ? hb : -hb;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += f * row(j, v);
+                }
+            }
+            if (hy != 0.0 && s != b) {
+                const int j = bpx[b * norb + s];
+                if (j >= 0 && j < len) {
+                    const double f = (s > b) ? -hy : hy;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += f * row(j, v);
+                }
+            }
+        }
+        double *dst = sg + base + ib;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) dst[v * lds] += acc[v];
+    }
+}
+
 template <int NV>
 __global__ __launch_bounds__(256) void k_sigma_n2(SigmaArgs A, int nv, const double *__restrict__ c,
                                                   int64_t ldc, double *__restrict__ sg, int64_t lds)
@@ -490,12 +629,38 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             // same-spin with the pair kernel (adds)
             for (int u0 = 0; u0 < nv; u0 += 4) {
                 const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                if (c->nquad > 0)
+                if (c->nquad > 0) {
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
                     k_sigma_ab_mfma<4><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
                                                                  ss + (int64_t)u0 * lds, lds);
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
+                }
             }
+            if (c->d.hscreen) {
+                // one-body alpha (two launches: spectator below / above the
+                // active orbital), one-body beta, then same-spin if any
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
+                const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
+                for (int u0 = 0; u0 < nv; u0 += 4) {
+                    const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                    for (int up = 1; up >= 0; --up)
+                        k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                           ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
+                    const size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
+                    if (shm <= 65536)
+                        k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
+                            A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                    else
+                        k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
+                            A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                }
+                ISCI_HIP(hipGetLastError());
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
+                if (c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
+            }
+            ISCI_CHECK(prof_mark(c, ISCI_KERNEL_PAIR_REST, true, s));
             SigmaArgs B = A;
-            B.classes = 3;
+            B.classes = c->d.hscreen ? 2 : 3;
             B.accumulate = 1;
             if (nv == 1)
                 k_sigma_n2<1><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
@@ -506,9 +671,12 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             else
                 k_sigma_n2<8><<<grid, 256, 0, s>>>(B, nv, cc, ldc, ss, lds);
             ISCI_HIP(hipGetLastError());
+            ISCI_CHECK(prof_mark(c, ISCI_KERNEL_PAIR_REST, false, s));
             continue;
         }
         const bool n2 = A.variant == 2;
+        const int kid = n2 ? ISCI_KERNEL_PAIR : ISCI_KERNEL_GENERAL;
+        ISCI_CHECK(prof_mark(c, kid, true, s));
         if (n2) {
             if (nv == 1)
                 k_sigma_n2<1><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
@@ -527,6 +695,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
         else
             k_sigma_generic<8><<<grid, 256, 0, s>>>(A, nv, cc, ldc, ss, lds);
         ISCI_HIP(hipGetLastError());
+        ISCI_CHECK(prof_mark(c, kid, false, s));
     }
     return ISCI_OK;
 }
