@@ -38,6 +38,13 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
+    ap.add_argument("--mode", choices=["sigma", "batched", "served"], default="sigma",
+                    help="sigma: headline line; batched: 64 uneven Davidson solves, engine vs plain loop; "
+                         "served: Poisson request stream with continuous batching")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=120, help="served mode: requests (of the 2000-request stream)")
+    ap.add_argument("--max-wall", type=float, default=240.0, help="served mode: wall-clock cap (s)")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sigma_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (optional)")
     return ap.parse_args()
@@ -49,6 +56,10 @@ def main():
         print("bench.py measures one GPU only: this build runs the sigma step on a single MI355X "
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if a.mode == "batched":
+        return bench_batched(a)
+    if a.mode == "served":
+        return bench_served(a)
     import numpy as np
     import torch
 
@@ -210,6 +221,107 @@ def cpu_baseline(W, h, eri, tau, nvec, dim, seconds):
     return {"value": value, "unit": "σ-vectors/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{len(tg)} of {dim} target determinants (random, seed 0), nvec={nvec}, "
                       f"{t:.1f} s; scaled by dim/sample"}
+
+
+def _kernel_variant(isci, name):
+    return {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
+            "mfma": isci.SIGMA_MFMA}[name]
+
+
+def bench_batched(a):
+    """64 uneven CI instances (norb 20-80, CISD/CISDT, 1-4 roots, tau 1e-12):
+    every solve run one at a time (one instance per launch) vs all solves in
+    one engine (one fused sigma launch per Davidson iteration).  Reports
+    sigma-vectors/s of both, their ratio and the largest energy difference."""
+    import numpy as np
+    import torch
+    import paper_1609_07757_amd as isci
+    from isci_inputs.device import integrals_on_device
+    from isci_inputs.workloads import batched_instances
+    insts = batched_instances(a.instances)
+    handles = []
+    t0 = time.perf_counter()
+    for W in insts:
+        h, eri = integrals_on_device(W.norb, W.box_len, W.n_aux, W.seed)
+        hd = isci.isci_create(h, eri, W.norb, 2, 2, W.level, W.tau)
+        del h, eri
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, _kernel_variant(isci, a.kernel))
+        handles.append(hd)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    # plain: one solve after the other
+    t0 = time.perf_counter()
+    plain_e, plain_sig = [], 0
+    for W, hd in zip(insts, handles):
+        e, _, info = isci.isci_davidson(hd, nroots=W.nroots)
+        plain_e.append(e)
+        plain_sig += info["sigma_calls"]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # batched: one engine, all slots
+    eng = isci.isci_engine_create()
+    t0 = time.perf_counter()
+    slots = [isci.isci_engine_add(eng, hd, nroots=W.nroots) for W, hd in zip(insts, handles)]
+    steps = 0
+    while isci.isci_engine_step(eng) > 0:
+        steps += 1
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batch_e, batch_sig, iters = [], 0, []
+    for sl in slots:
+        done, e, _, info = isci.isci_engine_result(eng, sl)
+        batch_e.append(e)
+        batch_sig += info["sigma_calls"]
+        iters.append(info["iterations"])
+    dE = max(float(np.abs(x - y).max()) for x, y in zip(plain_e, batch_e))
+    out = {"metric": "batched σ-vectors/s (64 uneven Davidson solves, one engine) vs plain loop",
+           "value": batch_sig / t_batch, "unit": "σ-vectors/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic (recipe A, per-instance seeds)",
+           "config": {"workload": "batched64", "instances": len(insts), "tau": 1e-12,
+                      "norb_range": [min(w.norb for w in insts), max(w.norb for w in insts)],
+                      "kernel": a.kernel},
+           "plain_sigma_vectors_per_s": plain_sig / t_plain, "speedup_vs_plain": (batch_sig / t_batch) / (plain_sig / t_plain),
+           "plain_s": t_plain, "batched_s": t_batch, "engine_steps": steps, "create_s": t_create,
+           "max_abs_energy_diff": dE, "sigma_vectors_plain": plain_sig, "sigma_vectors_batched": batch_sig,
+           "max_iterations": max(iters)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(a):
+    """Poisson stream (50 req/s) of Davidson solves, norb log-uniform in
+    [40, 200], CISD/CISDT (CISDTQ when its dimension is below 5M), 1-3
+    roots, tau 1e-12; admission by HBM footprint into a continuously
+    batched engine.  Runs the first `requests` of the 2000-request stream
+    (or until max_wall) and reports p50/p99 arrival-to-energy latency."""
+    import numpy as np
+    import torch
+    from paper_1609_07757_amd.serve import GpuExecutor, Request, Server
+    from isci_inputs.device import integrals_on_device
+    from isci_inputs.workloads import served_requests
+    stream = served_requests(2000)[: a.requests]
+    reqs = []
+    for i, (t, W) in enumerate(stream):
+        def payload(W=W):
+            return integrals_on_device(W.norb, W.box_len, W.n_aux, W.seed)
+        reqs.append(Request(i, t, W.norb, 2, 2, W.level, W.tau, W.nroots, payload=payload))
+    ex = GpuExecutor()
+    srv = Server(ex, hbm_budget=int(a.hbm_budget_gb * 2**30), max_slots=64)
+    t0 = time.perf_counter()
+    srv.run(reqs, max_wall=a.max_wall)
+    wall = time.perf_counter() - t0
+    rep = srv.report()
+    done = [r for r in srv.done if r.status == "done"]
+    out = {"metric": "served Davidson solves: p50/p99 latency and σ throughput",
+           "value": rep.get("p50_s"), "unit": "s (p50 latency)", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic (recipe A, per-request seeds, Poisson arrivals)",
+           "config": {"workload": "served_poisson50", "requests_offered": len(reqs), "rate_per_s": 50,
+                      "tau": 1e-12, "hbm_budget_gb": a.hbm_budget_gb},
+           "p50_s": rep.get("p50_s"), "p99_s": rep.get("p99_s"), "served": rep["served"],
+           "rejected": rep["rejected"], "wall_s": wall, "sigma_vectors_per_s": ex.sigma_vectors / wall,
+           "peak_concurrent": rep["peak_running"], "peak_bytes": rep["peak_bytes"],
+           "norb_served": sorted(r.norb for r in done)[-3:]}
+    ex.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -223,6 +223,149 @@ __global__ void k_normalize(double *__restrict__ x, int64_t n, const double *__r
         x[t] *= f;
 }
 
+
+// ---------------------------------------------------------------- batched block algebra
+// One launch serves every slot of an engine: each kernel reads a device
+// array of per-slot descriptors and blockIdx.z selects the descriptor.
+
+struct BDot {              // out[i*k + j] = sum_t A[i*lda + t] B[j*ldb + t]
+    const double *A, *B;
+    double *out, *partial;
+    int64_t lda, ldb, n;
+    int m, k, nblk;
+};
+
+__global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, int tiles_j)
+{
+    const BDot J = jobs[blockIdx.z];
+    const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
+    const int i0 = ti * kTile, j0 = tj * kTile;
+    if ((int)blockIdx.x >= J.nblk || i0 >= J.m || j0 >= J.k) return;
+    double acc[kTile][kTile];
+#pragma unroll
+    for (int a = 0; a < kTile; ++a)
+#pragma unroll
+        for (int b = 0; b < kTile; ++b) acc[a][b] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)J.nblk * blockDim.x) {
+        double bv[kTile];
+#pragma unroll
+        for (int b = 0; b < kTile; ++b) bv[b] = (j0 + b < J.k) ? J.B[(int64_t)(j0 + b) * J.ldb + t] : 0.0;
+#pragma unroll
+        for (int a = 0; a < kTile; ++a) {
+            if (i0 + a >= J.m) break;
+            const double av = J.A[(int64_t)(i0 + a) * J.lda + t];
+#pragma unroll
+            for (int b = 0; b < kTile; ++b) acc[a][b] += av * bv[b];
+        }
+    }
+    __shared__ double red[4][kTile * kTile];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < kTile; ++a)
+#pragma unroll
+        for (int b = 0; b < kTile; ++b) {
+            double v = acc[a][b];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[wave][a * kTile + b] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < kTile * kTile) {
+        const int a = threadIdx.x / kTile, b = threadIdx.x % kTile;
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        if (i0 + a < J.m && j0 + b < J.k) J.partial[((int64_t)blockIdx.x * J.m + i0 + a) * J.k + j0 + b] = v;
+    }
+}
+
+__global__ void k_bdots_reduce(const BDot *__restrict__ jobs)
+{
+    const BDot J = jobs[blockIdx.z];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mk = J.m * J.k;
+    if (e >= mk) return;
+    double s = 0.0;
+    for (int b = 0; b < J.nblk; ++b) s += J.partial[(int64_t)b * mk + e];
+    J.out[e] = s;
+}
+
+struct BLin {              // out_j[t] = beta out_j[t] + sign * sum_i V_i[t] Y[j*m + i]
+    const double *V, *Y;
+    double *out;
+    int64_t ldv, ldo, n;
+    int m, k;
+    double beta, sign;
+};
+
+__global__ __launch_bounds__(256) void k_blincomb(const BLin *__restrict__ jobs)
+{
+    const BLin J = jobs[blockIdx.z];
+    const int j0 = blockIdx.y * kTile;
+    if (j0 >= J.k) return;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x) {
+        double acc[kTile];
+#pragma unroll
+        for (int b = 0; b < kTile; ++b) acc[b] = 0.0;
+        for (int i = 0; i < J.m; ++i) {
+            const double v = J.V[(int64_t)i * J.ldv + t];
+#pragma unroll
+            for (int b = 0; b < kTile; ++b)
+                if (j0 + b < J.k) acc[b] += v * J.Y[(j0 + b) * J.m + i];
+        }
+#pragma unroll
+        for (int b = 0; b < kTile; ++b)
+            if (j0 + b < J.k) {
+                double *o = J.out + (int64_t)(j0 + b) * J.ldo + t;
+                *o = (J.beta == 0.0 ? 0.0 : J.beta * *o) + J.sign * acc[b];
+            }
+    }
+}
+
+struct BRes {              // residuals and Davidson corrections of one slot
+    double *WY, *T;
+    const double *X, *D, *theta;
+    int64_t ld, n;
+    int k;
+};
+
+__global__ void k_bresid(const BRes *__restrict__ jobs)
+{
+    const BRes J = jobs[blockIdx.z];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double d = J.D[t];
+        for (int j = 0; j < J.k; ++j) {
+            const double r = J.WY[(int64_t)j * J.ld + t] - J.theta[j] * J.X[(int64_t)j * J.ld + t];
+            J.WY[(int64_t)j * J.ld + t] = r;
+            double den = J.theta[j] - d;
+            if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+            J.T[(int64_t)j * J.ld + t] = r / den;
+        }
+    }
+}
+
+struct BVecOp {            // copy src -> dst, or normalise dst (see k_bnormalize)
+    const double *src;
+    double *dst;
+    const double *n0, *n1;
+    double *fac;
+    int64_t n;
+};
+
+__global__ void k_bcopy(const BVecOp *__restrict__ jobs)
+{
+    const BVecOp J = jobs[blockIdx.z];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x)
+        J.dst[t] = J.src[t];
+}
+
+__global__ void k_bnormalize(const BVecOp *__restrict__ jobs, double rel)
+{
+    const BVecOp J = jobs[blockIdx.z];
+    const double a = sqrt(*J.n1), a0 = sqrt(*J.n0);
+    const double f = (a > rel * a0 && a > 0.0) ? 1.0 / a : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *J.fac = f;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x)
+        J.dst[t] *= f;
+}
+
 // ---------------------------------------------------------------- engine
 
 // Per-solve state.  Device buffers: V, W (mmax x dim), X (nscr x dim), R, T
@@ -275,6 +418,11 @@ struct isci_engine_s {
     size_t cap_args = 0, cap_vecs = 0;
     int grid = 0;          // persistent grid size for the fused sigma (0: one block per item)
     int order = 1;         // 1: heaviest work items first, 0: natural order
+    // per-phase descriptor arena (pinned host -> device) and result arena
+    // (device -> pinned host) of the batched block algebra
+    char *arena_d = nullptr, *arena_h = nullptr;
+    double *res_d = nullptr, *res_h = nullptr;
+    size_t arena_cap = 0, res_cap = 0;
 };
 
 namespace isci {
@@ -515,6 +663,93 @@ static isci_status phase_sigma(isci_engine e, const std::vector<Slot *> &act)
     return fused_sigma(e, (int)hs.size(), hs.data(), nv.data(), cv.data(), ld.data(), sv.data(), ld.data());
 }
 
+// ---- descriptor arena: the host packs one phase's descriptors into
+// pinned memory, one copy moves them to the device, kernels read them there
+struct ArenaPack {
+    isci_engine e;
+    size_t used = 0;
+    template <typename T>
+    size_t push(const std::vector<T> &v)
+    {
+        const size_t off = (used + 255) & ~(size_t)255;
+        used = off + sizeof(T) * v.size();
+        return off;
+    }
+};
+
+static bool arena_reserve(isci_engine e, size_t bytes)
+{
+    if (bytes <= e->arena_cap) return true;
+    size_t n = std::max(bytes, 2 * e->arena_cap + 65536);
+    if (e->arena_d) (void)hipFree(e->arena_d);
+    if (e->arena_h) (void)hipHostFree(e->arena_h);
+    e->arena_d = nullptr;
+    e->arena_h = nullptr;
+    e->arena_cap = 0;
+    if (hipMalloc((void **)&e->arena_d, n) != hipSuccess) return false;
+    if (hipHostMalloc((void **)&e->arena_h, n, hipHostMallocDefault) != hipSuccess) return false;
+    e->arena_cap = n;
+    return true;
+}
+
+static bool res_reserve(isci_engine e, size_t ndouble)
+{
+    if (ndouble <= e->res_cap) return true;
+    size_t n = std::max(ndouble, 2 * e->res_cap + 4096);
+    if (e->res_d) (void)hipFree(e->res_d);
+    if (e->res_h) (void)hipHostFree(e->res_h);
+    e->res_d = nullptr;
+    e->res_h = nullptr;
+    e->res_cap = 0;
+    if (hipMalloc((void **)&e->res_d, sizeof(double) * n) != hipSuccess) return false;
+    if (hipHostMalloc((void **)&e->res_h, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) return false;
+    e->res_cap = n;
+    return true;
+}
+
+template <typename T>
+static T *arena_put(isci_engine e, size_t off, const std::vector<T> &v)
+{
+    if (!v.empty()) memcpy(e->arena_h + off, v.data(), sizeof(T) * v.size());
+    return (T *)(e->arena_d + off);
+}
+
+static isci_status launch_bdots(const BDot *d, const std::vector<BDot> &h, hipStream_t s)
+{
+    if (h.empty()) return ISCI_OK;
+    int gx = 1, ti = 1, tj = 1, mk = 1;
+    for (const BDot &j : h) {
+        gx = std::max(gx, j.nblk);
+        ti = std::max(ti, (j.m + kTile - 1) / kTile);
+        tj = std::max(tj, (j.k + kTile - 1) / kTile);
+        mk = std::max(mk, j.m * j.k);
+    }
+    k_bdots<<<dim3(gx, ti * tj, (unsigned)h.size()), 256, 0, s>>>(d, tj);
+    k_bdots_reduce<<<dim3((mk + 255) / 256, 1, (unsigned)h.size()), 256, 0, s>>>(d);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
+static isci_status launch_blincomb(const BLin *d, const std::vector<BLin> &h, hipStream_t s)
+{
+    if (h.empty()) return ISCI_OK;
+    int64_t n = 1;
+    int k = 1;
+    for (const BLin &j : h) { n = std::max(n, j.n); k = std::max(k, j.k); }
+    k_blincomb<<<dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256), (k + kTile - 1) / kTile,
+                      (unsigned)h.size()), 256, 0, s>>>(d);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
+template <typename J>
+static int64_t max_n(const std::vector<J> &h)
+{
+    int64_t n = 1;
+    for (const J &j : h) n = std::max(n, j.n);
+    return n;
+}
+
 // one Davidson iteration for every active slot
 static isci_status engine_step(isci_engine e, int *nactive)
 {
@@ -526,65 +761,124 @@ static isci_status engine_step(isci_engine e, int *nactive)
     if (act.empty()) return ISCI_OK;
     isci_status st = phase_sigma(e, act);
     if (st != ISCI_OK) return st;
-    // ---- phase B: new columns of G = V^T W_new
-    for (Slot *sl : act) {
+    const int na = (int)act.size();
+    // results needed this step: G columns, residual Gram matrices, CGS2 scalars
+    size_t need = 0;
+    for (Slot *sl : act) need += (size_t)sl->m * (sl->m - sl->mdone) + (size_t)sl->kk * sl->kk + 3 * (sl->block + 1);
+    if (!res_reserve(e, need + 64)) { set_error("allocation failed (engine results)"); return ISCI_E_OOM; }
+
+    // ---- phase B: new columns of G = V^T W_new, all slots in one launch pair
+    std::vector<BDot> jb;
+    std::vector<size_t> offB(na);
+    size_t roff = 0;
+    for (int j = 0; j < na; ++j) {
+        Slot *sl = act[j];
         const int nnew = sl->m - sl->mdone;
-        st = dots(sl->V, sl->dim, sl->m, sl->W + (size_t)sl->mdone * sl->dim, sl->dim, nnew, sl->dim, sl->small,
-                  sl->partial, sl->nblk, s);
-        if (st != ISCI_OK) return st;
-        ISCI_HIP(hipMemcpyAsync(sl->hsmall, sl->small, sizeof(double) * sl->m * nnew, hipMemcpyDeviceToHost, s));
+        offB[j] = roff;
+        BDot d;
+        d.A = sl->V; d.B = sl->W + (size_t)sl->mdone * sl->dim;
+        d.out = e->res_d + roff; d.partial = sl->partial;
+        d.lda = sl->dim; d.ldb = sl->dim; d.n = sl->dim;
+        d.m = sl->m; d.k = nnew; d.nblk = sl->nblk;
+        if (nnew > 0) jb.push_back(d);
+        roff += (size_t)sl->m * nnew;
     }
-    ISCI_HIP(hipStreamSynchronize(s));
-    // ---- phase C (host): projected eigenproblem; then Ritz vectors,
-    // residuals and preconditioned corrections on the device
-    for (Slot *sl : act) {
+    {
+        ArenaPack ap{e};
+        const size_t o = ap.push(jb);
+        if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
+        BDot *dd = arena_put(e, o, jb);
+        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        if ((st = launch_bdots(dd, jb, s)) != ISCI_OK) return st;
+        ISCI_HIP(hipMemcpyAsync(e->res_h, e->res_d, sizeof(double) * std::max<size_t>(roff, 1), hipMemcpyDeviceToHost, s));
+        ISCI_HIP(hipStreamSynchronize(s));
+    }
+    // ---- host: projected eigenproblems; phase C: Ritz vectors, residuals,
+    // corrections and residual norms for all slots
+    std::vector<double> params;
+    std::vector<size_t> offY(na), offR(na);
+    size_t rC = roff;
+    for (int j = 0; j < na; ++j) {
+        Slot *sl = act[j];
         const int m = sl->m, mdone = sl->mdone, nnew = m - mdone, mmax = sl->mmax;
+        const double *col = e->res_h + offB[j];
         for (int i = 0; i < m; ++i)
-            for (int j = 0; j < nnew; ++j) {
-                const double v = sl->hsmall[(size_t)i * nnew + j];
-                sl->G[(size_t)i * mmax + mdone + j] = v;
-                if (i < mdone) sl->G[(size_t)(mdone + j) * mmax + i] = v;
+            for (int q = 0; q < nnew; ++q) {
+                const double v = col[(size_t)i * nnew + q];
+                sl->G[(size_t)i * mmax + mdone + q] = v;
+                if (i < mdone) sl->G[(size_t)(mdone + q) * mmax + i] = v;
             }
         for (int i = mdone; i < m; ++i)
-            for (int j = mdone; j < i; ++j) {
-                const double a = 0.5 * (sl->G[(size_t)i * mmax + j] + sl->G[(size_t)j * mmax + i]);
-                sl->G[(size_t)i * mmax + j] = a;
-                sl->G[(size_t)j * mmax + i] = a;
+            for (int q = mdone; q < i; ++q) {
+                const double a2 = 0.5 * (sl->G[(size_t)i * mmax + q] + sl->G[(size_t)q * mmax + i]);
+                sl->G[(size_t)i * mmax + q] = a2;
+                sl->G[(size_t)q * mmax + i] = a2;
             }
         sl->mdone = m;
         std::vector<double> Gm((size_t)m * m);
         for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) Gm[(size_t)i * m + j] = sl->G[(size_t)i * mmax + j];
+            for (int q = 0; q < m; ++q) Gm[(size_t)i * m + q] = sl->G[(size_t)i * mmax + q];
         jacobi_eigh(m, Gm, sl->evals, sl->Z);
         const int kr = std::min(sl->kk, m);
         sl->kr = kr;
-        double *hY = sl->hsmall;                       // [kr][m], then theta[kr]
-        for (int j = 0; j < kr; ++j)
-            for (int i = 0; i < m; ++i) hY[(size_t)j * m + i] = sl->Z[(size_t)i * m + j];
-        for (int j = 0; j < kr; ++j) sl->theta[j] = hY[(size_t)kr * m + j] = sl->evals[j];
-        double *dY = sl->small, *dth = sl->small + (size_t)kr * m, *dn = dth + kr;
-        ISCI_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * ((size_t)kr * m + kr), hipMemcpyHostToDevice, s));
-        if ((st = lincomb(sl->V, sl->dim, m, dY, kr, sl->X, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
-        if ((st = lincomb(sl->W, sl->dim, m, dY, kr, sl->R, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
-        k_resid_precond<<<grid1(sl->dim), 256, 0, s>>>(sl->R, sl->X, sl->D, dth, kr, sl->dim, sl->dim, sl->T);
-        ISCI_HIP(hipGetLastError());
-        if ((st = dots(sl->R, sl->dim, kr, sl->R, sl->dim, kr, sl->dim, dn, sl->partial, sl->nblk, s)) != ISCI_OK)
-            return st;
-        ISCI_HIP(hipMemcpyAsync(sl->hsmall + (size_t)kr * m + kr, dn, sizeof(double) * kr * kr,
-                                hipMemcpyDeviceToHost, s));
+        offY[j] = params.size();
+        for (int q = 0; q < kr; ++q)
+            for (int i = 0; i < m; ++i) params.push_back(sl->Z[(size_t)i * m + q]);
+        for (int q = 0; q < kr; ++q) params.push_back(sl->theta[q] = sl->evals[q]);
+        offR[j] = rC;
+        rC += (size_t)kr * kr;
     }
-    ISCI_HIP(hipStreamSynchronize(s));
-    // ---- phase D (host): convergence, corrections, thick restart, CGS2
-    for (Slot *sl : act) {
+    {
+        ArenaPack ap{e};
+        std::vector<BLin> jl(2 * na);
+        std::vector<BRes> jr(na);
+        std::vector<BDot> jd(na);
+        const size_t op = ap.push(params);
+        const size_t ol = ap.push(jl), orr = ap.push(jr), od = ap.push(jd);
+        if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
+        jl.clear();
+        jr.clear();
+        jd.clear();
+        // the parameters' device addresses are fixed now that the arena is
+        const double *pd = (const double *)(e->arena_d + op);
+        for (int j = 0; j < na; ++j) {
+            Slot *sl = act[j];
+            const int m = sl->m, kr = sl->kr;
+            const double *Y = pd + offY[j], *th = Y + (size_t)kr * m;
+            jl.push_back(BLin{sl->V, Y, sl->X, sl->dim, sl->dim, sl->dim, m, kr, 0.0, 1.0});
+            jl.push_back(BLin{sl->W, Y, sl->R, sl->dim, sl->dim, sl->dim, m, kr, 0.0, 1.0});
+            jr.push_back(BRes{sl->R, sl->T, sl->X, sl->D, th, sl->dim, sl->dim, kr});
+            BDot d;
+            d.A = sl->R; d.B = sl->R; d.out = e->res_d + offR[j]; d.partial = sl->partial;
+            d.lda = sl->dim; d.ldb = sl->dim; d.n = sl->dim; d.m = kr; d.k = kr; d.nblk = sl->nblk;
+            jd.push_back(d);
+        }
+        arena_put(e, op, params);
+        BLin *dl = arena_put(e, ol, jl);
+        BRes *dr = arena_put(e, orr, jr);
+        BDot *dd = arena_put(e, od, jd);
+        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        if ((st = launch_blincomb(dl, jl, s)) != ISCI_OK) return st;
+        k_bresid<<<dim3((unsigned)std::min<int64_t>(4096, (max_n(jr) + 255) / 256), 1, (unsigned)jr.size()), 256, 0, s>>>(dr);
+        ISCI_HIP(hipGetLastError());
+        if ((st = launch_bdots(dd, jd, s)) != ISCI_OK) return st;
+        ISCI_HIP(hipMemcpyAsync(e->res_h + roff, e->res_d + roff, sizeof(double) * std::max<size_t>(rC - roff, 1),
+                                hipMemcpyDeviceToHost, s));
+        ISCI_HIP(hipStreamSynchronize(s));
+    }
+    // ---- host: convergence, corrections, thick restarts
+    std::vector<Slot *> grow_set;
+    for (int j = 0; j < na; ++j) {
+        Slot *sl = act[j];
         const int m = sl->m, kr = sl->kr, k = sl->k;
-        const double *rr = sl->hsmall + (size_t)kr * m + kr;
+        const double *rr = e->res_h + offR[j];
         sl->iter += 1;
         bool conv = kr >= k;
-        for (int j = 0; j < kr; ++j) {
-            sl->rn[j] = sqrt(std::max(0.0, rr[(size_t)j * kr + j]));
-            if (j < k) conv = conv && sl->rn[j] <= sl->o.tol_residual && fabs(sl->theta[j] - sl->prev[j]) <= sl->o.tol_energy;
+        for (int q = 0; q < kr; ++q) {
+            sl->rn[q] = sqrt(std::max(0.0, rr[(size_t)q * kr + q]));
+            if (q < k) conv = conv && sl->rn[q] <= sl->o.tol_residual && fabs(sl->theta[q] - sl->prev[q]) <= sl->o.tol_energy;
         }
-        for (int j = 0; j < kr; ++j) sl->prev[j] = sl->theta[j];
+        for (int q = 0; q < kr; ++q) sl->prev[q] = sl->theta[q];
         sl->conv = conv;
         if (conv || sl->iter >= sl->o.max_iter) {
             sl->done = true;
@@ -592,16 +886,16 @@ static isci_status engine_step(isci_engine e, int *nactive)
             continue;
         }
         sl->pick.clear();
-        for (int j = 0; j < kr && (int)sl->pick.size() < sl->block; ++j)
-            if (sl->rn[j] > sl->o.tol_residual) sl->pick.push_back(j);
+        for (int q = 0; q < kr && (int)sl->pick.size() < sl->block; ++q)
+            if (sl->rn[q] > sl->o.tol_residual) sl->pick.push_back(q);
         if (sl->pick.empty())
-            for (int j = 0; j < kr && (int)sl->pick.size() < sl->block; ++j) sl->pick.push_back(j);
+            for (int q = 0; q < kr && (int)sl->pick.size() < sl->block; ++q) sl->pick.push_back(q);
         if (m + (int)sl->pick.size() > sl->mmax) {
-            // thick restart: keep the lowest `keep` Ritz vectors
+            // thick restart (per slot; rare): keep the lowest `keep` Ritz vectors
             const int keep = std::min(m, sl->keep_max);
             double *hYk = sl->hsmall;
-            for (int j = 0; j < keep; ++j)
-                for (int i = 0; i < m; ++i) hYk[(size_t)j * m + i] = sl->Z[(size_t)i * m + j];
+            for (int q = 0; q < keep; ++q)
+                for (int i = 0; i < m; ++i) hYk[(size_t)q * m + i] = sl->Z[(size_t)i * m + q];
             double *dYk = sl->small;
             ISCI_HIP(hipMemcpyAsync(dYk, hYk, sizeof(double) * (size_t)keep * m, hipMemcpyHostToDevice, s));
             if ((st = lincomb(sl->V, sl->dim, m, dYk, keep, sl->X, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
@@ -609,30 +903,107 @@ static isci_status engine_step(isci_engine e, int *nactive)
             if ((st = lincomb(sl->W, sl->dim, m, dYk, keep, sl->X, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
             ISCI_HIP(hipMemcpyAsync(sl->W, sl->X, sizeof(double) * (size_t)keep * sl->dim, hipMemcpyDeviceToDevice, s));
             ISCI_HIP(hipMemcpyAsync(sl->X, sl->V, sizeof(double) * (size_t)kr * sl->dim, hipMemcpyDeviceToDevice, s));
-            // the host copy of hYk must stay valid until the copy above ran
             ISCI_HIP(hipStreamSynchronize(s));
             sl->m = keep;
             sl->mdone = keep;
             std::fill(sl->G.begin(), sl->G.end(), 0.0);
-            for (int j = 0; j < keep; ++j) sl->G[(size_t)j * sl->mmax + j] = sl->evals[j];
+            for (int q = 0; q < keep; ++q) sl->G[(size_t)q * sl->mmax + q] = sl->evals[q];
         }
-        const int m0 = sl->m;
-        int n = 0;
-        for (int j : sl->pick) {
-            if (sl->m >= sl->mmax) break;
-            if ((st = cgs2_enqueue(sl, sl->T + (size_t)j * sl->dim, n, s)) != ISCI_OK) return st;
-            ++n;
-        }
-        sl->pick.assign(1, m0);          // remember where this round's appends start
-        sl->pick.push_back(n);
-        ISCI_HIP(hipMemcpyAsync(sl->hscal, sl->scal, sizeof(double) * 3 * std::max(n, 1), hipMemcpyDeviceToHost, s));
+        grow_set.push_back(sl);
     }
-    ISCI_HIP(hipStreamSynchronize(s));
-    for (Slot *sl : act) {
-        if (sl->done) continue;
-        const int m0 = sl->pick[0], n = sl->pick[1];
-        if ((st = cgs2_finish(sl, m0, n, s)) != ISCI_OK) return st;
-        if (sl->m == m0) {   // stagnation: no new direction
+    // ---- phase D: CGS2 of the corrections, round i appends the i-th
+    // correction of every slot that has one (no host round trip inside)
+    if (grow_set.empty()) return ISCI_OK;
+    struct Round { std::vector<BVecOp> cp, nz; std::vector<BDot> n0, c1, c2, n1; std::vector<BLin> l1, l2; };
+    std::vector<Round> rounds;
+    std::vector<int> m0(grow_set.size()), nadd(grow_set.size(), 0);
+    std::vector<size_t> offS(grow_set.size());
+    size_t rs = rC;
+    for (size_t j = 0; j < grow_set.size(); ++j) {
+        m0[j] = grow_set[j]->m;
+        offS[j] = rs;
+        rs += 3 * grow_set[j]->pick.size();
+    }
+    size_t maxpick = 0;
+    for (Slot *sl : grow_set) maxpick = std::max(maxpick, sl->pick.size());
+    for (size_t i = 0; i < maxpick; ++i) {
+        Round R;
+        for (size_t j = 0; j < grow_set.size(); ++j) {
+            Slot *sl = grow_set[j];
+            if (i >= sl->pick.size() || sl->m >= sl->mmax) continue;
+            double *dst = sl->V + (size_t)sl->m * sl->dim;
+            const double *src = sl->T + (size_t)sl->pick[i] * sl->dim;
+            double *sc = e->res_d + offS[j] + 3 * i;
+            R.cp.push_back(BVecOp{src, dst, nullptr, nullptr, nullptr, sl->dim});
+            BDot d;
+            d.partial = sl->partial; d.lda = sl->dim; d.ldb = sl->dim; d.n = sl->dim; d.nblk = sl->nblk;
+            d.A = dst; d.B = dst; d.out = sc; d.m = 1; d.k = 1;
+            R.n0.push_back(d);
+            d.A = sl->V; d.B = dst; d.out = sl->small; d.m = sl->m; d.k = 1;
+            if (sl->m > 0) {
+                R.c1.push_back(d);
+                R.c2.push_back(d);
+                R.l1.push_back(BLin{sl->V, sl->small, dst, sl->dim, sl->dim, sl->dim, sl->m, 1, 1.0, -1.0});
+                R.l2.push_back(BLin{sl->V, sl->small, dst, sl->dim, sl->dim, sl->dim, sl->m, 1, 1.0, -1.0});
+            }
+            d.A = dst; d.B = dst; d.out = sc + 1; d.m = 1; d.k = 1;
+            R.n1.push_back(d);
+            R.nz.push_back(BVecOp{nullptr, dst, sc, sc + 1, sc + 2, sl->dim});
+            sl->m += 1;
+            nadd[j] += 1;
+        }
+        rounds.push_back(std::move(R));
+    }
+    {
+        ArenaPack ap{e};
+        struct Offs { size_t cp, nz, n0, c1, c2, n1, l1, l2; };
+        std::vector<Offs> of;
+        for (Round &R : rounds)
+            of.push_back(Offs{ap.push(R.cp), ap.push(R.nz), ap.push(R.n0), ap.push(R.c1), ap.push(R.c2),
+                              ap.push(R.n1), ap.push(R.l1), ap.push(R.l2)});
+        if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
+        for (size_t i = 0; i < rounds.size(); ++i) {
+            Round &R = rounds[i];
+            arena_put(e, of[i].cp, R.cp); arena_put(e, of[i].nz, R.nz); arena_put(e, of[i].n0, R.n0);
+            arena_put(e, of[i].c1, R.c1); arena_put(e, of[i].c2, R.c2); arena_put(e, of[i].n1, R.n1);
+            arena_put(e, of[i].l1, R.l1); arena_put(e, of[i].l2, R.l2);
+        }
+        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        for (size_t i = 0; i < rounds.size(); ++i) {
+            Round &R = rounds[i];
+            if (R.cp.empty()) continue;
+            const unsigned gz = (unsigned)R.cp.size();
+            const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(R.cp) + 255) / 256);
+            k_bcopy<<<dim3(gx, 1, gz), 256, 0, s>>>((const BVecOp *)(e->arena_d + of[i].cp));
+            ISCI_HIP(hipGetLastError());
+            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].n0), R.n0, s)) != ISCI_OK) return st;
+            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].c1), R.c1, s)) != ISCI_OK) return st;
+            if ((st = launch_blincomb((const BLin *)(e->arena_d + of[i].l1), R.l1, s)) != ISCI_OK) return st;
+            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].c2), R.c2, s)) != ISCI_OK) return st;
+            if ((st = launch_blincomb((const BLin *)(e->arena_d + of[i].l2), R.l2, s)) != ISCI_OK) return st;
+            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].n1), R.n1, s)) != ISCI_OK) return st;
+            k_bnormalize<<<dim3(gx, 1, gz), 256, 0, s>>>((const BVecOp *)(e->arena_d + of[i].nz), 1e-10);
+            ISCI_HIP(hipGetLastError());
+        }
+        ISCI_HIP(hipMemcpyAsync(e->res_h + rC, e->res_d + rC, sizeof(double) * std::max<size_t>(rs - rC, 1),
+                                hipMemcpyDeviceToHost, s));
+        ISCI_HIP(hipStreamSynchronize(s));
+    }
+    for (size_t j = 0; j < grow_set.size(); ++j) {
+        Slot *sl = grow_set[j];
+        // drop appended vectors whose normalisation factor is 0 (in the span)
+        const int64_t dim = sl->dim;
+        int w = m0[j];
+        for (int i = 0; i < nadd[j]; ++i) {
+            const bool keep = e->res_h[offS[j] + 3 * i + 2] != 0.0;
+            if (!keep) continue;
+            if (w != m0[j] + i)
+                ISCI_HIP(hipMemcpyAsync(sl->V + (size_t)w * dim, sl->V + (size_t)(m0[j] + i) * dim,
+                                        sizeof(double) * dim, hipMemcpyDeviceToDevice, s));
+            ++w;
+        }
+        sl->m = w;
+        if (w == m0[j]) {   // stagnation: no new direction
             sl->done = true;
             sl->status = sl->conv ? ISCI_OK : ISCI_E_NOT_CONVERGED;
         }
@@ -776,6 +1147,10 @@ void isci_engine_destroy(isci_engine e)
     if (e->h_args) (void)hipHostFree(e->h_args);
     if (e->d_vecs) (void)hipFree(e->d_vecs);
     if (e->h_vecs) (void)hipHostFree(e->h_vecs);
+    if (e->arena_d) (void)hipFree(e->arena_d);
+    if (e->arena_h) (void)hipHostFree(e->arena_h);
+    if (e->res_d) (void)hipFree(e->res_d);
+    if (e->res_h) (void)hipHostFree(e->res_h);
     delete e;
 }
 
