@@ -220,8 +220,9 @@ void isci_engine_destroy(isci_engine e);
 int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_opts *opts);
 
 /* Per-handle options.
- *   ISCI_OPT_SIGMA_KERNEL: ISCI_SIGMA_AUTO (default: pair kernel when both
- *   spins hold two electrons, else the general one), ISCI_SIGMA_GENERAL
+ *   ISCI_OPT_SIGMA_KERNEL: ISCI_SIGMA_AUTO (default: two electrons per spin
+ *   use the matrix-core path from 50000 determinants on and the pair kernel
+ *   below; other electron counts the general kernel), ISCI_SIGMA_GENERAL
  *   (string algebra for any electron count), ISCI_SIGMA_PAIR (two-electron
  *   pair tables; ISCI_E_UNSUPPORTED otherwise), ISCI_SIGMA_MFMA (pair
  *   tables, alpha-beta class on FP64 matrix cores; two electrons per spin).

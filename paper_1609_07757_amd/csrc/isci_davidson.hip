@@ -653,6 +653,15 @@ static isci_status phase_sigma(isci_engine e, const std::vector<Slot *> &act)
     for (Slot *sl : act) {
         const int nnew = sl->m - sl->mdone;
         if (nnew <= 0) continue;
+        if (sigma_args(sl->h).variant == 3) {
+            // large instances tuned for the matrix-core path run their own
+            // launches; the rest share the fused launch
+            isci_status st = launch_sigma(sl->h, nnew, sl->V + (size_t)sl->mdone * sl->dim, sl->dim,
+                                          sl->W + (size_t)sl->mdone * sl->dim, sl->dim, e->s);
+            if (st != ISCI_OK) return st;
+            sl->nsig += nnew;
+            continue;
+        }
         hs.push_back(sl->h);
         nv.push_back(nnew);
         cv.push_back(sl->V + (size_t)sl->mdone * sl->dim);

@@ -72,6 +72,11 @@ struct DevTabs {
     double *chunk_val = nullptr;    // [nchunk][64]
     uchar4 *quads = nullptr;        // target tiles (X, P, Y, R) with X<=P, Y<=R, level <= L
     double *hscreen = nullptr;      // [norb][norb] h with screened units set to 0 (one-body kernels)
+    // alpha row of the ordered pair (x, q): start and length (-1 / 0 when
+    // {x,q} is not a string of the space)
+    long long *arow_base = nullptr;
+    int *arow_len = nullptr;
+    int *chunk_cls = nullptr;       // [nblk*nblk][3] chunks per source level class
 };
 
 struct SigmaArgs {
@@ -96,6 +101,9 @@ struct SigmaArgs {
     const int2 *chunk_desc;
     const double *chunk_val;
     const uchar4 *quads;
+    const long long *arow_base;
+    const int *arow_len;
+    const int *chunk_cls;
 };
 
 // One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)

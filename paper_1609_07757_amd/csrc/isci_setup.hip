@@ -398,7 +398,10 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.apidx = c->d.apidx; A.bpidx = c->d.bpidx;
     const bool pair_ok = c->sa.n == 2 && c->sb.n == 2;
     A.variant = (c->sigma_variant == ISCI_SIGMA_GENERAL || !pair_ok) ? 1 : 2;
-    if (pair_ok && c->have_tiles && c->sigma_variant == ISCI_SIGMA_MFMA) A.variant = 3;
+    // automatic choice: the matrix-core path for spaces large enough to
+    // amortise its extra launches, the single pair kernel below that
+    const bool auto_mfma = c->sigma_variant == ISCI_SIGMA_AUTO && c->dim >= 50000;
+    if (pair_ok && c->have_tiles && (c->sigma_variant == ISCI_SIGMA_MFMA || auto_mfma)) A.variant = 3;
     A.classes = 7;
     A.accumulate = 0;
     A.nblk = c->nblk;
@@ -407,6 +410,9 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.chunk_desc = c->d.chunk_desc;
     A.chunk_val = c->d.chunk_val;
     A.quads = c->d.quads;
+    A.arow_base = c->d.arow_base;
+    A.arow_len = c->d.arow_len;
+    A.chunk_cls = c->d.chunk_cls;
     return A;
 }
 
@@ -437,18 +443,25 @@ __global__ void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
     cnt[g] = c;
 }
 
+// chunks of a row block are written in order of their source level class
+// (virtual q) + (virtual S-block), so the chunks a role may use form a
+// prefix; cls[g*3 + l] counts the chunks of class l
 __global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int nb, double tau,
-                             const int8_t *blk_orb, const int *off, int2 *desc, double *val)
+                             const int8_t *blk_orb, const int *off, int2 *desc, double *val, int *cls)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nb * nb) return;
     const int Ab = g / nb, Bb = g % nb;
     const long long k0 = (long long)g * n * nb;
     int w = off[g];
+    for (int lc = 0; lc < 3; ++lc) {
+    int cnt = 0;
     for (int q = 0; q < n; ++q)
         for (int S = 0; S < nb; ++S) {
+            if ((q >= 2) + (S != 0) != lc) continue;
             const long long k = k0 + (long long)q * nb + S;
             if (!((bits[k >> 5] >> (k & 31)) & 1u)) continue;
+            ++cnt;
             desc[w] = make_int2(q, S);
             for (int l = 0; l < 64; ++l) {
                 const int i = l & 15, kk = l >> 4;
@@ -462,6 +475,8 @@ __global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int
             }
             ++w;
         }
+    cls[g * 3 + lc] = cnt;
+    }
 }
 
 // blocks of four orbitals, o/v pure (two electrons per spin: the occupied
@@ -515,9 +530,10 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     ISCI_HIP(hipStreamSynchronize(s));   // also keeps the host tables above alive until copied
     d.chunk_desc = (int2 *)dev_alloc(c, sizeof(int2) * std::max(1, tot));
     d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * (size_t)std::max(1, tot));
-    if (!d.chunk_desc || !d.chunk_val) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
+    d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
+    if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
     k_chunk_fill<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, eri, n, nb, c->tau, d.blk_orb, d.chunk_off, d.chunk_desc,
-                                                     d.chunk_val);
+                                                     d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
     ISCI_HIP(hipFreeAsync(bits, s));
     ISCI_HIP(hipStreamSynchronize(s));
@@ -768,6 +784,24 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
         e2 = hipStreamSynchronize(stream);
         if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload pair index"); }
         (spin ? c->d.bpidx : c->d.apidx) = dp;
+        if (spin == 0) {
+            // alpha row (start, length) of every ordered pair (x, q)
+            std::vector<long long> base((size_t)norb * norb, -1);
+            std::vector<int> len((size_t)norb * norb, 0);
+            for (size_t k = 0; k < pidx.size(); ++k)
+                if (pidx[k] >= 0) {
+                    base[k] = c->h_rowstart[pidx[k]];
+                    len[k] = (int)(c->h_rowstart[pidx[k] + 1] - c->h_rowstart[pidx[k]]);
+                }
+            c->d.arow_base = (long long *)dev_alloc(c, sizeof(long long) * base.size());
+            c->d.arow_len = (int *)dev_alloc(c, sizeof(int) * len.size());
+            if (!c->d.arow_base || !c->d.arow_len) { destroy(c); set_error("device allocation failed (row tables)"); return ISCI_E_OOM; }
+            e2 = hipMemcpyAsync(c->d.arow_base, base.data(), sizeof(long long) * base.size(), hipMemcpyHostToDevice, stream);
+            if (e2 == hipSuccess)
+                e2 = hipMemcpyAsync(c->d.arow_len, len.data(), sizeof(int) * len.size(), hipMemcpyHostToDevice, stream);
+            if (e2 == hipSuccess) e2 = hipStreamSynchronize(stream);
+            if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload row tables"); }
+        }
     }
     isci_status st = build_lists(c, h, eri, stream);
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }

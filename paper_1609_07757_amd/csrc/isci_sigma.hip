@@ -343,11 +343,81 @@ __device__ __forceinline__ void sigma_target_n2(const SigmaArgs &A, int ia, int 
 // roles are combined through LDS and sigma is written once (no atomics).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int NV>
+// orbital of slot i (0..3) of block B: block 0 holds the two occupied
+// orbitals, block B >= 1 the virtual orbitals 2 + 4 (B - 1) + i
+__device__ __forceinline__ int blk_orbital(int B, int i, int norb)
+{
+    if (B == 0) return i < 2 ? i : -1;
+    const int v = 2 + 4 * (B - 1) + i;
+    return v < norb ? v : -1;
+}
+
+constexpr int kTabMax = 128;   // orbitals covered by the LDS lookup tables
+
+// B operand of one chunk for this lane: sign * c(v, {x,q}, {y,s}) or 0
+template <int NV, bool TAB>
+__device__ __forceinline__ void gather_b(const SigmaArgs &A, const double *__restrict__ c, int64_t ldc, int nv,
+                                         int x, int y, int ic, int id, int q, int s, int norb,
+                                         const long long *rb, const int *rl, const int *bi, double *b)
+{
+    bool ok = x >= 0 && y >= 0 && s >= 0 && x != q && y != s;
+    long long base = -1;
+    int len = 0, jb = -1;
+    if (ok) {
+        if (TAB) {
+            base = rb[ic * kTabMax + q];
+            len = rl[ic * kTabMax + q];
+            jb = bi[id * kTabMax + s];
+        } else {
+            base = A.arow_base[x * norb + q];
+            len = A.arow_len[x * norb + q];
+            jb = A.bpidx[y * norb + s];
+        }
+        ok = base >= 0 && jb >= 0 && jb < len;
+    }
+    const double f = ((q > x) == (s > y)) ? 1.0 : -1.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b[v] = 0.0;
+    if (ok) {
+        const double *src = c + base + jb;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) b[v] = f * src[v * ldc];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alpha-beta class on FP64 matrix cores (two electrons per spin).
+//
+// With T[x][q][y][s] = sgn(q-x) sgn(s-y) c({x,q},{y,s}) (the CI vector as an
+// antisymmetric pair tensor in each spin), the alpha-beta class is
+//   T'[x][p][y][r] = S[x][p][y][r] - S[p][x][y][r] - S[x][p][r][y] + S[p][x][r][y],
+//   S[x][p][y][r]  = sum_{q,s} (pq|rs) T[x][q][y][s],
+// i.e. for fixed spectators (x, y) a product with the screened matrix
+// W[(p,r),(q,s)] = (pq|rs) (the alpha-beta ladder of Eqs. h200ca..h200ab
+// when all four indices are virtual).  Orbitals are grouped in blocks of
+// four (o/v pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
+// block X, p in P, y in Y, r in R and computes the four role products
+// (which of x/p and y/r is the spectator) on four waves, one
+// 16 x 16 x 4 MFMA per (column chunk, vector): rows = the 16 active pairs,
+// columns = the 16 spectator pairs, K = 4 columns (q, s) of a chunk.  The
+// chunks of a row block are stored by source level class, so the chunks a
+// role may use (source level <= L) are a prefix.  Row starts and beta
+// indices of the wave's spectators are staged in LDS (TAB), and four
+// chunks are loaded before their MFMAs issue.  The roles are combined
+// through LDS and sigma is written once (no atomics).
+template <int NV, bool TAB>
 __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, const double *__restrict__ c,
                                                        int64_t ldc, double *__restrict__ sg, int64_t lds)
 {
-    __shared__ double tile[4][NV][16][17];
+    constexpr size_t kTileBytes = sizeof(double) * 4 * NV * 16 * 17;
+    constexpr size_t kTabBytes = TAB ? (size_t)4 * 4 * kTabMax * (sizeof(long long) + 2 * sizeof(int)) : 16;
+    __shared__ __attribute__((aligned(16))) char smem[kTileBytes > kTabBytes ? kTileBytes : kTabBytes];
+    double(*tile)[NV][16][17] = reinterpret_cast<double(*)[NV][16][17]>(smem);
+    long long *rb_all = reinterpret_cast<long long *>(smem);
+    int *rl_all = reinterpret_cast<int *>(smem + (size_t)4 * 4 * kTabMax * sizeof(long long));
+    int *bi_all = rl_all + 4 * 4 * kTabMax;
+
     const uchar4 qd = A.quads[blockIdx.x];
     const int X = qd.x, P = qd.y, Y = qd.z, R = qd.w;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -359,54 +429,75 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     else if (wave == 1) { Ab = X; Bb = R; Cb = P; Db = Y; active = !sameA; }
     else if (wave == 2) { Ab = P; Bb = Y; Cb = X; Db = R; active = !sameB; }
     else { Ab = X; Bb = Y; Cb = P; Db = R; active = !sameA && !sameB; }
+    long long *rb = rb_all + wave * 4 * kTabMax;
+    int *rl = rl_all + wave * 4 * kTabMax;
+    int *bi = bi_all + wave * 4 * kTabMax;
+    if (TAB && active)
+        for (int t = lane; t < 4 * norb; t += 64) {
+            const int i = t / norb, o = t % norb;
+            const int xx = blk_orbital(Cb, i, norb), yy = blk_orbital(Db, i, norb);
+            rb[i * kTabMax + o] = xx >= 0 ? A.arow_base[xx * norb + o] : -1;
+            rl[i * kTabMax + o] = xx >= 0 ? A.arow_len[xx * norb + o] : 0;
+            bi[i * kTabMax + o] = yy >= 0 ? A.bpidx[yy * norb + o] : -1;
+        }
+    __syncthreads();
     v4d acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = v4d{0.0, 0.0, 0.0, 0.0};
     if (active) {
         const int n = lane & 15, k = lane >> 4;
-        const int x = A.blk_orb[Cb * 4 + (n >> 2)], y = A.blk_orb[Db * 4 + (n & 3)];
+        const int ic = n >> 2, id = n & 3;
+        const int x = blk_orbital(Cb, ic, norb), y = blk_orbital(Db, id, norb);
         const int espec = (Cb != 0) + (Db != 0);
         const int row = Ab * nb + Bb;
-        const int e0 = A.chunk_off[row], e1 = A.chunk_off[row + 1];
-        for (int e = e0; e < e1; ++e) {
-            const int2 d = A.chunk_desc[e];
-            const int q = d.x, S = d.y;
-            if (espec + (q >= 2) + (S != 0) > L) continue;     // source level above the cut
-            const double a = A.chunk_val[(size_t)e * 64 + lane];
-            const int s = A.blk_orb[S * 4 + k];
-            bool ok = x >= 0 && y >= 0 && s >= 0 && x != q && y != s;
-            int64_t addr = 0;
-            double f = 0.0;
-            if (ok) {
-                const int ja = A.apidx[x * norb + q], jb = A.bpidx[y * norb + s];
-                ok = ja >= 0 && jb >= 0 && jb < A.sb.le[L - A.alev[ja]];
-                if (ok) {
-                    addr = A.rowstart[ja] + jb;
-                    f = ((q > x) == (s > y)) ? 1.0 : -1.0;
-                }
+        const int e0 = A.chunk_off[row];
+        int e1 = e0;
+        for (int l = 0; l < 3; ++l)
+            if (espec + l <= L) e1 += A.chunk_cls[row * 3 + l];
+        int e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            double a[4], b[4][NV];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int2 d = A.chunk_desc[e + u];
+                a[u] = A.chunk_val[(size_t)(e + u) * 64 + lane];
+                gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, blk_orbital(d.y, k, norb), norb, rb, rl, bi, b[u]);
             }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double b = (ok && v < nv) ? f * c[v * ldc + addr] : 0.0;
-                acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[v], 0, 0, 0);
-            }
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][v], acc[v], 0, 0, 0);
         }
+        for (; e < e1; ++e) {
+            double b[NV];
+            const int2 d = A.chunk_desc[e];
+            const double a = A.chunk_val[(size_t)e * 64 + lane];
+            gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, blk_orbital(d.y, k, norb), norb, rb, rl, bi, b);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[v], acc[v], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // the lookup tables share LDS with the role tiles
+    if (active) {
+        // 16x16x4 f64 result layout: element g of lane l is D[4 g + l / 16][l % 16]
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int g = 0; g < 4; ++g) tile[wave][v][4 * (lane >> 4) + g][lane & 15] = acc[v][g];
+            for (int g = 0; g < 4; ++g) tile[wave][v][4 * g + (lane >> 4)][lane & 15] = acc[v][g];
     }
     __syncthreads();
     const int t = threadIdx.x;
     const int ix = (t >> 6) & 3, ip = (t >> 4) & 3, iy = (t >> 2) & 3, ir = t & 3;
-    const int x = A.blk_orb[X * 4 + ix], p = A.blk_orb[P * 4 + ip];
-    const int y = A.blk_orb[Y * 4 + iy], r = A.blk_orb[R * 4 + ir];
+    const int x = blk_orbital(X, ix, norb), p = blk_orbital(P, ip, norb);
+    const int y = blk_orbital(Y, iy, norb), r = blk_orbital(R, ir, norb);
     if (x < 0 || p < 0 || y < 0 || r < 0 || x >= p || y >= r) return;
-    const int ja = A.apidx[x * norb + p], jb = A.bpidx[y * norb + r];
-    if (ja < 0 || jb < 0 || jb >= A.sb.le[L - A.alev[ja]]) return;
+    const long long tb = A.arow_base[x * norb + p];
+    const int tl = A.arow_len[x * norb + p];
+    const int jb = A.bpidx[y * norb + r];
+    if (tb < 0 || jb < 0 || jb >= tl) return;
     const int t1 = sameA ? 0 : 1, t2 = sameB ? 0 : 2;
     const int t3 = (sameA && sameB) ? 0 : sameA ? 2 : sameB ? 1 : 3;
-    double *dst = sg + A.rowstart[ja] + jb;
+    double *dst = sg + tb + jb;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if (v >= nv) break;
@@ -415,7 +506,6 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
         dst[v * lds] = val;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // One-body classes for two electrons per spin (add into sigma).
@@ -432,15 +522,14 @@ __global__ __launch_bounds__(256) void k_onebody_a(SigmaArgs A, int nv, const do
                                                    int64_t ldc, double *__restrict__ sg, int64_t lds,
                                                    const double *__restrict__ hs, int upper)
 {
-    const int norb = A.norb, L = A.L;
+    const int norb = A.norb;
     const int x = blockIdx.x;
     const int a0 = blockIdx.y * 8;
-    const int J = blockIdx.z * 256 + threadIdx.x;
-    const int *apx = A.apidx;
-    // target rows
-    int ta[8];
-    int tlen[8];
-    int64_t trow[8];
+    const int j0 = blockIdx.z * 256;
+    const int J = j0 + threadIdx.x;
+    // target rows {x, a}
+    int ta[8], tlen[8];
+    long long trow[8];
     int maxlen = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -449,44 +538,62 @@ __global__ __launch_bounds__(256) void k_onebody_a(SigmaArgs A, int nv, const do
         tlen[i] = 0;
         trow[i] = 0;
         if (a < norb && a != x && ((a > x) == (upper != 0))) {
-            const int ja = apx[x * norb + a];
-            if (ja >= 0) {
+            const long long base = A.arow_base[x * norb + a];
+            if (base >= 0) {
                 ta[i] = a;
-                tlen[i] = A.sb.le[L - A.alev[ja]];
-                trow[i] = A.rowstart[ja];
+                tlen[i] = A.arow_len[x * norb + a];
+                trow[i] = base;
                 maxlen = max(maxlen, tlen[i]);
             }
         }
     }
-    if ((int)(blockIdx.z * 256) >= maxlen) return;
+    if (j0 >= maxlen) return;
     double acc[8][NV];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
-    for (int q = 0; q < norb; ++q) {
-        if (q == x) continue;
-        const int jq = apx[x * norb + q];
-        if (jq < 0) continue;
-        const int slen = A.sb.le[L - A.alev[jq]];
-        if ((int)(blockIdx.z * 256) >= slen) continue;
-        double hq[8];
-        bool any = false;
+    const long long *__restrict__ rbase = A.arow_base + x * norb;
+    const int *__restrict__ rlen = A.arow_len + x * norb;
+    // source rows {x, q}: two at a time so their loads overlap
+    for (int q0 = 0; q0 < norb; q0 += 2) {
+        double cv[2][NV], hq[2][8];
+        bool use[2];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            hq[i] = ta[i] >= 0 ? hs[ta[i] * norb + q] : 0.0;
-            any |= hq[i] != 0.0;
+        for (int u = 0; u < 2; ++u) {
+            const int q = q0 + u;
+            use[u] = false;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) cv[u][v] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) hq[u][i] = 0.0;
+            if (q >= norb || q == x) continue;
+            const long long base = rbase[q];
+            const int slen = rlen[q];
+            if (base < 0 || j0 >= slen) continue;
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                hq[u][i] = ta[i] >= 0 ? hs[ta[i] * norb + q] : 0.0;
+                any |= hq[u][i] != 0.0;
+            }
+            if (!any) continue;
+            use[u] = true;
+            if (J < slen) {
+                const double sq = (q > x) ? 1.0 : -1.0;
+                const double *src = c + base + J;
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < nv) cv[u][v] = sq * src[v * ldc];
+            }
         }
-        if (!any || J >= slen) continue;
-        const double sq = (q > x) ? 1.0 : -1.0;
-        const double *src = c + A.rowstart[jq] + J;
-        double cv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) cv[v] = (v < nv) ? sq * src[v * ldc] : 0.0;
+        for (int u = 0; u < 2; ++u)
+            if (use[u])
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+                for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[i][v] += hq[i] * cv[v];
+                    for (int v = 0; v < NV; ++v) acc[i][v] += hq[u][i] * cv[u][v];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -502,27 +609,34 @@ __global__ __launch_bounds__(256) void k_onebody_a(SigmaArgs A, int nv, const do
 // Beta: within the alpha row I,
 //   sigma(I, {y<b}) += sum_s h_bs sgn(s - y) c(I, {y, s}) - sum_s h_ys sgn(s - b) c(I, {b, s}).
 // A workgroup stages row I (NV vectors) in LDS; one thread per target.
-// Rows that do not fit in LDS (STAGE = false) are read from global memory.
+// Rows that do not fit in LDS (STAGE = false) are read from global memory;
+// for norb <= 64 the beta pair-index table and h are staged in LDS too.
 template <int NV, bool STAGE>
 __global__ __launch_bounds__(256) void k_onebody_b(SigmaArgs A, int nv, const double *__restrict__ c,
                                                    int64_t ldc, double *__restrict__ sg, int64_t lds,
                                                    const double *__restrict__ hs)
 {
-    extern __shared__ double lrow[];   // [len][NV]
+    extern __shared__ double lrow[];   // [len][NV], then (norb <= 64) int pidx[norb*norb], double h[norb*norb]
     const int norb = A.norb, L = A.L;
     const int ia = blockIdx.x;
     const int len = A.sb.le[L - A.alev[ia]];
     const int64_t base = A.rowstart[ia];
+    const bool small = STAGE && norb <= 64;
+    double *lh = lrow + (size_t)A.sb.le[L] * NV;               // after the longest row
+    int *lp = reinterpret_cast<int *>(lh + (small ? norb * norb : 0));
     if (STAGE) {
         for (int t = threadIdx.x; t < len; t += blockDim.x)
 #pragma unroll
             for (int v = 0; v < NV; ++v) lrow[t * NV + v] = (v < nv) ? c[v * ldc + base + t] : 0.0;
+        if (small)
+            for (int t = threadIdx.x; t < norb * norb; t += blockDim.x) {
+                lh[t] = hs[t];
+                lp[t] = A.bpidx[t];
+            }
         __syncthreads();
     }
-    auto row = [&](int j, int v) -> double {
-        return STAGE ? lrow[j * NV + v] : (v < nv ? c[v * ldc + base + j] : 0.0);
-    };
-    const int *bpx = A.bpidx;
+    const int *bpx = small ? lp : A.bpidx;
+    const double *hh = small ? lh : hs;
     for (int ib = threadIdx.x; ib < len; ib += blockDim.x) {
         const uint32_t bs = A.bstr[ib];
         const int y = bs & 0xff, b = (bs >> 8) & 0xff;
@@ -530,22 +644,19 @@ __global__ __launch_bounds__(256) void k_onebody_b(SigmaArgs A, int nv, const do
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         for (int s = 0; s < norb; ++s) {
-            const double hb = hs[b * norb + s], hy = hs[y * norb + s];
-            if (hb != 0.0 && s != y) {
-                const int j = bpx[y * norb + s];
-                if (j >= 0 && j < len) {
-                    const double f = (s > y) ? hb : -hb;
+            const double hb = hh[b * norb + s], hy = hh[y * norb + s];
+            const int j1 = (hb != 0.0 && s != y) ? bpx[y * norb + s] : -1;
+            const int j2 = (hy != 0.0 && s != b) ? bpx[b * norb + s] : -1;
+            const double f1 = (s > y) ? hb : -hb, f2 = (s > b) ? -hy : hy;
+            if (j1 >= 0 && j1 < len) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += f * row(j, v);
-                }
+                for (int v = 0; v < NV; ++v)
+                    acc[v] += f1 * (STAGE ? lrow[j1 * NV + v] : (v < nv ? c[v * ldc + base + j1] : 0.0));
             }
-            if (hy != 0.0 && s != b) {
-                const int j = bpx[b * norb + s];
-                if (j >= 0 && j < len) {
-                    const double f = (s > b) ? -hy : hy;
+            if (j2 >= 0 && j2 < len) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += f * row(j, v);
-                }
+                for (int v = 0; v < NV; ++v)
+                    acc[v] += f2 * (STAGE ? lrow[j2 * NV + v] : (v < nv ? c[v * ldc + base + j2] : 0.0));
             }
         }
         double *dst = sg + base + ib;
@@ -631,8 +742,12 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                 const int nu = nv - u0 < 4 ? nv - u0 : 4;
                 if (c->nquad > 0) {
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
-                    k_sigma_ab_mfma<4><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                 ss + (int64_t)u0 * lds, lds);
+                    if (c->norb <= kTabMax)
+                        k_sigma_ab_mfma<4, true><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                           ss + (int64_t)u0 * lds, lds);
+                    else
+                        k_sigma_ab_mfma<4, false><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                            ss + (int64_t)u0 * lds, lds);
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
                 }
             }
@@ -646,7 +761,8 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                     for (int up = 1; up >= 0; --up)
                         k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
                                                            ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
-                    const size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
+                    size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
+                    if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
                     if (shm <= 65536)
                         k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
                             A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
