@@ -112,10 +112,13 @@ def main():
     isci.isci_profile(hd, False)
     # algorithmic flops each kernel performs per step (2 per sigma term per vector)
     terms_1b = int(tb[0:8].sum())
+    terms_vv = int(tb[41])       # alpha-beta units with all four orbitals virtual
+    vv_split = "k_vv_unfold+k_ab_vv" in prof
     kflops = {"k_sigma_generic": 2.0 * terms * nvec, "k_sigma_n2": 2.0 * terms * nvec,
-              "k_sigma_ab_mfma": 2.0 * terms_ab * nvec,
+              "k_sigma_ab_mfma": 2.0 * (terms_ab - (terms_vv if vv_split else 0)) * nvec,
               "k_sigma_n2(same-spin)": 2.0 * (terms_rest - terms_1b) * nvec,
-              "k_onebody_a+b": 2.0 * terms_1b * nvec}
+              "onebody": 2.0 * terms_1b * nvec,
+              "k_vv_unfold+k_ab_vv": 2.0 * terms_vv * nvec}
     kernels = {}
     for name, (tot_ms, nl) in prof.items():
         per_launch_ms = tot_ms / nl
@@ -158,7 +161,8 @@ def main():
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
         "wall_s_timed": wall,
-        "roofline": {"bound": "mfma" if kname == "k_sigma_ab_mfma" else "alu", "kernel": kname,
+        "roofline": {"bound": "alu" if kname in ("k_sigma_generic", "k_sigma_n2", "k_sigma_n2(same-spin)") else "mfma",
+                     "kernel": kname,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "launches_per_step": nlaunch,
@@ -307,7 +311,8 @@ def bench_served(a):
     ex = GpuExecutor()
     srv = Server(ex, hbm_budget=int(a.hbm_budget_gb * 2**30), max_slots=64)
     t0 = time.perf_counter()
-    srv.run(reqs, max_wall=a.max_wall)
+    srv.run(reqs, max_wall=a.max_wall,
+            progress=lambda r: print("served progress", json.dumps(r), file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     rep = srv.report()
     done = [r for r in srv.done if r.status == "done"]

@@ -231,7 +231,7 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_SIGMA_AUTO 0
 #define ISCI_SIGMA_GENERAL 1
 #define ISCI_SIGMA_PAIR 2
-#define ISCI_SIGMA_MFMA 3   /* pair kernel for one-body / same-spin + FP64 MFMA tiles for alpha-beta */
+#define ISCI_SIGMA_MFMA 3   /* FP64 matrix cores for the alpha-beta and one-body classes, pair kernel for same-spin */
 isci_status isci_set_option(isci_handle hd, int option, int value);
 
 /* Kernel timing hook (for measurement).  When enabled, HIP events are
@@ -243,7 +243,10 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
 #define ISCI_KERNEL_PAIR 1      /* k_sigma_n2: all classes, two electrons per spin */
 #define ISCI_KERNEL_AB_MFMA 2   /* k_sigma_ab_mfma: alpha-beta class on matrix cores */
 #define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
-#define ISCI_KERNEL_ONEBODY 4   /* k_onebody_a + k_onebody_b: one-body classes, two electrons per spin */
+#define ISCI_KERNEL_ONEBODY 4   /* one-body classes, two electrons per spin (matrix-core products, or
+                                   k_onebody_a + k_onebody_b above 80 orbitals) */
+#define ISCI_KERNEL_AB_VV 5     /* k_vv_unfold + k_ab_vv: all-virtual alpha-beta units as a block-sparse
+                                   product on matrix cores (two electrons per spin, L >= 2) */
 isci_status isci_profile(isci_handle hd, int enable);
 isci_status isci_profile_read(isci_handle hd, int kernel, double *total_ms, int64_t *launches);
 

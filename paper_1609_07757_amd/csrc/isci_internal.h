@@ -12,7 +12,7 @@
 #define ISCI_MAXN 4          // electrons per spin handled by the kernels
 #define ISCI_MAXNORB 255     // orbitals fit in one byte
 #define ISCI_MAXLEV 8        // level tables sized for 2 * ISCI_MAXN
-#define ISCI_NKERNEL_IDS 5   // ISCI_KERNEL_* ids of the timing hook
+#define ISCI_NKERNEL_IDS 6   // ISCI_KERNEL_* ids of the timing hook
 
 namespace isci {
 
@@ -77,6 +77,15 @@ struct DevTabs {
     long long *arow_base = nullptr;
     int *arow_len = nullptr;
     int *chunk_cls = nullptr;       // [nblk*nblk][3] chunks per source level class
+    // all-virtual alpha-beta units (vv|vv) as a product with an unfolded
+    // copy of the CI block: target tiles with both active blocks virtual,
+    // column offset of each spectator block pair ([nblk][nblk], -1 when the
+    // pair is above the level cut), packed (x, y, v) per column, and the
+    // unfolded operand T[(q, s)][column] (q, s virtual; rewritten per call)
+    uchar4 *vv_quads = nullptr;
+    int *vv_gofs = nullptr;
+    int *vv_col = nullptr;
+    double *vv_T = nullptr;
 };
 
 struct SigmaArgs {
@@ -104,6 +113,12 @@ struct SigmaArgs {
     const long long *arow_base;
     const int *arow_len;
     const int *chunk_cls;
+    int vv_split;            // alpha-beta MFMA kernel skips the vv|vv chunks (done by the product path)
+    const uchar4 *vv_quads;
+    const int *vv_gofs;
+    const int *vv_col;
+    double *vv_T;
+    int vv_ncol, vv_ks;      // columns of T; padded virtual count (row (q, s) = (q - 2) * vv_ks + s - 2)
 };
 
 // One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)
@@ -136,6 +151,8 @@ struct isci_ctx {
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int nblk = 0, nchunk = 0, nquad = 0;
+    int nvvquad = 0, vv_ncol = 0, vv_krows = 0, vv_ks = 0;
+    bool have_vv = false;
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
     // optional per-kernel timing: HIP events recorded around each launch on
@@ -170,6 +187,14 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
 // records a start (begin=true) or stop event for kernel id `k` when profiling
 isci_status prof_mark(const isci_ctx *c, int k, bool begin, hipStream_t s);
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
+// vv|vv alpha-beta units as unfold + block-sparse product (adds into sigma)
+isci_status launch_ab_vv(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
+                         hipStream_t s);
+// one-body classes on matrix cores (two electrons per spin, norb <= kObMaxNorb)
+constexpr int kObMaxNorb = 80;
+bool onebody_mfma_ok(const isci_ctx *c);
+isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
+                                hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

@@ -413,6 +413,13 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.arow_base = c->d.arow_base;
     A.arow_len = c->d.arow_len;
     A.chunk_cls = c->d.chunk_cls;
+    A.vv_split = c->have_vv ? 1 : 0;
+    A.vv_quads = c->d.vv_quads;
+    A.vv_gofs = c->d.vv_gofs;
+    A.vv_col = c->d.vv_col;
+    A.vv_T = c->d.vv_T;
+    A.vv_ncol = c->vv_ncol;
+    A.vv_ks = c->vv_ks;
     return A;
 }
 
@@ -539,6 +546,61 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     ISCI_HIP(hipStreamSynchronize(s));
     c->nchunk = tot;
     c->have_tiles = true;
+    return ISCI_OK;
+}
+
+// vv|vv product path: needs virtual blocks on both spins and an unfolded
+// operand of bounded size (the vectors of one pass: four)
+static constexpr size_t kVvMaxBytes = (size_t)2 << 30;
+
+static isci_status build_vv(isci_ctx *c, hipStream_t s)
+{
+    const int n = c->norb, nb = c->nblk, L = c->L;
+    if (L < 2 || nb < 2) return ISCI_OK;
+    auto width = [](int B) { return B == 0 ? 2 : 4; };
+    std::vector<int> gofs((size_t)nb * nb, -1);
+    std::vector<int> col;
+    for (int C = 0; C < nb; ++C)
+        for (int D = 0; D < nb; ++D) {
+            if ((C != 0) + (D != 0) > L - 2) continue;
+            gofs[(size_t)C * nb + D] = (int)col.size();
+            for (int ic = 0; ic < width(C); ++ic)
+                for (int id = 0; id < width(D); ++id) {
+                    const int x = C == 0 ? ic : 2 + 4 * (C - 1) + ic;
+                    const int y = D == 0 ? id : 2 + 4 * (D - 1) + id;
+                    for (int v = 0; v < 4; ++v)
+                        col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
+                }
+        }
+    const int ks = 4 * (nb - 1);
+    const int krows = (n - 2) * ks;
+    const size_t tbytes = sizeof(double) * (size_t)krows * col.size();
+    if (tbytes == 0 || tbytes > kVvMaxBytes) return ISCI_OK;
+    std::vector<uchar4> vq;
+    for (int X = 0; X < nb; ++X)
+        for (int P = std::max(X, 1); P < nb; ++P)
+            for (int Y = 0; Y < nb; ++Y)
+                for (int R = std::max(Y, 1); R < nb; ++R) {
+                    const int lev = (X != 0) + 1 + (Y != 0) + 1;
+                    if (lev > L) continue;
+                    vq.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
+                }
+    DevTabs &d = c->d;
+    d.vv_quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, vq.size()));
+    d.vv_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
+    d.vv_col = (int *)dev_alloc(c, sizeof(int) * col.size());
+    d.vv_T = (double *)dev_alloc(c, tbytes);
+    if (!d.vv_quads || !d.vv_gofs || !d.vv_col || !d.vv_T) { set_error("device allocation failed (vv)"); return ISCI_E_OOM; }
+    if (!vq.empty())
+        ISCI_HIP(hipMemcpyAsync(d.vv_quads, vq.data(), sizeof(uchar4) * vq.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.vv_gofs, gofs.data(), sizeof(int) * gofs.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.vv_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
+    c->nvvquad = (int)vq.size();
+    c->vv_ncol = (int)col.size();
+    c->vv_krows = krows;
+    c->vv_ks = ks;
+    c->have_vv = true;
     return ISCI_OK;
 }
 
@@ -807,6 +869,7 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
         st = build_tiles(c, eri, stream);
+        if (st == ISCI_OK) st = build_vv(c, stream);
         if (st == ISCI_OK) st = build_hscreen(c, h, stream);
         if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }

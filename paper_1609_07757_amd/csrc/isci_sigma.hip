@@ -452,7 +452,10 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
         const int row = Ab * nb + Bb;
         const int e0 = A.chunk_off[row];
         int e1 = e0;
-        for (int l = 0; l < 3; ++l)
+        // with the vv|vv product path, all-virtual chunks (class 2 of a
+        // virtual row block pair) are left to it
+        const int lmax = (A.vv_split && Ab != 0 && Bb != 0) ? 1 : 2;
+        for (int l = 0; l <= lmax; ++l)
             if (espec + l <= L) e1 += A.chunk_cls[row * 3 + l];
         int e = e0;
         for (; e + 4 <= e1; e += 4) {
@@ -750,27 +753,37 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                                                                             ss + (int64_t)u0 * lds, lds);
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
                 }
+                if (c->have_vv) {
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_VV, true, s));
+                    ISCI_CHECK(launch_ab_vv(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_VV, false, s));
+                }
             }
             if (c->d.hscreen) {
-                // one-body alpha (two launches: spectator below / above the
-                // active orbital), one-body beta, then same-spin if any
+                // one-body classes (matrix cores when the orbital count allows,
+                // else alpha in two launches by spectator side, then beta),
+                // then same-spin if any
                 ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
-                const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
-                for (int u0 = 0; u0 < nv; u0 += 4) {
-                    const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                    for (int up = 1; up >= 0; --up)
-                        k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                           ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
-                    size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
-                    if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
-                    if (shm <= 65536)
-                        k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
-                            A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
-                    else
-                        k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
-                            A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                if (onebody_mfma_ok(c)) {
+                    ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
+                } else {
+                    const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
+                    for (int u0 = 0; u0 < nv; u0 += 4) {
+                        const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                        for (int up = 1; up >= 0; --up)
+                            k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                               ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
+                        size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
+                        if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
+                        if (shm <= 65536)
+                            k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
+                                A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                        else
+                            k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
+                                A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                    }
+                    ISCI_HIP(hipGetLastError());
                 }
-                ISCI_HIP(hipGetLastError());
                 ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
                 if (c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
             }

@@ -160,14 +160,19 @@ class Server:
                 self.used -= b
                 self.done.append(r)
 
-    def run(self, requests, max_wall: float | None = None):
-        """Serve `requests` (sorted by arrival).  Returns the finished list."""
+    def run(self, requests, max_wall: float | None = None, progress=None, progress_every: float = 10.0):
+        """Serve `requests` (sorted by arrival).  Returns the finished list.
+        `progress(report)` is called about every `progress_every` seconds."""
         if self.clock is None:
             self.clock = time.perf_counter
         self._t0 = self.clock()
         pending = deque(sorted(requests, key=lambda r: r.arrival))
+        next_report = progress_every
         while pending or self.queue or self.running:
             now = self._now()
+            if progress is not None and now >= next_report:
+                progress(dict(self.report(), t=now, queued=len(self.queue), running=len(self.running)))
+                next_report = now + progress_every
             if max_wall is not None and now > max_wall:
                 break
             while pending and pending[0].arrival <= now:

@@ -42,6 +42,8 @@ CASES = [
     ("R", 4, 4, 4, 8, 0.0, 1),     # no virtual orbitals
     ("B", 20, 2, 2, 2, 1e-14, 1),  # CISD 20 orbitals, recipe B
     ("B", 16, 2, 2, 3, 1e-12, 17),
+    ("B", 26, 2, 2, 3, 1e-12, 2),  # 26 orbitals: two 16-orbital tiles, ragged
+    ("A", 72, 2, 2, 2, 1e-12, 3),  # 72 orbitals: five 16-orbital tiles
 ]
 
 
