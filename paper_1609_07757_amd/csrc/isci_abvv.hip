@@ -7,12 +7,16 @@
 // (zero when {x,q} or {y,s} is not a string, or the determinant lies above
 // the excitation cut).  The vv|vv part of the alpha-beta class is
 //   S[(p, r)][(x, y, v)] = sum_{q,s virtual} (pq|rs) T[(q, s)][(x, y, v)]
-// combined over the four spectator roles of a target determinant exactly
-// as in the gathered kernel (T'[x][p][y][r] = S[x][p][y][r] - S[p][x][y][r]
-// - S[x][p][r][y] + S[p][x][r][y]).  The unfold kernel writes T once per
+// combined over the four spectator roles of a target determinant
+// (T'[x][p][y][r] = S[x][p][y][r] - S[p][x][y][r] - S[x][p][r][y]
+// + S[p][x][r][y], S indexed [alpha spectator][alpha active][beta
+// spectator][beta active]).  The unfold kernel writes T once per
 // call (columns: spectator block pair, slots, four vectors), so the
 // product reads contiguous 16-column operand rows instead of scattered CI
 // elements, and the four vectors of a pass share every integral chunk.
+// The product writes S for every virtual row block pair and column (a
+// balanced block-sparse GEMM), then a fold adds the four role readings of
+// each target determinant into sigma.
 //
 // Rows (q, s) of T: (q - 2) * ks + (s - 2), s padded to whole blocks of
 // four (padding rows are zero).  Column groups: spectator block pair (C, D)
@@ -58,103 +62,120 @@ __device__ __forceinline__ int vv_orbital(int B, int i, int norb)
 
 __device__ __forceinline__ int vv_slots(int B) { return B == 0 ? 2 : 4; }
 
-// One workgroup per target tile (X, P, Y, R), P and R virtual blocks; wave
-// w computes spectator role w: rows = the 16 active pairs of its row block,
-// columns = its spectator group (1, 2 or 4 N tiles), K = the vv|vv chunks
-// of the row block (4 columns (q, s) each).  Roles are combined in LDS.
-__global__ __launch_bounds__(256) void k_ab_vv(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds)
+// S = W T for one virtual row block pair (P, R) (16 rows (p, r)) and 256
+// columns (blockIdx.y): wave w takes four 16-column N tiles; K runs over the
+// vv|vv chunks of the row block.  S rows are (p - 2) * ks + (r - 2) like T's.
+__global__ __launch_bounds__(256) void k_vv_gemm(SigmaArgs A)
 {
-    __shared__ double tile[4][16][65];
-    const uchar4 qd = A.vv_quads[blockIdx.x];
-    const int X = qd.x, P = qd.y, Y = qd.z, R = qd.w;
+    const int nb = A.nblk, ncol = A.vv_ncol, ks = A.vv_ks;
+    const int P = 1 + blockIdx.x / (nb - 1), R = 1 + blockIdx.x % (nb - 1);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool sameA = X == P, sameB = Y == R;
-    const int norb = A.norb, nb = A.nblk, ncol = A.vv_ncol;
-    int Ab, Bb, Cb, Db;
-    bool active;
-    if (wave == 0) { Ab = P; Bb = R; Cb = X; Db = Y; active = true; }
-    else if (wave == 1) { Ab = X; Bb = R; Cb = P; Db = Y; active = !sameA; }
-    else if (wave == 2) { Ab = P; Bb = Y; Cb = X; Db = R; active = !sameB; }
-    else { Ab = X; Bb = Y; Cb = P; Db = R; active = !sameA && !sameB; }
-    active = active && Ab != 0 && Bb != 0;
-    const int g0 = A.vv_gofs[Cb * nb + Db];
-    active = active && g0 >= 0;
-    const int ntile = vv_slots(Cb) * vv_slots(Db) / 4;   // 16-column tiles of the group
+    const int c0 = blockIdx.y * 256 + wave * 64;
+    if (c0 >= ncol) return;
+    const int row = P * nb + R;
+    const int e0 = A.chunk_off[row] + A.chunk_cls[row * 3] + A.chunk_cls[row * 3 + 1];
+    const int e1 = A.chunk_off[row + 1];
+    const int k = lane >> 4, n = lane & 15;
+    const int ntile = min(4, (ncol - c0) / 16);   // ncol is a multiple of 16
+    const double *Tb = A.vv_T + (size_t)k * ncol + c0 + n;
     v4d_vv acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = v4d_vv{0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        const int row = Ab * nb + Bb;
-        const int e0 = A.chunk_off[row] + A.chunk_cls[row * 3] + A.chunk_cls[row * 3 + 1];
-        const int e1 = A.chunk_off[row + 1];
-        const int k = lane >> 4, n = lane & 15;
-        const double *Tb = A.vv_T + g0 + n;
-        auto krow = [&](int e) {
-            const int2 dsc = A.chunk_desc[e];
-            return (size_t)((dsc.x - 2) * A.vv_ks + 4 * (dsc.y - 1) + k) * ncol;
-        };
-        double a_c = 0.0, b_c[4] = {0.0, 0.0, 0.0, 0.0};
-        if (e0 < e1) {
-            const size_t r0 = krow(e0);
-            a_c = A.chunk_val[(size_t)e0 * 64 + lane];
+    // two stages of two chunks each, ping-ponged so that the loads of one
+    // stage are in flight while the MFMAs of the other issue (no register
+    // copies, which would wait for the loads)
+    double ax[2], bx[2][4], ay[2], by[2][4];
+    auto load2 = [&](int e, double *a, double (*b)[4]) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (t < ntile) b_c[t] = Tb[r0 + 16 * t];
-        }
-        for (int e = e0; e < e1; ++e) {
-            double a_n = 0.0, b_n[4] = {0.0, 0.0, 0.0, 0.0};
-            if (e + 1 < e1) {
-                const size_t r1 = krow(e + 1);
-                a_n = A.chunk_val[(size_t)(e + 1) * 64 + lane];
+        for (int u = 0; u < 2; ++u) {
+            a[u] = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[u][t] = 0.0;
+            if (e + u < e1) {
+                const double *src = Tb + (size_t)A.vv_trow[e + u] * ncol;
+                a[u] = A.chunk_val[(size_t)(e + u) * 64 + lane];
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    if (t < ntile) b_n[t] = Tb[r1 + 16 * t];
+                    if (t < ntile) b[u][t] = src[16 * t];
             }
+        }
+    };
+    auto mma2 = [&](const double *a, const double (*b)[4]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_c, b_c[t], acc[t], 0, 0, 0);
-            a_c = a_n;
+                if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+    };
+    load2(e0, ax, bx);
+    for (int e = e0; e < e1; e += 4) {
+        load2(e + 2, ay, by);
+        mma2(ax, bx);
+        if (e + 4 < e1) load2(e + 4, ax, bx);
+        mma2(ay, by);
+    }
+    // element g of lane l is row 4 g + l / 16 = (p slot g, r slot l / 16), column l % 16
+    double *Sb = A.vv_S + ((size_t)(4 * (P - 1)) * ks + 4 * (R - 1) + k) * ncol + c0 + n;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b_c[t] = b_n[t];
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < ntile) Sb[(size_t)g * ks * ncol + 16 * t] = acc[t][g];
+}
+
+// sigma({a < b}, {c < d}) += the vv|vv part, from S: every way of reading
+// the target as (alpha spectator, alpha active virtual) x (beta spectator,
+// beta active virtual) with the spectator pair in a column group,
+// sign + for (a, b) / (c, d) spectator-first, - per swapped spin.
+__global__ __launch_bounds__(256) void k_vv_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds)
+{
+    const int ia = blockIdx.x;
+    const int jb = blockIdx.y * 256 + threadIdx.x;
+    const int L = A.L;
+    const int len = A.sb.le[L - A.alev[ia]];
+    if (jb >= len) return;
+    const int norb = A.norb, nb = A.nblk, ncol = A.vv_ncol, ks = A.vv_ks;
+    const uint32_t as = A.astr[ia], bs = A.bstr[jb];
+    const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
+    if (a1 < 2 || b1 < 2) return;   // no virtual active orbital on one spin
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool any = false;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra) {
+        const int xs = ra ? a1 : a0, xa = ra ? a0 : a1;   // alpha spectator, active
+        if (xa < 2) continue;
+        const int C = xs < 2 ? 0 : 1 + (xs - 2) / 4, ic = xs < 2 ? xs : (xs - 2) % 4;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int ys = rb ? b1 : b0, ya = rb ? b0 : b1;
+            if (ya < 2) continue;
+            const int D = ys < 2 ? 0 : 1 + (ys - 2) / 4, id = ys < 2 ? ys : (ys - 2) % 4;
+            const int g = A.vv_gofs[C * nb + D];
+            if (g < 0) continue;
+            const int wD = D == 0 ? 2 : 4;
+            const double *src = A.vv_S + (size_t)((xa - 2) * ks + (ya - 2)) * ncol + g + (ic * wD + id) * 4;
+            const double f = (ra ^ rb) ? -1.0 : 1.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += f * src[v];
+            any = true;
         }
     }
-    // 16x16x4 f64 result: element g of lane l is D[4 g + l / 16][l % 16]
+    if (!any) return;
+    double *dst = sg + A.rowstart[ia] + jb;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) tile[wave][4 * g + (lane >> 4)][16 * t + (lane & 15)] = acc[t][g];
-    __syncthreads();
-    // combine the roles: target slots (ix, ip, iy, ir) and vector v
-    const int t1 = sameA ? 0 : 1, t2 = sameB ? 0 : 2;
-    const int t3 = (sameA && sameB) ? 0 : sameA ? 2 : sameB ? 1 : 3;
-    const int wX = vv_slots(X), wP = vv_slots(P), wY = vv_slots(Y), wR = vv_slots(R);
-    for (int t = threadIdx.x; t < 1024; t += 256) {
-        const int v = t & 3, ir = (t >> 2) & 3, iy = (t >> 4) & 3, ip = (t >> 6) & 3, ix = t >> 8;
-        if (v >= nv || ix >= wX || ip >= wP || iy >= wY || ir >= wR) continue;
-        const int x = vv_orbital(X, ix, norb), p = vv_orbital(P, ip, norb);
-        const int y = vv_orbital(Y, iy, norb), r = vv_orbital(R, ir, norb);
-        if (x < 0 || p < 0 || y < 0 || r < 0 || x >= p || y >= r) continue;
-        const long long tb = A.arow_base[x * norb + p];
-        const int tl = A.arow_len[x * norb + p];
-        const int jb = A.bpidx[y * norb + r];
-        if (tb < 0 || jb < 0 || jb >= tl) continue;
-        // row = (alpha active slot) * 4 + beta active slot; column =
-        // ((alpha spectator slot) * slots(beta spectator block) + beta spectator slot) * 4 + v
-        const double s0 = tile[0][ip * 4 + ir][(ix * wY + iy) * 4 + v];
-        const double s1 = tile[t1][ix * 4 + ir][(ip * wY + iy) * 4 + v];
-        const double s2 = tile[t2][ip * 4 + iy][(ix * wR + ir) * 4 + v];
-        const double s3 = tile[t3][ix * 4 + iy][(ip * wR + ir) * 4 + v];
-        sg[(int64_t)v * lds + tb + jb] += s0 - s1 - s2 + s3;
-    }
+    for (int v = 0; v < 4; ++v)
+        if (v < nv) dst[(int64_t)v * lds] += acc[v];
 }
 
 isci_status launch_ab_vv(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
                          hipStream_t st)
 {
-    if (!cx->have_vv || cx->nvvquad == 0) return ISCI_OK;
+    if (!cx->have_vv) return ISCI_OK;
     const SigmaArgs A = sigma_args(cx);
+    const int nb = cx->nblk;
     k_vv_unfold<<<dim3((unsigned)((cx->vv_ncol + 255) / 256), (unsigned)cx->vv_krows), 256, 0, st>>>(A, nv, c, ldc);
-    k_ab_vv<<<(unsigned)cx->nvvquad, 256, 0, st>>>(A, nv, s, lds);
+    k_vv_gemm<<<dim3((unsigned)((nb - 1) * (nb - 1)), (unsigned)((cx->vv_ncol + 255) / 256)), 256, 0, st>>>(A);
+    k_vv_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, s, lds);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }

@@ -10,6 +10,7 @@
 
 namespace isci {
 
+
 // C(x, k) for 0 <= k <= 4 (exact: each partial product is a binomial).
 __host__ __device__ inline long long binom(int x, int k)
 {

@@ -78,14 +78,16 @@ struct DevTabs {
     int *arow_len = nullptr;
     int *chunk_cls = nullptr;       // [nblk*nblk][3] chunks per source level class
     // all-virtual alpha-beta units (vv|vv) as a product with an unfolded
-    // copy of the CI block: target tiles with both active blocks virtual,
-    // column offset of each spectator block pair ([nblk][nblk], -1 when the
-    // pair is above the level cut), packed (x, y, v) per column, and the
-    // unfolded operand T[(q, s)][column] (q, s virtual; rewritten per call)
-    uchar4 *vv_quads = nullptr;
+    // copy of the CI block: column offset of each spectator block pair
+    // ([nblk][nblk], -1 when the pair is above the level cut), packed
+    // (x, y, v) per column, T row of each chunk ((q - 2) * ks + 4 (S - 1);
+    // -1 outside the vv|vv chunks), the unfolded operand T[(q, s)][column]
+    // and the product S[(p, r)][column] (both rewritten per call)
     int *vv_gofs = nullptr;
     int *vv_col = nullptr;
+    int *vv_trow = nullptr;
     double *vv_T = nullptr;
+    double *vv_S = nullptr;
 };
 
 struct SigmaArgs {
@@ -114,10 +116,10 @@ struct SigmaArgs {
     const int *arow_len;
     const int *chunk_cls;
     int vv_split;            // alpha-beta MFMA kernel skips the vv|vv chunks (done by the product path)
-    const uchar4 *vv_quads;
     const int *vv_gofs;
     const int *vv_col;
-    double *vv_T;
+    const int *vv_trow;
+    double *vv_T, *vv_S;
     int vv_ncol, vv_ks;      // columns of T; padded virtual count (row (q, s) = (q - 2) * vv_ks + s - 2)
 };
 
@@ -151,7 +153,7 @@ struct isci_ctx {
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int nblk = 0, nchunk = 0, nquad = 0;
-    int nvvquad = 0, vv_ncol = 0, vv_krows = 0, vv_ks = 0;
+    int vv_ncol = 0, vv_krows = 0, vv_ks = 0;
     bool have_vv = false;
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;

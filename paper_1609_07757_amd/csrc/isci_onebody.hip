@@ -178,51 +178,37 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const dou
     }
 }
 
-// Alpha class, spectator x = blockIdx.x, beta columns blockIdx.y * 256 +
-// [0, 256) (64 per wave, four 16-column N tiles), vector blockIdx.z; targets
-// a > x (up = 1) or a < x (up = 0).  Columns run to jlim(x): every row
-// {q, x} is long enough for them to matter only up to there (for x virtual
-// the rows {q, x} with q virtual stop at level-2 length; the rest is the
-// two-term tail below).  h sits in LDS; the B operand of the next K step
-// is loaded before the MFMAs of the current one.
+// Alpha class, spectator x = blockIdx.x, beta columns blockIdx.y * 64 +
+// [0, 64) (four 16-column N tiles), vector blockIdx.z; wave w computes the
+// targets a in [16 w, 16 w + 16) with a > x (up = 1) or a < x (up = 0).
+// Columns run to jlim(x): for x virtual the rows {q, x} with q virtual stop
+// at the level-2 row length, the columns above reach only {0,x} and {1,x}
+// (the two-term tail below).  The operands of the next K step are in
+// flight while the MFMAs of the current one issue.
 template <int NT>
-__global__ __launch_bounds__(256) void k_ob_alpha(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
-                                                  double *__restrict__ sg, int64_t lds,
-                                                  const double *__restrict__ hs, int up, int jlim_occ,
-                                                  int jlim_virt)
+__global__ __launch_bounds__(64 * NT) void k_ob_alpha(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                      double *__restrict__ sg, int64_t lds,
+                                                      const double *__restrict__ hs, int up, int jlim_occ,
+                                                      int jlim_virt)
 {
     constexpr int NP = 16 * NT;
-    __shared__ double hl[NP * NP];   // hl[q * NP + a] = h[q][a]
     const int x = blockIdx.x, v = blockIdx.z;
     const int norb = A.norb;
     const int jlim = x < 2 ? jlim_occ : jlim_virt;
-    const int jb = blockIdx.y * 256;
-    if (jb >= jlim) return;
-    for (int t = threadIdx.x; t < NP * NP; t += 256) {
-        const int q = t / NP, a = t - q * NP;
-        hl[t] = (q < norb && a < norb) ? hs[q * norb + a] : 0.0;
-    }
-    __syncthreads();
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j0 = jb + 64 * w;
+    const int j0 = blockIdx.y * 64;
     if (j0 >= jlim) return;
+    const int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long *__restrict__ rb = A.arow_base + x * norb;
     const int *__restrict__ rl = A.arow_len + x * norb;
-    // targets {a, x} on this side of x holding a column of the wave's
-    // range, and sources {q, x} holding one
+    // this wave's targets {a, x} on the requested side of x that hold a
+    // column of the block, and the sources {q, x} that hold one
+    const int at = 16 * mt + (lane & 15);
+    const bool tok = lane < 16 && at < norb && at != x && ((at > x) == (up != 0)) && rl[at] > j0;
+    if (__ballot(tok) == 0) return;
     const int o1 = lane, o2 = lane + 64;
-    const bool t1 = o1 < norb && o1 != x && ((o1 > x) == (up != 0)) && rl[o1] > j0;
-    const bool t2 = o2 < NP && o2 < norb && o2 != x && ((o2 > x) == (up != 0)) && rl[o2] > j0;
     const bool s1 = o1 < norb && o1 != x && rl[o1] > j0;
     const bool s2 = o2 < NP && o2 < norb && o2 != x && rl[o2] > j0;
-    const unsigned long long tm0 = __ballot(t1), tm1 = __ballot(t2);
     const unsigned long long sm0 = __ballot(s1), sm1 = __ballot(s2);
-    if ((tm0 | tm1) == 0 || (sm0 | sm1) == 0) return;
-    bool mt_on[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-        mt_on[mt] = mt < 4 ? ((tm0 >> (16 * mt)) & 0xffffull) != 0 : ((tm1 >> (16 * (mt - 4))) & 0xffffull) != 0;
-    // active K steps (4 sources each)
     unsigned km = 0;
 #pragma unroll
     for (int ks = 0; ks < NP / 4; ++ks) {
@@ -231,62 +217,60 @@ __global__ __launch_bounds__(256) void k_ob_alpha(SigmaArgs A, const double *__r
     }
     const int n = lane & 15, kq = lane >> 4;
     const double *cv = c + (int64_t)v * ldc;
-    auto load_b = [&](int ks, double *b) {
+    auto next_ks = [&]() {
+        if (!km) return -1;
+        const int k = __ffs(km) - 1;
+        km &= km - 1;
+        return k;
+    };
+    auto load = [&](int ks, double &a, double *b) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) b[nt] = 0.0;
+        a = 0.0;
+        if (ks < 0) return;
         const int q = 4 * ks + kq;
-        long long base = -1;
-        int len = 0;
-        if (q < norb && q != x) {
-            base = rb[q];
-            len = rl[q];
-        }
+        a = hpad(hs, norb, 16 * mt + n, q);
+        if (q >= norb || q == x) return;
+        const long long base = rb[q];
+        const int len = min(rl[q], jlim);
+        if (base < 0) return;
         const double f = q < x ? 1.0 : -1.0;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int j = j0 + 16 * nt + n;
-            b[nt] = (base >= 0 && j < len && j < jlim) ? f * cv[base + j] : 0.0;
+            if (j < len) b[nt] = f * cv[base + j];
         }
     };
-    v4d_ob acc[NT][4];
+    v4d_ob acc[4];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
+    // two K steps in flight: stages x and y ping-pong (no register copies)
+    double ax, bx[4], ay, by[4];
+    int kx = next_ks();
+    load(kx, ax, bx);
+    while (kx >= 0) {
+        const int ky = next_ks();
+        load(ky, ay, by);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
-    double bc[4], bn[4];
-    int ks = __ffs(km) - 1;
-    km &= km - 1;
-    load_b(ks, bc);
-    while (ks >= 0) {
-        const int kn = km ? __ffs(km) - 1 : -1;
-        km &= km - 1;
-        if (kn >= 0) load_b(kn, bn);
-        const int q = 4 * ks + kq;
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ax, bx[nt], acc[nt]);
+        if (ky < 0) break;
+        kx = next_ks();
+        load(kx, ax, bx);
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-            if (!mt_on[mt]) continue;
-            const double a = hl[q * NP + 16 * mt + n];
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma16(a, bc[nt], acc[mt][nt]);
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
-        ks = kn;
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ay, by[nt], acc[nt]);
     }
     double *sv = sg + (int64_t)v * lds;
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-        if (!mt_on[mt]) continue;
+    for (int g = 0; g < 4; ++g) {
+        const int a = 16 * mt + 4 * g + kq;
+        if (a >= norb || a == x || ((a > x) != (up != 0))) continue;
+        const long long base = rb[a];
+        if (base < 0) continue;
+        const int len = min(rl[a], jlim);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int a = 16 * mt + 4 * g + kq;
-            if (a >= norb || a == x || ((a > x) != (up != 0))) continue;
-            const long long base = rb[a];
-            const int len = rl[a];
-            if (base < 0) continue;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int j = j0 + 16 * nt + n;
-                if (j < len && j < jlim) sv[base + j] += a < x ? acc[mt][nt][g] : -acc[mt][nt][g];
-            }
+        for (int nt = 0; nt < 4; ++nt) {
+            const int j = j0 + 16 * nt + n;
+            if (j < len) sv[base + j] += a < x ? acc[nt][g] : -acc[nt][g];
         }
     }
 }
@@ -333,9 +317,9 @@ static isci_status launch_ob_nt(const isci_ctx *cx, const SigmaArgs &A, int nv, 
     const int jlim_occ = le_b[L];
     const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
     const int jtail = L >= 1 ? le_b[L - 1] : 0;
-    const dim3 ga((unsigned)cx->norb, (unsigned)((jlim_occ + 255) / 256), (unsigned)nv);
+    const dim3 ga((unsigned)cx->norb, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
     for (int up = 1; up >= 0; --up)
-        k_ob_alpha<NT><<<ga, 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt);
+        k_ob_alpha<NT><<<ga, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt);
     if (jtail > jlim_virt && cx->norb > 2)
         k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
                           0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);

@@ -414,10 +414,11 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.arow_len = c->d.arow_len;
     A.chunk_cls = c->d.chunk_cls;
     A.vv_split = c->have_vv ? 1 : 0;
-    A.vv_quads = c->d.vv_quads;
     A.vv_gofs = c->d.vv_gofs;
     A.vv_col = c->d.vv_col;
+    A.vv_trow = c->d.vv_trow;
     A.vv_T = c->d.vv_T;
+    A.vv_S = c->d.vv_S;
     A.vv_ncol = c->vv_ncol;
     A.vv_ks = c->vv_ks;
     return A;
@@ -575,28 +576,37 @@ static isci_status build_vv(isci_ctx *c, hipStream_t s)
     const int ks = 4 * (nb - 1);
     const int krows = (n - 2) * ks;
     const size_t tbytes = sizeof(double) * (size_t)krows * col.size();
-    if (tbytes == 0 || tbytes > kVvMaxBytes) return ISCI_OK;
-    std::vector<uchar4> vq;
-    for (int X = 0; X < nb; ++X)
-        for (int P = std::max(X, 1); P < nb; ++P)
-            for (int Y = 0; Y < nb; ++Y)
-                for (int R = std::max(Y, 1); R < nb; ++R) {
-                    const int lev = (X != 0) + 1 + (Y != 0) + 1;
-                    if (lev > L) continue;
-                    vq.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
-                }
+    const size_t sbytes = sizeof(double) * (size_t)ks * ks * col.size();
+    if (tbytes == 0 || tbytes + sbytes > kVvMaxBytes) return ISCI_OK;
+    // T row of each vv|vv chunk (class 2 of a virtual row block pair)
+    std::vector<int> off(nb * nb + 1), cls(3 * nb * nb);
+    std::vector<int2> desc(std::max(1, c->nchunk));
+    ISCI_HIP(hipMemcpyAsync(off.data(), c->d.chunk_off, sizeof(int) * off.size(), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipMemcpyAsync(cls.data(), c->d.chunk_cls, sizeof(int) * cls.size(), hipMemcpyDeviceToHost, s));
+    if (c->nchunk > 0)
+        ISCI_HIP(hipMemcpyAsync(desc.data(), c->d.chunk_desc, sizeof(int2) * c->nchunk, hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipStreamSynchronize(s));
+    std::vector<int> trow(std::max(1, c->nchunk), -1);
+    for (int A = 1; A < nb; ++A)
+        for (int B = 1; B < nb; ++B) {
+            const int g = A * nb + B;
+            for (int e = off[g] + cls[3 * g] + cls[3 * g + 1]; e < off[g + 1]; ++e)
+                trow[e] = (desc[e].x - 2) * ks + 4 * (desc[e].y - 1);
+        }
     DevTabs &d = c->d;
-    d.vv_quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, vq.size()));
     d.vv_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
     d.vv_col = (int *)dev_alloc(c, sizeof(int) * col.size());
+    d.vv_trow = (int *)dev_alloc(c, sizeof(int) * trow.size());
     d.vv_T = (double *)dev_alloc(c, tbytes);
-    if (!d.vv_quads || !d.vv_gofs || !d.vv_col || !d.vv_T) { set_error("device allocation failed (vv)"); return ISCI_E_OOM; }
-    if (!vq.empty())
-        ISCI_HIP(hipMemcpyAsync(d.vv_quads, vq.data(), sizeof(uchar4) * vq.size(), hipMemcpyHostToDevice, s));
+    d.vv_S = (double *)dev_alloc(c, sbytes);
+    if (!d.vv_gofs || !d.vv_col || !d.vv_trow || !d.vv_T || !d.vv_S) {
+        set_error("device allocation failed (vv)");
+        return ISCI_E_OOM;
+    }
     ISCI_HIP(hipMemcpyAsync(d.vv_gofs, gofs.data(), sizeof(int) * gofs.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.vv_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.vv_trow, trow.data(), sizeof(int) * trow.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
-    c->nvvquad = (int)vq.size();
     c->vv_ncol = (int)col.size();
     c->vv_krows = krows;
     c->vv_ks = ks;
