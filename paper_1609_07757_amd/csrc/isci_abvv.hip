@@ -22,6 +22,7 @@
 // four (padding rows are zero).  Column groups: spectator block pair (C, D)
 // with (C virtual) + (D virtual) <= L - 2; the occupied block has two
 // slots, a virtual block four; a group has slots(C) * slots(D) * 4 columns.
+// Zero columns pad the total to a multiple of 64 (one wave's slab).
 #include <hip/hip_runtime.h>
 
 #include "isci_device.h"
@@ -76,7 +77,6 @@ __global__ __launch_bounds__(256) void k_vv_gemm(SigmaArgs A)
     const int e0 = A.chunk_off[row] + A.chunk_cls[row * 3] + A.chunk_cls[row * 3 + 1];
     const int e1 = A.chunk_off[row + 1];
     const int k = lane >> 4, n = lane & 15;
-    const int ntile = min(4, (ncol - c0) / 16);   // ncol is a multiple of 16
     const double *Tb = A.vv_T + (size_t)k * ncol + c0 + n;
     v4d_vv acc[4];
 #pragma unroll
@@ -85,33 +85,30 @@ __global__ __launch_bounds__(256) void k_vv_gemm(SigmaArgs A)
     // stage are in flight while the MFMAs of the other issue (no register
     // copies, which would wait for the loads)
     double ax[2], bx[2][4], ay[2], by[2][4];
+    // loads are unconditional (clamped chunk index, zero selected past the
+    // end), so waiting for one stage never waits for the other
     auto load2 = [&](int e, double *a, double (*b)[4]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            a[u] = 0.0;
+            const int eu = min(e + u, e1 - 1);
+            const double *src = Tb + (size_t)A.vv_trow[eu] * ncol;
+            const double av = A.chunk_val[(size_t)eu * 64 + lane];
+            a[u] = e + u < e1 ? av : 0.0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b[u][t] = 0.0;
-            if (e + u < e1) {
-                const double *src = Tb + (size_t)A.vv_trow[e + u] * ncol;
-                a[u] = A.chunk_val[(size_t)(e + u) * 64 + lane];
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (t < ntile) b[u][t] = src[16 * t];
-            }
+            for (int t = 0; t < 4; ++t) b[u][t] = src[16 * t];
         }
     };
     auto mma2 = [&](const double *a, const double (*b)[4]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
     };
-    load2(e0, ax, bx);
+    if (e0 < e1) load2(e0, ax, bx);
     for (int e = e0; e < e1; e += 4) {
         load2(e + 2, ay, by);
         mma2(ax, bx);
-        if (e + 4 < e1) load2(e + 4, ax, bx);
+        load2(e + 4, ax, bx);
         mma2(ay, by);
     }
     // element g of lane l is row 4 g + l / 16 = (p slot g, r slot l / 16), column l % 16
@@ -119,8 +116,7 @@ __global__ __launch_bounds__(256) void k_vv_gemm(SigmaArgs A)
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            if (t < ntile) Sb[(size_t)g * ks * ncol + 16 * t] = acc[t][g];
+        for (int t = 0; t < 4; ++t) Sb[(size_t)g * ks * ncol + 16 * t] = acc[t][g];
 }
 
 // sigma({a < b}, {c < d}) += the vv|vv part, from S: every way of reading

@@ -223,22 +223,24 @@ __global__ __launch_bounds__(64 * NT) void k_ob_alpha(SigmaArgs A, const double 
         km &= km - 1;
         return k;
     };
+    // every lane loads from a valid address whatever the step (invalid
+    // operands are selected to zero afterwards): with no loads under
+    // branches the compiler can wait for one stage's loads only
     auto load = [&](int ks, double &a, double *b) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = 0.0;
-        a = 0.0;
-        if (ks < 0) return;
-        const int q = 4 * ks + kq;
-        a = hpad(hs, norb, 16 * mt + n, q);
-        if (q >= norb || q == x) return;
-        const long long base = rb[q];
-        const int len = min(rl[q], jlim);
-        if (base < 0) return;
+        const int q = 4 * max(ks, 0) + kq;
+        const int qc = min(q, norb - 1), ac = min(16 * mt + n, norb - 1);
+        const double hv = hs[qc * norb + ac];
+        a = (ks >= 0 && q < norb && 16 * mt + n < norb) ? hv : 0.0;
+        const long long base = rb[qc];
+        const int len = min(rl[qc], jlim);
+        const bool rowok = ks >= 0 && q < norb && q != x && base >= 0;
         const double f = q < x ? 1.0 : -1.0;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int j = j0 + 16 * nt + n;
-            if (j < len) b[nt] = f * cv[base + j];
+            const bool ok = rowok && j < len;
+            const double val = cv[ok ? base + j : 0];
+            b[nt] = ok ? f * val : 0.0;
         }
     };
     v4d_ob acc[4];

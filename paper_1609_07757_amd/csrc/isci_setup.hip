@@ -573,6 +573,7 @@ static isci_status build_vv(isci_ctx *c, hipStream_t s)
                         col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
                 }
         }
+    while (col.size() % 64) col.push_back(255 | (255 << 8));   // zero padding columns
     const int ks = 4 * (nb - 1);
     const int krows = (n - 2) * ks;
     const size_t tbytes = sizeof(double) * (size_t)krows * col.size();

@@ -354,35 +354,34 @@ __device__ __forceinline__ int blk_orbital(int B, int i, int norb)
 
 constexpr int kTabMax = 128;   // orbitals covered by the LDS lookup tables
 
-// B operand of one chunk for this lane: sign * c(v, {x,q}, {y,s}) or 0
+// B operand of one chunk for this lane: sign * c(v, {x,q}, {y,s}) or 0.
+// Table reads and loads are unconditional (clamped indices, invalid
+// operands selected to zero), so the compiler can overlap chunks.
 template <int NV, bool TAB>
 __device__ __forceinline__ void gather_b(const SigmaArgs &A, const double *__restrict__ c, int64_t ldc, int nv,
                                          int x, int y, int ic, int id, int q, int s, int norb,
                                          const long long *rb, const int *rl, const int *bi, double *b)
 {
-    bool ok = x >= 0 && y >= 0 && s >= 0 && x != q && y != s;
-    long long base = -1;
-    int len = 0, jb = -1;
-    if (ok) {
-        if (TAB) {
-            base = rb[ic * kTabMax + q];
-            len = rl[ic * kTabMax + q];
-            jb = bi[id * kTabMax + s];
-        } else {
-            base = A.arow_base[x * norb + q];
-            len = A.arow_len[x * norb + q];
-            jb = A.bpidx[y * norb + s];
-        }
-        ok = base >= 0 && jb >= 0 && jb < len;
+    const bool idx_ok = x >= 0 && y >= 0 && s >= 0 && x != q && y != s;
+    const int xc = max(x, 0), yc = max(y, 0), sc = max(s, 0);
+    long long base;
+    int len, jb;
+    if (TAB) {
+        base = rb[ic * kTabMax + q];
+        len = rl[ic * kTabMax + q];
+        jb = bi[id * kTabMax + sc];
+    } else {
+        base = A.arow_base[xc * norb + q];
+        len = A.arow_len[xc * norb + q];
+        jb = A.bpidx[yc * norb + sc];
     }
+    const bool ok = idx_ok && base >= 0 && jb >= 0 && jb < len;
     const double f = ((q > x) == (s > y)) ? 1.0 : -1.0;
+    const double *src = c + (ok ? base + jb : 0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) b[v] = 0.0;
-    if (ok) {
-        const double *src = c + base + jb;
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < nv) b[v] = f * src[v * ldc];
+    for (int v = 0; v < NV; ++v) {
+        const double val = src[(int64_t)min(v, nv - 1) * ldc];
+        b[v] = (ok && v < nv) ? f * val : 0.0;
     }
 }
 
