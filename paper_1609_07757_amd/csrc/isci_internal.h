@@ -86,6 +86,7 @@ struct DevTabs {
     int *vv_gofs = nullptr;
     int *vv_col = nullptr;
     int *vv_trow = nullptr;
+    uchar4 *rest_quads = nullptr;   // target tiles whose roles have chunks outside vv|vv
     double *vv_T = nullptr;
     double *vv_S = nullptr;
 };
@@ -155,6 +156,7 @@ struct isci_ctx {
     int nblk = 0, nchunk = 0, nquad = 0;
     int vv_ncol = 0, vv_krows = 0, vv_ks = 0;
     bool have_vv = false;
+    int nrestquad = 0;       // target tiles with alpha-beta work left to the gathered kernel
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
     // optional per-kernel timing: HIP events recorded around each launch on
@@ -194,9 +196,12 @@ isci_status launch_ab_vv(const isci_ctx *c, int nv, const double *cv, int64_t ld
                          hipStream_t s);
 // one-body classes on matrix cores (two electrons per spin, norb <= kObMaxNorb)
 constexpr int kObMaxNorb = 80;
+// part: beta only (adds), beta writing sigma (every determinant once),
+// alpha only (adds), or both (adds)
+enum { ISCI_OB_BETA = 0, ISCI_OB_BETA_INIT = 1, ISCI_OB_ALPHA = 2, ISCI_OB_BOTH = 3 };
 bool onebody_mfma_ok(const isci_ctx *c);
-isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
-                                hipStream_t s);
+isci_status launch_onebody_mfma(const isci_ctx *c, int part, int nv, const double *cv, int64_t ldc, double *sv,
+                                int64_t lds, hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

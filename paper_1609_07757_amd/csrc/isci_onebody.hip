@@ -49,7 +49,7 @@ __device__ __forceinline__ double hpad(const double *__restrict__ hs, int norb, 
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0)
+                                                          const double *__restrict__ hs, int row0, int init)
 {
     constexpr int NP = 16 * NT, SP = NP + 1;   // odd row stride: no bank conflicts on U[y][s]
     __shared__ double T[NP * SP];
@@ -90,7 +90,11 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
     for (int j = threadIdx.x; j < len; j += 64 * NT) {
         const uint32_t bs = A.bstr[j];
         const int y = bs & 0xff, s = (bs >> 8) & 0xff;
-        sr[j] += T[y * SP + s] - T[s * SP + y];
+        const double u = T[y * SP + s] - T[s * SP + y];
+        if (init)
+            sr[j] = u;
+        else
+            sr[j] += u;
     }
 }
 
@@ -105,7 +109,8 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0, int nrows)
+                                                          const double *__restrict__ hs, int row0, int nrows,
+                                                          int init)
 {
     constexpr int NP = 16 * NT, SP = NP + 1, NR = 16, NC = 2 * NR;
     constexpr int RMAX = 1 + 2 * (kObMaxNorb - 2);   // longest row of level <= 1 strings
@@ -174,7 +179,10 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const dou
             const int jo = o ? t - 1 : t + 1;   // {o', b}
             add = (o ? h11 : h00) * R[t] + h01 * R[jo] - Ur[o * SP + bv];
         }
-        sv[t] += add;
+        if (init)
+            sv[t] = add;
+        else
+            sv[t] += add;
     }
 }
 
@@ -298,23 +306,31 @@ __global__ __launch_bounds__(256) void k_ob_alpha_tail(SigmaArgs A, const double
 }
 
 template <int NT>
-static isci_status launch_ob_nt(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
-                                double *s, int64_t lds, hipStream_t st)
+static void launch_ob_beta(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
+                           int64_t lds, int init, hipStream_t st)
 {
     const double *hs = cx->d.hscreen;
     const int L = cx->L;
-    const int *le_a = cx->sa.le;
-    // alpha rows by level: beta strings up to level 2 for level <= L - 2
-    const int full_end = L >= 2 ? le_a[L - 2] : 0;
+    // alpha rows by level: beta strings up to level 2 for level <= L - 2;
+    // the two kernels together visit every determinant once
+    const int full_end = L >= 2 ? cx->sa.le[L - 2] : 0;
     if (full_end > 0)
-        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, 0);
+        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, 0, init);
     const int ncap1 = cx->sa.nstr - full_end;   // rows whose beta strings stop at level 1 or 0
     if (ncap1 > 0)
         k_ob_beta_cap1<NT><<<dim3((unsigned)((ncap1 + 15) / 16), (unsigned)nv), 64 * NT, 0, st>>>(
-            A, c, ldc, s, lds, hs, full_end, ncap1);
-    // alpha: rows {q, x} hold beta strings up to level L - level({q, x});
-    // for x occupied every column reaches some row of level <= 1, for x
-    // virtual the columns above the level-2 row length only reach {0,x}, {1,x}
+            A, c, ldc, s, lds, hs, full_end, ncap1, init);
+}
+
+template <int NT>
+static void launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
+                            int64_t lds, hipStream_t st)
+{
+    const double *hs = cx->d.hscreen;
+    const int L = cx->L;
+    // rows {q, x} hold beta strings up to level L - level({q, x}); for x
+    // occupied every column reaches some row of level <= 1, for x virtual
+    // the columns above the level-2 row length only reach {0,x}, {1,x}
     const int *le_b = cx->sb.le;
     const int jlim_occ = le_b[L];
     const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
@@ -325,8 +341,6 @@ static isci_status launch_ob_nt(const isci_ctx *cx, const SigmaArgs &A, int nv, 
     if (jtail > jlim_virt && cx->norb > 2)
         k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
                           0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);
-    ISCI_HIP(hipGetLastError());
-    return ISCI_OK;
 }
 
 bool onebody_mfma_ok(const isci_ctx *cx)
@@ -335,19 +349,29 @@ bool onebody_mfma_ok(const isci_ctx *cx)
            cx->d.arow_base && cx->d.arow_len;
 }
 
-isci_status launch_onebody_mfma(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
-                                hipStream_t st)
+isci_status launch_onebody_mfma(const isci_ctx *cx, int part, int nv, const double *c, int64_t ldc, double *s,
+                                int64_t lds, hipStream_t st)
 {
     const SigmaArgs A = sigma_args(cx);
     const int nt = (cx->norb + 15) / 16;
+    if (nt < 1 || nt > 5) { set_error("one-body matrix-core path: norb too large"); return ISCI_E_UNSUPPORTED; }
+    const bool beta = part != ISCI_OB_ALPHA, alpha = part == ISCI_OB_ALPHA || part == ISCI_OB_BOTH;
+    const int init = part == ISCI_OB_BETA_INIT;
+#define ISCI_OB_CASE(N)                                                     \
+    case N:                                                                 \
+        if (beta) launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, init, st);   \
+        if (alpha) launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st);       \
+        break;
     switch (nt) {
-    case 1: return launch_ob_nt<1>(cx, A, nv, c, ldc, s, lds, st);
-    case 2: return launch_ob_nt<2>(cx, A, nv, c, ldc, s, lds, st);
-    case 3: return launch_ob_nt<3>(cx, A, nv, c, ldc, s, lds, st);
-    case 4: return launch_ob_nt<4>(cx, A, nv, c, ldc, s, lds, st);
-    case 5: return launch_ob_nt<5>(cx, A, nv, c, ldc, s, lds, st);
-    default: set_error("one-body matrix-core path: norb too large"); return ISCI_E_UNSUPPORTED;
+        ISCI_OB_CASE(1)
+        ISCI_OB_CASE(2)
+        ISCI_OB_CASE(3)
+        ISCI_OB_CASE(4)
+        ISCI_OB_CASE(5)
     }
+#undef ISCI_OB_CASE
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
 }
 
 }  // namespace isci

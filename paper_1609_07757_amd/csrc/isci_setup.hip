@@ -594,7 +594,33 @@ static isci_status build_vv(isci_ctx *c, hipStream_t s)
             for (int e = off[g] + cls[3 * g] + cls[3 * g + 1]; e < off[g + 1]; ++e)
                 trow[e] = (desc[e].x - 2) * ks + 4 * (desc[e].y - 1);
         }
+    // target tiles with chunks outside vv|vv in an active role (the rest
+    // of the alpha-beta class, same role rules as the gathered kernel)
+    std::vector<uchar4> rq;
+    for (int X = 0; X < nb; ++X)
+        for (int P = X; P < nb; ++P)
+            for (int Y = 0; Y < nb; ++Y)
+                for (int R = Y; R < nb; ++R) {
+                    if ((X != 0) + (P != 0) + (Y != 0) + (R != 0) > L) continue;
+                    const bool sameA = X == P, sameB = Y == R;
+                    const int role[4][5] = {{P, R, X, Y, 1}, {X, R, P, Y, !sameA}, {P, Y, X, R, !sameB},
+                                            {X, Y, P, R, !sameA && !sameB}};
+                    bool has = false;
+                    for (int w = 0; w < 4 && !has; ++w) {
+                        if (!role[w][4]) continue;
+                        const int Ab = role[w][0], Bb = role[w][1], espec = (role[w][2] != 0) + (role[w][3] != 0);
+                        const int g = Ab * nb + Bb, lmax = (Ab != 0 && Bb != 0) ? 1 : 2;
+                        for (int l = 0; l <= lmax; ++l)
+                            if (espec + l <= L && cls[3 * g + l] > 0) has = true;
+                    }
+                    if (has) rq.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
+                }
     DevTabs &d = c->d;
+    d.rest_quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, rq.size()));
+    if (!d.rest_quads) { set_error("device allocation failed (vv)"); return ISCI_E_OOM; }
+    if (!rq.empty())
+        ISCI_HIP(hipMemcpyAsync(d.rest_quads, rq.data(), sizeof(uchar4) * rq.size(), hipMemcpyHostToDevice, s));
+    c->nrestquad = (int)rq.size();
     d.vv_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
     d.vv_col = (int *)dev_alloc(c, sizeof(int) * col.size());
     d.vv_trow = (int *)dev_alloc(c, sizeof(int) * trow.size());
