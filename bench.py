@@ -112,13 +112,11 @@ def main():
     isci.isci_profile(hd, False)
     # algorithmic flops each kernel performs per step (2 per sigma term per vector)
     terms_1b = int(tb[0:8].sum())
-    terms_vv = int(tb[41])       # alpha-beta units with all four orbitals virtual
-    vv_split = "k_vv_unfold+k_ab_vv" in prof
     kflops = {"k_sigma_generic": 2.0 * terms * nvec, "k_sigma_n2": 2.0 * terms * nvec,
-              "k_sigma_ab_mfma": 2.0 * (terms_ab - (terms_vv if vv_split else 0)) * nvec,
+              "k_sigma_ab_mfma": 2.0 * terms_ab * nvec,
               "k_sigma_n2(same-spin)": 2.0 * (terms_rest - terms_1b) * nvec,
               "onebody": 2.0 * terms_1b * nvec,
-              "k_vv_unfold+k_ab_vv": 2.0 * terms_vv * nvec}
+              "k_ab_unfold+gemm+fold": 2.0 * terms_ab * nvec}
     kernels = {}
     for name, (tot_ms, nl) in prof.items():
         per_launch_ms = tot_ms / nl

@@ -241,12 +241,13 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
  * then clears them.  Kernel ids: */
 #define ISCI_KERNEL_GENERAL 0   /* k_sigma_generic: all classes, any electron count */
 #define ISCI_KERNEL_PAIR 1      /* k_sigma_n2: all classes, two electrons per spin */
-#define ISCI_KERNEL_AB_MFMA 2   /* k_sigma_ab_mfma: alpha-beta class on matrix cores */
+#define ISCI_KERNEL_AB_MFMA 2   /* k_sigma_ab_mfma: alpha-beta class on matrix cores, gathered operands
+                                   (when the product path's operands would exceed 2 GiB) */
 #define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
 #define ISCI_KERNEL_ONEBODY 4   /* one-body classes, two electrons per spin (matrix-core products, or
                                    k_onebody_a + k_onebody_b above 80 orbitals) */
-#define ISCI_KERNEL_AB_VV 5     /* k_vv_unfold + k_ab_vv: all-virtual alpha-beta units as a block-sparse
-                                   product on matrix cores (two electrons per spin, L >= 2) */
+#define ISCI_KERNEL_AB_PROD 5   /* k_ab_unfold + k_ab_gemm + k_ab_fold: alpha-beta class as a block-sparse
+                                   product on matrix cores (two electrons per spin) */
 isci_status isci_profile(isci_handle hd, int enable);
 isci_status isci_profile_read(isci_handle hd, int kernel, double *total_ms, int64_t *launches);
 

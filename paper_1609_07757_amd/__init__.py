@@ -315,7 +315,7 @@ def isci_davidson_footprint(hd: Handle, nroots: int = 1, **opts) -> int:
 
 
 KERNEL_NAMES = {0: "k_sigma_generic", 1: "k_sigma_n2", 2: "k_sigma_ab_mfma", 3: "k_sigma_n2(same-spin)",
-                4: "onebody", 5: "k_vv_unfold+k_ab_vv"}
+                4: "onebody", 5: "k_ab_unfold+gemm+fold"}
 
 
 def isci_profile(hd: Handle, enable: bool = True):

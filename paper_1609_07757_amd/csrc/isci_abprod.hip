@@ -1,0 +1,184 @@
+// Alpha-beta class (two electrons per spin) as unfold -> block-sparse
+// product on FP64 matrix cores -> fold.
+//
+// With T[x][q][y][s] = sgn(q - x) sgn(s - y) c({x,q},{y,s}) (the CI vector
+// as an antisymmetric pair tensor in each spin; zero where {x,q} or {y,s}
+// is not a string or the determinant lies above the excitation cut), the
+// alpha-beta class (Eq. sigma, the alpha-beta part, with the separable
+// phase of its final equation) is
+//   T'[x][p][y][r] = S[x][p][y][r] - S[p][x][y][r] - S[x][p][r][y] + S[p][x][r][y],
+//   S[x][p][y][r]  = sum_{q,s} (pq|rs) T[x][q][y][s],
+// S and T indexed [alpha spectator][alpha active][beta spectator][beta
+// active].  For fixed spectators (x, y) this is a product with the
+// screened matrix W[(p, r), (q, s)] = (pq|rs); over all spectators and the
+// vectors of a pass it is a block-sparse GEMM whose columns are (x, y, v).
+//
+// Orbitals come in blocks of four (block 0: the two occupied orbitals);
+// W is stored as 16 x 4 chunks (rows (p, r) of a row block pair, columns
+// (q, four s of an S block)), ordered inside a row block pair by the class
+// [q virtual] + [S virtual].  Columns are grouped by spectator block pair
+// (C, D), low level first (level = [C virtual] + [D virtual]), each level
+// section padded with zero columns to a multiple of 64; a group has
+// slots(C) * slots(D) * 4 columns (two slots for the occupied block).  A
+// source or target of class k only has the spectator groups of level
+// <= L - k, which is a prefix of the columns: pcols[k].
+//
+//  * unfold: every (q, S) that opens a chunk gets 4 rows of T, pcols[class]
+//    wide, written once per call from the CI vectors;
+//  * product: a workgroup takes one row block pair and 256 columns; each
+//    wave four 16-column tiles; K runs over the chunks whose class leaves
+//    the columns valid (a prefix of the chunk list); S gets 16 rows x
+//    pcols[class of the row block pair];
+//  * fold: every determinant sums its four role readings of S and writes
+//    sigma (the first class written; the others add).
+#include <hip/hip_runtime.h>
+
+#include "isci_device.h"
+#include "isci_internal.h"
+
+namespace isci {
+
+typedef double v4d_ab __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
+__device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
+
+// row kr = 4 * (T row block) + k of T; thread per column
+__global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const double *__restrict__ c, int64_t ldc)
+{
+    const int kr = blockIdx.y;
+    const int4 tr = A.abx_trow[kr >> 2];   // (q, S, T offset of row 0, width)
+    const int width = tr.w;
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= width) return;
+    const int norb = A.norb;
+    const int q = tr.x, S = tr.y, k = kr & 3;
+    const int s = S == 0 ? (k < 2 ? k : -1) : (2 + 4 * (S - 1) + k < norb ? 2 + 4 * (S - 1) + k : -1);
+    const int d = A.abx_col[col];
+    const int x = d & 0xff, y = (d >> 8) & 0xff, v = d >> 16;
+    double val = 0.0;
+    if (s >= 0 && x != 255 && y != 255 && x != q && y != s && v < nv) {
+        const long long base = A.arow_base[x * norb + q];
+        const int len = A.arow_len[x * norb + q];
+        const int jb = A.bpidx[y * norb + s];
+        if (base >= 0 && jb >= 0 && jb < len) {
+            const double cv = c[(int64_t)v * ldc + base + jb];
+            val = ((q > x) == (s > y)) ? cv : -cv;
+        }
+    }
+    A.abx_T[(size_t)tr.z + (size_t)k * width + col] = val;
+}
+
+// S for row block pair abx_rows[blockIdx.x] and columns blockIdx.y * 256 + [0, 256)
+__global__ __launch_bounds__(256) void k_ab_gemm(SigmaArgs A)
+{
+    const int nb = A.nblk;
+    const int g = A.abx_rows[blockIdx.x];
+    const int Ab = g / nb, Bb = g % nb;
+    const int m = (Ab != 0) + (Bb != 0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c0 = blockIdx.y * 256 + wave * 64;
+    const int swidth = A.abx_pcols[m];
+    if (c0 >= swidth) return;
+    // chunks whose class keeps these columns valid: classes l with
+    // c0 < pcols[max(l, m)], a prefix of the class-ordered list
+    const int e0 = A.chunk_off[g];
+    int e1 = e0;
+    for (int l = 0; l < 3; ++l)
+        if (c0 < A.abx_pcols[max(l, m)]) e1 += A.chunk_cls[g * 3 + l];
+    const int k = lane >> 4, n = lane & 15;
+    v4d_ab acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = v4d_ab{0.0, 0.0, 0.0, 0.0};
+    // two stages of two chunks, ping-ponged; loads are unconditional
+    // (clamped chunk index, zero selected past the end) so waiting for one
+    // stage never waits for the other
+    double ax[2], bx[2][4], ay[2], by[2][4];
+    auto load2 = [&](int e, double *a, double (*b)[4]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int eu = min(e + u, e1 - 1);
+            const int2 tx = A.abx_chunk[eu];   // (T offset of the chunk's row 0, row width)
+            const double *src = A.abx_T + (size_t)tx.x + (size_t)k * tx.y + c0 + n;
+            const double av = A.chunk_val[(size_t)eu * 64 + lane];
+            a[u] = e + u < e1 ? av : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[u][t] = src[16 * t];
+        }
+    };
+    auto mma2 = [&](const double *a, const double (*b)[4]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+    };
+    if (e0 < e1) {
+        load2(e0, ax, bx);
+        for (int e = e0; e < e1; e += 4) {
+            load2(e + 2, ay, by);
+            mma2(ax, bx);
+            load2(e + 4, ax, bx);
+            mma2(ay, by);
+        }
+    }
+    // element gg of lane l: row 4 gg + l / 16 (alpha active slot gg, beta active slot l / 16), column l % 16
+    double *Sb = A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + n;
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Sb[(size_t)gg * 4 * swidth + 16 * t] = acc[t][gg];
+}
+
+// sigma({a0 < a1}, {b0 < b1}) = sum over the four readings (alpha
+// spectator, alpha active) x (beta spectator, beta active) of S, sign - per
+// spin whose spectator is the larger orbital
+__global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds)
+{
+    const int ia = blockIdx.x;
+    const int jb = blockIdx.y * 256 + threadIdx.x;
+    const int len = A.sb.le[A.L - A.alev[ia]];
+    if (jb >= len) return;
+    const int nb = A.nblk;
+    const uint32_t as = A.astr[ia], bs = A.bstr[jb];
+    const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra) {
+        const int xs = ra ? a1 : a0, xa = ra ? a0 : a1;   // alpha spectator, active
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int ys = rb ? b1 : b0, ya = rb ? b0 : b1;
+            const int g = ab_block(xa) * nb + ab_block(ya);
+            const long long so = A.abx_soff[g];
+            if (so < 0) continue;
+            const int m = (ab_block(xa) != 0) + (ab_block(ya) != 0);
+            const int C = ab_block(xs), D = ab_block(ys);
+            const int col = A.abx_gofs[C * nb + D] + (ab_slot(xs) * (D == 0 ? 2 : 4) + ab_slot(ys)) * 4;
+            const int row = ab_slot(xa) * 4 + ab_slot(ya);
+            const double *src = A.abx_S + (size_t)so + (size_t)row * A.abx_pcols[m] + col;
+            const double f = (ra ^ rb) ? -1.0 : 1.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += f * src[v];
+        }
+    }
+    double *dst = sg + A.rowstart[ia] + jb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (v < nv) dst[(int64_t)v * lds] = acc[v];
+}
+
+isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
+                              hipStream_t st)
+{
+    const SigmaArgs A = sigma_args(cx);
+    if (cx->abx_ntrow > 0)
+        k_ab_unfold<<<dim3((unsigned)((cx->abx_pcols[0] + 255) / 256), (unsigned)(4 * cx->abx_ntrow)), 256, 0, st>>>(
+            A, nv, c, ldc);
+    if (cx->abx_nrows > 0)
+        k_ab_gemm<<<dim3((unsigned)cx->abx_nrows, (unsigned)((cx->abx_pcols[0] + 255) / 256)), 256, 0, st>>>(A);
+    k_ab_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, s, lds);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
+}  // namespace isci

@@ -77,18 +77,20 @@ struct DevTabs {
     long long *arow_base = nullptr;
     int *arow_len = nullptr;
     int *chunk_cls = nullptr;       // [nblk*nblk][3] chunks per source level class
-    // all-virtual alpha-beta units (vv|vv) as a product with an unfolded
-    // copy of the CI block: column offset of each spectator block pair
-    // ([nblk][nblk], -1 when the pair is above the level cut), packed
-    // (x, y, v) per column, T row of each chunk ((q - 2) * ks + 4 (S - 1);
-    // -1 outside the vv|vv chunks), the unfolded operand T[(q, s)][column]
-    // and the product S[(p, r)][column] (both rewritten per call)
-    int *vv_gofs = nullptr;
-    int *vv_col = nullptr;
-    int *vv_trow = nullptr;
-    uchar4 *rest_quads = nullptr;   // target tiles whose roles have chunks outside vv|vv
-    double *vv_T = nullptr;
-    double *vv_S = nullptr;
+    // alpha-beta class as unfold -> block-sparse product -> fold:
+    // column offset of each spectator block pair ([nblk][nblk], -1 above
+    // the level cut), packed (x, y, v) per column, T rows (q, S, T offset,
+    // width) of every (q, S) that opens a chunk, per chunk (T offset, width),
+    // row block pairs holding chunks, S offset per row block pair (-1: none),
+    // and the per-call operands T and S
+    int *abx_gofs = nullptr;
+    int *abx_col = nullptr;
+    int4 *abx_trow = nullptr;
+    int2 *abx_chunk = nullptr;
+    int *abx_rows = nullptr;
+    long long *abx_soff = nullptr;
+    double *abx_T = nullptr;
+    double *abx_S = nullptr;
 };
 
 struct SigmaArgs {
@@ -116,12 +118,14 @@ struct SigmaArgs {
     const long long *arow_base;
     const int *arow_len;
     const int *chunk_cls;
-    int vv_split;            // alpha-beta MFMA kernel skips the vv|vv chunks (done by the product path)
-    const int *vv_gofs;
-    const int *vv_col;
-    const int *vv_trow;
-    double *vv_T, *vv_S;
-    int vv_ncol, vv_ks;      // columns of T; padded virtual count (row (q, s) = (q - 2) * vv_ks + s - 2)
+    const int *abx_gofs;
+    const int *abx_col;
+    const int4 *abx_trow;
+    const int2 *abx_chunk;
+    const int *abx_rows;
+    const long long *abx_soff;
+    double *abx_T, *abx_S;
+    int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };
 
 // One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)
@@ -154,9 +158,8 @@ struct isci_ctx {
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int nblk = 0, nchunk = 0, nquad = 0;
-    int vv_ncol = 0, vv_krows = 0, vv_ks = 0;
-    bool have_vv = false;
-    int nrestquad = 0;       // target tiles with alpha-beta work left to the gathered kernel
+    bool have_abx = false;   // alpha-beta product path built
+    int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
     // optional per-kernel timing: HIP events recorded around each launch on
@@ -191,17 +194,14 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
 // records a start (begin=true) or stop event for kernel id `k` when profiling
 isci_status prof_mark(const isci_ctx *c, int k, bool begin, hipStream_t s);
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
-// vv|vv alpha-beta units as unfold + block-sparse product (adds into sigma)
-isci_status launch_ab_vv(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
-                         hipStream_t s);
+// alpha-beta class as unfold + block-sparse product + fold (writes sigma)
+isci_status launch_ab_product(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
+                              hipStream_t s);
 // one-body classes on matrix cores (two electrons per spin, norb <= kObMaxNorb)
 constexpr int kObMaxNorb = 80;
-// part: beta only (adds), beta writing sigma (every determinant once),
-// alpha only (adds), or both (adds)
-enum { ISCI_OB_BETA = 0, ISCI_OB_BETA_INIT = 1, ISCI_OB_ALPHA = 2, ISCI_OB_BOTH = 3 };
 bool onebody_mfma_ok(const isci_ctx *c);
-isci_status launch_onebody_mfma(const isci_ctx *c, int part, int nv, const double *cv, int64_t ldc, double *sv,
-                                int64_t lds, hipStream_t s);
+isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
+                                hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

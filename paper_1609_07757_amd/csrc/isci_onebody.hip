@@ -49,7 +49,7 @@ __device__ __forceinline__ double hpad(const double *__restrict__ hs, int norb, 
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0, int init)
+                                                          const double *__restrict__ hs, int row0)
 {
     constexpr int NP = 16 * NT, SP = NP + 1;   // odd row stride: no bank conflicts on U[y][s]
     __shared__ double T[NP * SP];
@@ -90,11 +90,7 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
     for (int j = threadIdx.x; j < len; j += 64 * NT) {
         const uint32_t bs = A.bstr[j];
         const int y = bs & 0xff, s = (bs >> 8) & 0xff;
-        const double u = T[y * SP + s] - T[s * SP + y];
-        if (init)
-            sr[j] = u;
-        else
-            sr[j] += u;
+        sr[j] += T[y * SP + s] - T[s * SP + y];
     }
 }
 
@@ -109,8 +105,7 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0, int nrows,
-                                                          int init)
+                                                          const double *__restrict__ hs, int row0, int nrows)
 {
     constexpr int NP = 16 * NT, SP = NP + 1, NR = 16, NC = 2 * NR;
     constexpr int RMAX = 1 + 2 * (kObMaxNorb - 2);   // longest row of level <= 1 strings
@@ -179,10 +174,7 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const dou
             const int jo = o ? t - 1 : t + 1;   // {o', b}
             add = (o ? h11 : h00) * R[t] + h01 * R[jo] - Ur[o * SP + bv];
         }
-        if (init)
-            sv[t] = add;
-        else
-            sv[t] += add;
+        sv[t] += add;
     }
 }
 
@@ -307,19 +299,18 @@ __global__ __launch_bounds__(256) void k_ob_alpha_tail(SigmaArgs A, const double
 
 template <int NT>
 static void launch_ob_beta(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
-                           int64_t lds, int init, hipStream_t st)
+                           int64_t lds, hipStream_t st)
 {
     const double *hs = cx->d.hscreen;
     const int L = cx->L;
-    // alpha rows by level: beta strings up to level 2 for level <= L - 2;
-    // the two kernels together visit every determinant once
+    // alpha rows by level: beta strings up to level 2 for level <= L - 2
     const int full_end = L >= 2 ? cx->sa.le[L - 2] : 0;
     if (full_end > 0)
-        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, 0, init);
+        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, 0);
     const int ncap1 = cx->sa.nstr - full_end;   // rows whose beta strings stop at level 1 or 0
     if (ncap1 > 0)
         k_ob_beta_cap1<NT><<<dim3((unsigned)((ncap1 + 15) / 16), (unsigned)nv), 64 * NT, 0, st>>>(
-            A, c, ldc, s, lds, hs, full_end, ncap1, init);
+            A, c, ldc, s, lds, hs, full_end, ncap1);
 }
 
 template <int NT>
@@ -349,18 +340,15 @@ bool onebody_mfma_ok(const isci_ctx *cx)
            cx->d.arow_base && cx->d.arow_len;
 }
 
-isci_status launch_onebody_mfma(const isci_ctx *cx, int part, int nv, const double *c, int64_t ldc, double *s,
-                                int64_t lds, hipStream_t st)
+isci_status launch_onebody_mfma(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
+                                hipStream_t st)
 {
     const SigmaArgs A = sigma_args(cx);
     const int nt = (cx->norb + 15) / 16;
-    if (nt < 1 || nt > 5) { set_error("one-body matrix-core path: norb too large"); return ISCI_E_UNSUPPORTED; }
-    const bool beta = part != ISCI_OB_ALPHA, alpha = part == ISCI_OB_ALPHA || part == ISCI_OB_BOTH;
-    const int init = part == ISCI_OB_BETA_INIT;
-#define ISCI_OB_CASE(N)                                                     \
-    case N:                                                                 \
-        if (beta) launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, init, st);   \
-        if (alpha) launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st);       \
+#define ISCI_OB_CASE(N)                                               \
+    case N:                                                           \
+        launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, st);             \
+        launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st);            \
         break;
     switch (nt) {
         ISCI_OB_CASE(1)
@@ -368,6 +356,7 @@ isci_status launch_onebody_mfma(const isci_ctx *cx, int part, int nv, const doub
         ISCI_OB_CASE(3)
         ISCI_OB_CASE(4)
         ISCI_OB_CASE(5)
+    default: set_error("one-body matrix-core path: norb too large"); return ISCI_E_UNSUPPORTED;
     }
 #undef ISCI_OB_CASE
     ISCI_HIP(hipGetLastError());

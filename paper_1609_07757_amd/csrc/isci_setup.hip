@@ -413,14 +413,15 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.arow_base = c->d.arow_base;
     A.arow_len = c->d.arow_len;
     A.chunk_cls = c->d.chunk_cls;
-    A.vv_split = c->have_vv ? 1 : 0;
-    A.vv_gofs = c->d.vv_gofs;
-    A.vv_col = c->d.vv_col;
-    A.vv_trow = c->d.vv_trow;
-    A.vv_T = c->d.vv_T;
-    A.vv_S = c->d.vv_S;
-    A.vv_ncol = c->vv_ncol;
-    A.vv_ks = c->vv_ks;
+    A.abx_gofs = c->d.abx_gofs;
+    A.abx_col = c->d.abx_col;
+    A.abx_trow = c->d.abx_trow;
+    A.abx_chunk = c->d.abx_chunk;
+    A.abx_rows = c->d.abx_rows;
+    A.abx_soff = c->d.abx_soff;
+    A.abx_T = c->d.abx_T;
+    A.abx_S = c->d.abx_S;
+    for (int k = 0; k < 3; ++k) A.abx_pcols[k] = c->abx_pcols[k];
     return A;
 }
 
@@ -550,94 +551,108 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     return ISCI_OK;
 }
 
-// vv|vv product path: needs virtual blocks on both spins and an unfolded
-// operand of bounded size (the vectors of one pass: four)
-static constexpr size_t kVvMaxBytes = (size_t)2 << 30;
+// alpha-beta product path (unfold -> block-sparse GEMM -> fold); its
+// per-call operands T and S are bounded (four vectors per pass)
+static constexpr size_t kAbxMaxBytes = (size_t)2 << 30;
 
-static isci_status build_vv(isci_ctx *c, hipStream_t s)
+static isci_status build_abx(isci_ctx *c, hipStream_t s)
 {
     const int n = c->norb, nb = c->nblk, L = c->L;
-    if (L < 2 || nb < 2) return ISCI_OK;
+    if (nb < 1 || c->nchunk == 0) return ISCI_OK;
     auto width = [](int B) { return B == 0 ? 2 : 4; };
+    // column groups, level by level, each level padded to 64 columns
     std::vector<int> gofs((size_t)nb * nb, -1);
     std::vector<int> col;
-    for (int C = 0; C < nb; ++C)
-        for (int D = 0; D < nb; ++D) {
-            if ((C != 0) + (D != 0) > L - 2) continue;
-            gofs[(size_t)C * nb + D] = (int)col.size();
-            for (int ic = 0; ic < width(C); ++ic)
-                for (int id = 0; id < width(D); ++id) {
-                    const int x = C == 0 ? ic : 2 + 4 * (C - 1) + ic;
-                    const int y = D == 0 ? id : 2 + 4 * (D - 1) + id;
-                    for (int v = 0; v < 4; ++v)
-                        col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
+    int plev[3] = {0, 0, 0};
+    for (int lev = 0; lev <= 2; ++lev) {
+        if (lev <= L)
+            for (int C = 0; C < nb; ++C)
+                for (int D = 0; D < nb; ++D) {
+                    if ((C != 0) + (D != 0) != lev) continue;
+                    gofs[(size_t)C * nb + D] = (int)col.size();
+                    for (int ic = 0; ic < width(C); ++ic)
+                        for (int id = 0; id < width(D); ++id) {
+                            const int x = C == 0 ? ic : 2 + 4 * (C - 1) + ic;
+                            const int y = D == 0 ? id : 2 + 4 * (D - 1) + id;
+                            for (int v = 0; v < 4; ++v)
+                                col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
+                        }
                 }
-        }
-    while (col.size() % 64) col.push_back(255 | (255 << 8));   // zero padding columns
-    const int ks = 4 * (nb - 1);
-    const int krows = (n - 2) * ks;
-    const size_t tbytes = sizeof(double) * (size_t)krows * col.size();
-    const size_t sbytes = sizeof(double) * (size_t)ks * ks * col.size();
-    if (tbytes == 0 || tbytes + sbytes > kVvMaxBytes) return ISCI_OK;
-    // T row of each vv|vv chunk (class 2 of a virtual row block pair)
+        while (col.size() % 64) col.push_back(255 | (255 << 8));
+        plev[lev] = (int)col.size();
+    }
+    int pcols[3];
+    for (int k = 0; k < 3; ++k) pcols[k] = L - k < 0 ? 0 : plev[std::min(2, L - k)];
+    // chunk lists from the device
     std::vector<int> off(nb * nb + 1), cls(3 * nb * nb);
-    std::vector<int2> desc(std::max(1, c->nchunk));
+    std::vector<int2> desc(c->nchunk);
     ISCI_HIP(hipMemcpyAsync(off.data(), c->d.chunk_off, sizeof(int) * off.size(), hipMemcpyDeviceToHost, s));
     ISCI_HIP(hipMemcpyAsync(cls.data(), c->d.chunk_cls, sizeof(int) * cls.size(), hipMemcpyDeviceToHost, s));
-    if (c->nchunk > 0)
-        ISCI_HIP(hipMemcpyAsync(desc.data(), c->d.chunk_desc, sizeof(int2) * c->nchunk, hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipMemcpyAsync(desc.data(), c->d.chunk_desc, sizeof(int2) * c->nchunk, hipMemcpyDeviceToHost, s));
     ISCI_HIP(hipStreamSynchronize(s));
-    std::vector<int> trow(std::max(1, c->nchunk), -1);
-    for (int A = 1; A < nb; ++A)
-        for (int B = 1; B < nb; ++B) {
-            const int g = A * nb + B;
-            for (int e = off[g] + cls[3 * g] + cls[3 * g + 1]; e < off[g + 1]; ++e)
-                trow[e] = (desc[e].x - 2) * ks + 4 * (desc[e].y - 1);
-        }
-    // target tiles with chunks outside vv|vv in an active role (the rest
-    // of the alpha-beta class, same role rules as the gathered kernel)
-    std::vector<uchar4> rq;
-    for (int X = 0; X < nb; ++X)
-        for (int P = X; P < nb; ++P)
-            for (int Y = 0; Y < nb; ++Y)
-                for (int R = Y; R < nb; ++R) {
-                    if ((X != 0) + (P != 0) + (Y != 0) + (R != 0) > L) continue;
-                    const bool sameA = X == P, sameB = Y == R;
-                    const int role[4][5] = {{P, R, X, Y, 1}, {X, R, P, Y, !sameA}, {P, Y, X, R, !sameB},
-                                            {X, Y, P, R, !sameA && !sameB}};
-                    bool has = false;
-                    for (int w = 0; w < 4 && !has; ++w) {
-                        if (!role[w][4]) continue;
-                        const int Ab = role[w][0], Bb = role[w][1], espec = (role[w][2] != 0) + (role[w][3] != 0);
-                        const int g = Ab * nb + Bb, lmax = (Ab != 0 && Bb != 0) ? 1 : 2;
-                        for (int l = 0; l <= lmax; ++l)
-                            if (espec + l <= L && cls[3 * g + l] > 0) has = true;
-                    }
-                    if (has) rq.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
+    // T rows: each (q, S) opening a chunk whose class admits some spectator
+    std::vector<int> krow_of((size_t)n * nb, -1);
+    std::vector<int4> trow;
+    std::vector<int2> chunk(c->nchunk, make_int2(0, 0));
+    size_t tsize = 0;
+    for (int g = 0; g < nb * nb; ++g) {
+        int e = off[g];
+        for (int l = 0; l < 3; ++l)
+            for (int i = 0; i < cls[3 * g + l]; ++i, ++e) {
+                if (pcols[l] == 0) continue;
+                const int q = desc[e].x, S = desc[e].y;
+                int &kr = krow_of[(size_t)q * nb + S];
+                if (kr < 0) {
+                    kr = (int)trow.size();
+                    trow.push_back(make_int4(q, S, (int)0, pcols[l]));
+                    if (tsize + (size_t)4 * pcols[l] > (size_t)INT32_MAX) return ISCI_OK;   // offsets stay int
+                    trow.back().z = (int)tsize;
+                    tsize += (size_t)4 * pcols[l];
                 }
+                chunk[e] = make_int2(trow[kr].z, trow[kr].w);
+            }
+    }
+    // S blocks: row block pairs holding chunks
+    std::vector<long long> soff((size_t)nb * nb, -1);
+    std::vector<int> rows;
+    size_t ssize = 0;
+    for (int g = 0; g < nb * nb; ++g) {
+        const int m = (g / nb != 0) + (g % nb != 0);
+        if (off[g + 1] == off[g] || pcols[m] == 0) continue;
+        soff[g] = (long long)ssize;
+        rows.push_back(g);
+        ssize += (size_t)16 * pcols[m];
+    }
+    const size_t tbytes = sizeof(double) * std::max<size_t>(1, tsize);
+    const size_t sbytes = sizeof(double) * std::max<size_t>(1, ssize);
+    if (tbytes + sbytes > kAbxMaxBytes) return ISCI_OK;   // gathered kernel instead
     DevTabs &d = c->d;
-    d.rest_quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, rq.size()));
-    if (!d.rest_quads) { set_error("device allocation failed (vv)"); return ISCI_E_OOM; }
-    if (!rq.empty())
-        ISCI_HIP(hipMemcpyAsync(d.rest_quads, rq.data(), sizeof(uchar4) * rq.size(), hipMemcpyHostToDevice, s));
-    c->nrestquad = (int)rq.size();
-    d.vv_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
-    d.vv_col = (int *)dev_alloc(c, sizeof(int) * col.size());
-    d.vv_trow = (int *)dev_alloc(c, sizeof(int) * trow.size());
-    d.vv_T = (double *)dev_alloc(c, tbytes);
-    d.vv_S = (double *)dev_alloc(c, sbytes);
-    if (!d.vv_gofs || !d.vv_col || !d.vv_trow || !d.vv_T || !d.vv_S) {
-        set_error("device allocation failed (vv)");
+    d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
+    d.abx_col = (int *)dev_alloc(c, sizeof(int) * col.size());
+    d.abx_trow = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, trow.size()));
+    d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * chunk.size());
+    d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
+    d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
+    d.abx_T = (double *)dev_alloc(c, tbytes);
+    d.abx_S = (double *)dev_alloc(c, sbytes);
+    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_T ||
+        !d.abx_S) {
+        set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
     }
-    ISCI_HIP(hipMemcpyAsync(d.vv_gofs, gofs.data(), sizeof(int) * gofs.size(), hipMemcpyHostToDevice, s));
-    ISCI_HIP(hipMemcpyAsync(d.vv_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
-    ISCI_HIP(hipMemcpyAsync(d.vv_trow, trow.data(), sizeof(int) * trow.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_gofs, gofs.data(), sizeof(int) * gofs.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
+    if (!trow.empty())
+        ISCI_HIP(hipMemcpyAsync(d.abx_trow, trow.data(), sizeof(int4) * trow.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_chunk, chunk.data(), sizeof(int2) * chunk.size(), hipMemcpyHostToDevice, s));
+    if (!rows.empty())
+        ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_soff, soff.data(), sizeof(long long) * soff.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
-    c->vv_ncol = (int)col.size();
-    c->vv_krows = krows;
-    c->vv_ks = ks;
-    c->have_vv = true;
+    c->abx_ntrow = (int)trow.size();
+    c->abx_nrows = (int)rows.size();
+    for (int k = 0; k < 3; ++k) c->abx_pcols[k] = pcols[k];
+    c->have_abx = true;
     return ISCI_OK;
 }
 
@@ -906,7 +921,7 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
         st = build_tiles(c, eri, stream);
-        if (st == ISCI_OK) st = build_vv(c, stream);
+        if (st == ISCI_OK) st = build_abx(c, stream);
         if (st == ISCI_OK) st = build_hscreen(c, h, stream);
         if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }

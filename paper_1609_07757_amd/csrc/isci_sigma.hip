@@ -407,8 +407,7 @@ __device__ __forceinline__ void gather_b(const SigmaArgs &A, const double *__res
 // through LDS and sigma is written once (no atomics).
 template <int NV, bool TAB>
 __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, const double *__restrict__ c,
-                                                       int64_t ldc, double *__restrict__ sg, int64_t lds,
-                                                       const uchar4 *__restrict__ quads, int accumulate)
+                                                       int64_t ldc, double *__restrict__ sg, int64_t lds)
 {
     constexpr size_t kTileBytes = sizeof(double) * 4 * NV * 16 * 17;
     constexpr size_t kTabBytes = TAB ? (size_t)4 * 4 * kTabMax * (sizeof(long long) + 2 * sizeof(int)) : 16;
@@ -418,7 +417,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     int *rl_all = reinterpret_cast<int *>(smem + (size_t)4 * 4 * kTabMax * sizeof(long long));
     int *bi_all = rl_all + 4 * 4 * kTabMax;
 
-    const uchar4 qd = quads[blockIdx.x];
+    const uchar4 qd = A.quads[blockIdx.x];
     const int X = qd.x, P = qd.y, Y = qd.z, R = qd.w;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool sameA = X == P, sameB = Y == R;
@@ -452,10 +451,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
         const int row = Ab * nb + Bb;
         const int e0 = A.chunk_off[row];
         int e1 = e0;
-        // with the vv|vv product path, all-virtual chunks (class 2 of a
-        // virtual row block pair) are left to it
-        const int lmax = (A.vv_split && Ab != 0 && Bb != 0) ? 1 : 2;
-        for (int l = 0; l <= lmax; ++l)
+        for (int l = 0; l < 3; ++l)
             if (espec + l <= L) e1 += A.chunk_cls[row * 3 + l];
         int e = e0;
         for (; e + 4 <= e1; e += 4) {
@@ -506,10 +502,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
         if (v >= nv) break;
         const double val = tile[0][v][ip * 4 + ir][ix * 4 + iy] - tile[t1][v][ix * 4 + ir][ip * 4 + iy]
                          - tile[t2][v][ip * 4 + iy][ix * 4 + ir] + tile[t3][v][ix * 4 + iy][ip * 4 + ir];
-        if (accumulate)
-            dst[v * lds] += val;
-        else
-            dst[v * lds] = val;
+        dst[v * lds] = val;
     }
 }
 
@@ -742,36 +735,25 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
         const double *cc = cv + (int64_t)v0 * ldc;
         double *ss = sv + (int64_t)v0 * lds;
         if (A.variant == 3) {
-            // Matrix-core path.  With the one-body products and the vv|vv
-            // product available, the beta one-body kernels write sigma
-            // (every determinant once) and everything else adds: the
-            // gathered alpha-beta kernel then runs only on target tiles
-            // with work outside vv|vv.  Otherwise the gathered alpha-beta
-            // kernel writes sigma over all tiles first.
-            const bool rest_mode = c->have_vv && onebody_mfma_ok(c);
-            if (rest_mode) {
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
-                ISCI_CHECK(launch_onebody_mfma(c, ISCI_OB_BETA_INIT, nv, cc, ldc, ss, lds, s));
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
-            }
-            const uchar4 *qlist = rest_mode ? c->d.rest_quads : c->d.quads;
-            const int nq = rest_mode ? c->nrestquad : c->nquad;
+            // Matrix-core path: the alpha-beta class writes sigma (as the
+            // unfold / block-sparse product / fold path when its operands
+            // fit, else with the gathered tile kernel), then the one-body
+            // and same-spin classes add.
             for (int u0 = 0; u0 < nv; u0 += 4) {
                 const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                if (nq > 0) {
+                if (c->have_abx) {
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_PROD, true, s));
+                    ISCI_CHECK(launch_ab_product(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_PROD, false, s));
+                } else if (c->nquad > 0) {
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
                     if (c->norb <= kTabMax)
-                        k_sigma_ab_mfma<4, true><<<nq, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                     ss + (int64_t)u0 * lds, lds, qlist, rest_mode);
+                        k_sigma_ab_mfma<4, true><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                           ss + (int64_t)u0 * lds, lds);
                     else
-                        k_sigma_ab_mfma<4, false><<<nq, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                      ss + (int64_t)u0 * lds, lds, qlist, rest_mode);
+                        k_sigma_ab_mfma<4, false><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                            ss + (int64_t)u0 * lds, lds);
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
-                }
-                if (c->have_vv) {
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_VV, true, s));
-                    ISCI_CHECK(launch_ab_vv(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_VV, false, s));
                 }
             }
             if (c->d.hscreen) {
@@ -780,7 +762,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                 // then same-spin if any
                 ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
                 if (onebody_mfma_ok(c)) {
-                    ISCI_CHECK(launch_onebody_mfma(c, rest_mode ? ISCI_OB_ALPHA : ISCI_OB_BOTH, nv, cc, ldc, ss, lds, s));
+                    ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
                 } else {
                     const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
                     for (int u0 = 0; u0 < nv; u0 += 4) {
