@@ -43,7 +43,8 @@ typedef double v4d_ab __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
 __device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
 
-// row kr = 4 * (T row block) + k of T; thread per column
+// row kr = 4 * (T row block) + k of T; thread per column (enough threads
+// in flight to cover the chain column descriptor -> tables -> CI element)
 __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const double *__restrict__ c, int64_t ldc)
 {
     const int kr = blockIdx.y;

@@ -197,9 +197,16 @@ __global__ __launch_bounds__(64 * NT) void k_ob_alpha(SigmaArgs A, const double 
     const int jlim = x < 2 ? jlim_occ : jlim_virt;
     const int j0 = blockIdx.y * 64;
     if (j0 >= jlim) return;
+    // row starts and lengths of {o, x} in LDS: the operand loads below then
+    // depend on no other global load
+    __shared__ long long rb[NP];
+    __shared__ int rl[NP];
+    for (int t = threadIdx.x; t < NP; t += 64 * NT) {
+        rb[t] = t < norb ? A.arow_base[x * norb + t] : -1;
+        rl[t] = t < norb ? A.arow_len[x * norb + t] : 0;
+    }
+    __syncthreads();
     const int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long *__restrict__ rb = A.arow_base + x * norb;
-    const int *__restrict__ rl = A.arow_len + x * norb;
     // this wave's targets {a, x} on the requested side of x that hold a
     // column of the block, and the sources {q, x} that hold one
     const int at = 16 * mt + (lane & 15);
