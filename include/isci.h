@@ -232,6 +232,13 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_SIGMA_GENERAL 1
 #define ISCI_SIGMA_PAIR 2
 #define ISCI_SIGMA_MFMA 3   /* FP64 matrix cores for the alpha-beta and one-body classes, pair kernel for same-spin */
+/*   ISCI_OPT_AB_PATH (matrix-core path only): ISCI_AB_AUTO (default: the
+ *   unfold / block-sparse product / fold path whenever its operands were
+ *   built, i.e. fit in 2 GiB), ISCI_AB_GATHER (the gathered tile kernel).
+ *   Both give the same sigma up to rounding. */
+#define ISCI_OPT_AB_PATH 2
+#define ISCI_AB_AUTO 0
+#define ISCI_AB_GATHER 1
 isci_status isci_set_option(isci_handle hd, int option, int value);
 
 /* Kernel timing hook (for measurement).  When enabled, HIP events are

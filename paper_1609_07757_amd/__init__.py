@@ -19,10 +19,13 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "lib_path", "BUCKET_NAMES", "Engine", "isci_engine_create", "isci_engine_config",
            "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
-           "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA"]
+           "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
+           "AB_GATHER"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
+OPT_AB_PATH = 2
+AB_AUTO, AB_GATHER = 0, 1
 
 
 def isci_set_option(hd, option: int, value: int):

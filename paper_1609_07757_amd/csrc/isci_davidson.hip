@@ -23,7 +23,7 @@
 
 namespace isci {
 
-constexpr int kDotBlocks = 512;
+constexpr int kDotBlocks = 256;
 constexpr int kTile = 8;
 
 // partial[(blk * m + i) * k + j] = sum_{t in blk's range} A_i[t] B_j[t]
@@ -67,23 +67,36 @@ __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ A, int6
     }
 }
 
-__global__ void k_dots_reduce(const double *__restrict__ partial, int nblk, int mk, double *__restrict__ out)
+// one wave per output: lanes stride over the block partials, then a
+// shuffle tree (fixed order for a given block count)
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ partial, int nblk, int mk, int e,
+                                                    int lane)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mk) return;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * mk + e];
-    out[e] = s;
+    for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)b * mk + e];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
 }
 
-int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
+__global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ partial, int nblk, int mk,
+                                                     double *__restrict__ out)
+{
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= mk) return;
+    const double s = wave_sum_partials(partial, nblk, mk, e, lane);
+    if (lane == 0) out[e] = s;
+}
+
+// partial-sum blocks for a dot product of length n: about 2048 elements
+// (8 per thread) per block, at most kDotBlocks
+int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 2047) / 2048)); }
 
 isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int k, int64_t n,
                  double *out_dev, double *partial, int nblk, hipStream_t s)
 {
     dim3 grid(nblk, (m + kTile - 1) / kTile, (k + kTile - 1) / kTile);
     k_dots<<<grid, 256, 0, s>>>(A, lda, m, B, ldb, k, n, partial);
-    k_dots_reduce<<<(m * k + 255) / 256, 256, 0, s>>>(partial, nblk, m * k, out_dev);
+    k_dots_reduce<<<(m * k + 3) / 4, 256, 0, s>>>(partial, nblk, m * k, out_dev);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }
@@ -276,15 +289,14 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
     }
 }
 
-__global__ void k_bdots_reduce(const BDot *__restrict__ jobs)
+__global__ __launch_bounds__(256) void k_bdots_reduce(const BDot *__restrict__ jobs)
 {
     const BDot J = jobs[blockIdx.z];
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int mk = J.m * J.k;
     if (e >= mk) return;
-    double s = 0.0;
-    for (int b = 0; b < J.nblk; ++b) s += J.partial[(int64_t)b * mk + e];
-    J.out[e] = s;
+    const double s = wave_sum_partials(J.partial, J.nblk, mk, e, lane);
+    if (lane == 0) J.out[e] = s;
 }
 
 struct BLin {              // out_j[t] = beta out_j[t] + sign * sum_i V_i[t] Y[j*m + i]
@@ -734,7 +746,7 @@ static isci_status launch_bdots(const BDot *d, const std::vector<BDot> &h, hipSt
         mk = std::max(mk, j.m * j.k);
     }
     k_bdots<<<dim3(gx, ti * tj, (unsigned)h.size()), 256, 0, s>>>(d, tj);
-    k_bdots_reduce<<<dim3((mk + 255) / 256, 1, (unsigned)h.size()), 256, 0, s>>>(d);
+    k_bdots_reduce<<<dim3((mk + 3) / 4, 1, (unsigned)h.size()), 256, 0, s>>>(d);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }

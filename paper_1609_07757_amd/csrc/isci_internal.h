@@ -159,6 +159,7 @@ struct isci_ctx {
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int nblk = 0, nchunk = 0, nquad = 0;
     bool have_abx = false;   // alpha-beta product path built
+    bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;

@@ -977,6 +977,10 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         }
         c->sigma_variant = value;
         return ISCI_OK;
+    case ISCI_OPT_AB_PATH:
+        if (value != ISCI_AB_AUTO && value != ISCI_AB_GATHER) { set_error("bad alpha-beta path"); return ISCI_E_INVALID; }
+        c->ab_gather = value == ISCI_AB_GATHER;
+        return ISCI_OK;
     default:
         set_error("unknown option");
         return ISCI_E_INVALID;

@@ -21,7 +21,11 @@ def create(h, eri, norb, na, nb, L, tau, variant=0):
     hd = isci.isci_create(ht, et, norb, na, nb, L, tau)
     torch.cuda.synchronize()
     del ht, et
-    if variant:
+    if variant == 4:
+        # matrix-core path with the gathered alpha-beta tile kernel
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA)
+        isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_GATHER)
+    elif variant:
         isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
     return hd
 

@@ -44,14 +44,17 @@ CASES = [
     ("B", 16, 2, 2, 3, 1e-12, 17),
     ("B", 26, 2, 2, 3, 1e-12, 2),  # 26 orbitals: two 16-orbital tiles, ragged
     ("A", 72, 2, 2, 2, 1e-12, 3),  # 72 orbitals: five 16-orbital tiles
+    ("A", 90, 2, 2, 2, 1e-12, 2),  # above the one-body matrix-core limit (80 orbitals)
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
 def test_sigma_parity(case, variant):
-    """variant 1: general string kernel; 2: pair tables; 3: pair tables +
-    MFMA alpha-beta tiles (2 and 3 need two electrons per spin)."""
+    """variant 1: general string kernel; 2: pair tables; 3: matrix-core
+    path (alpha-beta unfold / product / fold, one-body products); 4: matrix-
+    core path with the gathered alpha-beta tile kernel (2-4 need two
+    electrons per spin)."""
     recipe, norb, na, nb, L, tau, nvec = case
     if variant > 1 and not (na == 2 and nb == 2):
         pytest.skip("pair kernels need two electrons per spin")
@@ -155,12 +158,12 @@ def test_hermiticity_large():
     assert abs(a - b) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * max(1.0, np.abs(s).max())
 
 
-@pytest.mark.parametrize("variant", [3, 2, 1])
+@pytest.mark.parametrize("variant", [3, 4, 2, 1])
 @pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 1), ("cisdt_n30", 600, 2),
                                            ("cisdt_n60", 300, 8), ("fci_n48", 200, 8)])
 def test_sigma_workloads(wl, nsamp, nvec, variant):
     """Named workloads (recipe A): full comparison for the small one, sampled
-    targets (row ends included) at full size for the others; both kernels."""
+    targets (row ends included) at full size for the others; every path."""
     from isci_inputs import workload
     W = workload(wl)
     h, eri = W.integrals()
@@ -199,3 +202,18 @@ def test_pair_kernel_rejected_for_other_electron_counts():
     hd = create(h, eri, 7, 3, 2, 2, 0.0)
     with pytest.raises(isci.IsciError):
         isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, isci.SIGMA_PAIR)
+
+
+def test_ab_path_option():
+    import paper_1609_07757_amd as isci
+    h, eri = recipe_b(9, seed=1)
+    hd = create(h, eri, 9, 2, 2, 2, 0.0, 3)
+    with pytest.raises(isci.IsciError):
+        isci.isci_set_option(hd, isci.OPT_AB_PATH, 7)
+    c = random_vectors(hd.dim, 3, seed=2)
+    a = gpu_sigma(hd, c)
+    isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_GATHER)
+    b = gpu_sigma(hd, c)
+    isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_AUTO)
+    assert rel_err(b, a) <= TOL
+    assert np.array_equal(gpu_sigma(hd, c), a)   # same path again: bit-identical
