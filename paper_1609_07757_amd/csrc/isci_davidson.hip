@@ -771,6 +771,44 @@ static int64_t max_n(const std::vector<J> &h)
     return n;
 }
 
+// Cholesky QR coefficients of a block X of p columns from its Gram matrix G
+// (p x p, row major): columns are taken in order, and column i is dropped
+// when its norm after removing the kept earlier columns is <= thr[i].
+// C receives q x p coefficients (C[j * p + i]: weight of X_i in output j)
+// with X C^T orthonormal; returns q.
+static int chol_qr_coeffs(int p, const double *G, const double *thr, std::vector<double> &C)
+{
+    std::vector<double> R((size_t)p * p, 0.0);
+    std::vector<int> kept;
+    for (int i = 0; i < p; ++i) {
+        double d = G[(size_t)i * p + i];
+        for (int k : kept) d -= R[(size_t)k * p + i] * R[(size_t)k * p + i];
+        if (!(d > thr[i] * thr[i]) || !(d > 0.0)) continue;
+        const double rii = sqrt(d);
+        R[(size_t)i * p + i] = rii;
+        for (int jj = i + 1; jj < p; ++jj) {
+            double v = G[(size_t)i * p + jj];
+            for (int k : kept) v -= R[(size_t)k * p + i] * R[(size_t)k * p + jj];
+            R[(size_t)i * p + jj] = v / rii;
+        }
+        kept.push_back(i);
+    }
+    const int q = (int)kept.size();
+    C.assign((size_t)q * p, 0.0);
+    for (int a = 0; a < q; ++a) {
+        const int i = kept[a];
+        double *c = &C[(size_t)a * p];
+        c[i] = 1.0;
+        for (int b = 0; b < a; ++b) {
+            const double r = R[(size_t)kept[b] * p + i];
+            const double *cb = &C[(size_t)b * p];
+            for (int t = 0; t < p; ++t) c[t] -= r * cb[t];
+        }
+        for (int t = 0; t < p; ++t) c[t] /= R[(size_t)i * p + i];
+    }
+    return q;
+}
+
 // one Davidson iteration for every active slot
 static isci_status engine_step(isci_engine e, int *nactive)
 {
@@ -785,7 +823,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
     const int na = (int)act.size();
     // results needed this step: G columns, residual Gram matrices, CGS2 scalars
     size_t need = 0;
-    for (Slot *sl : act) need += (size_t)sl->m * (sl->m - sl->mdone) + (size_t)sl->kk * sl->kk + 3 * (sl->block + 1);
+    for (Slot *sl : act) need += (size_t)sl->m * (sl->m - sl->mdone) + (size_t)sl->kk * sl->kk + 3 * (size_t)sl->block * sl->block;
     if (!res_reserve(e, need + 64)) { set_error("allocation failed (engine results)"); return ISCI_E_OOM; }
 
     // ---- phase B: new columns of G = V^T W_new, all slots in one launch pair
@@ -932,99 +970,139 @@ static isci_status engine_step(isci_engine e, int *nactive)
         }
         grow_set.push_back(sl);
     }
-    // ---- phase D: CGS2 of the corrections, round i appends the i-th
-    // correction of every slot that has one (no host round trip inside)
+    // ---- phase D: the picked corrections of every slot are appended as a
+    // block: classical Gram-Schmidt against the basis applied twice (CGS2),
+    // then Cholesky QR applied twice inside the block.  A correction whose
+    // norm after the projections falls to 1e-10 of its norm before is in
+    // the span and dropped.  Every launch serves all slots.
     if (grow_set.empty()) return ISCI_OK;
-    struct Round { std::vector<BVecOp> cp, nz; std::vector<BDot> n0, c1, c2, n1; std::vector<BLin> l1, l2; };
-    std::vector<Round> rounds;
-    std::vector<int> m0(grow_set.size()), nadd(grow_set.size(), 0);
-    std::vector<size_t> offS(grow_set.size());
+    const size_t ng = grow_set.size();
+    std::vector<int> m0(ng), np(ng);
+    std::vector<size_t> offG0(ng), offG1(ng), offG2(ng);
     size_t rs = rC;
-    for (size_t j = 0; j < grow_set.size(); ++j) {
-        m0[j] = grow_set[j]->m;
-        offS[j] = rs;
-        rs += 3 * grow_set[j]->pick.size();
+    for (size_t j = 0; j < ng; ++j) {
+        Slot *sl = grow_set[j];
+        m0[j] = sl->m;
+        np[j] = std::max(0, std::min((int)sl->pick.size(), sl->mmax - sl->m));
+        const size_t p2 = (size_t)np[j] * np[j];
+        offG0[j] = rs; rs += p2;
+        offG1[j] = rs; rs += p2;
+        offG2[j] = rs; rs += p2;
     }
-    size_t maxpick = 0;
-    for (Slot *sl : grow_set) maxpick = std::max(maxpick, sl->pick.size());
-    for (size_t i = 0; i < maxpick; ++i) {
-        Round R;
-        for (size_t j = 0; j < grow_set.size(); ++j) {
+    if (!res_reserve(e, rs + 64)) { set_error("allocation failed (engine results)"); return ISCI_E_OOM; }
+    // D1: copy, pre-norm Gram, two projections, Gram of the projected block
+    {
+        std::vector<BVecOp> cp;
+        std::vector<BDot> g0, c1, c2, g1;
+        std::vector<BLin> l1, l2;
+        for (size_t j = 0; j < ng; ++j) {
             Slot *sl = grow_set[j];
-            if (i >= sl->pick.size() || sl->m >= sl->mmax) continue;
-            double *dst = sl->V + (size_t)sl->m * sl->dim;
-            const double *src = sl->T + (size_t)sl->pick[i] * sl->dim;
-            double *sc = e->res_d + offS[j] + 3 * i;
-            R.cp.push_back(BVecOp{src, dst, nullptr, nullptr, nullptr, sl->dim});
+            const int p = np[j], m = m0[j];
+            if (p == 0) continue;
+            double *X = sl->V + (size_t)m * sl->dim;
+            for (int i = 0; i < p; ++i)
+                cp.push_back(BVecOp{sl->T + (size_t)sl->pick[i] * sl->dim, X + (size_t)i * sl->dim, nullptr, nullptr,
+                                    nullptr, sl->dim});
             BDot d;
             d.partial = sl->partial; d.lda = sl->dim; d.ldb = sl->dim; d.n = sl->dim; d.nblk = sl->nblk;
-            d.A = dst; d.B = dst; d.out = sc; d.m = 1; d.k = 1;
-            R.n0.push_back(d);
-            d.A = sl->V; d.B = dst; d.out = sl->small; d.m = sl->m; d.k = 1;
-            if (sl->m > 0) {
-                R.c1.push_back(d);
-                R.c2.push_back(d);
-                R.l1.push_back(BLin{sl->V, sl->small, dst, sl->dim, sl->dim, sl->dim, sl->m, 1, 1.0, -1.0});
-                R.l2.push_back(BLin{sl->V, sl->small, dst, sl->dim, sl->dim, sl->dim, sl->m, 1, 1.0, -1.0});
+            d.A = X; d.B = X; d.m = p; d.k = p;
+            d.out = e->res_d + offG0[j];
+            g0.push_back(d);
+            d.out = e->res_d + offG1[j];
+            g1.push_back(d);
+            if (m > 0) {
+                d.A = X; d.B = sl->V; d.m = p; d.k = m; d.out = sl->small;   // Y[q * m + i] = X_q . V_i
+                c1.push_back(d);
+                c2.push_back(d);
+                l1.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0});
+                l2.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0});
             }
-            d.A = dst; d.B = dst; d.out = sc + 1; d.m = 1; d.k = 1;
-            R.n1.push_back(d);
-            R.nz.push_back(BVecOp{nullptr, dst, sc, sc + 1, sc + 2, sl->dim});
-            sl->m += 1;
-            nadd[j] += 1;
         }
-        rounds.push_back(std::move(R));
-    }
-    {
         ArenaPack ap{e};
-        struct Offs { size_t cp, nz, n0, c1, c2, n1, l1, l2; };
-        std::vector<Offs> of;
-        for (Round &R : rounds)
-            of.push_back(Offs{ap.push(R.cp), ap.push(R.nz), ap.push(R.n0), ap.push(R.c1), ap.push(R.c2),
-                              ap.push(R.n1), ap.push(R.l1), ap.push(R.l2)});
+        const size_t ocp = ap.push(cp), og0 = ap.push(g0), oc1 = ap.push(c1), oc2 = ap.push(c2), og1 = ap.push(g1),
+                     ol1 = ap.push(l1), ol2 = ap.push(l2);
         if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
-        for (size_t i = 0; i < rounds.size(); ++i) {
-            Round &R = rounds[i];
-            arena_put(e, of[i].cp, R.cp); arena_put(e, of[i].nz, R.nz); arena_put(e, of[i].n0, R.n0);
-            arena_put(e, of[i].c1, R.c1); arena_put(e, of[i].c2, R.c2); arena_put(e, of[i].n1, R.n1);
-            arena_put(e, of[i].l1, R.l1); arena_put(e, of[i].l2, R.l2);
-        }
+        BVecOp *dcp = arena_put(e, ocp, cp);
+        BDot *dg0 = arena_put(e, og0, g0), *dc1 = arena_put(e, oc1, c1), *dc2 = arena_put(e, oc2, c2),
+             *dg1 = arena_put(e, og1, g1);
+        BLin *dl1 = arena_put(e, ol1, l1), *dl2 = arena_put(e, ol2, l2);
         ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
-        for (size_t i = 0; i < rounds.size(); ++i) {
-            Round &R = rounds[i];
-            if (R.cp.empty()) continue;
-            const unsigned gz = (unsigned)R.cp.size();
-            const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(R.cp) + 255) / 256);
-            k_bcopy<<<dim3(gx, 1, gz), 256, 0, s>>>((const BVecOp *)(e->arena_d + of[i].cp));
-            ISCI_HIP(hipGetLastError());
-            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].n0), R.n0, s)) != ISCI_OK) return st;
-            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].c1), R.c1, s)) != ISCI_OK) return st;
-            if ((st = launch_blincomb((const BLin *)(e->arena_d + of[i].l1), R.l1, s)) != ISCI_OK) return st;
-            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].c2), R.c2, s)) != ISCI_OK) return st;
-            if ((st = launch_blincomb((const BLin *)(e->arena_d + of[i].l2), R.l2, s)) != ISCI_OK) return st;
-            if ((st = launch_bdots((const BDot *)(e->arena_d + of[i].n1), R.n1, s)) != ISCI_OK) return st;
-            k_bnormalize<<<dim3(gx, 1, gz), 256, 0, s>>>((const BVecOp *)(e->arena_d + of[i].nz), 1e-10);
+        if (!cp.empty()) {
+            const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(cp) + 255) / 256);
+            k_bcopy<<<dim3(gx, 1, (unsigned)cp.size()), 256, 0, s>>>(dcp);
             ISCI_HIP(hipGetLastError());
         }
+        if ((st = launch_bdots(dg0, g0, s)) != ISCI_OK) return st;
+        if ((st = launch_bdots(dc1, c1, s)) != ISCI_OK) return st;
+        if ((st = launch_blincomb(dl1, l1, s)) != ISCI_OK) return st;
+        if ((st = launch_bdots(dc2, c2, s)) != ISCI_OK) return st;
+        if ((st = launch_blincomb(dl2, l2, s)) != ISCI_OK) return st;
+        if ((st = launch_bdots(dg1, g1, s)) != ISCI_OK) return st;
         ISCI_HIP(hipMemcpyAsync(e->res_h + rC, e->res_d + rC, sizeof(double) * std::max<size_t>(rs - rC, 1),
                                 hipMemcpyDeviceToHost, s));
         ISCI_HIP(hipStreamSynchronize(s));
     }
-    for (size_t j = 0; j < grow_set.size(); ++j) {
-        Slot *sl = grow_set[j];
-        // drop appended vectors whose normalisation factor is 0 (in the span)
-        const int64_t dim = sl->dim;
-        int w = m0[j];
-        for (int i = 0; i < nadd[j]; ++i) {
-            const bool keep = e->res_h[offS[j] + 3 * i + 2] != 0.0;
-            if (!keep) continue;
-            if (w != m0[j] + i)
-                ISCI_HIP(hipMemcpyAsync(sl->V + (size_t)w * dim, sl->V + (size_t)(m0[j] + i) * dim,
-                                        sizeof(double) * dim, hipMemcpyDeviceToDevice, s));
-            ++w;
+    // D2 / D3: Cholesky QR of the projected block (columns in the span
+    // dropped), then once more on the result
+    std::vector<int> nq(ng, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<double> params;
+        std::vector<size_t> offC(ng);
+        std::vector<int> nout(ng, 0);
+        for (size_t j = 0; j < ng; ++j) {
+            const int p = pass == 0 ? np[j] : nq[j];
+            if (p == 0) continue;
+            const double *Gp = e->res_h + (pass == 0 ? offG1[j] : offG2[j]);
+            std::vector<double> thr(p);
+            for (int i = 0; i < p; ++i)
+                thr[i] = pass == 0 ? 1e-10 * sqrt(std::max(0.0, e->res_h[offG0[j] + (size_t)i * p + i])) : 1e-8;
+            std::vector<double> C;
+            nout[j] = chol_qr_coeffs(p, Gp, thr.data(), C);
+            offC[j] = params.size();
+            params.insert(params.end(), C.begin(), C.end());
         }
-        sl->m = w;
-        if (w == m0[j]) {   // stagnation: no new direction
+        std::vector<BLin> lq;
+        std::vector<BDot> g2;
+        ArenaPack ap{e};
+        const size_t opar = ap.push(params);
+        std::vector<BLin> lq_sz(ng);
+        std::vector<BDot> g2_sz(ng);
+        const size_t olq = ap.push(lq_sz), og2 = ap.push(g2_sz);
+        if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
+        const double *pd = (const double *)(e->arena_d + opar);
+        for (size_t j = 0; j < ng; ++j) {
+            Slot *sl = grow_set[j];
+            const int p = pass == 0 ? np[j] : nq[j], q = nout[j];
+            if (p == 0 || q == 0) continue;
+            double *X = sl->V + (size_t)m0[j] * sl->dim;
+            // pass 0: X (p columns) -> T (q columns); pass 1: T -> X
+            const double *src = pass == 0 ? X : sl->T;
+            double *dst = pass == 0 ? sl->T : X;
+            lq.push_back(BLin{src, pd + offC[j], dst, sl->dim, sl->dim, sl->dim, p, q, 0.0, 1.0});
+            if (pass == 0) {
+                BDot d;
+                d.partial = sl->partial; d.lda = sl->dim; d.ldb = sl->dim; d.n = sl->dim; d.nblk = sl->nblk;
+                d.A = sl->T; d.B = sl->T; d.m = q; d.k = q; d.out = e->res_d + offG2[j];
+                g2.push_back(d);
+            }
+        }
+        arena_put(e, opar, params);
+        BLin *dlq = arena_put(e, olq, lq);
+        BDot *dg2 = arena_put(e, og2, g2);
+        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        if ((st = launch_blincomb(dlq, lq, s)) != ISCI_OK) return st;
+        if (pass == 0) {
+            if ((st = launch_bdots(dg2, g2, s)) != ISCI_OK) return st;
+            ISCI_HIP(hipMemcpyAsync(e->res_h + rC, e->res_d + rC, sizeof(double) * std::max<size_t>(rs - rC, 1),
+                                    hipMemcpyDeviceToHost, s));
+            ISCI_HIP(hipStreamSynchronize(s));
+        }
+        for (size_t j = 0; j < ng; ++j) nq[j] = nout[j];
+    }
+    for (size_t j = 0; j < ng; ++j) {
+        Slot *sl = grow_set[j];
+        sl->m = m0[j] + nq[j];
+        if (nq[j] == 0) {   // stagnation: no new direction
             sl->done = true;
             sl->status = sl->conv ? ISCI_OK : ISCI_E_NOT_CONVERGED;
         }
