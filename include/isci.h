@@ -253,8 +253,9 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
 #define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
 #define ISCI_KERNEL_ONEBODY 4   /* one-body classes, two electrons per spin (matrix-core products, or
                                    k_onebody_a + k_onebody_b above 80 orbitals) */
-#define ISCI_KERNEL_AB_PROD 5   /* k_ab_unfold + k_ab_gemm + k_ab_fold: alpha-beta class as a block-sparse
-                                   product on matrix cores (two electrons per spin) */
+#define ISCI_KERNEL_AB_UNFOLD 5 /* k_ab_unfold: alpha-beta class, CI block unfolded into the product operand */
+#define ISCI_KERNEL_AB_GEMM 6   /* k_ab_gemm: alpha-beta class, block-sparse product on matrix cores */
+#define ISCI_KERNEL_AB_FOLD 7   /* k_ab_fold: alpha-beta class, role readings summed into sigma */
 isci_status isci_profile(isci_handle hd, int enable);
 isci_status isci_profile_read(isci_handle hd, int kernel, double *total_ms, int64_t *launches);
 

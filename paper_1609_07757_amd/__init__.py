@@ -318,7 +318,7 @@ def isci_davidson_footprint(hd: Handle, nroots: int = 1, **opts) -> int:
 
 
 KERNEL_NAMES = {0: "k_sigma_generic", 1: "k_sigma_n2", 2: "k_sigma_ab_mfma", 3: "k_sigma_n2(same-spin)",
-                4: "onebody", 5: "k_ab_unfold+gemm+fold"}
+                4: "onebody", 5: "k_ab_unfold", 6: "k_ab_gemm", 7: "k_ab_fold"}
 
 
 def isci_profile(hd: Handle, enable: bool = True):

@@ -172,12 +172,20 @@ isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64
                               hipStream_t st)
 {
     const SigmaArgs A = sigma_args(cx);
-    if (cx->abx_ntrow > 0)
+    if (cx->abx_ntrow > 0) {
+        ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
         k_ab_unfold<<<dim3((unsigned)((cx->abx_pcols[0] + 255) / 256), (unsigned)(4 * cx->abx_ntrow)), 256, 0, st>>>(
             A, nv, c, ldc);
-    if (cx->abx_nrows > 0)
+        ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, false, st));
+    }
+    if (cx->abx_nrows > 0) {
+        ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
         k_ab_gemm<<<dim3((unsigned)cx->abx_nrows, (unsigned)((cx->abx_pcols[0] + 255) / 256)), 256, 0, st>>>(A);
+        ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
+    }
+    ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));
     k_ab_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, s, lds);
+    ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, false, st));
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }

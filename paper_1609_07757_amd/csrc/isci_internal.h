@@ -12,7 +12,7 @@
 #define ISCI_MAXN 4          // electrons per spin handled by the kernels
 #define ISCI_MAXNORB 255     // orbitals fit in one byte
 #define ISCI_MAXLEV 8        // level tables sized for 2 * ISCI_MAXN
-#define ISCI_NKERNEL_IDS 6   // ISCI_KERNEL_* ids of the timing hook
+#define ISCI_NKERNEL_IDS 8   // ISCI_KERNEL_* ids of the timing hook
 
 namespace isci {
 

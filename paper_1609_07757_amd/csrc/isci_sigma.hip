@@ -742,9 +742,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             for (int u0 = 0; u0 < nv; u0 += 4) {
                 const int nu = nv - u0 < 4 ? nv - u0 : 4;
                 if (c->have_abx && !c->ab_gather) {
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_PROD, true, s));
                     ISCI_CHECK(launch_ab_product(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_PROD, false, s));
                 } else if (c->nquad > 0) {
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
                     if (c->norb <= kTabMax)
