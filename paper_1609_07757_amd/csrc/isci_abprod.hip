@@ -40,6 +40,9 @@ namespace isci {
 
 typedef double v4d_ab __attribute__((ext_vector_type(4)));
 
+// chunk-list parts per product tile (waves per tile = 4 * kAbSplit)
+constexpr int kAbSplit = 2;
+
 __device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
 __device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
 
@@ -70,27 +73,44 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
     A.abx_T[(size_t)tr.z + (size_t)k * width + col] = val;
 }
 
-// S for row block pair abx_rows[blockIdx.x] and columns blockIdx.y * 256 + [0, 256)
-__global__ __launch_bounds__(256) void k_ab_gemm(SigmaArgs A)
+// S for one row block pair and 256 columns (one tile).  The tiles, ordered
+// by row block pair, are split at setup into eight contiguous runs of
+// about equal work; workgroups are dealt to the eight XCDs round-robin,
+// so workgroup b takes tile b / 8 of run b % 8: each XCD sweeps
+// neighbouring row block pairs, whose chunks read largely the same rows
+// of T, through its own L2.  Within a tile, wave w takes the 64 columns
+// (w % 4) and the (w / 4)-th of KS contiguous parts of the chunk list
+// (more waves in flight per tile); the parts are summed through LDS in a
+// fixed order.
+template <int KS>
+__global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
 {
+    __shared__ double red[KS > 1 ? KS - 1 : 1][4][16][64];
     const int nb = A.nblk;
-    const int g = A.abx_rows[blockIdx.x];
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int t = A.abx_xrun[xcd] + local;
+    if (t >= A.abx_xrun[xcd + 1]) return;
+    const int2 tl = A.abx_tiles[t];   // (row block pair, column slab)
+    const int g = tl.x;
     const int Ab = g / nb, Bb = g % nb;
     const int m = (Ab != 0) + (Bb != 0);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c0 = blockIdx.y * 256 + wave * 64;
+    const int cw = wave & 3, part = wave >> 2;
+    const int c0 = tl.y * 256 + cw * 64;
     const int swidth = A.abx_pcols[m];
-    if (c0 >= swidth) return;
+    const bool active = c0 < swidth;
     // chunks whose class keeps these columns valid: classes l with
     // c0 < pcols[max(l, m)], a prefix of the class-ordered list
-    const int e0 = A.chunk_off[g];
-    int e1 = e0;
+    const int eb = A.chunk_off[g];
+    int ee = eb;
     for (int l = 0; l < 3; ++l)
-        if (c0 < A.abx_pcols[max(l, m)]) e1 += A.chunk_cls[g * 3 + l];
+        if (c0 < A.abx_pcols[max(l, m)]) ee += A.chunk_cls[g * 3 + l];
+    const int e0 = eb + (int)((long long)(ee - eb) * part / KS);
+    const int e1 = eb + (int)((long long)(ee - eb) * (part + 1) / KS);
     const int k = lane >> 4, n = lane & 15;
     v4d_ab acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = v4d_ab{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < 4; ++u) acc[u] = v4d_ab{0.0, 0.0, 0.0, 0.0};
     // two stages of two chunks, ping-ponged; loads are unconditional
     // (clamped chunk index, zero selected past the end) so waiting for one
     // stage never waits for the other
@@ -104,16 +124,16 @@ __global__ __launch_bounds__(256) void k_ab_gemm(SigmaArgs A)
             const double av = A.chunk_val[(size_t)eu * 64 + lane];
             a[u] = e + u < e1 ? av : 0.0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b[u][t] = src[16 * t];
+            for (int q = 0; q < 4; ++q) b[u][q] = src[16 * q];
         }
     };
     auto mma2 = [&](const double *a, const double (*b)[4]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][q], acc[q], 0, 0, 0);
     };
-    if (e0 < e1) {
+    if (active && e0 < e1) {
         load2(e0, ax, bx);
         for (int e = e0; e < e1; e += 4) {
             load2(e + 2, ay, by);
@@ -122,12 +142,28 @@ __global__ __launch_bounds__(256) void k_ab_gemm(SigmaArgs A)
             mma2(ay, by);
         }
     }
+    if (KS > 1) {
+        if (part > 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) red[part - 1][cw][4 * q + gg][lane] = acc[q][gg];
+        __syncthreads();
+        if (part > 0) return;
+#pragma unroll
+        for (int p2 = 0; p2 < KS - 1; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) acc[q][gg] += red[p2][cw][4 * q + gg][lane];
+    }
+    if (!active) return;
     // element gg of lane l: row 4 gg + l / 16 (alpha active slot gg, beta active slot l / 16), column l % 16
     double *Sb = A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + n;
 #pragma unroll
     for (int gg = 0; gg < 4; ++gg)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) Sb[(size_t)gg * 4 * swidth + 16 * t] = acc[t][gg];
+        for (int q = 0; q < 4; ++q) Sb[(size_t)gg * 4 * swidth + 16 * q] = acc[q][gg];
 }
 
 // sigma({a0 < a1}, {b0 < b1}) = sum over the four readings (alpha
@@ -180,7 +216,7 @@ isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64
     }
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
-        k_ab_gemm<<<dim3((unsigned)cx->abx_nrows, (unsigned)((cx->abx_pcols[0] + 255) / 256)), 256, 0, st>>>(A);
+        k_ab_gemm<kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 256 * kAbSplit, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));

@@ -89,6 +89,8 @@ struct DevTabs {
     int2 *abx_chunk = nullptr;
     int *abx_rows = nullptr;
     long long *abx_soff = nullptr;
+    int2 *abx_tiles = nullptr;      // product tiles (row block pair, 256-column slab)
+    int *abx_xrun = nullptr;        // [9]: tile runs of the eight XCDs
     double *abx_T = nullptr;
     double *abx_S = nullptr;
 };
@@ -124,6 +126,8 @@ struct SigmaArgs {
     const int2 *abx_chunk;
     const int *abx_rows;
     const long long *abx_soff;
+    const int2 *abx_tiles;
+    const int *abx_xrun;
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };
@@ -161,6 +165,7 @@ struct isci_ctx {
     bool have_abx = false;   // alpha-beta product path built
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
+    int abx_xmax = 0;        // longest XCD tile run
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
     // optional per-kernel timing: HIP events recorded around each launch on
