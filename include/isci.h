@@ -221,8 +221,8 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 
 /* Per-handle options.
  *   ISCI_OPT_SIGMA_KERNEL: ISCI_SIGMA_AUTO (default: two electrons per spin
- *   use the matrix-core path from 50000 determinants on and the pair kernel
- *   below; other electron counts the general kernel), ISCI_SIGMA_GENERAL
+ *   use the matrix-core path; other electron counts the general kernel),
+ *   ISCI_SIGMA_GENERAL
  *   (string algebra for any electron count), ISCI_SIGMA_PAIR (two-electron
  *   pair tables; ISCI_E_UNSUPPORTED otherwise), ISCI_SIGMA_MFMA (pair
  *   tables, alpha-beta class on FP64 matrix cores; two electrons per spin).

@@ -435,6 +435,10 @@ struct isci_engine_s {
     char *arena_d = nullptr, *arena_h = nullptr;
     double *res_d = nullptr, *res_h = nullptr;
     size_t arena_cap = 0, res_cap = 0;
+    // side streams for the per-instance matrix-core sigma launches (default
+    // priority), forked from and joined back into s with events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;   // [0]: fork, [1 + i]: join of side[i]
 };
 
 namespace isci {
@@ -654,7 +658,70 @@ static isci_status fused_sigma(isci_engine e, int n, const isci_handle *hds, con
     return launch_sigma_batched(e->d_args, e->d_vecs, (int)sorted.size(), (int)total, nvmax, e->grid, e->s);
 }
 
-// ---- phase A: one fused sigma launch over the new basis vectors of every active slot
+// side streams of the per-instance sigma launches
+static constexpr int kSideStreams = 4;
+
+static isci_status ensure_side_streams(isci_engine e)
+{
+    if (!e->side.empty()) return ISCI_OK;
+    for (int i = 0; i < kSideStreams; ++i) {
+        hipStream_t st;
+        ISCI_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        e->side.push_back(st);
+    }
+    for (int i = 0; i <= kSideStreams; ++i) {
+        hipEvent_t ev;
+        ISCI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        e->side_ev.push_back(ev);
+    }
+    return ISCI_OK;
+}
+
+// sigma of n (handle, vector block) jobs: handles on the matrix-core path
+// run their own launches (overlapping on side streams when there are
+// several; jobs sharing a handle share a stream, its product operands being
+// per handle), the others share one fused launch on e->s
+static isci_status batch_sigma(isci_engine e, int n, const isci_handle *hds, const int *nvec,
+                               const double *const *c, const int64_t *ldc, double *const *sg, const int64_t *lds)
+{
+    std::vector<int> own, rest;
+    for (int i = 0; i < n; ++i) (sigma_args(hds[i]).variant == 3 ? own : rest).push_back(i);
+    if (own.size() > 1) {
+        ISCI_CHECK(ensure_side_streams(e));
+        ISCI_HIP(hipEventRecord(e->side_ev[0], e->s));
+        for (hipStream_t st : e->side) ISCI_HIP(hipStreamWaitEvent(st, e->side_ev[0], 0));
+        for (size_t a = 0; a < own.size(); ++a) {
+            const int i = own[a];
+            size_t k = a % e->side.size();
+            for (size_t b = 0; b < a; ++b)
+                if (hds[own[b]] == hds[i]) { k = b % e->side.size(); break; }
+            ISCI_CHECK(launch_sigma(hds[i], nvec[i], c[i], ldc[i], sg[i], lds[i], e->side[k]));
+        }
+        for (size_t k = 0; k < e->side.size(); ++k) {
+            ISCI_HIP(hipEventRecord(e->side_ev[1 + k], e->side[k]));
+            ISCI_HIP(hipStreamWaitEvent(e->s, e->side_ev[1 + k], 0));
+        }
+    } else if (own.size() == 1) {
+        const int i = own[0];
+        ISCI_CHECK(launch_sigma(hds[i], nvec[i], c[i], ldc[i], sg[i], lds[i], e->s));
+    }
+    std::vector<isci_handle> h2;
+    std::vector<int> n2;
+    std::vector<const double *> c2;
+    std::vector<double *> s2;
+    std::vector<int64_t> lc2, ls2;
+    for (int i : rest) {
+        h2.push_back(hds[i]);
+        n2.push_back(nvec[i]);
+        c2.push_back(c[i]);
+        s2.push_back(sg[i]);
+        lc2.push_back(ldc[i]);
+        ls2.push_back(lds[i]);
+    }
+    return fused_sigma(e, (int)h2.size(), h2.data(), n2.data(), c2.data(), lc2.data(), s2.data(), ls2.data());
+}
+
+// ---- phase A: sigma of the new basis vectors of every active slot
 static isci_status phase_sigma(isci_engine e, const std::vector<Slot *> &act)
 {
     std::vector<isci_handle> hs;
@@ -665,23 +732,14 @@ static isci_status phase_sigma(isci_engine e, const std::vector<Slot *> &act)
     for (Slot *sl : act) {
         const int nnew = sl->m - sl->mdone;
         if (nnew <= 0) continue;
-        if (sigma_args(sl->h).variant == 3) {
-            // large instances tuned for the matrix-core path run their own
-            // launches; the rest share the fused launch
-            isci_status st = launch_sigma(sl->h, nnew, sl->V + (size_t)sl->mdone * sl->dim, sl->dim,
-                                          sl->W + (size_t)sl->mdone * sl->dim, sl->dim, e->s);
-            if (st != ISCI_OK) return st;
-            sl->nsig += nnew;
-            continue;
-        }
+        sl->nsig += nnew;
         hs.push_back(sl->h);
         nv.push_back(nnew);
         cv.push_back(sl->V + (size_t)sl->mdone * sl->dim);
         sv.push_back(sl->W + (size_t)sl->mdone * sl->dim);
         ld.push_back(sl->dim);
-        sl->nsig += nnew;
     }
-    return fused_sigma(e, (int)hs.size(), hs.data(), nv.data(), cv.data(), ld.data(), sv.data(), ld.data());
+    return batch_sigma(e, (int)hs.size(), hs.data(), nv.data(), cv.data(), ld.data(), sv.data(), ld.data());
 }
 
 // ---- descriptor arena: the host packs one phase's descriptors into
@@ -1234,7 +1292,7 @@ isci_status isci_engine_sigma(isci_engine e, int n, const isci_handle *hds, cons
             set_error("bad batch entry");
             return ISCI_E_INVALID;
         }
-    return fused_sigma(e, n, hds, nvec, c, ldc, sigma, lds);
+    return batch_sigma(e, n, hds, nvec, c, ldc, sigma, lds);
 }
 
 void isci_engine_destroy(isci_engine e)
@@ -1250,6 +1308,11 @@ void isci_engine_destroy(isci_engine e)
     if (e->arena_h) (void)hipHostFree(e->arena_h);
     if (e->res_d) (void)hipFree(e->res_d);
     if (e->res_h) (void)hipHostFree(e->res_h);
+    for (hipStream_t st : e->side) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : e->side_ev) (void)hipEventDestroy(ev);
     delete e;
 }
 

@@ -398,9 +398,10 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.apidx = c->d.apidx; A.bpidx = c->d.bpidx;
     const bool pair_ok = c->sa.n == 2 && c->sb.n == 2;
     A.variant = (c->sigma_variant == ISCI_SIGMA_GENERAL || !pair_ok) ? 1 : 2;
-    // automatic choice: the matrix-core path for spaces large enough to
-    // amortise its extra launches, the single pair kernel below that
-    const bool auto_mfma = c->sigma_variant == ISCI_SIGMA_AUTO && c->dim >= 50000;
+    // automatic choice: the matrix-core path whenever it is built (two
+    // electrons per spin); it is faster than the pair kernel from the
+    // smallest spaces on (20 orbitals CISD: 0.057 vs 0.197 ms per sigma)
+    const bool auto_mfma = c->sigma_variant == ISCI_SIGMA_AUTO;
     if (pair_ok && c->have_tiles && (c->sigma_variant == ISCI_SIGMA_MFMA || auto_mfma)) A.variant = 3;
     A.classes = 7;
     A.accumulate = 0;
