@@ -24,7 +24,7 @@
 // <= L - k, which is a prefix of the columns: pcols[k].
 //
 //  * unfold: every (q, S) that opens a chunk gets 4 rows of T, pcols[class]
-//    wide, written once per call from the CI vectors;
+//    wide; each determinant scatters its values into T once per call;
 //  * product: a workgroup takes one row block pair and 256 columns; each
 //    wave four 16-column tiles; K runs over the chunks whose class leaves
 //    the columns valid (a prefix of the chunk list); S gets 16 rows x
@@ -46,31 +46,42 @@ constexpr int kAbSplit = 2;
 __device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
 __device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
 
-// row kr = 4 * (T row block) + k of T; thread per column (enough threads
-// in flight to cover the chain column descriptor -> tables -> CI element)
+// Unfold by scatter: one thread per determinant ({a0<a1}, {b0<b1}) of the
+// space reads its 4 vector values (coalesced) and writes them, with the
+// role sign, to its four places in T, one per reading (alpha spectator x,
+// active q) x (beta spectator y, active s):
+//   T[(q, s)][(x, y, v)] = sgn(q - x) sgn(s - y) c_v({x,q},{y,s}).
+// Every entry of T belongs to at most one determinant; entries that belong
+// to none were zeroed when T was allocated.  Vectors v >= nv write zeros.
 __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const double *__restrict__ c, int64_t ldc)
 {
-    const int kr = blockIdx.y;
-    const int4 tr = A.abx_trow[kr >> 2];   // (q, S, T offset of row 0, width)
-    const int width = tr.w;
-    const int col = blockIdx.x * 256 + threadIdx.x;
-    if (col >= width) return;
-    const int norb = A.norb;
-    const int q = tr.x, S = tr.y, k = kr & 3;
-    const int s = S == 0 ? (k < 2 ? k : -1) : (2 + 4 * (S - 1) + k < norb ? 2 + 4 * (S - 1) + k : -1);
-    const int d = A.abx_col[col];
-    const int x = d & 0xff, y = (d >> 8) & 0xff, v = d >> 16;
-    double val = 0.0;
-    if (s >= 0 && x != 255 && y != 255 && x != q && y != s && v < nv) {
-        const long long base = A.arow_base[x * norb + q];
-        const int len = A.arow_len[x * norb + q];
-        const int jb = A.bpidx[y * norb + s];
-        if (base >= 0 && jb >= 0 && jb < len) {
-            const double cv = c[(int64_t)v * ldc + base + jb];
-            val = ((q > x) == (s > y)) ? cv : -cv;
+    const int ia = blockIdx.x;
+    const int jb = blockIdx.y * 256 + threadIdx.x;
+    const int len = A.sb.le[A.L - A.alev[ia]];
+    if (jb >= len) return;
+    const int nb = A.nblk;
+    const uint32_t as = A.astr[ia], bs = A.bstr[jb];
+    const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
+    const int64_t addr = A.rowstart[ia] + jb;
+    double cv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cv[v] = v < nv ? c[(int64_t)v * ldc + addr] : 0.0;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra) {
+        const int x = ra ? a1 : a0, q = ra ? a0 : a1;   // alpha spectator, active
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int y = rb ? b1 : b0, s = rb ? b0 : b1;
+            const int2 tq = A.abx_tq[q * nb + ab_block(s)];
+            if (tq.y == 0) continue;   // no chunk reads this row
+            const int D = ab_block(y);
+            const int col = A.abx_gofs[ab_block(x) * nb + D] + (ab_slot(x) * (D == 0 ? 2 : 4) + ab_slot(y)) * 4;
+            double *dst = A.abx_T + (size_t)tq.x + (size_t)ab_slot(s) * tq.y + col;
+            const double f = (ra ^ rb) ? -1.0 : 1.0;   // sgn(q - x) sgn(s - y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[v] = f * cv[v];
         }
     }
-    A.abx_T[(size_t)tr.z + (size_t)k * width + col] = val;
 }
 
 // S for one row block pair and 256 columns (one tile).  The tiles, ordered
@@ -210,8 +221,8 @@ isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64
     const SigmaArgs A = sigma_args(cx);
     if (cx->abx_ntrow > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
-        k_ab_unfold<<<dim3((unsigned)((cx->abx_pcols[0] + 255) / 256), (unsigned)(4 * cx->abx_ntrow)), 256, 0, st>>>(
-            A, nv, c, ldc);
+        k_ab_unfold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, c,
+                                                                                                          ldc);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, false, st));
     }
     if (cx->abx_nrows > 0) {

@@ -86,6 +86,7 @@ struct DevTabs {
     int *abx_gofs = nullptr;
     int *abx_col = nullptr;
     int4 *abx_trow = nullptr;
+    int2 *abx_tq = nullptr;         // [norb][nblk]: (T offset of row 0, width) of the rows of (q, S); width 0: none
     int2 *abx_chunk = nullptr;
     int *abx_rows = nullptr;
     long long *abx_soff = nullptr;
@@ -123,6 +124,7 @@ struct SigmaArgs {
     const int *abx_gofs;
     const int *abx_col;
     const int4 *abx_trow;
+    const int2 *abx_tq;
     const int2 *abx_chunk;
     const int *abx_rows;
     const long long *abx_soff;

@@ -417,6 +417,7 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.abx_gofs = c->d.abx_gofs;
     A.abx_col = c->d.abx_col;
     A.abx_trow = c->d.abx_trow;
+    A.abx_tq = c->d.abx_tq;
     A.abx_chunk = c->d.abx_chunk;
     A.abx_rows = c->d.abx_rows;
     A.abx_soff = c->d.abx_soff;
@@ -662,6 +663,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
     d.abx_col = (int *)dev_alloc(c, sizeof(int) * col.size());
     d.abx_trow = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, trow.size()));
+    d.abx_tq = (int2 *)dev_alloc(c, sizeof(int2) * (size_t)n * nb);
     d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * chunk.size());
     d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
     d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
@@ -669,7 +671,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     d.abx_xrun = (int *)dev_alloc(c, sizeof(int) * xrun.size());
     d.abx_T = (double *)dev_alloc(c, tbytes);
     d.abx_S = (double *)dev_alloc(c, sbytes);
-    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_tiles ||
+    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_tiles ||
         !d.abx_xrun || !d.abx_T || !d.abx_S) {
         set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
@@ -678,6 +680,16 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     ISCI_HIP(hipMemcpyAsync(d.abx_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
     if (!trow.empty())
         ISCI_HIP(hipMemcpyAsync(d.abx_trow, trow.data(), sizeof(int4) * trow.size(), hipMemcpyHostToDevice, s));
+    {
+        std::vector<int2> tq((size_t)n * nb, make_int2(0, 0));
+        for (size_t i = 0; i < tq.size(); ++i)
+            if (krow_of[i] >= 0) tq[i] = make_int2(trow[krow_of[i]].z, trow[krow_of[i]].w);
+        ISCI_HIP(hipMemcpyAsync(d.abx_tq, tq.data(), sizeof(int2) * tq.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipStreamSynchronize(s));
+    }
+    // entries of T that no determinant of the space fills stay zero; the
+    // scatter unfold writes the others every call
+    ISCI_HIP(hipMemsetAsync(d.abx_T, 0, tbytes, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_chunk, chunk.data(), sizeof(int2) * chunk.size(), hipMemcpyHostToDevice, s));
     if (!rows.empty())
         ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
