@@ -113,13 +113,17 @@ def main():
     torch.cuda.synchronize()
     prof = isci.isci_profile_read(hd)
     isci.isci_profile(hd, False)
-    # algorithmic flops each kernel performs per step (2 per sigma term per vector)
+    # algorithmic flops each kernel performs per step (2 per sigma term per
+    # vector); when no one-body launch shows up on the matrix-core path, its
+    # terms ride in the alpha-beta tiles (dense integrals)
     terms_1b = int(tb[0:8].sum())
+    ob_in_ab = "onebody" not in prof
+    t_ab = terms_ab + (terms_1b if ob_in_ab else 0)
     kflops = {"k_sigma_generic": 2.0 * terms * nvec, "k_sigma_n2": 2.0 * terms * nvec,
-              "k_sigma_ab_mfma": 2.0 * terms_ab * nvec,
+              "k_sigma_ab_mfma": 2.0 * t_ab * nvec,
               "k_sigma_n2(same-spin)": 2.0 * (terms_rest - terms_1b) * nvec,
               "onebody": 2.0 * terms_1b * nvec,
-              "k_ab_gemm": 2.0 * terms_ab * nvec,
+              "k_ab_gemm": 2.0 * t_ab * nvec,
               # data movement only (no sigma terms): unfold and fold
               "k_ab_unfold": 0.0, "k_ab_fold": 0.0}
     kernels = {}

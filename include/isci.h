@@ -127,6 +127,29 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
                         int nalpha, int nbeta, int max_excitation, double tau,
                         hipStream_t stream);
 
+/* Where the matrix-core path (two electrons per spin) applies the kept
+ * one-body units.  With two electrons of a spin, sum_r E_rr equals 2 on the
+ * whole space, so h_pq E^alpha_pq = sum_r (h_pq / 2) E^alpha_pq E^beta_rr
+ * (and likewise for beta): the units can ride in the alpha-beta tiles, at
+ * the price of the tiles they open.  SEPARATE keeps them in their own
+ * kernels; TILES puts them in the tiles; AUTO puts them in the tiles when
+ * that adds at most one tile in eight or the space has at most 65536
+ * determinants (there the extra launches cost more than the extra tiles).
+ * The sigma vector is the same either way (up to rounding order). */
+#define ISCI_OB_AUTO 0
+#define ISCI_OB_SEPARATE 1
+#define ISCI_OB_TILES 2
+
+typedef struct {
+    int onebody;                /* ISCI_OB_* (default ISCI_OB_AUTO) */
+} isci_create_opts;
+
+/* isci_create with build options; opts may be NULL (defaults).  Returns
+ * ISCI_E_INVALID for an unknown onebody value. */
+isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri, int norb,
+                           int nalpha, int nbeta, int max_excitation, double tau,
+                           const isci_create_opts *opts, hipStream_t stream);
+
 /* Number of determinants. */
 isci_status isci_dim(isci_handle hd, int64_t *dim);
 

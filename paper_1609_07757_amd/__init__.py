@@ -26,6 +26,8 @@ OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
 OPT_AB_PATH = 2
 AB_AUTO, AB_GATHER = 0, 1
+# isci_create_opts.onebody: where the matrix-core path applies the one-body units
+OB_AUTO, OB_SEPARATE, OB_TILES = 0, 1, 2
 
 
 def isci_set_option(hd, option: int, value: int):
@@ -84,15 +86,17 @@ class Handle:
 
 
 def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
-                stream=None) -> Handle:
+                stream=None, onebody: int = OB_AUTO) -> Handle:
+    """Build a handle (isci_create_ex; onebody is one of OB_*)."""
     L = _lib.load()
     hp = _dev_f64(h, "h")
     ep = _dev_f64(eri, "eri")
     if h.numel() != norb * norb or eri.numel() != norb ** 4:
         raise ValueError("h must hold norb^2 and eri norb^4 elements")
     out = ctypes.c_void_p()
-    st = L.isci_create(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
-                       int(max_excitation), float(tau), _stream_ptr(stream))
+    opts = _lib.IsciCreateOpts(int(onebody))
+    st = L.isci_create_ex(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
+                          int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create")
     return Handle(out, norb, nalpha, nbeta, max_excitation, tau)
 

@@ -25,7 +25,7 @@ ISCI_E_UNSUPPORTED = -5
 
 # Exported symbols declared in include/isci.h.
 ABI_SYMBOLS = (
-    "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
+    "isci_create", "isci_create_ex", "isci_dim", "isci_sigma", "isci_diag", "isci_davidson",
     "isci_davidson_defaults", "isci_strings", "isci_rowstart", "isci_get_stats",
     "isci_destroy", "isci_status_string", "isci_last_error",
     "isci_engine_create", "isci_engine_config", "isci_engine_add", "isci_engine_step",
@@ -39,6 +39,11 @@ class IsciStats(ctypes.Structure):
                 ("kept", ctypes.c_int64 * NBUCKET), ("terms", ctypes.c_int64 * NBUCKET),
                 ("kept_total", ctypes.c_int64), ("terms_total", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64)]
+
+
+class IsciCreateOpts(ctypes.Structure):
+    """isci_create_opts."""
+    _fields_ = [("onebody", ctypes.c_int)]
 
 
 class IsciDavidsonOpts(ctypes.Structure):
@@ -71,6 +76,9 @@ def load(path: str = LIBPATH):
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.isci_create.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i32, i32, dbl, vp]
     L.isci_create.restype = i32
+    L.isci_create_ex.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i32, i32, dbl,
+                                 ctypes.POINTER(IsciCreateOpts), vp]
+    L.isci_create_ex.restype = i32
     L.isci_dim.argtypes = [vp, ctypes.POINTER(i64)]
     L.isci_dim.restype = i32
     L.isci_sigma.argtypes = [vp, i32, vp, i64, vp, i64, vp]

@@ -170,6 +170,8 @@ struct isci_ctx {
     int abx_xmax = 0;        // longest XCD tile run
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
+    bool onebody_in_tiles = false;   // chunk values carry the one-body units (h/2 (x) identity)
+    int ob_place = 0;                // ISCI_OB_* requested at create
     // optional per-kernel timing: HIP events recorded around each launch on
     // the launch stream, summed when read
     bool profile = false;

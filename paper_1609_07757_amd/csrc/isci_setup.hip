@@ -446,6 +446,29 @@ __global__ void k_chunk_mark(const long long *ab_off, const uint8_t *ab_s, int n
     }
 }
 
+// With two electrons of each spin, N_beta = sum_r E^beta_rr is 2 on the
+// whole space (and likewise for alpha), so the kept one-body units are
+// alpha-beta units as well:
+//   h_pq E^alpha_pq = sum_r (h_pq / 2) E^alpha_pq E^beta_rr,
+//   h_rs E^beta_rs  = sum_p (h_rs / 2) E^alpha_pp E^beta_rs.
+// Their chunks are marked here and their values added in k_chunk_fill, so
+// the alpha-beta product forms the one-body classes too.  Thread (p, q):
+// the alpha image of h_pq over every r, and the beta image of h_pq (as
+// h_rs with r = p, s = q) over every alpha diagonal orbital.
+__global__ void k_chunk_mark_1b(const double *hs, int n, const int *orb_blk, int nb, unsigned *bits)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int p = t / n, q = t % n;
+    if (hs[t] == 0.0) return;
+    for (int o = 0; o < n; ++o) {
+        const long long ka = (((long long)orb_blk[p] * nb + orb_blk[o]) * n + q) * nb + orb_blk[o];
+        atomicOr(&bits[ka >> 5], 1u << (ka & 31));
+        const long long kb = (((long long)orb_blk[o] * nb + orb_blk[p]) * n + o) * nb + orb_blk[q];
+        atomicOr(&bits[kb >> 5], 1u << (kb & 31));
+    }
+}
+
 __global__ void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -459,7 +482,7 @@ __global__ void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
 // chunks of a row block are written in order of their source level class
 // (virtual q) + (virtual S-block), so the chunks a role may use form a
 // prefix; cls[g*3 + l] counts the chunks of class l
-__global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int nb, double tau,
+__global__ void k_chunk_fill(const unsigned *bits, const double *eri, const double *hs, int n, int nb, double tau,
                              const int8_t *blk_orb, const int *off, int2 *desc, double *val, int *cls)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -483,6 +506,9 @@ __global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int
                 if (p >= 0 && r >= 0 && s >= 0) {
                     v = geri(eri, n, p, q, r, s);
                     if (!(fabs(v) > tau)) v = 0.0;
+                    // one-body units in alpha-beta form (hs holds the kept h)
+                    if (hs && r == s) v += 0.5 * hs[p * n + q];
+                    if (hs && p == q) v += 0.5 * hs[r * n + s];
                 }
                 val[(size_t)w * 64 + l] = v;
             }
@@ -491,6 +517,10 @@ __global__ void k_chunk_fill(const unsigned *bits, const double *eri, int n, int
     cls[g * 3 + lc] = cnt;
     }
 }
+
+// spaces up to this many determinants take the one-body units into the
+// tiles by default (fewer launches; measured faster up to about 10^5)
+static constexpr int64_t kObTilesMaxDim = 65536;
 
 // blocks of four orbitals, o/v pure (two electrons per spin: the occupied
 // block is {0, 1, -, -}); target tiles with level <= L; column chunks
@@ -533,25 +563,59 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     ISCI_HIP(hipMemsetAsync(bits, 0, sizeof(unsigned) * (size_t)((nkeys + 31) / 32 + 1), s));
     ISCI_HIP(hipMemsetAsync(d.chunk_off, 0, sizeof(int) * (nb * nb + 1), s));
     const int64_t n3 = (int64_t)n * n * n;
+    const size_t nbits = sizeof(unsigned) * (size_t)((nkeys + 31) / 32 + 1);
     k_chunk_mark<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(d.ab_off, d.ab_s, n, dob, nb, bits);
-    k_chunk_count<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, n, nb, d.chunk_off);
     ISCI_HIP(hipGetLastError());
-    isci_status st = scan_inplace<int>(d.chunk_off, nb * nb + 1, s);
-    if (st != ISCI_OK) return st;
+    // chunk count of a mark set (offsets left in chunk_off)
+    auto count_chunks = [&](const unsigned *b, int *tot) -> isci_status {
+        ISCI_HIP(hipMemsetAsync(d.chunk_off, 0, sizeof(int) * (nb * nb + 1), s));
+        k_chunk_count<<<(nb * nb + 63) / 64, 64, 0, s>>>(b, n, nb, d.chunk_off);
+        ISCI_HIP(hipGetLastError());
+        isci_status st = scan_inplace<int>(d.chunk_off, nb * nb + 1, s);
+        if (st != ISCI_OK) return st;
+        ISCI_HIP(hipMemcpyAsync(tot, d.chunk_off + nb * nb, sizeof(int), hipMemcpyDeviceToHost, s));
+        ISCI_HIP(hipStreamSynchronize(s));   // also keeps the host tables above alive until copied
+        return ISCI_OK;
+    };
     int tot = 0;
-    ISCI_HIP(hipMemcpyAsync(&tot, d.chunk_off + nb * nb, sizeof(int), hipMemcpyDeviceToHost, s));
-    ISCI_HIP(hipStreamSynchronize(s));   // also keeps the host tables above alive until copied
+    isci_status st = count_chunks(bits, &tot);
+    if (st != ISCI_OK) return st;
+    // the one-body units join the tiles when asked to, or by default when
+    // that adds at most one chunk in eight (dense integrals: their chunks
+    // are mostly there already) or the space is small (launch latency
+    // outweighs the extra tiles); else they keep their own kernels
+    bool merged = false;
+    if (d.hscreen && c->ob_place != ISCI_OB_SEPARATE) {
+        unsigned *bits1 = nullptr;
+        ISCI_HIP(hipMallocAsync((void **)&bits1, nbits, s));
+        ISCI_HIP(hipMemcpyAsync(bits1, bits, nbits, hipMemcpyDeviceToDevice, s));
+        k_chunk_mark_1b<<<(unsigned)((n * n + 255) / 256), 256, 0, s>>>(d.hscreen, n, dob, nb, bits1);
+        ISCI_HIP(hipGetLastError());
+        int tot1 = 0;
+        st = count_chunks(bits1, &tot1);
+        if (st != ISCI_OK) return st;
+        if (c->ob_place == ISCI_OB_TILES || (long long)tot1 * 8 <= (long long)tot * 9 || c->dim <= kObTilesMaxDim) {
+            merged = true;
+            std::swap(bits, bits1);
+            tot = tot1;
+        } else {
+            st = count_chunks(bits, &tot);
+            if (st != ISCI_OK) return st;
+        }
+        ISCI_HIP(hipFreeAsync(bits1, s));
+    }
     d.chunk_desc = (int2 *)dev_alloc(c, sizeof(int2) * std::max(1, tot));
     d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * (size_t)std::max(1, tot));
     d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
     if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
-    k_chunk_fill<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, eri, n, nb, c->tau, d.blk_orb, d.chunk_off, d.chunk_desc,
-                                                     d.chunk_val, d.chunk_cls);
+    k_chunk_fill<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, eri, merged ? d.hscreen : nullptr, n, nb, c->tau,
+                                                     d.blk_orb, d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
     ISCI_HIP(hipFreeAsync(bits, s));
     ISCI_HIP(hipStreamSynchronize(s));
     c->nchunk = tot;
     c->have_tiles = true;
+    c->onebody_in_tiles = merged;
     return ISCI_OK;
 }
 
@@ -850,7 +914,20 @@ const char *isci_status_string(isci_status s)
 isci_status isci_create(isci_handle *out, const double *h, const double *eri, int norb, int nalpha,
                         int nbeta, int max_excitation, double tau, hipStream_t stream)
 {
+    return isci_create_ex(out, h, eri, norb, nalpha, nbeta, max_excitation, tau, nullptr, stream);
+}
+
+isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri, int norb, int nalpha,
+                           int nbeta, int max_excitation, double tau, const isci_create_opts *opts,
+                           hipStream_t stream)
+{
     if (!out) { set_error("out is NULL"); return ISCI_E_INVALID; }
+    *out = nullptr;
+    const int ob_place = opts ? opts->onebody : ISCI_OB_AUTO;
+    if (ob_place != ISCI_OB_AUTO && ob_place != ISCI_OB_SEPARATE && ob_place != ISCI_OB_TILES) {
+        set_error("isci_create_opts.onebody must be ISCI_OB_AUTO, ISCI_OB_SEPARATE or ISCI_OB_TILES");
+        return ISCI_E_INVALID;
+    }
     *out = nullptr;
     if (!h || !eri) { set_error("h or eri is NULL"); return ISCI_E_INVALID; }
     if (norb < 1) { set_error("norb < 1"); return ISCI_E_INVALID; }
@@ -868,6 +945,7 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     isci_ctx *c = new (std::nothrow) isci_ctx();
     if (!c) { set_error("host allocation failed"); return ISCI_E_OOM; }
     c->norb = norb; c->na = nalpha; c->nb = nbeta; c->tau = tau;
+    c->ob_place = ob_place;
     const int lmax = std::min(nalpha, norb - nalpha) + std::min(nbeta, norb - nbeta);
     c->L = std::min(max_excitation, lmax);
     spin_table(c->sa, norb, nalpha, c->L);
@@ -970,9 +1048,9 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     isci_status st = build_lists(c, h, eri, stream);
     if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
-        st = build_tiles(c, eri, stream);
+        st = build_hscreen(c, h, stream);
+        if (st == ISCI_OK) st = build_tiles(c, eri, stream);
         if (st == ISCI_OK) st = build_abx(c, stream);
-        if (st == ISCI_OK) st = build_hscreen(c, h, stream);
         if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     }

@@ -738,7 +738,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             // Matrix-core path: the alpha-beta class writes sigma (as the
             // unfold / block-sparse product / fold path when its operands
             // fit, else with the gathered tile kernel), then the one-body
-            // and same-spin classes add.
+            // (unless the tiles carry it) and same-spin classes add.
             for (int u0 = 0; u0 < nv; u0 += 4) {
                 const int nu = nv - u0 < 4 ? nv - u0 : 4;
                 if (c->have_abx && !c->ab_gather) {
@@ -754,10 +754,11 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
                 }
             }
-            if (c->d.hscreen) {
+            if (c->d.hscreen && !c->onebody_in_tiles) {
                 // one-body classes (matrix cores when the orbital count allows,
                 // else alpha in two launches by spectator side, then beta),
-                // then same-spin if any
+                // then same-spin if any; with dense integrals the tiles carry
+                // the one-body units instead
                 ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
                 if (onebody_mfma_ok(c)) {
                     ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
@@ -780,8 +781,8 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                     ISCI_HIP(hipGetLastError());
                 }
                 ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
-                if (c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
             }
+            if (c->d.hscreen && c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
             ISCI_CHECK(prof_mark(c, ISCI_KERNEL_PAIR_REST, true, s));
             SigmaArgs B = A;
             B.classes = c->d.hscreen ? 2 : 3;

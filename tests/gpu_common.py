@@ -14,17 +14,23 @@ def torch_dev():
 
 
 def create(h, eri, norb, na, nb, L, tau, variant=0):
+    """variant 0: automatic; 1-3: isci.SIGMA_* kernel; 4: matrix-core path
+    with the gathered alpha-beta tile kernel; 5 / 6: matrix-core path with
+    the one-body units in their own kernels / in the alpha-beta tiles."""
     import paper_1609_07757_amd as isci
     torch, dev = torch_dev()
     ht = torch.from_numpy(np.ascontiguousarray(h)).to(dev)
     et = torch.from_numpy(np.ascontiguousarray(eri)).to(dev)
-    hd = isci.isci_create(ht, et, norb, na, nb, L, tau)
+    ob = {5: isci.OB_SEPARATE, 6: isci.OB_TILES}.get(variant, isci.OB_AUTO)
+    hd = isci.isci_create(ht, et, norb, na, nb, L, tau, onebody=ob)
     torch.cuda.synchronize()
     del ht, et
     if variant == 4:
         # matrix-core path with the gathered alpha-beta tile kernel
         isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA)
         isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_GATHER)
+    elif variant in (5, 6):
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA)
     elif variant:
         isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
     return hd

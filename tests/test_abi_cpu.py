@@ -60,5 +60,9 @@ def test_invalid_arguments_rejected_before_any_device_work():
     assert L.isci_create(ctypes.byref(out), fake, fake, 4, 1, 1, 2, float("nan"), None) == _lib.ISCI_E_INVALID
     assert L.isci_create(ctypes.byref(out), fake, fake, 300, 1, 1, 2, 0.0, None) == _lib.ISCI_E_UNSUPPORTED
     assert L.isci_create(ctypes.byref(out), fake, fake, 20, 5, 1, 2, 0.0, None) == _lib.ISCI_E_UNSUPPORTED
+    bad = _lib.IsciCreateOpts(7)
+    assert L.isci_create_ex(ctypes.byref(out), fake, fake, 4, 1, 1, 2, 0.0, ctypes.byref(bad),
+                            None) == _lib.ISCI_E_INVALID
+    assert L.isci_create_ex(None, fake, fake, 4, 1, 1, 2, 0.0, None, None) == _lib.ISCI_E_INVALID
     assert L.isci_sigma(None, 1, fake, 1, fake, 1, None) == _lib.ISCI_E_INVALID
     assert L.isci_last_error()

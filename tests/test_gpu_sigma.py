@@ -48,13 +48,14 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
 def test_sigma_parity(case, variant):
     """variant 1: general string kernel; 2: pair tables; 3: matrix-core
-    path (alpha-beta unfold / product / fold, one-body products); 4: matrix-
-    core path with the gathered alpha-beta tile kernel (2-4 need two
-    electrons per spin)."""
+    path (alpha-beta unfold / product / fold; these small spaces take the
+    one-body units into the tiles); 4: matrix-core path with the gathered
+    alpha-beta tile kernel; 5: matrix-core path with the one-body kernels
+    (2-5 need two electrons per spin)."""
     recipe, norb, na, nb, L, tau, nvec = case
     if variant > 1 and not (na == 2 and nb == 2):
         pytest.skip("pair kernels need two electrons per spin")
@@ -158,7 +159,7 @@ def test_hermiticity_large():
     assert abs(a - b) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * max(1.0, np.abs(s).max())
 
 
-@pytest.mark.parametrize("variant", [3, 4, 2, 1])
+@pytest.mark.parametrize("variant", [3, 4, 2, 1, 6])
 @pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 1), ("cisdt_n30", 600, 2),
                                            ("cisdt_n60", 300, 8), ("fci_n48", 200, 8)])
 def test_sigma_workloads(wl, nsamp, nvec, variant):
