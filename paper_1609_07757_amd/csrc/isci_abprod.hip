@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
 // sigma({a0 < a1}, {b0 < b1}) = sum over the four readings (alpha
 // spectator, alpha active) x (beta spectator, beta active) of S, sign - per
 // spin whose spectator is the larger orbital
-__global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds)
+__global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds,
+                                                 int accumulate)
 {
     const int ia = blockIdx.x;
     const int jb = blockIdx.y * 256 + threadIdx.x;
@@ -210,15 +211,25 @@ __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__
         }
     }
     double *dst = sg + A.rowstart[ia] + jb;
+    if (accumulate) {
+        double old[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-        if (v < nv) dst[(int64_t)v * lds] = acc[v];
+        for (int v = 0; v < 4; ++v) old[v] = dst[(int64_t)min(v, nv - 1) * lds];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (v < nv) dst[(int64_t)v * lds] = old[v] + acc[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (v < nv) dst[(int64_t)v * lds] = acc[v];
+    }
 }
 
-isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
-                              hipStream_t st)
+isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *Sbuf,
+                                  hipStream_t st)
 {
-    const SigmaArgs A = sigma_args(cx);
+    SigmaArgs A = sigma_args(cx);
+    A.abx_S = Sbuf;
     if (cx->abx_ntrow > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
         k_ab_unfold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, c,
@@ -230,11 +241,28 @@ isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64
         k_ab_gemm<kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 256 * kAbSplit, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
+isci_status launch_ab_fold(const isci_ctx *cx, int nv, const double *Sbuf, double *s, int64_t lds, bool accumulate,
+                           hipStream_t st)
+{
+    SigmaArgs A = sigma_args(cx);
+    A.abx_S = const_cast<double *>(Sbuf);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));
-    k_ab_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, s, lds);
+    k_ab_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(
+        A, nv, s, lds, accumulate ? 1 : 0);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, false, st));
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
+}
+
+isci_status launch_ab_product(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
+                              hipStream_t st)
+{
+    ISCI_CHECK(launch_ab_unfold_gemm(cx, nv, c, ldc, cx->d.abx_S, st));
+    return launch_ab_fold(cx, nv, cx->d.abx_S, s, lds, false, st);
 }
 
 }  // namespace isci

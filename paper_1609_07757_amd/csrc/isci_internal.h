@@ -72,6 +72,7 @@ struct DevTabs {
     double *chunk_val = nullptr;    // [nchunk][64]
     uchar4 *quads = nullptr;        // target tiles (X, P, Y, R) with X<=P, Y<=R, level <= L
     double *hscreen = nullptr;      // [norb][norb] h with screened units set to 0 (one-body kernels)
+    double *hpad = nullptr;         // [kObMaxNorb][kObMaxNorb] the same, zero padded (matrix-core one-body)
     // alpha row of the ordered pair (x, q): start and length (-1 / 0 when
     // {x,q} is not a string of the space)
     long long *arow_base = nullptr;
@@ -94,6 +95,7 @@ struct DevTabs {
     int *abx_xrun = nullptr;        // [9]: tile runs of the eight XCDs
     double *abx_T = nullptr;
     double *abx_S = nullptr;
+    double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
 };
 
 struct SigmaArgs {
@@ -176,6 +178,11 @@ struct isci_ctx {
     // the launch stream, summed when read
     bool profile = false;
     std::vector<hipEvent_t> prof_ev[ISCI_NKERNEL_IDS];   // start/stop pairs
+    // side stream of the matrix-core one-body classes, which run beside the
+    // alpha-beta unfolds and products; fork / join events
+    hipStream_t ob_stream = nullptr;
+    hipEvent_t ob_fork = nullptr, ob_join = nullptr;
+    size_t abx_sbytes = 0;
     // scratch for the eigensolver (grown on demand)
     std::vector<void *> work;
 };
@@ -207,11 +214,19 @@ isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);
 // alpha-beta class as unfold + block-sparse product + fold (writes sigma)
 isci_status launch_ab_product(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
                               hipStream_t s);
+// its two halves: unfold + product into the S buffer Sbuf, and the fold
+// from Sbuf (accumulate: add into sigma instead of writing it)
+isci_status launch_ab_unfold_gemm(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *Sbuf,
+                                  hipStream_t s);
+isci_status launch_ab_fold(const isci_ctx *c, int nv, const double *Sbuf, double *sv, int64_t lds, bool accumulate,
+                           hipStream_t s);
 // one-body classes on matrix cores (two electrons per spin, norb <= kObMaxNorb)
 constexpr int kObMaxNorb = 80;
 bool onebody_mfma_ok(const isci_ctx *c);
+// first: the beta classes write sigma (they cover every element) instead
+// of adding, and the alpha classes add
 isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
-                                hipStream_t s);
+                                hipStream_t s, bool first = false);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

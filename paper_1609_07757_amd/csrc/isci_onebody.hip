@@ -10,16 +10,20 @@
 // screened units |h_pq| <= tau are zeros of h, so the product adds exactly
 // the kept terms (the diagonal units h_pp included).
 //
+// The cut splits both classes by the level of the other spin's string:
 //  * beta class, alpha rows whose beta strings reach level 2: T of the row
 //    is built in LDS and U = h T is formed whole;
 //  * beta class, rows whose beta strings stop at level 1: only the columns
 //    U[:, o] of the two occupied orbitals o are needed (a product over many
 //    rows at once), plus two units per target taken directly;
-//  * alpha class: for a spectator x the rows {q, x} of all q hold, for each
-//    beta column j, the column T_j[:, x]; U_j[:, x] = h T_j[:, x] is a
-//    product with K = q and the beta columns as N, read straight from the
-//    rows (coalesced).  Target rows {a, x} are split by a < x / a > x over
-//    two launches so that one workgroup writes each sigma element per launch.
+//  * alpha class, beta columns where every alpha pair exists: a workgroup
+//    holds the pair values of a few columns in LDS and forms the whole U of
+//    each column;
+//  * alpha class, columns where only the pairs {0,1}, {o, v} exist: U[:, o]
+//    for the two occupied o over 64 columns at once (rows staged in LDS),
+//    plus the two-term U[o][v];
+//  * alpha class, columns where only {0,1} exists: (h_00 + h_11) c.
+// Every sigma element is written by one workgroup of one launch.
 //
 // Everything adds into sigma.  16x16x4 f64 operand layouts: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result element g of lane l is
@@ -38,10 +42,34 @@ __device__ __forceinline__ v4d_ob mfma16(double a, double b, v4d_ob c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// screened h (symmetric, canonical) with zero padding
-__device__ __forceinline__ double hpad(const double *__restrict__ hs, int norb, int p, int q)
+// A operand column of the screened h (symmetric, canonical) for all K
+// steps: ah[ks] = h[a][q] with q = 4 ks + kq, from the zero-padded copy
+// hp (kObMaxNorb x kObMaxNorb), so the loads carry no conditions and are
+// issued together.
+template <int NK>
+__device__ __forceinline__ void load_hcol(const double *__restrict__ hp, int a, int kq, double *ah)
 {
-    return (p < norb && q < norb) ? hs[q * norb + p] : 0.0;
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) ah[ks] = hp[(4 * ks + kq) * kObMaxNorb + a];
+}
+
+// global loads per thread issued together in the staging loops below
+constexpr int kObBatch = 8;
+
+// start of the row of alpha string ia, from the level structure alone (no
+// table load): rows run level by level in string order, a row of level l
+// holding the beta strings of level <= L - l; two electrons: levels <= 2
+__device__ __forceinline__ int64_t row_start_n2(const SigmaArgs &A, int ia)
+{
+    int64_t r = 0;
+#pragma unroll
+    for (int l = 0; l <= 2; ++l) {
+        const int lo = A.sa.lev_off[l], hi = A.sa.lev_off[l + 1];
+        const int64_t len = A.sb.le[max(A.L - l, 0)];
+        if (ia < hi) return r + (int64_t)(ia - lo) * len;
+        r += (int64_t)(hi - lo) * len;
+    }
+    return r;
 }
 
 // Beta class on alpha rows [row0, row0 + gridDim.x) whose beta strings reach
@@ -49,9 +77,10 @@ __device__ __forceinline__ double hpad(const double *__restrict__ hs, int norb, 
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0)
+                                                          const double *__restrict__ hs, const double *__restrict__ hp, int row0,
+                                                          int ovw)
 {
-    constexpr int NP = 16 * NT, SP = NP + 1;   // odd row stride: no bank conflicts on U[y][s]
+    constexpr int NP = 16 * NT, SP = NP + 1, NK = NP / 4, NTH = 64 * NT;   // odd row stride: no bank conflicts
     __shared__ double T[NP * SP];
     const int ia = row0 + blockIdx.x;
     const int v = blockIdx.y;
@@ -59,27 +88,38 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
     const int len = A.sb.le[A.L - A.alev[ia]];
     const double *cr = c + (int64_t)v * ldc + A.rowstart[ia];
     double *sr = sg + (int64_t)v * lds + A.rowstart[ia];
-    for (int t = threadIdx.x; t < NP * SP; t += 64 * NT) T[t] = 0.0;
-    __syncthreads();
-    for (int j = threadIdx.x; j < len; j += 64 * NT) {
-        const uint32_t bs = A.bstr[j];
-        const int y = bs & 0xff, s = (bs >> 8) & 0xff;
-        const double val = cr[j];
-        T[y * SP + s] = val;
-        T[s * SP + y] = -val;
-    }
-    __syncthreads();
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int am = 16 * w + (lane & 15), kq = lane >> 4;
+    double ah[NK];
+    load_hcol<NK>(hp, am, kq, ah);
+    for (int t = threadIdx.x; t < NP * SP; t += NTH) T[t] = 0.0;
+    __syncthreads();
+    for (int jb = threadIdx.x; jb < len; jb += kObBatch * NTH) {
+        uint32_t bs[kObBatch];
+        double val[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) {
+            const int j = min(jb + u * NTH, len - 1);
+            bs[u] = A.bstr[j];
+            val[u] = cr[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (jb + u * NTH < len) {
+                const int y = bs[u] & 0xff, s = (bs[u] >> 8) & 0xff;
+                T[y * SP + s] = val[u];
+                T[s * SP + y] = -val[u];
+            }
+    }
+    __syncthreads();
     v4d_ob acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int ks = 0; ks < NP / 4; ++ks) {
-        const int k = 4 * ks + kq;
-        const double a = hpad(hs, norb, am, k);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16(a, T[k * SP + 16 * nt + (lane & 15)], acc[nt]);
+    for (int ks = 0; ks < NK; ++ks) {
+        const int k = 4 * ks + kq;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16(ah[ks], T[k * SP + 16 * nt + (lane & 15)], acc[nt]);
     }
     __syncthreads();
 #pragma unroll
@@ -87,10 +127,21 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
 #pragma unroll
         for (int g = 0; g < 4; ++g) T[(16 * w + 4 * g + kq) * SP + 16 * nt + (lane & 15)] = acc[nt][g];
     __syncthreads();
-    for (int j = threadIdx.x; j < len; j += 64 * NT) {
-        const uint32_t bs = A.bstr[j];
-        const int y = bs & 0xff, s = (bs >> 8) & 0xff;
-        sr[j] += T[y * SP + s] - T[s * SP + y];
+    for (int jb = threadIdx.x; jb < len; jb += kObBatch * NTH) {
+        uint32_t bs[kObBatch];
+        double old[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) {
+            const int j = min(jb + u * NTH, len - 1);
+            bs[u] = A.bstr[j];
+            old[u] = ovw ? 0.0 : sr[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (jb + u * NTH < len) {
+                const int y = bs[u] & 0xff, s = (bs[u] >> 8) & 0xff;
+                sr[jb + u * NTH] = old[u] + (T[y * SP + s] - T[s * SP + y]);
+            }
     }
 }
 
@@ -105,12 +156,14 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_full(SigmaArgs A, const dou
 template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                           double *__restrict__ sg, int64_t lds,
-                                                          const double *__restrict__ hs, int row0, int nrows)
+                                                          const double *__restrict__ hs, const double *__restrict__ hp, int row0,
+                                                          int nrows, int ovw)
 {
-    constexpr int NP = 16 * NT, SP = NP + 1, NR = 16, NC = 2 * NR;
+    constexpr int NP = 16 * NT, SP = NP + 1, NR = 16, NC = 2 * NR, NK = NP / 4, NTH = 64 * NT;
     constexpr int RMAX = 1 + 2 * (kObMaxNorb - 2);   // longest row of level <= 1 strings
     __shared__ double U[NC * SP];   // U[col][b]
     __shared__ double R[NR * RMAX];
+    __shared__ int ro[NR + 1];      // row offsets within R
     const int r0 = blockIdx.x * NR;
     const int v = blockIdx.y;
     const int norb = A.norb;
@@ -118,38 +171,45 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const dou
     const int nr = min(NR, nrows - r0);
     const int64_t base0 = A.rowstart[row0 + r0];
     const int tot = (int)(A.rowstart[row0 + r0 + nr] - base0);
-    const double *cv = c + (int64_t)v * ldc;
-    for (int t = threadIdx.x; t < tot; t += 64 * NT) R[t] = cv[base0 + t];
-    __syncthreads();
+    const double *cv = c + (int64_t)v * ldc + base0;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int am = 16 * w + (lane & 15), kq = lane >> 4;
+    double ah[NK];
+    load_hcol<NK>(hp, am, kq, ah);
+    if (threadIdx.x <= NR) ro[threadIdx.x] = (int)(A.rowstart[row0 + r0 + min((int)threadIdx.x, nr)] - base0);
+    for (int tb = threadIdx.x; tb < tot; tb += kObBatch * NTH) {
+        double val[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) val[u] = cv[min(tb + u * NTH, tot - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (tb + u * NTH < tot) R[tb + u * NTH] = val[u];
+    }
+    __syncthreads();
     int co[2], coff[2], clen[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
         const int col = 16 * nt + (lane & 15);
-        const int rl = col / 2;
+        const int rl = col / 2;   // < NR
         co[nt] = col & 1;
-        coff[nt] = rl < nr ? (int)(A.rowstart[row0 + r0 + rl] - base0) : 0;
-        clen[nt] = rl < nr ? (int)(A.rowstart[row0 + r0 + rl + 1] - base0) - coff[nt] : 0;
+        coff[nt] = ro[rl];
+        clen[nt] = ro[rl + 1] - ro[rl];   // 0 past the last row
     }
     v4d_ob acc[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int ks = 0; ks < NP / 4; ++ks) {
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) {
         const int k = 4 * ks + kq;
-        const double a = hpad(hs, norb, am, k);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             const int o = co[nt];
-            // T[k][o]: {k, o} is {0,1} (k occupied) or {o, k} (level 1)
+            // T[k][o]: {k, o} is {0,1} (k occupied) or {o, k} (level 1); the
+            // LDS read is clamped into the row and selected afterwards
             const int idx = k < 2 ? 0 : lo1 + 2 * (k - 2) + o;
-            double b = 0.0;
-            if (k < norb && k != o && idx < clen[nt]) {
-                const double val = R[coff[nt] + idx];
-                b = k < o ? val : -val;
-            }
-            acc[nt] = mfma16(a, b, acc[nt]);
+            const bool ok = k < norb && k != o && idx < clen[nt];
+            const double val = R[coff[nt] + (ok ? idx : 0)];
+            acc[nt] = mfma16(ah[ks], ok ? (k < o ? val : -val) : 0.0, acc[nt]);
         }
     }
 #pragma unroll
@@ -159,203 +219,349 @@ __global__ __launch_bounds__(64 * NT) void k_ob_beta_cap1(SigmaArgs A, const dou
     __syncthreads();
     const double h00 = hs[0], h01 = hs[1], h11 = hs[norb + 1];
     double *sv = sg + (int64_t)v * lds + base0;
-    for (int t = threadIdx.x; t < tot; t += 64 * NT) {
-        // row of element t (rows are short and few: linear scan)
-        int rl = 0;
-        while (rl + 1 < nr && A.rowstart[row0 + r0 + rl + 1] - base0 <= t) ++rl;
-        const int off = (int)(A.rowstart[row0 + r0 + rl] - base0);
-        const int j = t - off;
-        const double *Ur = U + (2 * rl) * SP;   // column (rl, o = 0); (rl, 1) follows at +SP
-        double add;
-        if (j < lo1) {
-            add = Ur[SP + 0] - Ur[1];
-        } else {
-            const int o = (j - lo1) & 1, bv = 2 + (j - lo1) / 2;
-            const int jo = o ? t - 1 : t + 1;   // {o', b}
-            add = (o ? h11 : h00) * R[t] + h01 * R[jo] - Ur[o * SP + bv];
+    for (int tb = threadIdx.x; tb < tot; tb += kObBatch * NTH) {
+        double old[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) old[u] = ovw ? 0.0 : sv[min(tb + u * NTH, tot - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) {
+            const int t = tb + u * NTH;
+            if (t >= tot) break;
+            // row of element t (rows are short and few: scan of the offsets)
+            int rl = 0;
+            while (rl + 1 < nr && ro[rl + 1] <= t) ++rl;
+            const int j = t - ro[rl];
+            const double *Ur = U + (2 * rl) * SP;   // column (rl, o = 0); (rl, 1) follows at +SP
+            double add;
+            if (j < lo1) {
+                add = Ur[SP + 0] - Ur[1];
+            } else {
+                const int o = (j - lo1) & 1, bv = 2 + (j - lo1) / 2;
+                const int jo = o ? t - 1 : t + 1;   // {o', b}
+                add = (o ? h11 : h00) * R[t] + h01 * R[jo] - Ur[o * SP + bv];
+            }
+            sv[t] = old[u] + add;
         }
-        sv[t] += add;
     }
 }
 
-// Alpha class, spectator x = blockIdx.x, beta columns blockIdx.y * 64 +
-// [0, 64) (four 16-column N tiles), vector blockIdx.z; wave w computes the
-// targets a in [16 w, 16 w + 16) with a > x (up = 1) or a < x (up = 0).
-// Columns run to jlim(x): for x virtual the rows {q, x} with q virtual stop
-// at the level-2 row length, the columns above reach only {0,x} and {1,x}
-// (the two-term tail below).  The operands of the next K step are in
-// flight while the MFMAs of the current one issue.
-template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_ob_alpha(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
-                                                      double *__restrict__ sg, int64_t lds,
-                                                      const double *__restrict__ hs, int up, int jlim_occ,
-                                                      int jlim_virt)
+// Alpha class on the beta columns [0, jd) where every alpha pair exists
+// (beta level <= L - 2).  A workgroup takes NC consecutive columns of one
+// vector (consecutive column blocks run on one XCD: they share cache
+// lines) and holds their pair values P[col][ia] in LDS, ia the alpha string
+// of the pair, with the table pcode[q][b] = +-(ia + 1) of the ordered pair
+// (q, b) (sign: q < b; 0: q == b or padding).  Wave w forms the rows
+// [16 w, 16 w + 16) of U = h T for every column; the pair differences
+// U[a][b] - U[b][a] are gathered back into P (upper entries stored, then
+// lower ones subtracted) and added to sigma row by row.
+constexpr int kObDenseBatch = 16;
+
+template <int NT, int NC>
+__global__ __launch_bounds__(64 * NT) void k_ob_alpha_dense(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                            double *__restrict__ sg, int64_t lds,
+                                                            const double *__restrict__ hp, int jd, int ncb_per_xcd)
 {
-    constexpr int NP = 16 * NT;
-    const int x = blockIdx.x, v = blockIdx.z;
+    constexpr int NP = 16 * NT, NK = NP / 4, NTH = 64 * NT;
+    extern __shared__ double ob_smem[];
+    const int npair = A.sa.nstr;
+    double *P = ob_smem;                                      // [NC][npair]
+    short *pcode = (short *)(ob_smem + (size_t)NC * npair);   // [NP][NP]
+    const int cb = (blockIdx.x & 7) * ncb_per_xcd + (blockIdx.x >> 3);
+    const int j0 = cb * NC;
+    if (j0 >= jd) return;
+    const int v = blockIdx.y;
     const int norb = A.norb;
-    const int jlim = x < 2 ? jlim_occ : jlim_virt;
-    const int j0 = blockIdx.y * 64;
-    if (j0 >= jlim) return;
-    // row starts and lengths of {o, x} in LDS: the operand loads below then
-    // depend on no other global load
-    __shared__ long long rb[NP];
-    __shared__ int rl[NP];
-    for (int t = threadIdx.x; t < NP; t += 64 * NT) {
-        rb[t] = t < norb ? A.arow_base[x * norb + t] : -1;
-        rl[t] = t < norb ? A.arow_len[x * norb + t] : 0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = lane & 15, kq = lane >> 4;
+    double ah[NK];
+    load_hcol<NK>(hp, 16 * w + n, kq, ah);
+    {
+        // NP * NP = 4 NT * NTH entries: one batch of table loads
+        int ia[4 * NT];
+#pragma unroll
+        for (int i = 0; i < 4 * NT; ++i) {
+            const int t = threadIdx.x + i * NTH, q = t / NP, b = t % NP;
+            ia[i] = A.apidx[min(q, norb - 1) * norb + min(b, norb - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4 * NT; ++i) {
+            const int t = threadIdx.x + i * NTH, q = t / NP, b = t % NP;
+            const bool ok = q < norb && b < norb && q != b && ia[i] >= 0;
+            pcode[t] = (short)(ok ? (q < b ? ia[i] + 1 : -(ia[i] + 1)) : 0);
+        }
+    }
+    const double *cv = c + (int64_t)v * ldc;
+    const int ne = NC * npair;
+    for (int eb = threadIdx.x; eb < ne; eb += kObDenseBatch * NTH) {
+        double val[kObDenseBatch];
+#pragma unroll
+        for (int u = 0; u < kObDenseBatch; ++u) {
+            const int e = min(eb + u * NTH, ne - 1), col = e % NC;
+            val[u] = cv[row_start_n2(A, e / NC) + min(j0 + col, jd - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kObDenseBatch; ++u) {
+            const int e = eb + u * NTH;
+            if (e < ne) P[(e % NC) * npair + e / NC] = j0 + e % NC < jd ? val[u] : 0.0;
+        }
     }
     __syncthreads();
-    const int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // this wave's targets {a, x} on the requested side of x that hold a
-    // column of the block, and the sources {q, x} that hold one
-    const int at = 16 * mt + (lane & 15);
-    const bool tok = lane < 16 && at < norb && at != x && ((at > x) == (up != 0)) && rl[at] > j0;
-    if (__ballot(tok) == 0) return;
-    const int o1 = lane, o2 = lane + 64;
-    const bool s1 = o1 < norb && o1 != x && rl[o1] > j0;
-    const bool s2 = o2 < NP && o2 < norb && o2 != x && rl[o2] > j0;
-    const unsigned long long sm0 = __ballot(s1), sm1 = __ballot(s2);
-    unsigned km = 0;
+    v4d_ob acc[NC][NT];
 #pragma unroll
-    for (int ks = 0; ks < NP / 4; ++ks) {
-        const unsigned long long sm = ks < 16 ? sm0 >> (4 * ks) : sm1 >> (4 * (ks - 16));
-        if (sm & 0xfull) km |= 1u << ks;
-    }
-    const int n = lane & 15, kq = lane >> 4;
-    const double *cv = c + (int64_t)v * ldc;
-    auto next_ks = [&]() {
-        if (!km) return -1;
-        const int k = __ffs(km) - 1;
-        km &= km - 1;
-        return k;
-    };
-    // every lane loads from a valid address whatever the step (invalid
-    // operands are selected to zero afterwards): with no loads under
-    // branches the compiler can wait for one stage's loads only
-    auto load = [&](int ks, double &a, double *b) {
-        const int q = 4 * max(ks, 0) + kq;
-        const int qc = min(q, norb - 1), ac = min(16 * mt + n, norb - 1);
-        const double hv = hs[qc * norb + ac];
-        a = (ks >= 0 && q < norb && 16 * mt + n < norb) ? hv : 0.0;
-        const long long base = rb[qc];
-        const int len = min(rl[qc], jlim);
-        const bool rowok = ks >= 0 && q < norb && q != x && base >= 0;
-        const double f = q < x ? 1.0 : -1.0;
+    for (int col = 0; col < NC; ++col)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int j = j0 + 16 * nt + n;
-            const bool ok = rowok && j < len;
-            const double val = cv[ok ? base + j : 0];
-            b[nt] = ok ? f * val : 0.0;
+        for (int nt = 0; nt < NT; ++nt) acc[col][nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // B[q][b] = T[q][b] with q = 4 ks + kq, b = 16 nt + n
+            const int code = pcode[(4 * ks + kq) * NP + 16 * nt + n];
+            const int idx = (code > 0 ? code : -code) - 1;
+            const int ic = idx < 0 ? 0 : idx;
+#pragma unroll
+            for (int col = 0; col < NC; ++col) {
+                const double t = P[col * npair + ic];
+                acc[col][nt] = mfma16(ah[ks], code > 0 ? t : (code < 0 ? -t : 0.0), acc[col][nt]);
+            }
         }
-    };
-    v4d_ob acc[4];
+    __syncthreads();   // P is reused for the pair differences
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
-    // two K steps in flight: stages x and y ping-pong (no register copies)
-    double ax, bx[4], ay, by[4];
-    int kx = next_ks();
-    load(kx, ax, bx);
-    while (kx >= 0) {
-        const int ky = next_ks();
-        load(ky, ay, by);
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ax, bx[nt], acc[nt]);
-        if (ky < 0) break;
-        kx = next_ks();
-        load(kx, ax, bx);
+        for (int g = 0; g < 4; ++g) {
+            const int code = pcode[(16 * w + 4 * g + kq) * NP + 16 * nt + n];
+            if (code > 0)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ay, by[nt], acc[nt]);
-    }
+                for (int col = 0; col < NC; ++col) P[col * npair + code - 1] = acc[col][nt][g];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int code = pcode[(16 * w + 4 * g + kq) * NP + 16 * nt + n];
+            if (code < 0)
+#pragma unroll
+                for (int col = 0; col < NC; ++col) P[col * npair - code - 1] -= acc[col][nt][g];
+        }
+    __syncthreads();
     double *sv = sg + (int64_t)v * lds;
+    for (int eb = threadIdx.x; eb < ne; eb += kObDenseBatch * NTH) {
+        double old[kObDenseBatch];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int a = 16 * mt + 4 * g + kq;
-        if (a >= norb || a == x || ((a > x) != (up != 0))) continue;
-        const long long base = rb[a];
-        if (base < 0) continue;
-        const int len = min(rl[a], jlim);
+        for (int u = 0; u < kObDenseBatch; ++u) {
+            const int e = min(eb + u * NTH, ne - 1), col = e % NC;
+            old[u] = sv[row_start_n2(A, e / NC) + min(j0 + col, jd - 1)];
+        }
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int j = j0 + 16 * nt + n;
-            if (j < len) sv[base + j] += a < x ? acc[nt][g] : -acc[nt][g];
+        for (int u = 0; u < kObDenseBatch; ++u) {
+            const int e = eb + u * NTH;
+            if (e < ne && j0 + e % NC < jd)
+                sv[row_start_n2(A, e / NC) + j0 + e % NC] = old[u] + P[(e % NC) * npair + e / NC];
         }
     }
 }
 
-// Alpha class, the columns j in [j0, j1) of a virtual spectator x that only
-// the rows {0, x} and {1, x} hold:
-//   sigma({o, x}, j) += h_o0 c({0, x}, j) + h_o1 c({1, x}, j),  o = 0, 1.
-__global__ __launch_bounds__(256) void k_ob_alpha_tail(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
-                                                       double *__restrict__ sg, int64_t lds,
-                                                       const double *__restrict__ hs, int j0, int j1)
+// Alpha class on the beta columns [j0c, jc) where the alpha pairs {0,1} and
+// {o, v} exist and no {v, w} (beta level L - 1).  A workgroup takes 64
+// columns of one vector and stages the signed rows
+//   B_o[q][j] = T_j[q][o] = +-c({q, o}, j)
+// of both occupied o in LDS; wave w forms U[a][o] for a in [16 w, 16 w + 16)
+// (K = q).  Then, for a virtual v,
+//   sigma({o, v}) += U[o][v] - U[v][o],  U[o][v] = h_o0 T[0][v] + h_o1 T[1][v]
+// (T[q][v] vanishes for virtual q here), and sigma({0,1}) += U[0][1] - U[1][0].
+template <int NT>
+__global__ __launch_bounds__(64 * NT) void k_ob_alpha_cross(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                            double *__restrict__ sg, int64_t lds,
+                                                            const double *__restrict__ hs, const double *__restrict__ hp, int j0c,
+                                                            int jc)
 {
-    const int x = 2 + blockIdx.x, v = blockIdx.z;
-    const int j = j0 + blockIdx.y * 256 + threadIdx.x;
+    constexpr int NP = 16 * NT, NK = NP / 4, NTH = 64 * NT, NRT = 2 * NP / NT;
+    __shared__ double B[2 * NP * 64];   // [o][q][jj]
+    __shared__ long long rbase[2 * NP];  // row {q, o} of staged row (o, q); -1: none
+    const int j0 = j0c + blockIdx.x * 64;
+    const int v = blockIdx.y;
     const int norb = A.norb;
-    const long long b0 = A.arow_base[x * norb + 0], b1 = A.arow_base[x * norb + 1];
-    const int l0 = A.arow_len[x * norb + 0], l1 = A.arow_len[x * norb + 1];
-    if (j >= j1 || b0 < 0 || b1 < 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = lane & 15, kq = lane >> 4;
+    double ah[NK];
+    load_hcol<NK>(hp, 16 * w + n, kq, ah);
+    for (int t = threadIdx.x; t < 2 * NP; t += NTH) {
+        const int o = t / NP, q = t % NP;
+        rbase[t] = q < norb ? A.arow_base[o * norb + q] : -1;
+    }
+    __syncthreads();
     const double *cv = c + (int64_t)v * ldc;
+    // staged row (o, q) = w + NT i of the 2 NP rows, column lane; rows {q, o}
+    // span [0, jc) (none for q = o)
+    const int jl = j0 + lane, jcl = min(jl, jc - 1);
+    {
+        double val[NRT];
+#pragma unroll
+        for (int i = 0; i < NRT; ++i) {
+            const long long base = rbase[w + NT * i];
+            val[i] = cv[(base >= 0 ? base : 0) + jcl];
+        }
+#pragma unroll
+        for (int i = 0; i < NRT; ++i) {
+            const int r = w + NT * i, o = r / NP, q = r % NP;
+            const bool ok = rbase[r] >= 0 && jl < jc;
+            B[r * 64 + lane] = ok ? (q < o ? val[i] : -val[i]) : 0.0;
+        }
+    }
+    __syncthreads();
+    v4d_ob acc[2][4];
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[o][nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks)
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[o][nt] = mfma16(ah[ks], B[(o * NP + 4 * ks + kq) * 64 + 16 * nt + n], acc[o][nt]);
+    // epilogue per staged row (o, a) of this thread, column lane: first the
+    // two-term U[o][a] from the staged operands, then U[a][o] from the
+    // products through LDS (over the operands), then one batch of sigma
+    // updates (coalesced rows)
+    const double h00 = hs[0], h01 = hs[1], h11 = hs[norb + 1];
+    double add[NRT];
+#pragma unroll
+    for (int i = 0; i < NRT; ++i) {
+        const int r = w + NT * i, o = r / NP, a = r % NP;
+        const double ho0 = o ? h01 : h00, ho1 = o ? h11 : h01;
+        // T[0][a] = -B_0[a][jj], T[1][a] = -B_1[a][jj] (zero for a < 2)
+        add[i] = a >= 2 ? -(ho0 * B[a * 64 + lane] + ho1 * B[(NP + a) * 64 + lane]) : 0.0;
+    }
+    __syncthreads();   // B is overwritten with the products U[a][o] below
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) B[(o * NP + 16 * w + 4 * g + kq) * 64 + 16 * nt + n] = acc[o][nt][g];
+    __syncthreads();
     double *sv = sg + (int64_t)v * lds;
-    const double c0 = j < l0 ? cv[b0 + j] : 0.0, c1 = j < l1 ? cv[b1 + j] : 0.0;
-    if (j < l0) sv[b0 + j] += hs[0] * c0 + hs[1] * c1;
-    if (j < l1) sv[b1 + j] += hs[norb] * c0 + hs[norb + 1] * c1;
+    const long long b01 = rbase[1];   // row {0, 1} (staged row o = 0, q = 1)
+    double old[NRT];
+#pragma unroll
+    for (int i = 0; i < NRT; ++i) {
+        const long long base = rbase[w + NT * i];
+        old[i] = sv[(base >= 0 ? base : b01) + jcl];
+    }
+#pragma unroll
+    for (int i = 0; i < NRT; ++i) {
+        const int r = w + NT * i, o = r / NP, a = r % NP;
+        if (jl >= jc || a >= norb) continue;
+        if (a >= 2) {
+            // sigma({o, a}) += U[o][a] - U[a][o]
+            sv[rbase[r] + jl] = old[i] + (add[i] - B[r * 64 + lane]);
+        } else if (o == 1 && a == 0) {
+            // sigma({0, 1}) += U[0][1] - U[1][0]
+            sv[b01 + jl] = old[i] + (B[(NP + 0) * 64 + lane] - B[1 * 64 + lane]);
+        }
+    }
+}
+
+// Alpha class on the beta columns [j0, j1) where only the alpha pair {0,1}
+// exists: U[0][1] - U[1][0] = (h_00 + h_11) c({0,1}).
+__global__ __launch_bounds__(256) void k_ob_alpha_occ(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                      double *__restrict__ sg, int64_t lds,
+                                                      const double *__restrict__ hs, int j0, int j1)
+{
+    const int j = j0 + blockIdx.x * 256 + threadIdx.x, v = blockIdx.y;
+    if (j >= j1) return;
+    const long long base = A.arow_base[1];   // row {0, 1}
+    sg[(int64_t)v * lds + base + j] += (hs[0] + hs[A.norb + 1]) * c[(int64_t)v * ldc + base + j];
 }
 
 template <int NT>
 static void launch_ob_beta(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
-                           int64_t lds, hipStream_t st)
+                           int64_t lds, int ovw, hipStream_t st)
 {
-    const double *hs = cx->d.hscreen;
+    const double *hs = cx->d.hscreen, *hp = cx->d.hpad;
     const int L = cx->L;
     // alpha rows by level: beta strings up to level 2 for level <= L - 2
     const int full_end = L >= 2 ? cx->sa.le[L - 2] : 0;
     if (full_end > 0)
-        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, 0);
+        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, hp, 0, ovw);
     const int ncap1 = cx->sa.nstr - full_end;   // rows whose beta strings stop at level 1 or 0
     if (ncap1 > 0)
         k_ob_beta_cap1<NT><<<dim3((unsigned)((ncap1 + 15) / 16), (unsigned)nv), 64 * NT, 0, st>>>(
-            A, c, ldc, s, lds, hs, full_end, ncap1);
+            A, c, ldc, s, lds, hs, hp, full_end, ncap1, ovw);
+}
+
+static int max_lds_bytes(const isci_ctx *cx)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, cx->device) != hipSuccess) v = 65536;
+    return v;
+}
+
+template <int NT, int NC>
+static isci_status launch_ob_dense(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
+                                   double *s, int64_t lds, int jd, size_t shm, hipStream_t st)
+{
+    const int ncb = (jd + NC - 1) / NC, per = (ncb + 7) / 8;
+    if (shm > 65536)
+        ISCI_HIP(hipFuncSetAttribute((const void *)k_ob_alpha_dense<NT, NC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_ob_alpha_dense<NT, NC><<<dim3((unsigned)(8 * per), (unsigned)nv), 64 * NT, shm, st>>>(
+        A, c, ldc, s, lds, cx->d.hpad, jd, per);
+    return ISCI_OK;
 }
 
 template <int NT>
-static void launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
-                            int64_t lds, hipStream_t st)
+static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
+                                   double *s, int64_t lds, hipStream_t st)
 {
     const double *hs = cx->d.hscreen;
     const int L = cx->L;
-    // rows {q, x} hold beta strings up to level L - level({q, x}); for x
-    // occupied every column reaches some row of level <= 1, for x virtual
-    // the columns above the level-2 row length only reach {0,x}, {1,x}
+    // beta columns by level: every alpha pair up to level L - 2, the pairs
+    // {0,1} and {o, v} at level L - 1, {0,1} alone at level L
     const int *le_b = cx->sb.le;
-    const int jlim_occ = le_b[L];
-    const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
-    const int jtail = L >= 1 ? le_b[L - 1] : 0;
-    const dim3 ga((unsigned)cx->norb, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
-    for (int up = 1; up >= 0; --up)
-        k_ob_alpha<NT><<<ga, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt);
-    if (jtail > jlim_virt && cx->norb > 2)
-        k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
-                          0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);
+    const int jd = L >= 2 ? le_b[L - 2] : 0;
+    const int jc = L >= 1 ? le_b[L - 1] : 0;
+    const int jall = le_b[L];
+    if (jd > 0) {
+        // two columns per workgroup: the pair block of 80 orbitals still
+        // fits 64 KB of LDS, and two or three workgroups share a CU
+        constexpr int NP = 16 * NT;
+        const size_t shm = 2 * (size_t)cx->sa.nstr * sizeof(double) + NP * NP * sizeof(short);
+        if (shm > (size_t)max_lds_bytes(cx)) {
+            set_error("one-body matrix-core path: alpha pair block exceeds LDS");
+            return ISCI_E_UNSUPPORTED;
+        }
+        ISCI_CHECK((launch_ob_dense<NT, 2>(cx, A, nv, c, ldc, s, lds, jd, shm, st)));
+    }
+    if (jc > jd)
+        k_ob_alpha_cross<NT><<<dim3((unsigned)((jc - jd + 63) / 64), (unsigned)nv), 64 * NT, 0, st>>>(
+            A, c, ldc, s, lds, hs, cx->d.hpad, jd, jc);
+    if (jall > jc)
+        k_ob_alpha_occ<<<dim3((unsigned)((jall - jc + 255) / 256), (unsigned)nv), 256, 0, st>>>(A, c, ldc, s, lds,
+                                                                                                 hs, jc, jall);
+    return ISCI_OK;
 }
 
 bool onebody_mfma_ok(const isci_ctx *cx)
 {
     return cx->d.hscreen && cx->na == 2 && cx->nb == 2 && cx->norb >= 3 && cx->norb <= kObMaxNorb &&
-           cx->d.arow_base && cx->d.arow_len;
+           cx->d.arow_base && cx->d.arow_len && cx->d.apidx && cx->d.hpad;
 }
 
 isci_status launch_onebody_mfma(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s, int64_t lds,
-                                hipStream_t st)
+                                hipStream_t st, bool first)
 {
+    const int ovw = first ? 1 : 0;
     const SigmaArgs A = sigma_args(cx);
     const int nt = (cx->norb + 15) / 16;
-#define ISCI_OB_CASE(N)                                               \
-    case N:                                                           \
-        launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, st);             \
-        launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st);            \
+#define ISCI_OB_CASE(N)                                                      \
+    case N:                                                                  \
+        launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, ovw, st);                    \
+        ISCI_CHECK(launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st));       \
         break;
     switch (nt) {
         ISCI_OB_CASE(1)

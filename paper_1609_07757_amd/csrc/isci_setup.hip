@@ -368,6 +368,15 @@ __global__ void k_hscreen(const double *h, int n, double tau, double *hs)
     hs[t] = fabs(v) > tau ? v : 0.0;
 }
 
+// hs (n x n) into the top-left corner of a zeroed P x P array
+__global__ void k_hpad(const double *hs, int n, int P, double *hp)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * P) return;
+    const int p = t / P, q = t % P;
+    hp[t] = (p < n && q < n) ? hs[p * n + q] : 0.0;
+}
+
 // diagonal units: h_pp, (pp|qq), and (pp|qq) - (pq|qp) formed with the
 // smaller index first
 __global__ void k_diag_units(const double *h, const double *eri, int n, double *hd, double *jj, double *ssd)
@@ -764,6 +773,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
     c->abx_ntrow = (int)trow.size();
     c->abx_nrows = (int)rows.size();
+    c->abx_sbytes = sbytes;
     c->abx_xmax = xmax;
     for (int k = 0; k < 3; ++k) c->abx_pcols[k] = pcols[k];
     c->have_abx = true;
@@ -777,6 +787,15 @@ static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
     if (!c->d.hscreen) { set_error("device allocation failed (h)"); return ISCI_E_OOM; }
     k_hscreen<<<(n * n + 255) / 256, 256, 0, s>>>(h, n, c->tau, c->d.hscreen);
     ISCI_HIP(hipGetLastError());
+    if (n <= kObMaxNorb) {
+        // zero-padded copy: the matrix-core one-body kernels load their h
+        // operands with no bounds conditions
+        constexpr int P = kObMaxNorb;
+        c->d.hpad = (double *)dev_alloc(c, sizeof(double) * P * P);
+        if (!c->d.hpad) { set_error("device allocation failed (h)"); return ISCI_E_OOM; }
+        k_hpad<<<(P * P + 255) / 256, 256, 0, s>>>(c->d.hscreen, n, P, c->d.hpad);
+        ISCI_HIP(hipGetLastError());
+    }
     return ISCI_OK;
 }
 
@@ -885,6 +904,12 @@ static void destroy(isci_ctx *c)
 {
     if (!c) return;
     prof_clear(c);
+    if (c->ob_stream) {
+        (void)hipStreamSynchronize(c->ob_stream);
+        (void)hipStreamDestroy(c->ob_stream);
+    }
+    if (c->ob_fork) (void)hipEventDestroy(c->ob_fork);
+    if (c->ob_join) (void)hipEventDestroy(c->ob_join);
     for (void *p : c->allocs) (void)hipFree(p);
     for (void *p : c->work) (void)hipFree(p);
     delete c;
@@ -1051,6 +1076,18 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         st = build_hscreen(c, h, stream);
         if (st == ISCI_OK) st = build_tiles(c, eri, stream);
         if (st == ISCI_OK) st = build_abx(c, stream);
+        if (st == ISCI_OK && c->have_abx && !c->onebody_in_tiles && onebody_mfma_ok(c)) {
+            // side stream (default priority) for the one-body classes and a
+            // second S buffer, so both 4-vector products run before the
+            // folds; without the buffer sigma runs the classes in turn
+            c->d.abx_S2 = (double *)dev_alloc(c, c->abx_sbytes);
+            if (c->d.abx_S2) {
+                hipError_t e = hipStreamCreateWithFlags(&c->ob_stream, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ob_fork, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ob_join, hipEventDisableTiming);
+                if (e != hipSuccess) st = hip_fail(e, "one-body side stream");
+            }
+        }
         if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     }

@@ -739,50 +739,71 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
             // unfold / block-sparse product / fold path when its operands
             // fit, else with the gathered tile kernel), then the one-body
             // (unless the tiles carry it) and same-spin classes add.
-            for (int u0 = 0; u0 < nv; u0 += 4) {
-                const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                if (c->have_abx && !c->ab_gather) {
-                    ISCI_CHECK(launch_ab_product(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
-                } else if (c->nquad > 0) {
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
-                    if (c->norb <= kTabMax)
-                        k_sigma_ab_mfma<4, true><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                           ss + (int64_t)u0 * lds, lds);
-                    else
-                        k_sigma_ab_mfma<4, false><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                            ss + (int64_t)u0 * lds, lds);
-                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
-                }
-            }
-            if (c->d.hscreen && !c->onebody_in_tiles) {
-                // one-body classes (matrix cores when the orbital count allows,
-                // else alpha in two launches by spectator side, then beta),
-                // then same-spin if any; with dense integrals the tiles carry
-                // the one-body units instead
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
-                if (onebody_mfma_ok(c)) {
-                    ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
-                } else {
-                    const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
-                    for (int u0 = 0; u0 < nv; u0 += 4) {
-                        const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                        for (int up = 1; up >= 0; --up)
-                            k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                               ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
-                        size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
-                        if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
-                        if (shm <= 65536)
-                            k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
-                                A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+            if (c->ob_stream && !c->ab_gather && c->d.hscreen && !c->onebody_in_tiles) {
+                // the one-body classes (beta writes sigma, alpha adds) run on
+                // the side stream while the unfolds and products of both
+                // 4-vector passes run here (into two S buffers); the folds
+                // wait for them and add
+                ISCI_HIP(hipEventRecord(c->ob_fork, s));
+                ISCI_HIP(hipStreamWaitEvent(c->ob_stream, c->ob_fork, 0));
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, c->ob_stream));
+                ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, c->ob_stream, true));
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, c->ob_stream));
+                ISCI_HIP(hipEventRecord(c->ob_join, c->ob_stream));
+                for (int u0 = 0; u0 < nv; u0 += 4)
+                    ISCI_CHECK(launch_ab_unfold_gemm(c, nv - u0 < 4 ? nv - u0 : 4, cc + (int64_t)u0 * ldc, ldc,
+                                                     u0 ? c->d.abx_S2 : c->d.abx_S, s));
+                ISCI_HIP(hipStreamWaitEvent(s, c->ob_join, 0));
+                for (int u0 = 0; u0 < nv; u0 += 4)
+                    ISCI_CHECK(launch_ab_fold(c, nv - u0 < 4 ? nv - u0 : 4, u0 ? c->d.abx_S2 : c->d.abx_S,
+                                              ss + (int64_t)u0 * lds, lds, true, s));
+                if (c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
+            } else {
+                for (int u0 = 0; u0 < nv; u0 += 4) {
+                    const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                    if (c->have_abx && !c->ab_gather) {
+                        ISCI_CHECK(launch_ab_product(c, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, s));
+                    } else if (c->nquad > 0) {
+                        ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, true, s));
+                        if (c->norb <= kTabMax)
+                            k_sigma_ab_mfma<4, true><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                               ss + (int64_t)u0 * lds, lds);
                         else
-                            k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
-                                A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                            k_sigma_ab_mfma<4, false><<<c->nquad, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                                ss + (int64_t)u0 * lds, lds);
+                        ISCI_CHECK(prof_mark(c, ISCI_KERNEL_AB_MFMA, false, s));
                     }
-                    ISCI_HIP(hipGetLastError());
                 }
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
+                if (c->d.hscreen && !c->onebody_in_tiles) {
+                    // one-body classes (matrix cores when the orbital count allows,
+                    // else alpha in two launches by spectator side, then beta),
+                    // then same-spin if any; with dense integrals the tiles carry
+                    // the one-body units instead
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
+                    if (onebody_mfma_ok(c)) {
+                        ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
+                    } else {
+                        const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
+                        for (int u0 = 0; u0 < nv; u0 += 4) {
+                            const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                            for (int up = 1; up >= 0; --up)
+                                k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                   ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
+                            size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
+                            if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
+                            if (shm <= 65536)
+                                k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
+                                    A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                            else
+                                k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
+                                    A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
+                        }
+                        ISCI_HIP(hipGetLastError());
+                    }
+                    ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
+                }
+                if (c->d.hscreen && c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
             }
-            if (c->d.hscreen && c->stats.kept_total - c->nkept_h - c->nkept_ab == 0) continue;   // no same-spin units
             ISCI_CHECK(prof_mark(c, ISCI_KERNEL_PAIR_REST, true, s));
             SigmaArgs B = A;
             B.classes = c->d.hscreen ? 2 : 3;
