@@ -105,7 +105,10 @@ __global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
     const int g = tl.x;
     const int Ab = g / nb, Bb = g % nb;
     const int m = (Ab != 0) + (Bb != 0);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave index made explicitly uniform: the chunk range and the chunk
+    // table reads below then compile to scalar loads, which retire apart
+    // from the vector loads of the operands
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int cw = wave & 3, part = wave >> 2;
     const int c0 = tl.y * 256 + cw * 64;
     const int swidth = A.abx_pcols[m];
