@@ -85,11 +85,12 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 }
 
 // S for one row block pair and 256 columns (one tile).  The tiles, ordered
-// by row block pair, are split at setup into eight contiguous runs of
-// about equal work; workgroups are dealt to the eight XCDs round-robin,
-// so workgroup b takes tile b / 8 of run b % 8: each XCD sweeps
-// neighbouring row block pairs, whose chunks read largely the same rows
-// of T, through its own L2.  Within a tile, wave w takes the 64 columns
+// column slab by column slab, are split at setup into eight contiguous
+// runs of about equal work; workgroups are dealt to the eight XCDs
+// round-robin, so workgroup b takes tile b / 8 of run b % 8 (its whole
+// description is one table entry, read with one scalar load): each XCD
+// sweeps the row block pairs of a few slabs, and the slab of T they read
+// stays in its own L2.  Within a tile, wave w takes the 64 columns
 // (w % 4) and the (w / 4)-th of KS contiguous parts of the chunk list
 // (more waves in flight per tile); the parts are summed through LDS in a
 // fixed order.
@@ -98,11 +99,9 @@ __global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
 {
     __shared__ double red[KS > 1 ? KS - 1 : 1][4][16][64];
     const int nb = A.nblk;
-    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
-    const int t = A.abx_xrun[xcd] + local;
-    if (t >= A.abx_xrun[xcd + 1]) return;
-    const int2 tl = A.abx_tiles[t];   // (row block pair, column slab)
-    const int g = tl.x;
+    const AbBlk tb = A.abx_blk[blockIdx.x];   // one scalar load: the tile of this workgroup
+    if (tb.g < 0) return;
+    const int g = tb.g;
     const int Ab = g / nb, Bb = g % nb;
     const int m = (Ab != 0) + (Bb != 0);
     // wave index made explicitly uniform: the chunk range and the chunk
@@ -110,15 +109,15 @@ __global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
     // from the vector loads of the operands
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int cw = wave & 3, part = wave >> 2;
-    const int c0 = tl.y * 256 + cw * 64;
+    const int c0 = tb.c0 + cw * 64;
     const int swidth = A.abx_pcols[m];
     const bool active = c0 < swidth;
     // chunks whose class keeps these columns valid: classes l with
     // c0 < pcols[max(l, m)], a prefix of the class-ordered list
-    const int eb = A.chunk_off[g];
+    const int eb = tb.eb;
     int ee = eb;
     for (int l = 0; l < 3; ++l)
-        if (c0 < A.abx_pcols[max(l, m)]) ee += A.chunk_cls[g * 3 + l];
+        if (c0 < A.abx_pcols[max(l, m)]) ee = tb.end[l];
     const int e0 = eb + (int)((long long)(ee - eb) * part / KS);
     const int e1 = eb + (int)((long long)(ee - eb) * (part + 1) / KS);
     const int k = lane >> 4, n = lane & 15;

@@ -33,6 +33,14 @@ struct SpinTab {
     int le[ISCI_MAXLEV + 2];     // number of strings with level <= l (l = 0..L)
 };
 
+// One workgroup of the alpha-beta product: row block pair g (-1: idle
+// workgroup), first column c0 of its 256-column slab, its chunk list from
+// eb, and the list ends end[l] that admit source classes <= l.
+struct AbBlk {
+    int g, c0, eb, pad;
+    int end[3], pad2;
+};
+
 // Device tables owned by a handle.
 struct DevTabs {
     uint32_t *astr = nullptr, *bstr = nullptr;  // packed strings (8 bits per orbital)
@@ -91,8 +99,7 @@ struct DevTabs {
     int2 *abx_chunk = nullptr;
     int *abx_rows = nullptr;
     long long *abx_soff = nullptr;
-    int2 *abx_tiles = nullptr;      // product tiles (row block pair, 256-column slab)
-    int *abx_xrun = nullptr;        // [9]: tile runs of the eight XCDs
+    AbBlk *abx_blk = nullptr;       // [8 * abx_xmax]: the product tile of each workgroup
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
@@ -130,8 +137,7 @@ struct SigmaArgs {
     const int2 *abx_chunk;
     const int *abx_rows;
     const long long *abx_soff;
-    const int2 *abx_tiles;
-    const int *abx_xrun;
+    const AbBlk *abx_blk;
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };

@@ -430,8 +430,7 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.abx_chunk = c->d.abx_chunk;
     A.abx_rows = c->d.abx_rows;
     A.abx_soff = c->d.abx_soff;
-    A.abx_tiles = c->d.abx_tiles;
-    A.abx_xrun = c->d.abx_xrun;
+    A.abx_blk = c->d.abx_blk;
     A.abx_T = c->d.abx_T;
     A.abx_S = c->d.abx_S;
     for (int k = 0; k < 3; ++k) A.abx_pcols[k] = c->abx_pcols[k];
@@ -703,20 +702,23 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     const size_t tbytes = sizeof(double) * std::max<size_t>(1, tsize);
     const size_t sbytes = sizeof(double) * std::max<size_t>(1, ssize);
     if (tbytes + sbytes > kAbxMaxBytes) return ISCI_OK;   // gathered kernel instead
-    // product tiles by row block pair, cost ~ chunks applied + 1, cut into
-    // eight contiguous runs of about equal cost (one per XCD)
+    // product tiles column slab by column slab (all row block pairs of a
+    // 256-column slab together: the slab of T they read, a few MB, stays in
+    // one XCD's L2), cost ~ chunks applied + 1, cut into eight contiguous
+    // runs of about equal cost (one per XCD)
     std::vector<int2> tiles;
     std::vector<double> cost;
-    for (int g : rows) {
-        const int m = (g / nb != 0) + (g % nb != 0);
-        for (int sl = 0; sl * 256 < pcols[m]; ++sl) {
+    const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + 255) / 256;
+    for (int sl = 0; sl < nslab; ++sl)
+        for (int g : rows) {
+            const int m = (g / nb != 0) + (g % nb != 0);
+            if (sl * 256 >= pcols[m]) continue;
             int ne = 0;
             for (int l = 0; l < 3; ++l)
                 if (sl * 256 < pcols[std::max(l, m)]) ne += cls[3 * g + l];
             tiles.push_back(make_int2(g, sl));
             cost.push_back(1.0 + ne);
         }
-    }
     double total = 0.0;
     for (double w : cost) total += w;
     std::vector<int> xrun(9, 0);
@@ -732,6 +734,20 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     }
     int xmax = 0;
     for (int r = 0; r < 8; ++r) xmax = std::max(xmax, xrun[r + 1] - xrun[r]);
+    // workgroup b runs on XCD b % 8 and takes tile b / 8 of that XCD's run
+    std::vector<AbBlk> blk((size_t)8 * std::max(xmax, 1));
+    for (size_t b = 0; b < blk.size(); ++b) {
+        AbBlk &e = blk[b];
+        e = AbBlk{-1, 0, 0, 0, {0, 0, 0}, 0};
+        const int r = (int)(b % 8), t = xrun[r] + (int)(b / 8);
+        if (t >= xrun[r + 1]) continue;
+        const int g = tiles[t].x;
+        e.g = g;
+        e.c0 = tiles[t].y * 256;
+        e.eb = off[g];
+        int acc = off[g];
+        for (int l = 0; l < 3; ++l) e.end[l] = (acc += cls[3 * g + l]);
+    }
     DevTabs &d = c->d;
     d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
     d.abx_col = (int *)dev_alloc(c, sizeof(int) * col.size());
@@ -740,12 +756,11 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * chunk.size());
     d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
     d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
-    d.abx_tiles = (int2 *)dev_alloc(c, sizeof(int2) * std::max<size_t>(1, tiles.size()));
-    d.abx_xrun = (int *)dev_alloc(c, sizeof(int) * xrun.size());
+    d.abx_blk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * blk.size());
     d.abx_T = (double *)dev_alloc(c, tbytes);
     d.abx_S = (double *)dev_alloc(c, sbytes);
-    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_tiles ||
-        !d.abx_xrun || !d.abx_T || !d.abx_S) {
+    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_blk ||
+        !d.abx_T || !d.abx_S) {
         set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
     }
@@ -767,9 +782,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     if (!rows.empty())
         ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_soff, soff.data(), sizeof(long long) * soff.size(), hipMemcpyHostToDevice, s));
-    if (!tiles.empty())
-        ISCI_HIP(hipMemcpyAsync(d.abx_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, s));
-    ISCI_HIP(hipMemcpyAsync(d.abx_xrun, xrun.data(), sizeof(int) * xrun.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_blk, blk.data(), sizeof(AbBlk) * blk.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
     c->abx_ntrow = (int)trow.size();
     c->abx_nrows = (int)rows.size();
