@@ -25,8 +25,8 @@
 //
 //  * unfold: every (q, S) that opens a chunk gets 4 rows of T, pcols[class]
 //    wide; each determinant scatters its values into T once per call;
-//  * product: a workgroup takes one row block pair and 256 columns; each
-//    wave four 16-column tiles; K runs over the chunks whose class leaves
+//  * product: a workgroup takes one row block pair and kAbTile (256)
+//    columns; each wave four 16-column tiles; K runs over the chunks whose class leaves
 //    the columns valid (a prefix of the chunk list); S gets 16 rows x
 //    pcols[class of the row block pair];
 //  * fold: every determinant sums its four role readings of S and writes
@@ -40,8 +40,6 @@ namespace isci {
 
 typedef double v4d_ab __attribute__((ext_vector_type(4)));
 
-// chunk-list parts per product tile (waves per tile = 4 * kAbSplit)
-constexpr int kAbSplit = 2;
 
 __device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
 __device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
@@ -84,20 +82,20 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
     }
 }
 
-// S for one row block pair and 256 columns (one tile).  The tiles, ordered
+// S for one row block pair and 64 CW columns (one tile).  The tiles, ordered
 // column slab by column slab, are split at setup into eight contiguous
 // runs of about equal work; workgroups are dealt to the eight XCDs
 // round-robin, so workgroup b takes tile b / 8 of run b % 8 (its whole
 // description is one table entry, read with one scalar load): each XCD
 // sweeps the row block pairs of a few slabs, and the slab of T they read
 // stays in its own L2.  Within a tile, wave w takes the 64 columns
-// (w % 4) and the (w / 4)-th of KS contiguous parts of the chunk list
+// (w % CW) and the (w / CW)-th of KS contiguous parts of the chunk list
 // (more waves in flight per tile); the parts are summed through LDS in a
 // fixed order.
-template <int KS>
-__global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
+template <int CW, int KS>
+__global__ __launch_bounds__(64 * CW * KS) void k_ab_gemm(SigmaArgs A)
 {
-    __shared__ double red[KS > 1 ? KS - 1 : 1][4][16][64];
+    __shared__ double red[KS > 1 ? KS - 1 : 1][CW][16][64];
     const int nb = A.nblk;
     const AbBlk tb = A.abx_blk[blockIdx.x];   // one scalar load: the tile of this workgroup
     if (tb.g < 0) return;
@@ -108,7 +106,7 @@ __global__ __launch_bounds__(256 * KS) void k_ab_gemm(SigmaArgs A)
     // table reads below then compile to scalar loads, which retire apart
     // from the vector loads of the operands
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int cw = wave & 3, part = wave >> 2;
+    const int cw = wave % CW, part = wave / CW;
     const int c0 = tb.c0 + cw * 64;
     const int swidth = A.abx_pcols[m];
     const bool active = c0 < swidth;
@@ -240,7 +238,7 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     }
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
-        k_ab_gemm<kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 256 * kAbSplit, 0, st>>>(A);
+        k_ab_gemm<kAbCW, kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
     ISCI_HIP(hipGetLastError());

@@ -33,8 +33,14 @@ struct SpinTab {
     int le[ISCI_MAXLEV + 2];     // number of strings with level <= l (l = 0..L)
 };
 
+// alpha-beta product tiles: 64-column groups per tile (one per wave) and
+// parts of the chunk list per tile (waves per tile = kAbCW * kAbSplit)
+constexpr int kAbCW = 4;
+constexpr int kAbSplit = 2;
+constexpr int kAbTile = 64 * kAbCW;   // columns per tile
+
 // One workgroup of the alpha-beta product: row block pair g (-1: idle
-// workgroup), first column c0 of its 256-column slab, its chunk list from
+// workgroup), first column c0 of its kAbTile-column slab, its chunk list from
 // eb, and the list ends end[l] that admit source classes <= l.
 struct AbBlk {
     int g, c0, eb, pad;

@@ -703,19 +703,19 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     const size_t sbytes = sizeof(double) * std::max<size_t>(1, ssize);
     if (tbytes + sbytes > kAbxMaxBytes) return ISCI_OK;   // gathered kernel instead
     // product tiles column slab by column slab (all row block pairs of a
-    // 256-column slab together: the slab of T they read, a few MB, stays in
+    // kAbTile-column slab together: the slab of T they read, a few MB, stays in
     // one XCD's L2), cost ~ chunks applied + 1, cut into eight contiguous
     // runs of about equal cost (one per XCD)
     std::vector<int2> tiles;
     std::vector<double> cost;
-    const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + 255) / 256;
+    const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + kAbTile - 1) / kAbTile;
     for (int sl = 0; sl < nslab; ++sl)
         for (int g : rows) {
             const int m = (g / nb != 0) + (g % nb != 0);
-            if (sl * 256 >= pcols[m]) continue;
+            if (sl * kAbTile >= pcols[m]) continue;
             int ne = 0;
             for (int l = 0; l < 3; ++l)
-                if (sl * 256 < pcols[std::max(l, m)]) ne += cls[3 * g + l];
+                if (sl * kAbTile < pcols[std::max(l, m)]) ne += cls[3 * g + l];
             tiles.push_back(make_int2(g, sl));
             cost.push_back(1.0 + ne);
         }
@@ -743,7 +743,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         if (t >= xrun[r + 1]) continue;
         const int g = tiles[t].x;
         e.g = g;
-        e.c0 = tiles[t].y * 256;
+        e.c0 = tiles[t].y * kAbTile;
         e.eb = off[g];
         int acc = off[g];
         for (int l = 0; l < 3; ++l) e.end[l] = (acc += cls[3 * g + l]);
