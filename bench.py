@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# revision of each kernel's code: stored HBM traffic (profiles/sigma_traffic.json)
+# is used only when it was counted for the same revision
+KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table"}
 HBM_PEAK_GBS = 8000.0
 METRIC = "σ-vectors/s + screened terms/s (% roofline); p50/p99 Davidson solve latency"
 
@@ -147,7 +150,7 @@ def main():
         try:
             tj = json.load(open(a.traffic_json))
             key = f"{a.workload}:nvec{nvec}:tau{tau:g}"
-            if key in tj and tj[key].get("kernel_version") == kname:
+            if key in tj and tj[key].get("kernel_version") == f"{kname}:{KERNEL_REV.get(kname, '')}":
                 traffic = tj[key]["bytes_per_launch"]
         except Exception:
             traffic = None
