@@ -25,6 +25,17 @@ namespace isci {
 
 constexpr int kDotBlocks = 256;
 constexpr int kTile = 8;
+// coefficient matrices of a linear combination staged in LDS up to this
+// many basis vectors (the default subspace bound is below it)
+constexpr int kLinMaxM = 256;
+
+// vectors are device (global) memory: reading them through global-space
+// pointers keeps the loads off the flat path, whose completion the
+// compiler must also wait for before LDS reads
+typedef __attribute__((address_space(1))) const double gdouble;
+typedef __attribute__((address_space(1))) double gdouble_w;
+__device__ __forceinline__ const gdouble *gptr(const double *p) { return (const gdouble *)p; }
+__device__ __forceinline__ gdouble_w *gptr_w(double *p) { return (gdouble_w *)p; }
 
 // partial[(blk * m + i) * k + j] = sum_{t in blk's range} A_i[t] B_j[t]
 __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ A, int64_t lda, int m,
@@ -37,17 +48,23 @@ __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ A, int6
     for (int a = 0; a < kTile; ++a)
 #pragma unroll
         for (int b = 0; b < kTile; ++b) acc[a][b] = 0.0;
+    // rows past m / k are read clamped and zeroed: no load sits under a branch
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        double bv[kTile];
+        double av[kTile], bv[kTile];
 #pragma unroll
-        for (int b = 0; b < kTile; ++b) bv[b] = (j0 + b < k) ? B[(int64_t)(j0 + b) * ldb + t] : 0.0;
+        for (int b = 0; b < kTile; ++b) {
+            const double x = B[(int64_t)min(j0 + b, k - 1) * ldb + t];
+            bv[b] = j0 + b < k ? x : 0.0;
+        }
 #pragma unroll
         for (int a = 0; a < kTile; ++a) {
-            if (i0 + a >= m) break;
-            const double av = A[(int64_t)(i0 + a) * lda + t];
-#pragma unroll
-            for (int b = 0; b < kTile; ++b) acc[a][b] += av * bv[b];
+            const double x = A[(int64_t)min(i0 + a, m - 1) * lda + t];
+            av[a] = i0 + a < m ? x : 0.0;
         }
+#pragma unroll
+        for (int a = 0; a < kTile; ++a)
+#pragma unroll
+            for (int b = 0; b < kTile; ++b) acc[a][b] += av[a] * bv[b];
     }
     __shared__ double red[4][kTile * kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -259,17 +276,21 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
     for (int a = 0; a < kTile; ++a)
 #pragma unroll
         for (int b = 0; b < kTile; ++b) acc[a][b] = 0.0;
+    // rows past m / k are skipped; the conditions are uniform over the
+    // workgroup (scalar branches), so only valid rows are loaded
+    const gdouble *A = gptr(J.A), *B = gptr(J.B);
+    const int na = __builtin_amdgcn_readfirstlane(min(kTile, J.m - i0));
+    const int nb = __builtin_amdgcn_readfirstlane(min(kTile, J.k - j0));
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)J.nblk * blockDim.x) {
-        double bv[kTile];
+        double av[kTile], bv[kTile];
 #pragma unroll
-        for (int b = 0; b < kTile; ++b) bv[b] = (j0 + b < J.k) ? J.B[(int64_t)(j0 + b) * J.ldb + t] : 0.0;
+        for (int b = 0; b < kTile; ++b) bv[b] = b < nb ? B[(int64_t)(j0 + b) * J.ldb + t] : 0.0;
 #pragma unroll
-        for (int a = 0; a < kTile; ++a) {
-            if (i0 + a >= J.m) break;
-            const double av = J.A[(int64_t)(i0 + a) * J.lda + t];
+        for (int a = 0; a < kTile; ++a) av[a] = a < na ? A[(int64_t)(i0 + a) * J.lda + t] : 0.0;
 #pragma unroll
-            for (int b = 0; b < kTile; ++b) acc[a][b] += av * bv[b];
-        }
+        for (int a = 0; a < kTile; ++a)
+#pragma unroll
+            for (int b = 0; b < kTile; ++b) acc[a][b] += av[a] * bv[b];
     }
     __shared__ double red[4][kTile * kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -312,22 +333,51 @@ __global__ __launch_bounds__(256) void k_blincomb(const BLin *__restrict__ jobs)
     const BLin J = jobs[blockIdx.z];
     const int j0 = blockIdx.y * kTile;
     if (j0 >= J.k) return;
+    const int m = J.m, kb = min(kTile, J.k - j0);
+    // this block's coefficients Y[(j0 + b) m + i] in LDS as Ys[i][b] (zero
+    // for b >= kb and for the eight rows past m), read back as broadcasts
+    __shared__ double Ys[(kLinMaxM + 8) * kTile];
+    const bool staged = m <= kLinMaxM;
+    if (staged)
+        for (int e = threadIdx.x; e < (m + 8) * kTile; e += blockDim.x) {
+            const int i = e / kTile, b = e % kTile;
+            Ys[e] = (b < kb && i < m) ? J.Y[(int64_t)(j0 + b) * m + i] : 0.0;
+        }
+    __syncthreads();
+    const gdouble *V = gptr(J.V), *Y = gptr(J.Y);
+    gdouble_w *out = gptr_w(J.out);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x) {
         double acc[kTile];
 #pragma unroll
         for (int b = 0; b < kTile; ++b) acc[b] = 0.0;
-        for (int i = 0; i < J.m; ++i) {
-            const double v = J.V[(int64_t)i * J.ldv + t];
+        if (staged) {
+            // eight basis rows per step, loaded together (rows past m
+            // clamped; their coefficients are zero)
+            for (int i0 = 0; i0 < m; i0 += 8) {
+                double v[8];
 #pragma unroll
-            for (int b = 0; b < kTile; ++b)
-                if (j0 + b < J.k) acc[b] += v * J.Y[(j0 + b) * J.m + i];
+                for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)min(i0 + u, m - 1) * J.ldv + t];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int b = 0; b < kTile; ++b) acc[b] += v[u] * Ys[(i0 + u) * kTile + b];
+            }
+        } else {
+            for (int i = 0; i < m; ++i) {
+                const double v = V[(int64_t)i * J.ldv + t];
+#pragma unroll
+                for (int b = 0; b < kTile; ++b) acc[b] += v * Y[(int64_t)min(j0 + b, J.k - 1) * m + i];
+            }
         }
+        double old[kTile];
+#pragma unroll
+        for (int b = 0; b < kTile; ++b) old[b] = 0.0;
+        if (J.beta != 0.0)
+#pragma unroll
+            for (int b = 0; b < kTile; ++b) old[b] = out[(int64_t)(j0 + min(b, kb - 1)) * J.ldo + t];
 #pragma unroll
         for (int b = 0; b < kTile; ++b)
-            if (j0 + b < J.k) {
-                double *o = J.out + (int64_t)(j0 + b) * J.ldo + t;
-                *o = (J.beta == 0.0 ? 0.0 : J.beta * *o) + J.sign * acc[b];
-            }
+            if (b < kb) out[(int64_t)(j0 + b) * J.ldo + t] = J.beta * old[b] + J.sign * acc[b];
     }
 }
 
