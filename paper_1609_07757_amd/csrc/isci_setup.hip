@@ -477,52 +477,83 @@ __global__ void k_chunk_mark_1b(const double *hs, int n, const int *orb_blk, int
     }
 }
 
-__global__ void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
+// one workgroup per row block pair g: marked chunks among its n * nb keys
+__global__ __launch_bounds__(256) void k_chunk_count(const unsigned *bits, int n, int nb, int *cnt)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nb * nb) return;
-    const long long k0 = (long long)g * n * nb, k1 = k0 + (long long)n * nb;
+    const int g = blockIdx.x;
+    const long long k0 = (long long)g * n * nb;
+    const int nk = n * nb;
     int c = 0;
-    for (long long k = k0; k < k1; ++k) c += (bits[k >> 5] >> (k & 31)) & 1u;
-    cnt[g] = c;
+    for (int key = threadIdx.x; key < nk; key += blockDim.x) {
+        const long long k = k0 + key;
+        c += (bits[k >> 5] >> (k & 31)) & 1u;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    __shared__ int ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[g] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// chunks of a row block are written in order of their source level class
-// (virtual q) + (virtual S-block), so the chunks a role may use form a
-// prefix; cls[g*3 + l] counts the chunks of class l
-__global__ void k_chunk_fill(const unsigned *bits, const double *eri, const double *hs, int n, int nb, double tau,
-                             const int8_t *blk_orb, const int *off, int2 *desc, double *val, int *cls)
+// Chunks of a row block pair are written in order of their source level
+// class (virtual q) + (virtual S-block), so the chunks a role may use form
+// a prefix; cls[g*3 + l] counts the chunks of class l.  One workgroup per
+// row block pair g: for each class, block-wide scans over batches of 256
+// (q, S) keys (in q, S order) place the marked chunks, then 64-lane groups
+// fill the 64 values of each chunk placed in the batch.
+__global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, const double *eri, const double *hs, int n,
+                                                    int nb, double tau, const int8_t *blk_orb, const int *off,
+                                                    int2 *desc, double *val, int *cls)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nb * nb) return;
+    const int g = blockIdx.x;
     const int Ab = g / nb, Bb = g % nb;
     const long long k0 = (long long)g * n * nb;
+    const int nk = n * nb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ int ws[4];
+    __shared__ int sel[256];
     int w = off[g];
     for (int lc = 0; lc < 3; ++lc) {
-    int cnt = 0;
-    for (int q = 0; q < n; ++q)
-        for (int S = 0; S < nb; ++S) {
-            if ((q >= 2) + (S != 0) != lc) continue;
-            const long long k = k0 + (long long)q * nb + S;
-            if (!((bits[k >> 5] >> (k & 31)) & 1u)) continue;
-            ++cnt;
-            desc[w] = make_int2(q, S);
-            for (int l = 0; l < 64; ++l) {
-                const int i = l & 15, kk = l >> 4;
-                const int p = blk_orb[Ab * 4 + (i >> 2)], r = blk_orb[Bb * 4 + (i & 3)], s = blk_orb[S * 4 + kk];
+        int cnt = 0;
+        for (int base = 0; base < nk; base += 256) {
+            const int key = base + (int)threadIdx.x;
+            const int q = key / nb, S = key % nb;
+            bool f = false;
+            if (key < nk) {
+                const long long k = k0 + key;
+                f = ((bits[k >> 5] >> (k & 31)) & 1u) && (q >= 2) + (S != 0) == lc;
+            }
+            const unsigned long long bal = __ballot(f);
+            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) ws[wv] = __popcll(bal);
+            __syncthreads();
+            int woff = 0;
+            for (int i = 0; i < wv; ++i) woff += ws[i];
+            const int tot = ws[0] + ws[1] + ws[2] + ws[3];
+            if (f) {
+                sel[woff + pre] = key;
+                desc[w + woff + pre] = make_int2(q, S);
+            }
+            __syncthreads();
+            for (int c = wv; c < tot; c += 4) {
+                const int kq = sel[c] / nb, kS = sel[c] % nb;
+                const int i = lane & 15, kk = lane >> 4;
+                const int p = blk_orb[Ab * 4 + (i >> 2)], r = blk_orb[Bb * 4 + (i & 3)], s = blk_orb[kS * 4 + kk];
                 double v = 0.0;
                 if (p >= 0 && r >= 0 && s >= 0) {
-                    v = geri(eri, n, p, q, r, s);
+                    v = geri(eri, n, p, kq, r, s);
                     if (!(fabs(v) > tau)) v = 0.0;
                     // one-body units in alpha-beta form (hs holds the kept h)
-                    if (hs && r == s) v += 0.5 * hs[p * n + q];
-                    if (hs && p == q) v += 0.5 * hs[r * n + s];
+                    if (hs && r == s) v += 0.5 * hs[p * n + kq];
+                    if (hs && p == kq) v += 0.5 * hs[r * n + s];
                 }
-                val[(size_t)w * 64 + l] = v;
+                val[(size_t)(w + c) * 64 + lane] = v;
             }
-            ++w;
+            w += tot;
+            cnt += tot;
+            __syncthreads();   // ws and sel are reused by the next batch
         }
-    cls[g * 3 + lc] = cnt;
+        if (threadIdx.x == 0) cls[g * 3 + lc] = cnt;
     }
 }
 
@@ -577,7 +608,7 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     // chunk count of a mark set (offsets left in chunk_off)
     auto count_chunks = [&](const unsigned *b, int *tot) -> isci_status {
         ISCI_HIP(hipMemsetAsync(d.chunk_off, 0, sizeof(int) * (nb * nb + 1), s));
-        k_chunk_count<<<(nb * nb + 63) / 64, 64, 0, s>>>(b, n, nb, d.chunk_off);
+        k_chunk_count<<<nb * nb, 256, 0, s>>>(b, n, nb, d.chunk_off);
         ISCI_HIP(hipGetLastError());
         isci_status st = scan_inplace<int>(d.chunk_off, nb * nb + 1, s);
         if (st != ISCI_OK) return st;
@@ -616,8 +647,8 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * (size_t)std::max(1, tot));
     d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
     if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
-    k_chunk_fill<<<(nb * nb + 63) / 64, 64, 0, s>>>(bits, eri, merged ? d.hscreen : nullptr, n, nb, c->tau,
-                                                     d.blk_orb, d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
+    k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, eri, merged ? d.hscreen : nullptr, n, nb, c->tau, d.blk_orb,
+                                          d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
     ISCI_HIP(hipFreeAsync(bits, s));
     ISCI_HIP(hipStreamSynchronize(s));
