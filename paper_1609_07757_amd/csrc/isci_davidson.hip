@@ -263,11 +263,13 @@ struct BDot {              // out[i*k + j] = sum_t A[i*lda + t] B[j*ldb + t]
     double *out, *partial;
     int64_t lda, ldb, n;
     int m, k, nblk;
+    const double *skip = nullptr;   // device flag: nonzero skips the job
 };
 
 __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, int tiles_j)
 {
     const BDot J = jobs[blockIdx.z];
+    if (J.skip && *J.skip != 0.0) return;
     const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
     const int i0 = ti * kTile, j0 = tj * kTile;
     if ((int)blockIdx.x >= J.nblk || i0 >= J.m || j0 >= J.k) return;
@@ -313,6 +315,7 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
 __global__ __launch_bounds__(256) void k_bdots_reduce(const BDot *__restrict__ jobs)
 {
     const BDot J = jobs[blockIdx.z];
+    if (J.skip && *J.skip != 0.0) return;
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int mk = J.m * J.k;
     if (e >= mk) return;
@@ -326,13 +329,34 @@ struct BLin {              // out_j[t] = beta out_j[t] + sign * sum_i V_i[t] Y[j
     int64_t ldv, ldo, n;
     int m, k;
     double beta, sign;
+    const double *skip = nullptr;   // device flag: nonzero skips the job
 };
+
+// Daniel-Gragg-Kaufman-Stewart test after the first projection of a block
+// against the basis: when every column kept at least half of its squared
+// norm (gm[q][q] >= g0[q][q] / 2), one projection already leaves it
+// orthogonal to working precision and the second is skipped.
+struct BFlag {
+    const double *g0, *gm;
+    double *flag;
+    int p;
+};
+
+__global__ void k_dgks_flag(const BFlag *__restrict__ jobs, int njobs)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    const BFlag J = jobs[j];
+    bool ok = true;
+    for (int q = 0; q < J.p; ++q) ok = ok && J.gm[q * J.p + q] >= 0.5 * J.g0[q * J.p + q];
+    *J.flag = ok ? 1.0 : 0.0;
+}
 
 __global__ __launch_bounds__(256) void k_blincomb(const BLin *__restrict__ jobs)
 {
     const BLin J = jobs[blockIdx.z];
     const int j0 = blockIdx.y * kTile;
-    if (j0 >= J.k) return;
+    if (j0 >= J.k || (J.skip && *J.skip != 0.0)) return;
     const int m = J.m, kb = min(kTile, J.k - j0);
     // this block's coefficients Y[(j0 + b) m + i] in LDS as Ys[i][b] (zero
     // for b >= kb and for the eight rows past m), read back as broadcasts
@@ -1086,7 +1110,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
     if (grow_set.empty()) return ISCI_OK;
     const size_t ng = grow_set.size();
     std::vector<int> m0(ng), np(ng);
-    std::vector<size_t> offG0(ng), offG1(ng), offG2(ng);
+    std::vector<size_t> offG0(ng), offG1(ng), offG2(ng), offGm(ng), offF(ng);
     size_t rs = rC;
     for (size_t j = 0; j < ng; ++j) {
         Slot *sl = grow_set[j];
@@ -1096,13 +1120,18 @@ static isci_status engine_step(isci_engine e, int *nactive)
         offG0[j] = rs; rs += p2;
         offG1[j] = rs; rs += p2;
         offG2[j] = rs; rs += p2;
+        offGm[j] = rs; rs += p2;
+        offF[j] = rs; rs += 1;
     }
     if (!res_reserve(e, rs + 64)) { set_error("allocation failed (engine results)"); return ISCI_E_OOM; }
-    // D1: copy, pre-norm Gram, two projections, Gram of the projected block
+    // D1: copy, pre-norm Gram, first projection, its Gram and the DGKS
+    // flag, second projection (skipped on the device when the flag says
+    // so), Gram of the projected block
     {
         std::vector<BVecOp> cp;
-        std::vector<BDot> g0, c1, c2, g1;
+        std::vector<BDot> g0, c1, c2, g1, gm;
         std::vector<BLin> l1, l2;
+        std::vector<BFlag> fl;
         for (size_t j = 0; j < ng; ++j) {
             Slot *sl = grow_set[j];
             const int p = np[j], m = m0[j];
@@ -1119,21 +1148,27 @@ static isci_status engine_step(isci_engine e, int *nactive)
             d.out = e->res_d + offG1[j];
             g1.push_back(d);
             if (m > 0) {
+                const double *flag = e->res_d + offF[j];
+                d.out = e->res_d + offGm[j];
+                gm.push_back(d);
+                fl.push_back(BFlag{e->res_d + offG0[j], e->res_d + offGm[j], e->res_d + offF[j], p});
                 d.A = X; d.B = sl->V; d.m = p; d.k = m; d.out = sl->small;   // Y[q * m + i] = X_q . V_i
                 c1.push_back(d);
+                d.skip = flag;
                 c2.push_back(d);
                 l1.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0});
-                l2.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0});
+                l2.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0, flag});
             }
         }
         ArenaPack ap{e};
         const size_t ocp = ap.push(cp), og0 = ap.push(g0), oc1 = ap.push(c1), oc2 = ap.push(c2), og1 = ap.push(g1),
-                     ol1 = ap.push(l1), ol2 = ap.push(l2);
+                     ol1 = ap.push(l1), ol2 = ap.push(l2), ogm = ap.push(gm), ofl = ap.push(fl);
         if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
         BVecOp *dcp = arena_put(e, ocp, cp);
         BDot *dg0 = arena_put(e, og0, g0), *dc1 = arena_put(e, oc1, c1), *dc2 = arena_put(e, oc2, c2),
-             *dg1 = arena_put(e, og1, g1);
+             *dg1 = arena_put(e, og1, g1), *dgm = arena_put(e, ogm, gm);
         BLin *dl1 = arena_put(e, ol1, l1), *dl2 = arena_put(e, ol2, l2);
+        BFlag *dfl = arena_put(e, ofl, fl);
         ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
         if (!cp.empty()) {
             const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(cp) + 255) / 256);
@@ -1143,6 +1178,11 @@ static isci_status engine_step(isci_engine e, int *nactive)
         if ((st = launch_bdots(dg0, g0, s)) != ISCI_OK) return st;
         if ((st = launch_bdots(dc1, c1, s)) != ISCI_OK) return st;
         if ((st = launch_blincomb(dl1, l1, s)) != ISCI_OK) return st;
+        if ((st = launch_bdots(dgm, gm, s)) != ISCI_OK) return st;
+        if (!fl.empty()) {
+            k_dgks_flag<<<(unsigned)((fl.size() + 63) / 64), 64, 0, s>>>(dfl, (int)fl.size());
+            ISCI_HIP(hipGetLastError());
+        }
         if ((st = launch_bdots(dc2, c2, s)) != ISCI_OK) return st;
         if ((st = launch_blincomb(dl2, l2, s)) != ISCI_OK) return st;
         if ((st = launch_bdots(dg1, g1, s)) != ISCI_OK) return st;
