@@ -275,7 +275,7 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
                                    (when the product path's operands would exceed 2 GiB) */
 #define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
 #define ISCI_KERNEL_ONEBODY 4   /* one-body classes, two electrons per spin (matrix-core products, or
-                                   k_onebody_a + k_onebody_b above 80 orbitals) */
+                                   k_ob_alpha_spec + k_onebody_b above 80 orbitals) */
 #define ISCI_KERNEL_AB_UNFOLD 5 /* k_ab_unfold: alpha-beta class, CI block unfolded into the product operand */
 #define ISCI_KERNEL_AB_GEMM 6   /* k_ab_gemm: alpha-beta class, block-sparse product on matrix cores */
 #define ISCI_KERNEL_AB_FOLD 7   /* k_ab_fold: alpha-beta class, role readings summed into sigma */

@@ -80,7 +80,7 @@ struct DevTabs {
     // blocks of 4 (occupied block padded with -1); per ordered row-block pair
     // (A,B) a CSR list of column chunks (q, S-block) with their 16x4 values
     // (pq|rs), p in A, r in B, s in S, laid out in MFMA operand-A lane order
-    int8_t *blk_orb = nullptr;      // [nblk][4]
+    int16_t *blk_orb = nullptr;     // [nblk][4] orbital of each block slot, -1: padding
     int *chunk_off = nullptr;       // [nblk*nblk + 1]
     int2 *chunk_desc = nullptr;     // (q, S)
     double *chunk_val = nullptr;    // [nchunk][64]
@@ -128,7 +128,7 @@ struct SigmaArgs {
     int classes;             // bit 0 one-body, bit 1 same-spin, bit 2 alpha-beta (pair kernel)
     int accumulate;          // pair kernel adds into sigma instead of overwriting
     int nblk;
-    const int8_t *blk_orb;
+    const int16_t *blk_orb;
     const int *chunk_off;
     const int2 *chunk_desc;
     const double *chunk_val;
@@ -239,6 +239,10 @@ bool onebody_mfma_ok(const isci_ctx *c);
 // of adding, and the alpha classes add
 isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,
                                 hipStream_t s, bool first = false);
+// alpha one-body class on matrix cores above kObMaxNorb (spectator form, up
+// to 256 orbitals; adds into sigma)
+isci_status launch_onebody_alpha_large(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv,
+                                       int64_t lds, hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

@@ -546,6 +546,189 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
     return ISCI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Alpha class above 80 orbitals, where the pair blocks of the kernels above
+// no longer fit LDS: spectator x = blockIdx.x, beta columns blockIdx.y * 64
+// + [0, 64) (four 16-column N tiles), vector blockIdx.z; wave w forms the
+// targets a in [16 w, 16 w + 16) with a > x (up = 1) or a < x (up = 0),
+//   U[a][x][j] = sum_q h_aq T_j[q][x],
+// with the B operand read straight from the rows {q, x} (coalesced).  One
+// side of x per launch, so each sigma row is written by one workgroup per
+// launch.  Columns run to jlim(x): for x virtual the rows {q, x} with q
+// virtual stop at the level-2 row length; the columns above reach only
+// {0,x} and {1,x} (k_ob_alpha_tail).  K steps without a row holding the
+// column block are skipped (64-bit step mask, up to 256 orbitals); the
+// operands of the next K step are in flight while the MFMAs of the current
+// one issue.
+template <int NT>
+__global__ __launch_bounds__(64 * NT) void k_ob_alpha_spec(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                           double *__restrict__ sg, int64_t lds,
+                                                           const double *__restrict__ hs, int up, int jlim_occ,
+                                                           int jlim_virt)
+{
+    constexpr int NP = 16 * NT;
+    const int x = blockIdx.x, v = blockIdx.z;
+    const int norb = A.norb;
+    const int jlim = x < 2 ? jlim_occ : jlim_virt;
+    const int j0 = blockIdx.y * 64;
+    if (j0 >= jlim) return;
+    // row starts and lengths of {o, x} in LDS: the operand loads below then
+    // depend on no other global load
+    __shared__ long long rb[NP];
+    __shared__ int rl[NP];
+    for (int t = threadIdx.x; t < NP; t += 64 * NT) {
+        rb[t] = t < norb ? A.arow_base[x * norb + t] : -1;
+        rl[t] = t < norb ? A.arow_len[x * norb + t] : 0;
+    }
+    __syncthreads();
+    const int mt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    // this wave's targets {a, x} on the requested side of x that hold a
+    // column of the block, and the K steps whose sources {q, x} hold one
+    const int at = 16 * mt + (lane & 15);
+    const bool tok = lane < 16 && at < norb && at != x && ((at > x) == (up != 0)) && rl[at] > j0;
+    if (__ballot(tok) == 0) return;
+    unsigned long long km = 0;
+#pragma unroll
+    for (int r = 0; r < (NP + 63) / 64; ++r) {
+        const int q = lane + 64 * r;
+        const bool sq = q < NP && q < norb && q != x && rl[q] > j0;
+        const unsigned long long sm = __ballot(sq);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+            if (16 * r + kk < NP / 4 && ((sm >> (4 * kk)) & 0xfull)) km |= 1ull << (16 * r + kk);
+    }
+    const int n = lane & 15, kq = lane >> 4;
+    const double *cv = c + (int64_t)v * ldc;
+    auto next_ks = [&]() {
+        if (!km) return -1;
+        const int k = __ffsll((long long)km) - 1;
+        km &= km - 1;
+        return k;
+    };
+    // every lane loads from a valid address whatever the step (invalid
+    // operands are selected to zero afterwards)
+    auto load = [&](int ks, double &a, double *b) {
+        const int q = 4 * max(ks, 0) + kq;
+        const int qc = min(q, norb - 1), ac = min(16 * mt + n, norb - 1);
+        const double hv = hs[qc * norb + ac];
+        a = (ks >= 0 && q < norb && 16 * mt + n < norb) ? hv : 0.0;
+        const long long base = rb[qc];
+        const int len = min(rl[qc], jlim);
+        const bool rowok = ks >= 0 && q < norb && q != x && base >= 0;
+        const double f = q < x ? 1.0 : -1.0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int j = j0 + 16 * nt + n;
+            const bool ok = rowok && j < len;
+            const double val = cv[ok ? base + j : 0];
+            b[nt] = ok ? f * val : 0.0;
+        }
+    };
+    v4d_ob acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
+    // two K steps in flight: stages x and y ping-pong (no register copies)
+    double ax, bx[4], ay, by[4];
+    int kx = next_ks();
+    load(kx, ax, bx);
+    while (kx >= 0) {
+        const int ky = next_ks();
+        load(ky, ay, by);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ax, bx[nt], acc[nt]);
+        if (ky < 0) break;
+        kx = next_ks();
+        load(kx, ax, bx);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ay, by[nt], acc[nt]);
+    }
+    double *sv = sg + (int64_t)v * lds;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int a = 16 * mt + 4 * g + kq;
+        if (a >= norb || a == x || ((a > x) != (up != 0))) continue;
+        const long long base = rb[a];
+        if (base < 0) continue;
+        const int len = min(rl[a], jlim);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int j = j0 + 16 * nt + n;
+            if (j < len) sv[base + j] += a < x ? acc[nt][g] : -acc[nt][g];
+        }
+    }
+}
+
+// Alpha class, the columns j in [j0, j1) of a virtual spectator x that only
+// the rows {0, x} and {1, x} hold:
+//   sigma({o, x}, j) += h_o0 c({0, x}, j) + h_o1 c({1, x}, j),  o = 0, 1.
+__global__ __launch_bounds__(256) void k_ob_alpha_tail(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                       double *__restrict__ sg, int64_t lds,
+                                                       const double *__restrict__ hs, int j0, int j1)
+{
+    const int x = 2 + blockIdx.x, v = blockIdx.z;
+    const int j = j0 + blockIdx.y * 256 + threadIdx.x;
+    const int norb = A.norb;
+    const long long b0 = A.arow_base[x * norb + 0], b1 = A.arow_base[x * norb + 1];
+    const int l0 = A.arow_len[x * norb + 0], l1 = A.arow_len[x * norb + 1];
+    if (j >= j1 || b0 < 0 || b1 < 0) return;
+    const double *cv = c + (int64_t)v * ldc;
+    double *sv = sg + (int64_t)v * lds;
+    const double c0 = j < l0 ? cv[b0 + j] : 0.0, c1 = j < l1 ? cv[b1 + j] : 0.0;
+    if (j < l0) sv[b0 + j] += hs[0] * c0 + hs[1] * c1;
+    if (j < l1) sv[b1 + j] += hs[norb] * c0 + hs[norb + 1] * c1;
+}
+
+template <int NT>
+static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
+                                 double *s, int64_t lds, hipStream_t st)
+{
+    const double *hs = cx->d.hscreen;
+    const int L = cx->L;
+    // rows {q, x} hold beta strings up to level L - level({q, x}); for x
+    // occupied every column reaches some row of level <= 1, for x virtual
+    // the columns above the level-2 row length only reach {0,x}, {1,x}
+    const int *le_b = cx->sb.le;
+    const int jlim_occ = le_b[L];
+    const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
+    const int jtail = L >= 1 ? le_b[L - 1] : 0;
+    const dim3 ga((unsigned)cx->norb, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
+    for (int up = 1; up >= 0; --up)
+        k_ob_alpha_spec<NT><<<ga, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt);
+    if (jtail > jlim_virt && cx->norb > 2)
+        k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
+                          0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);
+}
+
+isci_status launch_onebody_alpha_large(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
+                                       int64_t lds, hipStream_t st)
+{
+    if (!(cx->d.hscreen && cx->na == 2 && cx->nb == 2 && cx->d.arow_base && cx->d.arow_len) || cx->norb > 256) {
+        set_error("alpha one-body spectator path: needs two electrons per spin and at most 256 orbitals");
+        return ISCI_E_UNSUPPORTED;
+    }
+    const SigmaArgs A = sigma_args(cx);
+    const int nt = std::max(6, (cx->norb + 15) / 16);
+#define ISCI_OBS_CASE(N)                                         \
+    case N: launch_ob_alpha_spec<N>(cx, A, nv, c, ldc, s, lds, st); break;
+    switch (nt) {
+        ISCI_OBS_CASE(6)
+        ISCI_OBS_CASE(7)
+        ISCI_OBS_CASE(8)
+        ISCI_OBS_CASE(9)
+        ISCI_OBS_CASE(10)
+        ISCI_OBS_CASE(11)
+        ISCI_OBS_CASE(12)
+        ISCI_OBS_CASE(13)
+        ISCI_OBS_CASE(14)
+        ISCI_OBS_CASE(15)
+        ISCI_OBS_CASE(16)
+    default: set_error("alpha one-body spectator path: norb too large"); return ISCI_E_UNSUPPORTED;
+    }
+#undef ISCI_OBS_CASE
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
 bool onebody_mfma_ok(const isci_ctx *cx)
 {
     return cx->d.hscreen && cx->na == 2 && cx->nb == 2 && cx->norb >= 3 && cx->norb <= kObMaxNorb &&

@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_chunk_count(const unsigned *bits, int n
 // (q, S) keys (in q, S order) place the marked chunks, then 64-lane groups
 // fill the 64 values of each chunk placed in the batch.
 __global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, const double *eri, const double *hs, int n,
-                                                    int nb, double tau, const int8_t *blk_orb, const int *off,
+                                                    int nb, double tau, const int16_t *blk_orb, const int *off,
                                                     int2 *desc, double *val, int *cls)
 {
     const int g = blockIdx.x;
@@ -566,10 +566,11 @@ static constexpr int64_t kObTilesMaxDim = 65536;
 static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
 {
     const int n = c->norb;
-    std::vector<int8_t> bo;
-    bo.insert(bo.end(), {0, (int8_t)(n > 1 ? 1 : -1), -1, -1});
+    // orbitals of each block slot, -1 for padding (16 bits: up to 255 orbitals)
+    std::vector<int16_t> bo;
+    bo.insert(bo.end(), {0, (int16_t)(n > 1 ? 1 : -1), -1, -1});
     for (int v = 2; v < n; v += 4)
-        for (int k = 0; k < 4; ++k) bo.push_back((int8_t)(v + k < n ? v + k : -1));
+        for (int k = 0; k < 4; ++k) bo.push_back((int16_t)(v + k < n ? v + k : -1));
     const int nb = (int)bo.size() / 4;
     std::vector<int> ob(n, 0);
     for (int b = 0; b < nb; ++b)
@@ -587,7 +588,7 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     c->nblk = nb;
     c->nquad = (int)quads.size();
     DevTabs &d = c->d;
-    d.blk_orb = (int8_t *)dev_alloc(c, bo.size());
+    d.blk_orb = (int16_t *)dev_alloc(c, sizeof(int16_t) * bo.size());
     d.quads = (uchar4 *)dev_alloc(c, sizeof(uchar4) * std::max<size_t>(1, quads.size()));
     int *dob = (int *)dev_alloc(c, sizeof(int) * n);
     const long long nkeys = (long long)nb * nb * n * nb;
@@ -595,7 +596,7 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     ISCI_HIP(hipMallocAsync((void **)&bits, sizeof(unsigned) * (size_t)((nkeys + 31) / 32 + 1), s));
     d.chunk_off = (int *)dev_alloc(c, sizeof(int) * (nb * nb + 1));
     if (!d.blk_orb || !d.quads || !dob || !d.chunk_off) { set_error("device allocation failed (tiles)"); return ISCI_E_OOM; }
-    ISCI_HIP(hipMemcpyAsync(d.blk_orb, bo.data(), bo.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.blk_orb, bo.data(), sizeof(int16_t) * bo.size(), hipMemcpyHostToDevice, s));
     if (!quads.empty())
         ISCI_HIP(hipMemcpyAsync(d.quads, quads.data(), sizeof(uchar4) * quads.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(dob, ob.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));

@@ -507,104 +507,9 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
 }
 
 // ---------------------------------------------------------------------------
-// One-body classes for two electrons per spin (add into sigma).
+// One-body beta class for two electrons per spin above 80 orbitals (adds
+// into sigma; the alpha class is launch_onebody_alpha_large).
 //
-// Alpha: for a spectator x the target rows {x, a} receive
-//   sum_q h_aq sgn(a - x) sgn(q - x) c({x, q}, J)
-// for every beta index J both rows hold.  A workgroup takes one x, a block
-// of 8 target orbitals a and 256 consecutive J; each thread keeps 8 x NV
-// accumulators, so every source element loaded feeds 8 targets.  The
-// spectator role is split over two launches (x < a, then x > a) so that
-// each sigma row is updated by one workgroup per launch.
-template <int NV>
-__global__ __launch_bounds__(256) void k_onebody_a(SigmaArgs A, int nv, const double *__restrict__ c,
-                                                   int64_t ldc, double *__restrict__ sg, int64_t lds,
-                                                   const double *__restrict__ hs, int upper)
-{
-    const int norb = A.norb;
-    const int x = blockIdx.x;
-    const int a0 = blockIdx.y * 8;
-    const int j0 = blockIdx.z * 256;
-    const int J = j0 + threadIdx.x;
-    // target rows {x, a}
-    int ta[8], tlen[8];
-    long long trow[8];
-    int maxlen = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int a = a0 + i;
-        ta[i] = -1;
-        tlen[i] = 0;
-        trow[i] = 0;
-        if (a < norb && a != x && ((a > x) == (upper != 0))) {
-            const long long base = A.arow_base[x * norb + a];
-            if (base >= 0) {
-                ta[i] = a;
-                tlen[i] = A.arow_len[x * norb + a];
-                trow[i] = base;
-                maxlen = max(maxlen, tlen[i]);
-            }
-        }
-    }
-    if (j0 >= maxlen) return;
-    double acc[8][NV];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
-    const long long *__restrict__ rbase = A.arow_base + x * norb;
-    const int *__restrict__ rlen = A.arow_len + x * norb;
-    // source rows {x, q}: two at a time so their loads overlap
-    for (int q0 = 0; q0 < norb; q0 += 2) {
-        double cv[2][NV], hq[2][8];
-        bool use[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int q = q0 + u;
-            use[u] = false;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) cv[u][v] = 0.0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) hq[u][i] = 0.0;
-            if (q >= norb || q == x) continue;
-            const long long base = rbase[q];
-            const int slen = rlen[q];
-            if (base < 0 || j0 >= slen) continue;
-            bool any = false;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                hq[u][i] = ta[i] >= 0 ? hs[ta[i] * norb + q] : 0.0;
-                any |= hq[u][i] != 0.0;
-            }
-            if (!any) continue;
-            use[u] = true;
-            if (J < slen) {
-                const double sq = (q > x) ? 1.0 : -1.0;
-                const double *src = c + base + J;
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (v < nv) cv[u][v] = sq * src[v * ldc];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (use[u])
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[i][v] += hq[u][i] * cv[u][v];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        if (ta[i] < 0 || J >= tlen[i]) continue;
-        const double sa = (ta[i] > x) ? 1.0 : -1.0;
-        double *dst = sg + trow[i] + J;
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < nv) dst[v * lds] += sa * acc[i][v];
-    }
-}
-
 // Beta: within the alpha row I,
 //   sigma(I, {y<b}) += sum_s h_bs sgn(s - y) c(I, {y, s}) - sum_s h_ys sgn(s - b) c(I, {b, s}).
 // A workgroup stages row I (NV vectors) in LDS; one thread per target.
@@ -775,20 +680,18 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                     }
                 }
                 if (c->d.hscreen && !c->onebody_in_tiles) {
-                    // one-body classes (matrix cores when the orbital count allows,
-                    // else alpha in two launches by spectator side, then beta),
-                    // then same-spin if any; with dense integrals the tiles carry
-                    // the one-body units instead
+                    // one-body classes (matrix cores; above 80 orbitals alpha in
+                    // the spectator form, two launches by spectator side, and
+                    // beta on the pair-table kernel), then same-spin if any;
+                    // with dense integrals the tiles carry the one-body units
+                    // instead
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
                     if (onebody_mfma_ok(c)) {
                         ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
                     } else {
-                        const dim3 ga((unsigned)c->norb, (unsigned)((c->norb + 7) / 8), (unsigned)((c->max_rowlen + 255) / 256));
+                        ISCI_CHECK(launch_onebody_alpha_large(c, nv, cc, ldc, ss, lds, s));
                         for (int u0 = 0; u0 < nv; u0 += 4) {
                             const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                            for (int up = 1; up >= 0; --up)
-                                k_onebody_a<4><<<ga, 256, 0, s>>>(A, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                   ss + (int64_t)u0 * lds, lds, c->d.hscreen, up);
                             size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
                             if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
                             if (shm <= 65536)

@@ -183,6 +183,22 @@ def test_sigma_workloads(wl, nsamp, nvec, variant):
         assert np.abs(got[:, tg] - ref).max() <= TOL * scale
 
 
+@pytest.mark.parametrize("variant", [5, 3])
+def test_sigma_large_orbitals_sampled(variant):
+    """130 orbitals (above the LDS pair-block limit of the one-body kernels:
+    the alpha class runs in spectator form over three 64-row masks), CISD,
+    sampled targets (row ends included) against the oracle."""
+    norb, L, tau = 130, 2, 1e-12
+    h, eri = recipe_a(norb, seed=4)
+    hd = create(h, eri, norb, 2, 2, L, tau, variant)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, 2, seed=17)
+    got = gpu_sigma(hd, c)
+    tg = sample_targets(S.rowstart(), S.dim, 400, seed=9)
+    ref = O.sigma(S, h, eri, tau, c, targets=tg)
+    assert np.abs(got[:, tg] - ref).max() <= TOL * np.abs(got).max()
+
+
 @pytest.mark.parametrize("k,tau", [(0, 0.0), (1, 1e-14), (2, 1e-10)])
 def test_sigma_tau_sweep_cisdt_n30(k, tau):
     from isci_inputs import workload
