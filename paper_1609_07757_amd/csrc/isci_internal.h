@@ -109,6 +109,8 @@ struct DevTabs {
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
+    double *obT_c = nullptr;        // [4][dim] transposed CI block (beta one-body above kObMaxNorb)
+    double *obT_s = nullptr;        // [4][dim] its alpha-class image
 };
 
 struct SigmaArgs {
@@ -243,6 +245,10 @@ isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int
 // to 256 orbitals; adds into sigma)
 isci_status launch_onebody_alpha_large(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv,
                                        int64_t lds, hipStream_t s);
+// beta one-body class above kObMaxNorb: the alpha class of the transposed
+// block (nv <= 4; adds into sigma)
+isci_status launch_onebody_beta_large(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv,
+                                      int64_t lds, hipStream_t s);
 isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs_dev, int njobs, int nitems,
                                  int nvmax, int grid, hipStream_t s);
 

@@ -729,6 +729,62 @@ isci_status launch_onebody_alpha_large(const isci_ctx *cx, int nv, const double 
     return ISCI_OK;
 }
 
+// With two electrons of each spin the alpha and beta string sets, their
+// order and the row layout coincide, so the beta class of c is the alpha
+// class of its transpose c^T[j][i] = c[i][j] (row = beta string, column =
+// alpha string), with the same row tables.  One thread per determinant:
+//   add = 0: dst[row j][col i] = src[row i][col j]   (coalesced reads)
+//   add = 1: dst[row i][col j] += src[row j][col i]  (coalesced updates)
+__global__ __launch_bounds__(256) void k_det_transpose(SigmaArgs A, int nv, const double *__restrict__ src,
+                                                       int64_t lsrc, double *__restrict__ dst, int64_t ldst,
+                                                       int add)
+{
+    const int ia = blockIdx.x;
+    const int jb = blockIdx.y * 256 + threadIdx.x;
+    const int len = A.sb.le[A.L - A.alev[ia]];
+    if (jb >= len) return;
+    const int64_t here = A.rowstart[ia] + jb, there = A.rowstart[jb] + ia;
+    double val[4];
+    if (add) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) val[v] = src[(int64_t)min(v, nv - 1) * lsrc + there];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (v < nv) dst[(int64_t)v * ldst + here] += val[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) val[v] = src[(int64_t)min(v, nv - 1) * lsrc + here];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (v < nv) dst[(int64_t)v * ldst + there] = val[v];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ p, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0.0;
+}
+
+isci_status launch_onebody_beta_large(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
+                                      int64_t lds, hipStream_t st)
+{
+    if (!cx->d.obT_c || !cx->d.obT_s || nv > 4 || cx->sa.nstr != cx->sb.nstr) {
+        set_error("beta one-body transposed path: scratch missing or more than 4 vectors");
+        return ISCI_E_UNSUPPORTED;
+    }
+    const SigmaArgs A = sigma_args(cx);
+    const int64_t dim = cx->dim;
+    const dim3 grid((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256));
+    k_det_transpose<<<grid, 256, 0, st>>>(A, nv, c, ldc, cx->d.obT_c, dim, 0);
+    k_fill_zero<<<(unsigned)std::min<int64_t>(4096, (dim * nv + 255) / 256), 256, 0, st>>>(cx->d.obT_s, dim * nv);
+    ISCI_HIP(hipGetLastError());
+    ISCI_CHECK(launch_onebody_alpha_large(cx, nv, cx->d.obT_c, dim, cx->d.obT_s, dim, st));
+    k_det_transpose<<<grid, 256, 0, st>>>(A, nv, cx->d.obT_s, dim, s, lds, 1);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
 bool onebody_mfma_ok(const isci_ctx *cx)
 {
     return cx->d.hscreen && cx->na == 2 && cx->nb == 2 && cx->norb >= 3 && cx->norb <= kObMaxNorb &&

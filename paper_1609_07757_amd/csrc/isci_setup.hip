@@ -1121,6 +1121,13 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         st = build_hscreen(c, h, stream);
         if (st == ISCI_OK) st = build_tiles(c, eri, stream);
         if (st == ISCI_OK) st = build_abx(c, stream);
+        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && norb > kObMaxNorb) {
+            // beta one-body above kObMaxNorb runs as the alpha class of the
+            // transposed block: scratch for four vectors and their image
+            c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
+            c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
+            if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
+        }
         if (st == ISCI_OK && c->have_abx && !c->onebody_in_tiles && onebody_mfma_ok(c)) {
             // side stream (default priority) for the one-body classes and a
             // second S buffer, so both 4-vector products run before the

@@ -692,6 +692,11 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                         ISCI_CHECK(launch_onebody_alpha_large(c, nv, cc, ldc, ss, lds, s));
                         for (int u0 = 0; u0 < nv; u0 += 4) {
                             const int nu = nv - u0 < 4 ? nv - u0 : 4;
+                            if (c->d.obT_c) {
+                                ISCI_CHECK(launch_onebody_beta_large(c, nu, cc + (int64_t)u0 * ldc, ldc,
+                                                                     ss + (int64_t)u0 * lds, lds, s));
+                                continue;
+                            }
                             size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
                             if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
                             if (shm <= 65536)
