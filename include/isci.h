@@ -135,7 +135,8 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
  * kernels; TILES puts them in the tiles; AUTO puts them in the tiles when
  * that adds at most one tile in eight or the space has at most 65536
  * determinants (there the extra launches cost more than the extra tiles).
- * The sigma vector is the same either way (up to rounding order). */
+ * Below three orbitals the tiles always carry them.  The sigma vector is
+ * the same either way (up to rounding order). */
 #define ISCI_OB_AUTO 0
 #define ISCI_OB_SEPARATE 1
 #define ISCI_OB_TILES 2
@@ -275,7 +276,7 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
                                    (when the product path's operands would exceed 2 GiB) */
 #define ISCI_KERNEL_PAIR_REST 3 /* k_sigma_n2 restricted to the classes the MFMA path leaves */
 #define ISCI_KERNEL_ONEBODY 4   /* one-body classes, two electrons per spin (matrix-core products, or
-                                   k_ob_alpha_spec + k_onebody_b above 80 orbitals) */
+                                   k_ob_alpha_spec, also on the transposed block for beta, above 80 orbitals) */
 #define ISCI_KERNEL_AB_UNFOLD 5 /* k_ab_unfold: alpha-beta class, CI block unfolded into the product operand */
 #define ISCI_KERNEL_AB_GEMM 6   /* k_ab_gemm: alpha-beta class, block-sparse product on matrix cores */
 #define ISCI_KERNEL_AB_FOLD 7   /* k_ab_fold: alpha-beta class, role readings summed into sigma */

@@ -625,7 +625,9 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     // are mostly there already) or the space is small (launch latency
     // outweighs the extra tiles); else they keep their own kernels
     bool merged = false;
-    if (d.hscreen && c->ob_place != ISCI_OB_SEPARATE) {
+    // below three orbitals (no virtual orbital) the one-body kernels do not
+    // apply: the tiles always carry the units there
+    if (d.hscreen && (c->ob_place != ISCI_OB_SEPARATE || n < 3)) {
         unsigned *bits1 = nullptr;
         ISCI_HIP(hipMallocAsync((void **)&bits1, nbits, s));
         ISCI_HIP(hipMemcpyAsync(bits1, bits, nbits, hipMemcpyDeviceToDevice, s));
@@ -634,7 +636,8 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
         int tot1 = 0;
         st = count_chunks(bits1, &tot1);
         if (st != ISCI_OK) return st;
-        if (c->ob_place == ISCI_OB_TILES || (long long)tot1 * 8 <= (long long)tot * 9 || c->dim <= kObTilesMaxDim) {
+        if (c->ob_place == ISCI_OB_TILES || n < 3 || (long long)tot1 * 8 <= (long long)tot * 9 ||
+            c->dim <= kObTilesMaxDim) {
             merged = true;
             std::swap(bits, bits1);
             tot = tot1;

@@ -506,70 +506,6 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     }
 }
 
-// ---------------------------------------------------------------------------
-// One-body beta class for two electrons per spin above 80 orbitals (adds
-// into sigma; the alpha class is launch_onebody_alpha_large).
-//
-// Beta: within the alpha row I,
-//   sigma(I, {y<b}) += sum_s h_bs sgn(s - y) c(I, {y, s}) - sum_s h_ys sgn(s - b) c(I, {b, s}).
-// A workgroup stages row I (NV vectors) in LDS; one thread per target.
-// Rows that do not fit in LDS (STAGE = false) are read from global memory;
-// for norb <= 64 the beta pair-index table and h are staged in LDS too.
-template <int NV, bool STAGE>
-__global__ __launch_bounds__(256) void k_onebody_b(SigmaArgs A, int nv, const double *__restrict__ c,
-                                                   int64_t ldc, double *__restrict__ sg, int64_t lds,
-                                                   const double *__restrict__ hs)
-{
-    extern __shared__ double lrow[];   // [len][NV], then (norb <= 64) int pidx[norb*norb], double h[norb*norb]
-    const int norb = A.norb, L = A.L;
-    const int ia = blockIdx.x;
-    const int len = A.sb.le[L - A.alev[ia]];
-    const int64_t base = A.rowstart[ia];
-    const bool small = STAGE && norb <= 64;
-    double *lh = lrow + (size_t)A.sb.le[L] * NV;               // after the longest row
-    int *lp = reinterpret_cast<int *>(lh + (small ? norb * norb : 0));
-    if (STAGE) {
-        for (int t = threadIdx.x; t < len; t += blockDim.x)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) lrow[t * NV + v] = (v < nv) ? c[v * ldc + base + t] : 0.0;
-        if (small)
-            for (int t = threadIdx.x; t < norb * norb; t += blockDim.x) {
-                lh[t] = hs[t];
-                lp[t] = A.bpidx[t];
-            }
-        __syncthreads();
-    }
-    const int *bpx = small ? lp : A.bpidx;
-    const double *hh = small ? lh : hs;
-    for (int ib = threadIdx.x; ib < len; ib += blockDim.x) {
-        const uint32_t bs = A.bstr[ib];
-        const int y = bs & 0xff, b = (bs >> 8) & 0xff;
-        double acc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        for (int s = 0; s < norb; ++s) {
-            const double hb = hh[b * norb + s], hy = hh[y * norb + s];
-            const int j1 = (hb != 0.0 && s != y) ? bpx[y * norb + s] : -1;
-            const int j2 = (hy != 0.0 && s != b) ? bpx[b * norb + s] : -1;
-            const double f1 = (s > y) ? hb : -hb, f2 = (s > b) ? -hy : hy;
-            if (j1 >= 0 && j1 < len) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    acc[v] += f1 * (STAGE ? lrow[j1 * NV + v] : (v < nv ? c[v * ldc + base + j1] : 0.0));
-            }
-            if (j2 >= 0 && j2 < len) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    acc[v] += f2 * (STAGE ? lrow[j2 * NV + v] : (v < nv ? c[v * ldc + base + j2] : 0.0));
-            }
-        }
-        double *dst = sg + base + ib;
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < nv) dst[v * lds] += acc[v];
-    }
-}
-
 template <int NV>
 __global__ __launch_bounds__(256) void k_sigma_n2(SigmaArgs A, int nv, const double *__restrict__ c,
                                                   int64_t ldc, double *__restrict__ sg, int64_t lds)
@@ -680,32 +616,19 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                     }
                 }
                 if (c->d.hscreen && !c->onebody_in_tiles) {
-                    // one-body classes (matrix cores; above 80 orbitals alpha in
+                    // one-body classes on matrix cores (above 80 orbitals alpha in
                     // the spectator form, two launches by spectator side, and
-                    // beta on the pair-table kernel), then same-spin if any;
-                    // with dense integrals the tiles carry the one-body units
-                    // instead
+                    // beta as the alpha class of the transposed block), then
+                    // same-spin if any; with dense integrals the tiles carry
+                    // the one-body units instead
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, s));
                     if (onebody_mfma_ok(c)) {
                         ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, s));
                     } else {
                         ISCI_CHECK(launch_onebody_alpha_large(c, nv, cc, ldc, ss, lds, s));
-                        for (int u0 = 0; u0 < nv; u0 += 4) {
-                            const int nu = nv - u0 < 4 ? nv - u0 : 4;
-                            if (c->d.obT_c) {
-                                ISCI_CHECK(launch_onebody_beta_large(c, nu, cc + (int64_t)u0 * ldc, ldc,
-                                                                     ss + (int64_t)u0 * lds, lds, s));
-                                continue;
-                            }
-                            size_t shm = sizeof(double) * 4 * (size_t)c->max_rowlen;
-                            if (c->norb <= 64) shm += (sizeof(double) + sizeof(int)) * (size_t)c->norb * c->norb;
-                            if (shm <= 65536)
-                                k_onebody_b<4, true><<<(unsigned)c->sa.nstr, 256, shm, s>>>(
-                                    A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
-                            else
-                                k_onebody_b<4, false><<<(unsigned)c->sa.nstr, 256, 0, s>>>(
-                                    A, nu, cc + (int64_t)u0 * ldc, ldc, ss + (int64_t)u0 * lds, lds, c->d.hscreen);
-                        }
+                        for (int u0 = 0; u0 < nv; u0 += 4)
+                            ISCI_CHECK(launch_onebody_beta_large(c, nv - u0 < 4 ? nv - u0 : 4, cc + (int64_t)u0 * ldc,
+                                                                 ldc, ss + (int64_t)u0 * lds, lds, s));
                         ISCI_HIP(hipGetLastError());
                     }
                     ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, s));
