@@ -92,8 +92,9 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 // (w % CW) and the (w / CW)-th of KS contiguous parts of the chunk list
 // (more waves in flight per tile); the parts are summed through LDS in a
 // fixed order.
+// (at most 80 VGPRs: six waves per SIMD, three 8-wave workgroups per CU)
 template <int CW, int KS>
-__global__ __launch_bounds__(64 * CW * KS) void k_ab_gemm(SigmaArgs A)
+__global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6))) void k_ab_gemm(SigmaArgs A)
 {
     __shared__ double red[KS > 1 ? KS - 1 : 1][CW][16][64];
     const int nb = A.nblk;
@@ -116,8 +117,11 @@ __global__ __launch_bounds__(64 * CW * KS) void k_ab_gemm(SigmaArgs A)
     int ee = eb;
     for (int l = 0; l < 3; ++l)
         if (c0 < A.abx_pcols[max(l, m)]) ee = tb.end[l];
-    const int e0 = eb + (int)((long long)(ee - eb) * part / KS);
-    const int e1 = eb + (int)((long long)(ee - eb) * (part + 1) / KS);
+    // parts cut at multiples of four chunks (the loop's step), so only the
+    // last part runs zero-padded steps
+    const int step = ((ee - eb + KS - 1) / KS + 3) & ~3;
+    const int e0 = min(ee, eb + step * part);
+    const int e1 = min(ee, eb + step * (part + 1));
     const int k = lane >> 4, n = lane & 15;
     v4d_ab acc[4];
 #pragma unroll
