@@ -732,31 +732,40 @@ isci_status launch_onebody_alpha_large(const isci_ctx *cx, int nv, const double 
 // With two electrons of each spin the alpha and beta string sets, their
 // order and the row layout coincide, so the beta class of c is the alpha
 // class of its transpose c^T[j][i] = c[i][j] (row = beta string, column =
-// alpha string), with the same row tables.  One thread per determinant:
-//   add = 0: dst[row j][col i] = src[row i][col j]   (coalesced reads)
-//   add = 1: dst[row i][col j] += src[row j][col i]  (coalesced updates)
-__global__ __launch_bounds__(256) void k_det_transpose(SigmaArgs A, int nv, const double *__restrict__ src,
-                                                       int64_t lsrc, double *__restrict__ dst, int64_t ldst,
-                                                       int add)
+// alpha string), with the same row tables.  Row i holds the columns
+// j < len(i), and len does not grow with i, so a 32 x 32 tile of the
+// (row, column) square is empty when its first column lies past its first
+// row's length.  A workgroup moves one tile of one vector through LDS
+// (coalesced on both sides):
+//   add = 0: dst[row a][col b]  = src[row b][col a]
+//   add = 1: dst[row a][col b] += src[row b][col a]
+// for src rows b in [32 (bt0 + blockIdx.y), +32), columns a in
+// [32 blockIdx.x, +32).
+__global__ __launch_bounds__(256) void k_det_transpose(SigmaArgs A, const double *__restrict__ src, int64_t lsrc,
+                                                       double *__restrict__ dst, int64_t ldst, int add, int bt0)
 {
-    const int ia = blockIdx.x;
-    const int jb = blockIdx.y * 256 + threadIdx.x;
-    const int len = A.sb.le[A.L - A.alev[ia]];
-    if (jb >= len) return;
-    const int64_t here = A.rowstart[ia] + jb, there = A.rowstart[jb] + ia;
-    double val[4];
-    if (add) {
+    const int b0 = (bt0 + blockIdx.y) * 32, a0 = blockIdx.x * 32, v = blockIdx.z;
+    const int n = A.sa.nstr, L = A.L;
+    // tile rows of src are b, columns a: empty when a0 >= len(b0)
+    if (b0 >= n || a0 >= A.sb.le[L - A.alev[b0]]) return;
+    __shared__ double tile[32][33];
+    const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;
+    const double *s = src + (int64_t)v * lsrc;
+    double *d = dst + (int64_t)v * ldst;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) val[v] = src[(int64_t)min(v, nv - 1) * lsrc + there];
+    for (int r = ry; r < 32; r += 8) {
+        const int b = b0 + r, a = a0 + cx;
+        const bool ok = b < n && a < A.sb.le[L - A.alev[min(b, n - 1)]];
+        tile[r][cx] = ok ? s[A.rowstart[min(b, n - 1)] + (ok ? a : 0)] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (v < nv) dst[(int64_t)v * ldst + here] += val[v];
-    } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) val[v] = src[(int64_t)min(v, nv - 1) * lsrc + here];
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (v < nv) dst[(int64_t)v * ldst + there] = val[v];
+    for (int r = ry; r < 32; r += 8) {
+        const int a = a0 + r, b = b0 + cx;
+        if (a < n && b < A.sb.le[L - A.alev[a]]) {
+            double *o = d + A.rowstart[a] + b;
+            *o = add ? *o + tile[cx][r] : tile[cx][r];
+        }
     }
 }
 
@@ -775,12 +784,24 @@ isci_status launch_onebody_beta_large(const isci_ctx *cx, int nv, const double *
     }
     const SigmaArgs A = sigma_args(cx);
     const int64_t dim = cx->dim;
-    const dim3 grid((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256));
-    k_det_transpose<<<grid, 256, 0, st>>>(A, nv, c, ldc, cx->d.obT_c, dim, 0);
+    // row tiles grouped by the length of their first row (one value per
+    // level): each group launches only the column tiles that row reaches
+    auto transpose = [&](const double *src, int64_t lsrc, double *dst, int64_t ldst, int add) {
+        const int n = cx->sa.nstr, nt = (n + 31) / 32;
+        for (int t0 = 0; t0 < nt;) {
+            const int len0 = cx->sb.le[cx->L - cx->h_alev[32 * t0]];
+            int t1 = t0 + 1;
+            while (t1 < nt && cx->sb.le[cx->L - cx->h_alev[32 * t1]] == len0) ++t1;
+            k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0), (unsigned)nv), 256, 0, st>>>(
+                A, src, lsrc, dst, ldst, add, t0);
+            t0 = t1;
+        }
+    };
+    transpose(c, ldc, cx->d.obT_c, dim, 0);
     k_fill_zero<<<(unsigned)std::min<int64_t>(4096, (dim * nv + 255) / 256), 256, 0, st>>>(cx->d.obT_s, dim * nv);
     ISCI_HIP(hipGetLastError());
     ISCI_CHECK(launch_onebody_alpha_large(cx, nv, cx->d.obT_c, dim, cx->d.obT_s, dim, st));
-    k_det_transpose<<<grid, 256, 0, st>>>(A, nv, cx->d.obT_s, dim, s, lds, 1);
+    transpose(cx->d.obT_s, dim, s, lds, 1);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }
