@@ -157,7 +157,11 @@ isci_status isci_dim(isci_handle hd, int64_t *dim);
 /* sigma[v*lds + I] = sum_J (H_tau)_IJ c[v*ldc + J] for v < nvec, all I
  * (Eq. sigma).  c and sigma are device arrays of nvec vectors with leading
  * dimensions ldc, lds >= dim; sigma is overwritten and must not overlap c.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`.  The handle owns the call's scratch (unfolded
+ * operand, products, transposed block) and a side stream that it forks
+ * from and joins back to `stream` with events, so calls on one handle must
+ * be ordered (one stream at a time, or synchronised); different handles
+ * may run concurrently. */
 isci_status isci_sigma(isci_handle hd, int nvec, const double *c, int64_t ldc,
                        double *sigma, int64_t lds, hipStream_t stream);
 
