@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "isci_device.h"
@@ -509,6 +510,10 @@ struct isci_engine_s {
     char *arena_d = nullptr, *arena_h = nullptr;
     double *res_d = nullptr, *res_h = nullptr;
     size_t arena_cap = 0, res_cap = 0;
+    // the last upload from arena_h: the host rewrites the arena only after
+    // that copy has run
+    hipEvent_t arena_ev = nullptr;
+    bool arena_pending = false;
     // side streams for the per-instance matrix-core sigma launches (default
     // priority), forked from and joined back into s with events
     std::vector<hipStream_t> side;
@@ -830,8 +835,14 @@ struct ArenaPack {
     }
 };
 
+// wait for the previous upload, then make room (called before the host
+// writes a phase's descriptors)
 static bool arena_reserve(isci_engine e, size_t bytes)
 {
+    if (e->arena_pending) {
+        if (hipEventSynchronize(e->arena_ev) != hipSuccess) return false;
+        e->arena_pending = false;
+    }
     if (bytes <= e->arena_cap) return true;
     size_t n = std::max(bytes, 2 * e->arena_cap + 65536);
     if (e->arena_d) (void)hipFree(e->arena_d);
@@ -858,6 +869,16 @@ static bool res_reserve(isci_engine e, size_t ndouble)
     if (hipHostMalloc((void **)&e->res_h, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) return false;
     e->res_cap = n;
     return true;
+}
+
+// copy a phase's descriptors to the device on s and mark the arena busy
+static isci_status arena_upload(isci_engine e, size_t bytes, hipStream_t s)
+{
+    ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, bytes, hipMemcpyHostToDevice, s));
+    if (!e->arena_ev) ISCI_HIP(hipEventCreateWithFlags(&e->arena_ev, hipEventDisableTiming));
+    ISCI_HIP(hipEventRecord(e->arena_ev, s));
+    e->arena_pending = true;
+    return ISCI_OK;
 }
 
 template <typename T>
@@ -979,7 +1000,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
         const size_t o = ap.push(jb);
         if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
         BDot *dd = arena_put(e, o, jb);
-        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        ISCI_CHECK(arena_upload(e, ap.used, s));
         if ((st = launch_bdots(dd, jb, s)) != ISCI_OK) return st;
         ISCI_HIP(hipMemcpyAsync(e->res_h, e->res_d, sizeof(double) * std::max<size_t>(roff, 1), hipMemcpyDeviceToHost, s));
         ISCI_HIP(hipStreamSynchronize(s));
@@ -989,7 +1010,9 @@ static isci_status engine_step(isci_engine e, int *nactive)
     std::vector<double> params;
     std::vector<size_t> offY(na), offR(na);
     size_t rC = roff;
-    for (int j = 0; j < na; ++j) {
+    // each slot's projected matrix and its eigendecomposition depend on that
+    // slot alone: with many slots they are spread over host threads
+    auto project = [&](int j) {
         Slot *sl = act[j];
         const int m = sl->m, mdone = sl->mdone, nnew = m - mdone, mmax = sl->mmax;
         const double *col = e->res_h + offB[j];
@@ -1010,6 +1033,23 @@ static isci_status engine_step(isci_engine e, int *nactive)
         for (int i = 0; i < m; ++i)
             for (int q = 0; q < m; ++q) Gm[(size_t)i * m + q] = sl->G[(size_t)i * mmax + q];
         jacobi_eigh(m, Gm, sl->evals, sl->Z);
+    };
+    {
+        const int nth = std::min<int>(na / 4, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+        if (nth > 1) {
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nth; ++t)
+                pool.emplace_back([&, t]() {
+                    for (int j = t; j < na; j += nth) project(j);
+                });
+            for (std::thread &th : pool) th.join();
+        } else {
+            for (int j = 0; j < na; ++j) project(j);
+        }
+    }
+    for (int j = 0; j < na; ++j) {
+        Slot *sl = act[j];
+        const int m = sl->m;
         const int kr = std::min(sl->kk, m);
         sl->kr = kr;
         offY[j] = params.size();
@@ -1048,7 +1088,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
         BLin *dl = arena_put(e, ol, jl);
         BRes *dr = arena_put(e, orr, jr);
         BDot *dd = arena_put(e, od, jd);
-        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        ISCI_CHECK(arena_upload(e, ap.used, s));
         if ((st = launch_blincomb(dl, jl, s)) != ISCI_OK) return st;
         k_bresid<<<dim3((unsigned)std::min<int64_t>(4096, (max_n(jr) + 255) / 256), 1, (unsigned)jr.size()), 256, 0, s>>>(dr);
         ISCI_HIP(hipGetLastError());
@@ -1169,7 +1209,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
              *dg1 = arena_put(e, og1, g1), *dgm = arena_put(e, ogm, gm);
         BLin *dl1 = arena_put(e, ol1, l1), *dl2 = arena_put(e, ol2, l2);
         BFlag *dfl = arena_put(e, ofl, fl);
-        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        ISCI_CHECK(arena_upload(e, ap.used, s));
         if (!cp.empty()) {
             const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(cp) + 255) / 256);
             k_bcopy<<<dim3(gx, 1, (unsigned)cp.size()), 256, 0, s>>>(dcp);
@@ -1237,7 +1277,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
         arena_put(e, opar, params);
         BLin *dlq = arena_put(e, olq, lq);
         BDot *dg2 = arena_put(e, og2, g2);
-        ISCI_HIP(hipMemcpyAsync(e->arena_d, e->arena_h, ap.used, hipMemcpyHostToDevice, s));
+        ISCI_CHECK(arena_upload(e, ap.used, s));
         if ((st = launch_blincomb(dlq, lq, s)) != ISCI_OK) return st;
         if (pass == 0) {
             if ((st = launch_bdots(dg2, g2, s)) != ISCI_OK) return st;
@@ -1395,6 +1435,7 @@ void isci_engine_destroy(isci_engine e)
     if (e->d_vecs) (void)hipFree(e->d_vecs);
     if (e->h_vecs) (void)hipHostFree(e->h_vecs);
     if (e->arena_d) (void)hipFree(e->arena_d);
+    if (e->arena_ev) (void)hipEventDestroy(e->arena_ev);
     if (e->arena_h) (void)hipHostFree(e->arena_h);
     if (e->res_d) (void)hipFree(e->res_d);
     if (e->res_h) (void)hipHostFree(e->res_h);
