@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ 
 
 // partial-sum blocks for a dot product of length n: about 2048 elements
 // (8 per thread) per block, at most kDotBlocks
-int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 2047) / 2048)); }
+int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 511) / 512)); }
 
 isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int k, int64_t n,
                  double *out_dev, double *partial, int nblk, hipStream_t s)
@@ -236,6 +236,106 @@ static void jacobi_eigh(int m, std::vector<double> A, std::vector<double> &w, st
     Z.swap(Z2);
 }
 
+
+// Symmetric eigensolver: Householder reduction to tridiagonal form, then the
+// implicit symmetric QR iteration with Wilkinson shifts (Golub and Van Loan,
+// Matrix Computations, sections 8.3.1 and 8.3.2).  A (m x m, row major,
+// symmetric) -> eigenvalues w ascending, vectors Z (column j in Z[i*m+j]).
+// Returns false when the QR iteration does not settle (the caller then uses
+// the Jacobi solver).
+static bool tridiag_eigh(int m, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z)
+{
+    Z.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+    std::vector<double> v(m), p(m), d(m), e(std::max(m, 1), 0.0);
+    // (1) A <- H A H with H = I - 2 v v^T zeroing column k below its subdiagonal; Z <- Z H
+    for (int k = 0; k + 2 < m; ++k) {
+        const int n = m - k - 1;   // trailing size, indices k+1 .. m-1
+        double nx = 0.0;
+        for (int i = 0; i < n; ++i) nx += A[(size_t)(k + 1 + i) * m + k] * A[(size_t)(k + 1 + i) * m + k];
+        nx = sqrt(nx);
+        const double x0 = A[(size_t)(k + 1) * m + k];
+        const double alpha = x0 >= 0.0 ? -nx : nx;
+        for (int i = 0; i < n; ++i) v[i] = A[(size_t)(k + 1 + i) * m + k];
+        v[0] -= alpha;
+        double nv = 0.0;
+        for (int i = 0; i < n; ++i) nv += v[i] * v[i];
+        if (nv == 0.0) continue;   // column already reduced
+        nv = 1.0 / sqrt(nv);
+        for (int i = 0; i < n; ++i) v[i] *= nv;
+        double K = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            const double *row = &A[(size_t)(k + 1 + i) * m + k + 1];
+            for (int j = 0; j < n; ++j) s += row[j] * v[j];
+            p[i] = s;
+            K += v[i] * s;
+        }
+        for (int i = 0; i < n; ++i) p[i] = 2.0 * (p[i] - K * v[i]);
+        for (int i = 0; i < n; ++i) {
+            double *row = &A[(size_t)(k + 1 + i) * m + k + 1];
+            for (int j = 0; j < n; ++j) row[j] -= v[i] * p[j] + p[i] * v[j];
+        }
+        A[(size_t)(k + 1) * m + k] = A[(size_t)k * m + k + 1] = alpha;
+        for (int i = 1; i < n; ++i) A[(size_t)(k + 1 + i) * m + k] = A[(size_t)k * m + k + 1 + i] = 0.0;
+        for (int r = 0; r < m; ++r) {
+            double *zr = &Z[(size_t)r * m + k + 1];
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += zr[j] * v[j];
+            s *= 2.0;
+            for (int j = 0; j < n; ++j) zr[j] -= s * v[j];
+        }
+    }
+    // rotations below act on pairs of columns of Z: keep them as rows of Zt
+    std::vector<double> Zt((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Zt[(size_t)j * m + i] = Z[(size_t)i * m + j];
+    for (int i = 0; i < m; ++i) d[i] = A[(size_t)i * m + i];
+    for (int i = 0; i + 1 < m; ++i) e[i] = A[(size_t)(i + 1) * m + i];
+    // (2) implicit QR steps on the unreduced trailing block [lo, hi]; a
+    // subdiagonal entry at rounding level of its neighbours is set to zero
+    const double eps = 2.220446049250313e-16;
+    int hi = m - 1, steps = 0;
+    while (hi > 0) {
+        if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) { e[hi - 1] = 0.0; --hi; continue; }
+        if (++steps > 60 * m) return false;
+        int lo = hi - 1;
+        while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
+        const double dl = 0.5 * (d[hi - 1] - d[hi]), b = e[hi - 1];
+        const double mu = d[hi] - b * b / (dl + (dl >= 0.0 ? 1.0 : -1.0) * hypot(dl, b));
+        double x = d[lo] - mu, z = e[lo], bulge = 0.0;
+        for (int k = lo; k < hi; ++k) {
+            if (k > lo) { x = e[k - 1]; z = bulge; }
+            const double r = hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r != 0.0) { c = x / r; s = z / r; }
+            if (k > lo) e[k - 1] = r;
+            const double a = d[k], bb = e[k], cc = d[k + 1];
+            d[k] = c * c * a + 2.0 * c * s * bb + s * s * cc;
+            d[k + 1] = s * s * a - 2.0 * c * s * bb + c * c * cc;
+            e[k] = c * s * (cc - a) + (c * c - s * s) * bb;
+            if (k + 1 < hi) { bulge = s * e[k + 1]; e[k + 1] *= c; }
+            double *z0 = &Zt[(size_t)k * m], *z1 = z0 + m;
+            for (int r2 = 0; r2 < m; ++r2) {
+                const double a0 = z0[r2], a1 = z1[r2];
+                z0[r2] = c * a0 + s * a1;
+                z1[r2] = -s * a0 + c * a1;
+            }
+        }
+    }
+    std::vector<int> ord(m);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] < d[b]; });
+    w.resize(m);
+    for (int j = 0; j < m; ++j) {
+        w[j] = d[ord[j]];
+        const double *zt = &Zt[(size_t)ord[j] * m];
+        for (int i = 0; i < m; ++i) Z[(size_t)i * m + j] = zt[i];
+    }
+    return true;
+}
 
 __global__ void k_neg(double *__restrict__ x, int n)
 {
@@ -1032,7 +1132,7 @@ static isci_status engine_step(isci_engine e, int *nactive)
         std::vector<double> Gm((size_t)m * m);
         for (int i = 0; i < m; ++i)
             for (int q = 0; q < m; ++q) Gm[(size_t)i * m + q] = sl->G[(size_t)i * mmax + q];
-        jacobi_eigh(m, Gm, sl->evals, sl->Z);
+        if (!tridiag_eigh(m, Gm, sl->evals, sl->Z)) jacobi_eigh(m, Gm, sl->evals, sl->Z);
     };
     {
         const int nth = std::min<int>(na / 4, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
@@ -1099,6 +1199,11 @@ static isci_status engine_step(isci_engine e, int *nactive)
     }
     // ---- host: convergence, corrections, thick restarts
     std::vector<Slot *> grow_set;
+    // thick restarts of this step: their linear combinations run in the
+    // next launch group, batched over the slots, with no host wait
+    struct Restart { Slot *sl; int keep, m, kr; size_t off; };
+    std::vector<Restart> rst;
+    std::vector<double> rpar;
     for (int j = 0; j < na; ++j) {
         Slot *sl = act[j];
         const int m = sl->m, kr = sl->kr, k = sl->k;
@@ -1122,19 +1227,12 @@ static isci_status engine_step(isci_engine e, int *nactive)
         if (sl->pick.empty())
             for (int q = 0; q < kr && (int)sl->pick.size() < sl->block; ++q) sl->pick.push_back(q);
         if (m + (int)sl->pick.size() > sl->mmax) {
-            // thick restart (per slot; rare): keep the lowest `keep` Ritz vectors
+            // thick restart (per slot): keep the lowest `keep` Ritz vectors;
+            // V and W become V Z_keep and W Z_keep (launched below)
             const int keep = std::min(m, sl->keep_max);
-            double *hYk = sl->hsmall;
+            rst.push_back(Restart{sl, keep, m, kr, rpar.size()});
             for (int q = 0; q < keep; ++q)
-                for (int i = 0; i < m; ++i) hYk[(size_t)q * m + i] = sl->Z[(size_t)i * m + q];
-            double *dYk = sl->small;
-            ISCI_HIP(hipMemcpyAsync(dYk, hYk, sizeof(double) * (size_t)keep * m, hipMemcpyHostToDevice, s));
-            if ((st = lincomb(sl->V, sl->dim, m, dYk, keep, sl->X, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
-            ISCI_HIP(hipMemcpyAsync(sl->V, sl->X, sizeof(double) * (size_t)keep * sl->dim, hipMemcpyDeviceToDevice, s));
-            if ((st = lincomb(sl->W, sl->dim, m, dYk, keep, sl->X, sl->dim, sl->dim, 0.0, s)) != ISCI_OK) return st;
-            ISCI_HIP(hipMemcpyAsync(sl->W, sl->X, sizeof(double) * (size_t)keep * sl->dim, hipMemcpyDeviceToDevice, s));
-            ISCI_HIP(hipMemcpyAsync(sl->X, sl->V, sizeof(double) * (size_t)kr * sl->dim, hipMemcpyDeviceToDevice, s));
-            ISCI_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < m; ++i) rpar.push_back(sl->Z[(size_t)i * m + q]);
             sl->m = keep;
             sl->mdone = keep;
             std::fill(sl->G.begin(), sl->G.end(), 0.0);
@@ -1200,16 +1298,49 @@ static isci_status engine_step(isci_engine e, int *nactive)
                 l2.push_back(BLin{sl->V, sl->small, X, sl->dim, sl->dim, sl->dim, m, p, 1.0, -1.0, flag});
             }
         }
+        // restarts: X = V Z_keep, V = X; X = W Z_keep, W = X; X = V[0, kr)
+        // (the Ritz vectors, kept in X for the results)
+        std::vector<BLin> rv(rst.size()), rw(rst.size());
+        std::vector<BVecOp> rcv, rcw, rcx;
         ArenaPack ap{e};
+        const size_t orp = ap.push(rpar), orv = ap.push(rv), orw = ap.push(rw);
+        for (size_t r = 0; r < rst.size(); ++r) {
+            Slot *sl = rst[r].sl;
+            const int64_t dim = sl->dim;
+            rcv.push_back(BVecOp{sl->X, sl->V, nullptr, nullptr, nullptr, (int64_t)rst[r].keep * dim});
+            rcw.push_back(BVecOp{sl->X, sl->W, nullptr, nullptr, nullptr, (int64_t)rst[r].keep * dim});
+            rcx.push_back(BVecOp{sl->V, sl->X, nullptr, nullptr, nullptr, (int64_t)rst[r].kr * dim});
+        }
+        const size_t orcv = ap.push(rcv), orcw = ap.push(rcw), orcx = ap.push(rcx);
         const size_t ocp = ap.push(cp), og0 = ap.push(g0), oc1 = ap.push(c1), oc2 = ap.push(c2), og1 = ap.push(g1),
                      ol1 = ap.push(l1), ol2 = ap.push(l2), ogm = ap.push(gm), ofl = ap.push(fl);
         if (!arena_reserve(e, ap.used + 256)) { set_error("allocation failed (arena)"); return ISCI_E_OOM; }
+        {
+            const double *pd = (const double *)(e->arena_d + orp);
+            for (size_t r = 0; r < rst.size(); ++r) {
+                Slot *sl = rst[r].sl;
+                const Restart &q = rst[r];
+                rv[r] = BLin{sl->V, pd + q.off, sl->X, sl->dim, sl->dim, sl->dim, q.m, q.keep, 0.0, 1.0};
+                rw[r] = BLin{sl->W, pd + q.off, sl->X, sl->dim, sl->dim, sl->dim, q.m, q.keep, 0.0, 1.0};
+            }
+        }
+        arena_put(e, orp, rpar);
+        BLin *drv = arena_put(e, orv, rv), *drw = arena_put(e, orw, rw);
+        BVecOp *drcv = arena_put(e, orcv, rcv), *drcw = arena_put(e, orcw, rcw), *drcx = arena_put(e, orcx, rcx);
         BVecOp *dcp = arena_put(e, ocp, cp);
         BDot *dg0 = arena_put(e, og0, g0), *dc1 = arena_put(e, oc1, c1), *dc2 = arena_put(e, oc2, c2),
              *dg1 = arena_put(e, og1, g1), *dgm = arena_put(e, ogm, gm);
         BLin *dl1 = arena_put(e, ol1, l1), *dl2 = arena_put(e, ol2, l2);
         BFlag *dfl = arena_put(e, ofl, fl);
         ISCI_CHECK(arena_upload(e, ap.used, s));
+        if (!rst.empty()) {
+            if ((st = launch_blincomb(drv, rv, s)) != ISCI_OK) return st;
+            k_bcopy<<<dim3(grid1(max_n(rcv)), 1, (unsigned)rcv.size()), 256, 0, s>>>(drcv);
+            if ((st = launch_blincomb(drw, rw, s)) != ISCI_OK) return st;
+            k_bcopy<<<dim3(grid1(max_n(rcw)), 1, (unsigned)rcw.size()), 256, 0, s>>>(drcw);
+            k_bcopy<<<dim3(grid1(max_n(rcx)), 1, (unsigned)rcx.size()), 256, 0, s>>>(drcx);
+            ISCI_HIP(hipGetLastError());
+        }
         if (!cp.empty()) {
             const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_n(cp) + 255) / 256);
             k_bcopy<<<dim3(gx, 1, (unsigned)cp.size()), 256, 0, s>>>(dcp);
