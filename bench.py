@@ -101,6 +101,21 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     ms_per_step = ev_ms / a.steps
+    # the same step recorded once as a HIP graph and replayed (one graph
+    # launch per step instead of the call's kernel launches)
+    sg_g = torch.empty_like(c)
+    g = isci.isci_sigma_graph_create(hd, c, sg_g)
+    for _ in range(a.warmup):
+        g.launch(stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(a.steps):
+        g.launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / a.steps
+    graph_equal = bool(torch.equal(sg_g, sg))
+    g.destroy()
     terms = int(st["terms_total"])
     tb = st["terms"]
     terms_ab = int(tb[26:42].sum())
@@ -184,6 +199,8 @@ def main():
         "step_tflops": flops_step / (ms_per_step * 1e-3) / 1e12,
         "step_frac_fp64": flops_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
         "kernels": kernels,
+        "graph": {"ms_per_step": ms_graph, "sigma_vectors_per_s": nvec / (ms_graph * 1e-3),
+                  "speedup_vs_calls": ms_per_step / ms_graph, "bitwise_equal_to_calls": graph_equal},
     }
     if not a.skip_davidson:
         out["davidson"] = davidson_latency(isci, torch, dev)

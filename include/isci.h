@@ -165,6 +165,29 @@ isci_status isci_dim(isci_handle hd, int64_t *dim);
 isci_status isci_sigma(isci_handle hd, int nvec, const double *c, int64_t ldc,
                        double *sigma, int64_t lds, hipStream_t stream);
 
+/* A sigma call recorded as a HIP graph, for callers that apply H_tau many
+ * times to the same buffers (their own iterative solvers, serving loops
+ * that reuse work vectors): one graph launch replaces the call's kernel
+ * launches and its side-stream fork and join.
+ *
+ * isci_sigma_graph_create records isci_sigma(hd, nvec, c, ldc, sigma, lds)
+ * (same arguments, same checks, same errors) by stream capture on a private
+ * stream and instantiates it; nothing runs at creation.  Each
+ * isci_graph_launch then computes sigma from the current contents of c,
+ * exactly as the recorded call would (Eq. sigma), asynchronously on
+ * `stream`.  The graph keeps the pointers c and sigma and uses the
+ * handle's scratch: the caller keeps c, sigma and the handle alive until
+ * isci_graph_destroy, and orders launches with the handle's other sigma
+ * calls (one at a time).  The kernel path is the one the handle had at
+ * creation; options set later do not change it.  Refused (ISCI_E_INVALID)
+ * while kernel profiling is enabled on the handle.  *out is NULL on
+ * failure. */
+typedef struct isci_graph_s *isci_graph;
+isci_status isci_sigma_graph_create(isci_handle hd, int nvec, const double *c, int64_t ldc,
+                                    double *sigma, int64_t lds, isci_graph *out);
+isci_status isci_graph_launch(isci_graph g, hipStream_t stream);
+void isci_graph_destroy(isci_graph g);
+
 /* diag[I] = (H_tau)_II (the diagonal units kept by the same rule).
  * Device array of length dim.  Asynchronous. */
 isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);

@@ -20,7 +20,7 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
-           "AB_GATHER"]
+           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -121,6 +121,49 @@ def isci_sigma(hd: Handle, c, sigma=None, stream=None):
                                 _dev_f64(s2, "sigma"), int(s2.stride(0)), _stream_ptr(stream))
     check(st, "isci_sigma")
     return sigma.squeeze(0) if (squeeze and sigma.dim() == 2) else sigma
+
+
+class SigmaGraph:
+    """One sigma call recorded as a HIP graph (isci_sigma_graph_create).
+    Holds the handle and both tensors so they outlive the graph."""
+
+    def __init__(self, ptr, hd: Handle, c, sigma, squeeze: bool):
+        self._ptr, self.handle, self.c, self.sigma, self._squeeze = ptr, hd, c, sigma, squeeze
+
+    def launch(self, stream=None):
+        """sigma = H_tau c from the current contents of c; returns sigma."""
+        if self._ptr is None:
+            raise ValueError("graph destroyed")
+        check(_lib.load().isci_graph_launch(self._ptr, _stream_ptr(stream)), "isci_graph_launch")
+        return self.sigma.squeeze(0) if self._squeeze else self.sigma
+
+    def destroy(self):
+        if self._ptr is not None:
+            _lib.load().isci_graph_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def isci_sigma_graph_create(hd: Handle, c, sigma=None) -> SigmaGraph:
+    """Record isci_sigma(hd, c, sigma) as a graph; launch() replays it."""
+    torch = _torch()
+    squeeze = c.dim() == 1
+    c2 = c.unsqueeze(0) if squeeze else c
+    if c2.shape[-1] != hd.dim:
+        raise ValueError("c has wrong length")
+    if sigma is None:
+        sigma = torch.empty_like(c2)
+    s2 = sigma.unsqueeze(0) if sigma.dim() == 1 else sigma
+    out = ctypes.c_void_p()
+    st = _lib.load().isci_sigma_graph_create(hd.ptr, int(c2.shape[0]), _dev_f64(c2, "c"), int(c2.stride(0)),
+                                             _dev_f64(s2, "sigma"), int(s2.stride(0)), ctypes.byref(out))
+    check(st, "isci_sigma_graph_create")
+    return SigmaGraph(out, hd, c2, s2, squeeze)
 
 
 def isci_diag(hd: Handle, out=None, stream=None):

@@ -31,6 +31,7 @@ ABI_SYMBOLS = (
     "isci_engine_create", "isci_engine_config", "isci_engine_add", "isci_engine_step",
     "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
     "isci_davidson_footprint", "isci_set_option", "isci_profile", "isci_profile_read",
+    "isci_sigma_graph_create", "isci_graph_launch", "isci_graph_destroy",
 )
 
 
@@ -83,6 +84,12 @@ def load(path: str = LIBPATH):
     L.isci_dim.restype = i32
     L.isci_sigma.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.isci_sigma.restype = i32
+    L.isci_sigma_graph_create.argtypes = [vp, i32, vp, i64, vp, i64, ctypes.POINTER(vp)]
+    L.isci_sigma_graph_create.restype = i32
+    L.isci_graph_launch.argtypes = [vp, vp]
+    L.isci_graph_launch.restype = i32
+    L.isci_graph_destroy.argtypes = [vp]
+    L.isci_graph_destroy.restype = None
     L.isci_diag.argtypes = [vp, vp, vp]
     L.isci_diag.restype = i32
     L.isci_davidson.argtypes = [vp, i32, ctypes.POINTER(IsciDavidsonOpts), vp, i32,

@@ -721,6 +721,61 @@ isci_status isci_sigma(isci_handle c, int nvec, const double *cv, int64_t ldc, d
     return launch_sigma(c, nvec, cv, ldc, sv, lds, stream);
 }
 
+struct isci_graph_s {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+};
+
+void isci_graph_destroy(isci_graph g)
+{
+    if (!g) return;
+    if (g->x) (void)hipGraphExecDestroy(g->x);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
+}
+
+isci_status isci_sigma_graph_create(isci_handle c, int nvec, const double *cv, int64_t ldc, double *sv, int64_t lds,
+                                    isci_graph *out)
+{
+    if (!out) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    *out = nullptr;
+    if (!c || !cv || !sv) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    if (nvec < 1) { set_error("nvec < 1"); return ISCI_E_INVALID; }
+    if (ldc < c->dim || lds < c->dim) { set_error("leading dimension < dim"); return ISCI_E_INVALID; }
+    const char *c0 = (const char *)cv, *c1 = (const char *)(cv + (int64_t)(nvec - 1) * ldc + c->dim);
+    const char *s0 = (const char *)sv, *s1 = (const char *)(sv + (int64_t)(nvec - 1) * lds + c->dim);
+    if (c0 < s1 && s0 < c1) { set_error("sigma overlaps c"); return ISCI_E_INVALID; }
+    if (c->profile) { set_error("kernel profiling is enabled on this handle"); return ISCI_E_INVALID; }
+    hipStream_t cs = nullptr;
+    ISCI_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    isci_graph g = new isci_graph_s;
+    isci_status st = ISCI_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = launch_sigma(c, nvec, cv, ldc, sv, lds, cs);
+        // the capture is ended in every case, so the streams leave capture mode
+        const hipError_t e2 = hipStreamEndCapture(cs, &g->g);
+        if (st == ISCI_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+        if (st == ISCI_OK) {
+            e = hipGraphInstantiate(&g->x, g->g, nullptr, nullptr, 0);
+            if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+        }
+    } else {
+        st = hip_fail(e, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != ISCI_OK) { isci_graph_destroy(g); return st; }
+    *out = g;
+    return ISCI_OK;
+}
+
+isci_status isci_graph_launch(isci_graph g, hipStream_t stream)
+{
+    if (!g || !g->x) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    ISCI_HIP(hipGraphLaunch(g->x, stream));
+    return ISCI_OK;
+}
+
 isci_status isci_diag(isci_handle c, double *diag, hipStream_t stream)
 {
     if (!c || !diag) { set_error("NULL argument"); return ISCI_E_INVALID; }

@@ -65,4 +65,10 @@ def test_invalid_arguments_rejected_before_any_device_work():
                             None) == _lib.ISCI_E_INVALID
     assert L.isci_create_ex(None, fake, fake, 4, 1, 1, 2, 0.0, None, None) == _lib.ISCI_E_INVALID
     assert L.isci_sigma(None, 1, fake, 1, fake, 1, None) == _lib.ISCI_E_INVALID
+    g = ctypes.c_void_p(0x2000)
+    assert L.isci_sigma_graph_create(None, 1, fake, 1, fake, 1, ctypes.byref(g)) == _lib.ISCI_E_INVALID
+    assert g.value is None   # *out cleared on failure
+    assert L.isci_sigma_graph_create(None, 1, fake, 1, fake, 1, None) == _lib.ISCI_E_INVALID
+    assert L.isci_graph_launch(None, None) == _lib.ISCI_E_INVALID
+    L.isci_graph_destroy(None)
     assert L.isci_last_error()
