@@ -141,12 +141,32 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
 #define ISCI_OB_SEPARATE 1
 #define ISCI_OB_TILES 2
 
+/* Device memory provider for a handle's resident tables (screened lists,
+ * string and row tables, the product path's operand and result blocks):
+ * for callers that keep device memory in their own pool (a framework's
+ * caching allocator).  alloc returns `bytes` of device memory usable in
+ * stream order on `stream`, or NULL (isci_create then fails with
+ * ISCI_E_OOM and frees what it took); free releases one block.  Both are
+ * called on the creating thread with the stream given to isci_create_ex,
+ * alloc during isci_create_ex and free during isci_destroy (which first
+ * waits for all work on the device, so no launch still reads a block).
+ * Temporaries of isci_create itself use hipMallocAsync on that stream. */
 typedef struct {
-    int onebody;                /* ISCI_OB_* (default ISCI_OB_AUTO) */
+    void *(*alloc)(size_t bytes, hipStream_t stream, void *ctx);
+    void (*free)(void *p, hipStream_t stream, void *ctx);
+    void *ctx;
+} isci_allocator;
+
+typedef struct {
+    int onebody;                      /* ISCI_OB_* (default ISCI_OB_AUTO) */
+    const isci_allocator *allocator;  /* NULL: hipMalloc / hipFree; else
+                                         both function pointers set; the
+                                         struct is copied at creation */
 } isci_create_opts;
 
 /* isci_create with build options; opts may be NULL (defaults).  Returns
- * ISCI_E_INVALID for an unknown onebody value. */
+ * ISCI_E_INVALID for an unknown onebody value or an allocator with a NULL
+ * function pointer. */
 isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri, int norb,
                            int nalpha, int nbeta, int max_excitation, double tau,
                            const isci_create_opts *opts, hipStream_t stream);

@@ -20,7 +20,7 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
-           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create"]
+           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -62,8 +62,9 @@ def _dev_f64(t, name):
 class Handle:
     """Owns an isci_handle; destroyed with the object or by isci_destroy."""
 
-    def __init__(self, ptr, norb, nalpha, nbeta, level, tau):
+    def __init__(self, ptr, norb, nalpha, nbeta, level, tau, keep=None):
         self._ptr = ptr
+        self._keep = keep   # the allocator callbacks, alive until isci_destroy
         self.norb, self.nalpha, self.nbeta, self.level, self.tau = norb, nalpha, nbeta, level, tau
         self.dim = isci_dim(self)
 
@@ -85,20 +86,46 @@ class Handle:
             pass
 
 
+def torch_allocator():
+    """An isci_allocator that takes the handle's device memory from torch's
+    caching allocator (torch.cuda.caching_allocator_alloc / _delete)."""
+    torch = _torch()
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(p, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(p))
+        except Exception:
+            pass
+
+    return _lib.IsciAllocator(_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free), None)
+
+
 def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
-                stream=None, onebody: int = OB_AUTO) -> Handle:
-    """Build a handle (isci_create_ex; onebody is one of OB_*)."""
+                stream=None, onebody: int = OB_AUTO, allocator=None) -> Handle:
+    """Build a handle (isci_create_ex; onebody is one of OB_*).  allocator:
+    None (hipMalloc), "torch" (torch's caching allocator) or an
+    _lib.IsciAllocator."""
     L = _lib.load()
     hp = _dev_f64(h, "h")
     ep = _dev_f64(eri, "eri")
     if h.numel() != norb * norb or eri.numel() != norb ** 4:
         raise ValueError("h must hold norb^2 and eri norb^4 elements")
     out = ctypes.c_void_p()
-    opts = _lib.IsciCreateOpts(int(onebody))
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
+        allocator = torch_allocator()
+    opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None)
     st = L.isci_create_ex(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
                           int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create")
-    return Handle(out, norb, nalpha, nbeta, max_excitation, tau)
+    return Handle(out, norb, nalpha, nbeta, max_excitation, tau, keep=allocator)
 
 
 def isci_dim(hd: Handle) -> int:

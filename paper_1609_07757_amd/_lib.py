@@ -42,9 +42,18 @@ class IsciStats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class IsciAllocator(ctypes.Structure):
+    """isci_allocator."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class IsciCreateOpts(ctypes.Structure):
     """isci_create_opts."""
-    _fields_ = [("onebody", ctypes.c_int)]
+    _fields_ = [("onebody", ctypes.c_int), ("allocator", ctypes.POINTER(IsciAllocator))]
 
 
 class IsciDavidsonOpts(ctypes.Structure):

@@ -174,6 +174,9 @@ struct isci_ctx {
     isci::DevTabs d;
     isci_stats stats{};
     std::vector<void *> allocs;
+    // caller's device memory provider (alloc == nullptr: hipMalloc / hipFree)
+    isci_allocator allocator{};
+    hipStream_t alloc_stream = nullptr;
     std::vector<int32_t> h_aorb, h_borb, h_alev, h_blev;  // host string tables
     std::vector<int64_t> h_rowstart;
     int max_rowlen = 0;

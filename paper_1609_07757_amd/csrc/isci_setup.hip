@@ -40,7 +40,12 @@ void *dev_alloc(isci_ctx *c, size_t bytes)
 {
     void *p = nullptr;
     if (bytes == 0) bytes = 8;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (c->allocator.alloc) {
+        p = c->allocator.alloc(bytes, c->alloc_stream, c->allocator.ctx);
+        if (!p) return nullptr;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        return nullptr;
+    }
     c->allocs.push_back(p);
     c->stats.device_bytes += (int64_t)bytes;
     return p;
@@ -958,7 +963,14 @@ static void destroy(isci_ctx *c)
     }
     if (c->ob_fork) (void)hipEventDestroy(c->ob_fork);
     if (c->ob_join) (void)hipEventDestroy(c->ob_join);
-    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->allocator.free) {
+        // the provider may hand the blocks to other work at once: let every
+        // launch that reads them finish first, on whichever stream it ran
+        (void)hipDeviceSynchronize();
+        for (void *p : c->allocs) c->allocator.free(p, c->alloc_stream, c->allocator.ctx);
+    } else {
+        for (void *p : c->allocs) (void)hipFree(p);
+    }
     for (void *p : c->work) (void)hipFree(p);
     delete c;
 }
@@ -1002,6 +1014,11 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         return ISCI_E_INVALID;
     }
     *out = nullptr;
+    const isci_allocator *al = opts ? opts->allocator : nullptr;
+    if (al && (!al->alloc || !al->free)) {
+        set_error("isci_create_opts.allocator needs both alloc and free");
+        return ISCI_E_INVALID;
+    }
     if (!h || !eri) { set_error("h or eri is NULL"); return ISCI_E_INVALID; }
     if (norb < 1) { set_error("norb < 1"); return ISCI_E_INVALID; }
     if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb) {
@@ -1019,6 +1036,8 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
     if (!c) { set_error("host allocation failed"); return ISCI_E_OOM; }
     c->norb = norb; c->na = nalpha; c->nb = nbeta; c->tau = tau;
     c->ob_place = ob_place;
+    if (al) c->allocator = *al;
+    c->alloc_stream = stream;
     const int lmax = std::min(nalpha, norb - nalpha) + std::min(nbeta, norb - nbeta);
     c->L = std::min(max_excitation, lmax);
     spin_table(c->sa, norb, nalpha, c->L);

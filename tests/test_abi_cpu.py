@@ -64,6 +64,10 @@ def test_invalid_arguments_rejected_before_any_device_work():
     assert L.isci_create_ex(ctypes.byref(out), fake, fake, 4, 1, 1, 2, 0.0, ctypes.byref(bad),
                             None) == _lib.ISCI_E_INVALID
     assert L.isci_create_ex(None, fake, fake, 4, 1, 1, 2, 0.0, None, None) == _lib.ISCI_E_INVALID
+    half = _lib.IsciAllocator()   # NULL function pointers
+    ao = _lib.IsciCreateOpts(0, ctypes.pointer(half))
+    assert L.isci_create_ex(ctypes.byref(out), fake, fake, 4, 1, 1, 2, 0.0, ctypes.byref(ao),
+                            None) == _lib.ISCI_E_INVALID
     assert L.isci_sigma(None, 1, fake, 1, fake, 1, None) == _lib.ISCI_E_INVALID
     g = ctypes.c_void_p(0x2000)
     assert L.isci_sigma_graph_create(None, 1, fake, 1, fake, 1, ctypes.byref(g)) == _lib.ISCI_E_INVALID
