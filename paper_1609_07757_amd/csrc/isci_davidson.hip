@@ -367,13 +367,44 @@ struct BDot {              // out[i*k + j] = sum_t A[i*lda + t] B[j*ldb + t]
     const double *skip = nullptr;   // device flag: nonzero skips the job
 };
 
-__global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, int tiles_j)
+// Sum each of the 64 values v[] over the wave's 64 lanes, halving the
+// values per lane at every step: lane L ends with the sum of value L in
+// v[0] (63 lane exchanges instead of 6 per value).
+template <int O>
+__device__ __forceinline__ void transpose_sum_step(double (&v)[64], int lane)
+{
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < O; ++i) {
+        const double send = up ? v[i] : v[i + O];
+        const double keep = up ? v[i + O] : v[i];
+        v[i] = keep + __shfl_xor(send, O, 64);
+    }
+}
+
+__device__ __forceinline__ void wave_transpose_sum64(double (&v)[64], int lane)
+{
+    transpose_sum_step<32>(v, lane);
+    transpose_sum_step<16>(v, lane);
+    transpose_sum_step<8>(v, lane);
+    transpose_sum_step<4>(v, lane);
+    transpose_sum_step<2>(v, lane);
+    transpose_sum_step<1>(v, lane);
+}
+
+// Workgroup id -> (tile, block of the element range): the tiles of one
+// element block are consecutive ids eight apart, so they run on one XCD
+// at about the same time and share the block's rows in its L2.
+__global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, int tiles_i, int tiles_j)
 {
     const BDot J = jobs[blockIdx.z];
     if (J.skip && *J.skip != 0.0) return;
-    const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
+    const int ntiles = tiles_i * tiles_j;
+    const int id = blockIdx.x, rest = id >> 3;
+    const int tile = rest % ntiles, blk = (rest / ntiles) * 8 + (id & 7);
+    const int ti = tile / tiles_j, tj = tile % tiles_j;
     const int i0 = ti * kTile, j0 = tj * kTile;
-    if ((int)blockIdx.x >= J.nblk || i0 >= J.m || j0 >= J.k) return;
+    if (blk >= J.nblk || i0 >= J.m || j0 >= J.k) return;
     double acc[kTile][kTile];
 #pragma unroll
     for (int a = 0; a < kTile; ++a)
@@ -384,7 +415,7 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
     const gdouble *A = gptr(J.A), *B = gptr(J.B);
     const int na = __builtin_amdgcn_readfirstlane(min(kTile, J.m - i0));
     const int nb = __builtin_amdgcn_readfirstlane(min(kTile, J.k - j0));
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)J.nblk * blockDim.x) {
+    for (int64_t t = (int64_t)blk * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)J.nblk * blockDim.x) {
         double av[kTile], bv[kTile];
 #pragma unroll
         for (int b = 0; b < kTile; ++b) bv[b] = b < nb ? B[(int64_t)(j0 + b) * J.ldb + t] : 0.0;
@@ -397,19 +428,19 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
     }
     __shared__ double red[4][kTile * kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    static_assert(kTile * kTile == 64, "one accumulator per lane after the transpose sum");
+    double v[64];
 #pragma unroll
     for (int a = 0; a < kTile; ++a)
 #pragma unroll
-        for (int b = 0; b < kTile; ++b) {
-            double v = acc[a][b];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wave][a * kTile + b] = v;
-        }
+        for (int b = 0; b < kTile; ++b) v[a * kTile + b] = acc[a][b];
+    wave_transpose_sum64(v, lane);
+    red[wave][lane] = v[0];
     __syncthreads();
     if (threadIdx.x < kTile * kTile) {
         const int a = threadIdx.x / kTile, b = threadIdx.x % kTile;
-        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        if (i0 + a < J.m && j0 + b < J.k) J.partial[((int64_t)blockIdx.x * J.m + i0 + a) * J.k + j0 + b] = v;
+        const double r = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        if (i0 + a < J.m && j0 + b < J.k) J.partial[((int64_t)blk * J.m + i0 + a) * J.k + j0 + b] = r;
     }
 }
 
@@ -998,7 +1029,7 @@ static isci_status launch_bdots(const BDot *d, const std::vector<BDot> &h, hipSt
         tj = std::max(tj, (j.k + kTile - 1) / kTile);
         mk = std::max(mk, j.m * j.k);
     }
-    k_bdots<<<dim3(gx, ti * tj, (unsigned)h.size()), 256, 0, s>>>(d, tj);
+    k_bdots<<<dim3((unsigned)(((gx + 7) / 8) * 8 * ti * tj), 1, (unsigned)h.size()), 256, 0, s>>>(d, ti, tj);
     k_bdots_reduce<<<dim3((mk + 3) / 4, 1, (unsigned)h.size()), 256, 0, s>>>(d);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
