@@ -53,9 +53,9 @@ __device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; 
 // to none were zeroed when T was allocated.  Vectors v >= nv write zeros.
 __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const double *__restrict__ c, int64_t ldc)
 {
-    const int ia = blockIdx.x;
-    const int jb = blockIdx.y * 256 + threadIdx.x;
-    const int len = A.sb.le[A.L - A.alev[ia]];
+    int ia, j0, len;
+    row_block(A, blockIdx.x, ia, j0, len);
+    const int jb = j0 + threadIdx.x;
     if (jb >= len) return;
     const int nb = A.nblk;
     const uint32_t as = A.astr[ia], bs = A.bstr[jb];
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
 __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds,
                                                  int accumulate)
 {
-    const int ia = blockIdx.x;
-    const int jb = blockIdx.y * 256 + threadIdx.x;
-    const int len = A.sb.le[A.L - A.alev[ia]];
+    int ia, j0, len;
+    row_block(A, blockIdx.x, ia, j0, len);
+    const int jb = j0 + threadIdx.x;
     if (jb >= len) return;
     const int nb = A.nblk;
     const uint32_t as = A.astr[ia], bs = A.bstr[jb];
@@ -236,8 +236,7 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     A.abx_S = Sbuf;
     if (cx->abx_ntrow > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
-        k_ab_unfold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(A, nv, c,
-                                                                                                          ldc);
+        k_ab_unfold<<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, false, st));
     }
     if (cx->abx_nrows > 0) {
@@ -255,8 +254,7 @@ isci_status launch_ab_fold(const isci_ctx *cx, int nv, const double *Sbuf, doubl
     SigmaArgs A = sigma_args(cx);
     A.abx_S = const_cast<double *>(Sbuf);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));
-    k_ab_fold<<<dim3((unsigned)cx->sa.nstr, (unsigned)((cx->max_rowlen + 255) / 256)), 256, 0, st>>>(
-        A, nv, s, lds, accumulate ? 1 : 0);
+    k_ab_fold<<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, false, st));
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;

@@ -150,6 +150,29 @@ struct SigmaArgs {
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };
 
+// Workgroup b of a launch over the determinant rows that starts no empty
+// workgroup: the alpha strings of level k (contiguous from sa.lev_off[k])
+// hold sb.le[L - k] beta targets each, in ceil(len / 256) workgroups of
+// 256.  Gives the row ia, its first target j0 and its length; the level
+// walk is uniform and reads only kernel arguments.  The launch has one
+// workgroup per 256 targets of each row (isci_ctx::nplan in all).
+__device__ __forceinline__ void row_block(const SigmaArgs &A, int b, int &ia, int &j0, int &len)
+{
+    for (int k = 0;; ++k) {
+        const int nr = A.sa.lev_off[k + 1] - A.sa.lev_off[k];
+        const int l = A.sb.le[A.L - k];
+        const int nbk = (l + 255) >> 8;
+        if (b < nr * nbk || k >= A.sa.maxlev) {
+            const int r = b / nbk;
+            ia = A.sa.lev_off[k] + r;
+            j0 = (b - r * nbk) << 8;
+            len = l;
+            return;
+        }
+        b -= nr * nbk;
+    }
+}
+
 // One sigma job of a fused multi-instance launch: instance `inst`, nv (<= 8)
 // vectors at c / s with leading dimensions ldc / lds; its work items are
 // plan[0..nitems) of the instance (one alpha row, 256 beta targets each)

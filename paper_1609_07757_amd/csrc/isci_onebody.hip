@@ -548,7 +548,7 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
 
 // ---------------------------------------------------------------------------
 // Alpha class above 80 orbitals, where the pair blocks of the kernels above
-// no longer fit LDS: spectator x = blockIdx.x, beta columns blockIdx.y * 64
+// no longer fit LDS: spectator x = x0 + blockIdx.x, beta columns blockIdx.y * 64
 // + [0, 64) (four 16-column N tiles), vector blockIdx.z; wave w forms the
 // targets a in [16 w, 16 w + 16) with a > x (up = 1) or a < x (up = 0),
 //   U[a][x][j] = sum_q h_aq T_j[q][x],
@@ -564,10 +564,10 @@ template <int NT>
 __global__ __launch_bounds__(64 * NT) void k_ob_alpha_spec(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                            double *__restrict__ sg, int64_t lds,
                                                            const double *__restrict__ hs, int up, int jlim_occ,
-                                                           int jlim_virt)
+                                                           int jlim_virt, int x0)
 {
     constexpr int NP = 16 * NT;
-    const int x = blockIdx.x, v = blockIdx.z;
+    const int x = x0 + blockIdx.x, v = blockIdx.z;
     const int norb = A.norb;
     const int jlim = x < 2 ? jlim_occ : jlim_virt;
     const int j0 = blockIdx.y * 64;
@@ -691,9 +691,16 @@ static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv,
     const int jlim_occ = le_b[L];
     const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
     const int jtail = L >= 1 ? le_b[L - 1] : 0;
-    const dim3 ga((unsigned)cx->norb, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
-    for (int up = 1; up >= 0; --up)
-        k_ob_alpha_spec<NT><<<ga, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt);
+    // occupied spectators (x < 2) span jlim_occ columns, virtual ones only
+    // jlim_virt: one grid each, so no workgroup is launched past its row
+    const int nocc = std::min(2, cx->norb);
+    const dim3 go((unsigned)nocc, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
+    const dim3 gv((unsigned)(cx->norb - nocc), (unsigned)((jlim_virt + 63) / 64), (unsigned)nv);
+    for (int up = 1; up >= 0; --up) {
+        k_ob_alpha_spec<NT><<<go, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, 0);
+        if (gv.x > 0 && gv.y > 0)
+            k_ob_alpha_spec<NT><<<gv, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
+    }
     if (jtail > jlim_virt && cx->norb > 2)
         k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
                           0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);

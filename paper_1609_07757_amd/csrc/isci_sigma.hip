@@ -510,14 +510,18 @@ template <int NV>
 __global__ __launch_bounds__(256) void k_sigma_n2(SigmaArgs A, int nv, const double *__restrict__ c,
                                                   int64_t ldc, double *__restrict__ sg, int64_t lds)
 {
-    sigma_target_n2<NV>(A, blockIdx.x, blockIdx.y * blockDim.x + threadIdx.x, nv, c, ldc, sg, lds);
+    int ia, j0, len;
+    row_block(A, blockIdx.x, ia, j0, len);
+    sigma_target_n2<NV>(A, ia, j0 + threadIdx.x, nv, c, ldc, sg, lds);
 }
 
 template <int NV>
 __global__ __launch_bounds__(256) void k_sigma_generic(SigmaArgs A, int nv, const double *__restrict__ c,
                                                        int64_t ldc, double *__restrict__ sg, int64_t lds)
 {
-    sigma_target<NV>(A, blockIdx.x, blockIdx.y * blockDim.x + threadIdx.x, nv, c, ldc, sg, lds);
+    int ia, j0, len;
+    row_block(A, blockIdx.x, ia, j0, len);
+    sigma_target<NV>(A, ia, j0 + threadIdx.x, nv, c, ldc, sg, lds);
 }
 
 // Fused sigma over many instances: a persistent grid walks the global
@@ -544,10 +548,9 @@ __global__ __launch_bounds__(256) void k_sigma_batched(const SigmaArgs *__restri
 // diagonal of H_tau: kept diagonal units
 __global__ __launch_bounds__(256) void k_diag(SigmaArgs A, double *__restrict__ out)
 {
-    const int ia = blockIdx.x;
-    const int la = A.alev[ia];
-    const int rlen = A.sb.le[A.L - la];
-    const int ib = blockIdx.y * blockDim.x + threadIdx.x;
+    int ia, j0, rlen;
+    row_block(A, blockIdx.x, ia, j0, rlen);
+    const int ib = j0 + threadIdx.x;
     if (ib >= rlen) return;
     const int na = A.sa.n, nb = A.sb.n, n = A.norb;
     int ao[ISCI_MAXN], bo[ISCI_MAXN];
@@ -570,7 +573,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                          hipStream_t s)
 {
     const SigmaArgs A = sigma_args(c);
-    const dim3 grid((unsigned)c->sa.nstr, (unsigned)((c->max_rowlen + 255) / 256));
+    const dim3 grid((unsigned)c->nplan);
     for (int v0 = 0; v0 < nvec; v0 += 8) {
         const int nv = nvec - v0 < 8 ? nvec - v0 : 8;
         const double *cc = cv + (int64_t)v0 * ldc;
@@ -697,7 +700,7 @@ isci_status launch_sigma_batched(const SigmaArgs *args_dev, const BatchVec *vecs
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s)
 {
     const SigmaArgs A = sigma_args(c);
-    const dim3 grid((unsigned)c->sa.nstr, (unsigned)((c->max_rowlen + 255) / 256));
+    const dim3 grid((unsigned)c->nplan);
     k_diag<<<grid, 256, 0, s>>>(A, diag);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
