@@ -678,17 +678,78 @@ __global__ __launch_bounds__(256) void k_ob_alpha_tail(SigmaArgs A, const double
     if (j < l1) sv[b1 + j] += hs[norb] * c0 + hs[norb + 1] * c1;
 }
 
+// Alpha class, the columns j in [j0, j1) of the reference row {0, 1} past
+// the rows of level one (only the reference row reaches them; both
+// spectators x = 0, 1 map it onto itself):
+//   sigma({0,1}, j) += (h_00 + h_11) c({0,1}, j).
+__global__ __launch_bounds__(256) void k_ob_alpha_reftail(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                          double *__restrict__ sg, int64_t lds,
+                                                          const double *__restrict__ hs, int j0, int j1)
+{
+    const int j = j0 + blockIdx.x * 256 + threadIdx.x, v = blockIdx.y;
+    const int norb = A.norb;
+    const long long b = A.arow_base[1];   // row {0, 1} (spectator 0, active 1)
+    const int l = A.arow_len[1];
+    if (j >= j1 || j >= l || b < 0) return;
+    sg[(int64_t)v * lds + b + j] += (hs[0] + hs[norb + 1]) * c[(int64_t)v * ldc + b + j];
+}
+
+// Alpha class for virtual spectators whose rows hold at most kObNarrow
+// columns (CISD: the reference beta string only), where a 64-column
+// matrix-core tile would be almost all padding.  Workgroup (x, vector):
+// T[q][j] = sgn(q - x) c({q,x}, j) for all q staged in LDS, then thread a
+// forms U[a][j] = sum_q h_qa T[q][j] and adds sgn(a - x) U[a][j] to
+// sigma({a,x}, j) for the targets on one side of x (up: a > x), so each
+// row is written by one workgroup per launch.
+constexpr int kObNarrow = 8;
+__global__ __launch_bounds__(256) void k_ob_alpha_narrow(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                         double *__restrict__ sg, int64_t lds,
+                                                         const double *__restrict__ hs, int up, int jlim, int x0)
+{
+    const int x = x0 + blockIdx.x, v = blockIdx.y;
+    const int norb = A.norb;
+    __shared__ double tq[256 * kObNarrow];
+    const double *cv = c + (int64_t)v * ldc;
+    for (int t = threadIdx.x; t < norb * kObNarrow; t += blockDim.x) {
+        const int q = t / kObNarrow, j = t % kObNarrow;
+        const long long base = A.arow_base[x * norb + q];
+        const int len = min(A.arow_len[x * norb + q], jlim);
+        tq[t] = (q != x && base >= 0 && j < len) ? (q < x ? 1.0 : -1.0) * cv[base + j] : 0.0;
+    }
+    __syncthreads();
+    double *sv = sg + (int64_t)v * lds;
+    for (int a = threadIdx.x; a < norb; a += blockDim.x) {
+        if (a == x || (a > x) != (up != 0)) continue;
+        const long long base = A.arow_base[x * norb + a];
+        if (base < 0) continue;
+        const int len = min(A.arow_len[x * norb + a], jlim);
+        double u[kObNarrow];
+#pragma unroll
+        for (int j = 0; j < kObNarrow; ++j) u[j] = 0.0;
+        for (int q = 0; q < norb; ++q) {
+            const double hv = hs[q * norb + a];
+#pragma unroll
+            for (int j = 0; j < kObNarrow; ++j) u[j] += hv * tq[q * kObNarrow + j];
+        }
+#pragma unroll
+        for (int j = 0; j < kObNarrow; ++j)
+            if (j < len) sv[base + j] += a < x ? u[j] : -u[j];
+    }
+}
+
 template <int NT>
 static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
                                  double *s, int64_t lds, hipStream_t st)
 {
     const double *hs = cx->d.hscreen;
     const int L = cx->L;
-    // rows {q, x} hold beta strings up to level L - level({q, x}); for x
-    // occupied every column reaches some row of level <= 1, for x virtual
-    // the columns above the level-2 row length only reach {0,x}, {1,x}
+    // rows {q, x} hold beta strings up to level L - level({q, x}): for x
+    // occupied the columns past the level-1 row length only reach the
+    // reference row (k_ob_alpha_reftail), for x virtual the columns past
+    // the level-2 row length only reach {0,x}, {1,x} (k_ob_alpha_tail)
     const int *le_b = cx->sb.le;
-    const int jlim_occ = le_b[L];
+    const int jlim_occ = L >= 1 ? le_b[L - 1] : le_b[L];
+    const int jref = le_b[L];
     const int jlim_virt = L >= 2 ? le_b[L - 2] : 0;
     const int jtail = L >= 1 ? le_b[L - 1] : 0;
     // occupied spectators (x < 2) span jlim_occ columns, virtual ones only
@@ -698,9 +759,17 @@ static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv,
     const dim3 gv((unsigned)(cx->norb - nocc), (unsigned)((jlim_virt + 63) / 64), (unsigned)nv);
     for (int up = 1; up >= 0; --up) {
         k_ob_alpha_spec<NT><<<go, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, 0);
-        if (gv.x > 0 && gv.y > 0)
-            k_ob_alpha_spec<NT><<<gv, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
+        if (gv.x > 0 && gv.y > 0) {
+            if (jlim_virt <= kObNarrow)
+                k_ob_alpha_narrow<<<dim3(gv.x, (unsigned)nv), 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_virt,
+                                                                           nocc);
+            else
+                k_ob_alpha_spec<NT><<<gv, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
+        }
     }
+    if (jref > jlim_occ && cx->norb >= 2)
+        k_ob_alpha_reftail<<<dim3((unsigned)((jref - jlim_occ + 255) / 256), (unsigned)nv), 256, 0, st>>>(
+            A, c, ldc, s, lds, hs, jlim_occ, jref);
     if (jtail > jlim_virt && cx->norb > 2)
         k_ob_alpha_tail<<<dim3((unsigned)(cx->norb - 2), (unsigned)((jtail - jlim_virt + 255) / 256), (unsigned)nv), 256,
                           0, st>>>(A, c, ldc, s, lds, hs, jlim_virt, jtail);
