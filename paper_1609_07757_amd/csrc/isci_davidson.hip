@@ -500,8 +500,9 @@ __global__ __launch_bounds__(256) void k_blincomb(const BLin *__restrict__ jobs)
             Ys[e] = (b < kb && i < m) ? J.Y[(int64_t)(j0 + b) * m + i] : 0.0;
         }
     __syncthreads();
-    const gdouble *V = gptr(J.V), *Y = gptr(J.Y);
-    gdouble_w *out = gptr_w(J.out);
+    const gdouble *__restrict__ V = gptr(J.V);
+    const gdouble *__restrict__ Y = gptr(J.Y);
+    gdouble_w *__restrict__ out = gptr_w(J.out);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x) {
         double acc[kTile];
 #pragma unroll
@@ -544,17 +545,40 @@ struct BRes {              // residuals and Davidson corrections of one slot
     int k;
 };
 
+// Grid-stride element loops below take four elements per step, all loads
+// before any store, through restrict pointers: the loads of a step are in
+// flight together instead of one latency per element.
 __global__ void k_bresid(const BRes *__restrict__ jobs)
 {
     const BRes J = jobs[blockIdx.z];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x) {
-        const double d = J.D[t];
-        for (int j = 0; j < J.k; ++j) {
-            const double r = J.WY[(int64_t)j * J.ld + t] - J.theta[j] * J.X[(int64_t)j * J.ld + t];
-            J.WY[(int64_t)j * J.ld + t] = r;
-            double den = J.theta[j] - d;
-            if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
-            J.T[(int64_t)j * J.ld + t] = r / den;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x, n = J.n, ld = J.ld;
+    const int k = J.k;
+    const gdouble *__restrict__ X = gptr(J.X);
+    const gdouble *__restrict__ D = gptr(J.D);
+    gdouble_w *__restrict__ WY = gptr_w(J.WY);
+    gdouble_w *__restrict__ T = gptr_w(J.T);
+    for (int j = 0; j < k; ++j) {
+        const double th = J.theta[j];
+        const int64_t o = (int64_t)j * ld;
+        for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * st) {
+            double w[4], x[4], d[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t t = min(t0 + u * st, n - 1);
+                w[u] = WY[o + t];
+                x[u] = X[o + t];
+                d[u] = D[t];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t t = t0 + u * st;
+                if (t >= n) break;
+                const double r = w[u] - th * x[u];
+                double den = th - d[u];
+                if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+                WY[o + t] = r;
+                T[o + t] = r / den;
+            }
         }
     }
 }
@@ -570,8 +594,17 @@ struct BVecOp {            // copy src -> dst, or normalise dst (see k_bnormaliz
 __global__ void k_bcopy(const BVecOp *__restrict__ jobs)
 {
     const BVecOp J = jobs[blockIdx.z];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < J.n; t += (int64_t)gridDim.x * blockDim.x)
-        J.dst[t] = J.src[t];
+    const int64_t st = (int64_t)gridDim.x * blockDim.x, n = J.n;
+    const gdouble *__restrict__ src = gptr(J.src);
+    gdouble_w *__restrict__ dst = gptr_w(J.dst);
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * st) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[min(t0 + u * st, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u * st < n) dst[t0 + u * st] = v[u];
+    }
 }
 
 __global__ void k_bnormalize(const BVecOp *__restrict__ jobs, double rel)
