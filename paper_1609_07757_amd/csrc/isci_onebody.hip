@@ -605,42 +605,59 @@ __global__ __launch_bounds__(64 * NT) void k_ob_alpha_spec(SigmaArgs A, const do
         km &= km - 1;
         return k;
     };
-    // every lane loads from a valid address whatever the step (invalid
-    // operands are selected to zero afterwards)
-    auto load = [&](int ks, double &a, double *b) {
+    // every lane loads from a valid address whatever the step; the loaded
+    // values stay raw until their MFMAs, where invalid operands are zeroed,
+    // so waiting for one stage's loads never precedes the other stage's
+    // products (scheduling barriers keep the order)
+    struct Stage {
+        double a, b[4];
+        double f;       // sign of the source rows, 0 for an invalid step or row
+        bool aok;
+        int bmask;      // columns inside the source row
+    };
+    auto load = [&](int ks, Stage &S) {
         const int q = 4 * max(ks, 0) + kq;
         const int qc = min(q, norb - 1), ac = min(16 * mt + n, norb - 1);
-        const double hv = hs[qc * norb + ac];
-        a = (ks >= 0 && q < norb && 16 * mt + n < norb) ? hv : 0.0;
+        S.a = hs[qc * norb + ac];
+        S.aok = ks >= 0 && q < norb && 16 * mt + n < norb;
         const long long base = rb[qc];
         const int len = min(rl[qc], jlim);
         const bool rowok = ks >= 0 && q < norb && q != x && base >= 0;
-        const double f = q < x ? 1.0 : -1.0;
+        S.f = rowok ? (q < x ? 1.0 : -1.0) : 0.0;
+        int bm = 0;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int j = j0 + 16 * nt + n;
             const bool ok = rowok && j < len;
-            const double val = cv[ok ? base + j : 0];
-            b[nt] = ok ? f * val : 0.0;
+            bm |= ok ? 1 << nt : 0;
+            S.b[nt] = cv[ok ? base + j : 0];
         }
+        S.bmask = bm;
     };
     v4d_ob acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_ob{0.0, 0.0, 0.0, 0.0};
-    // two K steps in flight: stages x and y ping-pong (no register copies)
-    double ax, bx[4], ay, by[4];
-    int kx = next_ks();
-    load(kx, ax, bx);
-    while (kx >= 0) {
-        const int ky = next_ks();
-        load(ky, ay, by);
+    auto mma = [&](const Stage &S) {
+        const double a = S.aok ? S.a : 0.0;
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ax, bx[nt], acc[nt]);
-        if (ky < 0) break;
-        kx = next_ks();
-        load(kx, ax, bx);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(ay, by[nt], acc[nt]);
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, (S.bmask >> nt) & 1 ? S.f * S.b[nt] : 0.0, acc[nt]);
+    };
+    // two K steps in flight: stages x and y ping-pong over a counted loop
+    // with no exit between the halves (an odd count ends with a step of
+    // zero operands), so the stages keep their own registers
+    const int nk = __popcll(km);
+    Stage sx, sy;
+    load(next_ks(), sx);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int e = 0; e < nk; e += 2) {
+        load(next_ks(), sy);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(sx);
+        __builtin_amdgcn_sched_barrier(0);
+        load(next_ks(), sx);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(sy);
+        __builtin_amdgcn_sched_barrier(0);
     }
     double *sv = sg + (int64_t)v * lds;
 #pragma unroll
