@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=120, help="served mode: requests (of the 2000-request stream)")
     ap.add_argument("--max-wall", type=float, default=240.0, help="served mode: wall-clock cap (s)")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
+    ap.add_argument("--fast-dim", type=int, default=1_000_000,
+                    help="served mode: solves of at most this many determinants form the fast class (0: one class)")
+    ap.add_argument("--fast-share", type=float, default=0.75, help="served mode: GPU time share of the fast class")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sigma_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (optional)")
     return ap.parse_args()
@@ -338,7 +341,7 @@ def bench_served(a):
         def payload(W=W):
             return integrals_on_device(W.norb, W.box_len, W.n_aux, W.seed)
         reqs.append(Request(i, t, W.norb, 2, 2, W.level, W.tau, W.nroots, payload=payload))
-    ex = GpuExecutor()
+    ex = GpuExecutor(fast_dim=a.fast_dim, fast_share=a.fast_share)
     srv = Server(ex, hbm_budget=int(a.hbm_budget_gb * 2**30), max_slots=64)
     t0 = time.perf_counter()
     srv.run(reqs, max_wall=a.max_wall,
@@ -350,7 +353,8 @@ def bench_served(a):
            "value": rep.get("p50_s"), "unit": "s (p50 latency)", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64", "data": "synthetic (recipe A, per-request seeds, Poisson arrivals)",
            "config": {"workload": "served_poisson50", "requests_offered": len(reqs), "rate_per_s": 50,
-                      "tau": 1e-12, "hbm_budget_gb": a.hbm_budget_gb},
+                      "tau": 1e-12, "hbm_budget_gb": a.hbm_budget_gb,
+                      "fast_class_dim": a.fast_dim, "fast_class_share": a.fast_share},
            "p50_s": rep.get("p50_s"), "p99_s": rep.get("p99_s"), "served": rep["served"],
            "rejected": rep["rejected"], "wall_s": wall, "sigma_vectors_per_s": ex.sigma_vectors / wall,
            "peak_concurrent": rep["peak_running"], "peak_bytes": rep["peak_bytes"],

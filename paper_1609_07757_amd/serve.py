@@ -207,16 +207,28 @@ class Server:
 class GpuExecutor:
     """Runs requests on the HIP library: integrals are produced on the
     device by `payload` (a callable returning (h, eri) CUDA tensors), the
-    handle is built, the dense eri is dropped, and the solve joins the
-    engine.  Footprint = transient eri + handle tables (bound) + subspace."""
+    handle is built, the dense eri is dropped, and the solve joins an
+    engine.  Footprint = transient eri + handle tables (bound) + subspace.
 
-    def __init__(self, davidson_opts=None, stream=None):
+    Two size classes, each in its own engine: solves of at most `fast_dim`
+    determinants and the rest.  An engine step advances every solve of one
+    class by one iteration, and the classes share the GPU by time: the fast
+    class is stepped while its accumulated step time is below `fast_share`
+    of the total, so small solves are not held to the pace of the largest
+    ones (a size-based scheduling policy; each solve's arithmetic is the
+    same in either class).  fast_dim = 0 puts every solve in one engine."""
+
+    def __init__(self, davidson_opts=None, stream=None, fast_dim: int = 1_000_000, fast_share: float = 0.75):
         import paper_1609_07757_amd as isci
         self.isci = isci
-        self.eng = isci.isci_engine_create(stream)
+        self.engs = [isci.isci_engine_create(stream), isci.isci_engine_create(stream)]
         self.opts = davidson_opts or {}
+        self.fast_dim = int(fast_dim)
+        self.fast_share = float(fast_share)
         self.sigma_vectors = 0
         self.handles = {}
+        self.active = [0, 0]
+        self.tclass = [0.0, 0.0]
 
     def footprint(self, r: Request) -> int:
         dim = ci_dim(r.norb, r.nalpha, r.nbeta, r.level)
@@ -226,23 +238,43 @@ class GpuExecutor:
         h, eri = r.payload()
         hd = self.isci.isci_create(h, eri, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
         del h, eri
-        slot = self.isci.isci_engine_add(self.eng, hd, nroots=r.nroots, **self.opts)
-        self.handles[slot] = hd
-        return slot
+        cls = 0 if hd.dim <= self.fast_dim else 1
+        slot = self.isci.isci_engine_add(self.engs[cls], hd, nroots=r.nroots, **self.opts)
+        tok = (cls, slot)
+        self.handles[tok] = hd
+        self.active[cls] += 1
+        return tok
 
     def step(self) -> int:
-        return self.isci.isci_engine_step(self.eng)
+        """One engine step of the class that is behind its time share (the
+        other class when one is empty); returns the number of solves it
+        advanced."""
+        if self.active[0] and self.active[1]:
+            tot = self.tclass[0] + self.tclass[1]
+            cls = 0 if self.tclass[0] <= self.fast_share * tot else 1
+        else:
+            cls = 0 if self.active[0] else 1
+        t0 = time.perf_counter()
+        n = self.isci.isci_engine_step(self.engs[cls])
+        self.tclass[cls] += time.perf_counter() - t0
+        return n
 
-    def poll(self, slot):
-        done, en, _, info = self.isci.isci_engine_result(self.eng, slot)
+    def poll(self, tok):
+        cls, slot = tok
+        done, en, _, info = self.isci.isci_engine_result(self.engs[cls], slot)
         if done:
             self.sigma_vectors += info["sigma_calls"]
         return done, en, info
 
-    def finish(self, slot):
-        self.isci.isci_engine_release(self.eng, slot)
-        hd = self.handles.pop(slot)
+    def finish(self, tok):
+        cls, slot = tok
+        self.isci.isci_engine_release(self.engs[cls], slot)
+        hd = self.handles.pop(tok)
         hd.destroy()
+        self.active[cls] -= 1
+        if not self.active[cls]:
+            self.tclass = [0.0, 0.0]   # a new mix starts its share afresh
 
     def close(self):
-        self.eng.destroy()
+        for e in self.engs:
+            e.destroy()

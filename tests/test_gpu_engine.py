@@ -118,3 +118,30 @@ def test_python_footprint_model_matches_library():
         _, _, hd = _make(case, 2)
         for k in (1, 2, 4):
             assert davidson_bytes(hd.dim, k) == isci.isci_davidson_footprint(hd, k)
+
+
+def test_two_class_server_same_energies():
+    """The GPU executor's two size classes (separate engines, stepped by
+    time share): every solve gives the energies it gives alone, bit for
+    bit, whichever class it ran in."""
+    import paper_1609_07757_amd as isci
+    from paper_1609_07757_amd.serve import GpuExecutor, Request, Server
+    torch, dev = torch_dev()
+    alone, reqs = [], []
+    for i, case in enumerate(MIX):
+        h, eri, hd = _make(case, 90 + i)
+        alone.append(isci.isci_davidson(hd, nroots=case[4])[0])
+        hd.destroy()
+        recipe, norb, L, tau, nroots = case
+
+        def payload(h=h, eri=eri):
+            return (torch.from_numpy(np.ascontiguousarray(h)).to(dev),
+                    torch.from_numpy(np.ascontiguousarray(eri)).to(dev))
+        reqs.append(Request(i, 0.01 * i, norb, 2, 2, L, tau, nroots, payload=payload))
+    ex = GpuExecutor(fast_dim=300)
+    srv = Server(ex, hbm_budget=8 << 30, max_slots=8)
+    done = srv.run(reqs, max_wall=120.0)
+    assert sorted(r.rid for r in done if r.status == "done") == list(range(len(MIX)))
+    for r in done:
+        assert np.array_equal(np.asarray(r.energies), np.asarray(alone[r.rid])), r.rid
+    ex.close()
