@@ -828,36 +828,59 @@ isci_status launch_onebody_alpha_large(const isci_ctx *cx, int nv, const double 
 // alpha string), with the same row tables.  Row i holds the columns
 // j < len(i), and len does not grow with i, so a 32 x 32 tile of the
 // (row, column) square is empty when its first column lies past its first
-// row's length.  A workgroup moves one tile of one vector through LDS
-// (coalesced on both sides):
+// row's length.  A workgroup moves one tile through LDS
+// for every vector (coalesced on both sides):
 //   add = 0: dst[row a][col b]  = src[row b][col a]
 //   add = 1: dst[row a][col b] += src[row b][col a]
 // for src rows b in [32 (bt0 + blockIdx.y), +32), columns a in
 // [32 blockIdx.x, +32).
 __global__ __launch_bounds__(256) void k_det_transpose(SigmaArgs A, const double *__restrict__ src, int64_t lsrc,
-                                                       double *__restrict__ dst, int64_t ldst, int add, int bt0)
+                                                       double *__restrict__ dst, int64_t ldst, int add, int bt0,
+                                                       int nv)
 {
-    const int b0 = (bt0 + blockIdx.y) * 32, a0 = blockIdx.x * 32, v = blockIdx.z;
+    const int b0 = (bt0 + blockIdx.y) * 32, a0 = blockIdx.x * 32;
     const int n = A.sa.nstr, L = A.L;
     // tile rows of src are b, columns a: empty when a0 >= len(b0)
     if (b0 >= n || a0 >= A.sb.le[L - A.alev[b0]]) return;
-    __shared__ double tile[32][33];
-    const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;
-    const double *s = src + (int64_t)v * lsrc;
-    double *d = dst + (int64_t)v * ldst;
-#pragma unroll
-    for (int r = ry; r < 32; r += 8) {
-        const int b = b0 + r, a = a0 + cx;
-        const bool ok = b < n && a < A.sb.le[L - A.alev[min(b, n - 1)]];
-        tile[r][cx] = ok ? s[A.rowstart[min(b, n - 1)] + (ok ? a : 0)] : 0.0;
+    __shared__ double tile[4][32][33];
+    // row starts and lengths of the tile's 32 source rows b and 32 target
+    // rows a, read once: the element loads then depend on LDS only
+    __shared__ long long rsb[32], rsa[32];
+    __shared__ int lnb[32], lna[32];
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x & 31, r = (threadIdx.x < 32 ? b0 : a0) + t;
+        const long long rs = r < n ? A.rowstart[r] : 0;
+        const int ln = r < n ? A.sb.le[L - A.alev[r]] : 0;
+        if (threadIdx.x < 32) { rsb[t] = rs; lnb[t] = ln; } else { rsa[t] = rs; lna[t] = ln; }
     }
     __syncthreads();
+    const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;
+    // all vectors' loads before the LDS writes
+    double val[4][4];
 #pragma unroll
-    for (int r = ry; r < 32; r += 8) {
-        const int a = a0 + r, b = b0 + cx;
-        if (a < n && b < A.sb.le[L - A.alev[a]]) {
-            double *o = d + A.rowstart[a] + b;
-            *o = add ? *o + tile[cx][r] : tile[cx][r];
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = ry + 8 * i, a = a0 + cx;
+            const bool ok = v < nv && a < lnb[r];
+            val[v][i] = ok ? src[(int64_t)v * lsrc + rsb[r] + a] : 0.0;
+        }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[v][ry + 8 * i][cx] = val[v][i];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (v >= nv) break;
+        double *d = dst + (int64_t)v * ldst;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = ry + 8 * i, b = b0 + cx;
+            if (b < lna[r]) {
+                double *o = d + rsa[r] + b;
+                *o = add ? *o + tile[v][cx][r] : tile[v][cx][r];
+            }
         }
     }
 }
@@ -885,8 +908,8 @@ isci_status launch_onebody_beta_large(const isci_ctx *cx, int nv, const double *
             const int len0 = cx->sb.le[cx->L - cx->h_alev[32 * t0]];
             int t1 = t0 + 1;
             while (t1 < nt && cx->sb.le[cx->L - cx->h_alev[32 * t1]] == len0) ++t1;
-            k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0), (unsigned)nv), 256, 0, st>>>(
-                A, src, lsrc, dst, ldst, add, t0);
+            k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0)), 256, 0, st>>>(
+                A, src, lsrc, dst, ldst, add, t0, nv);
             t0 = t1;
         }
     };
