@@ -744,7 +744,7 @@ static isci_status cgs2_enqueue(Slot *sl, const double *src, int pos, hipStream_
     return ISCI_OK;
 }
 
-// After the enqueued appends of this round (count n, first at basis index
+// After the enqueued appends of this call (count n, first at basis index
 // m0) completed: drop the vectors whose factor is 0 by moving later ones
 // into their place.
 static isci_status cgs2_finish(Slot *sl, int m0, int n, hipStream_t s)
