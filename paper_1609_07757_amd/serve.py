@@ -204,6 +204,15 @@ class Server:
         return out
 
 
+def pick_class(active, tclass, share: float) -> int:
+    """Class to step next: with solves in both classes, the fast class (0)
+    while its accumulated step time is at most `share` of the total, else
+    the slow class (1); with one class busy, that class."""
+    if active[0] and active[1]:
+        return 0 if tclass[0] <= share * (tclass[0] + tclass[1]) else 1
+    return 0 if active[0] else 1
+
+
 class GpuExecutor:
     """Runs requests on the HIP library: integrals are produced on the
     device by `payload` (a callable returning (h, eri) CUDA tensors), the
@@ -249,11 +258,7 @@ class GpuExecutor:
         """One engine step of the class that is behind its time share (the
         other class when one is empty); returns the number of solves it
         advanced."""
-        if self.active[0] and self.active[1]:
-            tot = self.tclass[0] + self.tclass[1]
-            cls = 0 if self.tclass[0] <= self.fast_share * tot else 1
-        else:
-            cls = 0 if self.active[0] else 1
+        cls = pick_class(self.active, self.tclass, self.fast_share)
         t0 = time.perf_counter()
         n = self.isci.isci_engine_step(self.engs[cls])
         self.tclass[cls] += time.perf_counter() - t0

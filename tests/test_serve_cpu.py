@@ -140,3 +140,19 @@ def test_footprint_model():
     b4 = davidson_bytes(1000, 4)
     assert 0 < b1 < b4
     assert davidson_bytes(10**6, 1) >= 8 * 10**6 * 32
+
+
+def test_size_class_time_share():
+    """The executor's class choice gives the fast class its share of step
+    time while both classes have solves, and the busy class otherwise."""
+    from paper_1609_07757_amd.serve import pick_class
+    assert pick_class([1, 0], [0.0, 0.0], 0.75) == 0
+    assert pick_class([0, 3], [5.0, 0.0], 0.75) == 1
+    # simulated steps: fast steps cost 1, slow steps cost 10
+    active, t, n = [4, 2], [0.0, 0.0], [0, 0]
+    for _ in range(4000):
+        c = pick_class(active, t, 0.75)
+        t[c] += 1.0 if c == 0 else 10.0
+        n[c] += 1
+    assert abs(t[0] / (t[0] + t[1]) - 0.75) < 0.01
+    assert n[0] > 25 * n[1]
