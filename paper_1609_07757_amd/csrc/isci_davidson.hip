@@ -547,7 +547,8 @@ struct BRes {              // residuals and Davidson corrections of one slot
 
 // Grid-stride element loops below take four elements per step, all loads
 // before any store, through restrict pointers: the loads of a step are in
-// flight together instead of one latency per element.
+// flight together instead of one latency per element.  Loads past the end
+// are masked off, not clamped, so short vectors issue no extra traffic.
 __global__ void k_bresid(const BRes *__restrict__ jobs)
 {
     const BRes J = jobs[blockIdx.z];
@@ -557,17 +558,19 @@ __global__ void k_bresid(const BRes *__restrict__ jobs)
     const gdouble *__restrict__ D = gptr(J.D);
     gdouble_w *__restrict__ WY = gptr_w(J.WY);
     gdouble_w *__restrict__ T = gptr_w(J.T);
-    for (int j = 0; j < k; ++j) {
-        const double th = J.theta[j];
-        const int64_t o = (int64_t)j * ld;
-        for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * st) {
-            double w[4], x[4], d[4];
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * st) {
+        double d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = t0 + u * st < n ? D[t0 + u * st] : 0.0;
+        for (int j = 0; j < k; ++j) {
+            const double th = J.theta[j];
+            const int64_t o = (int64_t)j * ld;
+            double w[4], x[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t t = min(t0 + u * st, n - 1);
-                w[u] = WY[o + t];
-                x[u] = X[o + t];
-                d[u] = D[t];
+                const int64_t t = t0 + u * st;
+                w[u] = t < n ? WY[o + t] : 0.0;
+                x[u] = t < n ? X[o + t] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -600,7 +603,7 @@ __global__ void k_bcopy(const BVecOp *__restrict__ jobs)
     for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * st) {
         double v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = src[min(t0 + u * st, n - 1)];
+        for (int u = 0; u < 4; ++u) v[u] = t0 + u * st < n ? src[t0 + u * st] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (t0 + u * st < n) dst[t0 + u * st] = v[u];
