@@ -488,7 +488,9 @@ __global__ __launch_bounds__(256) void k_blincomb(const BLin *__restrict__ jobs)
 {
     const BLin J = jobs[blockIdx.z];
     const int j0 = blockIdx.y * kTile;
-    if (j0 >= J.k || (J.skip && *J.skip != 0.0)) return;
+    // the grid is sized for the longest job: workgroups past this job's
+    // elements leave before staging the coefficients
+    if (j0 >= J.k || (int64_t)blockIdx.x * blockDim.x >= J.n || (J.skip && *J.skip != 0.0)) return;
     const int m = J.m, kb = min(kTile, J.k - j0);
     // this block's coefficients Y[(j0 + b) m + i] in LDS as Ys[i][b] (zero
     // for b >= kb and for the eight rows past m), read back as broadcasts
