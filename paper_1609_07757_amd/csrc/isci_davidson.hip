@@ -13,8 +13,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -663,6 +667,75 @@ static int64_t slot_bytes(int64_t dim, int k, const isci_davidson_opts &o, int *
     return b;
 }
 
+// Host worker threads kept for an engine's life: run(count, f) calls f(j)
+// for j in [0, count) on the workers and the calling thread and returns
+// when all calls have finished (the per-step projected eigenproblems).
+class HostPool {
+  public:
+    explicit HostPool(int nworkers)
+    {
+        for (int t = 0; t < nworkers; ++t) th_.emplace_back([this]() { loop(); });
+    }
+    ~HostPool()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (std::thread &t : th_) t.join();
+    }
+    void run(int count, const std::function<void(int)> &f)
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            fn_ = &f;
+            total_ = count;
+            next_.store(0);
+            left_ = count;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> g(mu_);
+        done_.wait(g, [this]() { return left_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    void work()
+    {
+        for (;;) {
+            const int j = next_.fetch_add(1);
+            if (j >= total_) return;
+            (*fn_)(j);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--left_ == 0) done_.notify_all();
+        }
+    }
+    void loop()
+    {
+        long seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&]() { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            work();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *fn_ = nullptr;
+    std::atomic<int> next_{0};
+    int total_ = 0, left_ = 0;
+    long gen_ = 0;
+    bool stop_ = false;
+};
+
 }  // namespace isci
 
 struct isci_engine_s {
@@ -687,6 +760,7 @@ struct isci_engine_s {
     // priority), forked from and joined back into s with events
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_ev;   // [0]: fork, [1 + i]: join of side[i]
+    isci::HostPool *pool = nullptr;    // created on the first step with many slots
 };
 
 namespace isci {
@@ -1203,18 +1277,14 @@ static isci_status engine_step(isci_engine e, int *nactive)
             for (int q = 0; q < m; ++q) Gm[(size_t)i * m + q] = sl->G[(size_t)i * mmax + q];
         if (!tridiag_eigh(m, Gm, sl->evals, sl->Z)) jacobi_eigh(m, Gm, sl->evals, sl->Z);
     };
-    {
-        const int nth = std::min<int>(na / 4, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
-        if (nth > 1) {
-            std::vector<std::thread> pool;
-            for (int t = 0; t < nth; ++t)
-                pool.emplace_back([&, t]() {
-                    for (int j = t; j < na; j += nth) project(j);
-                });
-            for (std::thread &th : pool) th.join();
-        } else {
-            for (int j = 0; j < na; ++j) project(j);
+    if (na >= 8) {
+        if (!e->pool) {
+            const int hw = (int)std::max(2u, std::thread::hardware_concurrency());
+            e->pool = new HostPool(std::min(15, hw - 1));
         }
+        e->pool->run(na, project);
+    } else {
+        for (int j = 0; j < na; ++j) project(j);
     }
     for (int j = 0; j < na; ++j) {
         Slot *sl = act[j];
@@ -1629,6 +1699,7 @@ void isci_engine_destroy(isci_engine e)
 {
     if (!e) return;
     (void)hipStreamSynchronize(e->s);
+    delete e->pool;
     for (Slot *sl : e->slots) slot_free(sl);
     if (e->d_args) (void)hipFree(e->d_args);
     if (e->h_args) (void)hipHostFree(e->h_args);
