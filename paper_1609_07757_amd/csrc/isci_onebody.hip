@@ -549,8 +549,10 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
 // ---------------------------------------------------------------------------
 // Alpha class above 80 orbitals, where the pair blocks of the kernels above
 // no longer fit LDS: spectator x = x0 + blockIdx.x, beta columns blockIdx.y * 64
-// + [0, 64) (four 16-column N tiles), vector blockIdx.z; wave w forms the
-// targets a in [16 w, 16 w + 16) with a > x (up = 1) or a < x (up = 0),
+// + [0, 64) (four 16-column N tiles), vector blockIdx.z / NG and target
+// group blockIdx.z % NG (NG groups of four 16-target tiles: four-wave
+// workgroups whatever norb); wave w forms the targets a in [16 mt, 16 mt +
+// 16), mt = 4 group + w, with a > x (up = 1) or a < x (up = 0),
 //   U[a][x][j] = sum_q h_aq T_j[q][x],
 // with the B operand read straight from the rows {q, x} (coalesced).  One
 // side of x per launch, so each sigma row is written by one workgroup per
@@ -561,13 +563,13 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
 // operands of the next K step are in flight while the MFMAs of the current
 // one issue.
 template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_ob_alpha_spec(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+__global__ __launch_bounds__(256) void k_ob_alpha_spec(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                            double *__restrict__ sg, int64_t lds,
                                                            const double *__restrict__ hs, int up, int jlim_occ,
                                                            int jlim_virt, int x0)
 {
-    constexpr int NP = 16 * NT;
-    const int x = x0 + blockIdx.x, v = blockIdx.z;
+    constexpr int NP = 16 * NT, NG = (NT + 3) / 4;
+    const int x = x0 + blockIdx.x, v = blockIdx.z / NG, grp = blockIdx.z % NG;
     const int norb = A.norb;
     const int jlim = x < 2 ? jlim_occ : jlim_virt;
     const int j0 = blockIdx.y * 64;
@@ -576,12 +578,12 @@ __global__ __launch_bounds__(64 * NT) void k_ob_alpha_spec(SigmaArgs A, const do
     // depend on no other global load
     __shared__ long long rb[NP];
     __shared__ int rl[NP];
-    for (int t = threadIdx.x; t < NP; t += 64 * NT) {
+    for (int t = threadIdx.x; t < NP; t += 256) {
         rb[t] = t < norb ? A.arow_base[x * norb + t] : -1;
         rl[t] = t < norb ? A.arow_len[x * norb + t] : 0;
     }
     __syncthreads();
-    const int mt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int mt = 4 * grp + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     // this wave's targets {a, x} on the requested side of x that hold a
     // column of the block, and the K steps whose sources {q, x} hold one
     const int at = 16 * mt + (lane & 15);
@@ -772,16 +774,17 @@ static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv,
     // occupied spectators (x < 2) span jlim_occ columns, virtual ones only
     // jlim_virt: one grid each, so no workgroup is launched past its row
     const int nocc = std::min(2, cx->norb);
-    const dim3 go((unsigned)nocc, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv);
-    const dim3 gv((unsigned)(cx->norb - nocc), (unsigned)((jlim_virt + 63) / 64), (unsigned)nv);
+    const unsigned ng = (NT + 3) / 4;
+    const dim3 go((unsigned)nocc, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv * ng);
+    const dim3 gv((unsigned)(cx->norb - nocc), (unsigned)((jlim_virt + 63) / 64), (unsigned)nv * ng);
     for (int up = 1; up >= 0; --up) {
-        k_ob_alpha_spec<NT><<<go, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, 0);
+        k_ob_alpha_spec<NT><<<go, 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, 0);
         if (gv.x > 0 && gv.y > 0) {
             if (jlim_virt <= kObNarrow)
                 k_ob_alpha_narrow<<<dim3(gv.x, (unsigned)nv), 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_virt,
                                                                            nocc);
             else
-                k_ob_alpha_spec<NT><<<gv, 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
+                k_ob_alpha_spec<NT><<<gv, 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
         }
     }
     if (jref > jlim_occ && cx->norb >= 2)
