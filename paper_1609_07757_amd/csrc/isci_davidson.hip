@@ -1017,7 +1017,10 @@ static isci_status batch_sigma(isci_engine e, int n, const isci_handle *hds, con
             size_t k = a % e->side.size();
             for (size_t b = 0; b < a; ++b)
                 if (hds[own[b]] == hds[i]) { k = b % e->side.size(); break; }
-            ISCI_CHECK(launch_sigma(hds[i], nvec[i], c[i], ldc[i], sg[i], lds[i], e->side[k]));
+            // the handles already overlap on the side streams: each runs its
+            // one-body kernels in line (same results as with its own side
+            // stream, fewer cross-stream waits)
+            ISCI_CHECK(launch_sigma(hds[i], nvec[i], c[i], ldc[i], sg[i], lds[i], e->side[k], false));
         }
         for (size_t k = 0; k < e->side.size(); ++k) {
             ISCI_HIP(hipEventRecord(e->side_ev[1 + k], e->side[k]));

@@ -246,8 +246,11 @@ isci_status hip_fail(hipError_t e, const char *what);
 void *dev_alloc(isci_ctx *c, size_t bytes);
 SigmaArgs sigma_args(const isci_ctx *c);
 
+// side = false runs the one-body kernels of the overlap path on `s` too,
+// in the same order relative to the products and folds (same results, bit
+// for bit): for callers that already overlap many handles on several streams
 isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t ldc,
-                         double *sv, int64_t lds, hipStream_t s);
+                         double *sv, int64_t lds, hipStream_t s, bool side = true);
 // records a start (begin=true) or stop event for kernel id `k` when profiling
 isci_status prof_mark(const isci_ctx *c, int k, bool begin, hipStream_t s);
 isci_status launch_diag(const isci_ctx *c, double *diag, hipStream_t s);

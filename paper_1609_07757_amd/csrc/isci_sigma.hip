@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void k_diag(SigmaArgs A, double *__restrict__ 
 }
 
 isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t ldc, double *sv, int64_t lds,
-                         hipStream_t s)
+                         hipStream_t s, bool side)
 {
     const SigmaArgs A = sigma_args(c);
     const dim3 grid((unsigned)c->nplan);
@@ -588,16 +588,19 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                 // the side stream while the unfolds and products of both
                 // 4-vector passes run here (into two S buffers); the folds
                 // wait for them and add
-                ISCI_HIP(hipEventRecord(c->ob_fork, s));
-                ISCI_HIP(hipStreamWaitEvent(c->ob_stream, c->ob_fork, 0));
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, c->ob_stream));
-                ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, c->ob_stream, true));
-                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, c->ob_stream));
-                ISCI_HIP(hipEventRecord(c->ob_join, c->ob_stream));
+                const hipStream_t os = side ? c->ob_stream : s;
+                if (side) {
+                    ISCI_HIP(hipEventRecord(c->ob_fork, s));
+                    ISCI_HIP(hipStreamWaitEvent(c->ob_stream, c->ob_fork, 0));
+                }
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, true, os));
+                ISCI_CHECK(launch_onebody_mfma(c, nv, cc, ldc, ss, lds, os, true));
+                ISCI_CHECK(prof_mark(c, ISCI_KERNEL_ONEBODY, false, os));
+                if (side) ISCI_HIP(hipEventRecord(c->ob_join, c->ob_stream));
                 for (int u0 = 0; u0 < nv; u0 += 4)
                     ISCI_CHECK(launch_ab_unfold_gemm(c, nv - u0 < 4 ? nv - u0 : 4, cc + (int64_t)u0 * ldc, ldc,
                                                      u0 ? c->d.abx_S2 : c->d.abx_S, s));
-                ISCI_HIP(hipStreamWaitEvent(s, c->ob_join, 0));
+                if (side) ISCI_HIP(hipStreamWaitEvent(s, c->ob_join, 0));
                 for (int u0 = 0; u0 < nv; u0 += 4)
                     ISCI_CHECK(launch_ab_fold(c, nv - u0 < 4 ? nv - u0 : 4, u0 ? c->d.abx_S2 : c->d.abx_S,
                                               ss + (int64_t)u0 * lds, lds, true, s));
