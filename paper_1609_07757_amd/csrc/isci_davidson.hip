@@ -1012,11 +1012,25 @@ static isci_status batch_sigma(isci_engine e, int n, const isci_handle *hds, con
         ISCI_CHECK(ensure_side_streams(e));
         ISCI_HIP(hipEventRecord(e->side_ev[0], e->s));
         for (hipStream_t st : e->side) ISCI_HIP(hipStreamWaitEvent(st, e->side_ev[0], 0));
-        for (size_t a = 0; a < own.size(); ++a) {
-            const int i = own[a];
-            size_t k = a % e->side.size();
-            for (size_t b = 0; b < a; ++b)
-                if (hds[own[b]] == hds[i]) { k = b % e->side.size(); break; }
+        // longest work first, each job onto the side stream with the least
+        // work so far (work ~ determinants x vectors); jobs of one handle
+        // share its stream, its product operands being per handle
+        std::vector<int> ord(own);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return (double)hds[a]->dim * nvec[a] > (double)hds[b]->dim * nvec[b];
+        });
+        std::vector<double> load(e->side.size(), 0.0);
+        std::vector<std::pair<isci_handle, size_t>> placed;
+        for (int i : ord) {
+            size_t k = 0;
+            bool found = false;
+            for (const auto &pl : placed)
+                if (pl.first == hds[i]) { k = pl.second; found = true; break; }
+            if (!found) {
+                k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                placed.emplace_back(hds[i], k);
+            }
+            load[k] += (double)hds[i]->dim * nvec[i];
             // the handles already overlap on the side streams: each runs its
             // one-body kernels in line (same results as with its own side
             // stream, fewer cross-stream waits)
