@@ -48,6 +48,9 @@ WORKLOADS = {
     "cisdt_n60": Workload("cisdt_n60", norb=60, level=3, tau=1e-14, nvec=8),
     "cisdt_n30": Workload("cisdt_n30", norb=30, level=3, tau=1e-14, nvec=1),
     "cisdt_n120": Workload("cisdt_n120", norb=120, level=3, tau=1e-14, nvec=1),
+    # served-size CISDT, 160 orbitals, tau 1e-12, 4 vectors (one-body classes
+    # in the spectator form dominate)
+    "cisdt_n160": Workload("cisdt_n160", norb=160, level=3, tau=1e-12, nvec=4),
     # CISDTQ = FCI for 4 electrons, 48 orbitals, 8 simultaneous vectors
     "fci_n48": Workload("fci_n48", norb=48, level=4, tau=1e-14, nvec=8),
 }
