@@ -111,7 +111,13 @@ __global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ 
 
 // partial-sum blocks for a dot product of length n: about 2048 elements
 // (8 per thread) per block, at most kDotBlocks
-int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 511) / 512)); }
+// one element block (summed inside its workgroup, no second kernel) for
+// vectors of at most kDotOneBlock elements, else one block per 512 elements
+constexpr int64_t kDotOneBlock = 2048;
+int dots_blocks(int64_t n)
+{
+    return n <= kDotOneBlock ? 1 : (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 511) / 512));
+}
 
 isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int k, int64_t n,
                  double *out_dev, double *partial, int nblk, hipStream_t s)
@@ -444,14 +450,18 @@ __global__ __launch_bounds__(256) void k_bdots(const BDot *__restrict__ jobs, in
     if (threadIdx.x < kTile * kTile) {
         const int a = threadIdx.x / kTile, b = threadIdx.x % kTile;
         const double r = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        if (i0 + a < J.m && j0 + b < J.k) J.partial[((int64_t)blk * J.m + i0 + a) * J.k + j0 + b] = r;
+        // a job of one element block is complete here
+        if (i0 + a < J.m && j0 + b < J.k) {
+            if (J.nblk == 1) J.out[(i0 + a) * J.k + j0 + b] = r;
+            else J.partial[((int64_t)blk * J.m + i0 + a) * J.k + j0 + b] = r;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_bdots_reduce(const BDot *__restrict__ jobs)
 {
     const BDot J = jobs[blockIdx.z];
-    if (J.skip && *J.skip != 0.0) return;
+    if (J.nblk == 1 || (J.skip && *J.skip != 0.0)) return;
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int mk = J.m * J.k;
     if (e >= mk) return;
@@ -1152,14 +1162,16 @@ static isci_status launch_bdots(const BDot *d, const std::vector<BDot> &h, hipSt
 {
     if (h.empty()) return ISCI_OK;
     int gx = 1, ti = 1, tj = 1, mk = 1;
+    bool reduce = false;
     for (const BDot &j : h) {
+        reduce = reduce || j.nblk > 1;
         gx = std::max(gx, j.nblk);
         ti = std::max(ti, (j.m + kTile - 1) / kTile);
         tj = std::max(tj, (j.k + kTile - 1) / kTile);
         mk = std::max(mk, j.m * j.k);
     }
     k_bdots<<<dim3((unsigned)(((gx + 7) / 8) * 8 * ti * tj), 1, (unsigned)h.size()), 256, 0, s>>>(d, ti, tj);
-    k_bdots_reduce<<<dim3((mk + 3) / 4, 1, (unsigned)h.size()), 256, 0, s>>>(d);
+    if (reduce) k_bdots_reduce<<<dim3((mk + 3) / 4, 1, (unsigned)h.size()), 256, 0, s>>>(d);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
 }

@@ -63,7 +63,7 @@ def davidson_bytes(dim: int, nroots: int) -> int:
     mmax = min(max(32, 6 * kk, 2 * kk), dim)
     keep = max(kk, min(2 * kk + 4, mmax // 2))
     nscr = max(kk, keep)
-    nblk = min(256, max(1, (dim + 511) // 512))
+    nblk = 1 if dim <= 2048 else min(256, max(1, (dim + 511) // 512))
     return 8 * dim * (2 * mmax + nscr + 2 * kk + 1) + 8 * (mmax * mmax + 8 * mmax + 64 + nblk * mmax * mmax + 3 * (mmax + 8))
 
 
