@@ -45,6 +45,7 @@ CASES = [
     ("B", 26, 2, 2, 3, 1e-12, 2),  # 26 orbitals: two 16-orbital tiles, ragged
     ("A", 72, 2, 2, 2, 1e-12, 3),  # 72 orbitals: five 16-orbital tiles
     ("A", 90, 2, 2, 2, 1e-12, 2),  # above the one-body matrix-core limit (80 orbitals)
+    ("A", 84, 2, 2, 1, 1e-12, 3),  # CIS above 80 orbitals: reference-row and virtual tails only
     ("R", 2, 2, 2, 2, 0.0, 1),     # two orbitals, one determinant (one-body units in the tiles)
     ("R", 3, 2, 2, 2, 0.0, 2),     # one virtual orbital
 ]
