@@ -187,11 +187,15 @@ def test_sigma_workloads(wl, nsamp, nvec, variant):
 
 
 @pytest.mark.parametrize("variant", [5, 3])
-def test_sigma_large_orbitals_sampled(variant):
-    """130 orbitals (above the LDS pair-block limit of the one-body kernels:
-    the alpha class runs in spectator form over three 64-row masks), CISD,
-    sampled targets (row ends included) against the oracle."""
-    norb, L, tau = 130, 2, 1e-12
+@pytest.mark.parametrize("norb,L", [(130, 2), (84, 3), (150, 3)])
+def test_sigma_large_orbitals_sampled(variant, norb, L):
+    """Above the LDS pair-block limit of the one-body kernels the alpha class
+    runs in spectator form (up to four 64-row masks).  CISD 130 orbitals:
+    virtual spectators through the narrow kernel and the reference-row
+    tail; CISDT 84 and 150 orbitals: virtual spectators through the
+    matrix-core spectator kernel (165 and 297 columns).  Sampled targets
+    (row ends included) against the oracle."""
+    tau = 1e-12
     h, eri = recipe_a(norb, seed=4)
     hd = create(h, eri, norb, 2, 2, L, tau, variant)
     S = O.Space(norb, 2, 2, L)
