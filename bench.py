@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
-    ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal"], default="sigma",
+    ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal", "peaks"], default="sigma",
                     help="sigma: headline line; batched: 64 uneven Davidson solves, engine vs plain loop; "
                          "served: Poisson request stream with continuous batching; copycal: plain device "
                          "copies of known size (calibrates the HBM byte counters)")
@@ -69,6 +69,8 @@ def main():
         return bench_served(a)
     if a.mode == "copycal":
         return bench_copycal(a)
+    if a.mode == "peaks":
+        return bench_peaks(a)
     import numpy as np
     import torch
 
@@ -376,6 +378,50 @@ def bench_copycal(a):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "copycal", "bytes_per_copy": 8 * n, "copies": 3}), flush=True)
+
+
+def bench_peaks(a):
+    """Re-measures the roofline peaks on this GPU: HBM by a 2 GiB device copy
+    (bytes read + written per second), FP64 matrix and vector rates by the
+    library's issue-rate probes, and a 8192^3 FP64 GEMM through torch
+    (rocBLAS) for context.  Prints one JSON line."""
+    import torch
+    import paper_1609_07757_amd as isci
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    n = (2 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    t_copy = timed(lambda: y.copy_(x), 10)
+    hbm = 2.0 * 8 * n / t_copy / 1e12
+    del x, y
+    blocks = 256 * 8
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    res = {}
+    for kind, name, iters in ((0, "fp64_matrix_tflops", 20000), (1, "fp64_vector_tflops", 20000)):
+        fl = [0.0]
+
+        def run(kind=kind, iters=iters):
+            fl[0] = isci.isci_probe_fp64(kind, iters, blocks, out, st)
+        t = timed(run, 3)
+        res[name] = fl[0] / t / 1e12
+    m = torch.rand(8192, 8192, dtype=torch.float64, device=dev)
+    t_mm = timed(lambda: torch.matmul(m, m), 3)
+    out_line = {"mode": "peaks", "hbm_copy_tb_s": hbm, **res, "dgemm_8192_tflops": 2.0 * 8192 ** 3 / t_mm / 1e12,
+                "published": {"hbm_tb_s": 8.0, "fp64_matrix_tflops": FP64_PEAK_TFLOPS, "fp64_vector_tflops": 78.6}}
+    print(json.dumps(out_line), flush=True)
 
 
 if __name__ == "__main__":

@@ -330,6 +330,16 @@ isci_status isci_set_option(isci_handle hd, int option, int value);
 isci_status isci_profile(isci_handle hd, int enable);
 isci_status isci_profile_read(isci_handle hd, int kernel, double *total_ms, int64_t *launches);
 
+/* Measurement aid (not part of the method), for benchmarks that re-measure
+ * the chip's FP64 peaks: enqueues `blocks` workgroups of 256 threads that
+ * each run `iters` steps of independent FP64 chains on register operands,
+ * kind 0 on the matrix cores (16x16x4 MFMA, eight chains per wave), kind 1
+ * as vector FMAs (sixteen chains per lane), and write one value per thread
+ * to out (device, blocks * 256 doubles).  *flops receives the floating-point
+ * operations enqueued; time the call with events on `stream`. */
+isci_status isci_probe_fp64(int kind, int64_t iters, int blocks, double *out, double *flops,
+                            hipStream_t stream);
+
 void isci_destroy(isci_handle hd);
 const char *isci_status_string(isci_status s);
 const char *isci_last_error(void);

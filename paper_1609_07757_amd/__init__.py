@@ -193,6 +193,15 @@ def isci_sigma_graph_create(hd: Handle, c, sigma=None) -> SigmaGraph:
     return SigmaGraph(out, hd, c2, s2, squeeze)
 
 
+def isci_probe_fp64(kind: int, iters: int, blocks: int, out, stream=None) -> float:
+    """Enqueue the FP64 issue-rate probe (kind 0 matrix cores, 1 vector FMA);
+    returns the flops enqueued (a measurement aid, not part of the method)."""
+    fl = ctypes.c_double()
+    check(_lib.load().isci_probe_fp64(int(kind), int(iters), int(blocks), _dev_f64(out, "out"),
+                                      ctypes.byref(fl), _stream_ptr(stream)), "isci_probe_fp64")
+    return float(fl.value)
+
+
 def isci_diag(hd: Handle, out=None, stream=None):
     torch = _torch()
     if out is None:

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1609_07757_amd", "libisci.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(isci_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(isci_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_entry_points():
