@@ -15,6 +15,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
 * ``terms``: pinned by an independent closed-form count in the tests.
 * ``dropped_bound``: pinned by the Weyl inequality against exact spectra.
 * ``davidson``: pinned by dense diagonalisation on small spaces.
+* ``density1``: pinned by single determinants (occupation numbers), the
+  trace (electron count), the one-body energy against ``dense_h`` with the
+  two-electron integrals set to zero, the alpha/beta swap, and brute force
+  through ``apply_word`` on tiny spaces.
 """
 from __future__ import annotations
 
@@ -35,6 +39,9 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 _LIB = None
+
+# Mutation switches for the pin tests (a planted mistake; never set in use).
+_PLANT = set(os.environ.get("ISCI_ORACLE_PLANT", "").split(","))
 
 
 def lib():
@@ -333,3 +340,75 @@ def davidson(space: Space, h, eri, tau: float, nroots: int = 1, tol: float = 1e-
         V = np.hstack([V, A])
         W = np.hstack([W, WA])
     return theta, (V @ np.linalg.eigh(0.5 * (V.T @ W + W.T @ V))[1][:, :k]).T, rn
+
+
+def _excite(orbs, p, q):
+    """a+_p a_q on the ascending creator string `orbs`: (sign, new string) or
+    None.  a_q moves past the creators left of q; a+_p is then moved from the
+    front to its ascending place past the creators below p."""
+    if q not in orbs:
+        return None
+    k = orbs.index(q)
+    rest = orbs[:k] + orbs[k + 1:]
+    if p in rest:
+        return None
+    below = sum(1 for x in rest if x < p)
+    if "D1_HALF_SIGN" in _PLANT:
+        below = 0
+    sign = -1 if (k + below) % 2 else 1
+    return sign, tuple(sorted(rest + (p,)))
+
+
+def density1(space: Space, c) -> np.ndarray:
+    """One-body density matrix of each vector, by spin: the paper's D1 (its
+    density-matrix subsection, Eq. d1) with spin-orbital indices
+    restricted to one spin, d[v, s, p, q] = <c_v| a+_{p s} a_{q s} |c_v>,
+    s = 0 alpha, 1 beta.
+
+    Every (source determinant, replacement q -> p) pair that lands in the
+    space contributes sign * c(target) * c(source).  An alpha replacement
+    keeps the beta string, so the pair's contributions along a row are one
+    dot product over the beta strings both rows hold (rows are prefixes of
+    the beta list); a beta replacement stays inside its alpha row.  The
+    alpha creators stand left of the beta ones, and a+ a moved past them is
+    even, so beta replacements carry only their own sign."""
+    c = np.atleast_2d(np.asarray(c, dtype=np.float64))
+    nv = c.shape[0]
+    norb = space.norb
+    ao, _ = space.strings(0)
+    bo, _ = space.strings(1)
+    rs = space.rowstart()
+    ln = np.diff(rs)
+    amap = {tuple(int(x) for x in o): i for i, o in enumerate(ao)}
+    bmap = {tuple(int(x) for x in o): i for i, o in enumerate(bo)}
+    d = np.zeros((nv, 2, norb, norb))
+    for i, o in enumerate(ao):
+        src = tuple(int(x) for x in o)
+        for q in src:
+            for p in range(norb):
+                r = _excite(src, p, q)
+                if r is None or r[1] not in amap:
+                    continue
+                j = amap[r[1]]
+                m = int(max(ln[i], ln[j]) if "D1_LONG_ROW" in _PLANT else min(ln[i], ln[j]))
+                d[:, 0, p, q] += r[0] * np.einsum("vk,vk->v", c[:, rs[j]:rs[j] + m], c[:, rs[i]:rs[i] + m])
+    K, J, P, Q, S = [], [], [], [], []
+    for k, o in enumerate(bo):
+        src = tuple(int(x) for x in o)
+        for q in src:
+            for p in range(norb):
+                r = _excite(src, p, q)
+                if r is None or r[1] not in bmap:
+                    continue
+                K.append(k); J.append(bmap[r[1]]); P.append(p); Q.append(q); S.append(r[0])
+    K, J, P, Q, S = (np.array(x, dtype=np.int64) for x in (K, J, P, Q, S))
+    for i in range(len(ao)):
+        sel = (K < ln[i]) & (J < ln[i])
+        if not sel.any():
+            continue
+        vals = S[sel] * c[:, rs[i] + J[sel]] * c[:, rs[i] + K[sel]]
+        if "D1_BETA_PAST_ALPHA" in _PLANT and space.nalpha % 2:
+            vals = -vals
+        for v in range(nv):
+            np.add.at(d[v, 1], (P[sel], Q[sel]), vals[v])
+    return d

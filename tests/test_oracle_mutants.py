@@ -34,3 +34,22 @@ def test_pins_reject_planted_mistake(macro, tmp_path):
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch {macro}:\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout
+
+
+# Mistakes planted in the numpy part of the oracle (an environment switch
+# read when the module loads).
+PY_MUTANTS = [
+    "D1_HALF_SIGN",          # phase of a+_p ignored (only a_q's counted)
+    "D1_LONG_ROW",           # alpha dot over the longer row: reads past the shorter one
+    "D1_BETA_PAST_ALPHA",    # beta replacement signed by the alpha creators it passes
+]
+
+
+@pytest.mark.parametrize("plant", PY_MUTANTS)
+def test_density_pins_reject_planted_mistake(plant):
+    env = dict(os.environ, ISCI_ORACLE_PLANT=plant)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "density1"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"pins did not catch {plant}:\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout

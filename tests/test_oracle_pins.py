@@ -364,3 +364,95 @@ def test_term_count_alpha_beta_swap_symmetry():
     assert np.array_equal(kept[8:17], kept[17:26])
     ab = kept[26:42].reshape(2, 2, 2, 2)
     assert np.array_equal(ab, ab.transpose(2, 3, 0, 1))
+
+
+# ---------------------------------------------------------------- D1
+# One-body density matrices (the paper's density-matrix subsection, Eq. d1).
+_D1_SPACES = [(6, 2, 2, 2), (7, 3, 1, 3), (6, 2, 2, 4), (5, 1, 0, 1), (6, 3, 3, 6), (7, 2, 1, 2)]
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D1_SPACES)
+def test_density1_single_determinant_occupations(norb, na, nb, L):
+    """A single determinant has the occupation numbers of its strings on
+    the diagonal of each spin block and nothing off it."""
+    S = O.Space(norb, na, nb, L)
+    dets = S.determinants()
+    for k in sorted({0, S.dim // 3, S.dim - 1}):
+        e = np.zeros((1, S.dim))
+        e[0, k] = -1.5
+        d = O.density1(S, e)[0]
+        want = np.zeros((2, norb, norb))
+        for s, orbs in enumerate(dets[k]):
+            for o in orbs:
+                want[s, o, o] = 2.25
+        np.testing.assert_array_equal(d, want)
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D1_SPACES)
+def test_density1_trace_and_symmetry(norb, na, nb, L):
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 3, seed=norb + L)
+    d = O.density1(S, c)
+    nn = (c * c).sum(1)
+    for s, n in enumerate((na, nb)):
+        np.testing.assert_allclose(np.trace(d[:, s], axis1=1, axis2=2), n * nn, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(d, d.transpose(0, 1, 3, 2), rtol=0, atol=1e-13 * np.abs(d).max())
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D1_SPACES)
+def test_density1_one_body_energy_against_dense_h(norb, na, nb, L):
+    """<c|H1|c> with H1 the oracle's dense Hamiltonian for zero two-electron
+    integrals equals sum_pq h_pq (D1a + D1b)_pq, for several random
+    symmetric h (each draw weighs every element differently)."""
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 2, seed=7 * norb + L)
+    d = O.density1(S, c)
+    eri = np.zeros((norb,) * 4)
+    rng = np.random.default_rng(norb * 31 + L)
+    for _ in range(3):
+        h = rng.standard_normal((norb, norb))
+        h = h + h.T
+        H = O.dense_h(S, h, eri, 0.0)
+        for v in range(2):
+            e = c[v] @ H @ c[v]
+            assert abs(e - (h * (d[v, 0] + d[v, 1])).sum()) <= 1e-12 * max(1.0, abs(e))
+
+
+def test_density1_alpha_beta_swap():
+    """With as many alpha as beta electrons the space is closed under the
+    spin swap (Ia, Ib) -> (Ib, Ia); the swapped vector's alpha block is the
+    original beta block and vice versa."""
+    norb, n, L = 7, 2, 3
+    S = O.Space(norb, n, n, L)
+    c = random_vectors(S.dim, 2, seed=3)
+    dets = S.determinants()
+    perm = np.array([S.address(b, a) for a, b in dets])
+    assert (perm >= 0).all() and len(set(perm.tolist())) == S.dim
+    cs = np.zeros_like(c)
+    cs[:, perm] = c
+    d, ds = O.density1(S, c), O.density1(S, cs)
+    np.testing.assert_allclose(ds[:, 0], d[:, 1], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ds[:, 1], d[:, 0], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("norb,na,nb,L", [(5, 2, 2, 2), (5, 3, 1, 2), (4, 2, 2, 4)])
+def test_density1_brute_force_words(norb, na, nb, L):
+    """Every element by brute force: for each determinant and each (p, q),
+    the word a+_p a_q applied to the spin's creator string through
+    apply_word (pinned by the paper's worked sign examples), the target's
+    address in the space, and the coefficient product."""
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 1, seed=11)[0]
+    want = np.zeros((2, norb, norb))
+    for k, (a, b) in enumerate(S.determinants()):
+        for s, orbs in enumerate((a, b)):
+            for p in range(norb):
+                for q in range(norb):
+                    sg, out = O.apply_word([("+", p), ("-", q)] + [("+", o) for o in orbs], 1)
+                    if not sg:
+                        continue
+                    j = S.address(out, b) if s == 0 else S.address(a, out)
+                    if j < 0:
+                        continue
+                    want[s, p, q] += sg * c[j] * c[k]
+    np.testing.assert_allclose(O.density1(S, c[None])[0], want, rtol=0, atol=1e-13)
