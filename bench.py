@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
+    ap.add_argument("--skip-density", action="store_true", help="do not time the density matrices")
     ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal", "peaks"], default="sigma",
                     help="sigma: headline line; batched: 64 uneven Davidson solves, engine vs plain loop; "
                          "served: Poisson request stream with continuous batching; copycal: plain device "
@@ -207,11 +208,36 @@ def main():
         "graph": {"ms_per_step": ms_graph, "sigma_vectors_per_s": nvec / (ms_graph * 1e-3),
                   "speedup_vs_calls": ms_per_step / ms_graph, "bitwise_equal_to_calls": graph_equal},
     }
+    if not a.skip_density:
+        out["density1"] = density1_timing(isci, torch, hd, c, stream, a.steps)
     if not a.skip_davidson:
         out["davidson"] = davidson_latency(isci, torch, dev)
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(W, h, eri, tau, nvec, dim, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def density1_timing(isci, torch, hd, c, stream, steps):
+    """One-body density matrices of the bench vectors (not part of the sigma
+    step or its value), timed with HIP events on the launch stream.  Bytes a
+    pass must move at least: the alpha pass reads c (8 B per determinant
+    and vector), the beta pass transposes c (16 B) and reads the
+    transposed copy (8 B): 32 B per determinant and vector."""
+    d1 = isci.isci_density1(hd, c, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        isci.isci_density1(hd, c, d1, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nv = int(c.shape[0])
+    nb = 32.0 * hd.dim * nv
+    tr = [float(torch.trace(d1[v, s]) / (c[v] @ c[v])) for v in range(nv) for s in range(2)]
+    return {"ms_per_call": ms, "vectors": nv, "electrons_from_traces": [min(tr), max(tr)],
+            "roofline": {"bound": "hbm", "achieved": nb / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": nb / (ms * 1e-3) / 1e9 / 8000.0, "algorithmic_bytes": nb}}
 
 
 def davidson_latency(isci, torch, dev, reps=9):

@@ -212,6 +212,25 @@ void isci_graph_destroy(isci_graph g);
  * Device array of length dim.  Asynchronous. */
 isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
 
+/* One-body density matrix of each vector, by spin (the paper's density
+ * matrices, Eq. d1, with the spin-orbital indices of one spin):
+ *   d1[((v * 2 + s) * norb + p) * norb + q] = <c_v| a+_{p s} a_{q s} |c_v>,
+ * s = 0 alpha, 1 beta, for v < nvec (1..65535).  c: device, nvec vectors
+ * with leading dimension ldc >= dim, not normalised by the call (the trace
+ * of the s block is n_s * |c_v|^2).  d1: device, nvec * 2 * norb^2 doubles,
+ * overwritten, must not overlap c.  Every determinant pair connected by
+ * a+_p a_q counts; the screening threshold plays no part.  Deterministic
+ * (fixed summation order).  The beta block is computed from the vectors
+ * transposed into the spin-swapped layout, four at a time, in a buffer the
+ * handle allocates on its first density call with beta electrons and keeps
+ * until it is destroyed (4 * dim doubles and nstr_beta + 1 int64; that
+ * first call also copies the row starts synchronously).  Calls on one
+ * handle share the buffer and must be ordered.  Otherwise asynchronous on
+ * `stream`.  Errors: ISCI_E_INVALID for NULL pointers, nvec or ldc out of
+ * range, overlap; ISCI_E_OOM if the buffer cannot be allocated. */
+isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,
+                          hipStream_t stream);
+
 /* Lowest nroots eigenpairs by block Davidson (FP64, device resident; the
  * small projected eigenproblem is solved on the host).  guess: device
  * [nguess][dim] or NULL (unit vectors on the lowest diagonal entries,

@@ -20,7 +20,7 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
-           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator"]
+           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator", "isci_density1"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -208,6 +208,24 @@ def isci_diag(hd: Handle, out=None, stream=None):
         out = torch.empty(hd.dim, dtype=torch.float64, device="cuda")
     check(_lib.load().isci_diag(hd.ptr, _dev_f64(out, "diag"), _stream_ptr(stream)), "isci_diag")
     return out
+
+
+def isci_density1(hd: Handle, c, out=None, stream=None):
+    """One-body density matrices by spin: out[v, s, p, q] = <c_v| a+_{p s}
+    a_{q s} |c_v> (s = 0 alpha, 1 beta) for c of shape [nvec, dim] or [dim]."""
+    torch = _torch()
+    squeeze = c.dim() == 1
+    c2 = c.unsqueeze(0) if squeeze else c
+    if c2.shape[-1] != hd.dim:
+        raise ValueError("c has wrong length")
+    nv, n = int(c2.shape[0]), hd.norb
+    if out is None:
+        out = torch.empty((nv, 2, n, n), dtype=torch.float64, device=c2.device)
+    if tuple(out.shape) != (nv, 2, n, n) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [nvec, 2, norb, norb] tensor")
+    check(_lib.load().isci_density1(hd.ptr, nv, _dev_f64(c2, "c"), int(c2.stride(0)), _dev_f64(out, "d1"),
+                                    _stream_ptr(stream)), "isci_density1")
+    return out[0] if squeeze else out
 
 
 def _opts(tol_residual=1e-7, tol_energy=1e-11, max_iter=200, max_subspace=0, block=0):

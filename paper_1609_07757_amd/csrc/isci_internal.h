@@ -111,6 +111,10 @@ struct DevTabs {
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
     double *obT_c = nullptr;        // [4][dim] transposed CI block (beta one-body above kObMaxNorb)
     double *obT_s = nullptr;        // [4][dim] its alpha-class image
+    // density matrices: vectors in the spin-swapped layout (rows = beta
+    // strings holding alpha prefixes), allocated by the first density call
+    double *d1T = nullptr;          // [kD1Chunk][dim]
+    int64_t *d1T_rowstart = nullptr; // [nstr_b + 1]
 };
 
 struct SigmaArgs {

@@ -69,6 +69,8 @@ def test_invalid_arguments_rejected_before_any_device_work():
     assert L.isci_create_ex(ctypes.byref(out), fake, fake, 4, 1, 1, 2, 0.0, ctypes.byref(ao),
                             None) == _lib.ISCI_E_INVALID
     assert L.isci_sigma(None, 1, fake, 1, fake, 1, None) == _lib.ISCI_E_INVALID
+    assert L.isci_density1(None, 1, fake, 1, fake, None) == _lib.ISCI_E_INVALID
+    assert L.isci_probe_fp64(2, 1, 1, fake, None, None) == _lib.ISCI_E_INVALID
     g = ctypes.c_void_p(0x2000)
     assert L.isci_sigma_graph_create(None, 1, fake, 1, fake, 1, ctypes.byref(g)) == _lib.ISCI_E_INVALID
     assert g.value is None   # *out cleared on failure
