@@ -15,7 +15,7 @@
 // prefix), with the two spin tables exchanged.  The sign is
 // (-1)^(spectators strictly between p and q); a beta replacement passes
 // the alpha creators as an even pair and adds nothing.
-// One wave owns an element; each lane accumulates its own terms and the
+// One wave owns an element (four per workgroup); each lane accumulates its own terms and the
 // wave sums them in a fixed order, so the result is the same on every run.
 // Row starts follow from the level tables (rows of one level are contiguous
 // and equally long), so the walk issues no index loads.
@@ -31,7 +31,7 @@ namespace isci {
 
 namespace {
 
-constexpr int kD1Threads = 64;   // one wave per density element
+constexpr int kD1Threads = 256;  // four waves, one density element each
 constexpr int kD1Chunk = 4;   // vectors per transposed batch (the handle keeps kD1Chunk * dim doubles)
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
@@ -50,6 +50,37 @@ __device__ inline int64_t row_start(const SpinTab &R, const SpinTab &C, int L, i
     int64_t base = 0;
     for (int l = 0; l < k; ++l) base += (int64_t)(R.lev_off[l + 1] - R.lev_off[l]) * C.le[L - l];
     return base + (int64_t)(i - R.lev_off[k]) * C.le[L - k];
+}
+
+// C(x, k) for 0 <= k <= 4 and x <= 255 in closed form: every product fits
+// 32 unsigned bits (255 * 254 * 253 * 252 < 2^32) and the divisors are
+// constants, so no integer division routine runs.
+__device__ inline uint32_t binom_small(int x, int k)
+{
+    if (k < 0 || x < k) return 0u;
+    const uint32_t u = (uint32_t)x;
+    switch (k) {
+    case 0: return 1u;
+    case 1: return u;
+    case 2: return u * (u - 1u) / 2u;
+    case 3: return u * (u - 1u) * (u - 2u) / 6u;
+    default: return u * (u - 1u) * (u - 2u) * (u - 3u) / 24u;
+    }
+}
+
+// Index of an ascending string in (level, colex) order: the same rank as
+// the library's string tables, with the closed-form binomials.
+__device__ inline int rank_small(const int *o, const SpinTab &T)
+{
+    const int n = T.n;
+    int ip = 0, io = 0;
+    uint32_t rp = 0, ro = 0;
+    for (int i = 0; i < n; ++i) {
+        const int x = o[i];
+        if (x >= n) { ++ip; rp += binom_small(x - n, ip); }
+        else        { ++io; ro += binom_small(x, io); }
+    }
+    return T.lev_off[ip] + (int)(rp * (uint32_t)T.occ_mult[ip] + ro);
 }
 
 // Spectator walk of one element (p, q) of a spin with n electrons: the
@@ -112,7 +143,10 @@ __global__ __launch_bounds__(kD1Threads) void k_d1_rows(SigmaArgs A, const doubl
                                                          double *__restrict__ d1, int slot, int v0)
 {
     const int norb = A.norb;
-    const int p = blockIdx.x / norb, q = blockIdx.x - p * norb;
+    const int lane = threadIdx.x & 63;
+    const int pq = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pq >= norb * norb) return;   // whole wave: no barrier follows
+    const int p = pq / norb, q = pq - p * norb;
     const int v = blockIdx.y;
     const double *cv = c + (int64_t)v * ldc;
     double acc = 0.0;
@@ -124,19 +158,19 @@ __global__ __launch_bounds__(kD1Threads) void k_d1_rows(SigmaArgs A, const doubl
         const int ls = str_level(src, A.sa.n), lt = str_level(dst, A.sa.n);
         if (ls > A.sa.maxlev || lt > A.sa.maxlev) continue;
         const int len = A.sb.le[A.L - max(ls, lt)];
-        const double *rs = cv + row_start(A.sa, A.sb, A.L, str_index(src, A.sa), ls);
-        const double *rt = cv + row_start(A.sa, A.sb, A.L, str_index(dst, A.sa), lt);
+        const double *rs = cv + row_start(A.sa, A.sb, A.L, rank_small(src, A.sa), ls);
+        const double *rt = cv + row_start(A.sa, A.sb, A.L, rank_small(dst, A.sa), lt);
         double p0 = 0.0, p1 = 0.0;
-        int b = threadIdx.x;
-        for (; b + kD1Threads < len; b += 2 * kD1Threads) {
+        int b = lane;
+        for (; b + 64 < len; b += 128) {
             p0 = fma(rt[b], rs[b], p0);
-            p1 = fma(rt[b + kD1Threads], rs[b + kD1Threads], p1);
+            p1 = fma(rt[b + 64], rs[b + 64], p1);
         }
         if (b < len) p0 = fma(rt[b], rs[b], p0);
         acc = fma(sg, p0 + p1, acc);
     }
     const double tot = wave_sum(acc);
-    if (threadIdx.x == 0) d1[(((int64_t)(v0 + v) * 2 + slot) * norb + p) * norb + q] = tot;
+    if (lane == 0) d1[(((int64_t)(v0 + v) * 2 + slot) * norb + p) * norb + q] = tot;
 }
 
 // Vectors v < nv of c into the spin-swapped layout: determinant (ia, j) of
@@ -173,7 +207,7 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
     const char *d0 = (const char *)d1, *e1 = (const char *)(d1 + nd);
     if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
     const SigmaArgs A = sigma_args(h);
-    const unsigned npq = (unsigned)(h->norb * h->norb);
+    const unsigned npq = (unsigned)((h->norb * h->norb + 3) / 4);   // workgroups of four elements
     k_d1_rows<<<dim3(npq, (unsigned)nvec), kD1Threads, 0, stream>>>(A, c, ldc, d1, 0, 0);
     ISCI_HIP(hipGetLastError());
     // beta: the same kernel on the spin-swapped layout, kD1Chunk vectors at a time
