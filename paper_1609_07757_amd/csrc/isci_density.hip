@@ -3,22 +3,22 @@
 //
 // The paper's density loop is the Hamiltonian's class loop with the
 // integral fetch replaced by a product of two coefficients.  Here the
-// element (p, q) of one spin owns a workgroup: it walks the sets of the
-// other n - 1 electrons ("spectators", the orbitals other than p and q),
-// forms the source string spectators + q and the target string
-// spectators + p, and adds sign * c(target) * c(source) over every
-// determinant pair the replacement connects.  For alpha the beta string is
-// kept, so the pair is a dot product of the two alpha rows over the beta
-// prefix both rows hold (coalesced).  For beta the same kernel runs on the
-// vectors transposed into the spin-swapped layout (rows = beta strings,
-// each holding the alpha strings of level <= L - its level, again a
-// prefix), with the two spin tables exchanged.  The sign is
-// (-1)^(spectators strictly between p and q); a beta replacement passes
-// the alpha creators as an even pair and adds nothing.
-// One wave owns an element (four per workgroup); each lane accumulates its own terms and the
-// wave sums them in a fixed order, so the result is the same on every run.
-// Row starts follow from the level tables (rows of one level are contiguous
-// and equally long), so the walk issues no index loads.
+// replacement q -> p of one spin is read through its spectators: for a set
+// S of the other n - 1 electrons, source S + q and target S + p, with sign
+// (-1)^(members of S strictly between p and q) = s_S(p) s_S(q), s_S(x) =
+// (-1)^(members of S below x).  For alpha the beta string is kept, so a
+// connected pair contributes the dot product of the two alpha rows over the
+// beta prefix both rows hold, and
+//   D[p][q] = sum_S sum_b R_S[p][b] R_S[q][b],  R_S[x] = s_S(x) c(S + x, .)
+// is a Gram matrix of the set's signed rows per spectator set (k_d1_gram),
+// each row read once per set it belongs to.  For beta the same kernel runs
+// on the vectors transposed into the spin-swapped layout (rows = beta
+// strings, each holding the alpha strings of level <= L - its level, again
+// a prefix), with the two spin tables exchanged; a beta replacement passes
+// the alpha creators as an even pair and adds no sign.  Sets are split over
+// a fixed number of groups whose partial sums k_d1_reduce adds in order, so
+// the result is the same on every run.  Row starts follow from the level
+// tables (rows of one level are contiguous and equally long).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,8 +31,8 @@ namespace isci {
 
 namespace {
 
-constexpr int kD1Threads = 256;  // four waves, one density element each
-constexpr int kD1Chunk = 4;   // vectors per transposed batch (the handle keeps kD1Chunk * dim doubles)
+constexpr int kD1Chunk = 4;
+constexpr int kGramGroups = 64;   // spectator-set groups summed in fixed order by k_d1_reduce   // vectors per transposed batch (the handle keeps kD1Chunk * dim doubles)
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
 __device__ inline double wave_sum(double x)
@@ -83,94 +83,161 @@ __device__ inline int rank_small(const int *o, const SpinTab &T)
     return T.lev_off[ip] + (int)(rp * (uint32_t)T.occ_mult[ip] + ro);
 }
 
-// Spectator walk of one element (p, q) of a spin with n electrons: the
-// (n - 1)-subsets of the orbitals other than p and q in colex order,
-// advanced by `next`.  Gives the ascending source (spectators + q) and
-// target (spectators + p) strings and the replacement sign.
-struct SpecWalk {
-    int n, m, lo, hi;     // m orbitals to choose from; lo <= hi the skipped ones
-    int e[ISCI_MAXN];     // current subset as indices into the m orbitals
-    bool more;
-
-    __device__ void init(int n_, int norb, int p, int q)
-    {
-        n = n_;
-        lo = min(p, q);
-        hi = max(p, q);
-        m = norb - (p == q ? 1 : 2);
-        const int k = n - 1;
-        more = (n >= 1) && (k <= m);
-        for (int i = 0; i < k; ++i) e[i] = i;
-    }
-    __device__ int orb(int x) const
-    {
-        if (x >= lo) ++x;
-        if (lo != hi && x >= hi) ++x;
-        return x;
-    }
-    __device__ void next()
-    {
-        const int k = n - 1;
-        int i = k - 1;
-        while (i >= 0 && e[i] == m - k + i) --i;
-        if (i < 0) { more = false; return; }
-        ++e[i];
-        for (int j = i + 1; j < k; ++j) e[j] = e[j - 1] + 1;
-    }
-    // strings and sign of the current subset
-    __device__ int strings(int p, int q, int *src, int *dst) const
-    {
-        const int k = n - 1;
-        int between = 0, a = 0, b = 0;
-        bool qin = false, pin = false;
-        for (int i = 0; i < k; ++i) {
-            const int o = orb(e[i]);
-            between += (o > lo && o < hi);
-            if (!qin && q < o) { src[a++] = q; qin = true; }
-            if (!pin && p < o) { dst[b++] = p; pin = true; }
-            src[a++] = o;
-            dst[b++] = o;
-        }
-        if (!qin) src[a++] = q;
-        if (!pin) dst[b++] = p;
-        return (between & 1) ? -1 : 1;
-    }
-};
-
-// Element (p, q) of the spin whose strings index the rows of A (A.sa), for
-// vector blockIdx.y of c, written to slot `slot` of vector v0 + blockIdx.y.
-__global__ __launch_bounds__(kD1Threads) void k_d1_rows(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
-                                                         double *__restrict__ d1, int slot, int v0)
+// Spectator set number s (colex) of k orbitals out of norb, ascending.
+__device__ inline void unrank_set(uint32_t s, int k, int norb, int *S)
 {
-    const int norb = A.norb;
-    const int lane = threadIdx.x & 63;
-    const int pq = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (pq >= norb * norb) return;   // whole wave: no barrier follows
-    const int p = pq / norb, q = pq - p * norb;
-    const int v = blockIdx.y;
-    const double *cv = c + (int64_t)v * ldc;
-    double acc = 0.0;
-    SpecWalk w;
-    w.init(A.sa.n, norb, p, q);
-    for (; w.more; w.next()) {
-        int src[ISCI_MAXN], dst[ISCI_MAXN];
-        const double sg = (double)w.strings(p, q, src, dst);
-        const int ls = str_level(src, A.sa.n), lt = str_level(dst, A.sa.n);
-        if (ls > A.sa.maxlev || lt > A.sa.maxlev) continue;
-        const int len = A.sb.le[A.L - max(ls, lt)];
-        const double *rs = cv + row_start(A.sa, A.sb, A.L, rank_small(src, A.sa), ls);
-        const double *rt = cv + row_start(A.sa, A.sb, A.L, rank_small(dst, A.sa), lt);
-        double p0 = 0.0, p1 = 0.0;
-        int b = lane;
-        for (; b + 64 < len; b += 128) {
-            p0 = fma(rt[b], rs[b], p0);
-            p1 = fma(rt[b + 64], rs[b + 64], p1);
-        }
-        if (b < len) p0 = fma(rt[b], rs[b], p0);
-        acc = fma(sg, p0 + p1, acc);
+    for (int i = k; i >= 1; --i) {
+        int x = i - 1;
+        while (x + 1 < norb && binom_small(x + 1, i) <= s) ++x;
+        S[i - 1] = x;
+        s -= binom_small(x, i);
     }
-    const double tot = wave_sum(acc);
-    if (lane == 0) d1[(((int64_t)(v0 + v) * 2 + slot) * norb + p) * norb + q] = tot;
+}
+
+// Gram form of the density: for a set S of n - 1 orbitals of the spin whose
+// strings index the rows of A (A.sa), the rows R[q] = (-1)^{#S below q}
+// c(S + q, .) (zero when S + q is not a string of the space) give
+// D[p][q] += sum_b R[p][b] R[q][b] over the prefix both rows hold.  The rows
+// of one set have two lengths only (S + q one level higher for a virtual q),
+// so phase 1 takes every row over the shorter length and phase 2 the pairs
+// of the longer rows (q < n: at most 4, rows 0..3 of tile 0) over the rest.
+// Workgroup (tile pair, g * P + p, vector v) sums its tile of the output over
+// the sets g, g + G, ... and, of each, the phase-1 column pieces p, p + P, ...
+// of W columns (phase 2 with piece stream p = 0), so that long row sets are
+// shared out; it writes the tile to part[g * P + p][v] (norb x norb).
+constexpr int kGT = 64;   // output tile edge (rows)
+constexpr int kGK = 32;   // K step staged in LDS
+constexpr int kGramPiece = 2 * kGK;   // phase-1 columns per piece
+
+__global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__restrict__ c, int64_t ldc, int nv,
+                                                 int nsets, int G, int P, int W, int ntile, double *__restrict__ part)
+{
+    __shared__ double As[kGT][kGK + 1], Bs[kGT][kGK + 1];
+    __shared__ int64_t roff[2][kGT];
+    __shared__ double rsg[2][kGT];
+    __shared__ int rlen[2][kGT];
+    __shared__ int kmin_s, kmax_s;
+    __shared__ double ph2[4][4];
+    const int norb = A.norb, n = A.sa.n, tid = threadIdx.x;
+    const int tp = blockIdx.x / ntile, tq = blockIdx.x - tp * ntile;
+    const int P0 = tp * kGT, Q0 = tq * kGT;
+    const bool same = (tp == tq);
+    const int gp = blockIdx.y, g = gp / P, pc = gp - g * P, v = blockIdx.z;
+    const double *cv = c + (int64_t)v * ldc;
+    const int pr = (tid >> 4) * 4, qc = (tid & 15) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    for (int set = g; set < nsets; set += G) {
+        int S[ISCI_MAXN];
+        unrank_set((uint32_t)set, n - 1, norb, S);
+        if (tid == 0) { kmin_s = 0x7fffffff; kmax_s = 0; }
+        __syncthreads();
+        if (tid < 2 * kGT) {   // row tables of the two tiles
+            const int side = tid / kGT, r = tid - side * kGT;
+            const int q = (side ? Q0 : P0) + r;
+            double sg = 0.0;
+            int64_t off = 0;
+            int len = 0;
+            bool in = (q >= norb);
+            int below = 0;
+            for (int i = 0; i < n - 1; ++i) { in |= (S[i] == q); below += (S[i] < q); }
+            if (!in) {
+                int str[ISCI_MAXN], a = 0;
+                bool put = false;
+                for (int i = 0; i < n - 1; ++i) {
+                    if (!put && q < S[i]) { str[a++] = q; put = true; }
+                    str[a++] = S[i];
+                }
+                if (!put) str[a++] = q;
+                const int lev = str_level(str, n);
+                if (lev <= A.sa.maxlev) {
+                    len = A.sb.le[A.L - lev];
+                    off = row_start(A.sa, A.sb, A.L, rank_small(str, A.sa), lev);
+                    sg = (below & 1) ? -1.0 : 1.0;
+                    atomicMin(&kmin_s, len);
+                    atomicMax(&kmax_s, len);
+                }
+            }
+            roff[side][r] = off;
+            rsg[side][r] = sg;
+            rlen[side][r] = len;
+        }
+        __syncthreads();
+        const int K1 = (kmax_s == 0) ? 0 : kmin_s, K2 = kmax_s;
+        // phase 1: every row over this workgroup's pieces of [0, K1)
+        for (int kb = pc * W; kb < K1; kb += P * W)
+        for (int k0 = kb, ke = min(kb + W, K1); k0 < ke; k0 += kGK) {
+            for (int e = tid; e < kGT * kGK; e += 256) {
+                const int r = e >> 5, kk = e & (kGK - 1), k = k0 + kk;
+                const double sa = rsg[0][r];
+                As[r][kk] = (sa != 0.0 && k < ke) ? sa * cv[roff[0][r] + k] : 0.0;
+                if (!same) {
+                    const double sb = rsg[1][r];
+                    Bs[r][kk] = (sb != 0.0 && k < ke) ? sb * cv[roff[1][r] + k] : 0.0;
+                }
+            }
+            __syncthreads();
+            const double (*Bt)[kGK + 1] = same ? As : Bs;
+#pragma unroll 4
+            for (int kk = 0; kk < kGK; ++kk) {
+                double a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) { a[i] = As[pr + i][kk]; b[i] = Bt[qc + i][kk]; }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+        // phase 2: pairs of the longer rows over [K1, min of their lengths)
+        if (K2 > K1 && P0 == 0 && Q0 == 0 && pc == 0) {
+            const int w = tid >> 6, lane = tid & 63;
+            for (int pairi = w; pairi < 16; pairi += 4) {
+                const int i = pairi >> 2, j = pairi & 3;
+                const int le = min(rlen[0][i], rlen[1][j]);
+                double part2 = 0.0;
+                if (rsg[0][i] != 0.0 && rsg[1][j] != 0.0)
+                    for (int k = K1 + lane; k < le; k += 64) part2 = fma(cv[roff[0][i] + k], cv[roff[1][j] + k], part2);
+                part2 = wave_sum(part2) * rsg[0][i] * rsg[1][j];
+                if (lane == 0) ph2[i][j] = part2;
+            }
+            __syncthreads();
+            if (tid == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] += ph2[i][j];
+            }
+        }
+        __syncthreads();
+    }
+    double *out = part + ((int64_t)gp * nv + v) * norb * norb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = P0 + pr + i, q = Q0 + qc + j;
+            if (p < norb && q < norb) out[(int64_t)p * norb + q] = acc[i][j];
+        }
+}
+
+// d1[v0 + v][slot] = sum over g (in order) of part[g][v]; G = 0 writes zeros.
+__global__ __launch_bounds__(256) void k_d1_reduce(const double *__restrict__ part, int G, int nv, int norb,
+                                                   double *__restrict__ d1, int slot, int v0)
+{
+    const int64_t nn = (int64_t)norb * norb;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nv * nn) return;
+    const int v = (int)(t / nn);
+    const int64_t pq = t - v * nn;
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += part[((int64_t)g * nv + v) * nn + pq];
+    d1[((int64_t)(v0 + v) * 2 + slot) * nn + pq] = s;
 }
 
 // Vectors v < nv of c into the spin-swapped layout: determinant (ia, j) of
@@ -193,6 +260,36 @@ __global__ __launch_bounds__(256) void k_d1_transpose(SigmaArgs A, const double 
 
 }  // namespace isci
 
+namespace isci {
+namespace {
+
+// One spin block of vectors v0 .. v0 + nv - 1 (nv <= kD1Chunk): the Gram
+// kernel over the spectator sets of A's row spin, then the ordered sum of
+// its set groups into slot `slot` of d1.  A spin without electrons has no
+// sets and gets zeros (c is not read).
+isci_status gram_pass(const SigmaArgs &A, const double *c, int64_t ldc, int nv, double *part, double *d1, int slot,
+                      int v0, hipStream_t s)
+{
+    const int norb = A.norb, n = A.sa.n;
+    const long long nsets = (n >= 1) ? binom(norb, n - 1) : 0;
+    // set groups G and column-piece streams P with G * P <= kGramGroups slabs
+    const int G = (int)std::min<long long>(nsets, 16);
+    const int P = G > 0 ? kGramGroups / G : 0;
+    const int ntile = (norb + kGT - 1) / kGT;
+    if (G > 0) {
+        k_d1_gram<<<dim3((unsigned)(ntile * ntile), (unsigned)(G * P), (unsigned)nv), 256, 0, s>>>(
+            A, c, ldc, nv, (int)nsets, G, P, kGramPiece, ntile, part);
+        ISCI_HIP(hipGetLastError());
+    }
+    const int64_t tot = (int64_t)nv * norb * norb;
+    k_d1_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(part, G * P, nv, norb, d1, slot, v0);
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
+}  // namespace
+}  // namespace isci
+
 using namespace isci;
 
 extern "C" {
@@ -207,23 +304,18 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
     const char *d0 = (const char *)d1, *e1 = (const char *)(d1 + nd);
     if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
     const SigmaArgs A = sigma_args(h);
-    const unsigned npq = (unsigned)((h->norb * h->norb + 3) / 4);   // workgroups of four elements
-    k_d1_rows<<<dim3(npq, (unsigned)nvec), kD1Threads, 0, stream>>>(A, c, ldc, d1, 0, 0);
-    ISCI_HIP(hipGetLastError());
-    // beta: the same kernel on the spin-swapped layout, kD1Chunk vectors at a time
-    SigmaArgs T = A;
+    SigmaArgs T = A;   // the spin-swapped layout: beta strings index the rows
     T.sa = A.sb;
     T.sb = A.sa;
     T.astr = A.bstr;
     T.bstr = A.astr;
     T.alev = A.blev;
     T.blev = A.alev;
-    if (h->nb == 0) {   // no beta strings to replace: the kernel writes zeros without reading c
-        k_d1_rows<<<dim3(npq, (unsigned)nvec), kD1Threads, 0, stream>>>(T, c, ldc, d1, 1, 0);
-        ISCI_HIP(hipGetLastError());
-        return ISCI_OK;
+    if (!h->d.d1part) {
+        h->d.d1part = (double *)dev_alloc(h, sizeof(double) * kGramGroups * kD1Chunk * (size_t)h->norb * h->norb);
+        if (!h->d.d1part) { set_error("isci_density1: out of device memory"); return ISCI_E_OOM; }
     }
-    if (!h->d.d1T) {
+    if (h->nb > 0 && !h->d.d1T) {
         const int nsb = h->sb.nstr;
         std::vector<int64_t> rt(nsb + 1);
         rt[0] = 0;
@@ -239,11 +331,13 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
     T.rowstart = h->d.d1T_rowstart;
     for (int v0 = 0; v0 < nvec; v0 += kD1Chunk) {
         const int nv = std::min(kD1Chunk, nvec - v0);
-        k_d1_transpose<<<h->nplan, 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1T_rowstart, h->dim,
-                                                      h->d.d1T);
-        ISCI_HIP(hipGetLastError());
-        k_d1_rows<<<dim3(npq, (unsigned)nv), kD1Threads, 0, stream>>>(T, h->d.d1T, h->dim, d1, 1, v0);
-        ISCI_HIP(hipGetLastError());
+        ISCI_CHECK(gram_pass(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1part, d1, 0, v0, stream));
+        if (h->nb > 0) {
+            k_d1_transpose<<<h->nplan, 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1T_rowstart,
+                                                          h->dim, h->d.d1T);
+            ISCI_HIP(hipGetLastError());
+        }
+        ISCI_CHECK(gram_pass(T, h->d.d1T, h->dim, nv, h->d.d1part, d1, 1, v0, stream));
     }
     return ISCI_OK;
 }
