@@ -221,11 +221,12 @@ isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
  * overwritten, must not overlap c.  Every determinant pair connected by
  * a+_p a_q counts; the screening threshold plays no part.  Deterministic
  * (fixed summation order).  The beta block is computed from the vectors
- * transposed into the spin-swapped layout, four at a time, in a buffer the
- * handle allocates on its first density call with beta electrons and keeps
- * until it is destroyed (4 * dim doubles and nstr_beta + 1 int64; that
- * first call also copies the row starts synchronously).  Calls on one
- * handle share the buffer and must be ordered.  Otherwise asynchronous on
+ * transposed into the spin-swapped layout, eight at a time.  The handle
+ * allocates on its first density call, and keeps until it is destroyed,
+ * 64 * 8 * norb^2 doubles of partial sums and, with beta electrons, 8 * dim
+ * doubles and nstr_beta + 1 int64 for the transposed vectors (that first
+ * call also copies the row starts synchronously).  Calls on one handle
+ * share these buffers and must be ordered.  Otherwise asynchronous on
  * `stream`.  Errors: ISCI_E_INVALID for NULL pointers, nvec or ldc out of
  * range, overlap; ISCI_E_OOM if the buffer cannot be allocated. */
 isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,

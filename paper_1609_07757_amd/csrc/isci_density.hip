@@ -31,8 +31,8 @@ namespace isci {
 
 namespace {
 
-constexpr int kD1Chunk = 4;
-constexpr int kGramGroups = 64;   // spectator-set groups summed in fixed order by k_d1_reduce   // vectors per transposed batch (the handle keeps kD1Chunk * dim doubles)
+constexpr int kD1Chunk = 8;   // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
+constexpr int kGramGroups = 64;   // partial slabs (set groups x piece streams) summed in order by k_d1_reduce
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
 __device__ inline double wave_sum(double x)
