@@ -107,7 +107,7 @@ __device__ inline void unrank_set(uint32_t s, int k, int norb, int *S)
 // shared out; it writes the tile to part[g * P + p][v] (norb x norb).
 constexpr int kGT = 64;   // output tile edge (rows)
 constexpr int kGK = 32;   // K step staged in LDS
-constexpr int kGramPiece = 2 * kGK;   // phase-1 columns per piece
+constexpr int kGramPiece = kGK;   // phase-1 columns per piece
 
 __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__restrict__ c, int64_t ldc, int nv,
                                                  int nsets, int G, int P, int W, int ntile, double *__restrict__ part)
