@@ -49,7 +49,9 @@ def _gpu_d1(hd, c, ld=None):
 @pytest.mark.parametrize("recipe,norb,na,nb,L", [
     ("A", 6, 2, 2, 2), ("B", 7, 3, 1, 3), ("R", 8, 4, 4, 3), ("A", 9, 2, 2, 3), ("R", 5, 1, 0, 1),
     ("B", 6, 3, 3, 6), ("A", 12, 2, 2, 4), ("A", 20, 2, 2, 2), ("B", 10, 3, 2, 3), ("A", 30, 2, 2, 3),
-    ("R", 7, 2, 1, 2), ("R", 6, 1, 1, 2)])
+    ("R", 7, 2, 1, 2), ("R", 6, 1, 1, 2),
+    # above 64 orbitals the output has several 64 x 64 tiles
+    ("A", 100, 2, 2, 1), ("B", 70, 2, 2, 2), ("R", 66, 3, 2, 1), ("A", 130, 1, 1, 2), ("R", 90, 2, 1, 2)])
 def test_density1_parity(recipe, norb, na, nb, L):
     h, eri = _ints(recipe, norb, 3)
     print(f"density1 parity {recipe} norb={norb} na={na} nb={nb} L={L}", flush=True)
@@ -100,5 +102,33 @@ def test_density1_cisdt_n60():
         for s, n in enumerate((W.nalpha, W.nbeta)):
             assert abs(np.trace(d[v, s]) - n * nn[v]) <= 1e-12 * n * nn[v]
             assert np.abs(d[v, s] - d[v, s].T).max() <= TOL * scale
+        e1 = (h * (d[v, 0] + d[v, 1])).sum()
+        assert abs(e1 - e[v]) <= 1e-11 * np.abs(h).sum() * scale
+
+
+def test_density1_cisdt_n160_properties():
+    """Served-size space (CISDT, 160 orbitals, 7,963,991 determinants, 4
+    vectors, nine output tiles): traces, symmetry and the one-body energy
+    identity against the library's sigma for zero two-electron integrals."""
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    W = workload("cisdt_n160")
+    h, _eri = W.integrals()
+    del _eri
+    print("density1 cisdt_n160 properties", flush=True)
+    hd = create(h, np.zeros((W.norb,) * 4), W.norb, W.nalpha, W.nbeta, W.level, 0.0)
+    c = torch.from_numpy(random_vectors(hd.dim, 4, seed=23)).to(dev)
+    d = isci.isci_density1(hd, c)
+    sg = isci.isci_sigma(hd, c)
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    cn = c.cpu().numpy()
+    e = (cn * sg.cpu().numpy()).sum(1)
+    nn = (cn * cn).sum(1)
+    scale = np.abs(d).max()
+    for v in range(4):
+        for s_, n in enumerate((W.nalpha, W.nbeta)):
+            assert abs(np.trace(d[v, s_]) - n * nn[v]) <= 1e-12 * n * nn[v]
+            assert np.abs(d[v, s_] - d[v, s_].T).max() <= TOL * scale
         e1 = (h * (d[v, 0] + d[v, 1])).sum()
         assert abs(e1 - e[v]) <= 1e-11 * np.abs(h).sum() * scale
