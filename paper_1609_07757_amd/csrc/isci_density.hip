@@ -119,7 +119,11 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
     __shared__ int kmin_s, kmax_s;
     __shared__ double ph2[4][4];
     const int norb = A.norb, n = A.sa.n, tid = threadIdx.x;
-    const int tp = blockIdx.x / ntile, tq = blockIdx.x - tp * ntile;
+    // tile pair number blockIdx.x of the upper triangle tp <= tq (row-major);
+    // each set's Gram matrix is symmetric, so the lower tiles are not formed
+    int tp = 0, rem = blockIdx.x;
+    while (rem >= ntile - tp) { rem -= ntile - tp; ++tp; }
+    const int tq = tp + rem;
     const int P0 = tp * kGT, Q0 = tq * kGT;
     const bool same = (tp == tq);
     const int gp = blockIdx.y, g = gp / P, pc = gp - g * P, v = blockIdx.z;
@@ -227,6 +231,8 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
 }
 
 // d1[v0 + v][slot] = sum over g (in order) of part[g][v]; G = 0 writes zeros.
+// Elements whose row tile lies below their column tile were not formed:
+// they are read at the mirrored position (the sums are symmetric).
 __global__ __launch_bounds__(256) void k_d1_reduce(const double *__restrict__ part, int G, int nv, int norb,
                                                    double *__restrict__ d1, int slot, int v0)
 {
@@ -235,8 +241,10 @@ __global__ __launch_bounds__(256) void k_d1_reduce(const double *__restrict__ pa
     if (t >= nv * nn) return;
     const int v = (int)(t / nn);
     const int64_t pq = t - v * nn;
+    const int p = (int)(pq / norb), q = (int)(pq - (int64_t)p * norb);
+    const int64_t src = (p / kGT > q / kGT) ? (int64_t)q * norb + p : pq;
     double s = 0.0;
-    for (int g = 0; g < G; ++g) s += part[((int64_t)g * nv + v) * nn + pq];
+    for (int g = 0; g < G; ++g) s += part[((int64_t)g * nv + v) * nn + src];
     d1[((int64_t)(v0 + v) * 2 + slot) * nn + pq] = s;
 }
 
@@ -277,7 +285,7 @@ isci_status gram_pass(const SigmaArgs &A, const double *c, int64_t ldc, int nv, 
     const int P = G > 0 ? kGramGroups / G : 0;
     const int ntile = (norb + kGT - 1) / kGT;
     if (G > 0) {
-        k_d1_gram<<<dim3((unsigned)(ntile * ntile), (unsigned)(G * P), (unsigned)nv), 256, 0, s>>>(
+        k_d1_gram<<<dim3((unsigned)(ntile * (ntile + 1) / 2), (unsigned)(G * P), (unsigned)nv), 256, 0, s>>>(
             A, c, ldc, nv, (int)nsets, G, P, kGramPiece, ntile, part);
         ISCI_HIP(hipGetLastError());
     }
