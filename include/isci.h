@@ -224,9 +224,8 @@ isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
  * transposed into the spin-swapped layout, eight at a time.  The handle
  * allocates on its first density call, and keeps until it is destroyed,
  * 64 * 8 * norb^2 doubles of partial sums and, with beta electrons, 8 * dim
- * doubles and nstr_beta + 1 int64 for the transposed vectors (that first
- * call also copies the row starts synchronously).  Calls on one handle
- * share these buffers and must be ordered.  Otherwise asynchronous on
+ * doubles for the transposed vectors.  Calls on one handle share these
+ * buffers and must be ordered.  Otherwise asynchronous on
  * `stream`.  Errors: ISCI_E_INVALID for NULL pointers, nvec or ldc out of
  * range, overlap; ISCI_E_OOM if the buffer cannot be allocated. */
 isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,

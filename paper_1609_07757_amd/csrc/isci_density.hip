@@ -248,20 +248,51 @@ __global__ __launch_bounds__(256) void k_d1_reduce(const double *__restrict__ pa
     d1[((int64_t)(v0 + v) * 2 + slot) * nn + pq] = s;
 }
 
-// Vectors v < nv of c into the spin-swapped layout: determinant (ia, j) of
-// c (row ia, beta string j) goes to row j, position ia of cT (leading
-// dimension dim).  One thread per determinant, workgroups laid out by
-// row_block; reads are coalesced along the row, writes are scattered.
+// Vectors v < nv of c into the spin-swapped layout (row = beta string j,
+// position = alpha string ia; leading dimension dim).  The determinants of
+// one (alpha level ka, beta level kb) pair form a dense block in both
+// layouts: in c, row ia starts at baseA + (ia - first) * le_b[L - ka]; in
+// cT, row j starts at baseB + (j - first) * le_a[L - kb].  Each workgroup
+// moves one 32 x 32 tile of one block through LDS, reading along beta and
+// writing along alpha, so both sides are coalesced.  Workgroups are
+// numbered block by block (ka outer, kb inner), tile rows outer.
 __global__ __launch_bounds__(256) void k_d1_transpose(SigmaArgs A, const double *__restrict__ c, int64_t ldc, int nv,
-                                                      const int64_t *__restrict__ rowT, int64_t dim,
-                                                      double *__restrict__ cT)
+                                                      int64_t dim, double *__restrict__ cT)
 {
-    int ia, j0, len;
-    row_block(A, blockIdx.x, ia, j0, len);
-    const int j = j0 + threadIdx.x;
-    if (j >= len) return;
-    const int64_t src = A.rowstart[ia] + j, dst = rowT[j] + ia;
-    for (int v = 0; v < nv; ++v) cT[(int64_t)v * dim + dst] = c[(int64_t)v * ldc + src];
+    __shared__ double tile[32][33];
+    int b = blockIdx.x, ka = 0, kb = 0, ntj = 1;
+    for (ka = 0; ka <= A.sa.maxlev; ++ka) {
+        bool found = false;
+        for (kb = 0; kb <= min(A.L - ka, A.sb.maxlev); ++kb) {
+            const int na = A.sa.lev_off[ka + 1] - A.sa.lev_off[ka], nb = A.sb.lev_off[kb + 1] - A.sb.lev_off[kb];
+            ntj = (nb + 31) >> 5;
+            const int nt = ((na + 31) >> 5) * ntj;
+            if (b < nt) { found = true; break; }
+            b -= nt;
+        }
+        if (found) break;
+    }
+    if (ka > A.sa.maxlev) return;   // beyond the last tile (not launched)
+    const int a0 = A.sa.lev_off[ka], a1 = A.sa.lev_off[ka + 1];
+    const int j0 = A.sb.lev_off[kb], j1 = A.sb.lev_off[kb + 1];
+    const int ia0 = a0 + (b / ntj) * 32, jb0 = j0 + (b % ntj) * 32;
+    const int64_t baseA = row_start(A.sa, A.sb, A.L, a0, ka), strideA = A.sb.le[A.L - ka];
+    const int64_t baseB = row_start(A.sb, A.sa, A.L, j0, kb), strideB = A.sa.le[A.L - kb];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int v = 0; v < nv; ++v) {
+        const double *cv = c + (int64_t)v * ldc;
+        double *tv = cT + (int64_t)v * dim;
+        for (int r = ty; r < 32; r += 8) {
+            const int ia = ia0 + r, j = jb0 + tx;
+            if (ia < a1 && j < j1) tile[r][tx] = cv[baseA + (int64_t)(ia - a0) * strideA + j];
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int j = jb0 + r, ia = ia0 + tx;
+            if (ia < a1 && j < j1) tv[baseB + (int64_t)(j - j0) * strideB + ia] = tile[tx][r];
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -270,6 +301,19 @@ __global__ __launch_bounds__(256) void k_d1_transpose(SigmaArgs A, const double 
 
 namespace isci {
 namespace {
+
+// Workgroups of k_d1_transpose: 32 x 32 tiles of every (alpha level, beta
+// level) block of the space.
+unsigned transpose_tiles(const isci_ctx *h)
+{
+    unsigned n = 0;
+    for (int ka = 0; ka <= h->sa.maxlev; ++ka)
+        for (int kb = 0; kb <= std::min(h->L - ka, h->sb.maxlev); ++kb) {
+            const int na = h->sa.lev_off[ka + 1] - h->sa.lev_off[ka], nb = h->sb.lev_off[kb + 1] - h->sb.lev_off[kb];
+            n += (unsigned)(((na + 31) / 32) * ((nb + 31) / 32));
+        }
+    return n;
+}
 
 // One spin block of vectors v0 .. v0 + nv - 1 (nv <= kD1Chunk): the Gram
 // kernel over the spectator sets of A's row spin, then the ordered sum of
@@ -329,20 +373,15 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
         rt[0] = 0;
         for (int j = 0; j < nsb; ++j) rt[j + 1] = rt[j] + h->sa.le[h->L - h->h_blev[j]];
         if (rt[nsb] != h->dim) { set_error("isci_density1: transposed layout size mismatch"); return ISCI_E_INVALID; }
-        int64_t *rtd = (int64_t *)dev_alloc(h, sizeof(int64_t) * (nsb + 1));
         double *buf = (double *)dev_alloc(h, sizeof(double) * kD1Chunk * (size_t)h->dim);
-        if (!rtd || !buf) { set_error("isci_density1: out of device memory"); return ISCI_E_OOM; }
-        ISCI_HIP(hipMemcpy(rtd, rt.data(), sizeof(int64_t) * (nsb + 1), hipMemcpyHostToDevice));
-        h->d.d1T_rowstart = rtd;
+        if (!buf) { set_error("isci_density1: out of device memory"); return ISCI_E_OOM; }
         h->d.d1T = buf;
     }
-    T.rowstart = h->d.d1T_rowstart;
     for (int v0 = 0; v0 < nvec; v0 += kD1Chunk) {
         const int nv = std::min(kD1Chunk, nvec - v0);
         ISCI_CHECK(gram_pass(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1part, d1, 0, v0, stream));
         if (h->nb > 0) {
-            k_d1_transpose<<<h->nplan, 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1T_rowstart,
-                                                          h->dim, h->d.d1T);
+            k_d1_transpose<<<transpose_tiles(h), 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->dim, h->d.d1T);
             ISCI_HIP(hipGetLastError());
         }
         ISCI_CHECK(gram_pass(T, h->d.d1T, h->dim, nv, h->d.d1part, d1, 1, v0, stream));

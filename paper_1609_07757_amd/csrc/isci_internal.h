@@ -114,7 +114,6 @@ struct DevTabs {
     // density matrices: vectors in the spin-swapped layout (rows = beta
     // strings holding alpha prefixes), allocated by the first density call
     double *d1T = nullptr;          // [kD1Chunk][dim]
-    int64_t *d1T_rowstart = nullptr; // [nstr_b + 1]
     double *d1part = nullptr;       // [kGramGroups][kD1Chunk][norb][norb] partial Gram sums
 };
 
