@@ -560,7 +560,15 @@ static void diag_cb(void *vctx, int64_t j, double su, int bucket, int kept)
 {
     (void)bucket;
     diag_ctx *x = (diag_ctx *)vctx;
+#if defined(ORC_PLANT_DIAG_ROWSUM)
+    (void)j;
+    if (kept) x->acc += su;
+#elif defined(ORC_PLANT_DIAG_UNSCREENED)
+    (void)kept;
+    if (j == x->self) x->acc += su;
+#else
     if (kept && j == x->self) x->acc += su;
+#endif
 }
 
 int orc_diag(void *hs, const double *h, const double *eri, double tau,

@@ -6,10 +6,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
   closed-form space dimension, which reproduces the paper's table of
   determinant counts (application section, table of orbitals and
   coefficients), and by brute-force enumeration in the tests.
-* ``sigma`` / ``dense_h`` / ``diag``: pinned by the closed-form reference
-  energy, Hermiticity, the non-interacting limit, the one-electron-per-spin
+* ``sigma`` / ``dense_h``: pinned by the closed-form reference energy,
+  Hermiticity, the non-interacting limit, the one-electron-per-spin
   Kronecker construction, orbital-rotation invariance of FCI, alpha/beta
   swap covariance and exact diagonalisation (tests/test_oracle_*.py).
+* ``diag``: pinned by the textbook Slater-Condon diagonal of every
+  determinant (unit by unit under the keep rule), by the diagonal of the
+  pinned ``dense_h``, and by the closed-form reference energy of the
+  relabelled Hamiltonian for closed-shell determinants; two planted
+  mistakes (whole row summed, screened units counted) are rejected.
 * ``apply_word``: pinned by the paper's two worked sign examples
   (Eqs. contract and add).
 * ``terms``: pinned by an independent closed-form count in the tests.

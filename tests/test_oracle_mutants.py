@@ -17,10 +17,12 @@ MUTANTS = [
     "ORC_PLANT_SINGLE_NOSIGN",    # phase of single excitations ignored
     "ORC_PLANT_DROP_AB_DIAG",     # dropped alpha-beta Coulomb term of the diagonal
     "ORC_PLANT_KEEP_GE",          # keep rule |I| >= tau instead of |I| > tau
+    "ORC_PLANT_DIAG_ROWSUM",      # diagonal: the j == I filter dropped (whole row summed)
+    "ORC_PLANT_DIAG_UNSCREENED",  # diagonal: screened units counted
 ]
 
 PINS = ("reference_energy or hermiticity or noninteracting or kronecker or rotation "
-        "or swap or strict or term_counts_integral")
+        "or swap or strict or term_counts_integral or diag_")
 
 
 @pytest.mark.parametrize("macro", MUTANTS)

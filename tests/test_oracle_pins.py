@@ -147,6 +147,69 @@ def test_hermiticity(recipe, norb, na, nb, L, tau):
     assert abs(u @ sv - v @ su) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * np.abs(H).max()
 
 
+# ---------------------------------------------------------------- diagonal
+def _slater_condon_diag(h, eri, A, B, tau):
+    """Textbook Slater-Condon diagonal of the determinant with alpha
+    orbitals A and beta orbitals B, as a sum of units (h_pp; per same-spin
+    pair (pp|qq) - (pq|qp) formed by one subtraction; per alpha-beta pair
+    (pp|qq)), each kept iff |unit| > tau."""
+    units = [h[p, p] for p in A] + [h[p, p] for p in B]
+    for S in (A, B):
+        units += [eri[p, p, q, q] - eri[p, q, q, p] for i, p in enumerate(S) for q in S[i + 1:]]
+    units += [eri[p, p, q, q] for p in A for q in B]
+    return sum(u for u in units if abs(u) > tau)
+
+
+@pytest.mark.parametrize("recipe", ["A", "B", "R"])
+@pytest.mark.parametrize("norb,na,nb,L,tau", [(7, 2, 2, 2, 0.0), (7, 2, 2, 3, 1e-6), (6, 3, 2, 3, 0.0),
+                                              (8, 2, 2, 4, 1e-3), (7, 3, 2, 3, 0.2), (6, 1, 1, 2, 0.05)])
+def test_diag_slater_condon_and_dense_diagonal(recipe, norb, na, nb, L, tau):
+    """The oracle diagonal (section on diagonal classes; Eq. ham) equals the
+    Slater-Condon diagonal of every determinant, unit by unit under the
+    strict keep rule, and the diagonal of the dense H_tau."""
+    h, eri = _ints(recipe, norb, 5)
+    h = 0.5 * (h + h.T)
+    S = O.Space(norb, na, nb, L)
+    d = O.diag(S, h, eri, tau)
+    H = O.dense_h(S, h, eri, tau)
+    scale = max(1.0, np.abs(d).max())
+    assert np.abs(d - np.diag(H)).max() <= 1e-14 * scale
+    ao, _ = S.strings(0)
+    bo, _ = S.strings(1)
+    rs = S.rowstart()
+    ref = np.empty(S.dim)
+    for ia in range(len(rs) - 1):
+        for j in range(rs[ia + 1] - rs[ia]):
+            ref[rs[ia] + j] = _slater_condon_diag(h, eri, list(ao[ia]), list(bo[j]), tau)
+    assert np.abs(d - ref).max() <= 1e-13 * scale
+
+
+def test_diag_closed_shell_relabelled_reference():
+    """A closed-shell determinant (same orbitals in both spins) is the
+    reference of the Hamiltonian with its orbitals relabelled to 0..n-1, so
+    its diagonal element is that Hamiltonian's closed-form E_ref."""
+    norb, n, L = 7, 2, 4
+    h, eri = _ints("R", norb, 8)
+    S = O.Space(norb, n, n, L)
+    d = O.diag(S, h, eri, 0.0)
+    ao, _ = S.strings(0)
+    rs = S.rowstart()
+    bo, _ = S.strings(1)
+    checked = 0
+    for ia in range(len(rs) - 1):
+        for j in range(rs[ia + 1] - rs[ia]):
+            if list(ao[ia]) != list(bo[j]):
+                continue
+            occ = list(ao[ia])
+            perm = occ + [p for p in range(norb) if p not in occ]
+            hp = h[np.ix_(perm, perm)]
+            ep = eri[np.ix_(perm, perm, perm, perm)]
+            e = O.e_ref_closed_form(hp, ep, n, n)
+            assert abs(d[rs[ia] + j] - e) <= 1e-13 * max(1.0, abs(e))
+            checked += 1
+    assert checked == comb(norb, n)
+
+
 # ---------------------------------------------------------------- P7
 def test_noninteracting_limit():
     """eri = 0: FCI ground energy is the sum of the lowest na + nb orbital
