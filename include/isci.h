@@ -51,8 +51,10 @@
  * errors are detected before anything is enqueued.  isci_last_error()
  * returns a per-thread message for the last failure.
  *
- * Limits of this build: norb <= 255, 0 <= na, nb <= 4, dim < 2^62,
- * nvec >= 1 (vectors are processed in chunks of 8).
+ * Limits of this build: norb <= 255 (<= 200 with two electrons of each
+ * spin), 0 <= na, nb <= 4, dim < 2^62, nvec >= 1 (vectors are processed
+ * in chunks of 8).  isci_create refuses (ISCI_E_INVALID) integrals that
+ * hold a NaN or an infinity in a position it reads.
  */
 #ifndef ISCI_H
 #define ISCI_H
@@ -122,7 +124,14 @@ void isci_davidson_defaults(isci_davidson_opts *o);
  * count kept units and sigma terms per bucket, and tabulate the diagonal
  * units.  h: device [norb*norb]; eri: device [norb^4] ((pq|rs) at
  * ((p*norb+q)*norb+r)*norb+s).  Both are only read during this call (in
- * stream order; the call synchronises the stream before returning). */
+ * stream order; the call synchronises the stream before returning).
+ * Errors: ISCI_E_INVALID for NULL pointers, norb < 1, electron counts
+ * outside [0, norb], max_excitation < 0, tau negative, NaN or infinite,
+ * and for a NaN or infinity in any element that is read (one device pass
+ * over them before the lists are built: such a unit would fail
+ * |unit| > tau and vanish silently); ISCI_E_UNSUPPORTED beyond the limits
+ * above; ISCI_E_OOM / ISCI_E_HIP on device failures (the handle is not
+ * created). */
 isci_status isci_create(isci_handle *out, const double *h, const double *eri, int norb,
                         int nalpha, int nbeta, int max_excitation, double tau,
                         hipStream_t stream);
@@ -171,7 +180,12 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
                            int nalpha, int nbeta, int max_excitation, double tau,
                            const isci_create_opts *opts, hipStream_t stream);
 
-/* Number of determinants. */
+/* Number of determinants of the truncated space: the terms of the CI
+ * expansion (Eq. ci_ansatz) kept by the excitation hierarchy cut at
+ * max_excitation (Eq. ci_hierarchy), counted per (alpha, beta) string
+ * pair with level_a + level_b <= max_excitation.  *dim (host) receives the
+ * length of every vector the handle reads or writes.  ISCI_E_INVALID if
+ * hd or dim is NULL.  No device work. */
 isci_status isci_dim(isci_handle hd, int64_t *dim);
 
 /* sigma[v*lds + I] = sum_J (H_tau)_IJ c[v*ldc + J] for v < nvec, all I
@@ -208,8 +222,15 @@ isci_status isci_sigma_graph_create(isci_handle hd, int nvec, const double *c, i
 isci_status isci_graph_launch(isci_graph g, hipStream_t stream);
 void isci_graph_destroy(isci_graph g);
 
-/* diag[I] = (H_tau)_II (the diagonal units kept by the same rule).
- * Device array of length dim.  Asynchronous. */
+/* diag[I] = (H_tau)_II, the Slater-Condon diagonal of determinant I of
+ * the Hamiltonian of Eq. ham: the diagonal integrals of the classes present
+ * in each diagonal block (section "The excitation class formalism", the
+ * paper's list of classes of the reference block, of which only the
+ * diagonal integrals are used), i.e. h_pp per occupied orbital,
+ * (pp|qq) - (pq|qp) per same-spin pair and (pp|qq) per alpha-beta pair,
+ * each unit kept by the same rule |unit| > tau as sigma.  diag: device
+ * array of length dim, written (caller-owned).  Asynchronous on stream.
+ * ISCI_E_INVALID for NULL arguments; ISCI_E_HIP if the launch fails. */
 isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
 
 /* One-body density matrix of each vector, by spin (the paper's density
@@ -231,8 +252,14 @@ isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
 isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,
                           hipStream_t stream);
 
-/* Lowest nroots eigenpairs by block Davidson (FP64, device resident; the
- * small projected eigenproblem is solved on the host).  guess: device
+/* Lowest nroots eigenpairs of H_tau, the eigenvalue problem of Eq. hcec
+ * that the paper solves by repeated sigma steps (Eq. sigma) inside an
+ * iterative optimiser (Davidson or Lanczos, in the text after Eq. sigma):
+ * here block Davidson (FP64, device resident; the small projected
+ * eigenproblem is solved on the host), with the diagonal of isci_diag as
+ * preconditioner.  Errors: ISCI_E_INVALID for NULL hd or energies, nroots
+ * outside [1, min(dim, ISCI_MAX_ROOTS)] or bad options; ISCI_E_OOM when the
+ * subspace does not fit; ISCI_E_HIP on a runtime failure.  guess: device
  * [nguess][dim] or NULL (unit vectors on the lowest diagonal entries,
  * ties to the lowest address).  energies: host [nroots].  vectors: device
  * [nroots][dim] or NULL.  info may be NULL.  Returns ISCI_E_NOT_CONVERGED
@@ -241,13 +268,22 @@ isci_status isci_davidson(isci_handle hd, int nroots, const isci_davidson_opts *
                           const double *guess, int nguess, double *energies, double *vectors,
                           isci_davidson_info *info, hipStream_t stream);
 
-/* Host copies of the string tables: orbitals [nstr][n] (ascending) and
- * level [nstr] in layout order; either pointer may be NULL.  spin 0 is
- * alpha, 1 beta. */
+/* Host copies of the string tables of one spin: the occupation strings
+ * that build the determinants of Eq. ci_ansatz, with their excitation
+ * level (electrons in virtual orbitals, the particle rank of the spin's
+ * part of the excitation operator of Eq. ci_hierarchy).  orbitals
+ * [nstr][n] (ascending) and level [nstr] in layout order, host arrays
+ * owned by the caller; either pointer may be NULL; *nstr (host) receives
+ * the count.  spin 0 is alpha, 1 beta.  ISCI_E_INVALID for a NULL handle,
+ * a NULL nstr or spin outside {0, 1}.  No device work. */
 isci_status isci_strings(isci_handle hd, int spin, int32_t *orbitals, int32_t *level,
                          int64_t *nstr);
 
-/* Host copy of the row starts: rowstart[nstr_alpha + 1]. */
+/* Host copy of the row starts of the vector layout (the alpha-major
+ * arrangement of the space of Eqs. ci_ansatz / ci_hierarchy described at
+ * the top of this file): rowstart[nstr_alpha + 1], host array owned by
+ * the caller; row Ia occupies [rowstart[Ia], rowstart[Ia + 1]).
+ * ISCI_E_INVALID for NULL arguments.  No device work. */
 isci_status isci_rowstart(isci_handle hd, int64_t *rowstart);
 
 /* Screening statistics (host struct). */

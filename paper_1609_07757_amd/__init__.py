@@ -28,6 +28,8 @@ OPT_AB_PATH = 2
 AB_AUTO, AB_GATHER = 0, 1
 # isci_create_opts.onebody: where the matrix-core path applies the one-body units
 OB_AUTO, OB_SEPARATE, OB_TILES = 0, 1, 2
+# isci_status codes
+OK, E_INVALID, E_OOM, E_HIP, E_NOT_CONVERGED, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 
 
 def isci_set_option(hd, option: int, value: int):

@@ -269,6 +269,9 @@ isci_status launch_ab_fold(const isci_ctx *c, int nv, const double *Sbuf, double
                            hipStream_t s);
 // one-body classes on matrix cores (two electrons per spin, norb <= kObMaxNorb)
 constexpr int kObMaxNorb = 80;
+// largest orbital count accepted with two electrons per spin (the
+// spectator-form one-body kernels are compared with the oracle up to 199)
+constexpr int kPairMaxNorb = 200;
 bool onebody_mfma_ok(const isci_ctx *c);
 // first: the beta classes write sigma (they cover every element) instead
 // of adding, and the alpha classes add

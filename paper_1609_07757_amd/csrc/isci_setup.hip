@@ -302,6 +302,22 @@ __global__ void k_ss_fill(const double *eri, int n, double tau, const int *off, 
         }
 }
 
+// Input check: *bad = 1 if any element the builders read (the canonical
+// element of every (pq|rs), the lower triangle of h) is NaN or infinite.
+// Such a unit would fail |unit| > tau and be screened out silently, so the
+// handle would apply a corrupted H; isci_create refuses it instead.
+__global__ void k_check_finite(const double *h, const double *eri, int n, int *bad)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (t >= n3) return;
+    const int p = (int)(t / ((int64_t)n * n)), q = (int)((t / n) % n), r = (int)(t % n);
+    bool ok = true;
+    for (int s = 0; s < n; ++s) ok &= isfinite(geri(eri, n, p, q, r, s));
+    if (t < (int64_t)n * n) ok &= isfinite(gh(h, n, (int)(t / n), (int)(t % n)));
+    if (!ok) atomicOr(bad, 1);
+}
+
 __global__ void k_ab_count(const double *eri, int n, double tau, long long *cnt)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1032,6 +1048,10 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         set_error("more than 4 electrons per spin is not supported");
         return ISCI_E_UNSUPPORTED;
     }
+    if (nalpha == 2 && nbeta == 2 && norb > kPairMaxNorb) {
+        set_error("two electrons per spin: at most 200 orbitals (the verified range of the large-orbital one-body kernels)");
+        return ISCI_E_UNSUPPORTED;
+    }
     isci_ctx *c = new (std::nothrow) isci_ctx();
     if (!c) { set_error("host allocation failed"); return ISCI_E_OOM; }
     c->norb = norb; c->na = nalpha; c->nb = nbeta; c->tau = tau;
@@ -1135,6 +1155,26 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
                 e2 = hipMemcpyAsync(c->d.arow_len, len.data(), sizeof(int) * len.size(), hipMemcpyHostToDevice, stream);
             if (e2 == hipSuccess) e2 = hipStreamSynchronize(stream);
             if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload row tables"); }
+        }
+    }
+    {
+        // refuse non-finite integrals before any list is built
+        int *bad = nullptr, hbad = 0;
+        const int64_t n3 = (int64_t)norb * norb * norb;
+        hipError_t e3 = hipMallocAsync((void **)&bad, sizeof(int), stream);
+        if (e3 == hipSuccess) e3 = hipMemsetAsync(bad, 0, sizeof(int), stream);
+        if (e3 == hipSuccess) {
+            k_check_finite<<<nblk(n3, 256), 256, 0, stream>>>(h, eri, norb, bad);
+            e3 = hipGetLastError();
+        }
+        if (e3 == hipSuccess) e3 = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (bad) (void)hipFreeAsync(bad, stream);
+        if (e3 == hipSuccess) e3 = hipStreamSynchronize(stream);
+        if (e3 != hipSuccess) { destroy(c); return hip_fail(e3, "integral check"); }
+        if (hbad) {
+            destroy(c);
+            set_error("h or eri holds a NaN or infinite value in a position that is read");
+            return ISCI_E_INVALID;
         }
     }
     isci_status st = build_lists(c, h, eri, stream);

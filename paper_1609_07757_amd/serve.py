@@ -67,13 +67,27 @@ def davidson_bytes(dim: int, nroots: int) -> int:
     return 8 * dim * (2 * mmax + nscr + 2 * kk + 1) + 8 * (mmax * mmax + 8 * mmax + 64 + nblk * mmax * mmax + 3 * (mmax + 8))
 
 
-def handle_bytes_bound(norb: int, dim: int) -> int:
-    """Upper bound of a handle's resident tables (screened lists assume
-    every alpha-beta unit is kept) plus the transient dense eri."""
+def handle_bytes_estimate(norb: int, dim: int) -> int:
+    """Admission estimate of what building a handle needs at its peak: the
+    transient dense eri (8 norb^4), list offsets and tables sized for one
+    kept alpha-beta unit in eight, the product operands (about 16 B per
+    determinant and vector of a 4-vector pass, two result buffers), and
+    above 80 orbitals the transposed one-body blocks (64 B per
+    determinant).  It is an estimate, not a bound: at tau = 0 the lists
+    alone can exceed it.  The server therefore re-charges a running
+    request by what its handle really holds (isci_stats.device_bytes, read
+    after the build) and puts a request whose build ran out of memory back
+    at the head of the queue."""
     n3 = norb ** 3
     lists = 8 * (n3 + 1) + 9 * norb ** 4 // 8 + 4 * norb * norb * 16
     strings = 8 * (norb * norb) * 4
-    return 8 * norb ** 4 + lists + strings + 8 * dim
+    operands = 3 * 16 * 4 * dim
+    onebody = 64 * dim if norb > 80 else 0
+    return 8 * norb ** 4 + lists + strings + 8 * dim + operands + onebody
+
+
+# kept for callers of the earlier name
+handle_bytes_bound = handle_bytes_estimate
 
 
 class Server:
@@ -102,6 +116,7 @@ class Server:
         self.steps = 0
         self.peak_used = 0
         self.peak_running = 0
+        self.oom_requeued = 0
 
     def _now(self):
         return self.clock() - self._t0
@@ -139,11 +154,27 @@ class Server:
             if self.used + need > self.budget:
                 break
             self.queue.popleft()
-            tok = self.ex.start(r)
+            try:
+                tok = self.ex.start(r)
+            except MemoryError:
+                # the build ran out of device memory (the estimate was low):
+                # back to the head of the queue until a running solve frees
+                # memory; with nothing running there is nothing to wait for
+                if not self.running:
+                    r.status = "rejected"
+                    r.finished = self._now()
+                    self.done.append(r)
+                    continue
+                self.queue.appendleft(r)
+                self.oom_requeued += 1
+                break
+            # charge what the request really holds from now on
+            charge = getattr(self.ex, "charge", None)
+            held = int(charge(tok)) if charge is not None else need
             r.admitted = self._now()
             r.status = "running"
-            self.running[tok] = (r, need)
-            self.used += need
+            self.running[tok] = (r, held)
+            self.used += held
             self.peak_used = max(self.peak_used, self.used)
         self.peak_running = max(self.peak_running, len(self.running))
 
@@ -197,7 +228,8 @@ class Server:
     def report(self):
         lat = np.array([r.latency for r in self.done if r.status == "done"])
         out = {"served": int(len(lat)), "rejected": sum(r.status == "rejected" for r in self.done),
-               "steps": self.steps, "peak_running": self.peak_running, "peak_bytes": self.peak_used}
+               "steps": self.steps, "peak_running": self.peak_running, "peak_bytes": self.peak_used,
+               "oom_requeued": self.oom_requeued}
         if len(lat):
             out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                         "mean_s": float(lat.mean())})
@@ -236,23 +268,47 @@ class GpuExecutor:
         self.fast_share = float(fast_share)
         self.sigma_vectors = 0
         self.handles = {}
+        self._roots = {}
         self.active = [0, 0]
         self.tclass = [0.0, 0.0]
 
     def footprint(self, r: Request) -> int:
         dim = ci_dim(r.norb, r.nalpha, r.nbeta, r.level)
-        return handle_bytes_bound(r.norb, dim) + davidson_bytes(dim, r.nroots)
+        return handle_bytes_estimate(r.norb, dim) + davidson_bytes(dim, r.nroots)
 
     def start(self, r: Request):
-        h, eri = r.payload()
-        hd = self.isci.isci_create(h, eri, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
-        del h, eri
-        cls = 0 if hd.dim <= self.fast_dim else 1
-        slot = self.isci.isci_engine_add(self.engs[cls], hd, nroots=r.nroots, **self.opts)
+        """Build the handle and admit the solve.  Raises MemoryError (after
+        freeing what it took) when the device runs out of memory."""
+        import torch
+        hd = None
+        try:
+            h, eri = r.payload()
+            hd = self.isci.isci_create(h, eri, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
+            del h, eri
+            cls = 0 if hd.dim <= self.fast_dim else 1
+            slot = self.isci.isci_engine_add(self.engs[cls], hd, nroots=r.nroots, **self.opts)
+        except torch.cuda.OutOfMemoryError as e:
+            if hd is not None:
+                hd.destroy()
+            raise MemoryError(str(e)) from e
+        except self.isci.IsciError as e:
+            if hd is not None:
+                hd.destroy()
+            if e.status == self.isci.E_OOM:
+                raise MemoryError(str(e)) from e
+            raise
         tok = (cls, slot)
         self.handles[tok] = hd
+        self._roots[tok] = r.nroots
         self.active[cls] += 1
         return tok
+
+    def charge(self, tok) -> int:
+        """Device bytes a running request holds: its handle's tables and its
+        Davidson subspace (the dense eri is gone once the handle is built)."""
+        hd = self.handles[tok]
+        st = self.isci.isci_get_stats(hd)
+        return int(st["device_bytes"]) + int(self.isci.isci_davidson_footprint(hd, self._roots[tok]))
 
     def step(self) -> int:
         """One engine step of the class that is behind its time share (the
@@ -275,6 +331,7 @@ class GpuExecutor:
         cls, slot = tok
         self.isci.isci_engine_release(self.engs[cls], slot)
         hd = self.handles.pop(tok)
+        self._roots.pop(tok, None)
         hd.destroy()
         self.active[cls] -= 1
         if not self.active[cls]:

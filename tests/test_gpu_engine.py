@@ -127,12 +127,16 @@ def test_two_class_server_same_energies():
     import paper_1609_07757_amd as isci
     from paper_1609_07757_amd.serve import GpuExecutor, Request, Server
     torch, dev = torch_dev()
-    alone, reqs = [], []
+    import scipy.linalg
+    alone, reqs, exact = [], [], []
     for i, case in enumerate(MIX):
         h, eri, hd = _make(case, 90 + i)
         alone.append(isci.isci_davidson(hd, nroots=case[4])[0])
         hd.destroy()
         recipe, norb, L, tau, nroots = case
+        S = O.Space(norb, 2, 2, L)
+        exact.append(scipy.linalg.eigh(O.dense_h(S, h, eri, tau), eigvals_only=True,
+                                       subset_by_index=[0, nroots - 1]))
 
         def payload(h=h, eri=eri):
             return (torch.from_numpy(np.ascontiguousarray(h)).to(dev),
@@ -144,4 +148,40 @@ def test_two_class_server_same_energies():
     assert sorted(r.rid for r in done if r.status == "done") == list(range(len(MIX)))
     for r in done:
         assert np.array_equal(np.asarray(r.energies), np.asarray(alone[r.rid])), r.rid
+        # and the served energies are the oracle's (dense eigh of its H_tau)
+        assert np.abs(np.asarray(r.energies) - exact[r.rid]).max() <= 1e-10, r.rid
+    ex.close()
+
+
+@pytest.mark.parametrize("recipe,norb,L,tau", [("B", 20, 3, 0.0), ("A", 96, 2, 1e-12)])
+def test_server_charges_what_the_handle_holds(recipe, norb, L, tau):
+    """A running request is charged its handle's device bytes plus its
+    Davidson subspace (tau = 0 keeps every unit; 96 orbitals takes the
+    large-orbital one-body path with its transposed blocks)."""
+    import paper_1609_07757_amd as isci
+    from paper_1609_07757_amd.serve import GpuExecutor, Request, Server
+    torch, dev = torch_dev()
+    h, eri = (recipe_a if recipe == "A" else recipe_b)(norb, seed=3)
+
+    def payload():
+        return (torch.from_numpy(np.ascontiguousarray(h)).to(dev),
+                torch.from_numpy(np.ascontiguousarray(eri)).to(dev))
+    ex = GpuExecutor(fast_dim=0)
+    srv = Server(ex, hbm_budget=64 << 30, max_slots=4)
+    r = Request(0, 0.0, norb, 2, 2, L, tau, 2, payload=payload)
+    srv.queue.append(r)
+    srv._t0 = srv.clock() if srv.clock else 0.0
+    import time
+    srv.clock = time.perf_counter
+    srv._t0 = srv.clock()
+    srv._admit()
+    (tok, (req, held)), = srv.running.items()
+    hd = ex.handles[tok]
+    st = isci.isci_get_stats(hd)
+    assert held == st["device_bytes"] + isci.isci_davidson_footprint(hd, 2)
+    assert srv.used == held
+    while srv.running:
+        ex.step()
+        srv._retire()
+    assert r.status == "done" and srv.used == 0
     ex.close()

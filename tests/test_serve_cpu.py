@@ -156,3 +156,46 @@ def test_size_class_time_share():
         n[c] += 1
     assert abs(t[0] / (t[0] + t[1]) - 0.75) < 0.01
     assert n[0] > 25 * n[1]
+
+
+class OomExecutor(MockExecutor):
+    """Builds fail with MemoryError while `busy` other solves run above
+    `limit` (an estimate that was too low); running solves are charged a
+    held size different from the admission estimate."""
+
+    def __init__(self, clock, limit):
+        super().__init__(clock, fp=lambda r: 1000)
+        self.limit = limit
+        self.fails = 0
+
+    def start(self, r):
+        if len(self.left) >= self.limit:
+            self.fails += 1
+            raise MemoryError("device out of memory")
+        return super().start(r)
+
+    def charge(self, tok):
+        return 700 + tok
+
+
+def test_oom_build_requeues_and_charges_held_bytes():
+    clk = FakeClock()
+    ex = OomExecutor(clk, limit=2)
+    srv = Server(ex, hbm_budget=10_000, max_slots=8, clock=clk)
+    reqs = _reqs(6, gap=0.0, norbs=[30] * 6)
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done if r.status == "done") == list(range(6))
+    assert ex.fails >= 1 and srv.report()["oom_requeued"] == ex.fails
+    assert ex.running_max <= 2
+    # requests start in arrival order despite the failed builds
+    starts = [rid for kind, rid, _ in ex.log if kind == "start"]
+    assert starts == sorted(starts)
+    assert srv.used == 0
+
+
+def test_oom_with_nothing_running_rejects():
+    clk = FakeClock()
+    ex = OomExecutor(clk, limit=0)
+    srv = Server(ex, hbm_budget=10_000, max_slots=8, clock=clk)
+    done = srv.run(_reqs(2, gap=0.0, norbs=[30, 30]))
+    assert all(r.status == "rejected" for r in done) and len(done) == 2
