@@ -38,6 +38,12 @@ def parse():
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
+    ap.add_argument("--ab", choices=["plain", "pipe"], default="plain",
+                    help="kernel of the alpha-beta block-sparse product")
+    ap.add_argument("--onebody", choices=["transposed", "single"], default="transposed",
+                    help="one-body kernel on the rows / columns that hold every pair")
+    ap.add_argument("--onebody-stream", choices=["side", "inline"], default="side",
+                    help="one-body kernels on the side stream beside the alpha-beta products, or in line")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
@@ -91,6 +97,11 @@ def main():
     variant = {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
                "mfma": isci.SIGMA_MFMA}[a.kernel]
     isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
+    set_ab_product(isci, hd, a.ab)
+    isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL,
+                         isci.ONEBODY_SINGLE if a.onebody == "single" else isci.ONEBODY_TRANSPOSED)
+    isci.isci_set_option(hd, isci.OPT_ONEBODY_STREAM,
+                         isci.ONEBODY_SIDE if a.onebody_stream == "side" else isci.ONEBODY_INLINE)
     st = isci.isci_get_stats(hd)
     dim = hd.dim
     c = torch.from_numpy(random_vectors(dim, nvec, seed=21)).to(dev)
@@ -193,7 +204,8 @@ def main():
         "data": "synthetic (recipe A 1D local-orbital integrals, seeded)",
         "config": {"workload": a.workload, "norb": W.norb, "nalpha": W.nalpha, "nbeta": W.nbeta,
                    "max_excitation": W.level, "tau": tau, "nvec": nvec, "dim": dim,
-                   "box": W.box_len, "naux": W.n_aux, "seed": W.seed},
+                   "box": W.box_len, "naux": W.n_aux, "seed": W.seed, "ab_product": a.ab,
+                   "onebody_kernel": a.onebody, "onebody_stream": a.onebody_stream},
         "screened_terms_per_s": terms_per_s,
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
@@ -218,6 +230,11 @@ def main():
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(W, h, eri, tau, nvec, dim, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def set_ab_product(isci, hd, name):
+    """Kernel of the alpha-beta product: plain ping-pong or software pipeline."""
+    isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, isci.AB_PIPE if name == "pipe" else isci.AB_PLAIN)
 
 
 def density1_timing(isci, torch, hd, c, stream, steps):

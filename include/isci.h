@@ -365,6 +365,34 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_OPT_AB_PATH 2
 #define ISCI_AB_AUTO 0
 #define ISCI_AB_GATHER 1
+/*   ISCI_OPT_AB_PRODUCT (unfold / product / fold path only, for tuning):
+ *   the kernel of the block-sparse product (the alpha-beta classes, Eqs.
+ *   h200ca..h200ab among them, as one screened matrix of (pq|rs) applied
+ *   to the unfolded vectors), one row block pair per workgroup tile:
+ *   ISCI_AB_PLAIN (default) with a two-chunk ping-pong, ISCI_AB_PIPE with
+ *   an explicit two-stage software pipeline (chunk table read one stage
+ *   early).  Same sigma up to rounding order. */
+#define ISCI_OPT_AB_PRODUCT 3
+#define ISCI_AB_PLAIN 0
+#define ISCI_AB_PIPE 1
+/*   ISCI_OPT_ONEBODY_KERNEL (matrix-core one-body classes up to 80
+ *   orbitals, for tuning): ISCI_ONEBODY_TRANSPOSED (default) runs the alpha
+ *   class, where every beta column holds every alpha pair (full CI), as the
+ *   beta class of the transposed block (contiguous rows);
+ *   ISCI_ONEBODY_SINGLE takes two columns per workgroup there.  Same sigma
+ *   up to rounding order. */
+#define ISCI_OPT_ONEBODY_KERNEL 5
+#define ISCI_ONEBODY_SINGLE 1
+#define ISCI_ONEBODY_TRANSPOSED 2
+/*   ISCI_OPT_ONEBODY_STREAM (matrix-core path with separate one-body
+ *   kernels, for tuning): ISCI_ONEBODY_SIDE (default) runs the one-body
+ *   classes on the handle's side stream beside the alpha-beta unfolds and
+ *   products; ISCI_ONEBODY_INLINE runs them before those on the caller's
+ *   stream.  The same kernels in the same order per element: identical
+ *   sigma. */
+#define ISCI_OPT_ONEBODY_STREAM 6
+#define ISCI_ONEBODY_SIDE 0
+#define ISCI_ONEBODY_INLINE 1
 isci_status isci_set_option(isci_handle hd, int option, int value);
 
 /* Kernel timing hook (for measurement).  When enabled, HIP events are

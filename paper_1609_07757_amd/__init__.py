@@ -26,6 +26,15 @@ OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
 OPT_AB_PATH = 2
 AB_AUTO, AB_GATHER = 0, 1
+# kernel of the block-sparse alpha-beta product (tuning; same sigma up to rounding order)
+OPT_AB_PRODUCT = 3
+AB_PLAIN, AB_PIPE = 0, 1
+# one-body kernel where every column holds every pair (tuning)
+OPT_ONEBODY_KERNEL = 5
+ONEBODY_SINGLE, ONEBODY_TRANSPOSED = 1, 2
+# one-body kernels beside the alpha-beta products on a side stream, or in line (tuning)
+OPT_ONEBODY_STREAM = 6
+ONEBODY_SIDE, ONEBODY_INLINE = 0, 1
 # isci_create_opts.onebody: where the matrix-core path applies the one-body units
 OB_AUTO, OB_SEPARATE, OB_TILES = 0, 1, 2
 # isci_status codes

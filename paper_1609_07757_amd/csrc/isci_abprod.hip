@@ -181,6 +181,112 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
         for (int q = 0; q < 4; ++q) Sb[(size_t)gg * 4 * swidth + 16 * q] = acc[q][gg];
 }
 
+// The product of k_ab_gemm with an explicit two-stage software pipeline:
+// the chunks of a wave's list are taken U at a time; while the MFMAs of one
+// stage run, the operand loads of the next stage are in flight and the
+// chunk table of the stage after it is read (scalar loads one stage early,
+// so no operand address waits on the scalar cache).  The table holds only
+// each chunk's T offset; the row width follows from the chunk's class (the
+// list is class ordered).  Loads past the end of the list read the all-zero
+// chunk behind the last one (and a valid T row), so no value is selected
+// after it is loaded.  Scheduling barriers keep every load of a stage ahead
+// of the previous stage's MFMAs.  Tiles, waves and the K split as in
+// k_ab_gemm; same sums in the same order per K part.
+template <int CW, int KS, int U>
+__global__ __launch_bounds__(64 * CW * KS) void k_ab_pipe(SigmaArgs A)
+{
+    __shared__ double red[KS > 1 ? KS - 1 : 1][CW][16][64];
+    const int nb = A.nblk;
+    const AbBlk tb = A.abx_blk[blockIdx.x];   // one scalar load: the tile of this workgroup
+    if (tb.g < 0) return;
+    const int g = tb.g;
+    const int Ab = g / nb, Bb = g % nb;
+    const int m = (Ab != 0) + (Bb != 0);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int cw = wave % CW, part = wave / CW;
+    const int c0 = tb.c0 + cw * 64;
+    const int swidth = A.abx_pcols[m];
+    const bool active = c0 < swidth;
+    const int eb = tb.eb;
+    int ee = eb;
+    for (int l = 0; l < 3; ++l)
+        if (c0 < A.abx_pcols[max(l, m)]) ee = tb.end[l];
+    // parts cut at multiples of 2 U chunks (one loop step)
+    const int step = ((ee - eb + KS - 1) / KS + 2 * U - 1) / (2 * U) * (2 * U);
+    const int e0 = min(ee, eb + step * part);
+    const int e1 = min(ee, eb + step * (part + 1));
+    const int k = lane >> 4, n = lane & 15;
+    const int zc = A.nchunk;
+    const int w0 = A.abx_pcols[0], w1 = A.abx_pcols[1], w2 = A.abx_pcols[2];
+    const int end0 = tb.end[0], end1 = tb.end[1];
+    const double *Tb = A.abx_T + c0 + n;
+    const double *Va = A.chunk_val + lane;
+    v4d_ab acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = v4d_ab{0.0, 0.0, 0.0, 0.0};
+    double ax[U], bx[U][4], ay[U], by[U][4];
+    int tx[U], ty[U];
+    auto fetch_tab = [&](int e, int *t) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = A.abx_ctof[min(e + u, e1 - 1)];
+    };
+    auto issue = [&](int e, const int *t, double *a, double (*b)[4]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int eu = e + u, ec = min(eu, e1 - 1);
+            const int wd = ec >= end1 ? w2 : (ec >= end0 ? w1 : w0);
+            const double *src = Tb + (size_t)t[u] + (size_t)k * wd;
+            a[u] = Va[(size_t)(eu < e1 ? eu : zc) * 64];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[u][q] = src[16 * q];
+        }
+    };
+    auto mma = [&](const double *a, const double (*b)[4]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][q], acc[q], 0, 0, 0);
+    };
+    if (active && e0 < e1) {
+        fetch_tab(e0, tx);
+        issue(e0, tx, ax, bx);
+        fetch_tab(e0 + U, ty);
+        for (int e = e0; e < e1; e += 2 * U) {
+            issue(e + U, ty, ay, by);
+            fetch_tab(e + 2 * U, tx);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(ax, bx);
+            __builtin_amdgcn_sched_barrier(0);
+            issue(e + 2 * U, tx, ax, bx);
+            fetch_tab(e + 3 * U, ty);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(ay, by);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (KS > 1) {
+        if (part > 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) red[part - 1][cw][4 * q + gg][lane] = acc[q][gg];
+        __syncthreads();
+        if (part > 0) return;
+#pragma unroll
+        for (int p2 = 0; p2 < KS - 1; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) acc[q][gg] += red[p2][cw][4 * q + gg][lane];
+    }
+    if (!active) return;
+    double *Sb = A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + n;
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Sb[(size_t)gg * 4 * swidth + 16 * q] = acc[q][gg];
+}
+
 // sigma({a0 < a1}, {b0 < b1}) = sum over the four readings (alpha
 // spectator, alpha active) x (beta spectator, beta active) of S, sign - per
 // spin whose spectator is the larger orbital
@@ -241,7 +347,10 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     }
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
-        k_ab_gemm<kAbCW, kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
+        if (cx->ab_pipe)
+            k_ab_pipe<kAbCW, kAbSplit, 2><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
+        else
+            k_ab_gemm<kAbCW, kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
     ISCI_HIP(hipGetLastError());

@@ -103,6 +103,7 @@ struct DevTabs {
     int4 *abx_trow = nullptr;
     int2 *abx_tq = nullptr;         // [norb][nblk]: (T offset of row 0, width) of the rows of (q, S); width 0: none
     int2 *abx_chunk = nullptr;
+    int *abx_ctof = nullptr;        // [nchunk + 8]: T offset of each chunk's row 0 (its width follows from its class)
     int *abx_rows = nullptr;
     long long *abx_soff = nullptr;
     AbBlk *abx_blk = nullptr;       // [8 * abx_xmax]: the product tile of each workgroup
@@ -150,6 +151,8 @@ struct SigmaArgs {
     const int *abx_rows;
     const long long *abx_soff;
     const AbBlk *abx_blk;
+    const int *abx_ctof;
+    int nchunk;              // chunks of W; chunk_val holds one more, all zero
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };
@@ -214,6 +217,9 @@ struct isci_ctx {
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
     int abx_xmax = 0;        // longest XCD tile run
+    bool ab_pipe = false;    // ISCI_OPT_AB_PRODUCT: k_ab_pipe (else k_ab_gemm)
+    int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
+    bool ob_side = true;     // ISCI_OPT_ONEBODY_STREAM: one-body kernels on the side stream (else in line)
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;
     bool onebody_in_tiles = false;   // chunk values carry the one-body units (h/2 (x) identity)

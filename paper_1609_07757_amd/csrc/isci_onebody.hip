@@ -479,19 +479,21 @@ __global__ __launch_bounds__(256) void k_ob_alpha_occ(SigmaArgs A, const double 
 }
 
 template <int NT>
-static void launch_ob_beta(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc, double *s,
-                           int64_t lds, int ovw, hipStream_t st)
+static isci_status launch_ob_beta(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
+                                  double *s, int64_t lds, int ovw, hipStream_t st)
 {
     const double *hs = cx->d.hscreen, *hp = cx->d.hpad;
     const int L = cx->L;
     // alpha rows by level: beta strings up to level 2 for level <= L - 2
     const int full_end = L >= 2 ? cx->sa.le[L - 2] : 0;
     if (full_end > 0)
-        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, hp, 0, ovw);
+        k_ob_beta_full<NT><<<dim3((unsigned)full_end, (unsigned)nv), 64 * NT, 0, st>>>(A, c, ldc, s, lds, hs, hp, 0,
+                                                                                      ovw);
     const int ncap1 = cx->sa.nstr - full_end;   // rows whose beta strings stop at level 1 or 0
     if (ncap1 > 0)
         k_ob_beta_cap1<NT><<<dim3((unsigned)((ncap1 + 15) / 16), (unsigned)nv), 64 * NT, 0, st>>>(
             A, c, ldc, s, lds, hs, hp, full_end, ncap1, ovw);
+    return ISCI_OK;
 }
 
 static int max_lds_bytes(const isci_ctx *cx)
@@ -514,10 +516,33 @@ static isci_status launch_ob_dense(const isci_ctx *cx, const SigmaArgs &A, int n
     return ISCI_OK;
 }
 
+// block transpose of up to four vectors (defined with k_det_transpose):
+// dst = src^T (add = 0) or dst += src^T (add = 1), both in the layout of
+// the space (two electrons per spin, alpha and beta string tables equal)
+static void launch_block_transpose(const isci_ctx *cx, const SigmaArgs &A, const double *src, int64_t lsrc,
+                                   double *dst, int64_t ldst, int add, int nv, hipStream_t st);
+
 template <int NT>
 static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
                                    double *s, int64_t lds, hipStream_t st)
 {
+    if (cx->ob_kernel == ISCI_ONEBODY_TRANSPOSED && cx->d.obT_c && cx->d.obT_s &&
+        cx->sb.le[cx->L >= 2 ? cx->L - 2 : 0] == cx->sb.nstr && cx->sa.nstr == cx->sb.nstr) {
+        // every beta column holds every alpha pair (full CI with two
+        // electrons per spin): the alpha class is the beta class of the
+        // transposed block, whose rows are contiguous; beta kernel there,
+        // then added back through a second transpose
+        const int64_t dim = cx->dim;
+        for (int u0 = 0; u0 < nv; u0 += 4) {
+            const int nu = nv - u0 < 4 ? nv - u0 : 4;
+            launch_block_transpose(cx, A, c + (int64_t)u0 * ldc, ldc, cx->d.obT_c, dim, 0, nu, st);
+            k_ob_beta_full<NT><<<dim3((unsigned)cx->sa.nstr, (unsigned)nu), 64 * NT, 0, st>>>(
+                A, cx->d.obT_c, dim, cx->d.obT_s, dim, cx->d.hscreen, cx->d.hpad, 0, 1);
+            launch_block_transpose(cx, A, cx->d.obT_s, dim, s + (int64_t)u0 * lds, lds, 1, nu, st);
+        }
+        ISCI_HIP(hipGetLastError());
+        return ISCI_OK;
+    }
     const double *hs = cx->d.hscreen;
     const int L = cx->L;
     // beta columns by level: every alpha pair up to level L - 2, the pairs
@@ -903,26 +928,29 @@ isci_status launch_onebody_beta_large(const isci_ctx *cx, int nv, const double *
     }
     const SigmaArgs A = sigma_args(cx);
     const int64_t dim = cx->dim;
-    // row tiles grouped by the length of their first row (one value per
-    // level): each group launches only the column tiles that row reaches
-    auto transpose = [&](const double *src, int64_t lsrc, double *dst, int64_t ldst, int add) {
-        const int n = cx->sa.nstr, nt = (n + 31) / 32;
-        for (int t0 = 0; t0 < nt;) {
-            const int len0 = cx->sb.le[cx->L - cx->h_alev[32 * t0]];
-            int t1 = t0 + 1;
-            while (t1 < nt && cx->sb.le[cx->L - cx->h_alev[32 * t1]] == len0) ++t1;
-            k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0)), 256, 0, st>>>(
-                A, src, lsrc, dst, ldst, add, t0, nv);
-            t0 = t1;
-        }
-    };
-    transpose(c, ldc, cx->d.obT_c, dim, 0);
+    launch_block_transpose(cx, A, c, ldc, cx->d.obT_c, dim, 0, nv, st);
     k_fill_zero<<<(unsigned)std::min<int64_t>(4096, (dim * nv + 255) / 256), 256, 0, st>>>(cx->d.obT_s, dim * nv);
     ISCI_HIP(hipGetLastError());
     ISCI_CHECK(launch_onebody_alpha_large(cx, nv, cx->d.obT_c, dim, cx->d.obT_s, dim, st));
-    transpose(cx->d.obT_s, dim, s, lds, 1);
+    launch_block_transpose(cx, A, cx->d.obT_s, dim, s, lds, 1, nv, st);
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
+}
+
+// row tiles grouped by the length of their first row (one value per
+// level): each group launches only the column tiles that row reaches
+static void launch_block_transpose(const isci_ctx *cx, const SigmaArgs &A, const double *src, int64_t lsrc,
+                                   double *dst, int64_t ldst, int add, int nv, hipStream_t st)
+{
+    const int n = cx->sa.nstr, nt = (n + 31) / 32;
+    for (int t0 = 0; t0 < nt;) {
+        const int len0 = cx->sb.le[cx->L - cx->h_alev[32 * t0]];
+        int t1 = t0 + 1;
+        while (t1 < nt && cx->sb.le[cx->L - cx->h_alev[32 * t1]] == len0) ++t1;
+        k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0)), 256, 0, st>>>(A, src, lsrc, dst,
+                                                                                             ldst, add, t0, nv);
+        t0 = t1;
+    }
 }
 
 bool onebody_mfma_ok(const isci_ctx *cx)
@@ -939,7 +967,7 @@ isci_status launch_onebody_mfma(const isci_ctx *cx, int nv, const double *c, int
     const int nt = (cx->norb + 15) / 16;
 #define ISCI_OB_CASE(N)                                                      \
     case N:                                                                  \
-        launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, ovw, st);                    \
+        ISCI_CHECK(launch_ob_beta<N>(cx, A, nv, c, ldc, s, lds, ovw, st));   \
         ISCI_CHECK(launch_ob_alpha<N>(cx, A, nv, c, ldc, s, lds, st));       \
         break;
     switch (nt) {

@@ -452,6 +452,8 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.abx_rows = c->d.abx_rows;
     A.abx_soff = c->d.abx_soff;
     A.abx_blk = c->d.abx_blk;
+    A.abx_ctof = c->d.abx_ctof;
+    A.nchunk = c->nchunk;
     A.abx_T = c->d.abx_T;
     A.abx_S = c->d.abx_S;
     for (int k = 0; k < 3; ++k) A.abx_pcols[k] = c->abx_pcols[k];
@@ -669,9 +671,12 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
         ISCI_HIP(hipFreeAsync(bits1, s));
     }
     d.chunk_desc = (int2 *)dev_alloc(c, sizeof(int2) * std::max(1, tot));
-    d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * (size_t)std::max(1, tot));
+    // one more chunk, all zero: the product kernels point past-the-end
+    // loads at it instead of selecting zeros
+    d.chunk_val = (double *)dev_alloc(c, sizeof(double) * 64 * ((size_t)std::max(1, tot) + 1));
     d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
     if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
+    ISCI_HIP(hipMemsetAsync(d.chunk_val + (size_t)64 * tot, 0, sizeof(double) * 64, s));
     k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, eri, merged ? d.hscreen : nullptr, n, nb, c->tau, d.blk_orb,
                                           d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
@@ -810,12 +815,13 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     d.abx_trow = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, trow.size()));
     d.abx_tq = (int2 *)dev_alloc(c, sizeof(int2) * (size_t)n * nb);
     d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * chunk.size());
+    d.abx_ctof = (int *)dev_alloc(c, sizeof(int) * (chunk.size() + 8));
     d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
     d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
     d.abx_blk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * blk.size());
     d.abx_T = (double *)dev_alloc(c, tbytes);
     d.abx_S = (double *)dev_alloc(c, sbytes);
-    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_rows || !d.abx_soff || !d.abx_blk ||
+    if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_ctof || !d.abx_rows || !d.abx_soff || !d.abx_blk ||
         !d.abx_T || !d.abx_S) {
         set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
@@ -835,6 +841,9 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     // scatter unfold writes the others every call
     ISCI_HIP(hipMemsetAsync(d.abx_T, 0, tbytes, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_chunk, chunk.data(), sizeof(int2) * chunk.size(), hipMemcpyHostToDevice, s));
+    std::vector<int> ctof(chunk.size() + 8, 0);
+    for (size_t e = 0; e < chunk.size(); ++e) ctof[e] = chunk[e].x;
+    ISCI_HIP(hipMemcpyAsync(d.abx_ctof, ctof.data(), sizeof(int) * ctof.size(), hipMemcpyHostToDevice, s));
     if (!rows.empty())
         ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_soff, soff.data(), sizeof(long long) * soff.size(), hipMemcpyHostToDevice, s));
@@ -1183,9 +1192,12 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         st = build_hscreen(c, h, stream);
         if (st == ISCI_OK) st = build_tiles(c, eri, stream);
         if (st == ISCI_OK) st = build_abx(c, stream);
-        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && norb > kObMaxNorb) {
+        const bool full_pairs = c->L >= 2 && c->sb.le[c->L - 2] == c->sb.nstr && c->sa.nstr == c->sb.nstr;
+        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && (norb > kObMaxNorb || full_pairs)) {
             // beta one-body above kObMaxNorb runs as the alpha class of the
-            // transposed block: scratch for four vectors and their image
+            // transposed block, and where every column holds every pair
+            // (full CI) the alpha class as the beta class of the transposed
+            // block: scratch for four vectors and their image
             c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
             c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
             if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
@@ -1255,6 +1267,18 @@ isci_status isci_set_option(isci_handle c, int option, int value)
             return ISCI_E_UNSUPPORTED;
         }
         c->sigma_variant = value;
+        return ISCI_OK;
+    case ISCI_OPT_AB_PRODUCT:
+        if (value != ISCI_AB_PLAIN && value != ISCI_AB_PIPE) { set_error("bad alpha-beta product kernel"); return ISCI_E_INVALID; }
+        c->ab_pipe = value == ISCI_AB_PIPE;
+        return ISCI_OK;
+    case ISCI_OPT_ONEBODY_KERNEL:
+        if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED) { set_error("bad one-body kernel"); return ISCI_E_INVALID; }
+        c->ob_kernel = value;
+        return ISCI_OK;
+    case ISCI_OPT_ONEBODY_STREAM:
+        if (value != ISCI_ONEBODY_SIDE && value != ISCI_ONEBODY_INLINE) { set_error("bad one-body stream"); return ISCI_E_INVALID; }
+        c->ob_side = value == ISCI_ONEBODY_SIDE;
         return ISCI_OK;
     case ISCI_OPT_AB_PATH:
         if (value != ISCI_AB_AUTO && value != ISCI_AB_GATHER) { set_error("bad alpha-beta path"); return ISCI_E_INVALID; }

@@ -588,6 +588,7 @@ isci_status launch_sigma(const isci_ctx *c, int nvec, const double *cv, int64_t 
                 // the side stream while the unfolds and products of both
                 // 4-vector passes run here (into two S buffers); the folds
                 // wait for them and add
+                side = side && c->ob_side;
                 const hipStream_t os = side ? c->ob_stream : s;
                 if (side) {
                     ISCI_HIP(hipEventRecord(c->ob_fork, s));

@@ -243,3 +243,59 @@ def test_ab_path_option():
     isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_AUTO)
     assert rel_err(b, a) <= TOL
     assert np.array_equal(gpu_sigma(hd, c), a)   # same path again: bit-identical
+
+
+@pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 3), ("cisdt_n30", 400, 8), ("fci_n48", 200, 8),
+                                            ("cisdt_n60", 200, 5)])
+def test_ab_product_kernels(wl, nsamp, nvec):
+    """Both kernels of the block-sparse alpha-beta product against the
+    oracle, and bit for bit with each other (same K parts, same order within
+    each)."""
+    import paper_1609_07757_amd as isci
+    from isci_inputs import workload
+    W = workload(wl)
+    h, eri = W.integrals()
+    hd = create(h, eri, W.norb, 2, 2, W.level, W.tau, 5)
+    S = O.Space(W.norb, 2, 2, W.level)
+    c = random_vectors(S.dim, nvec, seed=22)
+    tg = None if nsamp is None else sample_targets(S.rowstart(), S.dim, nsamp, seed=6)
+    ref = O.sigma(S, h, eri, W.tau, c, targets=tg)
+    outs = []
+    for val in (isci.AB_PLAIN, isci.AB_PIPE):
+        isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, val)
+        got = gpu_sigma(hd, c)
+        outs.append(got)
+        if tg is None:
+            assert rel_err(got, ref) <= TOL, val
+        else:
+            ok, err = sampled_ok(got, tg, ref, TOL)
+            assert ok, (val, err)
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("recipe,norb,L,tau,nvec,nsamp", [("B", 12, 2, 1e-12, 3, None), ("B", 16, 4, 0.0, 5, None),
+                                                          ("A", 30, 3, 1e-14, 8, 400), ("A", 48, 4, 1e-14, 8, 300),
+                                                          ("A", 60, 3, 1e-14, 4, 300), ("B", 77, 2, 1e-12, 2, 300)])
+def test_onebody_kernels(recipe, norb, L, tau, nvec, nsamp):
+    """The one-body classes in their own kernels (one-body units kept out of
+    the alpha-beta tiles), 12 to 77 orbitals (one to five 16-orbital
+    tiles): two-column alpha kernel, and the alpha class through the
+    transposed block where every column holds every pair (full CI, 16 and 48
+    orbitals), on the side stream and in line; each against the oracle."""
+    import paper_1609_07757_amd as isci
+    h, eri = _ints(recipe, norb, 7)
+    hd = create(h, eri, norb, 2, 2, L, tau, 5)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, nvec, seed=23)
+    tg = None if nsamp is None else sample_targets(S.rowstart(), S.dim, nsamp, seed=7)
+    ref = O.sigma(S, h, eri, tau, c, targets=tg)
+    for kern, stream in ((isci.ONEBODY_SINGLE, isci.ONEBODY_SIDE), (isci.ONEBODY_TRANSPOSED, isci.ONEBODY_SIDE),
+                         (isci.ONEBODY_TRANSPOSED, isci.ONEBODY_INLINE)):
+        isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, kern)
+        isci.isci_set_option(hd, isci.OPT_ONEBODY_STREAM, stream)
+        got = gpu_sigma(hd, c)
+        if tg is None:
+            assert rel_err(got, ref) <= TOL, kern
+        else:
+            ok, err = sampled_ok(got, tg, ref, TOL)
+            assert ok, (kern, err)
