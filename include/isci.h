@@ -252,6 +252,22 @@ isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
 isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,
                           hipStream_t stream);
 
+/* isci_density1 without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as isci_density1 (bit for bit the same d1), but the partial sums
+ * and the transposed vectors live in a static 64 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of buffers
+ * owned by the handle; the vectors go through it in passes of up to eight,
+ * as many as fit.  ISCI_E_UNSUPPORTED (with a message naming the bytes
+ * needed) when one vector does not fit: 8 * (64 norb^2 + dim) bytes with
+ * beta electrons, 8 * 64 norb^2 without; ISCI_E_INVALID when the current
+ * device is not the handle's.  Calls on one GPU share the array, so calls
+ * that overlap in time on one GPU (different streams, threads or handles)
+ * race: order them.  The array needs no initial contents. */
+isci_status isci_density1_noalloc(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,
+                                  hipStream_t stream);
+
 /* Lowest nroots eigenpairs of H_tau, the eigenvalue problem of Eq. hcec
  * that the paper solves by repeated sigma steps (Eq. sigma) inside an
  * iterative optimiser (Davidson or Lanczos, in the text after Eq. sigma):

@@ -20,7 +20,8 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_add", "isci_engine_step", "isci_engine_result", "isci_engine_release",
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
-           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator", "isci_density1"]
+           "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator", "isci_density1",
+           "isci_density1_noalloc"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -237,6 +238,20 @@ def isci_density1(hd: Handle, c, out=None, stream=None):
     check(_lib.load().isci_density1(hd.ptr, nv, _dev_f64(c2, "c"), int(c2.stride(0)), _dev_f64(out, "d1"),
                                     _stream_ptr(stream)), "isci_density1")
     return out[0] if squeeze else out
+
+
+def isci_density1_noalloc(hd: Handle, c, out, stream=None):
+    """isci_density1 for callers that cannot allocate device memory: the
+    caller passes the output, and the library works in its static scratch
+    (no allocation by the library or this binding)."""
+    if c.dim() != 2 or c.shape[-1] != hd.dim:
+        raise ValueError("c must be [nvec, dim]")
+    nv, n = int(c.shape[0]), hd.norb
+    if tuple(out.shape) != (nv, 2, n, n) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [nvec, 2, norb, norb] tensor")
+    check(_lib.load().isci_density1_noalloc(hd.ptr, nv, _dev_f64(c, "c"), int(c.stride(0)), _dev_f64(out, "d1"),
+                                            _stream_ptr(stream)), "isci_density1_noalloc")
+    return out
 
 
 def _opts(tol_residual=1e-7, tol_energy=1e-11, max_iter=200, max_subspace=0, block=0):

@@ -32,6 +32,7 @@ ABI_SYMBOLS = (
     "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
     "isci_davidson_footprint", "isci_set_option", "isci_profile", "isci_profile_read",
     "isci_sigma_graph_create", "isci_graph_launch", "isci_graph_destroy", "isci_probe_fp64", "isci_density1",
+    "isci_density1_noalloc",
 )
 
 
@@ -103,6 +104,8 @@ def load(path: str = LIBPATH):
     L.isci_graph_destroy.restype = None
     L.isci_density1.argtypes = [vp, i32, vp, i64, vp, vp]
     L.isci_density1.restype = i32
+    L.isci_density1_noalloc.argtypes = [vp, i32, vp, i64, vp, vp]
+    L.isci_density1_noalloc.restype = i32
     L.isci_diag.argtypes = [vp, vp, vp]
     L.isci_diag.restype = i32
     L.isci_davidson.argtypes = [vp, i32, ctypes.POINTER(IsciDavidsonOpts), vp, i32,

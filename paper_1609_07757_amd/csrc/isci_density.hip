@@ -21,6 +21,9 @@
 // tables (rows of one level are contiguous and equally long).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include <algorithm>
 #include <vector>
 
@@ -344,9 +347,37 @@ isci_status gram_pass(const SigmaArgs &A, const double *c, int64_t ldc, int nv, 
 
 using namespace isci;
 
-extern "C" {
+// Scratch of isci_density1_noalloc: a file-scope device array that the code
+// object brings along (each GPU holds its own copy until the process ends).
+// Host code never uses its name as an address: the per-device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchDoubles = kScratchBytes / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
-isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc, double *d1, hipStream_t stream)
+namespace {
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// device address of `scratch` on device dev (the current device)
+isci_status scratch_address(int dev, double **out)
+{
+    if (dev < 0 || dev >= kScratchMaxDevices) { set_error("device index out of range"); return ISCI_E_UNSUPPORTED; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ISCI_OK;
+}
+
+// common argument checks of both density entry points
+isci_status density_args(isci_handle h, int nvec, const double *c, int64_t ldc, const double *d1)
 {
     if (!h || !c || !d1) { set_error("NULL argument"); return ISCI_E_INVALID; }
     if (nvec < 1 || nvec > 65535) { set_error("nvec outside 1..65535"); return ISCI_E_INVALID; }
@@ -355,6 +386,20 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
     const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
     const char *d0 = (const char *)d1, *e1 = (const char *)(d1 + nd);
     if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
+    if (h->nb > 0) {
+        // the spin-swapped layout (rows = beta strings) holds every determinant
+        int64_t tot = 0;
+        for (int j = 0; j < h->sb.nstr; ++j) tot += h->sa.le[h->L - h->h_blev[j]];
+        if (tot != h->dim) { set_error("isci_density1: transposed layout size mismatch"); return ISCI_E_INVALID; }
+    }
+    return ISCI_OK;
+}
+
+// vectors [0, nvec) in passes of nvc: both spin blocks, partial slabs in
+// part, the transposed copy in cT
+isci_status density_passes(isci_handle h, int nvec, const double *c, int64_t ldc, double *d1, int nvc, double *part,
+                           double *cT, hipStream_t stream)
+{
     const SigmaArgs A = sigma_args(h);
     SigmaArgs T = A;   // the spin-swapped layout: beta strings index the rows
     T.sa = A.sb;
@@ -363,30 +408,63 @@ isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc,
     T.bstr = A.astr;
     T.alev = A.blev;
     T.blev = A.alev;
+    for (int v0 = 0; v0 < nvec; v0 += nvc) {
+        const int nv = std::min(nvc, nvec - v0);
+        ISCI_CHECK(gram_pass(A, c + (int64_t)v0 * ldc, ldc, nv, part, d1, 0, v0, stream));
+        if (h->nb > 0) {
+            k_d1_transpose<<<transpose_tiles(h), 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->dim, cT);
+            ISCI_HIP(hipGetLastError());
+        }
+        ISCI_CHECK(gram_pass(T, cT, h->dim, nv, part, d1, 1, v0, stream));
+    }
+    return ISCI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+isci_status isci_density1(isci_handle h, int nvec, const double *c, int64_t ldc, double *d1, hipStream_t stream)
+{
+    ISCI_CHECK(density_args(h, nvec, c, ldc, d1));
     if (!h->d.d1part) {
         h->d.d1part = (double *)dev_alloc(h, sizeof(double) * kGramGroups * kD1Chunk * (size_t)h->norb * h->norb);
         if (!h->d.d1part) { set_error("isci_density1: out of device memory"); return ISCI_E_OOM; }
     }
     if (h->nb > 0 && !h->d.d1T) {
-        const int nsb = h->sb.nstr;
-        std::vector<int64_t> rt(nsb + 1);
-        rt[0] = 0;
-        for (int j = 0; j < nsb; ++j) rt[j + 1] = rt[j] + h->sa.le[h->L - h->h_blev[j]];
-        if (rt[nsb] != h->dim) { set_error("isci_density1: transposed layout size mismatch"); return ISCI_E_INVALID; }
         double *buf = (double *)dev_alloc(h, sizeof(double) * kD1Chunk * (size_t)h->dim);
         if (!buf) { set_error("isci_density1: out of device memory"); return ISCI_E_OOM; }
         h->d.d1T = buf;
     }
-    for (int v0 = 0; v0 < nvec; v0 += kD1Chunk) {
-        const int nv = std::min(kD1Chunk, nvec - v0);
-        ISCI_CHECK(gram_pass(A, c + (int64_t)v0 * ldc, ldc, nv, h->d.d1part, d1, 0, v0, stream));
-        if (h->nb > 0) {
-            k_d1_transpose<<<transpose_tiles(h), 256, 0, stream>>>(A, c + (int64_t)v0 * ldc, ldc, nv, h->dim, h->d.d1T);
-            ISCI_HIP(hipGetLastError());
-        }
-        ISCI_CHECK(gram_pass(T, h->d.d1T, h->dim, nv, h->d.d1part, d1, 1, v0, stream));
+    return density_passes(h, nvec, c, ldc, d1, kD1Chunk, h->d.d1part, h->d.d1T, stream);
+}
+
+isci_status isci_density1_noalloc(isci_handle h, int nvec, const double *c, int64_t ldc, double *d1,
+                                  hipStream_t stream)
+{
+    ISCI_CHECK(density_args(h, nvec, c, ldc, d1));
+    int dev = -1;
+    ISCI_HIP(hipGetDevice(&dev));
+    if (dev != h->device) {
+        set_error("isci_density1_noalloc: the current device is not the handle's device");
+        return ISCI_E_INVALID;
     }
-    return ISCI_OK;
+    // vectors per pass: partial slabs (64 norb^2 doubles) and the transposed
+    // copy (dim doubles, with beta electrons) of each must fit the scratch
+    const size_t per_vec = (size_t)kGramGroups * h->norb * h->norb + (h->nb > 0 ? (size_t)h->dim : 0);
+    const size_t fit = kScratchDoubles / per_vec;
+    if (fit < 1) {
+        set_error("isci_density1_noalloc: one vector needs " + std::to_string(per_vec * sizeof(double)) +
+                  " bytes of scratch; the static scratch holds " + std::to_string(kScratchBytes) +
+                  " (use isci_density1)");
+        return ISCI_E_UNSUPPORTED;
+    }
+    const int nvc = (int)std::min<size_t>(kD1Chunk, fit);
+    double *sp = nullptr;
+    ISCI_CHECK(scratch_address(dev, &sp));
+    double *part = sp;
+    double *cT = sp + (size_t)kGramGroups * nvc * h->norb * h->norb;
+    return density_passes(h, nvec, c, ldc, d1, nvc, part, cT, stream);
 }
 
 }  // extern "C"
