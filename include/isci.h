@@ -180,6 +180,31 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
                            int nalpha, int nbeta, int max_excitation, double tau,
                            const isci_create_opts *opts, hipStream_t stream);
 
+/* A handle built from factored two-electron integrals,
+ *   (pq|rs) = sum_{K < naux} L^K_pq L^K_rs,
+ * without forming the dense norb^4 tensor: the list builders form each
+ * integral they need from the factors (at its canonical indices, K
+ * ascending, every product and partial sum rounded once, no fused
+ * multiply-add) when the screened lists are built, so each is computed
+ * once and the sigma steps only fetch the kept units: the paper's minimum
+ * integral calculation (section "First part" of the implementation: the
+ * integrals of a Hamiltonian type computed once and fetched by every
+ * block) applied to the screening of Eqs. sigma_int / sigma_split.  A
+ * builder skips a unit without forming it when the Cauchy-Schwarz bound
+ * |(pq|rs)| <= |L_pq| |L_rs| (with a margin for rounding) shows it would be
+ * screened; the kept units and their values are exactly those of a dense
+ * tensor assembled in the same order, so the handle behaves as one built
+ * by isci_create_ex from that tensor.  Lfac: device [naux][norb][norb]
+ * (L^K_pq at (K norb + p) norb + q), read during this call only; only the
+ * elements p >= q are used (the lower triangle of each L^K).  The call
+ * takes 8 (naux + 1) norb^2 bytes of temporaries instead of the 8 norb^4
+ * bytes of a dense tensor.  Other arguments, the result and the errors as
+ * isci_create_ex; ISCI_E_INVALID also for naux < 1, and for a non-finite
+ * factor element that is used or a factor norm whose square overflows. */
+isci_status isci_create_factored(isci_handle *out, const double *h, const double *Lfac, int naux, int norb,
+                                 int nalpha, int nbeta, int max_excitation, double tau,
+                                 const isci_create_opts *opts, hipStream_t stream);
+
 /* Number of determinants of the truncated space: the terms of the CI
  * expansion (Eq. ci_ansatz) kept by the excitation hierarchy cut at
  * max_excitation (Eq. ci_hierarchy), counted per (alpha, beta) string

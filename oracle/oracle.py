@@ -20,6 +20,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
 * ``terms``: pinned by an independent closed-form count in the tests.
 * ``dropped_bound``: pinned by the Weyl inequality against exact spectra.
 * ``davidson``: pinned by dense diagonalisation on small spaces.
+* ``assemble_factored``: pinned by the Gram structure of the definition
+  (the (pq),(rs) matrix is positive semidefinite of rank <= naux, symmetric,
+  and obeys the Cauchy-Schwarz bound) and by agreement within rounding with
+  the inputs module's matrix-product assembly of the same factors.
 * ``density1``: pinned by single determinants (occupation numbers), the
   trace (electron count), the one-body energy against ``dense_h`` with the
   two-electron integrals set to zero, the alpha/beta swap, and brute force
@@ -280,6 +284,22 @@ def e_ref_closed_form(h, eri, nalpha: int, nbeta: int) -> float:
             if si == sj:
                 e -= 0.5 * eri[i, j, j, i]
     return float(e)
+
+
+def assemble_factored(L) -> np.ndarray:
+    """Dense (pq|rs) = sum_K L^K_pq L^K_rs from factors L [naux][norb][norb],
+    summed K by K in ascending order with each product and each partial sum
+    rounded once (numpy elementwise operations, no fused multiply-add): the
+    definition of factored integrals written out in the order the library's
+    factored handles use, so both sides screen the same doubles."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    naux, n, n2 = L.shape
+    if n != n2:
+        raise ValueError("L must be [naux][norb][norb]")
+    out = np.zeros((n, n, n, n))
+    for K in range(naux):
+        out = out + np.multiply.outer(L[K], L[K])
+    return out
 
 
 def dense_eigh(space: Space, h, eri, tau: float):

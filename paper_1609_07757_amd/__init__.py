@@ -21,7 +21,7 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
            "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator", "isci_density1",
-           "isci_density1_noalloc"]
+           "isci_density1_noalloc", "isci_create_factored"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -137,6 +137,28 @@ def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int,
     st = L.isci_create_ex(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
                           int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create")
+    return Handle(out, norb, nalpha, nbeta, max_excitation, tau, keep=allocator)
+
+
+def isci_create_factored(h, Lfac, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
+                         stream=None, onebody: int = OB_AUTO, allocator=None) -> Handle:
+    """Build a handle from factored integrals (pq|rs) = sum_K L^K_pq L^K_rs,
+    Lfac of shape [naux, norb, norb] on the device, with no dense norb^4
+    tensor (isci_create_factored)."""
+    L = _lib.load()
+    hp = _dev_f64(h, "h")
+    lp = _dev_f64(Lfac, "Lfac")
+    if h.numel() != norb * norb or Lfac.dim() != 3 or tuple(Lfac.shape[1:]) != (norb, norb):
+        raise ValueError("h must hold norb^2 elements and Lfac be [naux, norb, norb]")
+    out = ctypes.c_void_p()
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
+        allocator = torch_allocator()
+    opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None)
+    st = L.isci_create_factored(ctypes.byref(out), hp, lp, int(Lfac.shape[0]), int(norb), int(nalpha), int(nbeta),
+                                int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
+    check(st, "isci_create_factored")
     return Handle(out, norb, nalpha, nbeta, max_excitation, tau, keep=allocator)
 
 

@@ -32,7 +32,7 @@ ABI_SYMBOLS = (
     "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
     "isci_davidson_footprint", "isci_set_option", "isci_profile", "isci_profile_read",
     "isci_sigma_graph_create", "isci_graph_launch", "isci_graph_destroy", "isci_probe_fp64", "isci_density1",
-    "isci_density1_noalloc",
+    "isci_density1_noalloc", "isci_create_factored",
 )
 
 
@@ -89,6 +89,9 @@ def load(path: str = LIBPATH):
     L.isci_create.restype = i32
     L.isci_create_ex.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i32, i32, dbl,
                                  ctypes.POINTER(IsciCreateOpts), vp]
+    L.isci_create_factored.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i32, i32, i32, dbl,
+                                       ctypes.POINTER(IsciCreateOpts), vp]
+    L.isci_create_factored.restype = i32
     L.isci_create_ex.restype = i32
     L.isci_dim.argtypes = [vp, ctypes.POINTER(i64)]
     L.isci_dim.restype = i32

@@ -97,6 +97,50 @@ __device__ inline double geri(const double *eri, int n, int p, int q, int r, int
     return eri[eri_canon(n, p, q, r, s)];
 }
 
+// Source of the two-electron integrals read by the list builders: the
+// canonical element of a dense tensor, or, for a handle built from factors
+// (pq|rs) = sum_K L^K_pq L^K_rs, the sum formed on the fly at the canonical
+// indices in a fixed order (K ascending, each product and each partial sum
+// rounded once, no fused multiply-add), so every unit is the same double
+// whatever builder reads it; the dense tensor is never formed (the
+// minimum-integral-calculation idea of the paper's set-up part: each
+// integral is computed once, when the screened lists are built, and only
+// fetched by the sigma steps).  nrm[pq] >= sqrt(sum_K (L^K_pq)^2) gives the
+// Cauchy-Schwarz bound |(pq|rs)| <= nrm[pq] nrm[rs], which lets a builder
+// skip a unit it would screen away without forming it.
+struct EriSrc {
+    const double *eri;   // dense [n^4] ((pq|rs) at ((p n + q) n + r) n + s), or nullptr
+    const double *Lt;    // factored: [n * n][naux], L^K_pq at (p n + q) naux + K
+    const double *nrm;   // factored: [n * n] bounds of the factor norms
+    int n, naux;
+};
+
+__device__ inline double eri_value(const EriSrc &E, int p, int q, int r, int s)
+{
+    if (E.eri) return geri(E.eri, E.n, p, q, r, s);
+    int t;
+    if (p < q) { t = p; p = q; q = t; }
+    if (r < s) { t = r; r = s; s = t; }
+    if (p < r || (p == r && q < s)) { t = p; p = r; r = t; t = q; q = s; s = t; }
+    const double *a = E.Lt + ((size_t)p * E.n + q) * E.naux;
+    const double *b = E.Lt + ((size_t)r * E.n + s) * E.naux;
+    double acc = 0.0;
+    {
+        // product and sum rounded separately (no contraction to an FMA)
+#pragma clang fp contract(off)
+        for (int K = 0; K < E.naux; ++K) acc = acc + a[K] * b[K];
+    }
+    return acc;
+}
+
+// true when |(pq|rs)| as eri_value forms it is surely <= t (factored
+// sources only; the margin covers the rounding of the sums and the norms)
+__device__ inline bool eri_negligible(const EriSrc &E, int p, int q, int r, int s, double t)
+{
+    if (!E.nrm) return false;
+    return E.nrm[p * E.n + q] * E.nrm[r * E.n + s] * (1.0 + 1e-9) <= t;
+}
+
 __device__ inline double gh(const double *h, int n, int p, int q)
 {
     return p >= q ? h[(size_t)p * n + q] : h[(size_t)q * n + p];

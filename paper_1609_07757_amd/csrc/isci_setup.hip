@@ -259,8 +259,19 @@ __device__ inline void pair_of(int P, int &p, int &r)
     r = P - x * (x - 1) / 2;
 }
 
-__global__ void k_ss_count(const double *eri, int n, double tau, int *cnt)
+// same-spin unit (pq|rs) - (ps|rq), or 0 when both integrals are surely
+// below tau/2 (1 - 1e-6): then the difference, rounded, is below tau and
+// would be screened anyway
+__device__ inline double ss_unit(const EriSrc &E, int p, int q, int r, int s, double tau)
 {
+    const double t2 = 0.5 * tau * (1.0 - 1e-6);
+    if (eri_negligible(E, p, q, r, s, t2) && eri_negligible(E, p, s, r, q, t2)) return 0.0;
+    return eri_value(E, p, q, r, s) - eri_value(E, p, s, r, q);
+}
+
+__global__ void k_ss_count(EriSrc E, double tau, int *cnt)
+{
+    const int n = E.n;
     const int np = n * (n - 1) / 2;
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= np) return;
@@ -269,15 +280,16 @@ __global__ void k_ss_count(const double *eri, int n, double tau, int *cnt)
     int c = 0;
     for (int q = 1; q < n; ++q)
         for (int s = 0; s < q; ++s) {
-            double v = geri(eri, n, p, q, r, s) - geri(eri, n, p, s, r, q);
+            const double v = ss_unit(E, p, q, r, s, tau);
             c += fabs(v) > tau;
         }
     cnt[P] = c;
 }
 
-__global__ void k_ss_fill(const double *eri, int n, double tau, const int *off, uint16_t *qs,
+__global__ void k_ss_fill(EriSrc E, double tau, const int *off, uint16_t *qs,
                           double *val, SpinTab sa, SpinTab sb, int L, unsigned long long *ctr)
 {
+    const int n = E.n;
     const int np = n * (n - 1) / 2;
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= np) return;
@@ -286,7 +298,7 @@ __global__ void k_ss_fill(const double *eri, int n, double tau, const int *off, 
     int k = off[P];
     for (int q = 1; q < n; ++q)
         for (int s = 0; s < q; ++s) {
-            double v = geri(eri, n, p, q, r, s) - geri(eri, n, p, s, r, q);
+            const double v = ss_unit(E, p, q, r, s, tau);
             if (!(fabs(v) > tau)) continue;
             qs[k] = (uint16_t)((q << 8) | s);
             val[k] = v;
@@ -318,20 +330,55 @@ __global__ void k_check_finite(const double *h, const double *eri, int n, int *b
     if (!ok) atomicOr(bad, 1);
 }
 
-__global__ void k_ab_count(const double *eri, int n, double tau, long long *cnt)
+// The factored form of the input check, h part: *bad = 1 if an element of
+// the lower triangle of h is not finite (the factors are checked through
+// their norms in k_factor_prep).
+__global__ void k_check_finite_h(const double *h, int n, int *bad)
 {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * n && !isfinite(gh(h, n, t / n, t % n))) atomicOr(bad, 1);
+}
+
+// Lt[pq][K] = L[K][pq] for the canonical pairs p >= q (the ones read), and
+// nrm[pq] = nrm[qp] = (1 + 1e-12) sqrt(sum_K L[K][pq]^2) for all pairs; the
+// factor makes it an upper bound of the exact norm.  *bad = 1 when a norm
+// is not finite (a NaN or infinite factor entry) or its square overflows
+// (then a sum of products could).
+__global__ void k_factor_prep(const double *L, int n, int naux, double *Lt, double *nrm, int *bad)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int p = t / n, q = t % n;
+    if (p < q) return;
+    double ss = 0.0;
+    for (int K = 0; K < naux; ++K) {
+        const double v = L[(size_t)K * n * n + t];
+        Lt[(size_t)t * naux + K] = v;
+        ss = fma(v, v, ss);
+    }
+    const double b = sqrt(ss) * (1.0 + 1e-12);
+    nrm[t] = b;
+    nrm[q * n + p] = b;
+    if (!isfinite(b) || !isfinite(b * b)) atomicOr(bad, 1);
+}
+
+__global__ void k_ab_count(EriSrc E, double tau, long long *cnt)
+{
+    const int n = E.n;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n3 = (int64_t)n * n * n;
     if (t >= n3) return;
     const int p = (int)(t / ((int64_t)n * n)), q = (int)((t / n) % n), r = (int)(t % n);
     int c = 0;
-    for (int s = 0; s < n; ++s) c += fabs(geri(eri, n, p, q, r, s)) > tau;
+    for (int s = 0; s < n; ++s)
+        if (!eri_negligible(E, p, q, r, s, tau)) c += fabs(eri_value(E, p, q, r, s)) > tau;
     cnt[t] = c;
 }
 
-__global__ void k_ab_fill(const double *eri, int n, double tau, const long long *off, uint8_t *ss, double *val,
+__global__ void k_ab_fill(EriSrc E, double tau, const long long *off, uint8_t *ss, double *val,
                           SpinTab sa, SpinTab sb, int L, unsigned long long *ctr)
 {
+    const int n = E.n;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n3 = (int64_t)n * n * n;
     if (t >= n3) return;
@@ -339,7 +386,8 @@ __global__ void k_ab_fill(const double *eri, int n, double tau, const long long 
     long long k = off[t];
     unsigned long long kept[16] = {0}, terms[16] = {0};
     for (int s = 0; s < n; ++s) {
-        double v = geri(eri, n, p, q, r, s);
+        if (eri_negligible(E, p, q, r, s, tau)) continue;
+        const double v = eri_value(E, p, q, r, s);
         if (!(fabs(v) > tau)) continue;
         ss[k] = (uint8_t)s;
         val[k] = v;
@@ -400,15 +448,16 @@ __global__ void k_hpad(const double *hs, int n, int P, double *hp)
 
 // diagonal units: h_pp, (pp|qq), and (pp|qq) - (pq|qp) formed with the
 // smaller index first
-__global__ void k_diag_units(const double *h, const double *eri, int n, double *hd, double *jj, double *ssd)
+__global__ void k_diag_units(const double *h, EriSrc E, double *hd, double *jj, double *ssd)
 {
+    const int n = E.n;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * n) return;
     const int p = t / n, q = t % n;
     if (q == 0) hd[p] = gh(h, n, p, p);
-    jj[t] = geri(eri, n, p, p, q, q);
+    jj[t] = eri_value(E, p, p, q, q);
     const int a = min(p, q), b = max(p, q);
-    ssd[t] = geri(eri, n, a, a, b, b) - geri(eri, n, a, b, b, a);
+    ssd[t] = eri_value(E, a, a, b, b) - eri_value(E, a, b, b, a);
 }
 
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -524,7 +573,7 @@ __global__ __launch_bounds__(256) void k_chunk_count(const unsigned *bits, int n
 // row block pair g: for each class, block-wide scans over batches of 256
 // (q, S) keys (in q, S order) place the marked chunks, then 64-lane groups
 // fill the 64 values of each chunk placed in the batch.
-__global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, const double *eri, const double *hs, int n,
+__global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, EriSrc E, const double *hs, int n,
                                                     int nb, double tau, const int16_t *blk_orb, const int *off,
                                                     int2 *desc, double *val, int *cls)
 {
@@ -564,7 +613,7 @@ __global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, const 
                 const int p = blk_orb[Ab * 4 + (i >> 2)], r = blk_orb[Bb * 4 + (i & 3)], s = blk_orb[kS * 4 + kk];
                 double v = 0.0;
                 if (p >= 0 && r >= 0 && s >= 0) {
-                    v = geri(eri, n, p, kq, r, s);
+                    v = eri_value(E, p, kq, r, s);
                     if (!(fabs(v) > tau)) v = 0.0;
                     // one-body units in alpha-beta form (hs holds the kept h)
                     if (hs && r == s) v += 0.5 * hs[p * n + kq];
@@ -586,7 +635,7 @@ static constexpr int64_t kObTilesMaxDim = 65536;
 
 // blocks of four orbitals, o/v pure (two electrons per spin: the occupied
 // block is {0, 1, -, -}); target tiles with level <= L; column chunks
-static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
+static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
 {
     const int n = c->norb;
     // orbitals of each block slot, -1 for padding (16 bits: up to 255 orbitals)
@@ -677,7 +726,7 @@ static isci_status build_tiles(isci_ctx *c, const double *eri, hipStream_t s)
     d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
     if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
     ISCI_HIP(hipMemsetAsync(d.chunk_val + (size_t)64 * tot, 0, sizeof(double) * 64, s));
-    k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, eri, merged ? d.hscreen : nullptr, n, nb, c->tau, d.blk_orb,
+    k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, E, merged ? d.hscreen : nullptr, n, nb, c->tau, d.blk_orb,
                                           d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
     ISCI_HIP(hipFreeAsync(bits, s));
@@ -877,7 +926,7 @@ static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
     return ISCI_OK;
 }
 
-static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, hipStream_t s)
+static isci_status build_lists(isci_ctx *c, const double *h, const EriSrc &E, hipStream_t s)
 {
     const int n = c->norb;
     const int64_t n3 = (int64_t)n * n * n;
@@ -902,9 +951,9 @@ static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, 
     ISCI_HIP(hipMemsetAsync(d.pq_off, 0, sizeof(int) * (n + 1), s));
 
     k_h_count<<<nblk(n, 64), 64, 0, s>>>(h, n, c->tau, d.h_off);
-    if (np > 0) k_ss_count<<<nblk(np, 64), 64, 0, s>>>(eri, n, c->tau, d.ss_off);
-    k_ab_count<<<nblk(n3, 256), 256, 0, s>>>(eri, n, c->tau, d.ab_off);
-    k_diag_units<<<nblk((int64_t)n * n, 256), 256, 0, s>>>(h, eri, n, d.hd, d.jj, d.ssd);
+    if (np > 0) k_ss_count<<<nblk(np, 64), 64, 0, s>>>(E, c->tau, d.ss_off);
+    k_ab_count<<<nblk(n3, 256), 256, 0, s>>>(E, c->tau, d.ab_off);
+    k_diag_units<<<nblk((int64_t)n * n, 256), 256, 0, s>>>(h, E, d.hd, d.jj, d.ssd);
     ISCI_HIP(hipGetLastError());
     isci_status st;
     if ((st = scan_inplace<int>(d.h_off, n + 1, s)) != ISCI_OK) return st;
@@ -935,9 +984,9 @@ static isci_status build_lists(isci_ctx *c, const double *h, const double *eri, 
     }
     k_h_fill<<<nblk(n, 64), 64, 0, s>>>(h, n, c->tau, d.h_off, d.h_q, d.h_v, c->sa, c->sb, c->L, d.counters);
     if (np > 0)
-        k_ss_fill<<<nblk(np, 64), 64, 0, s>>>(eri, n, c->tau, d.ss_off, d.ss_qs, d.ss_v, c->sa, c->sb, c->L,
+        k_ss_fill<<<nblk(np, 64), 64, 0, s>>>(E, c->tau, d.ss_off, d.ss_qs, d.ss_v, c->sa, c->sb, c->L,
                                                d.counters);
-    k_ab_fill<<<nblk(n3, 256), 256, 0, s>>>(eri, n, c->tau, d.ab_off, d.ab_s, d.ab_v, c->sa, c->sb, c->L,
+    k_ab_fill<<<nblk(n3, 256), 256, 0, s>>>(E, c->tau, d.ab_off, d.ab_s, d.ab_v, c->sa, c->sb, c->L,
                                              d.counters);
     k_pq_fill<<<nblk(n, 64), 64, 0, s>>>(d.ab_off, n, d.pq_off, d.pq_q);
     ISCI_HIP(hipGetLastError());
@@ -1027,9 +1076,11 @@ isci_status isci_create(isci_handle *out, const double *h, const double *eri, in
     return isci_create_ex(out, h, eri, norb, nalpha, nbeta, max_excitation, tau, nullptr, stream);
 }
 
-isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri, int norb, int nalpha,
-                           int nbeta, int max_excitation, double tau, const isci_create_opts *opts,
-                           hipStream_t stream)
+// Shared body of isci_create_ex (dense eri) and isci_create_factored
+// (factors Lfac [naux][norb][norb], eri == nullptr).
+static isci_status create_impl(isci_handle *out, const double *h, const double *eri, const double *Lfac, int naux,
+                               int norb, int nalpha, int nbeta, int max_excitation, double tau,
+                               const isci_create_opts *opts, hipStream_t stream)
 {
     if (!out) { set_error("out is NULL"); return ISCI_E_INVALID; }
     *out = nullptr;
@@ -1044,7 +1095,8 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         set_error("isci_create_opts.allocator needs both alloc and free");
         return ISCI_E_INVALID;
     }
-    if (!h || !eri) { set_error("h or eri is NULL"); return ISCI_E_INVALID; }
+    if (!h || (!eri && !Lfac)) { set_error("h or the two-electron integrals are NULL"); return ISCI_E_INVALID; }
+    if (Lfac && naux < 1) { set_error("naux < 1"); return ISCI_E_INVALID; }
     if (norb < 1) { set_error("norb < 1"); return ISCI_E_INVALID; }
     if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb) {
         set_error("electron counts outside [0, norb]");
@@ -1166,31 +1218,53 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
             if (e2 != hipSuccess) { destroy(c); return hip_fail(e2, "upload row tables"); }
         }
     }
+    // integral source; for factors, their transposed copy and norm bounds
+    // live for this call only
+    EriSrc E{eri, nullptr, nullptr, norb, 0};
+    double *Lt = nullptr, *nrm = nullptr;
+    auto free_factors = [&]() {
+        if (Lt) (void)hipFreeAsync(Lt, stream);
+        if (nrm) (void)hipFreeAsync(nrm, stream);
+        Lt = nrm = nullptr;
+    };
     {
         // refuse non-finite integrals before any list is built
         int *bad = nullptr, hbad = 0;
         const int64_t n3 = (int64_t)norb * norb * norb;
         hipError_t e3 = hipMallocAsync((void **)&bad, sizeof(int), stream);
         if (e3 == hipSuccess) e3 = hipMemsetAsync(bad, 0, sizeof(int), stream);
-        if (e3 == hipSuccess) {
+        if (e3 == hipSuccess && Lfac) {
+            e3 = hipMallocAsync((void **)&Lt, sizeof(double) * (size_t)naux * norb * norb, stream);
+            if (e3 == hipSuccess) e3 = hipMallocAsync((void **)&nrm, sizeof(double) * (size_t)norb * norb, stream);
+            if (e3 == hipSuccess) {
+                k_check_finite_h<<<nblk((int64_t)norb * norb, 256), 256, 0, stream>>>(h, norb, bad);
+                k_factor_prep<<<nblk((int64_t)norb * norb, 256), 256, 0, stream>>>(Lfac, norb, naux, Lt, nrm, bad);
+                e3 = hipGetLastError();
+            }
+            E = EriSrc{nullptr, Lt, nrm, norb, naux};
+        } else if (e3 == hipSuccess) {
             k_check_finite<<<nblk(n3, 256), 256, 0, stream>>>(h, eri, norb, bad);
             e3 = hipGetLastError();
         }
         if (e3 == hipSuccess) e3 = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (bad) (void)hipFreeAsync(bad, stream);
         if (e3 == hipSuccess) e3 = hipStreamSynchronize(stream);
-        if (e3 != hipSuccess) { destroy(c); return hip_fail(e3, "integral check"); }
+        if (e3 != hipSuccess) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return hip_fail(e3, "integral check"); }
         if (hbad) {
+            free_factors();
+            (void)hipStreamSynchronize(stream);
             destroy(c);
-            set_error("h or eri holds a NaN or infinite value in a position that is read");
+            set_error(Lfac ? "h or the factors hold a NaN or infinite value in a position that is read, or a factor norm overflows"
+                           : "h or eri holds a NaN or infinite value in a position that is read");
             return ISCI_E_INVALID;
         }
     }
-    isci_status st = build_lists(c, h, eri, stream);
-    if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
+    isci_status st = build_lists(c, h, E, stream);
+    if (st != ISCI_OK) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return st; }
     if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
         st = build_hscreen(c, h, stream);
-        if (st == ISCI_OK) st = build_tiles(c, eri, stream);
+        if (st == ISCI_OK) st = build_tiles(c, E, stream);
+        free_factors();
         if (st == ISCI_OK) st = build_abx(c, stream);
         const bool full_pairs = c->L >= 2 && c->sb.le[c->L - 2] == c->sb.nstr && c->sa.nstr == c->sb.nstr;
         if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && (norb > kObMaxNorb || full_pairs)) {
@@ -1217,8 +1291,28 @@ isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri,
         if (st == ISCI_OK && hipStreamSynchronize(stream) != hipSuccess) st = ISCI_E_HIP;
         if (st != ISCI_OK) { (void)hipStreamSynchronize(stream); destroy(c); return st; }
     }
+    free_factors();
+    if (hipStreamSynchronize(stream) != hipSuccess) { destroy(c); set_error("stream synchronisation failed"); return ISCI_E_HIP; }
     *out = c;
     return ISCI_OK;
+}
+
+isci_status isci_create_ex(isci_handle *out, const double *h, const double *eri, int norb, int nalpha,
+                           int nbeta, int max_excitation, double tau, const isci_create_opts *opts,
+                           hipStream_t stream)
+{
+    if (out) *out = nullptr;
+    if (!eri) { set_error("eri is NULL"); return ISCI_E_INVALID; }
+    return create_impl(out, h, eri, nullptr, 0, norb, nalpha, nbeta, max_excitation, tau, opts, stream);
+}
+
+isci_status isci_create_factored(isci_handle *out, const double *h, const double *Lfac, int naux, int norb,
+                                 int nalpha, int nbeta, int max_excitation, double tau,
+                                 const isci_create_opts *opts, hipStream_t stream)
+{
+    if (out) *out = nullptr;
+    if (!Lfac) { set_error("Lfac is NULL"); return ISCI_E_INVALID; }
+    return create_impl(out, h, nullptr, Lfac, naux, norb, nalpha, nbeta, max_excitation, tau, opts, stream);
 }
 
 isci_status isci_dim(isci_handle c, int64_t *dim)

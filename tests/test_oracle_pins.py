@@ -519,3 +519,38 @@ def test_density1_brute_force_words(norb, na, nb, L):
                         continue
                     want[s, p, q] += sg * c[j] * c[k]
     np.testing.assert_allclose(O.density1(S, c[None])[0], want, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- factored integrals
+@pytest.mark.parametrize("norb,naux,seed", [(6, 4, 0), (9, 18, 1), (12, 5, 2)])
+def test_assemble_factored_gram_structure(norb, naux, seed):
+    """(pq|rs) = sum_K L^K_pq L^K_rs is a Gram matrix over the pair index:
+    positive semidefinite, rank <= naux, symmetric under (pq) <-> (rs), with
+    |(pq|rs)|^2 <= (pq|pq)(rs|rs); with symmetric factors it has the 8-fold
+    symmetry exactly (each term is formed from the same two doubles)."""
+    from isci_inputs.recipes import factors_a
+    rng = np.random.default_rng(seed)
+    Lr = rng.standard_normal((naux, norb, norb))
+    E = O.assemble_factored(Lr)
+    M = E.reshape(norb * norb, norb * norb)
+    assert np.array_equal(M, M.T)
+    w = np.linalg.eigvalsh(M)
+    assert w.min() >= -1e-12 * w.max()
+    assert np.sum(w > 1e-10 * w.max()) <= naux
+    d = np.diag(M)
+    assert np.all(M ** 2 <= np.outer(d, d) * (1 + 1e-12) + 1e-300)
+    _h, Ls = factors_a(norb, float(norb), naux, seed)
+    Ls = 0.5 * (Ls + Ls.transpose(0, 2, 1))
+    Es = O.assemble_factored(Ls)
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)]:
+        assert np.array_equal(Es, Es.transpose(perm))
+
+
+def test_assemble_factored_matches_matrix_product_assembly():
+    """The same recipe-A factors assembled by the inputs module (one matrix
+    product) agree within rounding."""
+    from isci_inputs.recipes import assemble_eri, factors_a
+    _h, L = factors_a(14, 14.0, 28, 3)
+    a = O.assemble_factored(L)
+    b = assemble_eri(L)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
