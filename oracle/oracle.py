@@ -24,6 +24,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
   (the (pq),(rs) matrix is positive semidefinite of rank <= naux, symmetric,
   and obeys the Cauchy-Schwarz bound) and by agreement within rounding with
   the inputs module's matrix-product assembly of the same factors.
+* ``density2``: pinned by the energy identity <c|H|c> = sum h D1 + 1/2 sum
+  (pq|rs) D2 against the oracle sigma for generic integrals, traces and
+  partial traces (electron-pair counts, reduction to ``density1``),
+  same-spin antisymmetry, Hermiticity and single determinants; planted
+  mistakes are rejected.
 * ``density1``: pinned by single determinants (occupation numbers), the
   trace (electron count), the one-body energy against ``dense_h`` with the
   two-electron integrals set to zero, the alpha/beta swap, and brute force
@@ -436,4 +441,107 @@ def density1(space: Space, c) -> np.ndarray:
             vals = -vals
         for v in range(nv):
             np.add.at(d[v, 1], (P[sel], Q[sel]), vals[v])
+    return d
+
+
+def _word(orbs, ops):
+    """Apply an operator word to the ascending creator string `orbs`: ops
+    are (kind, orbital) pairs in the order they act (rightmost operator of
+    the word first), kind '-' annihilates (sign (-1)^position), '+' creates
+    at the front and sorts into place (sign (-1)^(#creators below)).
+    Returns (sign, new string) or None when the word gives zero."""
+    cur = list(orbs)
+    sign = 1
+    for kind, x in ops:
+        if kind == "-":
+            if x not in cur:
+                return None
+            k = cur.index(x)
+            sign = -sign if k % 2 else sign
+            del cur[k]
+        else:
+            if x in cur:
+                return None
+            below = sum(1 for y in cur if y < x)
+            sign = -sign if below % 2 else sign
+            cur.append(x)
+            cur.sort()
+    return sign, tuple(cur)
+
+
+def density2(space: Space, c) -> np.ndarray:
+    """Two-body density matrices of each vector by spin block: the paper's
+    D2 (its density-matrix subsection, Eq. d2) with spin-orbital indices,
+    d[v, b, p, q, r, s] = <c_v| a+_{p S} a+_{r S'} a_{s S'} a_{q S} |c_v>,
+    b = 0: S = S' = alpha, 1: S = alpha, S' = beta, 2: S = S' = beta.  The
+    block S = beta, S' = alpha is d[v, 1] with (p, q) and (r, s) exchanged.
+
+    Every (source determinant, word) pair that lands in the space adds
+    sign * c(target) * c(source), the sign from applying the word to the
+    ordered creators.  Same-spin words act on one spin's string (the other
+    string is unchanged: alpha words pair rows over the beta strings both
+    hold; beta words stay in a row, and passing the alpha creators with an
+    even number of operators costs no sign).  The alpha-beta word equals
+    (a+_{p a} a_{q a})(a+_{r b} a_{s b}) (a_{q a} moved past two beta
+    operators), so its sign is the product of the two replacements'."""
+    c = np.atleast_2d(np.asarray(c, dtype=np.float64))
+    nv = c.shape[0]
+    n = space.norb
+    ao, _ = space.strings(0)
+    bo, _ = space.strings(1)
+    rs = space.rowstart()
+    ln = np.diff(rs)
+    amap = {tuple(int(x) for x in o): i for i, o in enumerate(ao)}
+    bmap = {tuple(int(x) for x in o): i for i, o in enumerate(bo)}
+    d = np.zeros((nv, 3, n, n, n, n))
+    # alpha-alpha: pair rows over the beta strings both hold
+    for i, o in enumerate(ao):
+        src = tuple(int(x) for x in o)
+        for q in src:
+            for s_ in src:
+                for p in range(n):
+                    for r in range(n):
+                        w = _word(src, [("-", q), ("-", s_), ("+", r), ("+", p)])
+                        if w is None or w[1] not in amap:
+                            continue
+                        j = amap[w[1]]
+                        m = int(min(ln[i], ln[j]))
+                        d[:, 0, p, q, r, s_] += w[0] * np.einsum("vk,vk->v", c[:, rs[j]:rs[j] + m],
+                                                                 c[:, rs[i]:rs[i] + m])
+    # beta words of one row, tabulated once: source k, target j, sign
+    def beta_words(two):
+        tab = []
+        for k, o in enumerate(bo):
+            src = tuple(int(x) for x in o)
+            for q in src:
+                for s_ in (src if two else [None]):
+                    for p in range(n):
+                        for r in (range(n) if two else [None]):
+                            ops = [("-", q), ("-", s_), ("+", r), ("+", p)] if two else [("-", q), ("+", p)]
+                            w = _word(src, ops)
+                            if w is None or w[1] not in bmap:
+                                continue
+                            tab.append((k, bmap[w[1]], p, q, r, s_, w[0]))
+        return tab
+    bb = beta_words(True)
+    for i in range(len(ao)):
+        for k, j, p, q, r, s_, sg in bb:
+            if k < ln[i] and j < ln[i]:
+                d[:, 2, p, q, r, s_] += sg * c[:, rs[i] + j] * c[:, rs[i] + k]
+    # alpha-beta: an alpha replacement q -> p times a beta replacement s -> r
+    b1 = beta_words(False)
+    for i, o in enumerate(ao):
+        src = tuple(int(x) for x in o)
+        for q in src:
+            for p in range(n):
+                w = _word(src, [("-", q), ("+", p)])
+                if w is None or w[1] not in amap:
+                    continue
+                j = amap[w[1]]
+                for k, jb, r, s_, _u1, _u2, sb in b1:
+                    if k < ln[i] and jb < ln[j]:
+                        sgn = w[0] * (1 if "D2_AB_NO_BETA_SIGN" in _PLANT else sb)
+                        d[:, 1, p, q, r, s_] += sgn * c[:, rs[j] + jb] * c[:, rs[i] + k]
+    if "D2_AA_SWAP_QS" in _PLANT:
+        d[:, 0] = d[:, 0].transpose(0, 1, 4, 3, 2).copy()
     return d

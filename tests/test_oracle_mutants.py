@@ -41,6 +41,8 @@ def test_pins_reject_planted_mistake(macro, tmp_path):
 # Mistakes planted in the numpy part of the oracle (an environment switch
 # read when the module loads).
 PY_MUTANTS = [
+    "D2_AB_NO_BETA_SIGN",    # two-body alpha-beta block: beta replacement sign dropped
+    "D2_AA_SWAP_QS",         # two-body alpha-alpha block: annihilator indices q and s exchanged
     "D1_HALF_SIGN",          # phase of a+_p ignored (only a_q's counted)
     "D1_LONG_ROW",           # alpha dot over the longer row: reads past the shorter one
     "D1_BETA_PAST_ALPHA",    # beta replacement signed by the alpha creators it passes
@@ -51,7 +53,7 @@ PY_MUTANTS = [
 def test_density_pins_reject_planted_mistake(plant):
     env = dict(os.environ, ISCI_ORACLE_PLANT=plant)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "density1"],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "density"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch {plant}:\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout

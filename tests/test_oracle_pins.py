@@ -554,3 +554,83 @@ def test_assemble_factored_matches_matrix_product_assembly():
     a = O.assemble_factored(L)
     b = assemble_eri(L)
     assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+# ---------------------------------------------------------------- two-body density matrices
+_D2_SPACES = [(6, 2, 2, 2), (5, 3, 1, 3), (5, 2, 1, 2), (5, 1, 1, 2), (5, 0, 2, 2), (6, 2, 2, 4)]
+
+
+def _d2_total(d2):
+    """sum over the spin blocks of <a+_p a+_r a_s a_q>: aa + ab + ba + bb,
+    ba[p,q,r,s] = ab[r,s,p,q]."""
+    return d2[:, 0] + d2[:, 1] + d2[:, 1].transpose(0, 3, 4, 1, 2) + d2[:, 2]
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D2_SPACES)
+def test_density2_energy_identity(norb, na, nb, L):
+    """<c|H|c> from the oracle sigma equals sum h D1 + 1/2 sum (pq|rs) D2 for
+    integrals with no symmetry beyond the 8-fold one."""
+    h, eri = _ints("R", norb, 11)
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 2, seed=5)
+    e = np.einsum("vi,vi->v", c, O.sigma(S, h, eri, 0.0, c))
+    d1 = O.density1(S, c)
+    d2 = O.density2(S, c)
+    e1 = np.einsum("pq,vpq->v", h, d1[:, 0] + d1[:, 1])
+    e2 = 0.5 * np.einsum("pqrs,vpqrs->v", eri, _d2_total(d2))
+    assert np.abs(e1 + e2 - e).max() <= 1e-12 * np.abs(e).max()
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D2_SPACES)
+def test_density2_traces_and_reduction(norb, na, nb, L):
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 2, seed=6)
+    nn = (c * c).sum(1)
+    d1 = O.density1(S, c)
+    d2 = O.density2(S, c)
+    tr = np.einsum("vbpprr->vb", d2)
+    assert np.allclose(tr[:, 0], na * (na - 1) * nn, rtol=1e-12, atol=1e-12)
+    assert np.allclose(tr[:, 1], na * nb * nn, rtol=1e-12, atol=1e-12)
+    assert np.allclose(tr[:, 2], nb * (nb - 1) * nn, rtol=1e-12, atol=1e-12)
+    # the other spin's number operator, or the same spin's minus one
+    assert np.allclose(np.einsum("vpqrr->vpq", d2[:, 1]), nb * d1[:, 0], atol=1e-12)
+    assert np.allclose(np.einsum("vpprs->vrs", d2[:, 1]), na * d1[:, 1], atol=1e-12)
+    assert np.allclose(np.einsum("vpqrr->vpq", d2[:, 0]), (na - 1) * d1[:, 0], atol=1e-12)
+    assert np.allclose(np.einsum("vpqrr->vpq", d2[:, 2]), (nb - 1) * d1[:, 1], atol=1e-12)
+
+
+@pytest.mark.parametrize("norb,na,nb,L", _D2_SPACES[:3])
+def test_density2_symmetries(norb, na, nb, L):
+    S = O.Space(norb, na, nb, L)
+    c = random_vectors(S.dim, 1, seed=2)
+    d2 = O.density2(S, c)
+    for b in (0, 2):
+        assert np.allclose(d2[:, b], -d2[:, b].transpose(0, 3, 2, 1, 4), atol=1e-13)
+        assert np.allclose(d2[:, b], -d2[:, b].transpose(0, 1, 4, 3, 2), atol=1e-13)
+    for b in range(3):   # real vectors: <a+p a+r a_s a_q> = <a+q a+s a_r a_p>
+        assert np.allclose(d2[:, b], d2[:, b].transpose(0, 2, 1, 4, 3), atol=1e-13)
+
+
+def test_density2_single_determinant():
+    norb, na, nb, L = 6, 2, 2, 2
+    S = O.Space(norb, na, nb, L)
+    ao, _ = S.strings(0)
+    bo, _ = S.strings(1)
+    rs = S.rowstart()
+    i = 3
+    k = 2
+    c = np.zeros((1, S.dim))
+    c[0, rs[i] + k] = 1.0
+    d2 = O.density2(S, c)
+    A, B = [int(x) for x in ao[i]], [int(x) for x in bo[k]]
+    want = np.zeros((3, norb, norb, norb, norb))
+    for p in A:
+        for r in B:
+            want[1, p, p, r, r] = 1.0
+    for blk, occ in ((0, A), (2, B)):
+        for p in occ:
+            for r in occ:
+                if p != r:
+                    want[blk, p, p, r, r] = 1.0
+                    want[blk, p, r, r, p] = -1.0
+    assert np.array_equal(d2[0], want)
