@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=120, help="served mode: requests (of the 2000-request stream)")
     ap.add_argument("--max-wall", type=float, default=240.0, help="served mode: wall-clock cap (s)")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
+    ap.add_argument("--dense-eri", action="store_true",
+                    help="served mode: requests carry dense eri tensors instead of factors")
     ap.add_argument("--fast-dim", type=int, default=1_000_000,
                     help="served mode: solves of at most this many determinants form the fast class (0: one class)")
     ap.add_argument("--fast-share", type=float, default=0.75, help="served mode: GPU time share of the fast class")
@@ -409,32 +411,47 @@ def bench_served(a):
     import numpy as np
     import torch
     from paper_1609_07757_amd.serve import GpuExecutor, Request, Server
-    from isci_inputs.device import integrals_on_device
+    from isci_inputs.device import factors_on_device, integrals_on_device
     from isci_inputs.workloads import served_requests
     stream = served_requests(2000)[: a.requests]
     reqs = []
     for i, (t, W) in enumerate(stream):
-        def payload(W=W):
-            return integrals_on_device(W.norb, W.box_len, W.n_aux, W.seed)
-        reqs.append(Request(i, t, W.norb, 2, 2, W.level, W.tau, W.nroots, payload=payload))
+        if a.dense_eri:
+            def payload(W=W):
+                return integrals_on_device(W.norb, W.box_len, W.n_aux, W.seed)
+        else:
+            def payload(W=W):
+                return factors_on_device(W.norb, W.box_len, W.n_aux, W.seed)
+        reqs.append(Request(i, t, W.norb, 2, 2, W.level, W.tau, W.nroots, payload=payload,
+                            naux=0 if a.dense_eri else W.n_aux))
     ex = GpuExecutor(fast_dim=a.fast_dim, fast_share=a.fast_share)
     srv = Server(ex, hbm_budget=int(a.hbm_budget_gb * 2**30), max_slots=64)
+    samples = []
+
+    def progress(r):
+        samples.append({k: r[k] for k in ("t", "queued", "running", "served") if k in r})
+        print("served progress", json.dumps(r), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    srv.run(reqs, max_wall=a.max_wall,
-            progress=lambda r: print("served progress", json.dumps(r), file=sys.stderr, flush=True))
+    srv.run(reqs, max_wall=a.max_wall, progress=progress)
     wall = time.perf_counter() - t0
     rep = srv.report()
     done = [r for r in srv.done if r.status == "done"]
+    last_arrival = max(r.arrival for r in reqs) if reqs else 0.0
     out = {"metric": "served Davidson solves: p50/p99 latency and σ throughput",
            "value": rep.get("p50_s"), "unit": "s (p50 latency)", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64", "data": "synthetic (recipe A, per-request seeds, Poisson arrivals)",
            "config": {"workload": "served_poisson50", "requests_offered": len(reqs), "rate_per_s": 50,
                       "tau": 1e-12, "hbm_budget_gb": a.hbm_budget_gb,
-                      "fast_class_dim": a.fast_dim, "fast_class_share": a.fast_share},
+                      "fast_class_dim": a.fast_dim, "fast_class_share": a.fast_share,
+                      "integrals": "dense eri" if a.dense_eri else "factors (isci_create_factored)"},
            "p50_s": rep.get("p50_s"), "p99_s": rep.get("p99_s"), "served": rep["served"],
            "rejected": rep["rejected"], "wall_s": wall, "sigma_vectors_per_s": ex.sigma_vectors / wall,
            "peak_concurrent": rep["peak_running"], "peak_bytes": rep["peak_bytes"],
-           "norb_served": sorted(r.norb for r in done)[-3:]}
+           "norb_served": sorted(r.norb for r in done)[-3:],
+           "offered_rate_per_s": len(reqs) / last_arrival if last_arrival > 0 else None,
+           "sustained_rate_per_s": rep["served"] / wall if wall > 0 else None,
+           "unfinished": len(reqs) - rep["served"] - rep["rejected"],
+           "oom_requeued": rep.get("oom_requeued", 0), "queue_over_time": samples}
     ex.close()
     print(json.dumps(out), flush=True)
 

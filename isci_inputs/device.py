@@ -22,3 +22,12 @@ def integrals_on_device(norb: int, box: float, naux: int, seed: int, recipe: str
     eri = (Lt.t() @ Lt).reshape(norb, norb, norb, norb)
     del Lt
     return torch.from_numpy(h).to(device), eri
+
+
+def factors_on_device(norb: int, box: float, naux: int, seed: int, recipe: str = "A", device="cuda"):
+    """(h, L) on the device, L[K, p, q] = L^K_pq as drawn by the recipe: the
+    input of a factored handle, 8 (naux + 1) norb^2 bytes instead of the
+    8 norb^4 of the dense tensor."""
+    import torch
+    h, L = factors_a(norb, box, naux, seed, recipe)
+    return torch.from_numpy(h).to(device), torch.from_numpy(np.ascontiguousarray(L)).to(device)

@@ -34,6 +34,7 @@ class Request:
     tau: float
     nroots: int
     payload: object = None      # executor-specific (integrals or a generator)
+    naux: int = 0               # > 0: the payload gives factors L [naux][norb][norb] instead of a dense eri
     # filled by the server
     admitted: float | None = None
     finished: float | None = None
@@ -67,7 +68,7 @@ def davidson_bytes(dim: int, nroots: int) -> int:
     return 8 * dim * (2 * mmax + nscr + 2 * kk + 1) + 8 * (mmax * mmax + 8 * mmax + 64 + nblk * mmax * mmax + 3 * (mmax + 8))
 
 
-def handle_bytes_estimate(norb: int, dim: int) -> int:
+def handle_bytes_estimate(norb: int, dim: int, naux: int = 0) -> int:
     """Admission estimate of what building a handle needs at its peak: the
     transient dense eri (8 norb^4), list offsets and tables sized for one
     kept alpha-beta unit in eight, the product operands (about 16 B per
@@ -77,13 +78,16 @@ def handle_bytes_estimate(norb: int, dim: int) -> int:
     alone can exceed it.  The server therefore re-charges a running
     request by what its handle really holds (isci_stats.device_bytes, read
     after the build) and puts a request whose build ran out of memory back
-    at the head of the queue."""
+    at the head of the queue.  With factored integrals (naux > 0) the
+    transient is the factors and their transposed copy, 8 (2 naux + 1)
+    norb^2 bytes, instead of the dense tensor."""
     n3 = norb ** 3
     lists = 8 * (n3 + 1) + 9 * norb ** 4 // 8 + 4 * norb * norb * 16
     strings = 8 * (norb * norb) * 4
     operands = 3 * 16 * 4 * dim
     onebody = 64 * dim if norb > 80 else 0
-    return 8 * norb ** 4 + lists + strings + 8 * dim + operands + onebody
+    transient = 8 * (2 * naux + 1) * norb * norb if naux > 0 else 8 * norb ** 4
+    return transient + lists + strings + 8 * dim + operands + onebody
 
 
 # kept for callers of the earlier name
@@ -247,9 +251,11 @@ def pick_class(active, tclass, share: float) -> int:
 
 class GpuExecutor:
     """Runs requests on the HIP library: integrals are produced on the
-    device by `payload` (a callable returning (h, eri) CUDA tensors), the
-    handle is built, the dense eri is dropped, and the solve joins an
-    engine.  Footprint = transient eri + handle tables (bound) + subspace.
+    device by `payload` (a callable returning (h, eri) CUDA tensors, or
+    (h, L) factors when the request has naux > 0, built with
+    isci_create_factored), the handle is built, the integrals are dropped,
+    and the solve joins an engine.  Footprint = transient integrals +
+    handle tables (estimate, then what the handle holds) + subspace.
 
     Two size classes, each in its own engine: solves of at most `fast_dim`
     determinants and the rest.  An engine step advances every solve of one
@@ -274,7 +280,7 @@ class GpuExecutor:
 
     def footprint(self, r: Request) -> int:
         dim = ci_dim(r.norb, r.nalpha, r.nbeta, r.level)
-        return handle_bytes_estimate(r.norb, dim) + davidson_bytes(dim, r.nroots)
+        return handle_bytes_estimate(r.norb, dim, r.naux) + davidson_bytes(dim, r.nroots)
 
     def start(self, r: Request):
         """Build the handle and admit the solve.  Raises MemoryError (after
@@ -282,9 +288,12 @@ class GpuExecutor:
         import torch
         hd = None
         try:
-            h, eri = r.payload()
-            hd = self.isci.isci_create(h, eri, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
-            del h, eri
+            h, ints = r.payload()
+            if r.naux > 0:
+                hd = self.isci.isci_create_factored(h, ints, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
+            else:
+                hd = self.isci.isci_create(h, ints, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
+            del h, ints
             cls = 0 if hd.dim <= self.fast_dim else 1
             slot = self.isci.isci_engine_add(self.engs[cls], hd, nroots=r.nroots, **self.opts)
         except torch.cuda.OutOfMemoryError as e:
