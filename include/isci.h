@@ -166,11 +166,26 @@ typedef struct {
     void *ctx;
 } isci_allocator;
 
+/* Distance screening (the paper's proposal, in its discussion of the
+ * screening results, of an additional integral screening by the distance
+ * between orbitals, the route to linear scaling): with orb_dist (host,
+ * [norb][norb] distances d(p, q) >= 0, read during creation only) and
+ * max_dist > 0, every integral unit whose orbitals are not all within
+ * max_dist of each other is removed from H as well: h_pq when d(p, q) >
+ * max_dist, a two-electron unit over p, q, r, s when any of the six
+ * pairwise distances exceeds it.  The handle then applies the Hamiltonian of
+ * the integrals with those elements set to zero (screened by the usual rule
+ * besides).  orb_dist NULL or max_dist == 0: off.  ISCI_E_INVALID when
+ * orb_dist is given with a NaN or negative max_dist, or (screening on) holds
+ * a NaN, infinite or negative distance.  A matrix that is not symmetric is
+ * read as max(d(p, q), d(q, p)) for the pair p, q. */
 typedef struct {
     int onebody;                      /* ISCI_OB_* (default ISCI_OB_AUTO) */
     const isci_allocator *allocator;  /* NULL: hipMalloc / hipFree; else
                                          both function pointers set; the
                                          struct is copied at creation */
+    const double *orb_dist;           /* host [norb][norb] or NULL (no distance screening) */
+    double max_dist;                  /* distance screening radius; 0: off */
 } isci_create_opts;
 
 /* isci_create with build options; opts may be NULL (defaults).  Returns
@@ -277,6 +292,30 @@ isci_status isci_diag(isci_handle hd, double *diag, hipStream_t stream);
 isci_status isci_density1(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d1,
                           hipStream_t stream);
 
+/* Two-body density matrices of each vector by spin block (the paper's
+ * density matrices, Eq. d2, with spin-orbital indices):
+ *   d2[(((v * 3 + b) * norb + p) * norb + q) * norb^2 + r * norb + s]
+ *     = <c_v| a+_{p S} a+_{r S'} a_{s S'} a_{q S} |c_v>,
+ * b = 0: S = S' = alpha; b = 1: S = alpha, S' = beta; b = 2: S = S' = beta
+ * (the block S = beta, S' = alpha is block 1 with (p, q) and (r, s)
+ * exchanged), for v < nvec (1..65535).  The energy of a vector is
+ * sum_pq h_pq D1_pq + 1/2 sum_pqrs (pq|rs) D2_pqrs summed over the spin
+ * blocks.  Two electrons of each spin and at most 128 orbitals
+ * (ISCI_E_UNSUPPORTED otherwise).  Each block is a Gram product on the
+ * matrix cores: same-spin blocks from the rows of c (alpha) or of its
+ * spin-swapped copy (beta), the alpha-beta block from the pair tensor
+ * M[(p, r)][(x, y)] = sgn(p - x) sgn(r - y) c({x, p}, {y, r}).  c: device,
+ * nvec vectors with leading dimension ldc >= dim, not normalised by the
+ * call; d2: device, nvec * 3 * norb^4 doubles, overwritten, must not
+ * overlap c.  The screening threshold plays no part.  Deterministic.  The
+ * handle allocates on its first call, and keeps until it is destroyed,
+ * about 16 norb^4 + 8 dim bytes of scratch.  Calls on one handle share it
+ * and must be ordered; otherwise asynchronous on `stream`.  Errors:
+ * ISCI_E_INVALID for NULL pointers, nvec or ldc out of range, overlap;
+ * ISCI_E_OOM if the scratch cannot be allocated. */
+isci_status isci_density2(isci_handle hd, int nvec, const double *c, int64_t ldc, double *d2,
+                          hipStream_t stream);
+
 /* isci_density1 without any device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Same arguments, results and
@@ -308,6 +347,49 @@ isci_status isci_density1_noalloc(isci_handle hd, int nvec, const double *c, int
 isci_status isci_davidson(isci_handle hd, int nroots, const isci_davidson_opts *opts,
                           const double *guess, int nguess, double *energies, double *vectors,
                           isci_davidson_info *info, hipStream_t stream);
+
+/* Propagation of CI vectors under H_tau by the short-iterative
+ * Arnoldi-Lanczos method: the optimiser the paper uses for the CI
+ * coefficients (propagation in imaginary time, application section: thousands
+ * of sigma steps), and real-time propagation for dynamics.  Each of nsteps
+ * steps of length dt builds a Krylov basis of H_tau from the current vector
+ * (each new direction orthogonalised against the basis twice), stops when
+ * the residual estimate of the step falls below tol |u| or at `krylov`
+ * vectors, and applies exp(-T dt) (imaginary) or exp(-i T dt) (real) of the
+ * projected matrix.  Coefficient screening (the paper's proposal in its
+ * section on the distribution of coefficients): after every step the
+ * elements of modulus <= coef_tau are set to zero (0: off).
+ *   imaginary = 1: c_re (device [dim]) <- exp(-H dt) c_re, normalised after
+ *                  every step; c_im is not read (may be NULL);
+ *   imaginary = 0: c_re + i c_im <- exp(-i H dt) (c_re + i c_im) (both device
+ *                  [dim], distinct).
+ * Vectors are updated in place.  The call allocates its Krylov basis
+ * ((krylov + 1) dim doubles per real chain) for its own duration and
+ * synchronises the stream a few times per Krylov vector (small host
+ * eigenproblems).  info (may be NULL): energy <c|H|c>/<c|c> of the result
+ * (one more sigma), its norm, sigma vectors computed, Krylov size of the
+ * last step and coefficients zeroed by the last screening.  Errors:
+ * ISCI_E_INVALID for NULL handle or c_re, a missing or aliased c_im in real
+ * time, dt negative or not finite, nsteps < 0, krylov outside 1..128,
+ * negative tol or coef_tau; ISCI_E_OOM when the basis does not fit. */
+typedef struct {
+    int krylov;         /* largest Krylov basis per step (default 16) */
+    int imaginary;      /* 1: imaginary time (default), 0: real time */
+    double tol;         /* Krylov residual tolerance relative to |u| (default 1e-12) */
+    double coef_tau;    /* coefficient screening threshold (default 0: off) */
+} isci_propagate_opts;
+
+typedef struct {
+    double energy;
+    double norm;
+    int sigma_calls;
+    int krylov_last;
+    int64_t screened_last;
+} isci_propagate_info;
+
+void isci_propagate_defaults(isci_propagate_opts *o);
+isci_status isci_propagate(isci_handle hd, double *c_re, double *c_im, double dt, int nsteps,
+                           const isci_propagate_opts *opts, isci_propagate_info *info, hipStream_t stream);
 
 /* Host copies of the string tables of one spin: the occupation strings
  * that build the determinants of Eq. ci_ansatz, with their excitation

@@ -29,6 +29,17 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
   partial traces (electron-pair counts, reduction to ``density1``),
   same-spin antisymmetry, Hermiticity and single determinants; planted
   mistakes are rejected.
+* ``propagate_exact``: pinned by the properties that fix the exponential:
+  real time keeps the norm and the energy, steps compose (t1 then t2 is
+  t1 + t2), the short-time difference quotient is -i H c (resp. -(H - E) c)
+  with H c from the oracle sigma, and imaginary time tends to the lowest
+  eigenvector; its coefficient screening by a threshold below every
+  coefficient (no change), one step checked element by element, and the
+  variational bound of the screened vector.
+* ``mask_by_distance``: pinned by brute-force enumeration of every element
+  on tiny inputs, and by its limits (a radius above every distance changes
+  nothing; below every non-zero distance only the one-orbital units p = q = r
+  = s and h_pp survive).
 * ``density1``: pinned by single determinants (occupation numbers), the
   trace (electron count), the one-body energy against ``dense_h`` with the
   two-electron integrals set to zero, the alpha/beta swap, and brute force
@@ -545,3 +556,49 @@ def density2(space: Space, c) -> np.ndarray:
     if "D2_AA_SWAP_QS" in _PLANT:
         d[:, 0] = d[:, 0].transpose(0, 1, 4, 3, 2).copy()
     return d
+
+
+def propagate_exact(space: Space, h, eri, tau: float, c_re, c_im=None, t: float = 0.0, imaginary: bool = True,
+                    nsteps: int = 1, coef_tau: float = 0.0):
+    """exp(-H_tau t) c normalised (imaginary time) or exp(-i H_tau t) (c_re +
+    i c_im) (real time) for tiny spaces, by the spectral decomposition of
+    the dense H_tau: the propagation the library's short-iterative
+    Arnoldi-Lanczos steps approximate.  With coef_tau > 0 the time t is
+    taken in nsteps equal steps and, after each (and after the
+    normalisation in imaginary time), every coefficient of modulus <=
+    coef_tau is set to zero: the screening of small CI coefficients the
+    paper proposes.  Returns a real vector (imaginary) or a complex one
+    (real time)."""
+    H = dense_h(space, h, eri, tau)
+    w, V = np.linalg.eigh(0.5 * (H + H.T))
+    c = np.asarray(c_re, dtype=np.float64) + (0.0 if c_im is None else 1j * np.asarray(c_im, dtype=np.float64))
+    steps = nsteps if coef_tau > 0.0 else 1
+    dt = t / steps
+    for _ in range(steps):
+        y = V.T @ c
+        if imaginary:
+            c = np.real(V @ (np.exp(-(w - w[0]) * dt) * y))
+            c = c / np.linalg.norm(c)
+        else:
+            c = V @ (np.exp(-1j * w * dt) * y)
+        if coef_tau > 0.0:
+            c = np.where(np.abs(c) <= coef_tau, 0.0, c)
+    return c
+
+
+def mask_by_distance(h, eri, dist, dmax: float):
+    """Distance screening of the integrals: h_pq set to zero when d(p, q) >
+    dmax, (pq|rs) when any of the six distances among p, q, r, s exceeds
+    dmax (the additional distance-dependent screening the paper proposes).
+    Returns masked copies."""
+    h = np.array(h, dtype=np.float64)
+    eri = np.array(eri, dtype=np.float64)
+    d = np.asarray(dist, dtype=np.float64)
+    far = (d > dmax) | (d.T > dmax)     # a pair is as far as its larger entry
+    h[far] = 0.0
+    n = h.shape[0]
+    I = np.arange(n)
+    p, q, r, s = np.meshgrid(I, I, I, I, indexing="ij")
+    span_far = far[p, q] | far[p, r] | far[p, s] | far[q, r] | far[q, s] | far[r, s]
+    eri[span_far] = 0.0
+    return h, eri

@@ -21,7 +21,7 @@ __all__ = ["Handle", "isci_create", "isci_dim", "isci_sigma", "isci_diag", "isci
            "isci_engine_sigma", "isci_engine_destroy", "isci_davidson_footprint", "isci_set_option",
            "SIGMA_AUTO", "SIGMA_GENERAL", "SIGMA_PAIR", "SIGMA_MFMA", "OPT_AB_PATH", "AB_AUTO",
            "AB_GATHER", "SigmaGraph", "isci_sigma_graph_create", "torch_allocator", "isci_density1",
-           "isci_density1_noalloc", "isci_create_factored"]
+           "isci_density1_noalloc", "isci_create_factored", "isci_density2", "isci_propagate"]
 
 OPT_SIGMA_KERNEL = 1
 SIGMA_AUTO, SIGMA_GENERAL, SIGMA_PAIR, SIGMA_MFMA = 0, 1, 2, 3
@@ -118,22 +118,36 @@ def torch_allocator():
     return _lib.IsciAllocator(_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free), None)
 
 
+def _create_opts(onebody, allocator, orb_dist, max_dist, norb):
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
+        allocator = torch_allocator()
+    dist = None
+    if orb_dist is not None:
+        dist = np.ascontiguousarray(orb_dist, dtype=np.float64)
+        if dist.shape != (norb, norb):
+            raise ValueError("orb_dist must be [norb, norb]")
+    opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None,
+                               dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dist is not None else None,
+                               float(max_dist))
+    return opts, allocator, dist
+
+
 def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
-                stream=None, onebody: int = OB_AUTO, allocator=None) -> Handle:
+                stream=None, onebody: int = OB_AUTO, allocator=None, orb_dist=None, max_dist: float = 0.0) -> Handle:
     """Build a handle (isci_create_ex; onebody is one of OB_*).  allocator:
     None (hipMalloc), "torch" (torch's caching allocator) or an
-    _lib.IsciAllocator."""
+    _lib.IsciAllocator.  orb_dist (host [norb, norb]) with max_dist > 0:
+    distance screening (units whose orbitals are not all within max_dist
+    are removed)."""
     L = _lib.load()
     hp = _dev_f64(h, "h")
     ep = _dev_f64(eri, "eri")
     if h.numel() != norb * norb or eri.numel() != norb ** 4:
         raise ValueError("h must hold norb^2 and eri norb^4 elements")
     out = ctypes.c_void_p()
-    if isinstance(allocator, str):
-        if allocator != "torch":
-            raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
-        allocator = torch_allocator()
-    opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None)
+    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb)
     st = L.isci_create_ex(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
                           int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create")
@@ -141,7 +155,8 @@ def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int,
 
 
 def isci_create_factored(h, Lfac, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
-                         stream=None, onebody: int = OB_AUTO, allocator=None) -> Handle:
+                         stream=None, onebody: int = OB_AUTO, allocator=None, orb_dist=None,
+                         max_dist: float = 0.0) -> Handle:
     """Build a handle from factored integrals (pq|rs) = sum_K L^K_pq L^K_rs,
     Lfac of shape [naux, norb, norb] on the device, with no dense norb^4
     tensor (isci_create_factored)."""
@@ -151,11 +166,7 @@ def isci_create_factored(h, Lfac, norb: int, nalpha: int, nbeta: int, max_excita
     if h.numel() != norb * norb or Lfac.dim() != 3 or tuple(Lfac.shape[1:]) != (norb, norb):
         raise ValueError("h must hold norb^2 elements and Lfac be [naux, norb, norb]")
     out = ctypes.c_void_p()
-    if isinstance(allocator, str):
-        if allocator != "torch":
-            raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
-        allocator = torch_allocator()
-    opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None)
+    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb)
     st = L.isci_create_factored(ctypes.byref(out), hp, lp, int(Lfac.shape[0]), int(norb), int(nalpha), int(nbeta),
                                 int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create_factored")
@@ -260,6 +271,46 @@ def isci_density1(hd: Handle, c, out=None, stream=None):
     check(_lib.load().isci_density1(hd.ptr, nv, _dev_f64(c2, "c"), int(c2.stride(0)), _dev_f64(out, "d1"),
                                     _stream_ptr(stream)), "isci_density1")
     return out[0] if squeeze else out
+
+
+def isci_density2(hd: Handle, c, out=None, stream=None):
+    """Two-body density matrices by spin block: out[v, b, p, q, r, s] =
+    <c_v| a+_{p S} a+_{r S'} a_{s S'} a_{q S} |c_v> with (S, S') = (a, a),
+    (a, b), (b, b) for b = 0, 1, 2; c of shape [nvec, dim] or [dim]."""
+    torch = _torch()
+    squeeze = c.dim() == 1
+    c2 = c.unsqueeze(0) if squeeze else c
+    if c2.shape[-1] != hd.dim:
+        raise ValueError("c has wrong length")
+    nv, n = int(c2.shape[0]), hd.norb
+    shape = (nv, 3, n, n, n, n)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=c2.device)
+    if tuple(out.shape) != shape or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [nvec, 3, norb, norb, norb, norb] tensor")
+    check(_lib.load().isci_density2(hd.ptr, nv, _dev_f64(c2, "c"), int(c2.stride(0)), _dev_f64(out, "d2"),
+                                    _stream_ptr(stream)), "isci_density2")
+    return out[0] if squeeze else out
+
+
+def isci_propagate(hd: Handle, c_re, dt: float, nsteps: int, c_im=None, imaginary: bool = True, krylov: int = 16,
+                   tol: float = 1e-12, coef_tau: float = 0.0, stream=None) -> dict:
+    """Short-iterative Arnoldi-Lanczos propagation in place: imaginary time
+    c_re <- exp(-H dt) c_re (normalised) or real time (c_re + i c_im) <-
+    exp(-i H dt) (c_re + i c_im), nsteps times; coef_tau > 0 zeroes small
+    coefficients after every step.  Returns the info record as a dict."""
+    L = _lib.load()
+    o = _lib.IsciPropagateOpts()
+    L.isci_propagate_defaults(ctypes.byref(o))
+    o.krylov, o.imaginary, o.tol, o.coef_tau = int(krylov), 1 if imaginary else 0, float(tol), float(coef_tau)
+    info = _lib.IsciPropagateInfo()
+    if c_re.dim() != 1 or c_re.shape[0] != hd.dim or (c_im is not None and tuple(c_im.shape) != tuple(c_re.shape)):
+        raise ValueError("c_re (and c_im) must be [dim] vectors")
+    im = _dev_f64(c_im, "c_im") if c_im is not None else None
+    check(L.isci_propagate(hd.ptr, _dev_f64(c_re, "c_re"), im, float(dt), int(nsteps), ctypes.byref(o),
+                           ctypes.byref(info), _stream_ptr(stream)), "isci_propagate")
+    return {"energy": info.energy, "norm": info.norm, "sigma_calls": info.sigma_calls,
+            "krylov_last": info.krylov_last, "screened_last": info.screened_last}
 
 
 def isci_density1_noalloc(hd: Handle, c, out, stream=None):

@@ -32,8 +32,19 @@ ABI_SYMBOLS = (
     "isci_engine_result", "isci_engine_release", "isci_engine_sigma", "isci_engine_destroy",
     "isci_davidson_footprint", "isci_set_option", "isci_profile", "isci_profile_read",
     "isci_sigma_graph_create", "isci_graph_launch", "isci_graph_destroy", "isci_probe_fp64", "isci_density1",
-    "isci_density1_noalloc", "isci_create_factored",
+    "isci_density1_noalloc", "isci_create_factored", "isci_density2",
+    "isci_propagate_defaults", "isci_propagate",
 )
+
+
+class IsciPropagateOpts(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int), ("imaginary", ctypes.c_int), ("tol", ctypes.c_double),
+                ("coef_tau", ctypes.c_double)]
+
+
+class IsciPropagateInfo(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("norm", ctypes.c_double), ("sigma_calls", ctypes.c_int),
+                ("krylov_last", ctypes.c_int), ("screened_last", ctypes.c_int64)]
 
 
 class IsciStats(ctypes.Structure):
@@ -54,7 +65,8 @@ class IsciAllocator(ctypes.Structure):
 
 class IsciCreateOpts(ctypes.Structure):
     """isci_create_opts."""
-    _fields_ = [("onebody", ctypes.c_int), ("allocator", ctypes.POINTER(IsciAllocator))]
+    _fields_ = [("onebody", ctypes.c_int), ("allocator", ctypes.POINTER(IsciAllocator)),
+                ("orb_dist", ctypes.POINTER(ctypes.c_double)), ("max_dist", ctypes.c_double)]
 
 
 class IsciDavidsonOpts(ctypes.Structure):
@@ -107,6 +119,13 @@ def load(path: str = LIBPATH):
     L.isci_graph_destroy.restype = None
     L.isci_density1.argtypes = [vp, i32, vp, i64, vp, vp]
     L.isci_density1.restype = i32
+    L.isci_propagate_defaults.argtypes = [ctypes.POINTER(IsciPropagateOpts)]
+    L.isci_propagate_defaults.restype = None
+    L.isci_propagate.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(IsciPropagateOpts),
+                                 ctypes.POINTER(IsciPropagateInfo), vp]
+    L.isci_propagate.restype = i32
+    L.isci_density2.argtypes = [vp, i32, vp, i64, vp, vp]
+    L.isci_density2.restype = i32
     L.isci_density1_noalloc.argtypes = [vp, i32, vp, i64, vp, vp]
     L.isci_density1_noalloc.restype = i32
     L.isci_diag.argtypes = [vp, vp, vp]

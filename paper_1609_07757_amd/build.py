@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libisci.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["isci_setup.hip", "isci_sigma.hip", "isci_onebody.hip", "isci_abprod.hip", "isci_davidson.hip",
-           "isci_probe.hip", "isci_density.hip"]
+           "isci_probe.hip", "isci_density.hip", "isci_propagate.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

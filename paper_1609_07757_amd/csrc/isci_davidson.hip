@@ -347,6 +347,13 @@ static bool tridiag_eigh(int m, std::vector<double> A, std::vector<double> &w, s
     return true;
 }
 
+// symmetric eigensolver for small projected matrices (used by the
+// propagator too): tridiagonal QR, cyclic Jacobi when that does not settle
+void sym_eigh(int m, const std::vector<double> &A, std::vector<double> &w, std::vector<double> &Z)
+{
+    if (!tridiag_eigh(m, A, w, Z)) jacobi_eigh(m, A, w, Z);
+}
+
 __global__ void k_neg(double *__restrict__ x, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -34,7 +34,10 @@ namespace isci {
 
 namespace {
 
-constexpr int kD1Chunk = 8;   // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
+typedef double v4d_d2 __attribute__((ext_vector_type(4)));
+
+constexpr int kD1Chunk = 8;
+constexpr int kD2MaxNorb = 128;   // two-body densities: 8 norb^4 bytes per scratch buffer   // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
 constexpr int kGramGroups = 64;   // partial slabs (set groups x piece streams) summed in order by k_d1_reduce
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
@@ -298,6 +301,156 @@ __global__ __launch_bounds__(256) void k_d1_transpose(SigmaArgs A, const double 
     }
 }
 
+// ---------------------------------------------------------------- two-body
+// Two-body density matrices (Eq. d2) for two electrons of each spin, from
+// Gram matrices of rows of the CI vector:
+//  * same spin: a+_p a+_r a_s a_q maps the string {q, s} to {p, r}, so
+//    D2ss[p][q][r][s] = eps(p, r) eps(q, s) G[{p,r}][{q,s}] with
+//    eps(a, b) = +1 for a < b, -1 for a > b (0 for a == b), and G the Gram
+//    matrix of the rows of the string's spin (each row zero beyond its
+//    length, so a pair of rows meets over their common prefix): rows of c
+//    for alpha, rows of the spin-swapped copy for beta (a beta word passes
+//    the alpha creators with four operators: no sign);
+//  * alpha-beta: a+_{p a} a+_{r b} a_{s b} a_{q a} = E^a_pq E^b_rs, so with
+//    the pair tensor M[(p, r)][(x, y)] = sgn(p - x) sgn(r - y) c({x, p},
+//    {y, r}) (zero where x == p, y == r or the determinant is outside the
+//    space), D2ab[p][q][r][s] = sum_{x, y} M[(p, r)][(x, y)] M[(q, s)][(x, y)],
+//    the Gram matrix of the rows of M.
+
+constexpr int kG2T = 64;   // Gram output tile edge
+constexpr int kG2K = 16;   // K step staged in LDS
+
+// G[i][j] = sum_k R_i[k] R_j[k] for rows R_i = src[rstart[i] + k], k <
+// rlen[i] (zero beyond), i, j < nrow, on FP64 matrix cores: workgroup =
+// one 64 x 64 tile of the upper triangle (tile pairs ti <= tj), wave w the
+// 16 rows [16 w, 16 w + 16) x 64 columns; K in steps of 16 through LDS; both
+// G[i][j] and G[j][i] written (the same sum in the same order).
+__global__ __launch_bounds__(256) void k_gram_rows(const double *__restrict__ src, const int64_t *__restrict__ rstart,
+                                                   const int *__restrict__ rlen, int nrow, int ntile,
+                                                   double *__restrict__ G, int64_t ldg)
+{
+    __shared__ double As[kG2T][kG2K + 1], Bs[kG2T][kG2K + 1];
+    __shared__ int kmax_s;
+    int ti = 0, rem = blockIdx.x;
+    while (rem >= ntile - ti) { rem -= ntile - ti; ++ti; }
+    const int tj = ti + rem;
+    const int I0 = ti * kG2T, J0 = tj * kG2T;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (tid == 0) kmax_s = 0;
+    __syncthreads();
+    if (tid < 2 * kG2T) {
+        const int r = (tid < kG2T ? I0 : J0) + (tid & (kG2T - 1));
+        if (r < nrow) atomicMax(&kmax_s, rlen[r]);
+    }
+    __syncthreads();
+    const int kmax = kmax_s;
+    v4d_d2 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_d2{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < kmax; k0 += kG2K) {
+        // 2 x 64 x 16 elements, eight per thread (16 consecutive k of a row)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;           // < 2048
+            const int side = e >> 10, r = (e >> 4) & 63, kk = e & 15;
+            const int row = (side ? J0 : I0) + r, k = k0 + kk;
+            const double v = (row < nrow && k < rlen[row]) ? src[rstart[row] + k] : 0.0;
+            if (side) Bs[r][kk] = v; else As[r][kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kG2K / 4; ++ks) {
+            const double a = As[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[16 * nt + (lane & 15)][4 * ks + (lane >> 4)],
+                                                               acc[nt], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // element g of lane l: row 4 g + l / 16, column l % 16 of the 16 x 16 tile
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int i = I0 + 16 * w + 4 * g + (lane >> 4), j = J0 + 16 * nt + (lane & 15);
+            if (i < nrow && j < nrow) {
+                G[(int64_t)i * ldg + j] = acc[nt][g];
+                G[(int64_t)j * ldg + i] = acc[nt][g];
+            }
+        }
+}
+
+// M[(p * n + r) * n * n + x * n + y] = sgn(p - x) sgn(r - y) c({x, p}, {y, r})
+// for every determinant of the space (one thread per determinant writes its
+// four role entries; M was zeroed before)
+__global__ __launch_bounds__(256) void k_d2_pair_tensor(const uint32_t *__restrict__ astr,
+                                                        const uint32_t *__restrict__ bstr,
+                                                        const int64_t *__restrict__ rowstart, int nstr_a,
+                                                        const double *__restrict__ c, int64_t dim, int n,
+                                                        double *__restrict__ M)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= dim) return;
+    // row of determinant t: binary search of the row starts
+    int lo = 0, hi = nstr_a;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rowstart[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int ia = lo, jb = (int)(t - rowstart[ia]);
+    const uint32_t as = astr[ia], bs = bstr[jb];
+    const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
+    const double v = c[t];
+    const int64_t nn = (int64_t)n * n;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra) {
+        const int x = ra ? a1 : a0, p = ra ? a0 : a1;   // spectator, active
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int y = rb ? b1 : b0, r = rb ? b0 : b1;
+            const double f = (ra ^ rb) ? -1.0 : 1.0;    // sgn(p - x) sgn(r - y)
+            M[((int64_t)p * n + r) * nn + (int64_t)x * n + y] = f * v;
+        }
+    }
+}
+
+// d2 block of one vector from a same-spin Gram matrix G (ldg = nstr):
+// D[p][q][r][s] = eps(p, r) eps(q, s) G[pidx(p, r)][pidx(q, s)]
+__global__ __launch_bounds__(256) void k_d2_expand_same(const double *__restrict__ G, int64_t ldg,
+                                                        const int *__restrict__ pidx, int n,
+                                                        double *__restrict__ D)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nn = (int64_t)n * n;
+    if (t >= nn * nn) return;
+    const int p = (int)(t / (nn * n)), q = (int)((t / nn) % n), r = (int)((t / n) % n), s = (int)(t % n);
+    double v = 0.0;
+    if (p != r && q != s) {
+        const int I = pidx[p * n + r], J = pidx[q * n + s];
+        if (I >= 0 && J >= 0) {
+            const double e = ((p < r) == (q < s)) ? 1.0 : -1.0;
+            v = e * G[(int64_t)I * ldg + J];
+        }
+    }
+    D[t] = v;
+}
+
+// alpha-beta block of one vector: D[p][q][r][s] = G[(p, r)][(q, s)]
+__global__ __launch_bounds__(256) void k_d2_expand_ab(const double *__restrict__ G, int n, double *__restrict__ D)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nn = (int64_t)n * n;
+    if (t >= nn * nn) return;
+    const int p = (int)(t / (nn * n)), q = (int)((t / nn) % n), r = (int)((t / n) % n), s = (int)(t % n);
+    D[t] = G[((int64_t)p * n + r) * nn + (int64_t)q * n + s];
+}
+
+__global__ __launch_bounds__(256) void k_d2_zero(double *__restrict__ p, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) p[t] = 0.0;
+}
+
 }  // namespace
 
 }  // namespace isci
@@ -465,6 +618,91 @@ isci_status isci_density1_noalloc(isci_handle h, int nvec, const double *c, int6
     double *part = sp;
     double *cT = sp + (size_t)kGramGroups * nvc * h->norb * h->norb;
     return density_passes(h, nvec, c, ldc, d1, nvc, part, cT, stream);
+}
+
+isci_status isci_density2(isci_handle h, int nvec, const double *c, int64_t ldc, double *d2, hipStream_t stream)
+{
+    if (!h || !c || !d2) { set_error("NULL argument"); return ISCI_E_INVALID; }
+    if (nvec < 1 || nvec > 65535) { set_error("nvec outside 1..65535"); return ISCI_E_INVALID; }
+    if (ldc < h->dim) { set_error("leading dimension < dim"); return ISCI_E_INVALID; }
+    const int n = h->norb;
+    const int64_t n4 = (int64_t)n * n * n * n;
+    {
+        const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
+        const char *d0 = (const char *)d2, *e1 = (const char *)(d2 + (int64_t)nvec * 3 * n4);
+        if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
+    }
+    if (h->na != 2 || h->nb != 2) {
+        set_error("isci_density2: two electrons of each spin only");
+        return ISCI_E_UNSUPPORTED;
+    }
+    if (n > kD2MaxNorb) {
+        set_error("isci_density2: at most 128 orbitals (the pair tensor and Gram matrix take 8 norb^4 bytes each)");
+        return ISCI_E_UNSUPPORTED;
+    }
+    const int na = h->sa.nstr, nb = h->sb.nstr, nn = n * n;
+    if (!h->d.d2G) {
+        // spin-swapped layout: rows = beta strings holding alpha prefixes
+        std::vector<int64_t> rs((size_t)na + nb + nn);
+        std::vector<int> rl(rs.size());
+        for (int i = 0; i < na; ++i) {
+            rs[i] = h->h_rowstart[i];
+            rl[i] = (int)(h->h_rowstart[i + 1] - h->h_rowstart[i]);
+        }
+        int64_t acc = 0;
+        for (int j = 0; j < nb; ++j) {
+            rs[na + j] = acc;
+            rl[na + j] = h->sa.le[h->L - h->h_blev[j]];
+            acc += rl[na + j];
+        }
+        if (acc != h->dim) { set_error("isci_density2: transposed layout size mismatch"); return ISCI_E_INVALID; }
+        for (int t = 0; t < nn; ++t) {
+            rs[na + nb + t] = (int64_t)t * nn;
+            rl[na + nb + t] = nn;
+        }
+        const int64_t gsz = std::max<int64_t>(std::max<int64_t>((int64_t)na * na, (int64_t)nb * nb), n4);
+        h->d.d2G = (double *)dev_alloc(h, sizeof(double) * (size_t)gsz);
+        h->d.d2M = (double *)dev_alloc(h, sizeof(double) * (size_t)n4);
+        h->d.d2cT = (double *)dev_alloc(h, sizeof(double) * (size_t)h->dim);
+        int64_t *drs = (int64_t *)dev_alloc(h, sizeof(int64_t) * rs.size());
+        int *drl = (int *)dev_alloc(h, sizeof(int) * rl.size());
+        if (!h->d.d2G || !h->d.d2M || !h->d.d2cT || !drs || !drl) {
+            set_error("isci_density2: out of device memory");
+            return ISCI_E_OOM;
+        }
+        ISCI_HIP(hipMemcpyAsync(drs, rs.data(), sizeof(int64_t) * rs.size(), hipMemcpyHostToDevice, stream));
+        ISCI_HIP(hipMemcpyAsync(drl, rl.data(), sizeof(int) * rl.size(), hipMemcpyHostToDevice, stream));
+        ISCI_HIP(hipStreamSynchronize(stream));   // the host tables die here
+        h->d.d2rs = drs;
+        h->d.d2rl = drl;
+    }
+    const SigmaArgs A = sigma_args(h);
+    double *G = h->d.d2G, *M = h->d.d2M;
+    auto gram = [&](const double *src, int roff, int nrow, hipStream_t st) {
+        const int nt = (nrow + kG2T - 1) / kG2T;
+        k_gram_rows<<<(unsigned)(nt * (nt + 1) / 2), 256, 0, st>>>(src, h->d.d2rs + roff, h->d.d2rl + roff, nrow, nt, G,
+                                                                   nrow);
+    };
+    const unsigned ge = (unsigned)((n4 + 255) / 256);
+    for (int v = 0; v < nvec; ++v) {
+        const double *cv = c + (int64_t)v * ldc;
+        double *dv = d2 + (int64_t)v * 3 * n4;
+        // alpha-alpha: Gram of the rows of c
+        gram(cv, 0, na, stream);
+        k_d2_expand_same<<<ge, 256, 0, stream>>>(G, na, h->d.apidx, n, dv);
+        // beta-beta: Gram of the rows of the spin-swapped copy
+        k_d1_transpose<<<transpose_tiles(h), 256, 0, stream>>>(A, cv, ldc, 1, h->dim, h->d.d2cT);
+        gram(h->d.d2cT, na, nb, stream);
+        k_d2_expand_same<<<ge, 256, 0, stream>>>(G, nb, h->d.bpidx, n, dv + 2 * n4);
+        // alpha-beta: Gram of the rows of the pair tensor
+        k_d2_zero<<<(unsigned)std::min<int64_t>(4096, (n4 + 255) / 256), 256, 0, stream>>>(M, n4);
+        k_d2_pair_tensor<<<(unsigned)((h->dim + 255) / 256), 256, 0, stream>>>(A.astr, A.bstr, A.rowstart, na, cv, h->dim,
+                                                                               n, M);
+        gram(M, na + nb, nn, stream);
+        k_d2_expand_ab<<<ge, 256, 0, stream>>>(G, n, dv + n4);
+        ISCI_HIP(hipGetLastError());
+    }
+    return ISCI_OK;
 }
 
 }  // extern "C"

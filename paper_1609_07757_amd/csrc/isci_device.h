@@ -113,10 +113,22 @@ struct EriSrc {
     const double *Lt;    // factored: [n * n][naux], L^K_pq at (p n + q) naux + K
     const double *nrm;   // factored: [n * n] bounds of the factor norms
     int n, naux;
+    const double *dist;  // distance screening: [n * n] orbital distances, or nullptr
+    double dmax;         // units whose orbitals are not all within dmax read as 0
 };
+
+// largest pairwise distance among p, q, r, s
+__device__ inline double eri_span(const EriSrc &E, int p, int q, int r, int s)
+{
+    const double *d = E.dist;
+    const int n = E.n;
+    return fmax(fmax(fmax(d[p * n + q], d[p * n + r]), fmax(d[p * n + s], d[q * n + r])),
+                fmax(d[q * n + s], d[r * n + s]));
+}
 
 __device__ inline double eri_value(const EriSrc &E, int p, int q, int r, int s)
 {
+    if (E.dist && eri_span(E, p, q, r, s) > E.dmax) return 0.0;
     if (E.eri) return geri(E.eri, E.n, p, q, r, s);
     int t;
     if (p < q) { t = p; p = q; q = t; }
@@ -137,6 +149,7 @@ __device__ inline double eri_value(const EriSrc &E, int p, int q, int r, int s)
 // sources only; the margin covers the rounding of the sums and the norms)
 __device__ inline bool eri_negligible(const EriSrc &E, int p, int q, int r, int s, double t)
 {
+    if (E.dist && eri_span(E, p, q, r, s) > E.dmax) return true;
     if (!E.nrm) return false;
     return E.nrm[p * E.n + q] * E.nrm[r * E.n + s] * (1.0 + 1e-9) <= t;
 }

@@ -116,6 +116,13 @@ struct DevTabs {
     // strings holding alpha prefixes), allocated by the first density call
     double *d1T = nullptr;          // [kD1Chunk][dim]
     double *d1part = nullptr;       // [kGramGroups][kD1Chunk][norb][norb] partial Gram sums
+    // two-body density matrices (two electrons per spin), allocated by the
+    // first isci_density2 call: a Gram matrix (max(nstr^2, norb^4)), the
+    // pair tensor (norb^4), one vector in the spin-swapped layout, and the
+    // row tables of the three Gram products
+    double *d2G = nullptr, *d2M = nullptr, *d2cT = nullptr;
+    int64_t *d2rs = nullptr;        // [nstr_a + nstr_b + norb^2] row starts: alpha rows, swapped rows, M rows
+    int *d2rl = nullptr;            // the same rows' lengths
 };
 
 struct SigmaArgs {
@@ -300,5 +307,8 @@ isci_status dots(const double *A, int64_t lda, int m, const double *B, int64_t l
 int dots_blocks(int64_t n);
 isci_status lincomb(const double *V, int64_t ldv, int m, const double *Y /*dev [k][m]*/, int k,
                     double *out, int64_t ldo, int64_t n, double beta, hipStream_t s);
+// eigen-decomposition of a small symmetric matrix A (m x m, row major):
+// eigenvalues w ascending, eigenvectors as columns of Z (Z[i * m + j])
+void sym_eigh(int m, const std::vector<double> &A, std::vector<double> &w, std::vector<double> &Z);
 
 }  // namespace isci

@@ -330,6 +330,13 @@ __global__ void k_check_finite(const double *h, const double *eri, int n, int *b
     if (!ok) atomicOr(bad, 1);
 }
 
+// distance screening of h: hm[p][q] = h[p][q], or 0 when d(p, q) > dmax
+__global__ void k_mask_h(const double *h, const double *dist, double dmax, int n, double *hm)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * n) hm[t] = dist[t] > dmax ? 0.0 : h[t];
+}
+
 // The factored form of the input check, h part: *bad = 1 if an element of
 // the lower triangle of h is not finite (the factors are checked through
 // their norms in k_factor_prep).
@@ -1220,13 +1227,49 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
     }
     // integral source; for factors, their transposed copy and norm bounds
     // live for this call only
-    EriSrc E{eri, nullptr, nullptr, norb, 0};
-    double *Lt = nullptr, *nrm = nullptr;
+    EriSrc E{eri, nullptr, nullptr, norb, 0, nullptr, 0.0};
+    double *Lt = nullptr, *nrm = nullptr, *dist = nullptr, *hm = nullptr;
     auto free_factors = [&]() {
         if (Lt) (void)hipFreeAsync(Lt, stream);
         if (nrm) (void)hipFreeAsync(nrm, stream);
-        Lt = nrm = nullptr;
+        if (dist) (void)hipFreeAsync(dist, stream);
+        if (hm) (void)hipFreeAsync(hm, stream);
+        Lt = nrm = dist = hm = nullptr;
     };
+    const bool by_dist = opts && opts->orb_dist && opts->max_dist > 0.0;
+    if (opts && opts->orb_dist && !(opts->max_dist >= 0.0)) {
+        destroy(c);
+        set_error("max_dist is NaN or negative");
+        return ISCI_E_INVALID;
+    }
+    if (by_dist) {
+        // the pair distance is the larger of d(p, q) and d(q, p), so that
+        // the mask does not depend on the order in which a unit is named
+        std::vector<double> dsym((size_t)norb * norb);
+        for (int p = 0; p < norb; ++p)
+            for (int q = 0; q < norb; ++q) {
+                const double a = opts->orb_dist[(size_t)p * norb + q], b = opts->orb_dist[(size_t)q * norb + p];
+                if (!std::isfinite(a) || a < 0.0) {
+                    destroy(c);
+                    set_error("orb_dist holds a NaN, infinite or negative distance");
+                    return ISCI_E_INVALID;
+                }
+                dsym[(size_t)p * norb + q] = std::max(a, b);
+            }
+        // distance screening: the distances on the device, and h with the
+        // elements of distant pairs set to zero (read by every builder)
+        hipError_t ed = hipMallocAsync((void **)&dist, sizeof(double) * (size_t)norb * norb, stream);
+        if (ed == hipSuccess) ed = hipMallocAsync((void **)&hm, sizeof(double) * (size_t)norb * norb, stream);
+        if (ed == hipSuccess)
+            ed = hipMemcpyAsync(dist, dsym.data(), sizeof(double) * (size_t)norb * norb, hipMemcpyHostToDevice, stream);
+        if (ed == hipSuccess) {
+            k_mask_h<<<nblk((int64_t)norb * norb, 256), 256, 0, stream>>>(h, dist, opts->max_dist, norb, hm);
+            ed = hipGetLastError();
+        }
+        if (ed == hipSuccess) ed = hipStreamSynchronize(stream);   // dsym is read
+        if (ed != hipSuccess) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return hip_fail(ed, "distance screening"); }
+        h = hm;
+    }
     {
         // refuse non-finite integrals before any list is built
         int *bad = nullptr, hbad = 0;
@@ -1241,7 +1284,7 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
                 k_factor_prep<<<nblk((int64_t)norb * norb, 256), 256, 0, stream>>>(Lfac, norb, naux, Lt, nrm, bad);
                 e3 = hipGetLastError();
             }
-            E = EriSrc{nullptr, Lt, nrm, norb, naux};
+            E = EriSrc{nullptr, Lt, nrm, norb, naux, nullptr, 0.0};
         } else if (e3 == hipSuccess) {
             k_check_finite<<<nblk(n3, 256), 256, 0, stream>>>(h, eri, norb, bad);
             e3 = hipGetLastError();
@@ -1258,6 +1301,10 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
                            : "h or eri holds a NaN or infinite value in a position that is read");
             return ISCI_E_INVALID;
         }
+    }
+    if (by_dist) {
+        E.dist = dist;
+        E.dmax = opts->max_dist;
     }
     isci_status st = build_lists(c, h, E, stream);
     if (st != ISCI_OK) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return st; }

@@ -634,3 +634,102 @@ def test_density2_single_determinant():
                     want[blk, p, p, r, r] = 1.0
                     want[blk, p, r, r, p] = -1.0
     assert np.array_equal(d2[0], want)
+
+
+# ---------------------------------------------------------------- propagation
+def test_propagate_exact_properties():
+    norb, L, tau = 7, 2, 0.0
+    h, eri = _ints("R", norb, 4)
+    S = O.Space(norb, 2, 2, L)
+    re, im = random_vectors(S.dim, 2, seed=3)
+    c = re + 1j * im
+    H = O.dense_h(S, h, eri, tau)
+    c1 = O.propagate_exact(S, h, eri, tau, re, im, 0.7, imaginary=False)
+    assert abs(np.linalg.norm(c1) - np.linalg.norm(c)) <= 1e-12 * np.linalg.norm(c)
+    e0 = np.real(np.vdot(c, H @ c))
+    assert abs(np.real(np.vdot(c1, H @ c1)) - e0) <= 1e-11 * abs(e0)
+    c2 = O.propagate_exact(S, h, eri, tau, np.real(c1), np.imag(c1), 0.5, imaginary=False)
+    c12 = O.propagate_exact(S, h, eri, tau, re, im, 1.2, imaginary=False)
+    assert np.abs(c2 - c12).max() <= 1e-12 * np.abs(c12).max()
+    # short-time difference quotient against the oracle sigma
+    d = 1e-6
+    cd = O.propagate_exact(S, h, eri, tau, re, im, d, imaginary=False)
+    hc = O.sigma(S, h, eri, tau, np.stack([re, im]))
+    want = -1j * (hc[0] + 1j * hc[1])
+    assert np.abs((cd - c) / d - want).max() <= 1e-4 * np.abs(want).max()
+    # imaginary time: difference quotient of the normalised flow and the
+    # long-time limit (lowest eigenvector, up to sign)
+    u = re / np.linalg.norm(re)
+    ud = O.propagate_exact(S, h, eri, tau, u, None, d)
+    hu = O.sigma(S, h, eri, tau, u[None])[0]
+    want = -(hu - (u @ hu) * u)
+    assert np.abs((ud - u) / d - want).max() <= 1e-4 * np.abs(want).max()
+    uinf = O.propagate_exact(S, h, eri, tau, u, None, 400.0)
+    w = np.linalg.eigvalsh(H)
+    assert abs(uinf @ (H @ uinf) - w[0]) <= 1e-10
+
+
+def test_propagate_exact_coefficient_screening():
+    """Screened stepping: a threshold below every coefficient changes
+    nothing (the steps compose to the unscreened flow); one screened step
+    is the unscreened step with its small entries zeroed, checked element by
+    element; the screened imaginary-time vector stays above the lowest
+    eigenvalue (variational) and approaches it as the threshold falls."""
+    norb, L, tau = 8, 2, 0.0
+    h, eri = _ints("R", norb, 6)
+    S = O.Space(norb, 2, 2, L)
+    re, im = random_vectors(S.dim, 2, seed=5)
+    a = O.propagate_exact(S, h, eri, tau, re, im, 1.0, imaginary=False, nsteps=5, coef_tau=1e-300)
+    b = O.propagate_exact(S, h, eri, tau, re, im, 1.0, imaginary=False)
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    u = np.zeros(S.dim)
+    u[0] = 1.0
+    one = O.propagate_exact(S, h, eri, tau, u, None, 0.4)
+    t1 = float(np.median(np.abs(one)))
+    scr = O.propagate_exact(S, h, eri, tau, u, None, 0.4, nsteps=1, coef_tau=t1)
+    for i in range(S.dim):
+        assert scr[i] == (0.0 if abs(one[i]) <= t1 else one[i])
+    assert 0 < int(np.sum(scr == 0.0)) < S.dim
+    H = O.dense_h(S, h, eri, tau)
+    w, V = np.linalg.eigh(H)
+    w0, a0 = w[0], np.sort(np.abs(V[:, 0]))
+    gaps = []
+    # thresholds that cut about 40 %, 20 % and 5 % of the ground state
+    for thr in (a0[int(0.4 * S.dim)], a0[int(0.2 * S.dim)], a0[int(0.05 * S.dim)]):
+        c = O.propagate_exact(S, h, eri, tau, u, None, 200.0, nsteps=100, coef_tau=thr)
+        e = (c @ (H @ c)) / (c @ c)
+        assert e >= w0 - 1e-12
+        gaps.append(e - w0)
+    assert gaps[0] > gaps[1] > gaps[2]
+
+
+# ---------------------------------------------------------------- distance screening
+def test_mask_by_distance_brute_force_and_limits():
+    norb = 5
+    h, eri = _ints("R", norb, 2)
+    x = np.array([0.0, 1.0, 2.5, 4.0, 7.0])
+    dist = np.abs(x[:, None] - x[None, :])
+    hm, em = O.mask_by_distance(h, eri, dist, 3.0)
+    for p in range(norb):
+        for q in range(norb):
+            assert hm[p, q] == (h[p, q] if dist[p, q] <= 3.0 else 0.0)
+            for r in range(norb):
+                for s in range(norb):
+                    orbs = (p, q, r, s)
+                    ok = all(dist[a, b] <= 3.0 for a in orbs for b in orbs)
+                    assert em[p, q, r, s] == (eri[p, q, r, s] if ok else 0.0)
+    h2, e2 = O.mask_by_distance(h, eri, dist, 100.0)
+    assert np.array_equal(h2, h) and np.array_equal(e2, eri)
+    h3, e3 = O.mask_by_distance(h, eri, dist, 0.5)
+    assert np.array_equal(h3, np.diag(np.diag(h)))
+    keep = np.zeros_like(eri)
+    for p in range(norb):
+        keep[p, p, p, p] = eri[p, p, p, p]
+    assert np.array_equal(e3, keep)
+    # a non-symmetric matrix reads as the pair maximum
+    rng = np.random.default_rng(1)
+    da = dist * rng.uniform(0.5, 1.5, dist.shape)
+    ha, ea = O.mask_by_distance(h, eri, da, 3.0)
+    hb, eb = O.mask_by_distance(h, eri, np.maximum(da, da.T), 3.0)
+    assert np.array_equal(ha, hb) and np.array_equal(ea, eb)
+    assert np.array_equal(ea, ea.transpose(1, 0, 2, 3)) and np.array_equal(ea, ea.transpose(2, 3, 0, 1))
