@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # revision of each kernel's code: stored HBM traffic (profiles/sigma_traffic.json)
 # is used only when it was counted for the same revision
-KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs"}
+KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs, 16-byte operand loads"}
 HBM_PEAK_GBS = 8000.0
 METRIC = "σ-vectors/s + screened terms/s (% roofline); p50/p99 Davidson solve latency"
 
@@ -38,10 +38,12 @@ def parse():
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
-    ap.add_argument("--ab", choices=["plain", "pipe"], default="plain",
+    ap.add_argument("--ab", choices=["plain", "pipe", "wide"], default="wide",
                     help="kernel of the alpha-beta block-sparse product")
     ap.add_argument("--onebody", choices=["transposed", "single"], default="transposed",
                     help="one-body kernel on the rows / columns that hold every pair")
+    ap.add_argument("--ob-place", choices=["auto", "separate", "tiles"], default="auto",
+                    help="one-body units in their own kernels or inside the alpha-beta tiles (default: by chunk growth)")
     ap.add_argument("--onebody-stream", choices=["side", "inline"], default="side",
                     help="one-body kernels on the side stream beside the alpha-beta products, or in line")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
@@ -95,7 +97,8 @@ def main():
     dev = torch.device("cuda:0")
     h, eri = W.integrals()
     hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb,
-                          W.nalpha, W.nbeta, W.level, tau)
+                          W.nalpha, W.nbeta, W.level, tau,
+                          onebody={"auto": isci.OB_AUTO, "separate": isci.OB_SEPARATE, "tiles": isci.OB_TILES}[a.ob_place])
     variant = {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
                "mfma": isci.SIGMA_MFMA}[a.kernel]
     isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
@@ -236,7 +239,8 @@ def main():
 
 def set_ab_product(isci, hd, name):
     """Kernel of the alpha-beta product: plain ping-pong or software pipeline."""
-    isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, isci.AB_PIPE if name == "pipe" else isci.AB_PLAIN)
+    isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, {"plain": isci.AB_PLAIN, "pipe": isci.AB_PIPE,
+                                                   "wide": isci.AB_WIDE}[name])
 
 
 def density1_timing(isci, torch, hd, c, stream, steps):

@@ -93,7 +93,11 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 // (more waves in flight per tile); the parts are summed through LDS in a
 // fixed order.
 // (at most 80 VGPRs: six waves per SIMD, three 8-wave workgroups per CU)
-template <int CW, int KS>
+// WIDE: each lane fetches two adjacent columns with one 16-byte load (two
+// loads per chunk instead of four), so the four 16-column N tiles of a
+// wave are the even and odd columns of its two 32-column halves; S is
+// stored two columns per lane in the same order.
+template <int CW, int KS, bool WIDE>
 __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6))) void k_ab_gemm(SigmaArgs A)
 {
     __shared__ double red[KS > 1 ? KS - 1 : 1][CW][16][64];
@@ -135,11 +139,18 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
         for (int u = 0; u < 2; ++u) {
             const int eu = min(e + u, e1 - 1);
             const int2 tx = A.abx_chunk[eu];   // (T offset of the chunk's row 0, row width)
-            const double *src = A.abx_T + (size_t)tx.x + (size_t)k * tx.y + c0 + n;
             const double av = A.chunk_val[(size_t)eu * 64 + lane];
             a[u] = e + u < e1 ? av : 0.0;
+            if (WIDE) {
+                // columns c0 + 32 h + 2 n + j -> N tile 2 h + j
+                const double2 *src = (const double2 *)(A.abx_T + (size_t)tx.x + (size_t)k * tx.y + c0 + 2 * n);
+                const double2 lo = src[0], hi = src[16];
+                b[u][0] = lo.x; b[u][1] = lo.y; b[u][2] = hi.x; b[u][3] = hi.y;
+            } else {
+                const double *src = A.abx_T + (size_t)tx.x + (size_t)k * tx.y + c0 + n;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[u][q] = src[16 * q];
+                for (int q = 0; q < 4; ++q) b[u][q] = src[16 * q];
+            }
         }
     };
     auto mma2 = [&](const double *a, const double (*b)[4]) {
@@ -174,11 +185,20 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
     }
     if (!active) return;
     // element gg of lane l: row 4 gg + l / 16 (alpha active slot gg, beta active slot l / 16), column l % 16
-    double *Sb = A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + n;
+    if (WIDE) {
+        double2 *Sb = (double2 *)(A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + 2 * n);
 #pragma unroll
-    for (int gg = 0; gg < 4; ++gg)
+        for (int gg = 0; gg < 4; ++gg) {
+            Sb[(size_t)gg * 2 * swidth] = double2{acc[0][gg], acc[1][gg]};
+            Sb[(size_t)gg * 2 * swidth + 16] = double2{acc[2][gg], acc[3][gg]};
+        }
+    } else {
+        double *Sb = A.abx_S + (size_t)A.abx_soff[g] + (size_t)k * swidth + c0 + n;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Sb[(size_t)gg * 4 * swidth + 16 * q] = acc[q][gg];
+        for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Sb[(size_t)gg * 4 * swidth + 16 * q] = acc[q][gg];
+    }
 }
 
 // The product of k_ab_gemm with an explicit two-stage software pipeline:
@@ -347,10 +367,13 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     }
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
-        if (cx->ab_pipe)
-            k_ab_pipe<kAbCW, kAbSplit, 2><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
+        const dim3 grid((unsigned)(8 * cx->abx_xmax)), block(64 * kAbCW * kAbSplit);
+        if (cx->ab_kernel == ISCI_AB_PIPE)
+            k_ab_pipe<kAbCW, kAbSplit, 2><<<grid, block, 0, st>>>(A);
+        else if (cx->ab_kernel == ISCI_AB_WIDE)
+            k_ab_gemm<kAbCW, kAbSplit, true><<<grid, block, 0, st>>>(A);
         else
-            k_ab_gemm<kAbCW, kAbSplit><<<(unsigned)(8 * cx->abx_xmax), 64 * kAbCW * kAbSplit, 0, st>>>(A);
+            k_ab_gemm<kAbCW, kAbSplit, false><<<grid, block, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
     ISCI_HIP(hipGetLastError());

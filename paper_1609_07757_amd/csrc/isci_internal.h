@@ -224,7 +224,7 @@ struct isci_ctx {
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
     int abx_xmax = 0;        // longest XCD tile run
-    bool ab_pipe = false;    // ISCI_OPT_AB_PRODUCT: k_ab_pipe (else k_ab_gemm)
+    int ab_kernel = ISCI_AB_WIDE;    // ISCI_OPT_AB_PRODUCT: wide-load k_ab_gemm (default), k_ab_gemm or k_ab_pipe
     int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
     bool ob_side = true;     // ISCI_OPT_ONEBODY_STREAM: one-body kernels on the side stream (else in line)
     int64_t nkept_h = 0, nkept_ab = 0;

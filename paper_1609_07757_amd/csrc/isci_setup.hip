@@ -1410,8 +1410,11 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         c->sigma_variant = value;
         return ISCI_OK;
     case ISCI_OPT_AB_PRODUCT:
-        if (value != ISCI_AB_PLAIN && value != ISCI_AB_PIPE) { set_error("bad alpha-beta product kernel"); return ISCI_E_INVALID; }
-        c->ab_pipe = value == ISCI_AB_PIPE;
+        if (value != ISCI_AB_PLAIN && value != ISCI_AB_PIPE && value != ISCI_AB_WIDE) {
+            set_error("bad alpha-beta product kernel");
+            return ISCI_E_INVALID;
+        }
+        c->ab_kernel = value;
         return ISCI_OK;
     case ISCI_OPT_ONEBODY_KERNEL:
         if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED) { set_error("bad one-body kernel"); return ISCI_E_INVALID; }

@@ -261,7 +261,7 @@ def test_ab_product_kernels(wl, nsamp, nvec):
     tg = None if nsamp is None else sample_targets(S.rowstart(), S.dim, nsamp, seed=6)
     ref = O.sigma(S, h, eri, W.tau, c, targets=tg)
     outs = []
-    for val in (isci.AB_PLAIN, isci.AB_PIPE):
+    for val in (isci.AB_PLAIN, isci.AB_PIPE, isci.AB_WIDE):
         isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, val)
         got = gpu_sigma(hd, c)
         outs.append(got)
@@ -270,7 +270,7 @@ def test_ab_product_kernels(wl, nsamp, nvec):
         else:
             ok, err = sampled_ok(got, tg, ref, TOL)
             assert ok, (val, err)
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
 @pytest.mark.parametrize("recipe,norb,L,tau,nvec,nsamp", [("B", 12, 2, 1e-12, 3, None), ("B", 16, 4, 0.0, 5, None),
