@@ -506,11 +506,15 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
  *   orbitals, for tuning): ISCI_ONEBODY_TRANSPOSED (default) runs the alpha
  *   class, where every beta column holds every alpha pair (full CI), as the
  *   beta class of the transposed block (contiguous rows);
- *   ISCI_ONEBODY_SINGLE takes two columns per workgroup there.  Same sigma
- *   up to rounding order. */
+ *   ISCI_ONEBODY_SINGLE takes two columns per workgroup there;
+ *   ISCI_ONEBODY_SPECTATOR runs the whole alpha class in the spectator form
+ *   used above 80 orbitals (U[a][x][j] = sum_q h_aq T_j[q][x], the rows
+ *   {q, x} read directly, no transposes).  Same sigma up to rounding
+ *   order. */
 #define ISCI_OPT_ONEBODY_KERNEL 5
 #define ISCI_ONEBODY_SINGLE 1
 #define ISCI_ONEBODY_TRANSPOSED 2
+#define ISCI_ONEBODY_SPECTATOR 3
 /*   ISCI_OPT_ONEBODY_STREAM (matrix-core path with separate one-body
  *   kernels, for tuning): ISCI_ONEBODY_SIDE (default) runs the one-body
  *   classes on the handle's side stream beside the alpha-beta unfolds and

@@ -526,6 +526,8 @@ template <int NT>
 static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
                                    double *s, int64_t lds, hipStream_t st)
 {
+    // the spectator form (rows {q, x} as B operands, no transposes) at any size
+    if (cx->ob_kernel == ISCI_ONEBODY_SPECTATOR) return launch_onebody_alpha_large(cx, nv, c, ldc, s, lds, st);
     if (cx->ob_kernel == ISCI_ONEBODY_TRANSPOSED && cx->d.obT_c && cx->d.obT_s &&
         cx->sb.le[cx->L >= 2 ? cx->L - 2 : 0] == cx->sb.nstr && cx->sa.nstr == cx->sb.nstr) {
         // every beta column holds every alpha pair (full CI with two
@@ -590,8 +592,9 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
 template <int NT>
 __global__ __launch_bounds__(256) void k_ob_alpha_spec(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                            double *__restrict__ sg, int64_t lds,
-                                                           const double *__restrict__ hs, int up, int jlim_occ,
-                                                           int jlim_virt, int x0)
+                                                           const double *__restrict__ hs,
+                                                           const unsigned long long *__restrict__ hkm, int up,
+                                                           int jlim_occ, int jlim_virt, int x0)
 {
     constexpr int NP = 16 * NT, NG = (NT + 3) / 4;
     const int x = x0 + blockIdx.x, v = blockIdx.z / NG, grp = blockIdx.z % NG;
@@ -624,6 +627,9 @@ __global__ __launch_bounds__(256) void k_ob_alpha_spec(SigmaArgs A, const double
         for (int kk = 0; kk < 16; ++kk)
             if (16 * r + kk < NP / 4 && ((sm >> (4 * kk)) & 0xfull)) km |= 1ull << (16 * r + kk);
     }
+    // and whose h operands are not all screened away for this tile's
+    // targets (a skipped step would only add zero products)
+    km &= hkm[mt];
     const int n = lane & 15, kq = lane >> 4;
     const double *cv = c + (int64_t)v * ldc;
     auto next_ks = [&]() {
@@ -802,14 +808,15 @@ static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv,
     const unsigned ng = (NT + 3) / 4;
     const dim3 go((unsigned)nocc, (unsigned)((jlim_occ + 63) / 64), (unsigned)nv * ng);
     const dim3 gv((unsigned)(cx->norb - nocc), (unsigned)((jlim_virt + 63) / 64), (unsigned)nv * ng);
+    const unsigned long long *hkm = cx->d.hkmask;
     for (int up = 1; up >= 0; --up) {
-        k_ob_alpha_spec<NT><<<go, 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, 0);
+        k_ob_alpha_spec<NT><<<go, 256, 0, st>>>(A, c, ldc, s, lds, hs, hkm, up, jlim_occ, jlim_virt, 0);
         if (gv.x > 0 && gv.y > 0) {
             if (jlim_virt <= kObNarrow)
                 k_ob_alpha_narrow<<<dim3(gv.x, (unsigned)nv), 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_virt,
                                                                            nocc);
             else
-                k_ob_alpha_spec<NT><<<gv, 256, 0, st>>>(A, c, ldc, s, lds, hs, up, jlim_occ, jlim_virt, nocc);
+                k_ob_alpha_spec<NT><<<gv, 256, 0, st>>>(A, c, ldc, s, lds, hs, hkm, up, jlim_occ, jlim_virt, nocc);
         }
     }
     if (jref > jlim_occ && cx->norb >= 2)
@@ -823,7 +830,8 @@ static void launch_ob_alpha_spec(const isci_ctx *cx, const SigmaArgs &A, int nv,
 isci_status launch_onebody_alpha_large(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
                                        int64_t lds, hipStream_t st)
 {
-    if (!(cx->d.hscreen && cx->na == 2 && cx->nb == 2 && cx->d.arow_base && cx->d.arow_len) || cx->norb > 256) {
+    if (!(cx->d.hscreen && cx->d.hkmask && cx->na == 2 && cx->nb == 2 && cx->d.arow_base && cx->d.arow_len) ||
+        cx->norb > 256) {
         set_error("alpha one-body spectator path: needs two electrons per spin and at most 256 orbitals");
         return ISCI_E_UNSUPPORTED;
     }

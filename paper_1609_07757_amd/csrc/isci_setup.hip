@@ -444,6 +444,23 @@ __global__ void k_hscreen(const double *h, int n, double tau, double *hs)
     hs[t] = fabs(v) > tau ? v : 0.0;
 }
 
+// K-step masks of the screened h for the spectator-form one-body kernel:
+// one thread per 16-orbital target tile mt (n <= 256, so at most 16 tiles
+// and 64 steps of four orbitals)
+__global__ void k_hkmask(const double *hs, int n, unsigned long long *mask)
+{
+    const int mt = threadIdx.x;
+    if (mt >= 16) return;
+    unsigned long long m = 0;
+    for (int ks = 0; 4 * ks < n; ++ks) {
+        bool any = false;
+        for (int q = 4 * ks; q < 4 * ks + 4 && q < n; ++q)
+            for (int a = 16 * mt; a < 16 * mt + 16 && a < n; ++a) any |= hs[(size_t)q * n + a] != 0.0;
+        if (any) m |= 1ull << ks;
+    }
+    mask[mt] = m;
+}
+
 // hs (n x n) into the top-left corner of a zeroed P x P array
 __global__ void k_hpad(const double *hs, int n, int P, double *hp)
 {
@@ -921,6 +938,12 @@ static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
     if (!c->d.hscreen) { set_error("device allocation failed (h)"); return ISCI_E_OOM; }
     k_hscreen<<<(n * n + 255) / 256, 256, 0, s>>>(h, n, c->tau, c->d.hscreen);
     ISCI_HIP(hipGetLastError());
+    if (n <= 256) {
+        c->d.hkmask = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * 16);
+        if (!c->d.hkmask) { set_error("device allocation failed (h masks)"); return ISCI_E_OOM; }
+        k_hkmask<<<1, 64, 0, s>>>(c->d.hscreen, n, c->d.hkmask);
+        ISCI_HIP(hipGetLastError());
+    }
     if (n <= kObMaxNorb) {
         // zero-padded copy: the matrix-core one-body kernels load their h
         // operands with no bounds conditions
@@ -1417,7 +1440,10 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         c->ab_kernel = value;
         return ISCI_OK;
     case ISCI_OPT_ONEBODY_KERNEL:
-        if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED) { set_error("bad one-body kernel"); return ISCI_E_INVALID; }
+        if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED && value != ISCI_ONEBODY_SPECTATOR) {
+            set_error("bad one-body kernel");
+            return ISCI_E_INVALID;
+        }
         c->ob_kernel = value;
         return ISCI_OK;
     case ISCI_OPT_ONEBODY_STREAM:

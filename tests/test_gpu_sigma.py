@@ -207,6 +207,23 @@ def test_sigma_large_orbitals_sampled(variant, norb, L):
     assert ok, err
 
 
+@pytest.mark.parametrize("norb,L,nvec", [(97, 2, 2), (199, 3, 1)])
+def test_spectator_kernel_edges(norb, L, nvec):
+    """Spectator-form one-body classes at 7 and 13 target tiles (CISD 97
+    and CISDT 199 orbitals, several vectors at 97): the oracle on sampled
+    targets, row ends included."""
+    tau = 1e-12
+    h, eri = recipe_a(norb, seed=6)
+    hd = create(h, eri, norb, 2, 2, L, tau, 5)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, nvec, seed=19)
+    got = gpu_sigma(hd, c)
+    tg = sample_targets(S.rowstart(), S.dim, 300, seed=13)
+    ref = O.sigma(S, h, eri, tau, c, targets=tg)
+    ok, err = sampled_ok(got, tg, ref, TOL)
+    assert ok, err
+
+
 @pytest.mark.parametrize("k,tau", [(0, 0.0), (1, 1e-14), (2, 1e-10)])
 def test_sigma_tau_sweep_cisdt_n30(k, tau):
     from isci_inputs import workload
@@ -281,7 +298,8 @@ def test_onebody_kernels(recipe, norb, L, tau, nvec, nsamp):
     the alpha-beta tiles), 12 to 77 orbitals (one to five 16-orbital
     tiles): two-column alpha kernel, and the alpha class through the
     transposed block where every column holds every pair (full CI, 16 and 48
-    orbitals), on the side stream and in line; each against the oracle."""
+    orbitals), on the side stream and in line, and the spectator form at
+    every size; each against the oracle."""
     import paper_1609_07757_amd as isci
     h, eri = _ints(recipe, norb, 7)
     hd = create(h, eri, norb, 2, 2, L, tau, 5)
@@ -290,7 +308,7 @@ def test_onebody_kernels(recipe, norb, L, tau, nvec, nsamp):
     tg = None if nsamp is None else sample_targets(S.rowstart(), S.dim, nsamp, seed=7)
     ref = O.sigma(S, h, eri, tau, c, targets=tg)
     for kern, stream in ((isci.ONEBODY_SINGLE, isci.ONEBODY_SIDE), (isci.ONEBODY_TRANSPOSED, isci.ONEBODY_SIDE),
-                         (isci.ONEBODY_TRANSPOSED, isci.ONEBODY_INLINE)):
+                         (isci.ONEBODY_TRANSPOSED, isci.ONEBODY_INLINE), (isci.ONEBODY_SPECTATOR, isci.ONEBODY_SIDE)):
         isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, kern)
         isci.isci_set_option(hd, isci.OPT_ONEBODY_STREAM, stream)
         got = gpu_sigma(hd, c)
