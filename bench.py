@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fci_n48")
+    ap.add_argument("--rows-factored", default="cisdt_n60", help="rows mode: workload of the factored and distance rows")
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
@@ -50,7 +51,7 @@ def parse():
     ap.add_argument("--skip-davidson", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--skip-density", action="store_true", help="do not time the density matrices")
-    ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal", "peaks", "sweep"], default="sigma",
+    ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal", "peaks", "sweep", "rows"], default="sigma",
                     help="sigma: headline line; batched: 64 uneven Davidson solves, engine vs plain loop; "
                          "served: Poisson request stream with continuous batching; copycal: plain device "
                          "copies of known size (calibrates the HBM byte counters); sweep: the CISDT "
@@ -83,6 +84,8 @@ def main():
         return bench_copycal(a)
     if a.mode == "peaks":
         return bench_peaks(a)
+    if a.mode == "rows":
+        return bench_rows(a)
     if a.mode == "sweep":
         return bench_sweep(a)
     import numpy as np
@@ -528,6 +531,133 @@ def bench_sweep(a):
            "paper_context": {"cisd": 1.24, "cisdt": 1.48, "cisdtq": 1.98,
                              "note": "the paper's flop-count exponents for beryllium in a finite-element basis; "
                                      "context only, not a target"}}
+    print(json.dumps(out), flush=True)
+
+
+def _events_ms(torch, stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_rows(a):
+    """The rows that extend the sigma path, each timed on the device and set
+    against its bound:
+      * two-body densities (isci_density2) on the workload's vectors: HBM,
+        the three spin blocks written once and c read once, 8 (3 norb^4 +
+        dim) B per vector;
+      * imaginary-time SIAL propagation (isci_propagate): time per step and
+        the share its sigma calls take at the one-vector sigma rate;
+      * handles from factors against dense handles: creation time, the
+        bytes handed over, and the sigma of both (bit for bit);
+      * distance screening: kept units and sigma time against the radius."""
+    import numpy as np
+    import torch
+    import paper_1609_07757_amd as isci
+    from isci_inputs import random_vectors, workload
+    from isci_inputs.recipes import factors_a, orbital_centres
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"metric": "extension rows: two-body densities, SIAL propagation, handles from factors, distance screening",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic (recipe A, seeded)"}
+    # two-body densities
+    W = workload(a.workload)
+    h, eri = W.integrals()
+    hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb, 2, 2, W.level, W.tau)
+    nv = 4
+    c = torch.from_numpy(random_vectors(hd.dim, nv, seed=21)).to(dev)
+    d2 = isci.isci_density2(hd, c)
+    ms = _events_ms(torch, stream, lambda: isci.isci_density2(hd, c, d2), 5)
+    n4 = float(W.norb) ** 4
+    nb = nv * 8.0 * (3 * n4 + hd.dim)
+    nrm = (c * c).sum(dim=1)
+    tr_ab = [float(torch.einsum("pprr->", d2[v, 1]) / nrm[v]) for v in range(nv)]
+
+    def gram_flops(lengths):
+        # 2 flops per product of two rows' common prefix, row pairs i <= j:
+        # sum over i <= j of min(len_i, len_j), from the lengths sorted downwards
+        ls = np.sort(np.asarray(lengths, dtype=np.float64))[::-1]
+        return 2.0 * float(np.sum(ls * (np.arange(len(ls)) + 1.0)))
+    rs = isci.isci_rowstart(hd)
+    _, lev_a = isci.isci_strings(hd, 0)
+    _, lev_b = isci.isci_strings(hd, 1)
+    le_a = np.array([np.sum(lev_a <= k) for k in range(W.level + 1)])
+    len_b = le_a[np.clip(W.level - lev_b, 0, W.level)]
+    nn = W.norb * W.norb
+    fl = nv * (gram_flops(np.diff(rs)) + gram_flops(len_b) + 2.0 * nn * nn * (nn + 1) / 2.0)
+    out["density2"] = {"workload": W.name, "vectors": nv, "ms_per_call": ms, "pairs_ab_from_traces": [min(tr_ab), max(tr_ab)],
+                       "roofline": {"bound": "mfma", "kernel": "k_gram_rows (whole call)",
+                                    "achieved": fl / (ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                                    "frac": fl / (ms * 1e-3) / 1e12 / 78.6, "algorithmic_flops": fl},
+                       "hbm": {"algorithmic_bytes": nb, "achieved_GBps": nb / (ms * 1e-3) / 1e9}}
+    del d2
+    # SIAL propagation (imaginary time from the reference determinant)
+    c1 = torch.zeros(hd.dim, dtype=torch.float64, device=dev)
+    c1[0] = 1.0
+    s1 = torch.empty_like(c1)
+    sig_ms = _events_ms(torch, stream, lambda: isci.isci_sigma(hd, c1, s1, stream=stream), 10)
+    steps = 10
+    isci.isci_propagate(hd, c1.clone(), 0.5, 1, krylov=16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = isci.isci_propagate(hd, c1, 0.5, steps, krylov=16)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["propagation"] = {"workload": W.name, "dt": 0.5, "steps": steps, "krylov_max": 16, "ms_per_step": wall * 1e3 / steps,
+                          "sigma_calls": info["sigma_calls"], "krylov_last": info["krylov_last"], "energy": info["energy"],
+                          "sigma_ms_one_vector": sig_ms,
+                          "sigma_share": info["sigma_calls"] * sig_ms / (wall * 1e3)}
+    del hd
+    # handles from factors against dense handles
+    Wf = workload(a.rows_factored)
+    hf_np, L_np = factors_a(Wf.norb, Wf.box_len, Wf.n_aux, Wf.seed)
+    ht = torch.from_numpy(hf_np).to(dev)
+    Lt = torch.from_numpy(np.ascontiguousarray(L_np)).to(dev)
+    et = torch.from_numpy(Wf.integrals()[1]).to(dev)
+    torch.cuda.synchronize()
+
+    def timed_create(fn):
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return x, best
+    hdn, t_dense = timed_create(lambda: isci.isci_create(ht, et, Wf.norb, 2, 2, Wf.level, Wf.tau))
+    hfa, t_fact = timed_create(lambda: isci.isci_create_factored(ht, Lt, Wf.norb, 2, 2, Wf.level, Wf.tau))
+    cv = torch.from_numpy(random_vectors(hdn.dim, 2, seed=3)).to(dev)
+    sd, sf = isci.isci_sigma(hdn, cv), isci.isci_sigma(hfa, cv)
+    # the dense tensor here is the recipe's own assembly (a matrix product),
+    # not the factors' ascending-K sums, so the two agree to rounding only
+    rel = float((sd - sf).abs().max() / sd.abs().max())
+    out["factored"] = {"workload": Wf.name, "naux": Wf.n_aux, "create_dense_s": t_dense, "create_factored_s": t_fact,
+                       "bytes_dense_eri": 8.0 * Wf.norb ** 4, "bytes_factors": 8.0 * Wf.n_aux * Wf.norb ** 2,
+                       "sigma_max_rel_diff": rel}
+    del hdn, hfa, et
+    # distance screening
+    x = orbital_centres(Wf.norb, Wf.box_len, Wf.n_aux, Wf.seed)
+    dist = np.abs(x[:, None] - x[None, :])
+    rows = []
+    for rmax in (0.0, 6.0, 4.0, 3.0):
+        hx = isci.isci_create(ht, torch.from_numpy(Wf.integrals()[1]).to(dev), Wf.norb, 2, 2, Wf.level, Wf.tau,
+                              orb_dist=dist if rmax > 0 else None, max_dist=rmax)
+        cx = torch.from_numpy(random_vectors(hx.dim, 8, seed=5)).to(dev)
+        sx = torch.empty_like(cx)
+        ms = _events_ms(torch, stream, lambda: isci.isci_sigma(hx, cx, sx, stream=stream), 10)
+        st = isci.isci_get_stats(hx)
+        rows.append({"max_dist": rmax if rmax > 0 else None, "kept_units": int(np.sum(st["kept"])),
+                     "terms_per_vector": int(np.sum(st["terms"])), "ms_per_step_8_vectors": ms})
+        del hx
+    out["distance"] = {"workload": Wf.name, "points": rows}
     print(json.dumps(out), flush=True)
 
 

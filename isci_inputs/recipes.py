@@ -36,6 +36,12 @@ def _grid(norb: int, box: float, naux: int, seed: int):
     return x, eps, X
 
 
+def orbital_centres(norb: int, box: float, naux: int, seed: int) -> np.ndarray:
+    """Centres x_p of the recipe's local orbitals (the same draw as the
+    integrals of that seed), for distance matrices |x_p - x_q|."""
+    return _grid(norb, box, naux, seed)[0]
+
+
 def _h_of(x, eps):
     h = -0.5 * np.exp(-np.abs(x[:, None] - x[None, :]))
     h[np.diag_indices_from(h)] += eps

@@ -347,17 +347,37 @@ __global__ __launch_bounds__(256) void k_gram_rows(const double *__restrict__ sr
     v4d_d2 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_d2{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < kmax; k0 += kG2K) {
-        // 2 x 64 x 16 elements, eight per thread (16 consecutive k of a row)
+    // 2 x 64 x 16 elements per K step, eight per thread (16 consecutive k
+    // of a row); the next step's elements are loaded into registers while
+    // the current step's products run
+    long long rs8[8];
+    int rl8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u;           // < 2048
+        const int side = e >> 10, r = (e >> 4) & 63;
+        const int row = (side ? J0 : I0) + r;
+        rs8[u] = row < nrow ? rstart[row] : 0;
+        rl8[u] = row < nrow ? rlen[row] : 0;
+    }
+    double pre[8];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = tid + 256 * u;           // < 2048
+            const int k = k0 + ((tid + 256 * u) & 15);
+            pre[u] = k < rl8[u] ? src[rs8[u] + k] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < kmax; k0 += kG2K) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
             const int side = e >> 10, r = (e >> 4) & 63, kk = e & 15;
-            const int row = (side ? J0 : I0) + r, k = k0 + kk;
-            const double v = (row < nrow && k < rlen[row]) ? src[rstart[row] + k] : 0.0;
-            if (side) Bs[r][kk] = v; else As[r][kk] = v;
+            if (side) Bs[r][kk] = pre[u]; else As[r][kk] = pre[u];
         }
         __syncthreads();
+        if (k0 + kG2K < kmax) fetch(k0 + kG2K);
 #pragma unroll
         for (int ks = 0; ks < kG2K / 4; ++ks) {
             const double a = As[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
