@@ -49,6 +49,7 @@ def parse():
                     help="one-body kernels on the side stream beside the alpha-beta products, or in line")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-davidson", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="batched mode: choose each handle's kernel options with tune.py")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--skip-density", action="store_true", help="do not time the density matrices")
     ap.add_argument("--mode", choices=["sigma", "batched", "served", "copycal", "peaks", "sweep", "rows"], default="sigma",
@@ -371,6 +372,17 @@ def bench_batched(a):
         handles.append(hd)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
+    t_tune, tuned = 0.0, {}
+    if a.tune:
+        # kernel options per handle from the tuner (timed on each handle,
+        # cached per shape); outside the timed regions
+        from paper_1609_07757_amd import tune
+        t0 = time.perf_counter()
+        for W, hd in zip(insts, handles):
+            cfg, _ = tune.tune_handle(hd, nvec=min(W.nroots + 2, 8))
+            tuned[str(cfg)] = tuned.get(str(cfg), 0) + 1
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
     # plain: one solve after the other
     t0 = time.perf_counter()
     plain_e, plain_sig = [], 0
@@ -405,7 +417,7 @@ def bench_batched(a):
            "plain_sigma_vectors_per_s": plain_sig / t_plain, "speedup_vs_plain": (batch_sig / t_batch) / (plain_sig / t_plain),
            "plain_s": t_plain, "batched_s": t_batch, "engine_steps": steps, "create_s": t_create,
            "max_abs_energy_diff": dE, "sigma_vectors_plain": plain_sig, "sigma_vectors_batched": batch_sig,
-           "max_iterations": max(iters)}
+           "max_iterations": max(iters), "tuned": bool(a.tune), "tune_s": t_tune, "tuned_configs": tuned}
     print(json.dumps(out), flush=True)
 
 

@@ -265,9 +265,11 @@ class GpuExecutor:
     ones (a size-based scheduling policy; each solve's arithmetic is the
     same in either class).  fast_dim = 0 puts every solve in one engine."""
 
-    def __init__(self, davidson_opts=None, stream=None, fast_dim: int = 1_000_000, fast_share: float = 0.75):
+    def __init__(self, davidson_opts=None, stream=None, fast_dim: int = 1_000_000, fast_share: float = 0.75,
+                 tune: bool = False):
         import paper_1609_07757_amd as isci
         self.isci = isci
+        self.tune = bool(tune)   # pick each handle's kernel options with tune.tune_handle (cached per shape)
         self.engs = [isci.isci_engine_create(stream), isci.isci_engine_create(stream)]
         self.opts = davidson_opts or {}
         self.fast_dim = int(fast_dim)
@@ -294,6 +296,9 @@ class GpuExecutor:
             else:
                 hd = self.isci.isci_create(h, ints, r.norb, r.nalpha, r.nbeta, r.level, r.tau)
             del h, ints
+            if self.tune:
+                from paper_1609_07757_amd import tune
+                tune.tune_handle(hd, nvec=min(r.nroots + 2, 8))
             cls = 0 if hd.dim <= self.fast_dim else 1
             slot = self.isci.isci_engine_add(self.engs[cls], hd, nroots=r.nroots, **self.opts)
         except torch.cuda.OutOfMemoryError as e:

@@ -8,7 +8,10 @@ later process with the same shape skips the search.
 Tunables
 --------
 * per handle: sigma kernel family (general string algebra, pair tables,
-  pair tables + FP64 MFMA alpha-beta tiles);
+  pair tables + FP64 MFMA alpha-beta tiles) and, on the matrix-core path,
+  the alpha-beta product kernel, the one-body kernel and whether the
+  one-body classes run on the handle's side stream or in line
+  (``tune_handle``);
 * per engine: persistent grid size of the fused sigma launch and the
   order of its jobs (heaviest first or natural).
 """
@@ -84,6 +87,65 @@ def tune_sigma(hd, nvec: int = 1, reps: int = 3, use_cache: bool = True):
     cache[key] = {"variant": best, "ms": {str(k): v for k, v in ms.items()}}
     _save(cache)
     return best, ms
+
+
+def handle_key(hd, nvec):
+    return sigma_key(hd, nvec).replace("sigma:", "handle:", 1)
+
+
+def _apply(hd, cfg):
+    """Set a handle configuration; False when the handle refuses it."""
+    try:
+        for opt, val in cfg:
+            isci.isci_set_option(hd, opt, val)
+        return True
+    except isci.IsciError:
+        return False
+
+
+def handle_candidates(hd):
+    """Option sets worth timing for this handle: the scalar pair kernel, and
+    for two electrons per spin every combination of product kernel,
+    one-body kernel (up to 80 orbitals, where there is a choice) and
+    one-body stream on the matrix-core path."""
+    if not (hd.nalpha == 2 and hd.nbeta == 2):
+        return [((isci.OPT_SIGMA_KERNEL, isci.SIGMA_GENERAL),)]
+    cands = [((isci.OPT_SIGMA_KERNEL, isci.SIGMA_PAIR),)]
+    obk = [isci.ONEBODY_TRANSPOSED, isci.ONEBODY_SINGLE, isci.ONEBODY_SPECTATOR] if hd.norb <= 80 else \
+        [isci.ONEBODY_TRANSPOSED]
+    for ab in (isci.AB_WIDE, isci.AB_PLAIN, isci.AB_PIPE):
+        for ob in obk:
+            for st in (isci.ONEBODY_SIDE, isci.ONEBODY_INLINE):
+                cands.append(((isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA), (isci.OPT_AB_PRODUCT, ab),
+                              (isci.OPT_ONEBODY_KERNEL, ob), (isci.OPT_ONEBODY_STREAM, st)))
+    return cands
+
+
+def tune_handle(hd, nvec: int = 1, reps: int = 3, use_cache: bool = True):
+    """Pick the fastest option set of `handle_candidates` for this handle and
+    block size, timed on the handle itself with HIP events; the winner is
+    applied and cached per shape.  Returns (config, {index: ms})."""
+    import torch
+    key = handle_key(hd, nvec)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        cfg = tuple(tuple(x) for x in cache[key]["config"])
+        if _apply(hd, cfg):
+            return cfg, cache[key]["ms"]
+    c = torch.randn(nvec, hd.dim, dtype=torch.float64, device="cuda")
+    sg = torch.empty_like(c)
+    ms = {}
+    cands = handle_candidates(hd)
+    for i, cfg in enumerate(cands):
+        if not _apply(hd, cfg):
+            continue
+        ms[i] = _time(lambda: isci.isci_sigma(hd, c, sg), reps, torch)
+    best = min(ms, key=ms.get)
+    _apply(hd, cands[best])
+    cache = _load()
+    cache[key] = {"config": [list(x) for x in cands[best]], "ms": {str(k): v for k, v in ms.items()}}
+    _save(cache)
+    return cands[best], ms
 
 
 def tune_engine(eng, handles, nvecs, reps: int = 3):

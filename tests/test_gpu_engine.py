@@ -185,3 +185,31 @@ def test_server_charges_what_the_handle_holds(recipe, norb, L, tau):
         srv._retire()
     assert r.status == "done" and srv.used == 0
     ex.close()
+
+
+@pytest.mark.parametrize("recipe,norb,L,tau,nvec", [("A", 30, 3, 1e-12, 3), ("B", 48, 4, 1e-14, 4),
+                                                     ("A", 90, 2, 1e-12, 2)])
+def test_tuned_handle_matches_oracle(recipe, norb, L, tau, nvec, tmp_path, monkeypatch):
+    """tune.tune_handle times every option set of the handle, applies the
+    fastest and caches it per shape: the tuned sigma matches the oracle, a
+    second handle of the same shape takes the cached choice without timing,
+    and sigma does not change with the choice beyond rounding."""
+    import paper_1609_07757_amd as isci
+    from paper_1609_07757_amd import tune
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "tune.json"))
+    torch, dev = torch_dev()
+    h, eri = (recipe_a if recipe == "A" else recipe_b)(norb, seed=3)
+    hd = create(h, eri, norb, 2, 2, L, tau)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, nvec, seed=4)
+    base = gpu_sigma(hd, c)
+    cfg, ms = tune.tune_handle(hd, nvec=nvec, reps=1)
+    assert len(ms) >= 2 and cfg in [tuple(x) for x in tune.handle_candidates(hd)]
+    got = gpu_sigma(hd, c)
+    assert rel_err(got, base) <= 1e-12
+    if S.dim <= 60000:
+        assert rel_err(got, O.sigma(S, h, eri, tau, c)) <= 1e-12
+    hd2 = create(h, eri, norb, 2, 2, L, tau)
+    cfg2, ms2 = tune.tune_handle(hd2, nvec=nvec, reps=1)
+    assert cfg2 == cfg and ms2 == {str(k): v for k, v in ms.items()}
+    assert np.array_equal(gpu_sigma(hd2, c), got)
