@@ -25,7 +25,7 @@
 //
 //  * unfold: every (q, S) that opens a chunk gets 4 rows of T, pcols[class]
 //    wide; each determinant scatters its values into T once per call;
-//  * product: a workgroup takes one row block pair and kAbTile (256)
+//  * product: a workgroup takes one row block pair and kAbTile (128)
 //    columns; each wave four 16-column tiles; K runs over the chunks whose class leaves
 //    the columns valid (a prefix of the chunk list); S gets 16 rows x
 //    pcols[class of the row block pair];
@@ -92,7 +92,8 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 // (w % CW) and the (w / CW)-th of KS contiguous parts of the chunk list
 // (more waves in flight per tile); the parts are summed through LDS in a
 // fixed order.
-// (at most 80 VGPRs: six waves per SIMD, three 8-wave workgroups per CU)
+// (at most 80 VGPRs: six waves per SIMD, six 4-wave workgroups per CU with
+// the default 2 x 2 wave shape)
 // WIDE: each lane fetches two adjacent columns with one 16-byte load (two
 // loads per chunk instead of four), so the four 16-column N tiles of a
 // wave are the even and odd columns of its two 32-column halves; S is

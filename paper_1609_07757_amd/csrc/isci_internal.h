@@ -35,9 +35,18 @@ struct SpinTab {
 
 // alpha-beta product tiles: 64-column groups per tile (one per wave) and
 // parts of the chunk list per tile (waves per tile = kAbCW * kAbSplit)
-constexpr int kAbCW = 4;
-constexpr int kAbSplit = 2;
+// (build-time tuning knobs ISCI_AB_CW / ISCI_AB_SPLIT; defaults measured best)
+#ifndef ISCI_AB_CW
+#define ISCI_AB_CW 2
+#endif
+#ifndef ISCI_AB_SPLIT
+#define ISCI_AB_SPLIT 2
+#endif
+constexpr int kAbCW = ISCI_AB_CW;
+constexpr int kAbSplit = ISCI_AB_SPLIT;
 constexpr int kAbTile = 64 * kAbCW;   // columns per tile
+// columns of T whose tiles run together on one XCD (a multiple of kAbTile)
+constexpr int kAbSlabCols = kAbTile > 256 ? kAbTile : 256;
 
 // One workgroup of the alpha-beta product: row block pair g (-1: idle
 // workgroup), first column c0 of its kAbTile-column slab, its chunk list from

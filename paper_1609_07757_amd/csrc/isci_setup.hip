@@ -837,22 +837,26 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     const size_t sbytes = sizeof(double) * std::max<size_t>(1, ssize);
     if (tbytes + sbytes > kAbxMaxBytes) return ISCI_OK;   // gathered kernel instead
     // product tiles column slab by column slab (all row block pairs of a
-    // kAbTile-column slab together: the slab of T they read, a few MB, stays in
-    // one XCD's L2), cost ~ chunks applied + 1, cut into eight contiguous
-    // runs of about equal cost (one per XCD)
+    // slab of kAbSlabCols columns together: the slab of T they read, a few
+    // MB, stays in one XCD's L2), the kAbTile-column tiles of one row block
+    // pair in a slab next to each other (their chunk values are read from
+    // memory once and then from L2), cost ~ chunks applied + 1, cut into
+    // eight contiguous runs of about equal cost (one per XCD)
     std::vector<int2> tiles;
     std::vector<double> cost;
     const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + kAbTile - 1) / kAbTile;
-    for (int sl = 0; sl < nslab; ++sl)
-        for (int g : rows) {
-            const int m = (g / nb != 0) + (g % nb != 0);
-            if (sl * kAbTile >= pcols[m]) continue;
-            int ne = 0;
-            for (int l = 0; l < 3; ++l)
-                if (sl * kAbTile < pcols[std::max(l, m)]) ne += cls[3 * g + l];
-            tiles.push_back(make_int2(g, sl));
-            cost.push_back(1.0 + ne);
-        }
+    constexpr int sgrp = kAbSlabCols / kAbTile;
+    for (int sg = 0; sg < nslab; sg += sgrp)
+        for (int g : rows)
+            for (int sl = sg; sl < std::min(sg + sgrp, nslab); ++sl) {
+                const int m = (g / nb != 0) + (g % nb != 0);
+                if (sl * kAbTile >= pcols[m]) continue;
+                int ne = 0;
+                for (int l = 0; l < 3; ++l)
+                    if (sl * kAbTile < pcols[std::max(l, m)]) ne += cls[3 * g + l];
+                tiles.push_back(make_int2(g, sl));
+                cost.push_back(1.0 + ne);
+            }
     double total = 0.0;
     for (double w : cost) total += w;
     std::vector<int> xrun(9, 0);
