@@ -45,8 +45,13 @@ struct SpinTab {
 constexpr int kAbCW = ISCI_AB_CW;
 constexpr int kAbSplit = ISCI_AB_SPLIT;
 constexpr int kAbTile = 64 * kAbCW;   // columns per tile
-// columns of T whose tiles run together on one XCD (a multiple of kAbTile)
-constexpr int kAbSlabCols = kAbTile > 256 ? kAbTile : 256;
+// columns of T whose tiles run together on one XCD (a multiple of kAbTile;
+// build-time knob ISCI_AB_SLAB_COLS)
+#ifndef ISCI_AB_SLAB_COLS
+#define ISCI_AB_SLAB_COLS 512
+#endif
+constexpr int kAbSlabCols = ISCI_AB_SLAB_COLS > kAbTile ? ISCI_AB_SLAB_COLS : kAbTile;
+static_assert(kAbSlabCols % kAbTile == 0, "slab width must be a multiple of the tile width");
 
 // One workgroup of the alpha-beta product: row block pair g (-1: idle
 // workgroup), first column c0 of its kAbTile-column slab, its chunk list from
