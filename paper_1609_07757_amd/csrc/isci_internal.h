@@ -126,8 +126,9 @@ struct DevTabs {
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
-    double *obT_c = nullptr;        // [4][dim] transposed CI block (beta one-body above kObMaxNorb)
-    double *obT_s = nullptr;        // [4][dim] its alpha-class image
+    double *obT_c = nullptr;        // [obT_nv][dim] transposed CI block (beta one-body above kObMaxNorb,
+                                    // full-CI alpha one-body)
+    double *obT_s = nullptr;        // [obT_nv][dim] its one-body image
     // density matrices: vectors in the spin-swapped layout (rows = beta
     // strings holding alpha prefixes), allocated by the first density call
     double *d1T = nullptr;          // [kD1Chunk][dim]
@@ -242,6 +243,7 @@ struct isci_ctx {
     int abx_xmax = 0;        // longest XCD tile run
     int ab_kernel = ISCI_AB_WIDE;    // ISCI_OPT_AB_PRODUCT: wide-load k_ab_gemm (default), k_ab_gemm or k_ab_pipe
     int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
+    int obT_nv = 4;                            // vectors of the transposed one-body scratch (4 or 8)
     bool ob_side = true;     // ISCI_OPT_ONEBODY_STREAM: one-body kernels on the side stream (else in line)
     int64_t nkept_h = 0, nkept_ab = 0;
     bool have_tiles = false;

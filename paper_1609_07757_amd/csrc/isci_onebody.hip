@@ -535,8 +535,9 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
         // transposed block, whose rows are contiguous; beta kernel there,
         // then added back through a second transpose
         const int64_t dim = cx->dim;
-        for (int u0 = 0; u0 < nv; u0 += 4) {
-            const int nu = nv - u0 < 4 ? nv - u0 : 4;
+        const int step = cx->obT_nv;   // vectors the transposed scratch holds
+        for (int u0 = 0; u0 < nv; u0 += step) {
+            const int nu = nv - u0 < step ? nv - u0 : step;
             launch_block_transpose(cx, A, c + (int64_t)u0 * ldc, ldc, cx->d.obT_c, dim, 0, nu, st);
             k_ob_beta_full<NT><<<dim3((unsigned)cx->sa.nstr, (unsigned)nu), 64 * NT, 0, st>>>(
                 A, cx->d.obT_c, dim, cx->d.obT_s, dim, cx->d.hscreen, cx->d.hpad, 0, 1);
@@ -878,6 +879,10 @@ __global__ __launch_bounds__(256) void k_det_transpose(SigmaArgs A, const double
     const int n = A.sa.nstr, L = A.L;
     // tile rows of src are b, columns a: empty when a0 >= len(b0)
     if (b0 >= n || a0 >= A.sb.le[L - A.alev[b0]]) return;
+    // vectors [4 blockIdx.z, 4 blockIdx.z + 4) of the nv
+    src += (int64_t)(4 * blockIdx.z) * lsrc;
+    dst += (int64_t)(4 * blockIdx.z) * ldst;
+    nv -= 4 * (int)blockIdx.z;
     __shared__ double tile[4][32][33];
     // row starts and lengths of the tile's 32 source rows b and 32 target
     // rows a, read once: the element loads then depend on LDS only
@@ -955,8 +960,8 @@ static void launch_block_transpose(const isci_ctx *cx, const SigmaArgs &A, const
         const int len0 = cx->sb.le[cx->L - cx->h_alev[32 * t0]];
         int t1 = t0 + 1;
         while (t1 < nt && cx->sb.le[cx->L - cx->h_alev[32 * t1]] == len0) ++t1;
-        k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0)), 256, 0, st>>>(A, src, lsrc, dst,
-                                                                                             ldst, add, t0, nv);
+        k_det_transpose<<<dim3((unsigned)((len0 + 31) / 32), (unsigned)(t1 - t0), (unsigned)((nv + 3) / 4)), 256, 0,
+                          st>>>(A, src, lsrc, dst, ldst, add, t0, nv);
         t0 = t1;
     }
 }

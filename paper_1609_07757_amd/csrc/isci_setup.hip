@@ -1345,9 +1345,12 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
             // beta one-body above kObMaxNorb runs as the alpha class of the
             // transposed block, and where every column holds every pair
             // (full CI) the alpha class as the beta class of the transposed
-            // block: scratch for four vectors and their image
-            c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
-            c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * 4 * (size_t)c->dim);
+            // block: scratch for a block of vectors and its image, eight
+            // vectors (one pass per sigma block) for full CI up to 80
+            // orbitals and 4 Mi determinants, else four
+            c->obT_nv = (norb <= kObMaxNorb && c->dim <= ((int64_t)1 << 22)) ? 8 : 4;
+            c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
+            c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
             if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
         }
         if (st == ISCI_OK && c->have_abx && !c->onebody_in_tiles && onebody_mfma_ok(c)) {
