@@ -7,8 +7,9 @@
 // screening the CI vector as the integrals are screened).
 //
 // One step of length dt: a Krylov basis V = [v_0 .. v_{m-1}] of H_tau from
-// v_0 = u / |u|, each new direction H v_j orthogonalised against the whole
-// basis twice (classical Gram-Schmidt, Arnoldi form), the projected matrix
+// v_0 = u / |u|, each new direction H v_j orthogonalised against v_{j-1},
+// v_j and then, once more, against the whole basis (classical
+// Gram-Schmidt, Arnoldi form with full reorthogonalisation), the projected matrix
 // T = V^T H V (symmetrised), and
 //   imaginary time:  u <- |u| V exp(-T dt) e_1, then normalised;
 //   real time:       u <- |u| V exp(-i T dt) e_1 for a real u; a complex
@@ -61,6 +62,21 @@ __global__ void k_coef_screen(double *__restrict__ re, double *__restrict__ im, 
     if ((threadIdx.x & 63) == 0 && mine) atomicAdd(cnt, mine);
 }
 
+// one Gram-Schmidt pass of each chain ch < nch over basis vectors i0 ..
+// i0 + m - 1: the dots h = V^T w just formed (outd[ch][i], i < m) are added
+// to column j of the chain's projected matrix (T[ch][i0 + i][j], leading
+// dimension mm) and negated into the coefficients of the update w -= V h
+__global__ void k_gs_pass(const double *__restrict__ outd, int nch, int mm, int m, int i0, int j,
+                          double *__restrict__ T, double *__restrict__ coef)
+{
+    for (int t = threadIdx.x; t < nch * m; t += blockDim.x) {
+        const int ch = t / m, i = t - ch * m;
+        const double hv = outd[(size_t)ch * mm + i];
+        T[((size_t)ch * mm + i0 + i) * mm + j] += hv;
+        coef[(size_t)ch * mm + i] = -hv;
+    }
+}
+
 unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256)); }
 
 // the symmetric m x m projected matrix from the Arnoldi entries T[i][j]
@@ -90,6 +106,7 @@ struct Krylov {
                               // [nch][mmax + 1]; real-time recombination: 4 rows)
     double *part = nullptr;   // dot partials
     double *outd = nullptr;   // [nch][mmax + 1] dot results
+    double *Td = nullptr;     // [nch][mmax + 1][mmax + 1] projected matrices (Arnoldi entries)
     int nblk = 1;
     double *vec(int j, int ch) const { return V + ((int64_t)j * nch + ch) * n; }
 };
@@ -136,9 +153,10 @@ isci_status isci_propagate(isci_handle h, double *c_re, double *c_im, double dt,
     if (e == hipSuccess) e = hipMallocAsync((void **)&K.coef, sizeof(double) * (size_t)4 * mm, stream);
     if (e == hipSuccess) e = hipMallocAsync((void **)&K.part, sizeof(double) * (size_t)K.nblk * mm, stream);
     if (e == hipSuccess) e = hipMallocAsync((void **)&K.outd, sizeof(double) * (size_t)K.nch * mm, stream);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&K.Td, sizeof(double) * (size_t)K.nch * mm * mm, stream);
     if (e == hipSuccess) e = hipMallocAsync((void **)&dcnt, sizeof(unsigned long long), stream);
     auto release = [&]() {
-        for (void *p : {(void *)K.V, (void *)K.W, (void *)K.coef, (void *)K.part, (void *)K.outd, (void *)dcnt})
+        for (void *p : {(void *)K.V, (void *)K.W, (void *)K.coef, (void *)K.part, (void *)K.outd, (void *)K.Td, (void *)dcnt})
             if (p) (void)hipFreeAsync(p, stream);
         (void)hipStreamSynchronize(stream);
     };
@@ -152,9 +170,6 @@ isci_status isci_propagate(isci_handle h, double *c_re, double *c_im, double dt,
     double *chain[2] = {c_re, o.imaginary ? nullptr : c_im};
     // host copy of dot results of chain ch (count k) after a sync
     std::vector<double> hbuf((size_t)K.nch * mm);
-    auto dot_many = [&](int ch, int k, const double *B) -> isci_status {
-        return dots(K.vec(0, ch), (int64_t)K.nch * n, k, B, n, 1, n, K.outd + (size_t)ch * mm, K.part, K.nblk, stream);
-    };
     auto fetch = [&]() -> isci_status {
         ISCI_HIP(hipMemcpyAsync(hbuf.data(), K.outd, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, stream));
         ISCI_HIP(hipStreamSynchronize(stream));
@@ -173,40 +188,45 @@ isci_status isci_propagate(isci_handle h, double *c_re, double *c_im, double dt,
             k_scale_to<<<grid_of(n), 256, 0, stream>>>(chain[ch], K.vec(0, ch), n, live[ch] ? 1.0 / beta0[ch] : 0.0);
         }
         if (!live[0] && !live[1]) break;
-        // Arnoldi: T[ch][i][j] = <v_i, H v_j>, i <= j + 1
+        // Arnoldi: T[ch][i][j] = <v_i, H v_j>, i <= j + 1, accumulated on the
+        // device pass by pass; one host wait per basis vector brings back
+        // the new column and the norm of the remainder for the stopping test
         std::vector<std::vector<double>> T(K.nch, std::vector<double>((size_t)mm * mm, 0.0));
+        std::vector<double> Th((size_t)K.nch * mm * mm);
+        ISCI_HIP(hipMemsetAsync(K.Td, 0, sizeof(double) * Th.size(), stream));
         int m = 0;
         bool stop = false;
         for (int j = 0; j < K.mmax && !stop; ++j) {
             if ((st = launch_sigma(h, K.nch, K.vec(j, 0), n, K.W, n, stream)) != ISCI_OK) break;
             sigma_calls += K.nch;
-            // two classical Gram-Schmidt passes against v_0 .. v_j
-            for (int pass = 0; pass < 2 && st == ISCI_OK; ++pass) {
-                for (int ch = 0; ch < K.nch && st == ISCI_OK; ++ch) st = dot_many(ch, j + 1, K.W + (size_t)ch * n);
-                if (st != ISCI_OK || (st = fetch()) != ISCI_OK) break;
-                std::vector<double> neg((size_t)K.nch * mm, 0.0);
+            // Gram-Schmidt in two passes: against v_{j-1}, v_j first (the
+            // three-term part, which removes the bulk of H v_j), then one
+            // classical pass against the whole basis v_0 .. v_j
+            auto gs_pass = [&](int i0, int cnt) -> isci_status {
                 for (int ch = 0; ch < K.nch; ++ch)
-                    for (int i = 0; i <= j; ++i) {
-                        T[ch][(size_t)i * mm + j] += hbuf[(size_t)ch * mm + i];
-                        neg[(size_t)ch * mm + i] = -hbuf[(size_t)ch * mm + i];
-                    }
-                ISCI_HIP(hipMemcpyAsync(K.coef, neg.data(), sizeof(double) * neg.size(), hipMemcpyHostToDevice, stream));
-                for (int ch = 0; ch < K.nch && st == ISCI_OK; ++ch)
-                    st = lincomb(K.vec(0, ch), (int64_t)K.nch * n, j + 1, K.coef + (size_t)ch * mm, 1,
-                                 K.W + (size_t)ch * n, n, n, 1.0, stream);
-                // the host vector `neg` is rewritten next pass: wait for the copy
-                if (st == ISCI_OK) ISCI_HIP(hipStreamSynchronize(stream));
-            }
-            if (st != ISCI_OK) break;
+                    ISCI_CHECK(dots(K.vec(i0, ch), (int64_t)K.nch * n, cnt, K.W + (size_t)ch * n, n, 1, n,
+                                    K.outd + (size_t)ch * mm, K.part, K.nblk, stream));
+                k_gs_pass<<<1, 256, 0, stream>>>(K.outd, K.nch, mm, cnt, i0, j, K.Td, K.coef);
+                ISCI_HIP(hipGetLastError());
+                for (int ch = 0; ch < K.nch; ++ch)
+                    ISCI_CHECK(lincomb(K.vec(i0, ch), (int64_t)K.nch * n, cnt, K.coef + (size_t)ch * mm, 1,
+                                       K.W + (size_t)ch * n, n, n, 1.0, stream));
+                return ISCI_OK;
+            };
+            const int i0 = j > 0 ? j - 1 : 0;
+            if ((st = gs_pass(i0, j + 1 - i0)) != ISCI_OK || (st = gs_pass(0, j + 1)) != ISCI_OK) break;
             for (int ch = 0; ch < K.nch && st == ISCI_OK; ++ch)
                 st = dots(K.W + (size_t)ch * n, n, 1, K.W + (size_t)ch * n, n, 1, n, K.outd + (size_t)ch * mm, K.part,
                           K.nblk, stream);
-            if (st != ISCI_OK || (st = fetch()) != ISCI_OK) break;
+            if (st != ISCI_OK) break;
+            ISCI_HIP(hipMemcpyAsync(Th.data(), K.Td, sizeof(double) * Th.size(), hipMemcpyDeviceToHost, stream));
+            if ((st = fetch()) != ISCI_OK) break;   // also waits for Th
             m = j + 1;
             double worst = 0.0;
             bool invariant = true;
             for (int ch = 0; ch < K.nch; ++ch) {
                 if (!live[ch]) continue;
+                for (int i = 0; i <= j; ++i) T[ch][(size_t)i * mm + j] = Th[((size_t)ch * mm + i) * mm + j];
                 const double beta = std::sqrt(std::max(0.0, hbuf[(size_t)ch * mm]));
                 T[ch][(size_t)(j + 1) * mm + j] = beta;
                 // residual estimate of exp over the current basis
