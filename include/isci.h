@@ -353,7 +353,8 @@ isci_status isci_davidson(isci_handle hd, int nroots, const isci_davidson_opts *
  * coefficients (propagation in imaginary time, application section: thousands
  * of sigma steps), and real-time propagation for dynamics.  Each of nsteps
  * steps of length dt builds a Krylov basis of H_tau from the current vector
- * (each new direction orthogonalised against the basis twice), stops when
+ * (each new direction orthogonalised against the two latest basis vectors
+ * and then once against the whole basis), stops when
  * the residual estimate of the step falls below tol |u| or at `krylov`
  * vectors, and applies exp(-T dt) (imaginary) or exp(-i T dt) (real) of the
  * projected matrix.  Coefficient screening (the paper's proposal in its
@@ -365,8 +366,8 @@ isci_status isci_davidson(isci_handle hd, int nroots, const isci_davidson_opts *
  *                  [dim], distinct).
  * Vectors are updated in place.  The call allocates its Krylov basis
  * ((krylov + 1) dim doubles per real chain) for its own duration and
- * synchronises the stream a few times per Krylov vector (small host
- * eigenproblems).  info (may be NULL): energy <c|H|c>/<c|c> of the result
+ * synchronises the stream once per Krylov vector (the stopping test runs
+ * small host eigenproblems).  info (may be NULL): energy <c|H|c>/<c|c> of the result
  * (one more sigma), its norm, sigma vectors computed, Krylov size of the
  * last step and coefficients zeroed by the last screening.  Errors:
  * ISCI_E_INVALID for NULL handle or c_re, a missing or aliased c_im in real
