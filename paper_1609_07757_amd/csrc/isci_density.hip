@@ -36,8 +36,8 @@ namespace {
 
 typedef double v4d_d2 __attribute__((ext_vector_type(4)));
 
-constexpr int kD1Chunk = 8;
-constexpr int kD2MaxNorb = 128;   // two-body densities: 8 norb^4 bytes per scratch buffer   // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
+constexpr int kD1Chunk = 8;       // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
+constexpr int kD2MaxNorb = 128;   // two-body densities: 8 norb^4 bytes per scratch buffer
 constexpr int kGramGroups = 64;   // partial slabs (set groups x piece streams) summed in order by k_d1_reduce
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
@@ -134,12 +134,13 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
     const bool same = (tp == tq);
     const int gp = blockIdx.y, g = gp / P, pc = gp - g * P, v = blockIdx.z;
     const double *cv = c + (int64_t)v * ldc;
-    const int pr = (tid >> 4) * 4, qc = (tid & 15) * 4;
-    double acc[4][4];
+    // products on FP64 matrix cores: wave w forms output rows
+    // [16 w, 16 w + 16) x 64 columns as four 16 x 16 tiles; element e of
+    // lane l of tile nt is row 16 w + 4 e + l / 16, column 16 nt + l % 16
+    const int w = tid >> 6, lane = tid & 63;
+    v4d_d2 acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4d_d2{0.0, 0.0, 0.0, 0.0};
 
     for (int set = g; set < nsets; set += G) {
         int S[ISCI_MAXN];
@@ -192,15 +193,13 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
             }
             __syncthreads();
             const double (*Bt)[kGK + 1] = same ? As : Bs;
-#pragma unroll 4
-            for (int kk = 0; kk < kGK; ++kk) {
-                double a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) { a[i] = As[pr + i][kk]; b[i] = Bt[qc + i][kk]; }
+            for (int ks = 0; ks < kGK / 4; ++ks) {
+                const double a = As[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bt[16 * nt + (lane & 15)][4 * ks + (lane >> 4)],
+                                                                   acc[nt], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -217,22 +216,19 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
                 if (lane == 0) ph2[i][j] = part2;
             }
             __syncthreads();
-            if (tid == 0) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] += ph2[i][j];
-            }
+            // rows and columns 0..3 of the tile: wave 0, tile 0, element 0,
+            // lanes 16 i + j
+            if (w == 0 && (lane >> 4) < 4 && (lane & 15) < 4) acc[0][0] += ph2[lane >> 4][lane & 15];
         }
         __syncthreads();
     }
     double *out = part + ((int64_t)gp * nv + v) * norb * norb;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int p = P0 + pr + i, q = Q0 + qc + j;
-            if (p < norb && q < norb) out[(int64_t)p * norb + q] = acc[i][j];
+        for (int e = 0; e < 4; ++e) {
+            const int p = P0 + 16 * w + 4 * e + (lane >> 4), q = Q0 + 16 * nt + (lane & 15);
+            if (p < norb && q < norb) out[(int64_t)p * norb + q] = acc[nt][e];
         }
 }
 
