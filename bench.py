@@ -130,6 +130,15 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     ms_per_step = ev_ms / a.steps
+    # distribution of single steps (an event pair around each, outside the
+    # timed region above)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    for ea, eb in evs:
+        ea.record(stream)
+        isci.isci_sigma(hd, c, sg, stream=stream)
+        eb.record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([ea.elapsed_time(eb) for ea, eb in evs])
     # the same step recorded once as a HIP graph and replayed (one graph
     # launch per step instead of the call's kernel launches)
     sg_g = torch.empty_like(c)
@@ -219,6 +228,7 @@ def main():
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
         "wall_s_timed": wall,
+        "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
         "roofline": {"bound": "alu" if kname in ("k_sigma_generic", "k_sigma_n2", "k_sigma_n2(same-spin)") else "mfma",
                      "kernel": kname,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
