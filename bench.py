@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # revision of each kernel's code: stored HBM traffic (profiles/sigma_traffic.json)
 # is used only when it was counted for the same revision
-KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs, 16-byte operand loads, 128-column tiles in 512-column slabs"}
+KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs, 16-byte operand loads, 128-column tiles in 512-column slabs, packed chunks"}
 HBM_PEAK_GBS = 8000.0
 METRIC = "σ-vectors/s + screened terms/s (% roofline); p50/p99 Davidson solve latency"
 
@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
-    ap.add_argument("--ab", choices=["plain", "pipe", "wide"], default="wide",
+    ap.add_argument("--ab", choices=["plain", "pipe", "wide", "packed"], default="packed",
                     help="kernel of the alpha-beta block-sparse product")
     ap.add_argument("--onebody", choices=["transposed", "single", "spectator"], default="transposed",
                     help="one-body kernel on the rows / columns that hold every pair")
@@ -254,7 +254,7 @@ def main():
 def set_ab_product(isci, hd, name):
     """Kernel of the alpha-beta product: plain ping-pong or software pipeline."""
     isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, {"plain": isci.AB_PLAIN, "pipe": isci.AB_PIPE,
-                                                   "wide": isci.AB_WIDE}[name])
+                                                   "wide": isci.AB_WIDE, "packed": isci.AB_PACKED}[name])
 
 
 def density1_timing(isci, torch, hd, c, stream, steps):

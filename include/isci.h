@@ -493,9 +493,12 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
  *   the kernel of the block-sparse product (the alpha-beta classes, Eqs.
  *   h200ca..h200ab among them, as one screened matrix of (pq|rs) applied
  *   to the unfolded vectors), one row block pair per workgroup tile:
- *   ISCI_AB_WIDE (default) with a two-chunk ping-pong and 16-byte operand
- *   loads and stores (two adjacent columns per lane), ISCI_AB_PLAIN the
- *   same with 8-byte ones, ISCI_AB_PIPE with an explicit two-stage
+ *   ISCI_AB_PACKED (default) as WIDE over packed chunks (per row block
+ *   pair and source class, the (q, s) columns that hold a kept value, four
+ *   per chunk: no all-zero K column); ISCI_AB_WIDE with a two-chunk
+ *   ping-pong and 16-byte operand loads and stores (two adjacent columns
+ *   per lane) over the (q, four-orbital block of s) chunks; ISCI_AB_PLAIN
+ *   the same with 8-byte ones; ISCI_AB_PIPE with an explicit two-stage
  *   software pipeline (chunk table read one stage early).  Same sigma up to
  *   rounding order (WIDE and PLAIN: the same sums in the same order, bit
  *   for bit). */
@@ -503,6 +506,7 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_AB_PLAIN 0
 #define ISCI_AB_PIPE 1
 #define ISCI_AB_WIDE 2
+#define ISCI_AB_PACKED 3
 /*   ISCI_OPT_ONEBODY_KERNEL (matrix-core one-body classes up to 80
  *   orbitals, for tuning): ISCI_ONEBODY_TRANSPOSED (default) runs the alpha
  *   class, where every beta column holds every alpha pair (full CI), as the

@@ -29,7 +29,7 @@ OPT_AB_PATH = 2
 AB_AUTO, AB_GATHER = 0, 1
 # kernel of the block-sparse alpha-beta product (tuning; same sigma up to rounding order)
 OPT_AB_PRODUCT = 3
-AB_PLAIN, AB_PIPE, AB_WIDE = 0, 1, 2
+AB_PLAIN, AB_PIPE, AB_WIDE, AB_PACKED = 0, 1, 2, 3
 # one-body kernel where every column holds every pair (tuning)
 OPT_ONEBODY_KERNEL = 5
 ONEBODY_SINGLE, ONEBODY_TRANSPOSED, ONEBODY_SPECTATOR = 1, 2, 3

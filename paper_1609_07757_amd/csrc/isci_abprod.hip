@@ -98,12 +98,15 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 // loads per chunk instead of four), so the four 16-column N tiles of a
 // wave are the even and odd columns of its two 32-column halves; S is
 // stored two columns per lane in the same order.
-template <int CW, int KS, bool WIDE>
+// PACKED (with WIDE): the packed chunk lists, whose four K columns may come
+// from different T rows (one offset per column, selected per lane group).
+template <int CW, int KS, bool WIDE, bool PACKED>
 __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6))) void k_ab_gemm(SigmaArgs A)
 {
+    static_assert(!PACKED || WIDE, "packed chunks use the 16-byte loads");
     __shared__ double red[KS > 1 ? KS - 1 : 1][CW][16][64];
     const int nb = A.nblk;
-    const AbBlk tb = A.abx_blk[blockIdx.x];   // one scalar load: the tile of this workgroup
+    const AbBlk tb = PACKED ? A.abx_pblk[blockIdx.x] : A.abx_blk[blockIdx.x];   // one scalar load: the tile
     if (tb.g < 0) return;
     const int g = tb.g;
     const int Ab = g / nb, Bb = g % nb;
@@ -139,6 +142,16 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int eu = min(e + u, e1 - 1);
+            if (PACKED) {
+                const int4 r4 = A.abx_pchunk[eu];   // T offsets of the chunk's four rows
+                const int ro = k == 0 ? r4.x : (k == 1 ? r4.y : (k == 2 ? r4.z : r4.w));
+                const double av = A.pchunk_val[(size_t)eu * 64 + lane];
+                a[u] = e + u < e1 ? av : 0.0;
+                const double2 *src = (const double2 *)(A.abx_T + (size_t)ro + c0 + 2 * n);
+                const double2 lo = src[0], hi = src[16];
+                b[u][0] = lo.x; b[u][1] = lo.y; b[u][2] = hi.x; b[u][3] = hi.y;
+                continue;
+            }
             const int2 tx = A.abx_chunk[eu];   // (T offset of the chunk's row 0, row width)
             const double av = A.chunk_val[(size_t)eu * 64 + lane];
             a[u] = e + u < e1 ? av : 0.0;
@@ -369,12 +382,14 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
         const dim3 grid((unsigned)(8 * cx->abx_xmax)), block(64 * kAbCW * kAbSplit);
-        if (cx->ab_kernel == ISCI_AB_PIPE)
+        if (cx->ab_kernel == ISCI_AB_PACKED && cx->abx_pxmax > 0)
+            k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abx_pxmax)), block, 0, st>>>(A);
+        else if (cx->ab_kernel == ISCI_AB_PIPE)
             k_ab_pipe<kAbCW, kAbSplit, 2><<<grid, block, 0, st>>>(A);
-        else if (cx->ab_kernel == ISCI_AB_WIDE)
-            k_ab_gemm<kAbCW, kAbSplit, true><<<grid, block, 0, st>>>(A);
+        else if (cx->ab_kernel == ISCI_AB_WIDE || cx->ab_kernel == ISCI_AB_PACKED)
+            k_ab_gemm<kAbCW, kAbSplit, true, false><<<grid, block, 0, st>>>(A);
         else
-            k_ab_gemm<kAbCW, kAbSplit, false><<<grid, block, 0, st>>>(A);
+            k_ab_gemm<kAbCW, kAbSplit, false, false><<<grid, block, 0, st>>>(A);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, false, st));
     }
     ISCI_HIP(hipGetLastError());

@@ -123,6 +123,11 @@ struct DevTabs {
     int *abx_rows = nullptr;
     long long *abx_soff = nullptr;
     AbBlk *abx_blk = nullptr;       // [8 * abx_xmax]: the product tile of each workgroup
+    // packed chunks: per row block pair and class, the non-empty (q, s)
+    // columns of its chunks four at a time (no all-zero column)
+    int4 *abx_pchunk = nullptr;     // [npchunk]: T offsets of the four rows a packed chunk reads
+    double *pchunk_val = nullptr;   // [npchunk][64]: values in MFMA operand-A lane order
+    AbBlk *abx_pblk = nullptr;      // [8 * abx_pxmax]: product tiles over the packed chunk lists
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
@@ -176,6 +181,9 @@ struct SigmaArgs {
     const long long *abx_soff;
     const AbBlk *abx_blk;
     const int *abx_ctof;
+    const int4 *abx_pchunk;
+    const double *pchunk_val;
+    const AbBlk *abx_pblk;
     int nchunk;              // chunks of W; chunk_val holds one more, all zero
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
@@ -241,7 +249,9 @@ struct isci_ctx {
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};
     int abx_xmax = 0;        // longest XCD tile run
-    int ab_kernel = ISCI_AB_WIDE;    // ISCI_OPT_AB_PRODUCT: wide-load k_ab_gemm (default), k_ab_gemm or k_ab_pipe
+    int abx_pxmax = 0;       // the same over the packed chunk lists (0: not built)
+    int npchunk = 0;         // packed chunks
+    int ab_kernel = ISCI_AB_PACKED;  // ISCI_OPT_AB_PRODUCT: packed wide-load k_ab_gemm (default), wide, plain, pipe
     int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
     int obT_nv = 4;                            // vectors of the transposed one-body scratch (4 or 8)
     bool ob_side = true;     // ISCI_OPT_ONEBODY_STREAM: one-body kernels on the side stream (else in line)

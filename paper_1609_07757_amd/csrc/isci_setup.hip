@@ -526,6 +526,9 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.abx_soff = c->d.abx_soff;
     A.abx_blk = c->d.abx_blk;
     A.abx_ctof = c->d.abx_ctof;
+    A.abx_pchunk = c->d.abx_pchunk;
+    A.pchunk_val = c->d.pchunk_val;
+    A.abx_pblk = c->d.abx_pblk;
     A.nchunk = c->nchunk;
     A.abx_T = c->d.abx_T;
     A.abx_S = c->d.abx_S;
@@ -841,51 +844,100 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     // MB, stays in one XCD's L2), the kAbTile-column tiles of one row block
     // pair in a slab next to each other (their chunk values are read from
     // memory once and then from L2), cost ~ chunks applied + 1, cut into
-    // eight contiguous runs of about equal cost (one per XCD)
-    std::vector<int2> tiles;
-    std::vector<double> cost;
-    const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + kAbTile - 1) / kAbTile;
-    constexpr int sgrp = kAbSlabCols / kAbTile;
-    for (int sg = 0; sg < nslab; sg += sgrp)
-        for (int g : rows)
-            for (int sl = sg; sl < std::min(sg + sgrp, nslab); ++sl) {
-                const int m = (g / nb != 0) + (g % nb != 0);
-                if (sl * kAbTile >= pcols[m]) continue;
-                int ne = 0;
-                for (int l = 0; l < 3; ++l)
-                    if (sl * kAbTile < pcols[std::max(l, m)]) ne += cls[3 * g + l];
-                tiles.push_back(make_int2(g, sl));
-                cost.push_back(1.0 + ne);
+    // eight contiguous runs of about equal cost (one per XCD); for the chunk
+    // lists given by (offsets, class counts)
+    auto make_tiles = [&](const std::vector<int> &loff, const std::vector<int> &lcls, int &xmax_out) {
+        std::vector<int2> tiles;
+        std::vector<double> cost;
+        const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + kAbTile - 1) / kAbTile;
+        constexpr int sgrp = kAbSlabCols / kAbTile;
+        for (int sg = 0; sg < nslab; sg += sgrp)
+            for (int g : rows)
+                for (int sl = sg; sl < std::min(sg + sgrp, nslab); ++sl) {
+                    const int m = (g / nb != 0) + (g % nb != 0);
+                    if (sl * kAbTile >= pcols[m]) continue;
+                    int ne = 0;
+                    for (int l = 0; l < 3; ++l)
+                        if (sl * kAbTile < pcols[std::max(l, m)]) ne += lcls[3 * g + l];
+                    tiles.push_back(make_int2(g, sl));
+                    cost.push_back(1.0 + ne);
+                }
+        double total = 0.0;
+        for (double w : cost) total += w;
+        std::vector<int> xrun(9, 0);
+        {
+            double acc = 0.0;
+            int r = 1;
+            for (size_t t = 0; t < tiles.size() && r < 8; ++t) {
+                acc += cost[t];
+                while (r < 8 && acc >= total * r / 8.0) xrun[r++] = (int)t + 1;
             }
-    double total = 0.0;
-    for (double w : cost) total += w;
-    std::vector<int> xrun(9, 0);
-    {
-        double acc = 0.0;
-        int r = 1;
-        for (size_t t = 0; t < tiles.size() && r < 8; ++t) {
-            acc += cost[t];
-            while (r < 8 && acc >= total * r / 8.0) xrun[r++] = (int)t + 1;
+            while (r < 8) xrun[r++] = (int)tiles.size();
+            xrun[8] = (int)tiles.size();
         }
-        while (r < 8) xrun[r++] = (int)tiles.size();
-        xrun[8] = (int)tiles.size();
-    }
+        int xmax = 0;
+        for (int r = 0; r < 8; ++r) xmax = std::max(xmax, xrun[r + 1] - xrun[r]);
+        // workgroup b runs on XCD b % 8 and takes tile b / 8 of that XCD's run
+        std::vector<AbBlk> blk((size_t)8 * std::max(xmax, 1));
+        for (size_t b = 0; b < blk.size(); ++b) {
+            AbBlk &e = blk[b];
+            e = AbBlk{-1, 0, 0, 0, {0, 0, 0}, 0};
+            const int r = (int)(b % 8), t = xrun[r] + (int)(b / 8);
+            if (t >= xrun[r + 1]) continue;
+            const int g = tiles[t].x;
+            e.g = g;
+            e.c0 = tiles[t].y * kAbTile;
+            e.eb = loff[g];
+            int acc = loff[g];
+            for (int l = 0; l < 3; ++l) e.end[l] = (acc += lcls[3 * g + l]);
+        }
+        xmax_out = xmax;
+        return blk;
+    };
     int xmax = 0;
-    for (int r = 0; r < 8; ++r) xmax = std::max(xmax, xrun[r + 1] - xrun[r]);
-    // workgroup b runs on XCD b % 8 and takes tile b / 8 of that XCD's run
-    std::vector<AbBlk> blk((size_t)8 * std::max(xmax, 1));
-    for (size_t b = 0; b < blk.size(); ++b) {
-        AbBlk &e = blk[b];
-        e = AbBlk{-1, 0, 0, 0, {0, 0, 0}, 0};
-        const int r = (int)(b % 8), t = xrun[r] + (int)(b / 8);
-        if (t >= xrun[r + 1]) continue;
-        const int g = tiles[t].x;
-        e.g = g;
-        e.c0 = tiles[t].y * kAbTile;
-        e.eb = off[g];
-        int acc = off[g];
-        for (int l = 0; l < 3; ++l) e.end[l] = (acc += cls[3 * g + l]);
+    const std::vector<AbBlk> blk = make_tiles(off, cls, xmax);
+    // packed chunks: the columns (q, s) of a row block pair's chunks of one
+    // class that hold a kept value, four per chunk in list order (a short
+    // last chunk of a class is filled with zero columns reading a valid row)
+    std::vector<double> cval((size_t)64 * c->nchunk);
+    ISCI_HIP(hipMemcpyAsync(cval.data(), c->d.chunk_val, sizeof(double) * cval.size(), hipMemcpyDeviceToHost, s));
+    ISCI_HIP(hipStreamSynchronize(s));
+    std::vector<int> poff(nb * nb + 1, 0), pcls(3 * nb * nb, 0);
+    std::vector<int4> pchunk;
+    std::vector<double> pval;
+    for (int g = 0; g < nb * nb; ++g) {
+        poff[g] = (int)pchunk.size();
+        int e = off[g];
+        for (int l = 0; l < 3; ++l) {
+            std::vector<int2> cols;   // (chunk, column k)
+            for (int i = 0; i < cls[3 * g + l]; ++i, ++e) {
+                if (pcols[l] == 0) continue;
+                for (int k = 0; k < 4; ++k) {
+                    bool any = false;
+                    for (int r = 0; r < 16; ++r) any |= cval[(size_t)e * 64 + 16 * k + r] != 0.0;
+                    if (any) cols.push_back(make_int2(e, k));
+                }
+            }
+            const int npc = (int)(cols.size() + 3) / 4;
+            for (int pc = 0; pc < npc; ++pc) {
+                int rowk[4];
+                const size_t base = pval.size();
+                pval.resize(base + 64, 0.0);
+                for (int k = 0; k < 4; ++k) {
+                    const size_t ci = (size_t)pc * 4 + k;
+                    const int2 ck = cols[ci < cols.size() ? ci : (size_t)pc * 4];
+                    rowk[k] = chunk[ck.x].x + ck.y * chunk[ck.x].y;
+                    if (ci < cols.size())
+                        for (int r = 0; r < 16; ++r) pval[base + 16 * k + r] = cval[(size_t)ck.x * 64 + 16 * ck.y + r];
+                }
+                pchunk.push_back(make_int4(rowk[0], rowk[1], rowk[2], rowk[3]));
+            }
+            pcls[3 * g + l] = npc;
+        }
     }
+    poff[nb * nb] = (int)pchunk.size();
+    int pxmax = 0;
+    const std::vector<AbBlk> pblk = make_tiles(poff, pcls, pxmax);
     DevTabs &d = c->d;
     d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
     d.abx_col = (int *)dev_alloc(c, sizeof(int) * col.size());
@@ -896,10 +948,13 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
     d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
     d.abx_blk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * blk.size());
+    d.abx_pchunk = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, pchunk.size()));
+    d.pchunk_val = (double *)dev_alloc(c, sizeof(double) * std::max<size_t>(64, pval.size()));
+    d.abx_pblk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * pblk.size());
     d.abx_T = (double *)dev_alloc(c, tbytes);
     d.abx_S = (double *)dev_alloc(c, sbytes);
     if (!d.abx_gofs || !d.abx_col || !d.abx_trow || !d.abx_tq || !d.abx_chunk || !d.abx_ctof || !d.abx_rows || !d.abx_soff || !d.abx_blk ||
-        !d.abx_T || !d.abx_S) {
+        !d.abx_pchunk || !d.pchunk_val || !d.abx_pblk || !d.abx_T || !d.abx_S) {
         set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
     }
@@ -925,11 +980,18 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_soff, soff.data(), sizeof(long long) * soff.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_blk, blk.data(), sizeof(AbBlk) * blk.size(), hipMemcpyHostToDevice, s));
+    if (!pchunk.empty()) {
+        ISCI_HIP(hipMemcpyAsync(d.abx_pchunk, pchunk.data(), sizeof(int4) * pchunk.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(d.pchunk_val, pval.data(), sizeof(double) * pval.size(), hipMemcpyHostToDevice, s));
+    }
+    ISCI_HIP(hipMemcpyAsync(d.abx_pblk, pblk.data(), sizeof(AbBlk) * pblk.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
     c->abx_ntrow = (int)trow.size();
     c->abx_nrows = (int)rows.size();
     c->abx_sbytes = sbytes;
     c->abx_xmax = xmax;
+    c->abx_pxmax = pxmax;
+    c->npchunk = (int)pchunk.size();
     for (int k = 0; k < 3; ++k) c->abx_pcols[k] = pcols[k];
     c->have_abx = true;
     return ISCI_OK;
@@ -1440,7 +1502,7 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         c->sigma_variant = value;
         return ISCI_OK;
     case ISCI_OPT_AB_PRODUCT:
-        if (value != ISCI_AB_PLAIN && value != ISCI_AB_PIPE && value != ISCI_AB_WIDE) {
+        if (value != ISCI_AB_PLAIN && value != ISCI_AB_PIPE && value != ISCI_AB_WIDE && value != ISCI_AB_PACKED) {
             set_error("bad alpha-beta product kernel");
             return ISCI_E_INVALID;
         }

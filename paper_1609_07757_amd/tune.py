@@ -113,7 +113,7 @@ def handle_candidates(hd):
     cands = [((isci.OPT_SIGMA_KERNEL, isci.SIGMA_PAIR),)]
     obk = [isci.ONEBODY_TRANSPOSED, isci.ONEBODY_SINGLE, isci.ONEBODY_SPECTATOR] if hd.norb <= 80 else \
         [isci.ONEBODY_TRANSPOSED]
-    for ab in (isci.AB_WIDE, isci.AB_PLAIN, isci.AB_PIPE):
+    for ab in (isci.AB_PACKED, isci.AB_WIDE, isci.AB_PLAIN, isci.AB_PIPE):
         for ob in obk:
             for st in (isci.ONEBODY_SIDE, isci.ONEBODY_INLINE):
                 cands.append(((isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA), (isci.OPT_AB_PRODUCT, ab),

@@ -265,9 +265,9 @@ def test_ab_path_option():
 @pytest.mark.parametrize("wl,nsamp,nvec", [("cisd_n20", None, 3), ("cisdt_n30", 400, 8), ("fci_n48", 200, 8),
                                             ("cisdt_n60", 200, 5)])
 def test_ab_product_kernels(wl, nsamp, nvec):
-    """Both kernels of the block-sparse alpha-beta product against the
-    oracle, and bit for bit with each other (same K parts, same order within
-    each)."""
+    """The kernels of the block-sparse alpha-beta product against the oracle:
+    8-byte, pipelined and 16-byte loads bit for bit with each other (same K
+    parts, same order within each), the packed chunks to rounding."""
     import paper_1609_07757_amd as isci
     from isci_inputs import workload
     W = workload(wl)
@@ -278,7 +278,7 @@ def test_ab_product_kernels(wl, nsamp, nvec):
     tg = None if nsamp is None else sample_targets(S.rowstart(), S.dim, nsamp, seed=6)
     ref = O.sigma(S, h, eri, W.tau, c, targets=tg)
     outs = []
-    for val in (isci.AB_PLAIN, isci.AB_PIPE, isci.AB_WIDE):
+    for val in (isci.AB_PLAIN, isci.AB_PIPE, isci.AB_WIDE, isci.AB_PACKED):
         isci.isci_set_option(hd, isci.OPT_AB_PRODUCT, val)
         got = gpu_sigma(hd, c)
         outs.append(got)
@@ -287,7 +287,10 @@ def test_ab_product_kernels(wl, nsamp, nvec):
         else:
             ok, err = sampled_ok(got, tg, ref, TOL)
             assert ok, (val, err)
+    # the same chunks in the same order: bit for bit; the packed chunks
+    # group the same products differently: rounding only
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert rel_err(outs[3], outs[0]) <= 1e-13
 
 
 @pytest.mark.parametrize("recipe,norb,L,tau,nvec,nsamp", [("B", 12, 2, 1e-12, 3, None), ("B", 16, 4, 0.0, 5, None),
