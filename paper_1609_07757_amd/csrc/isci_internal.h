@@ -134,6 +134,11 @@ struct DevTabs {
     double *obT_c = nullptr;        // [obT_nv][dim] transposed CI block (beta one-body above kObMaxNorb,
                                     // full-CI alpha one-body)
     double *obT_s = nullptr;        // [obT_nv][dim] its one-body image
+    // the beta columns of level <= L - 2 (every alpha pair present) as rows
+    // [j][alpha string] for up to 8 vectors, their alpha-class image, and
+    // the row starts j * nstr_a of that block
+    double *obS_c = nullptr, *obS_s = nullptr;
+    int64_t *obS_rs = nullptr;
     // density matrices: vectors in the spin-swapped layout (rows = beta
     // strings holding alpha prefixes), allocated by the first density call
     double *d1T = nullptr;          // [kD1Chunk][dim]

@@ -503,6 +503,44 @@ static int max_lds_bytes(const isci_ctx *cx)
     return v;
 }
 
+// The dense block of the first jd beta columns (every alpha row holds
+// them) moved to and from a [j][i] layout, row j being column j of c over
+// all na alpha rows, through 32 x 32 LDS tiles (coalesced both ways):
+//   add = 0: dst[j * na + i]  = src[rowstart[i] + j]
+//   add = 1: dst[rowstart[i] + j] += src[j * na + i]
+// for vector blockIdx.z (src and dst advanced by lsrc and ldst).
+__global__ __launch_bounds__(256) void k_sub_transpose(const int64_t *__restrict__ rowstart, int na, int jd,
+                                                       const double *__restrict__ src, int64_t lsrc,
+                                                       double *__restrict__ dst, int64_t ldst, int add)
+{
+    __shared__ double tile[32][33];
+    const int j0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    src += (int64_t)blockIdx.z * lsrc;
+    dst += (int64_t)blockIdx.z * ldst;
+    if (!add) {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + r, j = j0 + tx;
+            tile[r][tx] = (i < na && j < jd) ? src[rowstart[i] + j] : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int j = j0 + r, i = i0 + tx;
+            if (j < jd && i < na) dst[(int64_t)j * na + i] = tile[tx][r];
+        }
+    } else {
+        for (int r = ty; r < 32; r += 8) {
+            const int j = j0 + r, i = i0 + tx;
+            tile[r][tx] = (j < jd && i < na) ? src[(int64_t)j * na + i] : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + r, j = j0 + tx;
+            if (i < na && j < jd) dst[rowstart[i] + j] += tile[tx][r];
+        }
+    }
+}
+
 template <int NT, int NC>
 static isci_status launch_ob_dense(const isci_ctx *cx, const SigmaArgs &A, int nv, const double *c, int64_t ldc,
                                    double *s, int64_t lds, int jd, size_t shm, hipStream_t st)
@@ -554,7 +592,26 @@ static isci_status launch_ob_alpha(const isci_ctx *cx, const SigmaArgs &A, int n
     const int jd = L >= 2 ? le_b[L - 2] : 0;
     const int jc = L >= 1 ? le_b[L - 1] : 0;
     const int jall = le_b[L];
-    if (jd > 0) {
+    if (jd > 0 && cx->ob_kernel == ISCI_ONEBODY_TRANSPOSED && cx->d.obS_c) {
+        // the columns that hold every alpha pair as rows of their own block
+        // (alpha and beta string tables coincide): the beta kernel there,
+        // then added back; up to 8 vectors a pass
+        const int na = cx->sa.nstr;
+        const int64_t blk = (int64_t)jd * na;
+        SigmaArgs B = A;
+        B.rowstart = cx->d.obS_rs;
+        const dim3 tg((unsigned)((jd + 31) / 32), (unsigned)((na + 31) / 32));
+        for (int u0 = 0; u0 < nv; u0 += 8) {
+            const int nu = nv - u0 < 8 ? nv - u0 : 8;
+            k_sub_transpose<<<dim3(tg.x, tg.y, (unsigned)nu), 256, 0, st>>>(A.rowstart, na, jd, c + (int64_t)u0 * ldc,
+                                                                              ldc, cx->d.obS_c, blk, 0);
+            k_ob_beta_full<NT><<<dim3((unsigned)jd, (unsigned)nu), 64 * NT, 0, st>>>(
+                B, cx->d.obS_c, blk, cx->d.obS_s, blk, cx->d.hscreen, cx->d.hpad, 0, 1);
+            k_sub_transpose<<<dim3(tg.x, tg.y, (unsigned)nu), 256, 0, st>>>(A.rowstart, na, jd, cx->d.obS_s, blk,
+                                                                              s + (int64_t)u0 * lds, lds, 1);
+        }
+        ISCI_HIP(hipGetLastError());
+    } else if (jd > 0) {
         // two columns per workgroup: the pair block of 80 orbitals still
         // fits 64 KB of LDS, and two or three workgroups share a CU
         constexpr int NP = 16 * NT;

@@ -1415,6 +1415,26 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
             c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
             if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
         }
+        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && norb <= kObMaxNorb && !full_pairs && c->L >= 2 &&
+            c->sa.nstr == c->sb.nstr && c->sb.le[c->L - 2] > 0) {
+            // the alpha class on the beta columns that hold every alpha pair,
+            // as the beta class of that block transposed: its scratch
+            const int64_t jd = c->sb.le[c->L - 2], na = c->sa.nstr;
+            c->d.obS_c = (double *)dev_alloc(c, sizeof(double) * 8 * (size_t)(jd * na));
+            c->d.obS_s = (double *)dev_alloc(c, sizeof(double) * 8 * (size_t)(jd * na));
+            c->d.obS_rs = (int64_t *)dev_alloc(c, sizeof(int64_t) * (size_t)(jd + 1));
+            if (!c->d.obS_c || !c->d.obS_s || !c->d.obS_rs) {
+                set_error("device allocation failed (one-body scratch)");
+                st = ISCI_E_OOM;
+            } else {
+                std::vector<int64_t> rs((size_t)jd + 1);
+                for (int64_t j = 0; j <= jd; ++j) rs[(size_t)j] = j * na;
+                hipError_t e5 = hipMemcpyAsync(c->d.obS_rs, rs.data(), sizeof(int64_t) * rs.size(), hipMemcpyHostToDevice,
+                                               stream);
+                if (e5 == hipSuccess) e5 = hipStreamSynchronize(stream);   // rs dies here
+                if (e5 != hipSuccess) st = hip_fail(e5, "one-body block row starts");
+            }
+        }
         if (st == ISCI_OK && c->have_abx && !c->onebody_in_tiles && onebody_mfma_ok(c)) {
             // side stream (default priority) for the one-body classes and a
             // second S buffer, so both 4-vector products run before the
