@@ -509,9 +509,10 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
 #define ISCI_AB_PACKED 3
 /*   ISCI_OPT_ONEBODY_KERNEL (matrix-core one-body classes up to 80
  *   orbitals, for tuning): ISCI_ONEBODY_TRANSPOSED (default) runs the alpha
- *   class, where every beta column holds every alpha pair (full CI), as the
- *   beta class of the transposed block (contiguous rows);
- *   ISCI_ONEBODY_SINGLE takes two columns per workgroup there;
+ *   class on the beta columns that hold every alpha pair (all columns in
+ *   full CI, those of level <= L - 2 otherwise) as the beta class of that
+ *   block transposed (contiguous rows); ISCI_ONEBODY_SINGLE takes two
+ *   columns per workgroup there;
  *   ISCI_ONEBODY_SPECTATOR runs the whole alpha class in the spectator form
  *   used above 80 orbitals (U[a][x][j] = sum_q h_aq T_j[q][x], the rows
  *   {q, x} read directly, no transposes).  Same sigma up to rounding
