@@ -48,6 +48,14 @@
  * (highest orbital compared first).  Row Ia (alpha string) holds the beta
  * strings of level <= L - level(Ia), which is a prefix of the beta order;
  * addr = rowstart(Ia) + index(Ib).
+ *
+ * Two-space GAS restriction (section "Generalized Active Space"): with a
+ * boundary orbital b (n <= b <= norb for both spins) the level of a string
+ * is instead its number of electrons in orbitals >= b, so the space holds
+ * every determinant of the orbitals 0..b-1 (full CI there) with at most L
+ * electrons, alpha plus beta, in the outer space b..norb-1.  b = n per spin
+ * is the CI hierarchy above.  The one-body/same-spin/alpha-beta bucket of a
+ * unit classifies its orbitals as inner (< boundary) or outer.
  */
 #include <math.h>
 #include <stdint.h>
@@ -62,7 +70,7 @@
 #define NBUCKET 42
 
 typedef struct {
-    int norb, n, maxlev;
+    int norb, n, maxlev, bnd;  /* bnd: level = # electrons in orbitals >= bnd */
     int64_t nstr;
     int32_t *orbs;         /* [nstr][n], ascending */
     int32_t *lev;          /* [nstr] */
@@ -97,9 +105,9 @@ static int qsort_cmp(const void *pa, const void *pb)
     return cmp_level_colex(x->o, x->lev, y->o, y->lev, g_cmp_n);
 }
 
-static int build_strings(ostr_t *S, int norb, int n, int maxlev)
+static int build_strings(ostr_t *S, int norb, int n, int maxlev, int bnd)
 {
-    S->norb = norb; S->n = n; S->maxlev = maxlev;
+    S->norb = norb; S->n = n; S->maxlev = maxlev; S->bnd = bnd;
     /* count all n-subsets with level <= maxlev by enumeration */
     int64_t cap = 1024, cnt = 0;
     str_rec *buf = (str_rec *)malloc(sizeof(str_rec) * cap);
@@ -108,7 +116,11 @@ static int build_strings(ostr_t *S, int norb, int n, int maxlev)
     for (int i = 0; i < n; ++i) idx[i] = i;
     for (;;) {
         int lev = 0;
+#if defined(ORC_PLANT_GAS_LEVEL)
         for (int i = 0; i < n; ++i) lev += (idx[i] >= n);
+#else
+        for (int i = 0; i < n; ++i) lev += (idx[i] >= bnd);
+#endif
         if (lev <= maxlev) {
             if (cnt == cap) {
                 cap *= 2;
@@ -154,10 +166,15 @@ static int64_t find_string(const ostr_t *S, const int32_t *o, int lev)
     return -1;
 }
 
-static int level_of(const int32_t *o, int n)
+static int level_of(const int32_t *o, int n, int bnd)
 {
     int l = 0;
+#if defined(ORC_PLANT_GAS_LEVEL)
+    (void)bnd;
     for (int i = 0; i < n; ++i) l += (o[i] >= n);
+#else
+    for (int i = 0; i < n; ++i) l += (o[i] >= bnd);
+#endif
     return l;
 }
 
@@ -242,13 +259,17 @@ static inline double gh(const double *h, int n, int p, int q)
 /* ------------------------------------------------------------------ */
 /* space                                                              */
 
-static int space_init(ospace_t *S, int norb, int na, int nb, int L)
+/* bnd = 0: the CI hierarchy (boundary n per spin); else the two-space
+ * restriction with boundary orbital bnd, max(na, nb) <= bnd <= norb */
+static int space_init(ospace_t *S, int norb, int na, int nb, int L, int bnd)
 {
     memset(S, 0, sizeof(*S));
     if (norb < 1 || na < 0 || nb < 0 || na > norb || nb > norb || L < 0) return -1;
     if (na > OMAXN || nb > OMAXN || norb >= OSPIN) return -1;
+    if (bnd != 0 && (bnd < na || bnd < nb || bnd > norb)) return -1;
     S->norb = norb; S->na = na; S->nb = nb; S->L = L;
-    if (build_strings(&S->a, norb, na, L) || build_strings(&S->b, norb, nb, L)) return -1;
+    if (build_strings(&S->a, norb, na, L, bnd ? bnd : na) || build_strings(&S->b, norb, nb, L, bnd ? bnd : nb))
+        return -1;
     S->bprefix = (int64_t *)calloc((size_t)L + 2, sizeof(int64_t));
     for (int64_t k = 0; k < S->b.nstr; ++k)
         for (int l = S->b.lev[k]; l <= L; ++l) S->bprefix[l]++;
@@ -282,7 +303,7 @@ static int64_t row_of(const ospace_t *S, int64_t t)
 /* address of (alpha orbitals, beta orbitals) or -1 if outside the space */
 static int64_t address(const ospace_t *S, const int32_t *ao, const int32_t *bo)
 {
-    int la = level_of(ao, S->na), lb = level_of(bo, S->nb);
+    int la = level_of(ao, S->na, S->a.bnd), lb = level_of(bo, S->nb, S->b.bnd);
     if (la + lb > S->L) return -1;
     int64_t ia = find_string(&S->a, ao, la), ib = find_string(&S->b, bo, lb);
     if (ia < 0 || ib < 0) return -1;
@@ -348,6 +369,7 @@ static void keys_of(const int32_t *ao, int na, const int32_t *bo, int nb, int *k
 static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn, void *ctx)
 {
     const int n = S->norb, na = S->na, nb = S->nb;
+    const int ba = S->a.bnd, bb = S->b.bnd;   /* bucket classification: inner / outer */
     int64_t ia = row_of(S, t), ib = t - S->rowstart[ia];
     const int32_t *A = S->a.orbs + ia * na, *B = S->b.orbs + ib * nb;
     int ikeys[2 * OMAXN], jkeys[2 * OMAXN];
@@ -355,25 +377,25 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
     const double *h = I->h, *eri = I->eri;
 
     /* ---- diagonal ---- */
-    for (int i = 0; i < na; ++i) emit(fn, ctx, I, t, 1, gh(h, n, A[i], A[i]), b_one(0, A[i], A[i], na));
-    for (int i = 0; i < nb; ++i) emit(fn, ctx, I, t, 1, gh(h, n, B[i], B[i]), b_one(1, B[i], B[i], nb));
+    for (int i = 0; i < na; ++i) emit(fn, ctx, I, t, 1, gh(h, n, A[i], A[i]), b_one(0, A[i], A[i], ba));
+    for (int i = 0; i < nb; ++i) emit(fn, ctx, I, t, 1, gh(h, n, B[i], B[i]), b_one(1, B[i], B[i], bb));
     for (int i = 0; i < na; ++i)
         for (int j = i + 1; j < na; ++j) {
             int p = A[i], q = A[j];
             emit(fn, ctx, I, t, 1, geri(eri, n, p, p, q, q) - geri(eri, n, p, q, q, p),
-                 b_ss(0, p, q, p, q, na));
+                 b_ss(0, p, q, p, q, ba));
         }
     for (int i = 0; i < nb; ++i)
         for (int j = i + 1; j < nb; ++j) {
             int p = B[i], q = B[j];
             emit(fn, ctx, I, t, 1, geri(eri, n, p, p, q, q) - geri(eri, n, p, q, q, p),
-                 b_ss(1, p, q, p, q, nb));
+                 b_ss(1, p, q, p, q, bb));
         }
 #if !defined(ORC_PLANT_DROP_AB_DIAG)
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nb; ++j)
             emit(fn, ctx, I, t, 1, geri(eri, n, A[i], A[i], B[j], B[j]),
-                 b_ab(A[i], A[i], B[j], B[j], na, nb));
+                 b_ab(A[i], A[i], B[j], B[j], ba, bb));
 #endif
 
     int32_t J[OMAXN];
@@ -382,6 +404,7 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
         const int32_t *X = spin ? B : A;          /* string that changes */
         const int32_t *Y = spin ? A : B;          /* other spin, spectator */
         int nx = spin ? nb : na, ny = spin ? na : nb;
+        int bx = spin ? bb : ba;
         for (int i = 0; i < nx; ++i) {
             int p = X[i];
             for (int q = 0; q < n; ++q) {
@@ -397,7 +420,7 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
 #if defined(ORC_PLANT_SINGLE_NOSIGN)
                 sg = 1;
 #endif
-                emit(fn, ctx, I, jaddr, sg, gh(h, n, p, q), b_one(spin, p, q, nx));
+                emit(fn, ctx, I, jaddr, sg, gh(h, n, p, q), b_one(spin, p, q, bx));
                 for (int k = 0; k < nx; ++k) {
                     int kk = X[k];
                     if (kk == p) continue;        /* common occupied, same spin */
@@ -406,12 +429,12 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
 #endif
                     emit(fn, ctx, I, jaddr, sg,
                          geri(eri, n, p, q, kk, kk) - geri(eri, n, p, kk, kk, q),
-                         b_ss(spin, p, kk, q, kk, nx));
+                         b_ss(spin, p, kk, q, kk, bx));
                 }
                 for (int k = 0; k < ny; ++k) {
                     int kk = Y[k];
                     emit(fn, ctx, I, jaddr, sg, geri(eri, n, p, q, kk, kk),
-                         spin ? b_ab(kk, kk, p, q, na, nb) : b_ab(p, q, kk, kk, na, nb));
+                         spin ? b_ab(kk, kk, p, q, ba, bb) : b_ab(p, q, kk, kk, ba, bb));
                 }
             }
         }
@@ -422,6 +445,7 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
     for (int spin = 0; spin < 2; ++spin) {
         const int32_t *X = spin ? B : A;
         int nx = spin ? nb : na;
+        int bx = spin ? bb : ba;
         int off = spin ? OSPIN : 0;
         for (int i = 0; i < nx; ++i)
             for (int j = i + 1; j < nx; ++j) {
@@ -442,11 +466,11 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
 #if defined(ORC_PLANT_SS_EXCHANGE)
                         emit(fn, ctx, I, jaddr, sg,
                              geri(eri, n, p, q, r, s) + geri(eri, n, p, s, r, q),
-                             b_ss(spin, p, r, q, s, nx));
+                             b_ss(spin, p, r, q, s, bx));
 #else
                         emit(fn, ctx, I, jaddr, sg,
                              geri(eri, n, p, q, r, s) - geri(eri, n, p, s, r, q),
-                             b_ss(spin, p, r, q, s, nx));
+                             b_ss(spin, p, r, q, s, bx));
 #endif
                     }
                 }
@@ -476,9 +500,9 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
                     sg = -sg;
 #endif
 #if defined(ORC_PLANT_AB_INDEX)
-                    emit(fn, ctx, I, jaddr, sg, geri(eri, n, p, r, q, s), b_ab(p, q, r, s, na, nb));
+                    emit(fn, ctx, I, jaddr, sg, geri(eri, n, p, r, q, s), b_ab(p, q, r, s, ba, bb));
 #else
-                    emit(fn, ctx, I, jaddr, sg, geri(eri, n, p, q, r, s), b_ab(p, q, r, s, na, nb));
+                    emit(fn, ctx, I, jaddr, sg, geri(eri, n, p, q, r, s), b_ab(p, q, r, s, ba, bb));
 #endif
                 }
             }
@@ -489,13 +513,15 @@ static void visit_row(const ospace_t *S, const oints_t *I, int64_t t, unit_fn fn
 /* ------------------------------------------------------------------ */
 /* exported API (ctypes)                                               */
 
-void *orc_space_create(int norb, int na, int nb, int L)
+void *orc_space_create_gas(int norb, int na, int nb, int L, int bnd)
 {
     ospace_t *S = (ospace_t *)calloc(1, sizeof(ospace_t));
     if (!S) return NULL;
-    if (space_init(S, norb, na, nb, L)) { space_free(S); free(S); return NULL; }
+    if (space_init(S, norb, na, nb, L, bnd)) { space_free(S); free(S); return NULL; }
     return S;
 }
+
+void *orc_space_create(int norb, int na, int nb, int L) { return orc_space_create_gas(norb, na, nb, L, 0); }
 
 void orc_space_destroy(void *h) { if (h) { space_free((ospace_t *)h); free(h); } }
 int64_t orc_space_dim(void *h) { return ((ospace_t *)h)->dim; }

@@ -5,7 +5,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity status:
 * ``Space`` (strings, levels, row starts, addresses): pinned by the
   closed-form space dimension, which reproduces the paper's table of
   determinant counts (application section, table of orbitals and
-  coefficients), and by brute-force enumeration in the tests.
+  coefficients), and by brute-force enumeration in the tests.  With a
+  two-space boundary (section "Generalized Active Space"): by brute-force
+  filtering of every determinant by its outer-space electron count and the
+  matching closed form; the boundary-level count is checked by a planted
+  mistake (level counted from n) that these pins reject.
+* ``sigma`` / ``dense_h`` / ``diag`` on two-space spaces: pinned as the
+  restriction of the pinned full-CI matrix to the space's determinants, by
+  the full CI of the cut integrals when no outer electron is allowed, and
+  by variational nesting in the outer-electron limit.
 * ``sigma`` / ``dense_h``: pinned by the closed-form reference energy,
   Hermiticity, the non-interacting limit, the one-electron-per-spin
   Kronecker construction, orbital-rotation invariance of FCI, alpha/beta
@@ -79,6 +87,8 @@ def lib():
         L = ctypes.CDLL(LIBPATH)
         L.orc_space_create.restype = ctypes.c_void_p
         L.orc_space_create.argtypes = [ctypes.c_int] * 4
+        L.orc_space_create_gas.restype = ctypes.c_void_p
+        L.orc_space_create_gas.argtypes = [ctypes.c_int] * 5
         L.orc_space_destroy.argtypes = [ctypes.c_void_p]
         L.orc_space_dim.restype = _i64
         L.orc_space_dim.argtypes = [ctypes.c_void_p]
@@ -122,11 +132,17 @@ class Space:
 
     Strings per spin: ascending orbital sets sorted by (excitation level,
     colex); row Ia holds the beta strings of level <= L - level(Ia).
+
+    ``boundary`` (section "Generalized Active Space", two spaces): if given,
+    a string's level is its number of electrons in orbitals >= boundary
+    instead of >= n, so the space is the full CI of the orbitals below the
+    boundary with at most ``level`` electrons (alpha plus beta) above it.
     """
 
-    def __init__(self, norb: int, nalpha: int, nbeta: int, level: int):
+    def __init__(self, norb: int, nalpha: int, nbeta: int, level: int, boundary: int | None = None):
         self.norb, self.nalpha, self.nbeta, self.level = norb, nalpha, nbeta, level
-        self._h = lib().orc_space_create(norb, nalpha, nbeta, level)
+        self.boundary = boundary
+        self._h = lib().orc_space_create_gas(norb, nalpha, nbeta, level, int(boundary or 0))
         if not self._h:
             raise ValueError("invalid space")
         self.dim = int(lib().orc_space_dim(self._h))
@@ -278,14 +294,17 @@ def bucket_names():
     return names
 
 
-def dim_closed_form(norb: int, nalpha: int, nbeta: int, level: int) -> int:
-    """sum over ka + kb <= level of C(na,ka) C(norb-na,ka) C(nb,kb) C(norb-nb,kb)."""
+def dim_closed_form(norb: int, nalpha: int, nbeta: int, level: int, boundary: int | None = None) -> int:
+    """sum over ka + kb <= level of C(ba,na-ka) C(norb-ba,ka) C(bb,nb-kb) C(norb-bb,kb),
+    with the boundary b_sigma = n_sigma (the CI hierarchy) unless given."""
+    ba = nalpha if boundary is None else boundary
+    bb = nbeta if boundary is None else boundary
     tot = 0
     for ka in range(0, nalpha + 1):
         for kb in range(0, nbeta + 1):
             if ka + kb <= level:
-                tot += (comb(nalpha, ka) * comb(norb - nalpha, ka)
-                        * comb(nbeta, kb) * comb(norb - nbeta, kb))
+                tot += (comb(ba, nalpha - ka) * comb(norb - ba, ka)
+                        * comb(bb, nbeta - kb) * comb(norb - bb, kb))
     return tot
 
 

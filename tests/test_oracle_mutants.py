@@ -19,10 +19,11 @@ MUTANTS = [
     "ORC_PLANT_KEEP_GE",          # keep rule |I| >= tau instead of |I| > tau
     "ORC_PLANT_DIAG_ROWSUM",      # diagonal: the j == I filter dropped (whole row summed)
     "ORC_PLANT_DIAG_UNSCREENED",  # diagonal: screened units counted
+    "ORC_PLANT_GAS_LEVEL",        # two-space restriction: level counted from n, not the boundary
 ]
 
 PINS = ("reference_energy or hermiticity or noninteracting or kronecker or rotation "
-        "or swap or strict or term_counts_integral or diag_")
+        "or swap or strict or term_counts_integral or diag_ or gas_")
 
 
 @pytest.mark.parametrize("macro", MUTANTS)

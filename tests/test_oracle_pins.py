@@ -350,13 +350,15 @@ def test_strict_threshold():
 
 
 # ---------------------------------------------------------------- P12
-def _integral_driven_counts(h, eri, norb, L, tau):
+def _integral_driven_counts(h, eri, norb, L, tau, boundary=None):
     """Independent count for na = nb = 2, written in the paper's loop
-    order: integral indices outside, spectator strings inside."""
+    order: integral indices outside, spectator strings inside.  A string's
+    level counts its electrons in orbitals >= boundary (default n)."""
     n = 2
-    e = (np.arange(norb) >= n).astype(int)
+    b = n if boundary is None else boundary
+    e = (np.arange(norb) >= b).astype(int)
     # number of beta strings with level <= l
-    nb_le = [sum(comb(n, n - k) * comb(norb - n, k) for k in range(0, min(l, 2) + 1)) if l >= 0 else 0
+    nb_le = [sum(comb(b, n - k) * comb(norb - b, k) for k in range(0, min(l, 2) + 1)) if l >= 0 else 0
              for l in range(0, 5)]
 
     def nble(l):
@@ -733,3 +735,111 @@ def test_mask_by_distance_brute_force_and_limits():
     hb, eb = O.mask_by_distance(h, eri, np.maximum(da, da.T), 3.0)
     assert np.array_equal(ha, hb) and np.array_equal(ea, eb)
     assert np.array_equal(ea, ea.transpose(1, 0, 2, 3)) and np.array_equal(ea, ea.transpose(2, 3, 0, 1))
+
+
+# ---------------------------------------------------------------- GAS (two spaces)
+# Section "Generalized Active Space": the orbitals split at a boundary b
+# into an inner space 0..b-1 (full CI there) and an outer space b..norb-1
+# holding at most L electrons, alpha plus beta.  b = n is the CI hierarchy.
+_GAS_SPACES = [(8, 2, 2, 1, 4), (8, 2, 2, 2, 3), (8, 2, 2, 0, 5), (9, 3, 2, 1, 4),
+               (7, 2, 2, 3, 4), (7, 2, 1, 2, 5), (7, 2, 2, 1, 7), (6, 0, 2, 1, 3)]
+
+
+def _brute_gas(norb, na, nb, L, b):
+    out = []
+    for a in combinations(range(norb), na):
+        for bb in combinations(range(norb), nb):
+            if sum(x >= b for x in a) + sum(x >= b for x in bb) <= L:
+                out.append((a, bb))
+    return out
+
+
+@pytest.mark.parametrize("norb,na,nb,L,b", _GAS_SPACES)
+def test_gas_layout_brute_force(norb, na, nb, L, b):
+    """The space is exactly the determinants with at most L electrons in
+    the outer orbitals, each once; strings in (outer count, colex) order;
+    rows hold prefixes of the beta order; the closed form counts it."""
+    S = O.Space(norb, na, nb, L, boundary=b)
+    dets = S.determinants()
+    brute = _brute_gas(norb, na, nb, L, b)
+    assert S.dim == len(brute) == len(set(dets)) == O.dim_closed_form(norb, na, nb, L, boundary=b)
+    assert set(dets) == set(brute)
+    ao, _ = S.strings(0)
+    bo, _ = S.strings(1)
+    key = lambda r: (sum(int(x) >= b for x in r), tuple(sorted((int(x) for x in r), reverse=True)))
+    assert [key(r) for r in ao] == sorted(key(r) for r in ao)
+    assert [key(r) for r in bo] == sorted(key(r) for r in bo)
+    for i, (a, bb) in enumerate(dets):
+        assert S.address(a, bb) == i
+
+
+def test_gas_boundary_at_n_is_the_hierarchy_and_at_norb_is_fci():
+    for norb, na, nb, L in [(8, 2, 2, 2), (7, 3, 2, 3)]:
+        S, G = O.Space(norb, na, nb, L), O.Space(norb, na, nb, L, boundary=max(na, nb))
+        if na == nb:
+            assert S.determinants() == G.determinants()
+    F = O.Space(7, 2, 2, 4)
+    for L in (0, 1, 3):
+        assert O.Space(7, 2, 2, L, boundary=7).dim == F.dim
+    with pytest.raises(ValueError):
+        O.Space(7, 3, 2, 1, boundary=2)        # boundary below an electron count
+    with pytest.raises(ValueError):
+        O.Space(7, 2, 2, 1, boundary=8)
+
+
+@pytest.mark.parametrize("recipe", ["B", "R"])
+@pytest.mark.parametrize("norb,na,nb,L,b", [(8, 2, 2, 1, 4), (7, 2, 2, 2, 3), (7, 3, 2, 1, 4)])
+@pytest.mark.parametrize("tau", [0.0, 1e-3])
+def test_gas_h_is_the_fci_submatrix(recipe, norb, na, nb, L, b, tau):
+    """A matrix element depends only on its two determinants: the GAS
+    Hamiltonian (dense, sigma and diagonal) is the full-CI one restricted
+    to the GAS determinants (the full-CI H is pinned by the closed forms,
+    the noninteracting and one-electron limits and rotation invariance)."""
+    h, eri = _ints(recipe, norb, 11)
+    G = O.Space(norb, na, nb, L, boundary=b)
+    F = O.Space(norb, na, nb, na + nb)
+    idx = np.array([F.address(a, bb) for a, bb in G.determinants()])
+    HF = O.dense_h(F, h, eri, tau)
+    HG = O.dense_h(G, h, eri, tau)
+    assert np.array_equal(HG, HF[np.ix_(idx, idx)])
+    c = random_vectors(G.dim, 2, 4)
+    assert np.allclose(O.sigma(G, h, eri, tau, c), c @ HF[np.ix_(idx, idx)].T, rtol=0, atol=1e-12)
+    # the diagonal is summed in long double, the dense matrix in double
+    assert np.allclose(O.diag(G, h, eri, tau), np.diag(HF)[idx], rtol=0, atol=1e-13 * np.abs(HF).max())
+
+
+def test_gas_no_outer_electrons_is_inner_fci():
+    """L = 0 keeps every electron in the inner orbitals: the spectrum is the
+    full CI of the integrals cut to those orbitals (a smaller problem built
+    independently)."""
+    h, eri = recipe_b(9, seed=2)
+    b = 5
+    G = O.Space(9, 2, 2, 0, boundary=b)
+    F = O.Space(b, 2, 2, 4)
+    eg = np.linalg.eigvalsh(O.dense_h(G, h, eri, 0.0))
+    ef = np.linalg.eigvalsh(O.dense_h(F, h[:b, :b].copy(), eri[:b, :b, :b, :b].copy(), 0.0))
+    assert G.dim == F.dim
+    assert np.allclose(eg, ef, rtol=0, atol=1e-12)
+
+
+def test_gas_variational_nesting():
+    """Spaces nested by L give non-increasing lowest energies (Cauchy
+    interlacing), equal to full CI once L reaches every electron."""
+    h, eri = recipe_a(8, seed=1)
+    b = 4
+    e = [np.linalg.eigvalsh(O.dense_h(O.Space(8, 2, 2, L, boundary=b), h, eri, 0.0))[0] for L in range(5)]
+    ef = np.linalg.eigvalsh(O.dense_h(O.Space(8, 2, 2, 4), h, eri, 0.0))[0]
+    assert all(e[i + 1] <= e[i] + 1e-12 for i in range(4))
+    assert e[0] > e[-1] + 1e-6
+    assert abs(e[-1] - ef) <= 1e-12
+
+
+@pytest.mark.parametrize("recipe,norb,L,b,tau", [("R", 7, 1, 4, 0.0), ("B", 8, 2, 3, 1e-3), ("A", 8, 1, 5, 1e-6)])
+def test_gas_term_counts_integral_driven(recipe, norb, L, b, tau):
+    h, eri = _ints(recipe, norb, 3)
+    S = O.Space(norb, 2, 2, L, boundary=b)
+    kept, _ = O.terms(S, h, eri, tau)
+    one, ss, ab = _integral_driven_counts(h, eri, norb, L, tau, boundary=b)
+    assert kept[0:8].sum() == one
+    assert kept[8:26].sum() == ss
+    assert kept[26:42].sum() == ab
