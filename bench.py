@@ -102,7 +102,8 @@ def main():
     h, eri = W.integrals()
     hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), W.norb,
                           W.nalpha, W.nbeta, W.level, tau,
-                          onebody={"auto": isci.OB_AUTO, "separate": isci.OB_SEPARATE, "tiles": isci.OB_TILES}[a.ob_place])
+                          onebody={"auto": isci.OB_AUTO, "separate": isci.OB_SEPARATE, "tiles": isci.OB_TILES}[a.ob_place],
+                          gas_boundary=W.gas_boundary)
     variant = {"auto": isci.SIGMA_AUTO, "general": isci.SIGMA_GENERAL, "pair": isci.SIGMA_PAIR,
                "mfma": isci.SIGMA_MFMA}[a.kernel]
     isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
@@ -223,7 +224,8 @@ def main():
         "config": {"workload": a.workload, "norb": W.norb, "nalpha": W.nalpha, "nbeta": W.nbeta,
                    "max_excitation": W.level, "tau": tau, "nvec": nvec, "dim": dim,
                    "box": W.box_len, "naux": W.n_aux, "seed": W.seed, "ab_product": a.ab,
-                   "onebody_kernel": a.onebody, "onebody_stream": a.onebody_stream},
+                   "onebody_kernel": a.onebody, "onebody_stream": a.onebody_stream,
+                   **({"gas_boundary": W.gas_boundary} if W.gas_boundary else {})},
         "screened_terms_per_s": terms_per_s,
         "terms_per_vector": terms,
         "kept_integral_units": int(st["kept_total"]),
@@ -308,7 +310,7 @@ def cpu_baseline(W, h, eri, tau, nvec, dim, seconds):
     import numpy as np
     import oracle as O
     from isci_inputs import random_vectors
-    S = O.Space(W.norb, W.nalpha, W.nbeta, W.level)
+    S = O.Space(W.norb, W.nalpha, W.nbeta, W.level, boundary=W.gas_boundary or None)
     c = random_vectors(dim, nvec, seed=21)
     rng = np.random.default_rng(0)
     n = 64
@@ -337,7 +339,8 @@ def cpu_baseline_one_core(W, tau, nvec, dim, ntarget, seconds):
     import subprocess
     code = ("import sys, time, json, numpy as np; sys.path.insert(0, %r); import oracle as O; "
             "from isci_inputs import random_vectors, workload; W = workload(%r); h, eri = W.integrals(); "
-            "S = O.Space(W.norb, W.nalpha, W.nbeta, W.level); c = random_vectors(%d, %d, seed=21); "
+            "S = O.Space(W.norb, W.nalpha, W.nbeta, W.level, boundary=W.gas_boundary or None); "
+            "c = random_vectors(%d, %d, seed=21); "
             "rng = np.random.default_rng(1); n = %d\n"
             "while True:\n"
             "    tg = np.sort(rng.choice(%d, size=min(n, %d), replace=False)); t0 = time.perf_counter(); "

@@ -186,7 +186,26 @@ typedef struct {
                                          struct is copied at creation */
     const double *orb_dist;           /* host [norb][norb] or NULL (no distance screening) */
     double max_dist;                  /* distance screening radius; 0: off */
+    int gas_boundary;                 /* two-space GAS restriction (below); 0: off */
 } isci_create_opts;
+
+/* Two-space GAS restriction (section "Generalized Active Space"; the
+ * restriction to at most one electron in the continuum in the appendix on
+ * CAAB types): with gas_boundary = b, max(nalpha, nbeta) <= b <= norb, the
+ * orbitals split into an inner space 0..b-1 and an outer space b..norb-1,
+ * a string's level is its number of electrons in the outer space, and
+ * max_excitation limits the outer electrons, alpha plus beta.  The space is
+ * then every determinant of the inner orbitals (full CI there) with at most
+ * max_excitation electrons in the outer ones; b = n_sigma for both spins is
+ * the excitation hierarchy of Eq. ci_hierarchy (the default, 0).  The
+ * layout is unchanged in form: strings sorted by (level, colex), the row of
+ * a level-k alpha string holding the beta strings of level <= L - k.  Such
+ * a handle runs sigma on the pair-table kernel (two electrons per spin) or
+ * the general-string kernel (the matrix-core path, whose operand blocks
+ * take orbitals 0 and 1 as the occupied block, is not built for it); the
+ * densities (isci_density1, isci_density1_noalloc, isci_density2) return
+ * ISCI_E_UNSUPPORTED.  ISCI_E_INVALID for b outside [max(nalpha, nbeta),
+ * norb]. */
 
 /* isci_create with build options; opts may be NULL (defaults).  Returns
  * ISCI_E_INVALID for an unknown onebody value or an allocator with a NULL

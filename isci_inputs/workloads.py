@@ -28,6 +28,11 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
     @property
+    def gas_boundary(self) -> int:
+        """Two-space GAS boundary orbital (0: the excitation hierarchy)."""
+        return int(self.extra.get("gas_boundary", 0))
+
+    @property
     def box_len(self) -> float:
         return float(self.norb) if self.box is None else float(self.box)
 
@@ -53,6 +58,11 @@ WORKLOADS = {
     "cisdt_n160": Workload("cisdt_n160", norb=160, level=3, tau=1e-12, nvec=4),
     # CISDTQ = FCI for 4 electrons, 48 orbitals, 8 simultaneous vectors
     "fci_n48": Workload("fci_n48", norb=48, level=4, tau=1e-14, nvec=8),
+    # two-space GAS: full CI in the 16 lowest orbitals, at most one electron
+    # in the 184 above them (the single-continuum-electron restriction),
+    # 200 orbitals in a 200 bohr box, tau 1e-12, 8 vectors
+    "gas1_n200": Workload("gas1_n200", norb=200, level=1, tau=1e-12, nvec=8,
+                          extra={"gas_boundary": 16}),
 }
 
 

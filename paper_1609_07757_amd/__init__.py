@@ -118,7 +118,7 @@ def torch_allocator():
     return _lib.IsciAllocator(_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free), None)
 
 
-def _create_opts(onebody, allocator, orb_dist, max_dist, norb):
+def _create_opts(onebody, allocator, orb_dist, max_dist, norb, gas_boundary=0):
     if isinstance(allocator, str):
         if allocator != "torch":
             raise ValueError("allocator must be None, 'torch' or an IsciAllocator")
@@ -130,24 +130,26 @@ def _create_opts(onebody, allocator, orb_dist, max_dist, norb):
             raise ValueError("orb_dist must be [norb, norb]")
     opts = _lib.IsciCreateOpts(int(onebody), ctypes.pointer(allocator) if allocator is not None else None,
                                dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dist is not None else None,
-                               float(max_dist))
+                               float(max_dist), int(gas_boundary or 0))
     return opts, allocator, dist
 
 
 def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
-                stream=None, onebody: int = OB_AUTO, allocator=None, orb_dist=None, max_dist: float = 0.0) -> Handle:
+                stream=None, onebody: int = OB_AUTO, allocator=None, orb_dist=None, max_dist: float = 0.0,
+                gas_boundary: int = 0) -> Handle:
     """Build a handle (isci_create_ex; onebody is one of OB_*).  allocator:
     None (hipMalloc), "torch" (torch's caching allocator) or an
     _lib.IsciAllocator.  orb_dist (host [norb, norb]) with max_dist > 0:
     distance screening (units whose orbitals are not all within max_dist
-    are removed)."""
+    are removed).  gas_boundary b > 0: the two-space GAS restriction (full
+    CI of orbitals 0..b-1, at most max_excitation electrons in b..norb-1)."""
     L = _lib.load()
     hp = _dev_f64(h, "h")
     ep = _dev_f64(eri, "eri")
     if h.numel() != norb * norb or eri.numel() != norb ** 4:
         raise ValueError("h must hold norb^2 and eri norb^4 elements")
     out = ctypes.c_void_p()
-    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb)
+    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb, gas_boundary)
     st = L.isci_create_ex(ctypes.byref(out), hp, ep, int(norb), int(nalpha), int(nbeta),
                           int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create")
@@ -156,7 +158,7 @@ def isci_create(h, eri, norb: int, nalpha: int, nbeta: int, max_excitation: int,
 
 def isci_create_factored(h, Lfac, norb: int, nalpha: int, nbeta: int, max_excitation: int, tau: float,
                          stream=None, onebody: int = OB_AUTO, allocator=None, orb_dist=None,
-                         max_dist: float = 0.0) -> Handle:
+                         max_dist: float = 0.0, gas_boundary: int = 0) -> Handle:
     """Build a handle from factored integrals (pq|rs) = sum_K L^K_pq L^K_rs,
     Lfac of shape [naux, norb, norb] on the device, with no dense norb^4
     tensor (isci_create_factored)."""
@@ -166,7 +168,7 @@ def isci_create_factored(h, Lfac, norb: int, nalpha: int, nbeta: int, max_excita
     if h.numel() != norb * norb or Lfac.dim() != 3 or tuple(Lfac.shape[1:]) != (norb, norb):
         raise ValueError("h must hold norb^2 elements and Lfac be [naux, norb, norb]")
     out = ctypes.c_void_p()
-    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb)
+    opts, allocator, _dist = _create_opts(onebody, allocator, orb_dist, max_dist, norb, gas_boundary)
     st = L.isci_create_factored(ctypes.byref(out), hp, lp, int(Lfac.shape[0]), int(norb), int(nalpha), int(nbeta),
                                 int(max_excitation), float(tau), ctypes.byref(opts), _stream_ptr(stream))
     check(st, "isci_create_factored")

@@ -66,7 +66,8 @@ class IsciAllocator(ctypes.Structure):
 class IsciCreateOpts(ctypes.Structure):
     """isci_create_opts."""
     _fields_ = [("onebody", ctypes.c_int), ("allocator", ctypes.POINTER(IsciAllocator)),
-                ("orb_dist", ctypes.POINTER(ctypes.c_double)), ("max_dist", ctypes.c_double)]
+                ("orb_dist", ctypes.POINTER(ctypes.c_double)), ("max_dist", ctypes.c_double),
+                ("gas_boundary", ctypes.c_int)]
 
 
 class IsciDavidsonOpts(ctypes.Structure):

@@ -78,12 +78,12 @@ __device__ inline uint32_t binom_small(int x, int k)
 // the library's string tables, with the closed-form binomials.
 __device__ inline int rank_small(const int *o, const SpinTab &T)
 {
-    const int n = T.n;
+    const int n = T.n, b = T.nocc;
     int ip = 0, io = 0;
     uint32_t rp = 0, ro = 0;
     for (int i = 0; i < n; ++i) {
         const int x = o[i];
-        if (x >= n) { ++ip; rp += binom_small(x - n, ip); }
+        if (x >= b) { ++ip; rp += binom_small(x - b, ip); }
         else        { ++io; ro += binom_small(x, io); }
     }
     return T.lev_off[ip] + (int)(rp * (uint32_t)T.occ_mult[ip] + ro);
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
                     str[a++] = S[i];
                 }
                 if (!put) str[a++] = q;
-                const int lev = str_level(str, n);
+                const int lev = str_level(str, n, A.sa.nocc);
                 if (lev <= A.sa.maxlev) {
                     len = A.sb.le[A.L - lev];
                     off = row_start(A.sa, A.sb, A.L, rank_small(str, A.sa), lev);
@@ -555,6 +555,12 @@ isci_status density_args(isci_handle h, int nvec, const double *c, int64_t ldc, 
     const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
     const char *d0 = (const char *)d1, *e1 = (const char *)(d1 + nd);
     if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
+    if (h->gas_bnd) {
+        // the Gram form takes the longer rows of a spectator set to be those
+        // of its at most n inner orbitals (the hierarchy's occupied ones)
+        set_error("isci_density1: not built for a GAS-restricted handle");
+        return ISCI_E_UNSUPPORTED;
+    }
     if (h->nb > 0) {
         // the spin-swapped layout (rows = beta strings) holds every determinant
         int64_t tot = 0;
@@ -647,6 +653,10 @@ isci_status isci_density2(isci_handle h, int nvec, const double *c, int64_t ldc,
         const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
         const char *d0 = (const char *)d2, *e1 = (const char *)(d2 + (int64_t)nvec * 3 * n4);
         if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
+    }
+    if (h->gas_bnd) {
+        set_error("isci_density2: not built for a GAS-restricted handle");
+        return ISCI_E_UNSUPPORTED;
     }
     if (h->na != 2 || h->nb != 2) {
         set_error("isci_density2: two electrons of each spin only");

@@ -34,23 +34,24 @@ __host__ __device__ inline uint32_t pack_str(const int *o, int n)
     return s;
 }
 
-// level = number of electrons in orbitals >= n
-__host__ __device__ inline int str_level(const int *o, int n)
+// level = number of electrons in orbitals >= b (b = n: excitation level;
+// a GAS boundary: electrons in the outer space)
+__host__ __device__ inline int str_level(const int *o, int n, int b)
 {
     int l = 0;
-    for (int i = 0; i < n; ++i) l += (o[i] >= n);
+    for (int i = 0; i < n; ++i) l += (o[i] >= b);
     return l;
 }
 
 // index of an ascending orbital list in (level, colex) order
 __host__ __device__ inline int str_index(const int *o, const SpinTab &T)
 {
-    const int n = T.n;
+    const int n = T.n, b = T.nocc;
     int ip = 0, io = 0;
     long long rp = 0, ro = 0;
     for (int i = 0; i < n; ++i) {
         int x = o[i];
-        if (x >= n) { ++ip; rp += binom(x - n, ip); }
+        if (x >= b) { ++ip; rp += binom(x - b, ip); }
         else        { ++io; ro += binom(x, io); }
     }
     return T.lev_off[ip] + (int)(rp * T.occ_mult[ip] + ro);

@@ -19,17 +19,19 @@ namespace isci {
 // Binomial table C(x, k) for x < 256, k <= ISCI_MAXN (+1 for counting).
 constexpr int kBinomK = ISCI_MAXN + 1;
 
-// Strings of one spin, sorted by (level, colex).  Within level k the
-// index is lev_off[k] + colexrank(particles - n) * C(n, n - k)
-// + colexrank(kept occupied), colexrank({e_1 < ... < e_m}) = sum C(e_i, i).
+// Strings of one spin, sorted by (level, colex).  The level is the number
+// of electrons in orbitals >= nocc (nocc = n: the excitation level; a GAS
+// boundary b: the outer-space electrons).  Within level k the index is
+// lev_off[k] + colexrank(outer orbitals - nocc) * C(nocc, n - k)
+// + colexrank(inner orbitals), colexrank({e_1 < ... < e_m}) = sum C(e_i, i).
 struct SpinTab {
     int n;                       // electrons of this spin
-    int nocc;                    // reference occupied orbitals (= n)
-    int nvirt;                   // norb - n
+    int nocc;                    // level boundary: orbitals below it are inner (= n, or the GAS boundary)
+    int nvirt;                   // norb - nocc
     int maxlev;                  // highest level present (<= L)
     int nstr;                    // number of strings with level <= maxlev
     int lev_off[ISCI_MAXLEV + 2];
-    int occ_mult[ISCI_MAXN + 1]; // C(n, n - k)
+    int occ_mult[ISCI_MAXN + 1]; // C(nocc, n - k)
     int le[ISCI_MAXLEV + 2];     // number of strings with level <= l (l = 0..L)
 };
 
@@ -249,6 +251,7 @@ struct isci_ctx {
     int max_rowlen = 0;
     int nplan = 0;           // work items of one sigma job (blocks of 256 beta targets)
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
+    int gas_bnd = 0;         // two-space GAS boundary orbital (0: the excitation hierarchy)
     int nblk = 0, nchunk = 0, nquad = 0;
     bool have_abx = false;   // alpha-beta product path built
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER

@@ -53,18 +53,19 @@ void *dev_alloc(isci_ctx *c, size_t bytes)
 
 // ------------------------------------------------------------------ host tables
 
-static void spin_table(SpinTab &T, int norb, int n, int L)
+// b: level boundary (n for the excitation hierarchy, n <= b <= norb)
+static void spin_table(SpinTab &T, int norb, int n, int L, int b)
 {
     memset(&T, 0, sizeof(T));
     T.n = n;
-    T.nocc = n;
-    T.nvirt = norb - n;
-    T.maxlev = std::min(std::min(n, norb - n), L);
+    T.nocc = b;
+    T.nvirt = norb - b;
+    T.maxlev = std::min(std::min(n, norb - b), L);
     int acc = 0;
     for (int k = 0; k <= T.maxlev; ++k) {
         T.lev_off[k] = acc;
-        T.occ_mult[k] = (int)binom(n, n - k);
-        acc += (int)(binom(n, n - k) * binom(norb - n, k));
+        T.occ_mult[k] = (int)binom(b, n - k);
+        acc += (int)(binom(b, n - k) * binom(norb - b, k));
     }
     for (int k = T.maxlev + 1; k <= ISCI_MAXLEV + 1; ++k) T.lev_off[k] = acc;
     T.nstr = acc;
@@ -83,7 +84,7 @@ static bool enumerate(const SpinTab &T, int norb, std::vector<int32_t> &orb,
     int idx[ISCI_MAXN];
     for (int i = 0; i < n; ++i) idx[i] = i;
     for (;;) {
-        int l = str_level(idx, n);
+        int l = str_level(idx, n, T.nocc);
         if (l <= T.maxlev) {
             int r = str_index(idx, T);
             if (r < 0 || r >= T.nstr || lev[r] >= 0) return false;
@@ -1205,6 +1206,11 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
         set_error("more than 4 electrons per spin is not supported");
         return ISCI_E_UNSUPPORTED;
     }
+    const int gas_bnd = opts ? opts->gas_boundary : 0;
+    if (gas_bnd != 0 && (gas_bnd < nalpha || gas_bnd < nbeta || gas_bnd > norb)) {
+        set_error("isci_create_opts.gas_boundary must be 0 or within [max(nalpha, nbeta), norb]");
+        return ISCI_E_INVALID;
+    }
     if (nalpha == 2 && nbeta == 2 && norb > kPairMaxNorb) {
         set_error("two electrons per spin: at most 200 orbitals (the verified range of the large-orbital one-body kernels)");
         return ISCI_E_UNSUPPORTED;
@@ -1213,12 +1219,15 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
     if (!c) { set_error("host allocation failed"); return ISCI_E_OOM; }
     c->norb = norb; c->na = nalpha; c->nb = nbeta; c->tau = tau;
     c->ob_place = ob_place;
+    c->gas_bnd = gas_bnd;
     if (al) c->allocator = *al;
     c->alloc_stream = stream;
-    const int lmax = std::min(nalpha, norb - nalpha) + std::min(nbeta, norb - nbeta);
+    // level boundary per spin: n (excitation hierarchy) or the GAS boundary
+    const int ba = c->gas_bnd ? c->gas_bnd : nalpha, bb = c->gas_bnd ? c->gas_bnd : nbeta;
+    const int lmax = std::min(nalpha, norb - ba) + std::min(nbeta, norb - bb);
     c->L = std::min(max_excitation, lmax);
-    spin_table(c->sa, norb, nalpha, c->L);
-    spin_table(c->sb, norb, nbeta, c->L);
+    spin_table(c->sa, norb, nalpha, c->L, ba);
+    spin_table(c->sb, norb, nbeta, c->L, bb);
     if (hipGetDevice(&c->device) != hipSuccess) { destroy(c); set_error("hipGetDevice failed"); return ISCI_E_HIP; }
 
     std::vector<uint32_t> pa, pb;
@@ -1284,7 +1293,7 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
             for (int b = 0; b < norb; ++b) {
                 if (a == b) continue;
                 int o[2] = {std::min(a, b), std::max(a, b)};
-                if (str_level(o, 2) > T.maxlev) continue;
+                if (str_level(o, 2, T.nocc) > T.maxlev) continue;
                 pidx[(size_t)a * norb + b] = str_index(o, T);
             }
         int *dp = (int *)dev_alloc(c, sizeof(int) * pidx.size());
@@ -1397,7 +1406,9 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
     }
     isci_status st = build_lists(c, h, E, stream);
     if (st != ISCI_OK) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return st; }
-    if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
+    // the matrix-core path (its operand blocks take orbitals 0 and 1 as the
+    // occupied block) for two electrons per spin at the hierarchy's boundary
+    if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2 && c->sa.nocc == 2 && c->sb.nocc == 2) {
         st = build_hscreen(c, h, stream);
         if (st == ISCI_OK) st = build_tiles(c, E, stream);
         free_factors();
@@ -1515,8 +1526,13 @@ isci_status isci_set_option(isci_handle c, int option, int value)
     switch (option) {
     case ISCI_OPT_SIGMA_KERNEL:
         if (value < ISCI_SIGMA_AUTO || value > ISCI_SIGMA_MFMA) { set_error("bad sigma kernel"); return ISCI_E_INVALID; }
-        if ((value == ISCI_SIGMA_PAIR || value == ISCI_SIGMA_MFMA) && !(c->sa.n == 2 && c->sb.n == 2 && c->have_tiles)) {
+        if ((value == ISCI_SIGMA_PAIR || value == ISCI_SIGMA_MFMA) && !(c->sa.n == 2 && c->sb.n == 2)) {
             set_error("pair kernel needs two electrons of each spin");
+            return ISCI_E_UNSUPPORTED;
+        }
+        if (value == ISCI_SIGMA_MFMA && !c->have_tiles) {
+            set_error("matrix-core kernel not built for a GAS-restricted handle (its operand blocks take orbitals 0 "
+                      "and 1 as the occupied block)");
             return ISCI_E_UNSUPPORTED;
         }
         c->sigma_variant = value;

@@ -78,7 +78,7 @@ __device__ __forceinline__ void sigma_target(const SigmaArgs &A, int ia, int ib,
         for (int e = A.h_off[p]; e < A.h_off[p + 1]; ++e) {
             const int q = A.h_q[e];
             if (!replace_one(ao, na, i, q, jo)) continue;
-            const int lj = str_level(jo, na);
+            const int lj = str_level(jo, na, A.sa.nocc);
             if (lj + lb > L) continue;
             const int ja = str_index(jo, A.sa);
             const double f = (sp * phase_below(ao, na, i, q)) * A.h_v[e];
@@ -97,7 +97,7 @@ __device__ __forceinline__ void sigma_target(const SigmaArgs &A, int ia, int ib,
             for (int e = A.ss_off[P]; e < A.ss_off[P + 1]; ++e) {
                 const int q = A.ss_qs[e] >> 8, s = A.ss_qs[e] & 0xff;
                 if (!replace_two(ao, na, i, j, q, s, jo)) continue;
-                const int lj = str_level(jo, na);
+                const int lj = str_level(jo, na, A.sa.nocc);
                 if (lj + lb > L) continue;
                 const int ja = str_index(jo, A.sa);
                 const int eta_qs = phase_below2(ao, na, i, j, q) * phase_below2(ao, na, i, j, s);
@@ -152,7 +152,7 @@ __device__ __forceinline__ void sigma_target(const SigmaArgs &A, int ia, int ib,
         for (int e1 = A.pq_off[p]; e1 < A.pq_off[p + 1]; ++e1) {
             const int q = A.pq_q[e1];
             if (!replace_one(ao, na, i, q, jo)) continue;
-            const int lj = str_level(jo, na);
+            const int lj = str_level(jo, na, A.sa.nocc);
             if (lj > L) continue;
             const int ja = str_index(jo, A.sa);
             const int lenJ = A.sb.le[L - lj];

@@ -1,0 +1,156 @@
+"""GPU: the two-space GAS restriction (isci_create_opts.gas_boundary, the
+section "Generalized Active Space" and the single-continuum-electron
+restriction of the appendix on CAAB types): full CI in the orbitals below
+the boundary, at most max_excitation electrons above it.  Compared with
+the oracle built on the same space (oracle.Space(..., boundary=b)).
+
+Bar: sigma |delta| <= 1e-12 * ||sigma||_inf (the oracle's); strings, row
+starts and term counts exact; Davidson energies within 1e-10 Eh of the
+oracle's dense spectrum."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from isci_inputs import random_vectors, recipe_a, recipe_b
+
+from gpu_common import gpu_sigma, rel_err, sample_targets, sampled_ok, torch_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _gas(h, eri, norb, na, nb, L, tau, b, kernel=0):
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    ht = torch.from_numpy(np.ascontiguousarray(h)).to(dev)
+    et = torch.from_numpy(np.ascontiguousarray(eri)).to(dev)
+    hd = isci.isci_create(ht, et, norb, na, nb, L, tau, gas_boundary=b)
+    torch.cuda.synchronize()
+    if kernel:
+        isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, kernel)
+    return hd
+
+
+@pytest.mark.parametrize("recipe,norb,na,nb,L,b,tau,nvec", [
+    ("A", 12, 2, 2, 1, 5, 0.0, 2), ("B", 12, 2, 2, 2, 4, 1e-8, 3), ("A", 14, 2, 2, 1, 3, 1e-12, 1),
+    ("B", 10, 3, 2, 2, 4, 0.0, 2), ("A", 9, 2, 1, 1, 4, 1e-10, 2), ("B", 10, 1, 1, 1, 3, 0.0, 1),
+    ("A", 11, 2, 2, 0, 6, 1e-12, 2), ("B", 9, 3, 3, 2, 5, 1e-9, 1)])
+def test_gas_sigma_matches_oracle(recipe, norb, na, nb, L, b, tau, nvec):
+    """Every element of sigma, on the pair-table kernel (two electrons per
+    spin) and the general-string kernel (the others), and on the general
+    kernel forced for two electrons per spin."""
+    import paper_1609_07757_amd as isci
+    h, eri = (recipe_a if recipe == "A" else recipe_b)(norb, seed=3)
+    S = O.Space(norb, na, nb, L, boundary=b)
+    hd = _gas(h, eri, norb, na, nb, L, tau, b)
+    assert isci.isci_dim(hd) == S.dim
+    c = random_vectors(S.dim, nvec, seed=7)
+    ref = O.sigma(S, h, eri, tau, c)
+    got = gpu_sigma(hd, c)
+    assert rel_err(got, ref) <= TOL
+    if na == 2 and nb == 2:
+        from paper_1609_07757_amd import _lib
+        hg = _gas(h, eri, norb, na, nb, L, tau, b, kernel=isci.SIGMA_GENERAL)
+        assert rel_err(gpu_sigma(hg, c), ref) <= TOL
+        hp = _gas(h, eri, norb, na, nb, L, tau, b, kernel=isci.SIGMA_PAIR)
+        assert np.array_equal(gpu_sigma(hp, c), got)
+        # the matrix-core operands are not built for a GAS handle
+        with pytest.raises(isci.IsciError) as ei:
+            isci.isci_set_option(hp, isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA)
+        assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("norb,na,nb,L,b", [(12, 2, 2, 1, 5), (10, 3, 2, 2, 4), (9, 2, 1, 2, 9)])
+def test_gas_strings_rows_and_term_counts_exact(norb, na, nb, L, b):
+    import paper_1609_07757_amd as isci
+    h, eri = recipe_b(norb, seed=5)
+    tau = 1e-9
+    S = O.Space(norb, na, nb, L, boundary=b)
+    hd = _gas(h, eri, norb, na, nb, L, tau, b)
+    for spin in (0, 1):
+        go, gl = isci.isci_strings(hd, spin)
+        oo, ol = S.strings(spin)
+        assert np.array_equal(go, oo) and np.array_equal(gl, ol)
+    assert np.array_equal(isci.isci_rowstart(hd), S.rowstart())
+    kept, _ = O.terms(S, h, eri, tau)
+    st = isci.isci_get_stats(hd)
+    assert np.array_equal(np.asarray(st["terms"], dtype=np.int64), kept)
+    d = isci.isci_diag(hd).cpu().numpy()
+    assert rel_err(d[None], O.diag(S, h, eri, tau)[None]) <= TOL
+
+
+def test_gas_boundary_at_norb_is_fci():
+    """b = norb leaves no outer orbital: the handle is full CI whatever the
+    limit.  Every string then has level 0, so the strings are in plain
+    colex order: the determinants are the full-CI ones in another order,
+    and sigma is the full-CI sigma (hierarchy layout) permuted."""
+    norb = 8
+    h, eri = recipe_a(norb, seed=2)
+    F = O.Space(norb, 2, 2, 4)
+    G = O.Space(norb, 2, 2, 1, boundary=norb)
+    perm = np.array([F.address(a, b) for a, b in G.determinants()])
+    assert np.array_equal(np.sort(perm), np.arange(F.dim))
+    hd = _gas(h, eri, norb, 2, 2, 1, 1e-12, norb)
+    c = random_vectors(F.dim, 2, seed=4)
+    assert rel_err(gpu_sigma(hd, c[:, perm]), O.sigma(F, h, eri, 1e-12, c)[:, perm]) <= TOL
+
+
+def test_gas_davidson_energies():
+    """Davidson on the GAS handle against the dense spectrum of the
+    oracle's matrix on the same space, and the nesting of the ground
+    energy in the outer-electron limit."""
+    import paper_1609_07757_amd as isci
+    norb, b = 12, 5
+    h, eri = recipe_a(norb, seed=1)
+    e0 = []
+    for L in (0, 1, 2):
+        S = O.Space(norb, 2, 2, L, boundary=b)
+        ref = np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))[:3]
+        hd = _gas(h, eri, norb, 2, 2, L, 0.0, b)
+        e, _v, info = isci.isci_davidson(hd, nroots=3, tol_residual=1e-8)
+        assert info["converged"]
+        assert np.abs(np.asarray(e) - ref).max() <= 1e-10
+        e0.append(e[0])
+    assert e0[0] > e0[1] > e0[2]
+
+
+def test_gas_single_outer_electron_sampled():
+    """At the benchmark's shape (200 orbitals, 16 inner, at most one
+    electron outside them, eight vectors): sampled targets, row ends
+    included."""
+    norb, b, L, tau = 200, 16, 1, 1e-12
+    h, eri = recipe_a(norb, seed=1)
+    S = O.Space(norb, 2, 2, L, boundary=b)
+    hd = _gas(h, eri, norb, 2, 2, L, tau, b)
+    c = random_vectors(S.dim, 8, seed=21)
+    got = gpu_sigma(hd, c)
+    tg = sample_targets(S.rowstart(), S.dim, 300, seed=5)
+    ok, err = sampled_ok(got, tg, O.sigma(S, h, eri, tau, c, targets=tg), TOL)
+    assert ok, err
+
+
+def test_gas_errors():
+    import paper_1609_07757_amd as isci
+    from paper_1609_07757_amd import _lib
+    torch, dev = torch_dev()
+    norb = 8
+    h, eri = recipe_a(norb, seed=0)
+    ht = torch.from_numpy(h).to(dev)
+    et = torch.from_numpy(eri).to(dev)
+    for b in (1, norb + 1):
+        with pytest.raises(isci.IsciError) as ei:
+            isci.isci_create(ht, et, norb, 2, 2, 1, 0.0, gas_boundary=b)
+        assert ei.value.status == _lib.ISCI_E_INVALID
+    with pytest.raises(isci.IsciError):
+        isci.isci_create(ht, et, norb, 3, 2, 1, 0.0, gas_boundary=2)
+    hd = isci.isci_create(ht, et, norb, 2, 2, 1, 0.0, gas_boundary=4)
+    c = torch.zeros((1, isci.isci_dim(hd)), dtype=torch.float64, device=dev)
+    for fn in (isci.isci_density1, isci.isci_density2):
+        with pytest.raises(isci.IsciError) as ei:
+            fn(hd, c)
+        assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
+    d1 = torch.zeros((1, 2, norb, norb), dtype=torch.float64, device=dev)
+    with pytest.raises(isci.IsciError) as ei:
+        isci.isci_density1_noalloc(hd, c, d1)
+    assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
