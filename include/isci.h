@@ -199,10 +199,12 @@ typedef struct {
  * max_excitation electrons in the outer ones; b = n_sigma for both spins is
  * the excitation hierarchy of Eq. ci_hierarchy (the default, 0).  The
  * layout is unchanged in form: strings sorted by (level, colex), the row of
- * a level-k alpha string holding the beta strings of level <= L - k.  Such
- * a handle runs sigma on the pair-table kernel (two electrons per spin) or
- * the general-string kernel (the matrix-core path, whose operand blocks
- * take orbitals 0 and 1 as the occupied block, is not built for it); the
+ * a level-k alpha string holding the beta strings of level <= L - k.  With
+ * two electrons per spin such a handle runs the matrix-core path with its
+ * orbital blocks split at b (inner blocks first) and the one-body units
+ * carried in the alpha-beta tiles (the separate one-body kernels take
+ * orbitals 0 and 1 as the occupied ones; onebody = ISCI_OB_SEPARATE is
+ * overridden); other electron counts run the general-string kernel.  The
  * densities (isci_density1, isci_density1_noalloc, isci_density2) return
  * ISCI_E_UNSUPPORTED.  ISCI_E_INVALID for b outside [max(nalpha, nbeta),
  * norb]. */

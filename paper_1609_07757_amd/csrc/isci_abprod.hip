@@ -13,13 +13,15 @@
 // screened matrix W[(p, r), (q, s)] = (pq|rs); over all spectators and the
 // vectors of a pass it is a block-sparse GEMM whose columns are (x, y, v).
 //
-// Orbitals come in blocks of four (block 0: the two occupied orbitals);
-// W is stored as 16 x 4 chunks (rows (p, r) of a row block pair, columns
-// (q, four s of an S block)), ordered inside a row block pair by the class
-// [q virtual] + [S virtual].  Columns are grouped by spectator block pair
-// (C, D), low level first (level = [C virtual] + [D virtual]), each level
-// section padded with zero columns to a multiple of 64; a group has
-// slots(C) * slots(D) * 4 columns (two slots for the occupied block).  A
+// Orbitals come in blocks of four, inner and outer apart (for the
+// excitation hierarchy block 0 holds the two occupied orbitals; with a GAS
+// boundary the inner space takes the first blocks); W is stored as 16 x 4
+// chunks (rows (p, r) of a row block pair, columns (q, four s of an S
+// block)), ordered inside a row block pair by the class [q outer] +
+// [S outer].  Columns are grouped by spectator block pair (C, D), low level
+// first (level = [C outer] + [D outer]), each level section padded with
+// zero columns to a multiple of 64; a group has slots(C) * slots(D) * 4
+// columns (fewer slots for a short inner block).  A
 // source or target of class k only has the spectator groups of level
 // <= L - k, which is a prefix of the columns: pcols[k].
 //
@@ -40,9 +42,6 @@ namespace isci {
 
 typedef double v4d_ab __attribute__((ext_vector_type(4)));
 
-
-__device__ __forceinline__ int ab_block(int o) { return o < 2 ? 0 : 1 + (o - 2) / 4; }
-__device__ __forceinline__ int ab_slot(int o) { return o < 2 ? o : (o - 2) % 4; }
 
 // Unfold by scatter: one thread per determinant ({a0<a1}, {b0<b1}) of the
 // space reads its 4 vector values (coalesced) and writes them, with the
@@ -70,11 +69,11 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
             const int y = rb ? b1 : b0, s = rb ? b0 : b1;
-            const int2 tq = A.abx_tq[q * nb + ab_block(s)];
+            const int2 tq = A.abx_tq[q * nb + ab_block(A, s)];
             if (tq.y == 0) continue;   // no chunk reads this row
-            const int D = ab_block(y);
-            const int col = A.abx_gofs[ab_block(x) * nb + D] + (ab_slot(x) * (D == 0 ? 2 : 4) + ab_slot(y)) * 4;
-            double *dst = A.abx_T + (size_t)tq.x + (size_t)ab_slot(s) * tq.y + col;
+            const int D = ab_block(A, y);
+            const int col = A.abx_gofs[ab_block(A, x) * nb + D] + (ab_slot(A, x) * ab_width(A, D) + ab_slot(A, y)) * 4;
+            double *dst = A.abx_T + (size_t)tq.x + (size_t)ab_slot(A, s) * tq.y + col;
             const double f = (ra ^ rb) ? -1.0 : 1.0;   // sgn(q - x) sgn(s - y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) dst[v] = f * cv[v];
@@ -110,7 +109,7 @@ __global__ __launch_bounds__(64 * CW * KS) __attribute__((amdgpu_waves_per_eu(6)
     if (tb.g < 0) return;
     const int g = tb.g;
     const int Ab = g / nb, Bb = g % nb;
-    const int m = (Ab != 0) + (Bb != 0);
+    const int m = ab_outer(A, Ab) + ab_outer(A, Bb);
     // wave index made explicitly uniform: the chunk range and the chunk
     // table reads below then compile to scalar loads, which retire apart
     // from the vector loads of the operands
@@ -235,7 +234,7 @@ __global__ __launch_bounds__(64 * CW * KS) void k_ab_pipe(SigmaArgs A)
     if (tb.g < 0) return;
     const int g = tb.g;
     const int Ab = g / nb, Bb = g % nb;
-    const int m = (Ab != 0) + (Bb != 0);
+    const int m = ab_outer(A, Ab) + ab_outer(A, Bb);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int cw = wave % CW, part = wave / CW;
     const int c0 = tb.c0 + cw * 64;
@@ -341,13 +340,13 @@ __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
             const int ys = rb ? b1 : b0, ya = rb ? b0 : b1;
-            const int g = ab_block(xa) * nb + ab_block(ya);
+            const int g = ab_block(A, xa) * nb + ab_block(A, ya);
             const long long so = A.abx_soff[g];
             if (so < 0) continue;
-            const int m = (ab_block(xa) != 0) + (ab_block(ya) != 0);
-            const int C = ab_block(xs), D = ab_block(ys);
-            const int col = A.abx_gofs[C * nb + D] + (ab_slot(xs) * (D == 0 ? 2 : 4) + ab_slot(ys)) * 4;
-            const int row = ab_slot(xa) * 4 + ab_slot(ya);
+            const int m = ab_outer(A, ab_block(A, xa)) + ab_outer(A, ab_block(A, ya));
+            const int C = ab_block(A, xs), D = ab_block(A, ys);
+            const int col = A.abx_gofs[C * nb + D] + (ab_slot(A, xs) * ab_width(A, D) + ab_slot(A, ys)) * 4;
+            const int row = ab_slot(A, xa) * 4 + ab_slot(A, ya);
             const double *src = A.abx_S + (size_t)so + (size_t)row * A.abx_pcols[m] + col;
             const double f = (ra ^ rb) ? -1.0 : 1.0;
 #pragma unroll

@@ -171,6 +171,7 @@ struct SigmaArgs {
     int classes;             // bit 0 one-body, bit 1 same-spin, bit 2 alpha-beta (pair kernel)
     int accumulate;          // pair kernel adds into sigma instead of overwriting
     int nblk;
+    int ab_b, ab_nib;        // orbital blocks: inner orbitals 0..ab_b-1 in ab_nib blocks, outer ones after
     const int16_t *blk_orb;
     const int *chunk_off;
     const int2 *chunk_desc;
@@ -195,6 +196,25 @@ struct SigmaArgs {
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
 };
+
+// Orbital blocks of the matrix-core path: the inner orbitals 0..b-1 (the
+// two occupied ones for the excitation hierarchy, the inner space of a GAS
+// boundary) in blocks of four from 0, the last one short when b is not a
+// multiple of four, then the outer orbitals in blocks of four from b; a
+// block's level is 1 when it is outer.  Blocks follow orbital order.
+__device__ __forceinline__ int ab_block(const SigmaArgs &A, int o)
+{
+    return o < A.ab_b ? (o >> 2) : A.ab_nib + ((o - A.ab_b) >> 2);
+}
+__device__ __forceinline__ int ab_slot(const SigmaArgs &A, int o) { return o < A.ab_b ? (o & 3) : ((o - A.ab_b) & 3); }
+__device__ __forceinline__ int ab_width(const SigmaArgs &A, int B) { return B < A.ab_nib ? min(4, A.ab_b - 4 * B) : 4; }
+__device__ __forceinline__ int ab_outer(const SigmaArgs &A, int B) { return B >= A.ab_nib ? 1 : 0; }
+// orbital of slot i (0..3) of block B, -1 for padding
+__device__ __forceinline__ int ab_orbital(const SigmaArgs &A, int B, int i)
+{
+    const int o = B < A.ab_nib ? 4 * B + i : A.ab_b + 4 * (B - A.ab_nib) + i;
+    return (B < A.ab_nib ? o < A.ab_b : o < A.norb) ? o : -1;
+}
 
 // Workgroup b of a launch over the determinant rows that starts no empty
 // workgroup: the alpha strings of level k (contiguous from sa.lev_off[k])
@@ -253,6 +273,7 @@ struct isci_ctx {
     int sigma_variant = 0;   // ISCI_SIGMA_AUTO / _GENERAL / _PAIR / _MFMA
     int gas_bnd = 0;         // two-space GAS boundary orbital (0: the excitation hierarchy)
     int nblk = 0, nchunk = 0, nquad = 0;
+    int ab_b = 2, ab_nib = 1;         // orbital blocks: inner orbitals 0..ab_b-1 in ab_nib blocks
     bool have_abx = false;   // alpha-beta product path built
     bool ab_gather = false;  // ISCI_OPT_AB_PATH = ISCI_AB_GATHER
     int abx_ntrow = 0, abx_nrows = 0, abx_pcols[3] = {0, 0, 0};

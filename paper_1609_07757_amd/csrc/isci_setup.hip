@@ -510,6 +510,8 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.classes = 7;
     A.accumulate = 0;
     A.nblk = c->nblk;
+    A.ab_b = c->ab_b;
+    A.ab_nib = c->ab_nib;
     A.blk_orb = c->d.blk_orb;
     A.chunk_off = c->d.chunk_off;
     A.chunk_desc = c->d.chunk_desc;
@@ -596,14 +598,14 @@ __global__ __launch_bounds__(256) void k_chunk_count(const unsigned *bits, int n
 }
 
 // Chunks of a row block pair are written in order of their source level
-// class (virtual q) + (virtual S-block), so the chunks a role may use form
+// class (outer q) + (outer S-block), so the chunks a role may use form
 // a prefix; cls[g*3 + l] counts the chunks of class l.  One workgroup per
 // row block pair g: for each class, block-wide scans over batches of 256
 // (q, S) keys (in q, S order) place the marked chunks, then 64-lane groups
 // fill the 64 values of each chunk placed in the batch.
 __global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, EriSrc E, const double *hs, int n,
-                                                    int nb, double tau, const int16_t *blk_orb, const int *off,
-                                                    int2 *desc, double *val, int *cls)
+                                                    int nb, int bnd, int nib, double tau, const int16_t *blk_orb,
+                                                    const int *off, int2 *desc, double *val, int *cls)
 {
     const int g = blockIdx.x;
     const int Ab = g / nb, Bb = g % nb;
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, EriSrc
             bool f = false;
             if (key < nk) {
                 const long long k = k0 + key;
-                f = ((bits[k >> 5] >> (k & 31)) & 1u) && (q >= 2) + (S != 0) == lc;
+                f = ((bits[k >> 5] >> (k & 31)) & 1u) && (q >= bnd) + (S >= nib) == lc;
             }
             const unsigned long long bal = __ballot(f);
             const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -666,12 +668,19 @@ static constexpr int64_t kObTilesMaxDim = 65536;
 static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
 {
     const int n = c->norb;
-    // orbitals of each block slot, -1 for padding (16 bits: up to 255 orbitals)
+    // orbitals of each block slot, -1 for padding (16 bits: up to 255
+    // orbitals): the inner orbitals 0..b-1 in blocks of four (the last one
+    // short), then the outer ones in blocks of four from b
+    const int bnd = std::min(c->sa.nocc, n);
     std::vector<int16_t> bo;
-    bo.insert(bo.end(), {0, (int16_t)(n > 1 ? 1 : -1), -1, -1});
-    for (int v = 2; v < n; v += 4)
+    for (int v = 0; v < bnd; v += 4)
+        for (int k = 0; k < 4; ++k) bo.push_back((int16_t)(v + k < bnd ? v + k : -1));
+    const int nib = (int)bo.size() / 4;
+    for (int v = bnd; v < n; v += 4)
         for (int k = 0; k < 4; ++k) bo.push_back((int16_t)(v + k < n ? v + k : -1));
     const int nb = (int)bo.size() / 4;
+    c->ab_b = bnd;
+    c->ab_nib = nib;
     std::vector<int> ob(n, 0);
     for (int b = 0; b < nb; ++b)
         for (int k = 0; k < 4; ++k)
@@ -681,7 +690,7 @@ static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
         for (int P = X; P < nb; ++P)
             for (int Y = 0; Y < nb; ++Y)
                 for (int R = Y; R < nb; ++R) {
-                    const int lev = (X != 0) + (P != 0) + (Y != 0) + (R != 0);
+                    const int lev = (X >= nib) + (P >= nib) + (Y >= nib) + (R >= nib);
                     if (lev > c->L) continue;
                     quads.push_back(make_uchar4((unsigned char)X, (unsigned char)P, (unsigned char)Y, (unsigned char)R));
                 }
@@ -727,7 +736,9 @@ static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
     bool merged = false;
     // below three orbitals (no virtual orbital) the one-body kernels do not
     // apply: the tiles always carry the units there
-    if (d.hscreen && (c->ob_place != ISCI_OB_SEPARATE || n < 3)) {
+    // (a GAS-restricted handle always: the one-body kernels take orbitals 0
+    // and 1 as the occupied ones)
+    if (d.hscreen && (c->ob_place != ISCI_OB_SEPARATE || n < 3 || c->gas_bnd)) {
         unsigned *bits1 = nullptr;
         ISCI_HIP(hipMallocAsync((void **)&bits1, nbits, s));
         ISCI_HIP(hipMemcpyAsync(bits1, bits, nbits, hipMemcpyDeviceToDevice, s));
@@ -736,7 +747,7 @@ static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
         int tot1 = 0;
         st = count_chunks(bits1, &tot1);
         if (st != ISCI_OK) return st;
-        if (c->ob_place == ISCI_OB_TILES || n < 3 || (long long)tot1 * 8 <= (long long)tot * 9 ||
+        if (c->ob_place == ISCI_OB_TILES || n < 3 || c->gas_bnd || (long long)tot1 * 8 <= (long long)tot * 9 ||
             c->dim <= kObTilesMaxDim) {
             merged = true;
             std::swap(bits, bits1);
@@ -754,7 +765,7 @@ static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
     d.chunk_cls = (int *)dev_alloc(c, sizeof(int) * 3 * nb * nb);
     if (!d.chunk_desc || !d.chunk_val || !d.chunk_cls) { set_error("device allocation failed (chunks)"); return ISCI_E_OOM; }
     ISCI_HIP(hipMemsetAsync(d.chunk_val + (size_t)64 * tot, 0, sizeof(double) * 64, s));
-    k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, E, merged ? d.hscreen : nullptr, n, nb, c->tau, d.blk_orb,
+    k_chunk_fill<<<nb * nb, 256, 0, s>>>(bits, E, merged ? d.hscreen : nullptr, n, nb, bnd, nib, c->tau, d.blk_orb,
                                           d.chunk_off, d.chunk_desc, d.chunk_val, d.chunk_cls);
     ISCI_HIP(hipGetLastError());
     ISCI_HIP(hipFreeAsync(bits, s));
@@ -771,9 +782,12 @@ static constexpr size_t kAbxMaxBytes = (size_t)2 << 30;
 
 static isci_status build_abx(isci_ctx *c, hipStream_t s)
 {
-    const int n = c->norb, nb = c->nblk, L = c->L;
+    const int n = c->norb, nb = c->nblk, L = c->L, nib = c->ab_nib, bnd = c->ab_b;
     if (nb < 1 || c->nchunk == 0) return ISCI_OK;
-    auto width = [](int B) { return B == 0 ? 2 : 4; };
+    // slots of block B, its orbital i, its level (1: outer)
+    auto width = [&](int B) { return B < nib ? std::min(4, bnd - 4 * B) : 4; };
+    auto orbital = [&](int B, int i) { return B < nib ? 4 * B + i : bnd + 4 * (B - nib) + i; };
+    auto outer = [&](int B) { return B >= nib ? 1 : 0; };
     // column groups, level by level, each level padded to 64 columns
     std::vector<int> gofs((size_t)nb * nb, -1);
     std::vector<int> col;
@@ -782,12 +796,12 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         if (lev <= L)
             for (int C = 0; C < nb; ++C)
                 for (int D = 0; D < nb; ++D) {
-                    if ((C != 0) + (D != 0) != lev) continue;
+                    if (outer(C) + outer(D) != lev) continue;
                     gofs[(size_t)C * nb + D] = (int)col.size();
                     for (int ic = 0; ic < width(C); ++ic)
                         for (int id = 0; id < width(D); ++id) {
-                            const int x = C == 0 ? ic : 2 + 4 * (C - 1) + ic;
-                            const int y = D == 0 ? id : 2 + 4 * (D - 1) + id;
+                            const int x = orbital(C, ic);
+                            const int y = orbital(D, id);
                             for (int v = 0; v < 4; ++v)
                                 col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
                         }
@@ -831,7 +845,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     std::vector<int> rows;
     size_t ssize = 0;
     for (int g = 0; g < nb * nb; ++g) {
-        const int m = (g / nb != 0) + (g % nb != 0);
+        const int m = outer(g / nb) + outer(g % nb);
         if (off[g + 1] == off[g] || pcols[m] == 0) continue;
         soff[g] = (long long)ssize;
         rows.push_back(g);
@@ -855,7 +869,7 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         for (int sg = 0; sg < nslab; sg += sgrp)
             for (int g : rows)
                 for (int sl = sg; sl < std::min(sg + sgrp, nslab); ++sl) {
-                    const int m = (g / nb != 0) + (g % nb != 0);
+                    const int m = outer(g / nb) + outer(g % nb);
                     if (sl * kAbTile >= pcols[m]) continue;
                     int ne = 0;
                     for (int l = 0; l < 3; ++l)
@@ -1406,9 +1420,9 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
     }
     isci_status st = build_lists(c, h, E, stream);
     if (st != ISCI_OK) { free_factors(); (void)hipStreamSynchronize(stream); destroy(c); return st; }
-    // the matrix-core path (its operand blocks take orbitals 0 and 1 as the
-    // occupied block) for two electrons per spin at the hierarchy's boundary
-    if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2 && c->sa.nocc == 2 && c->sb.nocc == 2) {
+    // the matrix-core path for two electrons per spin (orbital blocks split
+    // at the level boundary: the two occupied orbitals, or a GAS boundary)
+    if (c->sa.n == 2 && c->sb.n == 2 && norb >= 2) {
         st = build_hscreen(c, h, stream);
         if (st == ISCI_OK) st = build_tiles(c, E, stream);
         free_factors();

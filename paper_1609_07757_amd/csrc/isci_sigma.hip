@@ -343,15 +343,6 @@ __device__ __forceinline__ void sigma_target_n2(const SigmaArgs &A, int ia, int 
 // roles are combined through LDS and sigma is written once (no atomics).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// orbital of slot i (0..3) of block B: block 0 holds the two occupied
-// orbitals, block B >= 1 the virtual orbitals 2 + 4 (B - 1) + i
-__device__ __forceinline__ int blk_orbital(int B, int i, int norb)
-{
-    if (B == 0) return i < 2 ? i : -1;
-    const int v = 2 + 4 * (B - 1) + i;
-    return v < norb ? v : -1;
-}
-
 constexpr int kTabMax = 128;   // orbitals covered by the LDS lookup tables
 
 // B operand of one chunk for this lane: sign * c(v, {x,q}, {y,s}) or 0.
@@ -434,7 +425,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     if (TAB && active)
         for (int t = lane; t < 4 * norb; t += 64) {
             const int i = t / norb, o = t % norb;
-            const int xx = blk_orbital(Cb, i, norb), yy = blk_orbital(Db, i, norb);
+            const int xx = ab_orbital(A, Cb, i), yy = ab_orbital(A, Db, i);
             rb[i * kTabMax + o] = xx >= 0 ? A.arow_base[xx * norb + o] : -1;
             rl[i * kTabMax + o] = xx >= 0 ? A.arow_len[xx * norb + o] : 0;
             bi[i * kTabMax + o] = yy >= 0 ? A.bpidx[yy * norb + o] : -1;
@@ -446,8 +437,8 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     if (active) {
         const int n = lane & 15, k = lane >> 4;
         const int ic = n >> 2, id = n & 3;
-        const int x = blk_orbital(Cb, ic, norb), y = blk_orbital(Db, id, norb);
-        const int espec = (Cb != 0) + (Db != 0);
+        const int x = ab_orbital(A, Cb, ic), y = ab_orbital(A, Db, id);
+        const int espec = ab_outer(A, Cb) + ab_outer(A, Db);
         const int row = Ab * nb + Bb;
         const int e0 = A.chunk_off[row];
         int e1 = e0;
@@ -460,7 +451,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
             for (int u = 0; u < 4; ++u) {
                 const int2 d = A.chunk_desc[e + u];
                 a[u] = A.chunk_val[(size_t)(e + u) * 64 + lane];
-                gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, blk_orbital(d.y, k, norb), norb, rb, rl, bi, b[u]);
+                gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, ab_orbital(A, d.y, k), norb, rb, rl, bi, b[u]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -471,7 +462,7 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
             double b[NV];
             const int2 d = A.chunk_desc[e];
             const double a = A.chunk_val[(size_t)e * 64 + lane];
-            gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, blk_orbital(d.y, k, norb), norb, rb, rl, bi, b);
+            gather_b<NV, TAB>(A, c, ldc, nv, x, y, ic, id, d.x, ab_orbital(A, d.y, k), norb, rb, rl, bi, b);
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[v], acc[v], 0, 0, 0);
         }
@@ -487,8 +478,8 @@ __global__ __launch_bounds__(256) void k_sigma_ab_mfma(SigmaArgs A, int nv, cons
     __syncthreads();
     const int t = threadIdx.x;
     const int ix = (t >> 6) & 3, ip = (t >> 4) & 3, iy = (t >> 2) & 3, ir = t & 3;
-    const int x = blk_orbital(X, ix, norb), p = blk_orbital(P, ip, norb);
-    const int y = blk_orbital(Y, iy, norb), r = blk_orbital(R, ir, norb);
+    const int x = ab_orbital(A, X, ix), p = ab_orbital(A, P, ip);
+    const int y = ab_orbital(A, Y, iy), r = ab_orbital(A, R, ir);
     if (x < 0 || p < 0 || y < 0 || r < 0 || x >= p || y >= r) return;
     const long long tb = A.arow_base[x * norb + p];
     const int tl = A.arow_len[x * norb + p];

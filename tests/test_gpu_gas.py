@@ -37,9 +37,11 @@ def _gas(h, eri, norb, na, nb, L, tau, b, kernel=0):
     ("B", 10, 3, 2, 2, 4, 0.0, 2), ("A", 9, 2, 1, 1, 4, 1e-10, 2), ("B", 10, 1, 1, 1, 3, 0.0, 1),
     ("A", 11, 2, 2, 0, 6, 1e-12, 2), ("B", 9, 3, 3, 2, 5, 1e-9, 1)])
 def test_gas_sigma_matches_oracle(recipe, norb, na, nb, L, b, tau, nvec):
-    """Every element of sigma, on the pair-table kernel (two electrons per
-    spin) and the general-string kernel (the others), and on the general
-    kernel forced for two electrons per spin."""
+    """Every element of sigma: for two electrons per spin on the
+    matrix-core path (blocks split at the boundary, one-body units in the
+    tiles; the unfold / product / fold route and the gathered tile kernel),
+    the pair-table kernel and the general-string kernel; for other electron
+    counts on the general-string kernel."""
     import paper_1609_07757_amd as isci
     h, eri = (recipe_a if recipe == "A" else recipe_b)(norb, seed=3)
     S = O.Space(norb, na, nb, L, boundary=b)
@@ -50,15 +52,12 @@ def test_gas_sigma_matches_oracle(recipe, norb, na, nb, L, b, tau, nvec):
     got = gpu_sigma(hd, c)
     assert rel_err(got, ref) <= TOL
     if na == 2 and nb == 2:
-        from paper_1609_07757_amd import _lib
-        hg = _gas(h, eri, norb, na, nb, L, tau, b, kernel=isci.SIGMA_GENERAL)
-        assert rel_err(gpu_sigma(hg, c), ref) <= TOL
-        hp = _gas(h, eri, norb, na, nb, L, tau, b, kernel=isci.SIGMA_PAIR)
-        assert np.array_equal(gpu_sigma(hp, c), got)
-        # the matrix-core operands are not built for a GAS handle
-        with pytest.raises(isci.IsciError) as ei:
-            isci.isci_set_option(hp, isci.OPT_SIGMA_KERNEL, isci.SIGMA_MFMA)
-        assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
+        for kern in (isci.SIGMA_GENERAL, isci.SIGMA_PAIR):
+            hk = _gas(h, eri, norb, na, nb, L, tau, b, kernel=kern)
+            assert rel_err(gpu_sigma(hk, c), ref) <= TOL
+        hm = _gas(h, eri, norb, na, nb, L, tau, b, kernel=isci.SIGMA_MFMA)
+        isci.isci_set_option(hm, isci.OPT_AB_PATH, isci.AB_GATHER)
+        assert rel_err(gpu_sigma(hm, c), ref) <= TOL
 
 
 @pytest.mark.parametrize("norb,na,nb,L,b", [(12, 2, 2, 1, 5), (10, 3, 2, 2, 4), (9, 2, 1, 2, 9)])
