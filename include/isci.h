@@ -205,9 +205,9 @@ typedef struct {
  * carried in the alpha-beta tiles (the separate one-body kernels take
  * orbitals 0 and 1 as the occupied ones; onebody = ISCI_OB_SEPARATE is
  * overridden); other electron counts run the general-string kernel.  The
- * densities (isci_density1, isci_density1_noalloc, isci_density2) return
- * ISCI_E_UNSUPPORTED.  ISCI_E_INVALID for b outside [max(nalpha, nbeta),
- * norb]. */
+ * densities apply as for any handle (isci_density1 and
+ * isci_density1_noalloc for b <= 16, else ISCI_E_UNSUPPORTED).
+ * ISCI_E_INVALID for b outside [max(nalpha, nbeta), norb]. */
 
 /* isci_create with build options; opts may be NULL (defaults).  Returns
  * ISCI_E_INVALID for an unknown onebody value or an allocator with a NULL

@@ -38,6 +38,7 @@ typedef double v4d_d2 __attribute__((ext_vector_type(4)));
 
 constexpr int kD1Chunk = 8;       // vectors per pass (the handle keeps kD1Chunk * dim doubles for the transposed copy)
 constexpr int kD2MaxNorb = 128;   // two-body densities: 8 norb^4 bytes per scratch buffer
+constexpr int kD1MaxInner = 16;   // level boundary (inner orbitals) the one-body Gram form handles
 constexpr int kGramGroups = 64;   // partial slabs (set groups x piece streams) summed in order by k_d1_reduce
 
 // Fixed-order sum over the 64 lanes of a wave (butterfly).
@@ -104,9 +105,11 @@ __device__ inline void unrank_set(uint32_t s, int k, int norb, int *S)
 // strings index the rows of A (A.sa), the rows R[q] = (-1)^{#S below q}
 // c(S + q, .) (zero when S + q is not a string of the space) give
 // D[p][q] += sum_b R[p][b] R[q][b] over the prefix both rows hold.  The rows
-// of one set have two lengths only (S + q one level higher for a virtual q),
-// so phase 1 takes every row over the shorter length and phase 2 the pairs
-// of the longer rows (q < n: at most 4, rows 0..3 of tile 0) over the rest.
+// of one set have two lengths only (S + q one level higher for q at or above
+// the level boundary b), so phase 1 takes every row over the shorter length
+// and phase 2 the pairs of the longer rows (q < b: rows 0..b-1 of tile 0;
+// b = n <= 4 for the excitation hierarchy, b <= kD1MaxInner for a GAS
+// boundary) over the rest.
 // Workgroup (tile pair, g * P + p, vector v) sums its tile of the output over
 // the sets g, g + G, ... and, of each, the phase-1 column pieces p, p + P, ...
 // of W columns (phase 2 with piece stream p = 0), so that long row sets are
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
     __shared__ double rsg[2][kGT];
     __shared__ int rlen[2][kGT];
     __shared__ int kmin_s, kmax_s;
-    __shared__ double ph2[4][4];
+    __shared__ double ph2[kD1MaxInner][kD1MaxInner];
     const int norb = A.norb, n = A.sa.n, tid = threadIdx.x;
     // tile pair number blockIdx.x of the upper triangle tp <= tq (row-major);
     // each set's Gram matrix is symmetric, so the lower tiles are not formed
@@ -206,8 +209,9 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
         // phase 2: pairs of the longer rows over [K1, min of their lengths)
         if (K2 > K1 && P0 == 0 && Q0 == 0 && pc == 0) {
             const int w = tid >> 6, lane = tid & 63;
-            for (int pairi = w; pairi < 16; pairi += 4) {
-                const int i = pairi >> 2, j = pairi & 3;
+            const int nl = max(4, A.sa.nocc);   // rows that may be long (<= kD1MaxInner)
+            for (int pairi = w; pairi < nl * nl; pairi += 4) {
+                const int i = pairi / nl, j = pairi - i * nl;
                 const int le = min(rlen[0][i], rlen[1][j]);
                 double part2 = 0.0;
                 if (rsg[0][i] != 0.0 && rsg[1][j] != 0.0)
@@ -216,9 +220,14 @@ __global__ __launch_bounds__(256) void k_d1_gram(SigmaArgs A, const double *__re
                 if (lane == 0) ph2[i][j] = part2;
             }
             __syncthreads();
-            // rows and columns 0..3 of the tile: wave 0, tile 0, element 0,
-            // lanes 16 i + j
-            if (w == 0 && (lane >> 4) < 4 && (lane & 15) < 4) acc[0][0] += ph2[lane >> 4][lane & 15];
+            // rows and columns 0..nl-1 of the tile: wave 0, tile 0, element
+            // e of lane l is row 4 e + l / 16, column l % 16
+            if (w == 0)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = 4 * e + (lane >> 4), j = lane & 15;
+                    if (i < nl && j < nl) acc[0][e] += ph2[i][j];
+                }
         }
         __syncthreads();
     }
@@ -555,10 +564,10 @@ isci_status density_args(isci_handle h, int nvec, const double *c, int64_t ldc, 
     const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
     const char *d0 = (const char *)d1, *e1 = (const char *)(d1 + nd);
     if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
-    if (h->gas_bnd) {
-        // the Gram form takes the longer rows of a spectator set to be those
-        // of its at most n inner orbitals (the hierarchy's occupied ones)
-        set_error("isci_density1: not built for a GAS-restricted handle");
+    if (h->sa.nocc > kD1MaxInner || h->sb.nocc > kD1MaxInner) {
+        // the Gram form's second phase holds the pairs of a spectator set's
+        // inner rows (those below the level boundary) in a 16 x 16 block
+        set_error("isci_density1: a GAS boundary above 16 orbitals is not supported");
         return ISCI_E_UNSUPPORTED;
     }
     if (h->nb > 0) {
@@ -653,10 +662,6 @@ isci_status isci_density2(isci_handle h, int nvec, const double *c, int64_t ldc,
         const char *c0 = (const char *)c, *c1 = (const char *)(c + (int64_t)(nvec - 1) * ldc + h->dim);
         const char *d0 = (const char *)d2, *e1 = (const char *)(d2 + (int64_t)nvec * 3 * n4);
         if (c0 < e1 && d0 < c1) { set_error("density overlaps c"); return ISCI_E_INVALID; }
-    }
-    if (h->gas_bnd) {
-        set_error("isci_density2: not built for a GAS-restricted handle");
-        return ISCI_E_UNSUPPORTED;
     }
     if (h->na != 2 || h->nb != 2) {
         set_error("isci_density2: two electrons of each spin only");

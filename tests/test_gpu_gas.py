@@ -129,6 +129,41 @@ def test_gas_single_outer_electron_sampled():
     assert ok, err
 
 
+@pytest.mark.parametrize("norb,na,nb,L,b,nvec", [(12, 2, 2, 1, 5, 2), (40, 2, 2, 1, 16, 3), (10, 3, 2, 2, 4, 1),
+                                                  (18, 2, 2, 2, 16, 2), (9, 2, 1, 1, 9, 1)])
+def test_gas_density1_matches_oracle(norb, na, nb, L, b, nvec):
+    """One-body densities of a GAS handle (the Gram form's second phase over
+    the pairs of up to 16 inner rows), and the allocation-free entry point
+    bit for bit against it."""
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    h, eri = recipe_b(norb, seed=8)
+    S = O.Space(norb, na, nb, L, boundary=b)
+    hd = _gas(h, eri, norb, na, nb, L, 1e-12, b)
+    c = random_vectors(S.dim, nvec, seed=3)
+    ct = torch.from_numpy(c).to(dev)
+    got = isci.isci_density1(hd, ct).cpu().numpy()
+    want = O.density1(S, c)
+    assert np.abs(got - want).max() <= TOL * np.abs(want).max()
+    d1 = torch.empty((nvec, 2, norb, norb), dtype=torch.float64, device=dev)
+    isci.isci_density1_noalloc(hd, ct, d1)
+    torch.cuda.synchronize()
+    assert np.array_equal(d1.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("norb,L,b", [(12, 1, 5), (10, 2, 4), (14, 1, 8)])
+def test_gas_density2_matches_oracle(norb, L, b):
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    h, eri = recipe_a(norb, seed=6)
+    S = O.Space(norb, 2, 2, L, boundary=b)
+    hd = _gas(h, eri, norb, 2, 2, L, 0.0, b)
+    c = random_vectors(S.dim, 2, seed=12)
+    got = isci.isci_density2(hd, torch.from_numpy(c).to(dev)).cpu().numpy()
+    want = O.density2(S, c)
+    assert np.abs(got - want).max() <= TOL * np.abs(want).max()
+
+
 def test_gas_errors():
     import paper_1609_07757_amd as isci
     from paper_1609_07757_amd import _lib
@@ -143,12 +178,15 @@ def test_gas_errors():
         assert ei.value.status == _lib.ISCI_E_INVALID
     with pytest.raises(isci.IsciError):
         isci.isci_create(ht, et, norb, 3, 2, 1, 0.0, gas_boundary=2)
-    hd = isci.isci_create(ht, et, norb, 2, 2, 1, 0.0, gas_boundary=4)
+    # one-body densities: at most 16 inner orbitals
+    norb = 20
+    h, eri = recipe_a(norb, seed=0)
+    hd = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), norb, 2, 2, 1, 0.0,
+                          gas_boundary=17)
     c = torch.zeros((1, isci.isci_dim(hd)), dtype=torch.float64, device=dev)
-    for fn in (isci.isci_density1, isci.isci_density2):
-        with pytest.raises(isci.IsciError) as ei:
-            fn(hd, c)
-        assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
+    with pytest.raises(isci.IsciError) as ei:
+        isci.isci_density1(hd, c)
+    assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
     d1 = torch.zeros((1, 2, norb, norb), dtype=torch.float64, device=dev)
     with pytest.raises(isci.IsciError) as ei:
         isci.isci_density1_noalloc(hd, c, d1)
