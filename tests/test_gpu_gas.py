@@ -191,3 +191,68 @@ def test_gas_errors():
     with pytest.raises(isci.IsciError) as ei:
         isci.isci_density1_noalloc(hd, c, d1)
     assert ei.value.status == _lib.ISCI_E_UNSUPPORTED
+
+
+def test_gas_factored_and_distance_screened():
+    """A GAS handle built from factors equals the one built from the dense
+    tensor of the same factors bit for bit; with distance screening it
+    matches the oracle on the masked integrals."""
+    import paper_1609_07757_amd as isci
+    from isci_inputs.recipes import factors_a, orbital_centres
+    torch, dev = torch_dev()
+    norb, L, b, tau = 14, 1, 6, 1e-12
+    h, Lf = factors_a(norb, float(norb), 2 * norb, 4)
+    eri = O.assemble_factored(Lf)
+    S = O.Space(norb, 2, 2, L, boundary=b)
+    c = random_vectors(S.dim, 2, seed=9)
+    ht = torch.from_numpy(np.ascontiguousarray(h)).to(dev)
+    hd = isci.isci_create(ht, torch.from_numpy(eri).to(dev), norb, 2, 2, L, tau, gas_boundary=b)
+    hf = isci.isci_create_factored(ht, torch.from_numpy(np.ascontiguousarray(Lf)).to(dev), norb, 2, 2, L, tau,
+                                   gas_boundary=b)
+    torch.cuda.synchronize()
+    g = gpu_sigma(hd, c)
+    assert np.array_equal(g, gpu_sigma(hf, c))
+    assert rel_err(g, O.sigma(S, h, eri, tau, c)) <= TOL
+    x = orbital_centres(norb, float(norb), 2 * norb, 4)
+    dist = np.abs(x[:, None] - x[None, :])
+    hm, em = O.mask_by_distance(h, eri, dist, 4.0)
+    hs = isci.isci_create(ht, torch.from_numpy(eri).to(dev), norb, 2, 2, L, tau, gas_boundary=b,
+                          orb_dist=dist, max_dist=4.0)
+    torch.cuda.synchronize()
+    assert rel_err(gpu_sigma(hs, c), O.sigma(S, hm, em, tau, c)) <= TOL
+
+
+def test_gas_engine_and_propagation():
+    """GAS handles in the multi-solve engine beside a hierarchy handle give
+    the energies of their own Davidson solves and of the oracle's dense
+    spectrum; imaginary-time propagation on a GAS handle falls to the
+    lowest of them."""
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    cases = [(12, 1, 5, 2), (10, 2, 4, 1)]
+    handles, refs = [], []
+    for norb, L, b, nroots in cases:
+        h, eri = recipe_a(norb, seed=norb)
+        S = O.Space(norb, 2, 2, L, boundary=b)
+        refs.append(np.linalg.eigvalsh(O.dense_h(S, h, eri, 0.0))[:nroots])
+        handles.append((_gas(h, eri, norb, 2, 2, L, 0.0, b), nroots))
+    h, eri = recipe_a(10, seed=3)
+    hh = isci.isci_create(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), 10, 2, 2, 2, 0.0)
+    refs.append(np.linalg.eigvalsh(O.dense_h(O.Space(10, 2, 2, 2), h, eri, 0.0))[:1])
+    handles.append((hh, 1))
+    eng = isci.isci_engine_create()
+    slots = [isci.isci_engine_add(eng, hd, nroots=k, tol_residual=1e-8) for hd, k in handles]
+    for _ in range(400):
+        if isci.isci_engine_step(eng) == 0:
+            break
+    for s, (hd, k), ref in zip(slots, handles, refs):
+        done, e, _v, info = isci.isci_engine_result(eng, s)
+        assert done and info["converged"]
+        assert np.abs(e - ref).max() <= 1e-10
+        e1, _, _ = isci.isci_davidson(hd, nroots=k, tol_residual=1e-8)
+        assert np.abs(e1 - ref).max() <= 1e-10
+    eng.destroy()
+    hd, _ = handles[0]
+    c0 = torch.from_numpy(random_vectors(hd.dim, 1, seed=2)[0]).to(dev)
+    info = isci.isci_propagate(hd, c0, 0.5, 120)   # t = 60: 3.6e-12 above the ground energy (gap 0.21)
+    assert abs(info["energy"] - refs[0][0]) <= 1e-8
