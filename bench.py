@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # revision of each kernel's code: stored HBM traffic (profiles/sigma_traffic.json)
 # is used only when it was counted for the same revision
-KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs, 16-byte operand loads, 128-column tiles in 512-column slabs, packed chunks"}
+KERNEL_REV = {"k_ab_gemm": "slab-major tiles, scalar chunk table, step-aligned parts, 80 VGPRs, 16-byte operand loads, 128-column tiles in 512-column slabs, packed chunks, block levels from the level boundary"}
 HBM_PEAK_GBS = 8000.0
 METRIC = "σ-vectors/s + screened terms/s (% roofline); p50/p99 Davidson solve latency"
 
