@@ -256,3 +256,24 @@ def test_gas_engine_and_propagation():
     c0 = torch.from_numpy(random_vectors(hd.dim, 1, seed=2)[0]).to(dev)
     info = isci.isci_propagate(hd, c0, 0.5, 120)   # t = 60: 3.6e-12 above the ground energy (gap 0.21)
     assert abs(info["energy"] - refs[0][0]) <= 1e-8
+
+
+@pytest.mark.parametrize("norb,na,nb,L,b", [(3, 2, 2, 1, 2), (4, 2, 2, 1, 3), (5, 2, 2, 0, 5), (6, 2, 2, 2, 2),
+                                           (9, 2, 2, 3, 6), (23, 2, 2, 2, 7), (21, 2, 2, 1, 13)])
+def test_gas_edges(norb, na, nb, L, b):
+    """Tiny spaces (fewer than three orbitals outside or inside), the
+    boundary at n (the hierarchy, with the one-body units in the tiles),
+    limits above what the outer space can hold, and boundaries that cut an
+    orbital block (7, 13) with several outer blocks."""
+    import paper_1609_07757_amd as isci
+    h, eri = recipe_b(norb, seed=norb + b)
+    tau = 1e-12
+    S = O.Space(norb, na, nb, L, boundary=b)
+    hd = _gas(h, eri, norb, na, nb, L, tau, b)
+    assert isci.isci_dim(hd) == S.dim
+    c = random_vectors(S.dim, 3, seed=b)
+    got = gpu_sigma(hd, c)
+    assert rel_err(got, O.sigma(S, h, eri, tau, c)) <= TOL
+    if b == na:
+        from gpu_common import create
+        assert rel_err(gpu_sigma(create(h, eri, norb, na, nb, L, tau), c), got) <= TOL
