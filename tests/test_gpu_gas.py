@@ -7,6 +7,7 @@ the oracle built on the same space (oracle.Space(..., boundary=b)).
 Bar: sigma |delta| <= 1e-12 * ||sigma||_inf (the oracle's); strings, row
 starts and term counts exact; Davidson energies within 1e-10 Eh of the
 oracle's dense spectrum."""
+import functools
 
 import numpy as np
 import pytest
@@ -114,17 +115,39 @@ def test_gas_davidson_energies():
     assert e0[0] > e0[1] > e0[2]
 
 
-def test_gas_single_outer_electron_sampled():
-    """At the benchmark's shape (200 orbitals, 16 inner, at most one
-    electron outside them, eight vectors): sampled targets, row ends
-    included."""
-    norb, b, L, tau = 200, 16, 1, 1e-12
-    h, eri = recipe_a(norb, seed=1)
+@functools.lru_cache(maxsize=1)
+def _ints200():
+    return recipe_a(200, seed=1)
+
+
+@pytest.mark.parametrize("L,nvec", [(1, 8), (2, 2)])
+def test_gas_outer_electrons_sampled(L, nvec):
+    """200 orbitals, 16 inner: at most one electron outside them (the
+    benchmark's shape, 720,960 determinants, eight vectors) and at most two
+    (13.4 million determinants): sampled targets, row ends included."""
+    norb, b, tau = 200, 16, 1e-12
+    h, eri = _ints200()
     S = O.Space(norb, 2, 2, L, boundary=b)
     hd = _gas(h, eri, norb, 2, 2, L, tau, b)
-    c = random_vectors(S.dim, 8, seed=21)
+    c = random_vectors(S.dim, nvec, seed=21)
     got = gpu_sigma(hd, c)
     tg = sample_targets(S.rowstart(), S.dim, 300, seed=5)
+    ok, err = sampled_ok(got, tg, O.sigma(S, h, eri, tau, c, targets=tg), TOL)
+    assert ok, err
+
+
+def test_gas_gathered_tiles_above_128_orbitals():
+    """The gathered tile kernel without its LDS lookup tables (above 128
+    orbitals) on a GAS handle: sampled targets against the oracle."""
+    import paper_1609_07757_amd as isci
+    norb, b, L, tau = 140, 12, 1, 1e-12
+    h, eri = recipe_a(norb, seed=2)
+    S = O.Space(norb, 2, 2, L, boundary=b)
+    hd = _gas(h, eri, norb, 2, 2, L, tau, b, kernel=isci.SIGMA_MFMA)
+    isci.isci_set_option(hd, isci.OPT_AB_PATH, isci.AB_GATHER)
+    c = random_vectors(S.dim, 2, seed=4)
+    got = gpu_sigma(hd, c)
+    tg = sample_targets(S.rowstart(), S.dim, 300, seed=6)
     ok, err = sampled_ok(got, tg, O.sigma(S, h, eri, tau, c, targets=tg), TOL)
     assert ok, err
 
