@@ -663,8 +663,9 @@ __global__ __launch_bounds__(256) void k_chunk_fill(const unsigned *bits, EriSrc
 // tiles by default (fewer launches; measured faster up to about 10^5)
 static constexpr int64_t kObTilesMaxDim = 65536;
 
-// blocks of four orbitals, o/v pure (two electrons per spin: the occupied
-// block is {0, 1, -, -}); target tiles with level <= L; column chunks
+// blocks of four orbitals, inner / outer pure (split at the level boundary;
+// for the excitation hierarchy the occupied block is {0, 1, -, -}); target
+// tiles with level <= L; column chunks
 static isci_status build_tiles(isci_ctx *c, const EriSrc &E, hipStream_t s)
 {
     const int n = c->norb;
@@ -1545,8 +1546,7 @@ isci_status isci_set_option(isci_handle c, int option, int value)
             return ISCI_E_UNSUPPORTED;
         }
         if (value == ISCI_SIGMA_MFMA && !c->have_tiles) {
-            set_error("matrix-core kernel not built for a GAS-restricted handle (its operand blocks take orbitals 0 "
-                      "and 1 as the occupied block)");
+            set_error("matrix-core kernel: its tiles were not built for this handle");
             return ISCI_E_UNSUPPORTED;
         }
         c->sigma_variant = value;

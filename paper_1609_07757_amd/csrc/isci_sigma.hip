@@ -335,7 +335,7 @@ __device__ __forceinline__ void sigma_target_n2(const SigmaArgs &A, int ia, int 
 // i.e. for fixed spectators (x, y) a product with the screened matrix
 // W[(p,r),(q,s)] = (pq|rs) (the alpha-beta ladder of Eqs. h200ca..h200ab
 // when all four indices are virtual).  Orbitals are grouped in blocks of
-// four (o/v pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
+// four (inner / outer pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
 // block X, p in P, y in Y, r in R and computes the four role products
 // (which of x/p and y/r is the spectator) on four waves, one
 // 16 x 16 x 4 MFMA per (column chunk, vector): rows = the 16 active pairs,
@@ -386,7 +386,7 @@ __device__ __forceinline__ void gather_b(const SigmaArgs &A, const double *__res
 // i.e. for fixed spectators (x, y) a product with the screened matrix
 // W[(p,r),(q,s)] = (pq|rs) (the alpha-beta ladder of Eqs. h200ca..h200ab
 // when all four indices are virtual).  Orbitals are grouped in blocks of
-// four (o/v pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
+// four (inner / outer pure); a workgroup owns the sigma tile {x,p} x {y,r} with x in
 // block X, p in P, y in Y, r in R and computes the four role products
 // (which of x/p and y/r is the spectator) on four waves, one
 // 16 x 16 x 4 MFMA per (column chunk, vector): rows = the 16 active pairs,
