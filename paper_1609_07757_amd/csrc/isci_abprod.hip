@@ -50,6 +50,7 @@ typedef double v4d_ab __attribute__((ext_vector_type(4)));
 //   T[(q, s)][(x, y, v)] = sgn(q - x) sgn(s - y) c_v({x,q},{y,s}).
 // Every entry of T belongs to at most one determinant; entries that belong
 // to none were zeroed when T was allocated.  Vectors v >= nv write zeros.
+template <int VS>
 __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const double *__restrict__ c, int64_t ldc)
 {
     int ia, j0, len;
@@ -60,9 +61,9 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
     const uint32_t as = A.astr[ia], bs = A.bstr[jb];
     const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
     const int64_t addr = A.rowstart[ia] + jb;
-    double cv[4];
+    double cv[VS];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) cv[v] = v < nv ? c[(int64_t)v * ldc + addr] : 0.0;
+    for (int v = 0; v < VS; ++v) cv[v] = v < nv ? c[(int64_t)v * ldc + addr] : 0.0;
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra) {
         const int x = ra ? a1 : a0, q = ra ? a0 : a1;   // alpha spectator, active
@@ -72,11 +73,11 @@ __global__ __launch_bounds__(256) void k_ab_unfold(SigmaArgs A, int nv, const do
             const int2 tq = A.abx_tq[q * nb + ab_block(A, s)];
             if (tq.y == 0) continue;   // no chunk reads this row
             const int D = ab_block(A, y);
-            const int col = A.abx_gofs[ab_block(A, x) * nb + D] + (ab_slot(A, x) * ab_width(A, D) + ab_slot(A, y)) * 4;
+            const int col = A.abx_gofs[ab_block(A, x) * nb + D] + (ab_slot(A, x) * ab_width(A, D) + ab_slot(A, y)) * VS;
             double *dst = A.abx_T + (size_t)tq.x + (size_t)ab_slot(A, s) * tq.y + col;
             const double f = (ra ^ rb) ? -1.0 : 1.0;   // sgn(q - x) sgn(s - y)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dst[v] = f * cv[v];
+            for (int v = 0; v < VS; ++v) dst[v] = f * cv[v];
         }
     }
 }
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(64 * CW * KS) void k_ab_pipe(SigmaArgs A)
 // sigma({a0 < a1}, {b0 < b1}) = sum over the four readings (alpha
 // spectator, alpha active) x (beta spectator, beta active) of S, sign - per
 // spin whose spectator is the larger orbital
+template <int VS>
 __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__restrict__ sg, int64_t lds,
                                                  int accumulate)
 {
@@ -333,7 +335,9 @@ __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__
     const int nb = A.nblk;
     const uint32_t as = A.astr[ia], bs = A.bstr[jb];
     const int a0 = as & 0xff, a1 = (as >> 8) & 0xff, b0 = bs & 0xff, b1 = (bs >> 8) & 0xff;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[VS];
+#pragma unroll
+    for (int v = 0; v < VS; ++v) acc[v] = 0.0;
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra) {
         const int xs = ra ? a1 : a0, xa = ra ? a0 : a1;   // alpha spectator, active
@@ -345,43 +349,74 @@ __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__
             if (so < 0) continue;
             const int m = ab_outer(A, ab_block(A, xa)) + ab_outer(A, ab_block(A, ya));
             const int C = ab_block(A, xs), D = ab_block(A, ys);
-            const int col = A.abx_gofs[C * nb + D] + (ab_slot(A, xs) * ab_width(A, D) + ab_slot(A, ys)) * 4;
+            const int col = A.abx_gofs[C * nb + D] + (ab_slot(A, xs) * ab_width(A, D) + ab_slot(A, ys)) * VS;
             const int row = ab_slot(A, xa) * 4 + ab_slot(A, ya);
             const double *src = A.abx_S + (size_t)so + (size_t)row * A.abx_pcols[m] + col;
             const double f = (ra ^ rb) ? -1.0 : 1.0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += f * src[v];
+            for (int v = 0; v < VS; ++v) acc[v] += f * src[v];
         }
     }
     double *dst = sg + A.rowstart[ia] + jb;
     if (accumulate) {
-        double old[4];
+        double old[VS];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) old[v] = dst[(int64_t)min(v, nv - 1) * lds];
+        for (int v = 0; v < VS; ++v) old[v] = dst[(int64_t)min(v, nv - 1) * lds];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < VS; ++v)
             if (v < nv) dst[(int64_t)v * lds] = old[v] + acc[v];
     } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < VS; ++v)
             if (v < nv) dst[(int64_t)v * lds] = acc[v];
     }
+}
+
+// A pass of one vector takes the single-vector layout (one vector slot per
+// spectator pair: a quarter of the four-slot operands and product) when it
+// is built and the packed product is selected
+static bool single_slot(const isci_ctx *cx, int nv)
+{
+    return nv == 1 && cx->have_abx1 && cx->ab_kernel == ISCI_AB_PACKED && cx->abx1_pxmax > 0;
+}
+
+// arguments of the product path for a pass of nv vectors
+static SigmaArgs product_args(const isci_ctx *cx, int nv)
+{
+    SigmaArgs A = sigma_args(cx);
+    if (single_slot(cx, nv)) {
+        A.abx_vs = 1;
+        A.abx_gofs = cx->d.abx1_gofs;
+        A.abx_tq = cx->d.abx1_tq;
+        A.abx_soff = cx->d.abx1_soff;
+        A.abx_pchunk = cx->d.abx1_pchunk;
+        A.abx_pblk = cx->d.abx1_pblk;
+        A.abx_T = cx->d.abx1_T;
+        for (int k = 0; k < 3; ++k) A.abx_pcols[k] = cx->abx1_pcols[k];
+    }
+    return A;
 }
 
 isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *Sbuf,
                                   hipStream_t st)
 {
-    SigmaArgs A = sigma_args(cx);
+    SigmaArgs A = product_args(cx, nv);
     A.abx_S = Sbuf;
+    const bool one = A.abx_vs == 1;
     if (cx->abx_ntrow > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
-        k_ab_unfold<<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
+        if (one)
+            k_ab_unfold<1><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
+        else
+            k_ab_unfold<4><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, false, st));
     }
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
         const dim3 grid((unsigned)(8 * cx->abx_xmax)), block(64 * kAbCW * kAbSplit);
-        if (cx->ab_kernel == ISCI_AB_PACKED && cx->abx_pxmax > 0)
+        if (one)
+            k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abx1_pxmax)), block, 0, st>>>(A);
+        else if (cx->ab_kernel == ISCI_AB_PACKED && cx->abx_pxmax > 0)
             k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abx_pxmax)), block, 0, st>>>(A);
         else if (cx->ab_kernel == ISCI_AB_PIPE)
             k_ab_pipe<kAbCW, kAbSplit, 2><<<grid, block, 0, st>>>(A);
@@ -398,10 +433,13 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
 isci_status launch_ab_fold(const isci_ctx *cx, int nv, const double *Sbuf, double *s, int64_t lds, bool accumulate,
                            hipStream_t st)
 {
-    SigmaArgs A = sigma_args(cx);
+    SigmaArgs A = product_args(cx, nv);
     A.abx_S = const_cast<double *>(Sbuf);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));
-    k_ab_fold<<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
+    if (A.abx_vs == 1)
+        k_ab_fold<1><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
+    else
+        k_ab_fold<4><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, false, st));
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;

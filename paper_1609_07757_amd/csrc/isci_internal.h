@@ -133,6 +133,15 @@ struct DevTabs {
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
+    // the single-vector layout of the packed product (one vector slot per
+    // spectator pair instead of four), its own T (zero where no determinant
+    // writes) and its tables; S is shared with the four-slot layout
+    int *abx1_gofs = nullptr;
+    int2 *abx1_tq = nullptr;
+    long long *abx1_soff = nullptr;
+    int4 *abx1_pchunk = nullptr;
+    AbBlk *abx1_pblk = nullptr;
+    double *abx1_T = nullptr;
     double *obT_c = nullptr;        // [obT_nv][dim] transposed CI block (beta one-body above kObMaxNorb,
                                     // full-CI alpha one-body)
     double *obT_s = nullptr;        // [obT_nv][dim] its one-body image
@@ -195,6 +204,7 @@ struct SigmaArgs {
     int nchunk;              // chunks of W; chunk_val holds one more, all zero
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
+    int abx_vs;              // vector slots per spectator pair in the product operands (4, or 1)
 };
 
 // Orbital blocks of the matrix-core path: the inner orbitals 0..b-1 (the
@@ -280,6 +290,8 @@ struct isci_ctx {
     int abx_xmax = 0;        // longest XCD tile run
     int abx_pxmax = 0;       // the same over the packed chunk lists (0: not built)
     int npchunk = 0;         // packed chunks
+    bool have_abx1 = false;  // single-vector layout of the packed product built
+    int abx1_pcols[3] = {0, 0, 0}, abx1_pxmax = 0;
     int ab_kernel = ISCI_AB_PACKED;  // ISCI_OPT_AB_PRODUCT: packed wide-load k_ab_gemm (default), wide, plain, pipe
     int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
     int obT_nv = 4;                            // vectors of the transposed one-body scratch (4 or 8)

@@ -536,6 +536,7 @@ SigmaArgs sigma_args(const isci_ctx *c)
     A.abx_T = c->d.abx_T;
     A.abx_S = c->d.abx_S;
     for (int k = 0; k < 3; ++k) A.abx_pcols[k] = c->abx_pcols[k];
+    A.abx_vs = 4;
     return A;
 }
 
@@ -789,29 +790,6 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     auto width = [&](int B) { return B < nib ? std::min(4, bnd - 4 * B) : 4; };
     auto orbital = [&](int B, int i) { return B < nib ? 4 * B + i : bnd + 4 * (B - nib) + i; };
     auto outer = [&](int B) { return B >= nib ? 1 : 0; };
-    // column groups, level by level, each level padded to 64 columns
-    std::vector<int> gofs((size_t)nb * nb, -1);
-    std::vector<int> col;
-    int plev[3] = {0, 0, 0};
-    for (int lev = 0; lev <= 2; ++lev) {
-        if (lev <= L)
-            for (int C = 0; C < nb; ++C)
-                for (int D = 0; D < nb; ++D) {
-                    if (outer(C) + outer(D) != lev) continue;
-                    gofs[(size_t)C * nb + D] = (int)col.size();
-                    for (int ic = 0; ic < width(C); ++ic)
-                        for (int id = 0; id < width(D); ++id) {
-                            const int x = orbital(C, ic);
-                            const int y = orbital(D, id);
-                            for (int v = 0; v < 4; ++v)
-                                col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
-                        }
-                }
-        while (col.size() % 64) col.push_back(255 | (255 << 8));
-        plev[lev] = (int)col.size();
-    }
-    int pcols[3];
-    for (int k = 0; k < 3; ++k) pcols[k] = L - k < 0 ? 0 : plev[std::min(2, L - k)];
     // chunk lists from the device
     std::vector<int> off(nb * nb + 1), cls(3 * nb * nb);
     std::vector<int2> desc(c->nchunk);
@@ -819,41 +797,75 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     ISCI_HIP(hipMemcpyAsync(cls.data(), c->d.chunk_cls, sizeof(int) * cls.size(), hipMemcpyDeviceToHost, s));
     ISCI_HIP(hipMemcpyAsync(desc.data(), c->d.chunk_desc, sizeof(int2) * c->nchunk, hipMemcpyDeviceToHost, s));
     ISCI_HIP(hipStreamSynchronize(s));
-    // T rows: each (q, S) opening a chunk whose class admits some spectator
-    std::vector<int> krow_of((size_t)n * nb, -1);
-    std::vector<int4> trow;
-    std::vector<int2> chunk(c->nchunk, make_int2(0, 0));
-    size_t tsize = 0;
-    for (int g = 0; g < nb * nb; ++g) {
-        int e = off[g];
-        for (int l = 0; l < 3; ++l)
-            for (int i = 0; i < cls[3 * g + l]; ++i, ++e) {
-                if (pcols[l] == 0) continue;
-                const int q = desc[e].x, S = desc[e].y;
-                int &kr = krow_of[(size_t)q * nb + S];
-                if (kr < 0) {
-                    kr = (int)trow.size();
-                    trow.push_back(make_int4(q, S, (int)0, pcols[l]));
-                    if (tsize + (size_t)4 * pcols[l] > (size_t)INT32_MAX) return ISCI_OK;   // offsets stay int
-                    trow.back().z = (int)tsize;
-                    tsize += (size_t)4 * pcols[l];
+    // The operand layout for VS vector slots per spectator pair (four for the
+    // passes of a sigma call, one for single-vector calls): column groups
+    // level by level (each level padded to 64 columns), the valid prefix of
+    // each class, the T rows (4 per (q, S) that opens a chunk whose class
+    // admits some spectator) and the S blocks (row block pairs holding chunks)
+    struct Layout {
+        std::vector<int> gofs, col, rows;
+        int pcols[3] = {0, 0, 0};
+        std::vector<int> krow_of;
+        std::vector<int4> trow;
+        std::vector<int2> chunk;
+        std::vector<long long> soff;
+        size_t tsize = 0, ssize = 0;
+        bool fits = true;
+    };
+    auto layout = [&](int VS, Layout &Y) {
+        Y.gofs.assign((size_t)nb * nb, -1);
+        int plev[3] = {0, 0, 0};
+        for (int lev = 0; lev <= 2; ++lev) {
+            if (lev <= L)
+                for (int C = 0; C < nb; ++C)
+                    for (int D = 0; D < nb; ++D) {
+                        if (outer(C) + outer(D) != lev) continue;
+                        Y.gofs[(size_t)C * nb + D] = (int)Y.col.size();
+                        for (int ic = 0; ic < width(C); ++ic)
+                            for (int id = 0; id < width(D); ++id) {
+                                const int x = orbital(C, ic);
+                                const int y = orbital(D, id);
+                                for (int v = 0; v < VS; ++v)
+                                    Y.col.push_back((x < n ? x : 255) | ((y < n ? y : 255) << 8) | (v << 16));
+                            }
+                    }
+            while (Y.col.size() % 64) Y.col.push_back(255 | (255 << 8));
+            plev[lev] = (int)Y.col.size();
+        }
+        for (int k = 0; k < 3; ++k) Y.pcols[k] = L - k < 0 ? 0 : plev[std::min(2, L - k)];
+        Y.krow_of.assign((size_t)n * nb, -1);
+        Y.chunk.assign(c->nchunk, make_int2(0, 0));
+        for (int g = 0; g < nb * nb; ++g) {
+            int e = off[g];
+            for (int l = 0; l < 3; ++l)
+                for (int i = 0; i < cls[3 * g + l]; ++i, ++e) {
+                    if (Y.pcols[l] == 0) continue;
+                    const int q = desc[e].x, S = desc[e].y;
+                    int &kr = Y.krow_of[(size_t)q * nb + S];
+                    if (kr < 0) {
+                        kr = (int)Y.trow.size();
+                        Y.trow.push_back(make_int4(q, S, (int)0, Y.pcols[l]));
+                        if (Y.tsize + (size_t)4 * Y.pcols[l] > (size_t)INT32_MAX) { Y.fits = false; return; }   // offsets stay int
+                        Y.trow.back().z = (int)Y.tsize;
+                        Y.tsize += (size_t)4 * Y.pcols[l];
+                    }
+                    Y.chunk[e] = make_int2(Y.trow[kr].z, Y.trow[kr].w);
                 }
-                chunk[e] = make_int2(trow[kr].z, trow[kr].w);
-            }
-    }
-    // S blocks: row block pairs holding chunks
-    std::vector<long long> soff((size_t)nb * nb, -1);
-    std::vector<int> rows;
-    size_t ssize = 0;
-    for (int g = 0; g < nb * nb; ++g) {
-        const int m = outer(g / nb) + outer(g % nb);
-        if (off[g + 1] == off[g] || pcols[m] == 0) continue;
-        soff[g] = (long long)ssize;
-        rows.push_back(g);
-        ssize += (size_t)16 * pcols[m];
-    }
-    const size_t tbytes = sizeof(double) * std::max<size_t>(1, tsize);
-    const size_t sbytes = sizeof(double) * std::max<size_t>(1, ssize);
+        }
+        Y.soff.assign((size_t)nb * nb, -1);
+        for (int g = 0; g < nb * nb; ++g) {
+            const int m = outer(g / nb) + outer(g % nb);
+            if (off[g + 1] == off[g] || Y.pcols[m] == 0) continue;
+            Y.soff[g] = (long long)Y.ssize;
+            Y.rows.push_back(g);
+            Y.ssize += (size_t)16 * Y.pcols[m];
+        }
+    };
+    Layout Y4;
+    layout(4, Y4);
+    if (!Y4.fits) return ISCI_OK;
+    const size_t tbytes = sizeof(double) * std::max<size_t>(1, Y4.tsize);
+    const size_t sbytes = sizeof(double) * std::max<size_t>(1, Y4.ssize);
     if (tbytes + sbytes > kAbxMaxBytes) return ISCI_OK;   // gathered kernel instead
     // product tiles column slab by column slab (all row block pairs of a
     // slab of kAbSlabCols columns together: the slab of T they read, a few
@@ -861,14 +873,15 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     // pair in a slab next to each other (their chunk values are read from
     // memory once and then from L2), cost ~ chunks applied + 1, cut into
     // eight contiguous runs of about equal cost (one per XCD); for the chunk
-    // lists given by (offsets, class counts)
-    auto make_tiles = [&](const std::vector<int> &loff, const std::vector<int> &lcls, int &xmax_out) {
+    // lists given by (offsets, class counts) and a layout's columns
+    auto make_tiles = [&](const std::vector<int> &loff, const std::vector<int> &lcls, const Layout &Y, int &xmax_out) {
+        const int *pcols = Y.pcols;
         std::vector<int2> tiles;
         std::vector<double> cost;
         const int nslab = (std::max(pcols[0], std::max(pcols[1], pcols[2])) + kAbTile - 1) / kAbTile;
         constexpr int sgrp = kAbSlabCols / kAbTile;
         for (int sg = 0; sg < nslab; sg += sgrp)
-            for (int g : rows)
+            for (int g : Y.rows)
                 for (int sl = sg; sl < std::min(sg + sgrp, nslab); ++sl) {
                     const int m = outer(g / nb) + outer(g % nb);
                     if (sl * kAbTile >= pcols[m]) continue;
@@ -911,23 +924,25 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         return blk;
     };
     int xmax = 0;
-    const std::vector<AbBlk> blk = make_tiles(off, cls, xmax);
+    const std::vector<AbBlk> blk = make_tiles(off, cls, Y4, xmax);
     // packed chunks: the columns (q, s) of a row block pair's chunks of one
     // class that hold a kept value, four per chunk in list order (a short
-    // last chunk of a class is filled with zero columns reading a valid row)
+    // last chunk of a class is filled with zero columns reading a valid row);
+    // psel keeps each packed column's (chunk, column k) so the row offsets of
+    // another layout follow from the same selection
     std::vector<double> cval((size_t)64 * c->nchunk);
     ISCI_HIP(hipMemcpyAsync(cval.data(), c->d.chunk_val, sizeof(double) * cval.size(), hipMemcpyDeviceToHost, s));
     ISCI_HIP(hipStreamSynchronize(s));
     std::vector<int> poff(nb * nb + 1, 0), pcls(3 * nb * nb, 0);
-    std::vector<int4> pchunk;
+    std::vector<int2> psel;
     std::vector<double> pval;
     for (int g = 0; g < nb * nb; ++g) {
-        poff[g] = (int)pchunk.size();
+        poff[g] = (int)(psel.size() / 4);
         int e = off[g];
         for (int l = 0; l < 3; ++l) {
             std::vector<int2> cols;   // (chunk, column k)
             for (int i = 0; i < cls[3 * g + l]; ++i, ++e) {
-                if (pcols[l] == 0) continue;
+                if (Y4.pcols[l] == 0) continue;
                 for (int k = 0; k < 4; ++k) {
                     bool any = false;
                     for (int r = 0; r < 16; ++r) any |= cval[(size_t)e * 64 + 16 * k + r] != 0.0;
@@ -936,33 +951,61 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
             }
             const int npc = (int)(cols.size() + 3) / 4;
             for (int pc = 0; pc < npc; ++pc) {
-                int rowk[4];
                 const size_t base = pval.size();
                 pval.resize(base + 64, 0.0);
                 for (int k = 0; k < 4; ++k) {
                     const size_t ci = (size_t)pc * 4 + k;
                     const int2 ck = cols[ci < cols.size() ? ci : (size_t)pc * 4];
-                    rowk[k] = chunk[ck.x].x + ck.y * chunk[ck.x].y;
+                    psel.push_back(ck);
                     if (ci < cols.size())
                         for (int r = 0; r < 16; ++r) pval[base + 16 * k + r] = cval[(size_t)ck.x * 64 + 16 * ck.y + r];
                 }
-                pchunk.push_back(make_int4(rowk[0], rowk[1], rowk[2], rowk[3]));
             }
             pcls[3 * g + l] = npc;
         }
     }
-    poff[nb * nb] = (int)pchunk.size();
+    poff[nb * nb] = (int)(psel.size() / 4);
+    auto pchunk_of = [&](const Layout &Y) {
+        std::vector<int4> pc(psel.size() / 4);
+        for (size_t i = 0; i < pc.size(); ++i) {
+            int rowk[4];
+            for (int k = 0; k < 4; ++k) {
+                const int2 ck = psel[4 * i + k];
+                rowk[k] = Y.chunk[ck.x].x + ck.y * Y.chunk[ck.x].y;
+            }
+            pc[i] = make_int4(rowk[0], rowk[1], rowk[2], rowk[3]);
+        }
+        return pc;
+    };
+    const std::vector<int4> pchunk = pchunk_of(Y4);
     int pxmax = 0;
-    const std::vector<AbBlk> pblk = make_tiles(poff, pcls, pxmax);
+    const std::vector<AbBlk> pblk = make_tiles(poff, pcls, Y4, pxmax);
+    // the single-vector layout (packed product only): its own column groups,
+    // T rows and S blocks over the same chunks, and its own T, whose entries
+    // that no determinant fills must stay zero (S is shared)
+    Layout Y1;
+    layout(1, Y1);
+    int pxmax1 = 0;
+    std::vector<int4> pchunk1;
+    std::vector<AbBlk> pblk1;
+    if (Y1.fits && Y1.ssize <= Y4.ssize && !pchunk.empty()) {
+        pchunk1 = pchunk_of(Y1);
+        pblk1 = make_tiles(poff, pcls, Y1, pxmax1);
+    }
+    std::vector<int2> tq((size_t)n * nb, make_int2(0, 0)), tq1((size_t)n * nb, make_int2(0, 0));
+    for (size_t i = 0; i < tq.size(); ++i) {
+        if (Y4.krow_of[i] >= 0) tq[i] = make_int2(Y4.trow[Y4.krow_of[i]].z, Y4.trow[Y4.krow_of[i]].w);
+        if (!pblk1.empty() && Y1.krow_of[i] >= 0) tq1[i] = make_int2(Y1.trow[Y1.krow_of[i]].z, Y1.trow[Y1.krow_of[i]].w);
+    }
     DevTabs &d = c->d;
-    d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * gofs.size());
-    d.abx_col = (int *)dev_alloc(c, sizeof(int) * col.size());
-    d.abx_trow = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, trow.size()));
+    d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * Y4.gofs.size());
+    d.abx_col = (int *)dev_alloc(c, sizeof(int) * Y4.col.size());
+    d.abx_trow = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, Y4.trow.size()));
     d.abx_tq = (int2 *)dev_alloc(c, sizeof(int2) * (size_t)n * nb);
-    d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * chunk.size());
-    d.abx_ctof = (int *)dev_alloc(c, sizeof(int) * (chunk.size() + 8));
-    d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, rows.size()));
-    d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * soff.size());
+    d.abx_chunk = (int2 *)dev_alloc(c, sizeof(int2) * Y4.chunk.size());
+    d.abx_ctof = (int *)dev_alloc(c, sizeof(int) * (Y4.chunk.size() + 8));
+    d.abx_rows = (int *)dev_alloc(c, sizeof(int) * std::max<size_t>(1, Y4.rows.size()));
+    d.abx_soff = (long long *)dev_alloc(c, sizeof(long long) * Y4.soff.size());
     d.abx_blk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * blk.size());
     d.abx_pchunk = (int4 *)dev_alloc(c, sizeof(int4) * std::max<size_t>(1, pchunk.size()));
     d.pchunk_val = (double *)dev_alloc(c, sizeof(double) * std::max<size_t>(64, pval.size()));
@@ -974,41 +1017,57 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         set_error("device allocation failed (alpha-beta product)");
         return ISCI_E_OOM;
     }
-    ISCI_HIP(hipMemcpyAsync(d.abx_gofs, gofs.data(), sizeof(int) * gofs.size(), hipMemcpyHostToDevice, s));
-    ISCI_HIP(hipMemcpyAsync(d.abx_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
-    if (!trow.empty())
-        ISCI_HIP(hipMemcpyAsync(d.abx_trow, trow.data(), sizeof(int4) * trow.size(), hipMemcpyHostToDevice, s));
-    {
-        std::vector<int2> tq((size_t)n * nb, make_int2(0, 0));
-        for (size_t i = 0; i < tq.size(); ++i)
-            if (krow_of[i] >= 0) tq[i] = make_int2(trow[krow_of[i]].z, trow[krow_of[i]].w);
-        ISCI_HIP(hipMemcpyAsync(d.abx_tq, tq.data(), sizeof(int2) * tq.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipStreamSynchronize(s));
-    }
+    ISCI_HIP(hipMemcpyAsync(d.abx_gofs, Y4.gofs.data(), sizeof(int) * Y4.gofs.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_col, Y4.col.data(), sizeof(int) * Y4.col.size(), hipMemcpyHostToDevice, s));
+    if (!Y4.trow.empty())
+        ISCI_HIP(hipMemcpyAsync(d.abx_trow, Y4.trow.data(), sizeof(int4) * Y4.trow.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_tq, tq.data(), sizeof(int2) * tq.size(), hipMemcpyHostToDevice, s));
     // entries of T that no determinant of the space fills stay zero; the
     // scatter unfold writes the others every call
     ISCI_HIP(hipMemsetAsync(d.abx_T, 0, tbytes, s));
-    ISCI_HIP(hipMemcpyAsync(d.abx_chunk, chunk.data(), sizeof(int2) * chunk.size(), hipMemcpyHostToDevice, s));
-    std::vector<int> ctof(chunk.size() + 8, 0);
-    for (size_t e = 0; e < chunk.size(); ++e) ctof[e] = chunk[e].x;
+    ISCI_HIP(hipMemcpyAsync(d.abx_chunk, Y4.chunk.data(), sizeof(int2) * Y4.chunk.size(), hipMemcpyHostToDevice, s));
+    std::vector<int> ctof(Y4.chunk.size() + 8, 0);
+    for (size_t e = 0; e < Y4.chunk.size(); ++e) ctof[e] = Y4.chunk[e].x;
     ISCI_HIP(hipMemcpyAsync(d.abx_ctof, ctof.data(), sizeof(int) * ctof.size(), hipMemcpyHostToDevice, s));
-    if (!rows.empty())
-        ISCI_HIP(hipMemcpyAsync(d.abx_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
-    ISCI_HIP(hipMemcpyAsync(d.abx_soff, soff.data(), sizeof(long long) * soff.size(), hipMemcpyHostToDevice, s));
+    if (!Y4.rows.empty())
+        ISCI_HIP(hipMemcpyAsync(d.abx_rows, Y4.rows.data(), sizeof(int) * Y4.rows.size(), hipMemcpyHostToDevice, s));
+    ISCI_HIP(hipMemcpyAsync(d.abx_soff, Y4.soff.data(), sizeof(long long) * Y4.soff.size(), hipMemcpyHostToDevice, s));
     ISCI_HIP(hipMemcpyAsync(d.abx_blk, blk.data(), sizeof(AbBlk) * blk.size(), hipMemcpyHostToDevice, s));
     if (!pchunk.empty()) {
         ISCI_HIP(hipMemcpyAsync(d.abx_pchunk, pchunk.data(), sizeof(int4) * pchunk.size(), hipMemcpyHostToDevice, s));
         ISCI_HIP(hipMemcpyAsync(d.pchunk_val, pval.data(), sizeof(double) * pval.size(), hipMemcpyHostToDevice, s));
     }
     ISCI_HIP(hipMemcpyAsync(d.abx_pblk, pblk.data(), sizeof(AbBlk) * pblk.size(), hipMemcpyHostToDevice, s));
+    if (!pblk1.empty()) {
+        const size_t tbytes1 = sizeof(double) * std::max<size_t>(1, Y1.tsize);
+        d.abx1_gofs = (int *)dev_alloc(c, sizeof(int) * Y1.gofs.size());
+        d.abx1_tq = (int2 *)dev_alloc(c, sizeof(int2) * tq1.size());
+        d.abx1_soff = (long long *)dev_alloc(c, sizeof(long long) * Y1.soff.size());
+        d.abx1_pchunk = (int4 *)dev_alloc(c, sizeof(int4) * pchunk1.size());
+        d.abx1_pblk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * pblk1.size());
+        d.abx1_T = (double *)dev_alloc(c, tbytes1);
+        if (!d.abx1_gofs || !d.abx1_tq || !d.abx1_soff || !d.abx1_pchunk || !d.abx1_pblk || !d.abx1_T) {
+            set_error("device allocation failed (single-vector alpha-beta product)");
+            return ISCI_E_OOM;
+        }
+        ISCI_HIP(hipMemcpyAsync(d.abx1_gofs, Y1.gofs.data(), sizeof(int) * Y1.gofs.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(d.abx1_tq, tq1.data(), sizeof(int2) * tq1.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(d.abx1_soff, Y1.soff.data(), sizeof(long long) * Y1.soff.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(d.abx1_pchunk, pchunk1.data(), sizeof(int4) * pchunk1.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(d.abx1_pblk, pblk1.data(), sizeof(AbBlk) * pblk1.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemsetAsync(d.abx1_T, 0, tbytes1, s));
+        for (int k = 0; k < 3; ++k) c->abx1_pcols[k] = Y1.pcols[k];
+        c->abx1_pxmax = pxmax1;
+        c->have_abx1 = true;
+    }
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
-    c->abx_ntrow = (int)trow.size();
-    c->abx_nrows = (int)rows.size();
+    c->abx_ntrow = (int)Y4.trow.size();
+    c->abx_nrows = (int)Y4.rows.size();
     c->abx_sbytes = sbytes;
     c->abx_xmax = xmax;
     c->abx_pxmax = pxmax;
     c->npchunk = (int)pchunk.size();
-    for (int k = 0; k < 3; ++k) c->abx_pcols[k] = pcols[k];
+    for (int k = 0; k < 3; ++k) c->abx_pcols[k] = Y4.pcols[k];
     c->have_abx = true;
     return ISCI_OK;
 }

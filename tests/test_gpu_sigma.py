@@ -320,3 +320,30 @@ def test_onebody_kernels(recipe, norb, L, tau, nvec, nsamp):
         else:
             ok, err = sampled_ok(got, tg, ref, TOL)
             assert ok, (kern, err)
+
+
+@pytest.mark.parametrize("norb,L,b,ob", [(12, 4, 0, "auto"), (20, 3, 0, "auto"), (24, 2, 0, "separate"),
+                                        (16, 1, 6, "auto"), (48, 4, 0, "auto")])
+def test_single_vector_layout_matches_four_slot_passes(norb, L, b, ob):
+    """A one-vector sigma runs the product on the single-slot operand layout;
+    each vector's sigma equals, bit for bit, the same vector computed inside
+    a four-vector call (four-slot layout), and a five-vector call (a
+    four-slot pass and a single-slot pass) matches both."""
+    import paper_1609_07757_amd as isci
+    torch, dev = torch_dev()
+    h, eri = recipe_a(norb, seed=9)
+    ht, et = torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev)
+    place = {"auto": isci.OB_AUTO, "separate": isci.OB_SEPARATE}[ob]
+    hd = isci.isci_create(ht, et, norb, 2, 2, L, 1e-12, onebody=place, gas_boundary=b)
+    torch.cuda.synchronize()
+    c = random_vectors(hd.dim, 5, seed=4)
+    s4 = gpu_sigma(hd, c[:4])
+    s5 = gpu_sigma(hd, c)
+    for v in range(5):
+        s1 = gpu_sigma(hd, c[v:v + 1])[0]
+        if v < 4:
+            assert np.array_equal(s1, s4[v])
+        assert np.array_equal(s1, s5[v])
+    if norb <= 24:
+        S = O.Space(norb, 2, 2, L, boundary=b or None)
+        assert rel_err(s5, O.sigma(S, h, eri, 1e-12, c)) <= TOL
