@@ -634,17 +634,28 @@ def bench_rows(a):
     c1[0] = 1.0
     s1 = torch.empty_like(c1)
     sig_ms = _events_ms(torch, stream, lambda: isci.isci_sigma(hd, c1, s1, stream=stream), 10)
-    steps = 10
     isci.isci_propagate(hd, c1.clone(), 0.5, 1, krylov=16)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = isci.isci_propagate(hd, c1, 0.5, steps, krylov=16)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    out["propagation"] = {"workload": W.name, "dt": 0.5, "steps": steps, "krylov_max": 16, "ms_per_step": wall * 1e3 / steps,
-                          "sigma_calls": info["sigma_calls"], "krylov_last": info["krylov_last"], "energy": info["energy"],
-                          "sigma_ms_one_vector": sig_ms,
-                          "sigma_share": info["sigma_calls"] * sig_ms / (wall * 1e3)}
+
+    def prop(steps):
+        x = c1.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = isci.isci_propagate(hd, x, 0.5, steps, krylov=16)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, inf
+
+    # a call's time is a fixed part (buffers, the final energy) plus a
+    # steady part per step: from calls of 5 and 25 steps
+    ms5, inf5 = prop(5)
+    ms25, info = prop(25)
+    per_step = (ms25 - ms5) / 20.0
+    calls_per_step = (info["sigma_calls"] - inf5["sigma_calls"]) / 20.0
+    out["propagation"] = {"workload": W.name, "dt": 0.5, "krylov_max": 16, "ms_per_step": per_step,
+                          "ms_per_call_fixed": ms5 - 5 * per_step, "ms_25_step_call": ms25,
+                          "sigma_calls_per_step": calls_per_step, "krylov_last": info["krylov_last"],
+                          "energy": info["energy"], "sigma_ms_one_vector": sig_ms,
+                          "sigma_share": calls_per_step * sig_ms / per_step}
     del hd
     # handles from factors against dense handles
     Wf = workload(a.rows_factored)
