@@ -372,27 +372,32 @@ __global__ __launch_bounds__(256) void k_ab_fold(SigmaArgs A, int nv, double *__
     }
 }
 
-// A pass of one vector takes the single-vector layout (one vector slot per
-// spectator pair: a quarter of the four-slot operands and product) when it
-// is built and the packed product is selected
-static bool single_slot(const isci_ctx *cx, int nv)
+// A pass of one or two vectors takes the narrow layout with that many
+// vector slots per spectator pair (a quarter or half of the four-slot
+// operands and product) when it is built and the packed product is
+// selected; returns its index, or -1 for the four-slot layout
+static int narrow_layout(const isci_ctx *cx, int nv)
 {
-    return nv == 1 && cx->have_abx1 && cx->ab_kernel == ISCI_AB_PACKED && cx->abx1_pxmax > 0;
+    const int w = nv - 1;
+    if (w < 0 || w > 1 || !cx->have_abxn[w] || cx->ab_kernel != ISCI_AB_PACKED || cx->abxn_pxmax[w] <= 0) return -1;
+    return w;
 }
 
 // arguments of the product path for a pass of nv vectors
 static SigmaArgs product_args(const isci_ctx *cx, int nv)
 {
     SigmaArgs A = sigma_args(cx);
-    if (single_slot(cx, nv)) {
-        A.abx_vs = 1;
-        A.abx_gofs = cx->d.abx1_gofs;
-        A.abx_tq = cx->d.abx1_tq;
-        A.abx_soff = cx->d.abx1_soff;
-        A.abx_pchunk = cx->d.abx1_pchunk;
-        A.abx_pblk = cx->d.abx1_pblk;
-        A.abx_T = cx->d.abx1_T;
-        for (int k = 0; k < 3; ++k) A.abx_pcols[k] = cx->abx1_pcols[k];
+    const int w = narrow_layout(cx, nv);
+    if (w >= 0) {
+        const auto &x = cx->d.abxn[w];
+        A.abx_vs = w + 1;
+        A.abx_gofs = x.gofs;
+        A.abx_tq = x.tq;
+        A.abx_soff = x.soff;
+        A.abx_pchunk = x.pchunk;
+        A.abx_pblk = x.pblk;
+        A.abx_T = x.T;
+        for (int k = 0; k < 3; ++k) A.abx_pcols[k] = cx->abxn_pcols[w][k];
     }
     return A;
 }
@@ -402,11 +407,13 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
 {
     SigmaArgs A = product_args(cx, nv);
     A.abx_S = Sbuf;
-    const bool one = A.abx_vs == 1;
+    const int w = narrow_layout(cx, nv);
     if (cx->abx_ntrow > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, true, st));
-        if (one)
+        if (w == 0)
             k_ab_unfold<1><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
+        else if (w == 1)
+            k_ab_unfold<2><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
         else
             k_ab_unfold<4><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, c, ldc);
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_UNFOLD, false, st));
@@ -414,8 +421,8 @@ isci_status launch_ab_unfold_gemm(const isci_ctx *cx, int nv, const double *c, i
     if (cx->abx_nrows > 0) {
         ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_GEMM, true, st));
         const dim3 grid((unsigned)(8 * cx->abx_xmax)), block(64 * kAbCW * kAbSplit);
-        if (one)
-            k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abx1_pxmax)), block, 0, st>>>(A);
+        if (w >= 0)
+            k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abxn_pxmax[w])), block, 0, st>>>(A);
         else if (cx->ab_kernel == ISCI_AB_PACKED && cx->abx_pxmax > 0)
             k_ab_gemm<kAbCW, kAbSplit, true, true><<<dim3((unsigned)(8 * cx->abx_pxmax)), block, 0, st>>>(A);
         else if (cx->ab_kernel == ISCI_AB_PIPE)
@@ -438,6 +445,8 @@ isci_status launch_ab_fold(const isci_ctx *cx, int nv, const double *Sbuf, doubl
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, true, st));
     if (A.abx_vs == 1)
         k_ab_fold<1><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
+    else if (A.abx_vs == 2)
+        k_ab_fold<2><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
     else
         k_ab_fold<4><<<(unsigned)cx->nplan, 256, 0, st>>>(A, nv, s, lds, accumulate ? 1 : 0);
     ISCI_CHECK(prof_mark(cx, ISCI_KERNEL_AB_FOLD, false, st));

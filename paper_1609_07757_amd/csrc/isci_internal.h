@@ -133,15 +133,18 @@ struct DevTabs {
     double *abx_T = nullptr;
     double *abx_S = nullptr;
     double *abx_S2 = nullptr;       // second S (one-body overlap: both passes' products before the folds)
-    // the single-vector layout of the packed product (one vector slot per
-    // spectator pair instead of four), its own T (zero where no determinant
-    // writes) and its tables; S is shared with the four-slot layout
-    int *abx1_gofs = nullptr;
-    int2 *abx1_tq = nullptr;
-    long long *abx1_soff = nullptr;
-    int4 *abx1_pchunk = nullptr;
-    AbBlk *abx1_pblk = nullptr;
-    double *abx1_T = nullptr;
+    // narrow layouts of the packed product for passes of one and of two
+    // vectors (one or two vector slots per spectator pair instead of four):
+    // each has its own T (zero where no determinant writes) and tables; S
+    // is shared with the four-slot layout
+    struct AbxNarrow {
+        int *gofs = nullptr;
+        int2 *tq = nullptr;
+        long long *soff = nullptr;
+        int4 *pchunk = nullptr;
+        AbBlk *pblk = nullptr;
+        double *T = nullptr;
+    } abxn[2];
     double *obT_c = nullptr;        // [obT_nv][dim] transposed CI block (beta one-body above kObMaxNorb,
                                     // full-CI alpha one-body)
     double *obT_s = nullptr;        // [obT_nv][dim] its one-body image
@@ -204,7 +207,7 @@ struct SigmaArgs {
     int nchunk;              // chunks of W; chunk_val holds one more, all zero
     double *abx_T, *abx_S;
     int abx_pcols[3];        // columns valid for sources / targets of class 0, 1, 2
-    int abx_vs;              // vector slots per spectator pair in the product operands (4, or 1)
+    int abx_vs;              // vector slots per spectator pair in the product operands (4, 2 or 1)
 };
 
 // Orbital blocks of the matrix-core path: the inner orbitals 0..b-1 (the
@@ -290,8 +293,9 @@ struct isci_ctx {
     int abx_xmax = 0;        // longest XCD tile run
     int abx_pxmax = 0;       // the same over the packed chunk lists (0: not built)
     int npchunk = 0;         // packed chunks
-    bool have_abx1 = false;  // single-vector layout of the packed product built
-    int abx1_pcols[3] = {0, 0, 0}, abx1_pxmax = 0;
+    // narrow layouts (index 0: one vector slot, 1: two), built with the product path
+    bool have_abxn[2] = {false, false};
+    int abxn_pcols[2][3] = {{0, 0, 0}, {0, 0, 0}}, abxn_pxmax[2] = {0, 0};
     int ab_kernel = ISCI_AB_PACKED;  // ISCI_OPT_AB_PRODUCT: packed wide-load k_ab_gemm (default), wide, plain, pipe
     int ob_kernel = ISCI_ONEBODY_TRANSPOSED;   // ISCI_OPT_ONEBODY_KERNEL
     int obT_nv = 4;                            // vectors of the transposed one-body scratch (4 or 8)

@@ -980,23 +980,28 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     const std::vector<int4> pchunk = pchunk_of(Y4);
     int pxmax = 0;
     const std::vector<AbBlk> pblk = make_tiles(poff, pcls, Y4, pxmax);
-    // the single-vector layout (packed product only): its own column groups,
-    // T rows and S blocks over the same chunks, and its own T, whose entries
-    // that no determinant fills must stay zero (S is shared)
-    Layout Y1;
-    layout(1, Y1);
-    int pxmax1 = 0;
-    std::vector<int4> pchunk1;
-    std::vector<AbBlk> pblk1;
-    if (Y1.fits && Y1.ssize <= Y4.ssize && !pchunk.empty()) {
-        pchunk1 = pchunk_of(Y1);
-        pblk1 = make_tiles(poff, pcls, Y1, pxmax1);
+    // the narrow layouts (packed product only) for passes of one and two
+    // vectors: their own column groups, T rows and S blocks over the same
+    // chunks, and their own T, whose entries that no determinant fills must
+    // stay zero (S is shared)
+    Layout YN[2];
+    int pxmaxn[2] = {0, 0};
+    std::vector<int4> pchunkn[2];
+    std::vector<AbBlk> pblkn[2];
+    for (int w = 0; w < 2; ++w) {
+        layout(w + 1, YN[w]);
+        if (YN[w].fits && YN[w].ssize <= Y4.ssize && !pchunk.empty()) {
+            pchunkn[w] = pchunk_of(YN[w]);
+            pblkn[w] = make_tiles(poff, pcls, YN[w], pxmaxn[w]);
+        }
     }
-    std::vector<int2> tq((size_t)n * nb, make_int2(0, 0)), tq1((size_t)n * nb, make_int2(0, 0));
-    for (size_t i = 0; i < tq.size(); ++i) {
-        if (Y4.krow_of[i] >= 0) tq[i] = make_int2(Y4.trow[Y4.krow_of[i]].z, Y4.trow[Y4.krow_of[i]].w);
-        if (!pblk1.empty() && Y1.krow_of[i] >= 0) tq1[i] = make_int2(Y1.trow[Y1.krow_of[i]].z, Y1.trow[Y1.krow_of[i]].w);
-    }
+    auto tq_of = [&](const Layout &Y) {
+        std::vector<int2> t((size_t)n * nb, make_int2(0, 0));
+        for (size_t i = 0; i < t.size(); ++i)
+            if (Y.krow_of[i] >= 0) t[i] = make_int2(Y.trow[Y.krow_of[i]].z, Y.trow[Y.krow_of[i]].w);
+        return t;
+    };
+    const std::vector<int2> tq = tq_of(Y4);
     DevTabs &d = c->d;
     d.abx_gofs = (int *)dev_alloc(c, sizeof(int) * Y4.gofs.size());
     d.abx_col = (int *)dev_alloc(c, sizeof(int) * Y4.col.size());
@@ -1038,27 +1043,32 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
         ISCI_HIP(hipMemcpyAsync(d.pchunk_val, pval.data(), sizeof(double) * pval.size(), hipMemcpyHostToDevice, s));
     }
     ISCI_HIP(hipMemcpyAsync(d.abx_pblk, pblk.data(), sizeof(AbBlk) * pblk.size(), hipMemcpyHostToDevice, s));
-    if (!pblk1.empty()) {
-        const size_t tbytes1 = sizeof(double) * std::max<size_t>(1, Y1.tsize);
-        d.abx1_gofs = (int *)dev_alloc(c, sizeof(int) * Y1.gofs.size());
-        d.abx1_tq = (int2 *)dev_alloc(c, sizeof(int2) * tq1.size());
-        d.abx1_soff = (long long *)dev_alloc(c, sizeof(long long) * Y1.soff.size());
-        d.abx1_pchunk = (int4 *)dev_alloc(c, sizeof(int4) * pchunk1.size());
-        d.abx1_pblk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * pblk1.size());
-        d.abx1_T = (double *)dev_alloc(c, tbytes1);
-        if (!d.abx1_gofs || !d.abx1_tq || !d.abx1_soff || !d.abx1_pchunk || !d.abx1_pblk || !d.abx1_T) {
-            set_error("device allocation failed (single-vector alpha-beta product)");
+    for (int w = 0; w < 2; ++w) {
+        if (pblkn[w].empty()) continue;
+        const Layout &Y = YN[w];
+        const std::vector<int2> tqn = tq_of(Y);
+        const size_t tb = sizeof(double) * std::max<size_t>(1, Y.tsize);
+        auto &x = d.abxn[w];
+        x.gofs = (int *)dev_alloc(c, sizeof(int) * Y.gofs.size());
+        x.tq = (int2 *)dev_alloc(c, sizeof(int2) * tqn.size());
+        x.soff = (long long *)dev_alloc(c, sizeof(long long) * Y.soff.size());
+        x.pchunk = (int4 *)dev_alloc(c, sizeof(int4) * pchunkn[w].size());
+        x.pblk = (AbBlk *)dev_alloc(c, sizeof(AbBlk) * pblkn[w].size());
+        x.T = (double *)dev_alloc(c, tb);
+        if (!x.gofs || !x.tq || !x.soff || !x.pchunk || !x.pblk || !x.T) {
+            set_error("device allocation failed (narrow alpha-beta product layout)");
             return ISCI_E_OOM;
         }
-        ISCI_HIP(hipMemcpyAsync(d.abx1_gofs, Y1.gofs.data(), sizeof(int) * Y1.gofs.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipMemcpyAsync(d.abx1_tq, tq1.data(), sizeof(int2) * tq1.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipMemcpyAsync(d.abx1_soff, Y1.soff.data(), sizeof(long long) * Y1.soff.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipMemcpyAsync(d.abx1_pchunk, pchunk1.data(), sizeof(int4) * pchunk1.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipMemcpyAsync(d.abx1_pblk, pblk1.data(), sizeof(AbBlk) * pblk1.size(), hipMemcpyHostToDevice, s));
-        ISCI_HIP(hipMemsetAsync(d.abx1_T, 0, tbytes1, s));
-        for (int k = 0; k < 3; ++k) c->abx1_pcols[k] = Y1.pcols[k];
-        c->abx1_pxmax = pxmax1;
-        c->have_abx1 = true;
+        ISCI_HIP(hipMemcpyAsync(x.gofs, Y.gofs.data(), sizeof(int) * Y.gofs.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(x.tq, tqn.data(), sizeof(int2) * tqn.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(x.soff, Y.soff.data(), sizeof(long long) * Y.soff.size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(x.pchunk, pchunkn[w].data(), sizeof(int4) * pchunkn[w].size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemcpyAsync(x.pblk, pblkn[w].data(), sizeof(AbBlk) * pblkn[w].size(), hipMemcpyHostToDevice, s));
+        ISCI_HIP(hipMemsetAsync(x.T, 0, tb, s));
+        ISCI_HIP(hipStreamSynchronize(s));   // tqn dies here
+        for (int k = 0; k < 3; ++k) c->abxn_pcols[w][k] = Y.pcols[k];
+        c->abxn_pxmax[w] = pxmaxn[w];
+        c->have_abxn[w] = true;
     }
     ISCI_HIP(hipStreamSynchronize(s));   // host tables above are freed on return
     c->abx_ntrow = (int)Y4.trow.size();

@@ -324,11 +324,12 @@ def test_onebody_kernels(recipe, norb, L, tau, nvec, nsamp):
 
 @pytest.mark.parametrize("norb,L,b,ob", [(12, 4, 0, "auto"), (20, 3, 0, "auto"), (24, 2, 0, "separate"),
                                         (16, 1, 6, "auto"), (48, 4, 0, "auto")])
-def test_single_vector_layout_matches_four_slot_passes(norb, L, b, ob):
-    """A one-vector sigma runs the product on the single-slot operand layout;
-    each vector's sigma equals, bit for bit, the same vector computed inside
-    a four-vector call (four-slot layout), and a five-vector call (a
-    four-slot pass and a single-slot pass) matches both."""
+def test_narrow_layouts_match_four_slot_passes(norb, L, b, ob):
+    """Passes of one and of two vectors run the product on the narrow
+    operand layouts (one or two vector slots per spectator pair); every
+    vector's sigma equals, bit for bit, the same vector computed inside a
+    four-vector call, and five- and six-vector calls (a four-slot pass and a
+    one- or two-slot pass) match both."""
     import paper_1609_07757_amd as isci
     torch, dev = torch_dev()
     h, eri = recipe_a(norb, seed=9)
@@ -336,14 +337,17 @@ def test_single_vector_layout_matches_four_slot_passes(norb, L, b, ob):
     place = {"auto": isci.OB_AUTO, "separate": isci.OB_SEPARATE}[ob]
     hd = isci.isci_create(ht, et, norb, 2, 2, L, 1e-12, onebody=place, gas_boundary=b)
     torch.cuda.synchronize()
-    c = random_vectors(hd.dim, 5, seed=4)
-    s4 = gpu_sigma(hd, c[:4])
-    s5 = gpu_sigma(hd, c)
-    for v in range(5):
-        s1 = gpu_sigma(hd, c[v:v + 1])[0]
-        if v < 4:
-            assert np.array_equal(s1, s4[v])
-        assert np.array_equal(s1, s5[v])
+    c = random_vectors(hd.dim, 6, seed=4)
+    s4 = np.concatenate([gpu_sigma(hd, c[:4]), gpu_sigma(hd, c[2:6])[2:]])
+    s5 = gpu_sigma(hd, c[:5])
+    s6 = gpu_sigma(hd, c)
+    assert np.array_equal(s6, s4)
+    assert np.array_equal(s5, s4[:5])
+    for v in range(6):
+        assert np.array_equal(gpu_sigma(hd, c[v:v + 1])[0], s4[v])
+    for v in range(0, 6, 2):
+        assert np.array_equal(gpu_sigma(hd, c[v:v + 2]), s4[v:v + 2])
+    assert np.array_equal(gpu_sigma(hd, c[1:4]), s4[1:4])
     if norb <= 24:
         S = O.Space(norb, 2, 2, L, boundary=b or None)
-        assert rel_err(s5, O.sigma(S, h, eri, 1e-12, c)) <= TOL
+        assert rel_err(s6, O.sigma(S, h, eri, 1e-12, c)) <= TOL
