@@ -73,7 +73,7 @@ def handle_bytes_estimate(norb: int, dim: int, naux: int = 0) -> int:
     transient dense eri (8 norb^4), list offsets and tables sized for one
     kept alpha-beta unit in eight, the product operands (about 16 B per
     determinant and vector of a 4-vector pass, two result buffers, and the
-    single-vector layout's own operand, a quarter of a pass's), and
+    one- and two-vector layouts' own operands, three quarters of a pass's), and
     above 80 orbitals the transposed one-body blocks (64 B per
     determinant).  It is an estimate, not a bound: at tau = 0 the lists
     alone can exceed it.  The server therefore re-charges a running
@@ -85,7 +85,7 @@ def handle_bytes_estimate(norb: int, dim: int, naux: int = 0) -> int:
     n3 = norb ** 3
     lists = 8 * (n3 + 1) + 9 * norb ** 4 // 8 + 4 * norb * norb * 16
     strings = 8 * (norb * norb) * 4
-    operands = 3 * 16 * 4 * dim + 16 * dim
+    operands = 3 * 16 * 4 * dim + 48 * dim
     onebody = 64 * dim if norb > 80 else 0
     transient = 8 * (2 * naux + 1) * norb * norb if naux > 0 else 8 * norb ** 4
     return transient + lists + strings + 8 * dim + operands + onebody
