@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -588,7 +589,10 @@ def bench_rows(a):
         the share its sigma calls take at the one-vector sigma rate;
       * handles from factors against dense handles: creation time, the
         bytes handed over, and the sigma of both (bit for bit);
-      * distance screening: kept units and sigma time against the radius."""
+      * distance screening: kept units and sigma time against the radius;
+      * the two-space GAS restriction (200 orbitals, at most one outer
+        electron, handle from factors): sigma time and the product
+        kernel's roofline."""
     import numpy as np
     import torch
     import paper_1609_07757_amd as isci
@@ -596,7 +600,7 @@ def bench_rows(a):
     from isci_inputs.recipes import factors_a, orbital_centres
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    out = {"metric": "extension rows: two-body densities, SIAL propagation, handles from factors, distance screening",
+    out = {"metric": "extension rows: two-body densities, SIAL propagation, handles from factors, distance screening, GAS",
            "n_gpus": 1, "dtype": "f64", "data": "synthetic (recipe A, seeded)"}
     # two-body densities
     W = workload(a.workload)
@@ -701,6 +705,34 @@ def bench_rows(a):
                      "terms_per_vector": int(np.sum(st["terms"])), "ms_per_step_8_vectors": ms})
         del hx
     out["distance"] = {"workload": Wf.name, "points": rows}
+    # two-space GAS restriction (the 200-orbital single-outer-electron
+    # workload, its handle built from factors): sigma time of its vectors
+    # and the product kernel's share, against the size of the full-CI and
+    # excitation-hierarchy spaces of the same orbitals
+    Wg = workload("gas1_n200")
+    hg_np, Lg_np = factors_a(Wg.norb, Wg.box_len, Wg.n_aux, Wg.seed)
+    hg = isci.isci_create_factored(torch.from_numpy(hg_np).to(dev), torch.from_numpy(np.ascontiguousarray(Lg_np)).to(dev),
+                                   Wg.norb, 2, 2, Wg.level, Wg.tau, gas_boundary=Wg.gas_boundary)
+    cg = torch.from_numpy(random_vectors(hg.dim, Wg.nvec, seed=21)).to(dev)
+    sgg = torch.empty_like(cg)
+    ms = _events_ms(torch, stream, lambda: isci.isci_sigma(hg, cg, sgg, stream=stream), 20)
+    st = isci.isci_get_stats(hg)
+    isci.isci_profile(hg, True)
+    for _ in range(10):
+        isci.isci_sigma(hg, cg, sgg, stream=stream)
+    torch.cuda.synchronize()
+    prof = isci.isci_profile_read(hg)
+    isci.isci_profile(hg, False)
+    gm_ms, gm_n = prof.get("k_ab_gemm", (0.0, 1))
+    t_ab = int(np.sum(st["terms"][26:42])) + int(np.sum(st["terms"][0:8]))   # one-body units ride in the tiles
+    fl = 2.0 * t_ab * Wg.nvec / (gm_n / 10.0)
+    out["gas"] = {"workload": Wg.name, "gas_boundary": Wg.gas_boundary, "max_outer_electrons": Wg.level, "dim": hg.dim,
+                  "dim_full_ci": math.comb(Wg.norb, 2) ** 2, "nvec": Wg.nvec, "ms_per_step": ms,
+                  "sigma_vectors_per_s": Wg.nvec / (ms * 1e-3), "terms_per_vector": int(st["terms_total"]),
+                  "roofline": {"bound": "mfma", "kernel": "k_ab_gemm", "avg_launch_ms": gm_ms / gm_n,
+                               "achieved": fl / (gm_ms / gm_n * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                               "frac": fl / (gm_ms / gm_n * 1e-3) / 1e12 / 78.6}}
+    del hg
     print(json.dumps(out), flush=True)
 
 
