@@ -44,9 +44,10 @@ typedef double v4d_ab __attribute__((ext_vector_type(4)));
 
 
 // Unfold by scatter: one thread per determinant ({a0<a1}, {b0<b1}) of the
-// space reads its 4 vector values (coalesced) and writes them, with the
-// role sign, to its four places in T, one per reading (alpha spectator x,
-// active q) x (beta spectator y, active s):
+// space reads its VS vector values (coalesced; VS = 4 vector slots, or 1 or
+// 2 in the narrow layouts) and writes them, with the role sign, to its four
+// places in T, one per reading (alpha spectator x, active q) x (beta
+// spectator y, active s):
 //   T[(q, s)][(x, y, v)] = sgn(q - x) sgn(s - y) c_v({x,q},{y,s}).
 // Every entry of T belongs to at most one determinant; entries that belong
 // to none were zeroed when T was allocated.  Vectors v >= nv write zeros.
