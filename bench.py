@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--kernel", choices=["auto", "general", "pair", "mfma"], default="auto")
     ap.add_argument("--ab", choices=["plain", "pipe", "wide", "packed"], default="packed",
                     help="kernel of the alpha-beta block-sparse product")
-    ap.add_argument("--onebody", choices=["transposed", "single", "spectator"], default="transposed",
+    ap.add_argument("--onebody", choices=["auto", "transposed", "single", "spectator", "rows"], default="auto",
                     help="one-body kernel on the rows / columns that hold every pair")
     ap.add_argument("--ob-place", choices=["auto", "separate", "tiles"], default="auto",
                     help="one-body units in their own kernels or inside the alpha-beta tiles (default: by chunk growth)")
@@ -109,8 +109,10 @@ def main():
                "mfma": isci.SIGMA_MFMA}[a.kernel]
     isci.isci_set_option(hd, isci.OPT_SIGMA_KERNEL, variant)
     set_ab_product(isci, hd, a.ab)
-    isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, {"single": isci.ONEBODY_SINGLE, "transposed": isci.ONEBODY_TRANSPOSED,
-                                                       "spectator": isci.ONEBODY_SPECTATOR}[a.onebody])
+    if a.onebody != "auto":   # auto: the handle's own choice
+        isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL,
+                             {"single": isci.ONEBODY_SINGLE, "transposed": isci.ONEBODY_TRANSPOSED,
+                              "spectator": isci.ONEBODY_SPECTATOR, "rows": isci.ONEBODY_ROWS}[a.onebody])
     isci.isci_set_option(hd, isci.OPT_ONEBODY_STREAM,
                          isci.ONEBODY_SIDE if a.onebody_stream == "side" else isci.ONEBODY_INLINE)
     st = isci.isci_get_stats(hd)

@@ -536,12 +536,17 @@ int64_t isci_davidson_footprint(isci_handle hd, int nroots, const isci_davidson_
  *   columns per workgroup there;
  *   ISCI_ONEBODY_SPECTATOR runs the whole alpha class in the spectator form
  *   used above 80 orbitals (U[a][x][j] = sum_q h_aq T_j[q][x], the rows
- *   {q, x} read directly, no transposes).  Same sigma up to rounding
- *   order. */
+ *   {q, x} read directly, no transposes).  Above 80 orbitals the option
+ *   picks the beta class: ISCI_ONEBODY_ROWS (default there for the
+ *   excitation hierarchy where a row holding every beta pair fits a
+ *   workgroup's LDS, up to 202 orbitals; ISCI_E_UNSUPPORTED elsewhere) runs
+ *   it on the rows themselves, any other value as the alpha class of the
+ *   transposed block.  Same sigma up to rounding order. */
 #define ISCI_OPT_ONEBODY_KERNEL 5
 #define ISCI_ONEBODY_SINGLE 1
 #define ISCI_ONEBODY_TRANSPOSED 2
 #define ISCI_ONEBODY_SPECTATOR 3
+#define ISCI_ONEBODY_ROWS 4
 /*   ISCI_OPT_ONEBODY_STREAM (matrix-core path with separate one-body
  *   kernels, for tuning): ISCI_ONEBODY_SIDE (default) runs the one-body
  *   classes on the handle's side stream beside the alpha-beta unfolds and

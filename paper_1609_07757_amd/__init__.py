@@ -32,7 +32,7 @@ OPT_AB_PRODUCT = 3
 AB_PLAIN, AB_PIPE, AB_WIDE, AB_PACKED = 0, 1, 2, 3
 # one-body kernel where every column holds every pair (tuning)
 OPT_ONEBODY_KERNEL = 5
-ONEBODY_SINGLE, ONEBODY_TRANSPOSED, ONEBODY_SPECTATOR = 1, 2, 3
+ONEBODY_SINGLE, ONEBODY_TRANSPOSED, ONEBODY_SPECTATOR, ONEBODY_ROWS = 1, 2, 3, 4
 # one-body kernels beside the alpha-beta products on a side stream, or in line (tuning)
 OPT_ONEBODY_STREAM = 6
 ONEBODY_SIDE, ONEBODY_INLINE = 0, 1

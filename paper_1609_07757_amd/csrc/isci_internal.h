@@ -359,6 +359,9 @@ constexpr int kObMaxNorb = 80;
 // spectator-form one-body kernels are compared with the oracle up to 199)
 constexpr int kPairMaxNorb = 200;
 bool onebody_mfma_ok(const isci_ctx *c);
+// beta one-body class above kObMaxNorb on the rows themselves (excitation
+// hierarchy, a full beta row fits LDS)
+bool onebody_beta_rows_ok(const isci_ctx *c);
 // first: the beta classes write sigma (they cover every element) instead
 // of adding, and the alpha classes add
 isci_status launch_onebody_mfma(const isci_ctx *c, int nv, const double *cv, int64_t ldc, double *sv, int64_t lds,

@@ -989,9 +989,297 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ p, int64
         p[t] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Beta class above kObMaxNorb on the rows themselves (no transposes), for the
+// excitation hierarchy (orbitals 0 and 1 occupied), where a row whose beta
+// strings reach level 2 (it then holds every beta pair) fits LDS.  The rank
+// of the pair {y < s} in the (level, colex) string order:
+//   {0,1}: 0;   {o, v}, o < 2 <= v: lo1 + 2 (v - 2) + o;
+//   {v, w}, 2 <= v < w: lo2 + (v - 2) + (w - 2)(w - 3) / 2.
+__device__ __forceinline__ int pair_rank_hier(int y, int s, int lo1, int lo2)
+{
+    return s < 2 ? 0 : (y < 2 ? lo1 + 2 * (s - 2) + y : lo2 + (y - 2) + ((s - 2) * (s - 3)) / 2);
+}
+
+// Rows whose beta strings reach level 2: one workgroup per (row, vector)
+// stages the row (pair rank -> value) in LDS; the image of the row's
+// antisymmetric pair matrix T under the one-body operator is
+//   T'[a][x] = (h T)[a][x] + (T h)[a][x],   sigma({a < x}) += T'[a][x]
+// (h symmetric, T antisymmetric).  Each wave takes 16 x 16 tile pairs
+// (I <= J) of the orbital square and forms both products of its tile on
+// matrix cores: the T operands gathered from LDS by pair rank, the h
+// operands read from the screened h (coalesced), K steps whose h operands
+// are all screened for the tile skipped.  Once every wave has read the
+// row, the results replace it in LDS and the row is added to sigma.
+constexpr int kObRowWaves = 16;
+constexpr int kObRowTpw = 9;   // tile pairs per wave: 16 tiles give 136 pairs
+
+__global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, const double *__restrict__ c,
+                                                                  int64_t ldc, double *__restrict__ sg, int64_t lds,
+                                                                  const double *__restrict__ hs,
+                                                                  const unsigned long long *__restrict__ hkm)
+{
+    constexpr int NTH = 64 * kObRowWaves;
+    extern __shared__ double rrow[];
+    const int ia = blockIdx.x, v = blockIdx.y;
+    const int norb = A.norb, nt = (norb + 15) >> 4;
+    const int len = A.sb.le[A.L - A.alev[ia]];
+    const int64_t rs = A.rowstart[ia];
+    const double *cr = c + (int64_t)v * ldc + rs;
+    double *sr = sg + (int64_t)v * lds + rs;
+    for (int tb = threadIdx.x; tb < len; tb += kObBatch * NTH) {
+        double val[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) val[u] = cr[min(tb + u * NTH, len - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (tb + u * NTH < len) rrow[tb + u * NTH] = val[u];
+    }
+    __syncthreads();
+    const int lo1 = A.sb.lev_off[1], lo2 = A.sb.lev_off[2];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int n = lane & 15, kq = lane >> 4;
+    const int npairs = nt * (nt + 1) / 2;
+    // T[q][x] from the staged row; zero on the diagonal and past norb
+    auto tget = [&](int q, int x) -> double {
+        const int lo = min(q, x), hi = max(q, x);
+        const bool ok = q != x && hi < norb;
+        const double r = rrow[ok ? pair_rank_hier(lo, hi, lo1, lo2) : 0];
+        return ok ? (q < x ? r : -r) : 0.0;
+    };
+    // h_aq of the screened h (symmetric), zero past norb
+    auto hget = [&](int a, int q) -> double {
+        const double h = hs[(size_t)min(q, norb - 1) * norb + min(a, norb - 1)];
+        return (a < norb && q < norb) ? h : 0.0;
+    };
+    v4d_ob acc[kObRowTpw];
+    int tI[kObRowTpw], tJ[kObRowTpw];
+#pragma unroll
+    for (int i = 0; i < kObRowTpw; ++i) {
+        acc[i] = v4d_ob{0.0, 0.0, 0.0, 0.0};
+        tI[i] = -1;
+        tJ[i] = -1;
+        const int tp = wave + i * kObRowWaves;
+        if (tp >= npairs) continue;   // uniform over the wave
+        int I = 0, rem = tp;
+        while (rem >= nt - I) { rem -= nt - I; ++I; }
+        const int J = I + rem;
+        tI[i] = I;
+        tJ[i] = J;
+        // (h T) of the tile: A = h[16 I + n][q], B = T[q][16 J + n], q = 4 ks + kq;
+        // then (T h): A = T[16 I + n][q], B = h[q][16 J + n].  One step of
+        // lookahead: the operands of the next step load while the current
+        // step's product issues.
+#pragma unroll
+        for (int term = 0; term < 2; ++term) {
+            unsigned long long km = hkm[term == 0 ? I : J];
+            auto next_ks = [&]() {
+                if (!km) return -1;
+                const int k = __ffsll((long long)km) - 1;
+                km &= km - 1;
+                return k;
+            };
+            auto opa = [&](int ks) {
+                const int q = 4 * max(ks, 0) + kq;
+                return term == 0 ? hget(16 * I + n, q) : tget(16 * I + n, q);
+            };
+            auto opb = [&](int ks) {
+                const int q = 4 * max(ks, 0) + kq;
+                return term == 0 ? tget(q, 16 * J + n) : hget(16 * J + n, q);
+            };
+            int ks = next_ks();
+            double a0 = opa(ks), b0 = opb(ks);
+            while (ks >= 0) {
+                const int ks1 = next_ks();
+                const double a1 = opa(ks1), b1 = opb(ks1);
+                acc[i] = mfma16(a0, b0, acc[i]);
+                ks = ks1;
+                a0 = a1;
+                b0 = b1;
+            }
+        }
+    }
+    __syncthreads();   // every wave has read the row
+#pragma unroll
+    for (int i = 0; i < kObRowTpw; ++i) {
+        if (tI[i] < 0) continue;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            // element g of the lane: a = 16 I + 4 g + kq, x = 16 J + n
+            const int a = 16 * tI[i] + 4 * g + kq, x = 16 * tJ[i] + n;
+            if (a < x && x < norb) rrow[pair_rank_hier(a, x, lo1, lo2)] = acc[i][g];
+        }
+    }
+    __syncthreads();
+    for (int tb = threadIdx.x; tb < len; tb += kObBatch * NTH) {
+        double old[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) old[u] = sr[min(tb + u * NTH, len - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (tb + u * NTH < len) sr[tb + u * NTH] = old[u] + rrow[tb + u * NTH];
+    }
+}
+
+// Rows whose beta strings stop at level 1 ({0,1} and {o, v}) or level 0,
+// above kObMaxNorb: the scheme of k_ob_beta_cap1 (columns (row, o) for the
+// two occupied o, V_o[b] = (h T[:, o])[b] on matrix cores) with kObShortRows
+// rows per workgroup, four waves looping over the 16-orbital target tiles,
+// the h operands read from the screened h with the per-tile K-step masks,
+// and LDS sized by norb (dynamic):
+//   sigma({o, b}), b virtual: h_oo c({o,b}) + h_oo' c({o',b}) - V_o[b]
+//   sigma({0, 1})           : V_1[0] - V_0[1]
+constexpr int kObShortRows = 8;
+
+__global__ __launch_bounds__(256) void k_ob_beta_short(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+                                                       double *__restrict__ sg, int64_t lds,
+                                                       const double *__restrict__ hs,
+                                                       const unsigned long long *__restrict__ hkm, int row0, int nrows)
+{
+    constexpr int NR = kObShortRows, NTH = 256;
+    extern __shared__ double ssm[];
+    const int norb = A.norb, nt = (norb + 15) >> 4, rmax = 2 * norb - 3;
+    double *R = ssm;              // the workgroup's rows, contiguous (at most NR * rmax values)
+    double *U = ssm + NR * rmax;  // U[col][b], col = 2 (row) + o
+    __shared__ int ro[NR + 1];    // row offsets within R
+    const int r0 = blockIdx.x * NR;
+    const int v = blockIdx.y;
+    const int lo1 = A.sb.lev_off[1];
+    const int nr = min(NR, nrows - r0);
+    const int64_t base0 = A.rowstart[row0 + r0];
+    const int tot = (int)(A.rowstart[row0 + r0 + nr] - base0);
+    const double *cv = c + (int64_t)v * ldc + base0;
+    if (threadIdx.x <= NR) ro[threadIdx.x] = (int)(A.rowstart[row0 + r0 + min((int)threadIdx.x, nr)] - base0);
+    for (int tb = threadIdx.x; tb < tot; tb += kObBatch * NTH) {
+        double val[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) val[u] = cv[min(tb + u * NTH, tot - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u)
+            if (tb + u * NTH < tot) R[tb + u * NTH] = val[u];
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int n = lane & 15, kq = lane >> 4;
+    // the lane's column (row rl, occupied o): one 16-column N tile
+    const int rl = n >> 1, o = n & 1;
+    const int coff = ro[rl], clen = ro[rl + 1] - ro[rl];   // 0 past the last row
+    for (int mt = wave; mt < nt; mt += 4) {
+        unsigned long long km = hkm[mt];
+        auto next_ks = [&]() {
+            if (!km) return -1;
+            const int k = __ffsll((long long)km) - 1;
+            km &= km - 1;
+            return k;
+        };
+        // A = h[16 mt + n][k], B = T[k][o] of the column's row: {k, o} is
+        // {0,1} (k occupied) or {o, k} (k virtual, level 1); the LDS read is
+        // clamped into the row and selected afterwards
+        auto opa = [&](int ks) {
+            const int k = 4 * max(ks, 0) + kq, a = 16 * mt + n;
+            const double h = hs[(size_t)min(k, norb - 1) * norb + min(a, norb - 1)];
+            return (a < norb && k < norb) ? h : 0.0;
+        };
+        auto opb = [&](int ks) {
+            const int k = 4 * max(ks, 0) + kq;
+            const int idx = k < 2 ? 0 : lo1 + 2 * (k - 2) + o;
+            const bool ok = k < norb && k != o && idx < clen;
+            const double val = R[coff + (ok ? idx : 0)];
+            return ok ? (k < o ? val : -val) : 0.0;
+        };
+        v4d_ob acc = v4d_ob{0.0, 0.0, 0.0, 0.0};
+        int ks = next_ks();
+        double a0 = opa(ks), b0 = opb(ks);
+        while (ks >= 0) {
+            const int ks1 = next_ks();
+            const double a1 = opa(ks1), b1 = opb(ks1);
+            acc = mfma16(a0, b0, acc);
+            ks = ks1;
+            a0 = a1;
+            b0 = b1;
+        }
+        // element g: target b = 16 mt + 4 g + kq, column n
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int b = 16 * mt + 4 * g + kq;
+            if (b < norb) U[n * norb + b] = acc[g];
+        }
+    }
+    __syncthreads();
+    const double h00 = hs[0], h01 = hs[1], h11 = hs[norb + 1];
+    double *sv = sg + (int64_t)v * lds + base0;
+    for (int tb = threadIdx.x; tb < tot; tb += kObBatch * NTH) {
+        double old[kObBatch];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) old[u] = sv[min(tb + u * NTH, tot - 1)];
+#pragma unroll
+        for (int u = 0; u < kObBatch; ++u) {
+            const int t = tb + u * NTH;
+            if (t >= tot) break;
+            // row of element t (a scan of the few offsets)
+            int r = 0;
+            while (r + 1 < nr && ro[r + 1] <= t) ++r;
+            const int j = t - ro[r];
+            const double *Ur = U + (size_t)(2 * r) * norb;   // column (r, o = 0); (r, 1) follows at +norb
+            double add;
+            if (j < lo1) {
+                add = Ur[norb + 0] - Ur[1];
+            } else {
+                const int oo = (j - lo1) & 1, bv = 2 + (j - lo1) / 2;
+                const int jo = oo ? t - 1 : t + 1;   // {o', b}
+                add = (oo ? h11 : h00) * R[t] + h01 * R[jo] - Ur[oo * norb + bv];
+            }
+            sv[t] = old[u] + add;
+        }
+    }
+}
+
+bool onebody_beta_rows_ok(const isci_ctx *cx)
+{
+    return cx->d.hscreen && cx->d.hkmask && cx->na == 2 && cx->nb == 2 && cx->norb > kObMaxNorb &&
+           cx->norb <= 256 && cx->sa.nocc == 2 && cx->sb.nocc == 2 && cx->sa.nstr == cx->sb.nstr &&
+           (size_t)cx->sb.nstr * sizeof(double) <= (size_t)max_lds_bytes(cx);
+}
+
+static isci_status launch_onebody_beta_rows(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
+                                            int64_t lds, hipStream_t st)
+{
+    const SigmaArgs A = sigma_args(cx);
+    const int L = cx->L, norb = cx->norb;
+    // alpha rows by level: every beta pair for level <= L - 2, beta strings
+    // up to level 1 (or 0) past those
+    const int nfull = L >= 2 ? cx->sa.le[L - 2] : 0;
+    if (nfull > 0) {
+        const size_t shm = sizeof(double) * (size_t)cx->sb.nstr;
+        if (shm > 65536)
+            ISCI_HIP(hipFuncSetAttribute((const void *)k_ob_beta_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)shm));
+        k_ob_beta_rows<<<dim3((unsigned)nfull, (unsigned)nv), 64 * kObRowWaves, shm, st>>>(A, c, ldc, s, lds,
+                                                                                           cx->d.hscreen, cx->d.hkmask);
+    }
+    const int nshort = cx->sa.nstr - nfull;
+    if (nshort > 0) {
+        const size_t shm = sizeof(double) * ((size_t)kObShortRows * (2 * norb - 3) + 2 * kObShortRows * (size_t)norb);
+        if (shm > 65536)
+            ISCI_HIP(hipFuncSetAttribute((const void *)k_ob_beta_short, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)shm));
+        k_ob_beta_short<<<dim3((unsigned)((nshort + kObShortRows - 1) / kObShortRows), (unsigned)nv), 256, shm, st>>>(
+            A, c, ldc, s, lds, cx->d.hscreen, cx->d.hkmask, nfull, nshort);
+    }
+    ISCI_HIP(hipGetLastError());
+    return ISCI_OK;
+}
+
 isci_status launch_onebody_beta_large(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
                                       int64_t lds, hipStream_t st)
 {
+    if (cx->ob_kernel == ISCI_ONEBODY_ROWS) {
+        if (!onebody_beta_rows_ok(cx)) {
+            set_error("beta one-body row path: not available for this handle");
+            return ISCI_E_UNSUPPORTED;
+        }
+        return launch_onebody_beta_rows(cx, nv, c, ldc, s, lds, st);
+    }
     if (!cx->d.obT_c || !cx->d.obT_s || nv > 4 || cx->sa.nstr != cx->sb.nstr) {
         set_error("beta one-body transposed path: scratch missing or more than 4 vectors");
         return ISCI_E_UNSUPPORTED;

@@ -1510,6 +1510,8 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
             c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
             if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
         }
+        // above kObMaxNorb the beta class runs on the rows where it can
+        if (st == ISCI_OK && norb > kObMaxNorb && onebody_beta_rows_ok(c)) c->ob_kernel = ISCI_ONEBODY_ROWS;
         if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && norb <= kObMaxNorb && !full_pairs && c->L >= 2 &&
             c->sa.nstr == c->sb.nstr && c->sb.le[c->L - 2] > 0) {
             // the alpha class on the beta columns that hold every alpha pair,
@@ -1628,9 +1630,15 @@ isci_status isci_set_option(isci_handle c, int option, int value)
         c->ab_kernel = value;
         return ISCI_OK;
     case ISCI_OPT_ONEBODY_KERNEL:
-        if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED && value != ISCI_ONEBODY_SPECTATOR) {
+        if (value != ISCI_ONEBODY_SINGLE && value != ISCI_ONEBODY_TRANSPOSED && value != ISCI_ONEBODY_SPECTATOR &&
+            value != ISCI_ONEBODY_ROWS) {
             set_error("bad one-body kernel");
             return ISCI_E_INVALID;
+        }
+        if (value == ISCI_ONEBODY_ROWS && !onebody_beta_rows_ok(c)) {
+            set_error("beta one-body row path: needs more than 80 orbitals, the excitation hierarchy and a beta row "
+                      "that fits LDS");
+            return ISCI_E_UNSUPPORTED;
         }
         c->ob_kernel = value;
         return ISCI_OK;

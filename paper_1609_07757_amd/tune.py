@@ -106,13 +106,13 @@ def _apply(hd, cfg):
 def handle_candidates(hd):
     """Option sets worth timing for this handle: the scalar pair kernel, and
     for two electrons per spin every combination of product kernel,
-    one-body kernel (up to 80 orbitals, where there is a choice) and
+    one-body kernel (the alpha route up to 80 orbitals, the beta route above) and
     one-body stream on the matrix-core path."""
     if not (hd.nalpha == 2 and hd.nbeta == 2):
         return [((isci.OPT_SIGMA_KERNEL, isci.SIGMA_GENERAL),)]
     cands = [((isci.OPT_SIGMA_KERNEL, isci.SIGMA_PAIR),)]
     obk = [isci.ONEBODY_TRANSPOSED, isci.ONEBODY_SINGLE, isci.ONEBODY_SPECTATOR] if hd.norb <= 80 else \
-        [isci.ONEBODY_TRANSPOSED]
+        [isci.ONEBODY_ROWS, isci.ONEBODY_TRANSPOSED]
     for ab in (isci.AB_PACKED, isci.AB_WIDE, isci.AB_PLAIN, isci.AB_PIPE):
         for ob in obk:
             for st in (isci.ONEBODY_SIDE, isci.ONEBODY_INLINE):

@@ -224,6 +224,37 @@ def test_spectator_kernel_edges(norb, L, nvec):
     assert ok, err
 
 
+@pytest.mark.parametrize("norb,L,nvec", [(81, 1, 1), (97, 2, 4), (84, 3, 3), (90, 4, 2)])
+def test_beta_rows_match_transposed(norb, L, nvec):
+    """Above 80 orbitals the beta one-body class runs on the rows themselves
+    (rows holding every beta pair staged whole, rows capped at level 1 or 0
+    eight to a workgroup): CIS 81 orbitals (capped rows only), CISD 97,
+    CISDT 84 (both kinds), full CI 90 (whole rows only), orbital counts off
+    the 16-orbital tiles.  Every element against the transposed-block route
+    (same terms, other summation order) and sampled targets, row ends
+    included, against the oracle; the row route is refused at 80 orbitals."""
+    import paper_1609_07757_amd as isci
+    tau = 1e-12
+    h, eri = recipe_a(norb, seed=8)
+    hd = create(h, eri, norb, 2, 2, L, tau, 5)
+    S = O.Space(norb, 2, 2, L)
+    c = random_vectors(S.dim, nvec, seed=31)
+    print(f"beta rows norb={norb} L={L} nvec={nvec}", flush=True)
+    rows = gpu_sigma(hd, c)   # the default above 80 orbitals
+    isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, isci.ONEBODY_TRANSPOSED)
+    tr = gpu_sigma(hd, c)
+    isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, isci.ONEBODY_ROWS)
+    assert np.array_equal(gpu_sigma(hd, c), rows)   # deterministic
+    assert rel_err(rows, tr) <= 1e-13
+    tg = sample_targets(S.rowstart(), S.dim, 300, seed=12)
+    ok, err = sampled_ok(rows, tg, O.sigma(S, h, eri, tau, c, targets=tg), TOL)
+    assert ok, err
+    h80, eri80 = recipe_b(12, seed=2)
+    hs = create(h80, eri80, 12, 2, 2, 2, 0.0, 5)
+    with pytest.raises(isci.IsciError):
+        isci.isci_set_option(hs, isci.OPT_ONEBODY_KERNEL, isci.ONEBODY_ROWS)
+
+
 @pytest.mark.parametrize("k,tau", [(0, 0.0), (1, 1e-14), (2, 1e-10)])
 def test_sigma_tau_sweep_cisdt_n30(k, tau):
     from isci_inputs import workload
