@@ -1066,10 +1066,11 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
         const int J = I + rem;
         tI[i] = I;
         tJ[i] = J;
+        v4d_ob acc2 = v4d_ob{0.0, 0.0, 0.0, 0.0};
         // (h T) of the tile: A = h[16 I + n][q], B = T[q][16 J + n], q = 4 ks + kq;
-        // then (T h): A = T[16 I + n][q], B = h[q][16 J + n].  One step of
-        // lookahead: the operands of the next step load while the current
-        // step's product issues.
+        // then (T h): A = T[16 I + n][q], B = h[q][16 J + n].  The operands
+        // of the next two steps load while the current two steps' products
+        // issue.
 #pragma unroll
         for (int term = 0; term < 2; ++term) {
             unsigned long long km = hkm[term == 0 ? I : J];
@@ -1081,23 +1082,33 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
             };
             auto opa = [&](int ks) {
                 const int q = 4 * max(ks, 0) + kq;
-                return term == 0 ? hget(16 * I + n, q) : tget(16 * I + n, q);
+                const double a = term == 0 ? hget(16 * I + n, q) : tget(16 * I + n, q);
+                return ks >= 0 ? a : 0.0;
             };
             auto opb = [&](int ks) {
                 const int q = 4 * max(ks, 0) + kq;
-                return term == 0 ? tget(q, 16 * J + n) : hget(16 * J + n, q);
+                const double b = term == 0 ? tget(q, 16 * J + n) : hget(16 * J + n, q);
+                return ks >= 0 ? b : 0.0;
             };
-            int ks = next_ks();
-            double a0 = opa(ks), b0 = opb(ks);
-            while (ks >= 0) {
-                const int ks1 = next_ks();
-                const double a1 = opa(ks1), b1 = opb(ks1);
+            // steps taken two at a time into two accumulators (two
+            // independent product chains); a missing second step has zero
+            // operands
+            int k0 = next_ks(), k1 = next_ks();
+            double a0 = opa(k0), b0 = opb(k0), a1 = opa(k1), b1 = opb(k1);
+            while (k0 >= 0) {
+                const int k2 = next_ks(), k3 = next_ks();
+                const double a2 = opa(k2), b2 = opb(k2), a3 = opa(k3), b3 = opb(k3);
                 acc[i] = mfma16(a0, b0, acc[i]);
-                ks = ks1;
-                a0 = a1;
-                b0 = b1;
+                acc2 = mfma16(a1, b1, acc2);
+                k0 = k2;
+                k1 = k3;
+                a0 = a2;
+                b0 = b2;
+                a1 = a3;
+                b1 = b3;
             }
         }
+        acc[i] += acc2;
     }
     __syncthreads();   // every wave has read the row
 #pragma unroll
@@ -1124,19 +1135,19 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
 // Rows whose beta strings stop at level 1 ({0,1} and {o, v}) or level 0,
 // above kObMaxNorb: the scheme of k_ob_beta_cap1 (columns (row, o) for the
 // two occupied o, V_o[b] = (h T[:, o])[b] on matrix cores) with kObShortRows
-// rows per workgroup, four waves looping over the 16-orbital target tiles,
+// rows per workgroup, eight waves looping over the 16-orbital target tiles,
 // the h operands read from the screened h with the per-tile K-step masks,
 // and LDS sized by norb (dynamic):
 //   sigma({o, b}), b virtual: h_oo c({o,b}) + h_oo' c({o',b}) - V_o[b]
 //   sigma({0, 1})           : V_1[0] - V_0[1]
-constexpr int kObShortRows = 8;
+constexpr int kObShortRows = 8, kObShortWaves = 8;
 
-__global__ __launch_bounds__(256) void k_ob_beta_short(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
+__global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                        double *__restrict__ sg, int64_t lds,
                                                        const double *__restrict__ hs,
                                                        const unsigned long long *__restrict__ hkm, int row0, int nrows)
 {
-    constexpr int NR = kObShortRows, NTH = 256;
+    constexpr int NR = kObShortRows, NTH = 64 * kObShortWaves;
     extern __shared__ double ssm[];
     const int norb = A.norb, nt = (norb + 15) >> 4, rmax = 2 * norb - 3;
     double *R = ssm;              // the workgroup's rows, contiguous (at most NR * rmax values)
@@ -1164,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_ob_beta_short(SigmaArgs A, const double
     // the lane's column (row rl, occupied o): one 16-column N tile
     const int rl = n >> 1, o = n & 1;
     const int coff = ro[rl], clen = ro[rl + 1] - ro[rl];   // 0 past the last row
-    for (int mt = wave; mt < nt; mt += 4) {
+    for (int mt = wave; mt < nt; mt += kObShortWaves) {
         unsigned long long km = hkm[mt];
         auto next_ks = [&]() {
             if (!km) return -1;
@@ -1178,26 +1189,33 @@ __global__ __launch_bounds__(256) void k_ob_beta_short(SigmaArgs A, const double
         auto opa = [&](int ks) {
             const int k = 4 * max(ks, 0) + kq, a = 16 * mt + n;
             const double h = hs[(size_t)min(k, norb - 1) * norb + min(a, norb - 1)];
-            return (a < norb && k < norb) ? h : 0.0;
+            return (ks >= 0 && a < norb && k < norb) ? h : 0.0;
         };
         auto opb = [&](int ks) {
             const int k = 4 * max(ks, 0) + kq;
             const int idx = k < 2 ? 0 : lo1 + 2 * (k - 2) + o;
-            const bool ok = k < norb && k != o && idx < clen;
+            const bool ok = ks >= 0 && k < norb && k != o && idx < clen;
             const double val = R[coff + (ok ? idx : 0)];
             return ok ? (k < o ? val : -val) : 0.0;
         };
-        v4d_ob acc = v4d_ob{0.0, 0.0, 0.0, 0.0};
-        int ks = next_ks();
-        double a0 = opa(ks), b0 = opb(ks);
-        while (ks >= 0) {
-            const int ks1 = next_ks();
-            const double a1 = opa(ks1), b1 = opb(ks1);
+        // steps two at a time into two accumulators (a missing second step
+        // has zero operands)
+        v4d_ob acc = v4d_ob{0.0, 0.0, 0.0, 0.0}, acc2 = acc;
+        int k0 = next_ks(), k1 = next_ks();
+        double a0 = opa(k0), b0 = opb(k0), a1 = opa(k1), b1 = opb(k1);
+        while (k0 >= 0) {
+            const int k2 = next_ks(), k3 = next_ks();
+            const double a2 = opa(k2), b2 = opb(k2), a3 = opa(k3), b3 = opb(k3);
             acc = mfma16(a0, b0, acc);
-            ks = ks1;
-            a0 = a1;
-            b0 = b1;
+            acc2 = mfma16(a1, b1, acc2);
+            k0 = k2;
+            k1 = k3;
+            a0 = a2;
+            b0 = b2;
+            a1 = a3;
+            b1 = b3;
         }
+        acc += acc2;
         // element g: target b = 16 mt + 4 g + kq, column n
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -1263,7 +1281,8 @@ static isci_status launch_onebody_beta_rows(const isci_ctx *cx, int nv, const do
         if (shm > 65536)
             ISCI_HIP(hipFuncSetAttribute((const void *)k_ob_beta_short, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)shm));
-        k_ob_beta_short<<<dim3((unsigned)((nshort + kObShortRows - 1) / kObShortRows), (unsigned)nv), 256, shm, st>>>(
+        k_ob_beta_short<<<dim3((unsigned)((nshort + kObShortRows - 1) / kObShortRows), (unsigned)nv), 64 * kObShortWaves,
+                          shm, st>>>(
             A, c, ldc, s, lds, cx->d.hscreen, cx->d.hkmask, nfull, nshort);
     }
     ISCI_HIP(hipGetLastError());
