@@ -1001,6 +1001,37 @@ __device__ __forceinline__ int pair_rank_hier(int y, int s, int lo1, int lo2)
     return s < 2 ? 0 : (y < 2 ? lo1 + 2 * (s - 2) + y : lo2 + (y - 2) + ((s - 2) * (s - 3)) / 2);
 }
 
+// Sum over the K steps of mask km (bit ks: step ks kept) of the products
+// of opa(ks) and opb(ks), added to acc: the kept steps are taken eight at a
+// time, the operands of a batch loaded together (one memory latency per
+// batch), then its products issued into two accumulator chains.  opa and
+// opb return zero for ks < 0 (the padding of the last batch).
+template <class OpA, class OpB>
+__device__ __forceinline__ v4d_ob ob_masked_product(unsigned long long km, OpA opa, OpB opb, v4d_ob acc)
+{
+    v4d_ob acc2 = v4d_ob{0.0, 0.0, 0.0, 0.0};
+    while (km) {
+        int ks[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            ks[g] = km ? __ffsll((long long)km) - 1 : -1;
+            km &= km - 1;
+        }
+        double a[8], b[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            a[g] = opa(ks[g]);
+            b[g] = opb(ks[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < 8; g += 2) {
+            acc = mfma16(a[g], b[g], acc);
+            acc2 = mfma16(a[g + 1], b[g + 1], acc2);
+        }
+    }
+    return acc + acc2;
+}
+
 // Rows whose beta strings reach level 2: one workgroup per (row, vector)
 // stages the row (pair rank -> value) in LDS; the image of the row's
 // antisymmetric pair matrix T under the one-body operator is
@@ -1176,13 +1207,7 @@ __global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs 
     const int rl = n >> 1, o = n & 1;
     const int coff = ro[rl], clen = ro[rl + 1] - ro[rl];   // 0 past the last row
     for (int mt = wave; mt < nt; mt += kObShortWaves) {
-        unsigned long long km = hkm[mt];
-        auto next_ks = [&]() {
-            if (!km) return -1;
-            const int k = __ffsll((long long)km) - 1;
-            km &= km - 1;
-            return k;
-        };
+        const unsigned long long km = hkm[mt];
         // A = h[16 mt + n][k], B = T[k][o] of the column's row: {k, o} is
         // {0,1} (k occupied) or {o, k} (k virtual, level 1); the LDS read is
         // clamped into the row and selected afterwards
@@ -1198,24 +1223,7 @@ __global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs 
             const double val = R[coff + (ok ? idx : 0)];
             return ok ? (k < o ? val : -val) : 0.0;
         };
-        // steps two at a time into two accumulators (a missing second step
-        // has zero operands)
-        v4d_ob acc = v4d_ob{0.0, 0.0, 0.0, 0.0}, acc2 = acc;
-        int k0 = next_ks(), k1 = next_ks();
-        double a0 = opa(k0), b0 = opb(k0), a1 = opa(k1), b1 = opb(k1);
-        while (k0 >= 0) {
-            const int k2 = next_ks(), k3 = next_ks();
-            const double a2 = opa(k2), b2 = opb(k2), a3 = opa(k3), b3 = opb(k3);
-            acc = mfma16(a0, b0, acc);
-            acc2 = mfma16(a1, b1, acc2);
-            k0 = k2;
-            k1 = k3;
-            a0 = a2;
-            b0 = b2;
-            a1 = a3;
-            b1 = b3;
-        }
-        acc += acc2;
+        const v4d_ob acc = ob_masked_product(km, opa, opb, v4d_ob{0.0, 0.0, 0.0, 0.0});
         // element g: target b = 16 mt + 4 g + kq, column n
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -1256,7 +1264,8 @@ bool onebody_beta_rows_ok(const isci_ctx *cx)
 {
     return cx->d.hscreen && cx->d.hkmask && cx->na == 2 && cx->nb == 2 && cx->norb > kObMaxNorb &&
            cx->norb <= 256 && cx->sa.nocc == 2 && cx->sb.nocc == 2 && cx->sa.nstr == cx->sb.nstr &&
-           (size_t)cx->sb.nstr * sizeof(double) <= (size_t)max_lds_bytes(cx);
+           (size_t)cx->sb.nstr * sizeof(double) <= (size_t)max_lds_bytes(cx) &&
+           ((cx->norb + 15) / 16) * ((cx->norb + 15) / 16 + 1) / 2 <= kObRowWaves * kObRowTpw;
 }
 
 static isci_status launch_onebody_beta_rows(const isci_ctx *cx, int nv, const double *c, int64_t ldc, double *s,
