@@ -1082,6 +1082,25 @@ static isci_status build_abx(isci_ctx *c, hipStream_t s)
     return ISCI_OK;
 }
 
+// Scratch of the transposed-block one-body routes: the beta class above
+// kObMaxNorb as the alpha class of the transposed block (where the beta
+// rows do not fit LDS, or on request), and the full-CI alpha class up to
+// kObMaxNorb as the beta class of the transposed block.  A block of vectors
+// and its image: eight vectors (one pass per sigma block) for full CI up to
+// 80 orbitals and 4 Mi determinants, else four.
+static isci_status alloc_onebody_scratch(isci_ctx *c)
+{
+    if (c->d.obT_c && c->d.obT_s) return ISCI_OK;
+    c->obT_nv = (c->norb <= kObMaxNorb && c->dim <= ((int64_t)1 << 22)) ? 8 : 4;
+    c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
+    c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
+    if (!c->d.obT_c || !c->d.obT_s) {
+        set_error("device allocation failed (one-body scratch)");
+        return ISCI_E_OOM;
+    }
+    return ISCI_OK;
+}
+
 static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
 {
     const int n = c->norb;
@@ -1498,20 +1517,12 @@ static isci_status create_impl(isci_handle *out, const double *h, const double *
         free_factors();
         if (st == ISCI_OK) st = build_abx(c, stream);
         const bool full_pairs = c->L >= 2 && c->sb.le[c->L - 2] == c->sb.nstr && c->sa.nstr == c->sb.nstr;
-        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && (norb > kObMaxNorb || full_pairs)) {
-            // beta one-body above kObMaxNorb runs as the alpha class of the
-            // transposed block, and where every column holds every pair
-            // (full CI) the alpha class as the beta class of the transposed
-            // block: scratch for a block of vectors and its image, eight
-            // vectors (one pass per sigma block) for full CI up to 80
-            // orbitals and 4 Mi determinants, else four
-            c->obT_nv = (norb <= kObMaxNorb && c->dim <= ((int64_t)1 << 22)) ? 8 : 4;
-            c->d.obT_c = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
-            c->d.obT_s = (double *)dev_alloc(c, sizeof(double) * c->obT_nv * (size_t)c->dim);
-            if (!c->d.obT_c || !c->d.obT_s) { set_error("device allocation failed (one-body scratch)"); st = ISCI_E_OOM; }
-        }
         // above kObMaxNorb the beta class runs on the rows where it can
-        if (st == ISCI_OK && norb > kObMaxNorb && onebody_beta_rows_ok(c)) c->ob_kernel = ISCI_ONEBODY_ROWS;
+        const bool beta_rows = st == ISCI_OK && norb > kObMaxNorb && onebody_beta_rows_ok(c);
+        if (beta_rows) c->ob_kernel = ISCI_ONEBODY_ROWS;
+        if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles &&
+            (norb > kObMaxNorb ? !beta_rows : full_pairs))
+            st = alloc_onebody_scratch(c);
         if (st == ISCI_OK && c->have_tiles && !c->onebody_in_tiles && norb <= kObMaxNorb && !full_pairs && c->L >= 2 &&
             c->sa.nstr == c->sb.nstr && c->sb.le[c->L - 2] > 0) {
             // the alpha class on the beta columns that hold every alpha pair,
@@ -1639,6 +1650,20 @@ isci_status isci_set_option(isci_handle c, int option, int value)
             set_error("beta one-body row path: needs more than 80 orbitals, the excitation hierarchy and a beta row "
                       "that fits LDS");
             return ISCI_E_UNSUPPORTED;
+        }
+        if (value != ISCI_ONEBODY_ROWS && c->norb > kObMaxNorb && c->have_tiles && !c->onebody_in_tiles &&
+            !c->d.obT_c) {
+            // the transposed-block beta route of a handle that runs it on the
+            // rows by default: its scratch, on the handle's device
+            int prev = -1;
+            if (hipGetDevice(&prev) != hipSuccess) { set_error("hipGetDevice failed"); return ISCI_E_HIP; }
+            if (prev != c->device && hipSetDevice(c->device) != hipSuccess) {
+                set_error("hipSetDevice failed");
+                return ISCI_E_HIP;
+            }
+            const isci_status st = alloc_onebody_scratch(c);
+            if (prev != c->device) (void)hipSetDevice(prev);
+            if (st != ISCI_OK) return st;
         }
         c->ob_kernel = value;
         return ISCI_OK;

@@ -74,8 +74,9 @@ def handle_bytes_estimate(norb: int, dim: int, naux: int = 0) -> int:
     kept alpha-beta unit in eight, the product operands (about 16 B per
     determinant and vector of a 4-vector pass, two result buffers, and the
     one- and two-vector layouts' own operands, three quarters of a pass's), and
-    above 80 orbitals the transposed one-body blocks (64 B per
-    determinant).  It is an estimate, not a bound: at tau = 0 the lists
+    above 202 orbitals (where a row of every beta pair no longer fits LDS and
+    the beta one-body class takes the transposed-block route) that route's
+    blocks (64 B per determinant).  It is an estimate, not a bound: at tau = 0 the lists
     alone can exceed it.  The server therefore re-charges a running
     request by what its handle really holds (isci_stats.device_bytes, read
     after the build) and puts a request whose build ran out of memory back
@@ -86,7 +87,7 @@ def handle_bytes_estimate(norb: int, dim: int, naux: int = 0) -> int:
     lists = 8 * (n3 + 1) + 9 * norb ** 4 // 8 + 4 * norb * norb * 16
     strings = 8 * (norb * norb) * 4
     operands = 3 * 16 * 4 * dim + 48 * dim
-    onebody = 64 * dim if norb > 80 else 0
+    onebody = 64 * dim if norb > 202 else 0
     transient = 8 * (2 * naux + 1) * norb * norb if naux > 0 else 8 * norb ** 4
     return transient + lists + strings + 8 * dim + operands + onebody
 

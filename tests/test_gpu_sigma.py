@@ -232,7 +232,9 @@ def test_beta_rows_match_transposed(norb, L, nvec):
     CISDT 84 (both kinds), full CI 90 (whole rows only), orbital counts off
     the 16-orbital tiles.  Every element against the transposed-block route
     (same terms, other summation order) and sampled targets, row ends
-    included, against the oracle; the row route is refused at 80 orbitals."""
+    included, against the oracle; the row route is refused at 80 orbitals,
+    and the transposed route's scratch is allocated only when that route is
+    selected."""
     import paper_1609_07757_amd as isci
     tau = 1e-12
     h, eri = recipe_a(norb, seed=8)
@@ -241,7 +243,11 @@ def test_beta_rows_match_transposed(norb, L, nvec):
     c = random_vectors(S.dim, nvec, seed=31)
     print(f"beta rows norb={norb} L={L} nvec={nvec}", flush=True)
     rows = gpu_sigma(hd, c)   # the default above 80 orbitals
+    held = isci.isci_get_stats(hd)["device_bytes"]
     isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, isci.ONEBODY_TRANSPOSED)
+    # the transposed route's scratch (a 4-vector block and its image) is
+    # allocated only when that route is selected
+    assert isci.isci_get_stats(hd)["device_bytes"] - held == 2 * 4 * 8 * S.dim
     tr = gpu_sigma(hd, c)
     isci.isci_set_option(hd, isci.OPT_ONEBODY_KERNEL, isci.ONEBODY_ROWS)
     assert np.array_equal(gpu_sigma(hd, c), rows)   # deterministic
