@@ -103,6 +103,7 @@ struct DevTabs {
     uchar4 *quads = nullptr;        // target tiles (X, P, Y, R) with X<=P, Y<=R, level <= L
     double *hscreen = nullptr;      // [norb][norb] h with screened units set to 0 (one-body kernels)
     double *hpad = nullptr;         // [kObMaxNorb][kObMaxNorb] the same, zero padded (matrix-core one-body)
+    double *hpadT = nullptr;        // above kObMaxNorb: [P][P], P = 16 ceil(norb / 16), the same, zero padded
     unsigned long long *hkmask = nullptr;   // [16] per 16-orbital tile of targets a: bit ks set when
                                             // some kept h_qa has q in [4 ks, 4 ks + 4) (norb <= 256)
     // alpha row of the ordered pair (x, q): start and length (-1 / 0 when

@@ -1045,9 +1045,16 @@ __device__ __forceinline__ v4d_ob ob_masked_product(unsigned long long km, OpA o
 constexpr int kObRowWaves = 16;
 constexpr int kObRowTpw = 9;   // tile pairs per wave: 16 tiles give 136 pairs
 
+// TAB: the T operands through a table of signed pair codes in LDS beside
+// the row (pcode[f][q] = +-(rank of {f, q} + 1), + for q > f, 0 on the
+// diagonal and past norb; P x P with P = 16 nt) and the h operands from the
+// copy of h zero-padded to P x P, so no operand needs a bounds test or a
+// rank formula.
+template <bool TAB>
 __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, const double *__restrict__ c,
                                                                   int64_t ldc, double *__restrict__ sg, int64_t lds,
                                                                   const double *__restrict__ hs,
+                                                                  const double *__restrict__ hp,
                                                                   const unsigned long long *__restrict__ hkm)
 {
     constexpr int NTH = 64 * kObRowWaves;
@@ -1066,13 +1073,27 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
         for (int u = 0; u < kObBatch; ++u)
             if (tb + u * NTH < len) rrow[tb + u * NTH] = val[u];
     }
-    __syncthreads();
     const int lo1 = A.sb.lev_off[1], lo2 = A.sb.lev_off[2];
+    const int P = 16 * nt;
+    short *pcode = (short *)(rrow + A.sb.nstr);
+    if (TAB)
+        for (int t = threadIdx.x; t < P * P; t += NTH) {
+            const int f = t / P, q = t - f * P;
+            const bool ok = f < norb && q < norb && f != q;
+            const int r = pair_rank_hier(min(f, q), max(f, q), lo1, lo2) + 1;
+            pcode[t] = (short)(ok ? (q > f ? r : -r) : 0);
+        }
+    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int n = lane & 15, kq = lane >> 4;
     const int npairs = nt * (nt + 1) / 2;
     // T[q][x] from the staged row; zero on the diagonal and past norb
     auto tget = [&](int q, int x) -> double {
+        if (TAB) {
+            const int code = pcode[q * P + x];
+            const double r = rrow[max(abs(code) - 1, 0)];
+            return code > 0 ? r : (code < 0 ? -r : 0.0);
+        }
         const int lo = min(q, x), hi = max(q, x);
         const bool ok = q != x && hi < norb;
         const double r = rrow[ok ? pair_rank_hier(lo, hi, lo1, lo2) : 0];
@@ -1080,6 +1101,7 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
     };
     // h_aq of the screened h (symmetric), zero past norb
     auto hget = [&](int a, int q) -> double {
+        if (TAB) return hp[q * P + a];
         const double h = hs[(size_t)min(q, norb - 1) * norb + min(a, norb - 1)];
         return (a < norb && q < norb) ? h : 0.0;
     };
@@ -1277,12 +1299,20 @@ static isci_status launch_onebody_beta_rows(const isci_ctx *cx, int nv, const do
     // up to level 1 (or 0) past those
     const int nfull = L >= 2 ? cx->sa.le[L - 2] : 0;
     if (nfull > 0) {
-        const size_t shm = sizeof(double) * (size_t)cx->sb.nstr;
-        if (shm > 65536)
-            ISCI_HIP(hipFuncSetAttribute((const void *)k_ob_beta_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)shm));
-        k_ob_beta_rows<<<dim3((unsigned)nfull, (unsigned)nv), 64 * kObRowWaves, shm, st>>>(A, c, ldc, s, lds,
-                                                                                           cx->d.hscreen, cx->d.hkmask);
+        // the pair-code table beside the row where both fit LDS
+        const int P = 16 * ((norb + 15) / 16);
+        const size_t row = sizeof(double) * (size_t)cx->sb.nstr, tab = sizeof(short) * (size_t)P * P;
+        const bool use_tab = cx->d.hpadT && row + tab <= (size_t)max_lds_bytes(cx);
+        const size_t shm = use_tab ? row + tab : row;
+        const void *fn = use_tab ? (const void *)k_ob_beta_rows<true> : (const void *)k_ob_beta_rows<false>;
+        if (shm > 65536) ISCI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        const dim3 grid((unsigned)nfull, (unsigned)nv);
+        if (use_tab)
+            k_ob_beta_rows<true><<<grid, 64 * kObRowWaves, shm, st>>>(A, c, ldc, s, lds, cx->d.hscreen, cx->d.hpadT,
+                                                                    cx->d.hkmask);
+        else
+            k_ob_beta_rows<false><<<grid, 64 * kObRowWaves, shm, st>>>(A, c, ldc, s, lds, cx->d.hscreen, cx->d.hpadT,
+                                                                     cx->d.hkmask);
     }
     const int nshort = cx->sa.nstr - nfull;
     if (nshort > 0) {

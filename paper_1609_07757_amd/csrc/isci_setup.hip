@@ -1114,6 +1114,14 @@ static isci_status build_hscreen(isci_ctx *c, const double *h, hipStream_t s)
         k_hkmask<<<1, 64, 0, s>>>(c->d.hscreen, n, c->d.hkmask);
         ISCI_HIP(hipGetLastError());
     }
+    if (n > kObMaxNorb && n <= 256) {
+        // zero-padded copy to whole 16-orbital tiles for the beta row kernel
+        const int P = 16 * ((n + 15) / 16);
+        c->d.hpadT = (double *)dev_alloc(c, sizeof(double) * P * P);
+        if (!c->d.hpadT) { set_error("device allocation failed (h)"); return ISCI_E_OOM; }
+        k_hpad<<<(P * P + 255) / 256, 256, 0, s>>>(c->d.hscreen, n, P, c->d.hpadT);
+        ISCI_HIP(hipGetLastError());
+    }
     if (n <= kObMaxNorb) {
         // zero-padded copy: the matrix-core one-body kernels load their h
         // operands with no bounds conditions
