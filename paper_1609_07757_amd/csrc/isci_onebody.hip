@@ -1189,7 +1189,8 @@ __global__ __launch_bounds__(64 * kObRowWaves) void k_ob_beta_rows(SigmaArgs A, 
 // above kObMaxNorb: the scheme of k_ob_beta_cap1 (columns (row, o) for the
 // two occupied o, V_o[b] = (h T[:, o])[b] on matrix cores) with kObShortRows
 // rows per workgroup, eight waves looping over the 16-orbital target tiles,
-// the h operands read from the screened h with the per-tile K-step masks,
+// the h operands read from the copy of h zero-padded to whole 16-orbital
+// tiles with the per-tile K-step masks,
 // and LDS sized by norb (dynamic):
 //   sigma({o, b}), b virtual: h_oo c({o,b}) + h_oo' c({o',b}) - V_o[b]
 //   sigma({0, 1})           : V_1[0] - V_0[1]
@@ -1197,7 +1198,7 @@ constexpr int kObShortRows = 8, kObShortWaves = 8;
 
 __global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs A, const double *__restrict__ c, int64_t ldc,
                                                        double *__restrict__ sg, int64_t lds,
-                                                       const double *__restrict__ hs,
+                                                       const double *__restrict__ hs, const double *__restrict__ hp,
                                                        const unsigned long long *__restrict__ hkm, int row0, int nrows)
 {
     constexpr int NR = kObShortRows, NTH = 64 * kObShortWaves;
@@ -1233,10 +1234,11 @@ __global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs 
         // A = h[16 mt + n][k], B = T[k][o] of the column's row: {k, o} is
         // {0,1} (k occupied) or {o, k} (k virtual, level 1); the LDS read is
         // clamped into the row and selected afterwards
+        // h from its copy zero-padded to whole 16-orbital tiles (P = 16 nt)
         auto opa = [&](int ks) {
             const int k = 4 * max(ks, 0) + kq, a = 16 * mt + n;
-            const double h = hs[(size_t)min(k, norb - 1) * norb + min(a, norb - 1)];
-            return (ks >= 0 && a < norb && k < norb) ? h : 0.0;
+            const double h = hp[k * (16 * nt) + a];
+            return ks >= 0 ? h : 0.0;
         };
         auto opb = [&](int ks) {
             const int k = 4 * max(ks, 0) + kq;
@@ -1285,7 +1287,7 @@ __global__ __launch_bounds__(64 * kObShortWaves) void k_ob_beta_short(SigmaArgs 
 bool onebody_beta_rows_ok(const isci_ctx *cx)
 {
     return cx->d.hscreen && cx->d.hkmask && cx->na == 2 && cx->nb == 2 && cx->norb > kObMaxNorb &&
-           cx->norb <= 256 && cx->sa.nocc == 2 && cx->sb.nocc == 2 && cx->sa.nstr == cx->sb.nstr &&
+           cx->d.hpadT && cx->norb <= 256 && cx->sa.nocc == 2 && cx->sb.nocc == 2 && cx->sa.nstr == cx->sb.nstr &&
            (size_t)cx->sb.nstr * sizeof(double) <= (size_t)max_lds_bytes(cx) &&
            ((cx->norb + 15) / 16) * ((cx->norb + 15) / 16 + 1) / 2 <= kObRowWaves * kObRowTpw;
 }
@@ -1322,7 +1324,7 @@ static isci_status launch_onebody_beta_rows(const isci_ctx *cx, int nv, const do
                                          (int)shm));
         k_ob_beta_short<<<dim3((unsigned)((nshort + kObShortRows - 1) / kObShortRows), (unsigned)nv), 64 * kObShortWaves,
                           shm, st>>>(
-            A, c, ldc, s, lds, cx->d.hscreen, cx->d.hkmask, nfull, nshort);
+            A, c, ldc, s, lds, cx->d.hscreen, cx->d.hpadT, cx->d.hkmask, nfull, nshort);
     }
     ISCI_HIP(hipGetLastError());
     return ISCI_OK;
