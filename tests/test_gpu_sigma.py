@@ -234,7 +234,8 @@ def test_beta_rows_match_transposed(norb, L, nvec):
     (same terms, other summation order) and sampled targets, row ends
     included, against the oracle; the row route is refused at 80 orbitals,
     and the transposed route's scratch is allocated only when that route is
-    selected."""
+    selected.  These sizes run the row kernel with its pair-code table; 176
+    and 199 orbitals (test_gpu_configs) run its rank-formula form."""
     import paper_1609_07757_amd as isci
     tau = 1e-12
     h, eri = recipe_a(norb, seed=8)
